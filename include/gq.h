@@ -1,0 +1,326 @@
+/*
+ * gq.h -- C-ABI of libgq.so: columnar query operators on AMD Instinct MI355X
+ * (gfx950): filter, hash partition, hash-join build and probe, hash group-by
+ * over int64 fixed-point decimals, and a fused filter -> probe -> group-by
+ * pipeline.
+ *
+ * Operator model (paper "Accelerating Presto with GPUs"):
+ *  - Operators consume and produce batches of rows held column-wise in device
+ *    memory in an Arrow-compatible layout (Section 3.1 describes a RowVector as
+ *    a batch of typically thousands of rows; Section 3.2 the cuDF table it wraps
+ *    on the GPU).
+ *  - Each batch travels with a stream; an operator enqueues its work on that
+ *    stream and returns at once without blocking the calling thread, and
+ *    streams are synchronised only at pipeline boundaries such as join build ->
+ *    probe (Section 3, "asynchronous execution model" and "cross-pipeline
+ *    synchronization"; Section 3.2).
+ *  - Expressions are evaluated fused into one pass where possible (Section 3.2,
+ *    AST execution versus standalone functions): here predicates and aggregate
+ *    input products are fused into the scanning kernel.
+ *  - Hash aggregation is a batch operator (Section 3.2, HashAggregation).
+ *  - The partitioned output operator splits a batch into per-destination
+ *    packed contiguous buffers (Section 3.3): gq_hash_partition writes every
+ *    partition contiguously plus an offsets array.
+ *
+ * Conventions shared by every call:
+ *  - All data pointers in gq_column / gq_batch are DEVICE pointers.  Arrays of
+ *    descriptors (gq_batch, gq_column, gq_pred, gq_agg, key and projection
+ *    lists, gq_plan) are HOST memory read during the call only.
+ *  - Inputs are borrowed: they must stay valid until the stream has passed the
+ *    call.  Outputs are caller-allocated at the caller's capacity.
+ *  - Every compute call enqueues on `stream` and returns without waiting.
+ *    Errors detectable on the host are returned at once (negative gq_status)
+ *    and nothing is enqueued.  Conditions found on the device (output capacity
+ *    exceeded, hash table full) are OR-ed into the context's device status word
+ *    and read with gq_ctx_sync_status; the required size is still written to
+ *    the call's device count so the caller can retry.  No kernel ever writes
+ *    past a caller's capacity.
+ *  - Calls never call hipMemset*, never synchronise, and allocate only through
+ *    the context allocator (stream ordered), so they can be captured in a HIP
+ *    graph.
+ *  - Row indices are int32: a batch holds at most 2^31-1 rows.
+ *  - A context is used by one host thread at a time.  Different contexts may be
+ *    used concurrently, on different streams.
+ *  - No C++ exception crosses this interface.
+ */
+#ifndef GQ_H
+#define GQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes -------------------------------------------------------- */
+typedef enum gq_status {
+  GQ_OK = 0,
+  GQ_ERR_INVALID = -1,     /* bad descriptor, type mismatch, size out of range */
+  GQ_ERR_UNSUPPORTED = -2, /* valid request outside what the library implements */
+  GQ_ERR_NOMEM = -3,       /* the allocator returned NULL */
+  GQ_ERR_HIP = -4,         /* a HIP runtime call failed; text in gq_last_error */
+  GQ_ERR_CAPACITY = -5,    /* device: output capacity too small (count = required) */
+  GQ_ERR_TABLE_FULL = -6   /* device: hash table could not hold every key */
+} gq_status;
+
+/* Device status word bits (see gq_ctx_sync_status). */
+#define GQ_DEV_CAPACITY 1
+#define GQ_DEV_TABLE_FULL 2
+
+/* ---- columns and batches -------------------------------------------------- */
+typedef enum gq_type { GQ_I8 = 1, GQ_I16 = 2, GQ_I32 = 3, GQ_I64 = 4 } gq_type;
+
+/*
+ * One fixed-width signed integer column, Arrow layout.
+ *  type      GQ_I8 .. GQ_I64, little-endian values.
+ *  scale     fixed-point decimal digits (metadata only; 0 = plain integer).
+ *  length    rows (input) or capacity in rows (output).
+ *  offset    first row: row i lives at data + (offset + i) * width and at bit
+ *            (offset + i) of the validity bitmap (Arrow slice offset).
+ *  data      device pointer.
+ *  validity  device pointer to an LSB-first bitmap, bit = 1 means valid, or
+ *            NULL = all rows valid.  Output bitmaps must be 4-byte aligned and
+ *            are written for exactly the output rows (other bits untouched).
+ */
+typedef struct gq_column {
+  int32_t type;
+  int32_t scale;
+  int64_t length;
+  int64_t offset;
+  void* data;
+  uint8_t* validity;
+} gq_column;
+
+/* A batch: `ncols` columns of `nrows` rows each. */
+typedef struct gq_batch {
+  int64_t nrows;
+  int32_t ncols;
+  int32_t reserved;
+  gq_column* cols;
+} gq_batch;
+
+/* ---- predicates and aggregate expressions --------------------------------- */
+typedef enum gq_pred_op {
+  GQ_RANGE = 1, /* lo <= x <= hi, compared as int64 after sign extension */
+  GQ_NE = 2     /* x != lo */
+} gq_pred_op;
+
+/* An array of predicates is a conjunction; a NULL value never passes (SQL
+ * three-valued logic drops UNKNOWN rows).  An empty array keeps every row. */
+typedef struct gq_pred {
+  int32_t col;
+  int32_t op;
+  int64_t lo;
+  int64_t hi;
+} gq_pred;
+
+typedef enum gq_factor_kind {
+  GQ_F_COL = 1,         /* x          */
+  GQ_F_K_MINUS_COL = 2, /* k - x      */
+  GQ_F_K_PLUS_COL = 3,  /* k + x      */
+  GQ_F_CONST = 4        /* k          */
+} gq_factor_kind;
+
+typedef struct gq_factor {
+  int32_t kind;
+  int32_t col;
+  int64_t k;
+} gq_factor;
+
+typedef enum gq_agg_op {
+  GQ_SUM = 1,        /* wrapping int64 sum of non-NULL inputs; NULL if none  */
+  GQ_COUNT_STAR = 2, /* rows in the group                                    */
+  GQ_COUNT = 3,      /* non-NULL inputs                                      */
+  GQ_MIN = 4,        /* NULL if no non-NULL input                            */
+  GQ_MAX = 5
+} gq_agg_op;
+
+/* Aggregate over an input expression: the product of `nfactors` (0..3)
+ * factors in wrapping int64 arithmetic, NULL if any referenced column is NULL.
+ * Fixed-point scale of a product is the sum of its factors' scales. */
+typedef struct gq_agg {
+  int32_t op;
+  int32_t nfactors;
+  gq_factor f[3];
+} gq_agg;
+
+#define GQ_MAX_COLS 16
+#define GQ_MAX_PREDS 8
+#define GQ_MAX_AGGS 8
+#define GQ_MAX_KEYS 4
+
+/* ---- context --------------------------------------------------------------- */
+typedef struct gq_ctx gq_ctx;
+
+/* Stream-ordered allocator.  alloc returns device memory usable by work
+ * enqueued on `stream` after the call, or NULL.  free releases it once work
+ * enqueued on `stream` before the call has finished. */
+typedef struct gq_allocator {
+  void* (*alloc)(size_t bytes, hipStream_t stream, void* user);
+  void (*free)(void* ptr, size_t bytes, hipStream_t stream, void* user);
+  void* user;
+} gq_allocator;
+
+/* Create a context on `device`.  `alloc` may be NULL: hipMallocAsync /
+ * hipFreeAsync on the device's default memory pool.  The allocator struct is
+ * copied.  Returns GQ_ERR_INVALID for a bad device, GQ_ERR_HIP on a runtime
+ * failure, GQ_ERR_NOMEM if the status word cannot be allocated. */
+int gq_ctx_create(int device, const gq_allocator* alloc, gq_ctx** out);
+/* Destroy a context; waits for the device first.  NULL is a no-op. */
+int gq_ctx_destroy(gq_ctx* ctx);
+/* Text of the last host-side error on this context ("" if none).  The pointer
+ * stays valid until the next call on the context. */
+const char* gq_last_error(gq_ctx* ctx);
+/* Synchronise `stream`, read and clear the device status word.  Writes the raw
+ * GQ_DEV_* bits to *bits (if not NULL) and returns GQ_OK, GQ_ERR_CAPACITY or
+ * GQ_ERR_TABLE_FULL (capacity first if both). */
+int gq_ctx_sync_status(gq_ctx* ctx, hipStream_t stream, int32_t* bits);
+/* Device address of the context's status word (int32), for callers that read
+ * it themselves without a synchronisation. */
+int32_t* gq_ctx_status_ptr(gq_ctx* ctx);
+
+/* ---- filter -----------------------------------------------------------------
+ * Stable stream compaction (Section 3.2, filter and projection on the GPU):
+ * rows of `in` for which every predicate holds, in input order, projected to
+ * the input columns listed in `proj` (nproj entries, 0..GQ_MAX_COLS).
+ *  out     nproj columns; out->cols[j] must have the type of in->cols[proj[j]];
+ *          its `length` is the capacity in rows.  If the input column has a
+ *          validity bitmap the output column must have one too.
+ *  d_count device int64: number of kept rows (written even when it exceeds the
+ *          capacity, in which case GQ_DEV_CAPACITY is raised and rows beyond
+ *          the capacity are not written).
+ * Errors: GQ_ERR_INVALID (bad column index, type mismatch, too many columns or
+ * predicates, more than 2^31-1 rows). */
+int gq_filter(gq_ctx* ctx, const gq_batch* in, const gq_pred* preds, int npreds,
+              const int32_t* proj, int nproj, gq_batch* out, int64_t* d_count,
+              hipStream_t stream);
+
+/* ---- hash partition -----------------------------------------------------------
+ * Split `in` into `nparts` partitions by a hash of its key columns (the
+ * partitioned-output operator of Section 3.3; the packed per-destination
+ * layout of the same section).
+ *  hash       h = seed; for each key column in order h = fmix64(h ^ x) with x
+ *             the value sign-extended to 64 bits, 0 for NULL; fmix64 is the
+ *             MurmurHash3 64-bit finaliser.
+ *  partition  p = floor(h * nparts / 2^64).
+ *  out        same column count and types as `in`, capacity >= in->nrows; rows
+ *             grouped by ascending p and in input order within a partition.
+ *  d_offsets  device int64[nparts + 1]: partition q occupies rows
+ *             [d_offsets[q], d_offsets[q+1]); d_offsets[0] = 0.
+ * 1 <= nparts <= 1024.  Errors: GQ_ERR_INVALID. */
+int gq_hash_partition(gq_ctx* ctx, const gq_batch* in, const int32_t* keys, int nkeys,
+                      int32_t nparts, uint64_t seed, gq_batch* out, int64_t* d_offsets,
+                      hipStream_t stream);
+
+/* ---- hash join ----------------------------------------------------------------
+ * Inner equi-join on one integer key column (Section 3.1 names Join among the
+ * relational operators run on the GPU; the build -> probe hand-over is the
+ * pipeline boundary of Section 3).  NULL keys never match.  Duplicate build
+ * keys are allowed. */
+typedef struct gq_join_table gq_join_table;
+
+typedef struct gq_join_opts {
+  float load_factor; /* target keys / slots, (0, 0.9]; 0 = 0.5 */
+  int32_t acc_slots; /* 8-byte accumulator words reserved per slot for a fused
+                        group-by on the join key (0, 2 or 6); see gq_pipeline */
+} gq_join_opts;
+
+/* Build a table over the rows of `build` that pass `preds` and have a non-NULL
+ * key.  The table (library-owned, allocated through the context allocator) is
+ * ready for probes enqueued after this call on the same stream, or on another
+ * stream ordered after it by an event.  Its capacity is sized on the device
+ * from the number of passing rows. */
+int gq_join_build(gq_ctx* ctx, const gq_batch* build, const int32_t* keys, int nkeys,
+                  const gq_pred* preds, int npreds, const gq_join_opts* opts,
+                  hipStream_t stream, gq_join_table** out);
+
+/* Probe: for each row of `probe` that passes `preds` and has a non-NULL key,
+ * emit one (probe row, build row) pair per matching build row.  Pairs are
+ * ordered by probe row, then build row, ascending (a canonical order of the
+ * SQL result).  `probe_idx`/`build_idx` are device int32[out_cap]; *d_count
+ * receives the number of pairs (GQ_DEV_CAPACITY if above out_cap). */
+int gq_join_probe(gq_ctx* ctx, const gq_join_table* table, const gq_batch* probe,
+                  const int32_t* keys, int nkeys, const gq_pred* preds, int npreds,
+                  int32_t* probe_idx, int32_t* build_idx, int64_t out_cap, int64_t* d_count,
+                  hipStream_t stream);
+
+/* Number of build rows inserted (device int64 inside the table), for callers
+ * that size outputs; valid once the build has run. */
+const int64_t* gq_join_table_count_ptr(const gq_join_table* table);
+
+/* Stream-ordered release of a table. */
+int gq_join_table_free(gq_ctx* ctx, gq_join_table* table, hipStream_t stream);
+
+/* Gather: out column j row r = in column cols[j] row idx[r] (with validity),
+ * for r < n.  idx is device int32[n]; each output needs capacity >= n.  Used
+ * after a probe to materialise payload columns (late materialisation,
+ * Section 2.3). */
+int gq_gather(gq_ctx* ctx, const gq_batch* in, const int32_t* cols, int ncols,
+              const int32_t* idx, int64_t n, gq_batch* out, hipStream_t stream);
+
+/* ---- hash group-by ------------------------------------------------------------
+ * SQL GROUP BY over the rows that pass `preds` (the Single aggregation mode of
+ * Section 3.2).  Up to GQ_MAX_KEYS key columns whose combined width plus one
+ * NULL flag bit per nullable column fits 64 bits, or one int64 key column of
+ * any nullability.  NULL keys form one group.  nkeys = 0 gives one global row,
+ * also for an empty input (COUNT = 0, SUM NULL).
+ *  out       nkeys key columns (the key types) followed by naggs int64 columns;
+ *            capacity in each `length`; key and aggregate validity written when
+ *            the output column has a bitmap (required where NULL can occur).
+ *  d_groups  device int64: groups found (GQ_DEV_CAPACITY if above capacity).
+ * Output order is the hash table's slot order unless flags has GQ_SORTED, in
+ * which case groups come in ascending key order, NULL first. */
+#define GQ_SORTED 1
+
+typedef enum gq_strategy {
+  GQ_STRATEGY_AUTO = 0,
+  GQ_STRATEGY_LDS = 1,   /* block-private tables in LDS, merged into HBM */
+  GQ_STRATEGY_GLOBAL = 2 /* one table in HBM, device-scope atomics */
+} gq_strategy;
+
+typedef struct gq_groupby_opts {
+  float load_factor;       /* 0 = 0.5 */
+  int32_t strategy;        /* gq_strategy */
+  int32_t flags;           /* GQ_SORTED */
+  int32_t block_size;      /* 0 = library choice; else 256 or 512 */
+  int64_t expected_groups; /* sizing hint; 0 = number of input rows.  Fewer
+                              slots than groups raises GQ_DEV_TABLE_FULL. */
+} gq_groupby_opts;
+
+int gq_groupby_agg(gq_ctx* ctx, const gq_batch* in, const int32_t* keys, int nkeys,
+                   const gq_pred* preds, int npreds, const gq_agg* aggs, int naggs,
+                   const gq_groupby_opts* opts, gq_batch* out, int64_t* d_groups,
+                   hipStream_t stream);
+
+/* ---- fused pipeline -------------------------------------------------------------
+ * filter(in) [-> probe `join` on probe_key] -> group-by, in one pass over `in`
+ * with nothing materialised between the steps (the fused per-batch operator
+ * chain of Section 3.2).  Group keys and aggregate inputs are columns of `in`.
+ * With a join, a probe row matching m build rows counts m times (SUM adds
+ * m * value, COUNT adds m), exactly as aggregating the materialised join.
+ * When the single group key is the probe key and the table reserved
+ * accumulators (gq_join_opts.acc_slots), groups are accumulated inside the join
+ * table itself (a group-join).  Output as for gq_groupby_agg. */
+typedef struct gq_plan {
+  const gq_pred* preds;
+  int32_t npreds;
+  int32_t probe_key;           /* column of `in`, used when join != NULL */
+  const gq_join_table* join;   /* NULL: filter -> group-by only */
+  const int32_t* group_keys;
+  int32_t ngroup_keys;
+  int32_t naggs;
+  const gq_agg* aggs;
+  gq_groupby_opts opts;
+} gq_plan;
+
+int gq_pipeline(gq_ctx* ctx, const gq_plan* plan, const gq_batch* in, gq_batch* out,
+                int64_t* d_groups, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GQ_H */

@@ -1,0 +1,322 @@
+// Shared device and host helpers of libgq (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <string>
+
+#include "../../include/gq.h"
+
+namespace gq {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------------------
+// Context
+// ---------------------------------------------------------------------------
+}  // namespace gq
+
+struct gq_ctx {
+  int device = 0;
+  gq_allocator alloc{};
+  bool default_alloc = true;
+  int32_t* d_status = nullptr;
+  std::string err;
+};
+
+namespace gq {
+
+int set_error(gq_ctx* ctx, int code, const std::string& msg);
+int hip_error(gq_ctx* ctx, hipError_t e, const char* what);
+void* ctx_alloc(gq_ctx* ctx, size_t bytes, hipStream_t s);
+void ctx_free(gq_ctx* ctx, void* p, size_t bytes, hipStream_t s);
+
+#define GQ_HIP_CHECK(ctx, expr)                                    \
+  do {                                                             \
+    hipError_t e_ = (expr);                                        \
+    if (e_ != hipSuccess) return ::gq::hip_error((ctx), e_, #expr); \
+  } while (0)
+
+// Launch check: kernel launches report errors through hipGetLastError.
+#define GQ_LAUNCH_CHECK(ctx)                                                    \
+  do {                                                                          \
+    hipError_t e_ = hipGetLastError();                                          \
+    if (e_ != hipSuccess) return ::gq::hip_error((ctx), e_, "kernel launch");   \
+  } while (0)
+
+// Stream-ordered scratch memory released when the owning call returns (the
+// release is ordered after the work the call enqueued on the same stream).
+struct Scratch {
+  gq_ctx* ctx;
+  hipStream_t s;
+  void* p = nullptr;
+  size_t bytes = 0;
+  Scratch(gq_ctx* c, hipStream_t st) : ctx(c), s(st) {}
+  bool get(size_t n) {
+    bytes = n < 256 ? 256 : n;
+    p = ctx_alloc(ctx, bytes, s);
+    return p != nullptr;
+  }
+  ~Scratch() {
+    if (p) ctx_free(ctx, p, bytes, s);
+  }
+  template <class T>
+  T* as(size_t byte_offset = 0) const {
+    return reinterpret_cast<T*>(static_cast<char*>(p) + byte_offset);
+  }
+};
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// ---------------------------------------------------------------------------
+// Column descriptors as kernels see them
+// ---------------------------------------------------------------------------
+
+// Input column: data points at row 0 of the slice; validity bits start at voff.
+struct DCol {
+  const uint8_t* data;
+  const uint8_t* valid;  // NULL = all valid
+  int64_t voff;
+  int32_t type;          // GQ_I8..GQ_I64
+  int32_t align;         // largest power of two (<= 16) dividing the data address
+};
+
+// Output column.
+struct OCol {
+  uint8_t* data;
+  uint32_t* valid;  // 32-bit words of the output bitmap, NULL = not written
+  int32_t type;
+  int32_t pad;
+};
+
+struct DPred {
+  int32_t col;
+  int32_t op;
+  int64_t lo;
+  int64_t hi;
+};
+
+__host__ __device__ inline int type_width(int t) { return 1 << (t - 1); }
+
+inline int addr_align(const void* p) {
+  uintptr_t a = reinterpret_cast<uintptr_t>(p);
+  int al = 16;
+  while (al > 1 && (a % al) != 0) al >>= 1;
+  return al;
+}
+
+// ---------------------------------------------------------------------------
+// Device helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int64_t load_one(const DCol& c, int64_t i) {
+  switch (c.type) {
+    case GQ_I8: return (int64_t)((const int8_t*)c.data)[i];
+    case GQ_I16: return (int64_t)((const int16_t*)c.data)[i];
+    case GQ_I32: return (int64_t)((const int32_t*)c.data)[i];
+    default: return ((const int64_t*)c.data)[i];
+  }
+}
+
+__device__ __forceinline__ bool valid_one(const DCol& c, int64_t i) {
+  if (c.valid == nullptr) return true;
+  int64_t b = c.voff + i;
+  return (c.valid[b >> 3] >> (b & 7)) & 1;
+}
+
+// Blocked load of ITEMS consecutive rows r0..r0+ITEMS-1 into int64 registers,
+// sign-extended.  Uses 128-bit loads (or the widest that covers ITEMS*width
+// bytes) when the whole group is in range and the slice is aligned for it;
+// rows past n read as 0.
+template <int ITEMS>
+__device__ __forceinline__ void load_items(const DCol& c, int64_t r0, int64_t n, int64_t (&v)[ITEMS]) {
+  const int w = type_width(c.type);
+  const int need = ITEMS * w < 16 ? ITEMS * w : 16;
+  if (r0 + ITEMS <= n && c.align >= need) {
+    const uint8_t* p = c.data + r0 * w;
+    switch (c.type) {
+      case GQ_I64: {
+#pragma unroll
+        for (int k = 0; k < ITEMS; k += 2) {
+          int4 x = *reinterpret_cast<const int4*>(p + k * 8);
+          v[k] = (int64_t)(((uint64_t)(uint32_t)x.y << 32) | (uint32_t)x.x);
+          v[k + 1] = (int64_t)(((uint64_t)(uint32_t)x.w << 32) | (uint32_t)x.z);
+        }
+        return;
+      }
+      case GQ_I32: {
+#pragma unroll
+        for (int k = 0; k < ITEMS; k += 4) {
+          int4 x = *reinterpret_cast<const int4*>(p + k * 4);
+          v[k] = x.x; v[k + 1] = x.y; v[k + 2] = x.z; v[k + 3] = x.w;
+        }
+        return;
+      }
+      case GQ_I16: {
+        if constexpr (ITEMS % 8 == 0) {
+#pragma unroll
+          for (int k = 0; k < ITEMS; k += 8) {
+            int4 x = *reinterpret_cast<const int4*>(p + k * 2);
+            int32_t q[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              v[k + 2 * j] = (int16_t)(q[j] & 0xffff);
+              v[k + 2 * j + 1] = (int16_t)((uint32_t)q[j] >> 16);
+            }
+          }
+          return;
+        }
+        break;
+      }
+      default: {  // GQ_I8
+        if constexpr (ITEMS % 16 == 0) {
+#pragma unroll
+          for (int k = 0; k < ITEMS; k += 16) {
+            int4 x = *reinterpret_cast<const int4*>(p + k);
+            int32_t q[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+            for (int j = 0; j < 16; ++j) v[k + j] = (int8_t)((uint32_t)q[j >> 2] >> (8 * (j & 3)));
+          }
+          return;
+        } else if constexpr (ITEMS == 8) {
+          int2 x = *reinterpret_cast<const int2*>(p);
+#pragma unroll
+          for (int j = 0; j < 8; ++j)
+            v[j] = (int8_t)((uint32_t)(j < 4 ? x.x : x.y) >> (8 * (j & 3)));
+          return;
+        } else if constexpr (ITEMS == 4) {
+          int32_t x = *reinterpret_cast<const int32_t*>(p);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) v[j] = (int8_t)((uint32_t)x >> (8 * j));
+          return;
+        }
+        break;
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k) v[k] = (r0 + k < n) ? load_one(c, r0 + k) : 0;
+}
+
+// Validity bits of rows r0..r0+ITEMS-1 as a bit mask (bit k = row r0+k).
+template <int ITEMS>
+__device__ __forceinline__ uint32_t valid_items(const DCol& c, int64_t r0, int64_t n) {
+  uint32_t m = 0;
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k)
+    if (r0 + k < n && valid_one(c, r0 + k)) m |= 1u << k;
+  return m;
+}
+
+__device__ __forceinline__ bool pred_pass(const DPred& p, int64_t v) {
+  return p.op == GQ_RANGE ? (v >= p.lo && v <= p.hi) : (v != p.lo);
+}
+
+// MurmurHash3 64-bit finaliser.
+__host__ __device__ __forceinline__ uint64_t fmix64(uint64_t k) {
+  k ^= k >> 33;
+  k *= 0xff51afd7ed558ccdULL;
+  k ^= k >> 33;
+  k *= 0xc4ceb9fe1a85ec53ULL;
+  k ^= k >> 33;
+  return k;
+}
+
+__device__ __forceinline__ uint64_t mulhi64(uint64_t a, uint64_t b) { return __umul64hi(a, b); }
+
+// Lane helpers (wave64).
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint32_t rank_in(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+template <class T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Exclusive prefix over the wave of small per-lane counts c (0 <= c < 2^BITS),
+// from one ballot per bit.  Returns the lane's prefix; *total gets the wave sum.
+template <int BITS>
+__device__ __forceinline__ uint32_t wave_prefix_small(uint32_t c, uint32_t* total) {
+  uint32_t pre = 0, tot = 0;
+#pragma unroll
+  for (int b = 0; b < BITS; ++b) {
+    uint64_t m = ballot((c >> b) & 1u);
+    pre += rank_in(m) << b;
+    tot += (uint32_t)__popcll(m) << b;
+  }
+  *total = tot;
+  return pre;
+}
+
+// ---------------------------------------------------------------------------
+// Single-pass device-wide exclusive prefix by decoupled look-back
+// (Merrill and Garland, "Single-pass Parallel Prefix Scan with Decoupled
+// Look-back", NVIDIA TR 2016).  One 64-bit status word per tile: the top two
+// bits say "nothing yet" (0), "tile aggregate" (1) or "inclusive prefix" (2),
+// the low 62 bits hold the value.  Flag and value travel in one atomic word,
+// so relaxed device-scope atomics suffice (no other data is published).
+// Tiles are numbered in the order blocks start (a global ticket), so a tile
+// only ever waits for tiles whose blocks are already running.
+// ---------------------------------------------------------------------------
+constexpr uint64_t kFlagAgg = 1ull << 62;
+constexpr uint64_t kFlagPre = 2ull << 62;
+constexpr uint64_t kValMask = (1ull << 62) - 1;
+
+__device__ __forceinline__ uint64_t status_load(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void status_store(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Called by all 64 lanes of one wave.  Returns the exclusive prefix of `tile`.
+__device__ inline int64_t lookback_exclusive(uint64_t* status, int64_t tile, int64_t agg) {
+  const int lane = lane_id();
+  if (tile == 0) {
+    if (lane == 0) status_store(&status[0], kFlagPre | (uint64_t)agg);
+    return 0;
+  }
+  if (lane == 0) status_store(&status[tile], kFlagAgg | (uint64_t)agg);
+  int64_t excl = 0;
+  int64_t hi = tile - 1;
+  while (true) {
+    const int64_t idx = hi - lane;
+    uint64_t s = kFlagPre;  // before tile 0: an inclusive prefix of 0
+    if (idx >= 0) {
+      s = status_load(&status[idx]);
+      while ((s >> 62) == 0) {
+        __builtin_amdgcn_s_sleep(1);
+        s = status_load(&status[idx]);
+      }
+    }
+    const uint64_t pre = ballot((s >> 62) == 2);
+    const int first = pre ? (__ffsll((unsigned long long)pre) - 1) : 64;
+    int64_t v = lane <= first ? (int64_t)(s & kValMask) : 0;
+    excl += wave_sum(v);
+    if (pre) break;
+    hi -= 64;
+  }
+  if (lane == 0) status_store(&status[tile], kFlagPre | (uint64_t)(excl + agg));
+  return excl;
+}
+
+// Fill kernel (graph-capture safe replacement for hipMemsetAsync).
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n);
+
+int launch_fill_u32(gq_ctx* ctx, void* p, uint32_t v, int64_t nwords, hipStream_t s);
+
+// Host-side validation helpers.
+int check_batch(gq_ctx* ctx, const gq_batch* b, const char* what);
+DCol make_dcol(const gq_column& c);
+
+}  // namespace gq

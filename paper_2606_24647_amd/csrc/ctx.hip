@@ -1,0 +1,147 @@
+// Context, allocator, device status word and shared host helpers of libgq.
+#include "common.h"
+
+#include <cstdio>
+
+namespace gq {
+
+int set_error(gq_ctx* ctx, int code, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  return code;
+}
+
+int hip_error(gq_ctx* ctx, hipError_t e, const char* what) {
+  std::string m = std::string(what) + ": " + hipGetErrorString(e);
+  return set_error(ctx, e == hipErrorOutOfMemory ? GQ_ERR_NOMEM : GQ_ERR_HIP, m);
+}
+
+void* ctx_alloc(gq_ctx* ctx, size_t bytes, hipStream_t s) {
+  if (bytes == 0) bytes = 256;
+  if (!ctx->default_alloc) return ctx->alloc.alloc(bytes, s, ctx->alloc.user);
+  void* p = nullptr;
+  if (hipMallocAsync(&p, bytes, s) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return p;
+}
+
+void ctx_free(gq_ctx* ctx, void* p, size_t bytes, hipStream_t s) {
+  if (!p) return;
+  if (bytes == 0) bytes = 256;
+  if (!ctx->default_alloc) {
+    ctx->alloc.free(p, bytes, s, ctx->alloc.user);
+    return;
+  }
+  (void)hipFreeAsync(p, s);
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = v;
+}
+
+int launch_fill_u32(gq_ctx* ctx, void* p, uint32_t v, int64_t nwords, hipStream_t s) {
+  if (nwords <= 0) return GQ_OK;
+  int64_t blocks = (nwords + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, s, (uint32_t*)p, v, nwords);
+  GQ_LAUNCH_CHECK(ctx);
+  return GQ_OK;
+}
+
+int check_batch(gq_ctx* ctx, const gq_batch* b, const char* what) {
+  if (!b) return set_error(ctx, GQ_ERR_INVALID, std::string(what) + ": NULL batch");
+  if (b->nrows < 0 || b->nrows > INT32_MAX)
+    return set_error(ctx, GQ_ERR_INVALID, std::string(what) + ": row count outside [0, 2^31-1]");
+  if (b->ncols < 0 || b->ncols > GQ_MAX_COLS)
+    return set_error(ctx, GQ_ERR_INVALID, std::string(what) + ": column count outside [0, 16]");
+  if (b->ncols > 0 && !b->cols) return set_error(ctx, GQ_ERR_INVALID, std::string(what) + ": NULL columns");
+  for (int i = 0; i < b->ncols; ++i) {
+    const gq_column& c = b->cols[i];
+    if (c.type < GQ_I8 || c.type > GQ_I64)
+      return set_error(ctx, GQ_ERR_INVALID, std::string(what) + ": bad column type");
+    if (c.offset < 0) return set_error(ctx, GQ_ERR_INVALID, std::string(what) + ": negative offset");
+    if (b->nrows > 0 && !c.data) return set_error(ctx, GQ_ERR_INVALID, std::string(what) + ": NULL data");
+  }
+  return GQ_OK;
+}
+
+DCol make_dcol(const gq_column& c) {
+  DCol d;
+  const int w = type_width(c.type);
+  d.data = static_cast<const uint8_t*>(c.data) + c.offset * w;
+  d.valid = c.validity;
+  d.voff = c.offset;
+  d.type = c.type;
+  d.align = addr_align(d.data);
+  return d;
+}
+
+}  // namespace gq
+
+using namespace gq;
+
+extern "C" {
+
+int gq_ctx_create(int device, const gq_allocator* alloc, gq_ctx** out) {
+  if (!out) return GQ_ERR_INVALID;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return GQ_ERR_INVALID;
+  if (alloc && (!alloc->alloc || !alloc->free)) return GQ_ERR_INVALID;
+  gq_ctx* ctx = new (std::nothrow) gq_ctx;
+  if (!ctx) return GQ_ERR_NOMEM;
+  ctx->device = device;
+  if (alloc) {
+    ctx->alloc = *alloc;
+    ctx->default_alloc = false;
+  }
+  if (hipSetDevice(device) != hipSuccess) {
+    delete ctx;
+    return GQ_ERR_HIP;
+  }
+  if (hipMalloc(&ctx->d_status, 256) != hipSuccess) {
+    delete ctx;
+    return GQ_ERR_NOMEM;
+  }
+  if (hipMemset(ctx->d_status, 0, 256) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+    (void)hipFree(ctx->d_status);
+    delete ctx;
+    return GQ_ERR_HIP;
+  }
+  *out = ctx;
+  return GQ_OK;
+}
+
+int gq_ctx_destroy(gq_ctx* ctx) {
+  if (!ctx) return GQ_OK;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  (void)hipFree(ctx->d_status);
+  delete ctx;
+  return GQ_OK;
+}
+
+const char* gq_last_error(gq_ctx* ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+
+int32_t* gq_ctx_status_ptr(gq_ctx* ctx) { return ctx ? ctx->d_status : nullptr; }
+
+int gq_ctx_sync_status(gq_ctx* ctx, hipStream_t stream, int32_t* bits) {
+  if (!ctx) return GQ_ERR_INVALID;
+  int32_t h = 0;
+  GQ_HIP_CHECK(ctx, hipMemcpyAsync(&h, ctx->d_status, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+  GQ_HIP_CHECK(ctx, hipStreamSynchronize(stream));
+  if (h != 0) {
+    const int32_t zero = 0;
+    GQ_HIP_CHECK(ctx, hipMemcpyAsync(ctx->d_status, &zero, sizeof(int32_t), hipMemcpyHostToDevice, stream));
+    GQ_HIP_CHECK(ctx, hipStreamSynchronize(stream));
+  }
+  if (bits) *bits = h;
+  if (h & GQ_DEV_CAPACITY) return set_error(ctx, GQ_ERR_CAPACITY, "output capacity exceeded");
+  if (h & GQ_DEV_TABLE_FULL) return set_error(ctx, GQ_ERR_TABLE_FULL, "hash table full");
+  return GQ_OK;
+}
+
+}  // extern "C"

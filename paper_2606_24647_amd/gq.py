@@ -1,0 +1,455 @@
+"""Python binding of libgq.so (include/gq.h): argument marshalling only.
+
+Device memory comes from torch tensors and streams from ``torch.cuda`` (HIP
+streams under ROCm); every step of every operator runs in the HIP kernels of
+libgq.so.  There is no fallback: if the library is missing, importing this
+module raises.
+
+Operator specs are plain tuples:
+
+* predicate ``("range", col, lo, hi)`` (lo <= x <= hi) or ``("ne", col, v)``;
+* factor ``("col", c)``, ``("k-col", k, c)``, ``("k+col", k, c)``, ``("const", k)``;
+* aggregate ``("sum", factors)``, ``("count*",)``, ``("count", factors)``,
+  ``("min", factors)``, ``("max", factors)``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libgq.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2606_24647_amd.build` "
+                      "(there is no CPU fallback)")
+
+_lib = C.CDLL(LIB_PATH)
+
+# ---------------------------------------------------------------------------
+# ABI structures (mirror include/gq.h)
+# ---------------------------------------------------------------------------
+GQ_OK = 0
+GQ_ERR_INVALID, GQ_ERR_UNSUPPORTED, GQ_ERR_NOMEM, GQ_ERR_HIP = -1, -2, -3, -4
+GQ_ERR_CAPACITY, GQ_ERR_TABLE_FULL = -5, -6
+GQ_I8, GQ_I16, GQ_I32, GQ_I64 = 1, 2, 3, 4
+GQ_RANGE, GQ_NE = 1, 2
+GQ_SUM, GQ_COUNT_STAR, GQ_COUNT, GQ_MIN, GQ_MAX = 1, 2, 3, 4, 5
+GQ_SORTED = 1
+STRATEGY = {"auto": 0, "lds": 1, "global": 2}
+
+_STATUS_NAMES = {0: "GQ_OK", -1: "GQ_ERR_INVALID", -2: "GQ_ERR_UNSUPPORTED", -3: "GQ_ERR_NOMEM",
+                 -4: "GQ_ERR_HIP", -5: "GQ_ERR_CAPACITY", -6: "GQ_ERR_TABLE_FULL"}
+
+_TORCH_TYPE = {torch.int8: GQ_I8, torch.int16: GQ_I16, torch.int32: GQ_I32, torch.int64: GQ_I64}
+_TYPE_TORCH = {v: k for k, v in _TORCH_TYPE.items()}
+_PRED_OPS = {"range": GQ_RANGE, "ne": GQ_NE}
+_FACTORS = {"col": 1, "k-col": 2, "k+col": 3, "const": 4}
+_AGGS = {"sum": GQ_SUM, "count*": GQ_COUNT_STAR, "count": GQ_COUNT, "min": GQ_MIN, "max": GQ_MAX}
+
+
+class GqColumn(C.Structure):
+    _fields_ = [("type", C.c_int32), ("scale", C.c_int32), ("length", C.c_int64),
+                ("offset", C.c_int64), ("data", C.c_void_p), ("validity", C.c_void_p)]
+
+
+class GqBatch(C.Structure):
+    _fields_ = [("nrows", C.c_int64), ("ncols", C.c_int32), ("reserved", C.c_int32),
+                ("cols", C.POINTER(GqColumn))]
+
+
+class GqPred(C.Structure):
+    _fields_ = [("col", C.c_int32), ("op", C.c_int32), ("lo", C.c_int64), ("hi", C.c_int64)]
+
+
+class GqFactor(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("col", C.c_int32), ("k", C.c_int64)]
+
+
+class GqAgg(C.Structure):
+    _fields_ = [("op", C.c_int32), ("nfactors", C.c_int32), ("f", GqFactor * 3)]
+
+
+class GqJoinOpts(C.Structure):
+    _fields_ = [("load_factor", C.c_float), ("acc_slots", C.c_int32)]
+
+
+class GqGroupbyOpts(C.Structure):
+    _fields_ = [("load_factor", C.c_float), ("strategy", C.c_int32), ("flags", C.c_int32),
+                ("block_size", C.c_int32), ("expected_groups", C.c_int64)]
+
+
+class GqPlan(C.Structure):
+    _fields_ = [("preds", C.POINTER(GqPred)), ("npreds", C.c_int32), ("probe_key", C.c_int32),
+                ("join", C.c_void_p), ("group_keys", C.POINTER(C.c_int32)),
+                ("ngroup_keys", C.c_int32), ("naggs", C.c_int32), ("aggs", C.POINTER(GqAgg)),
+                ("opts", GqGroupbyOpts)]
+
+
+class GqAllocator(C.Structure):
+    _fields_ = [("alloc", C.c_void_p), ("free", C.c_void_p), ("user", C.c_void_p)]
+
+
+_P = C.c_void_p
+_SIGS = {
+    "gq_ctx_create": (C.c_int, [C.c_int, _P, C.POINTER(_P)]),
+    "gq_ctx_destroy": (C.c_int, [_P]),
+    "gq_last_error": (C.c_char_p, [_P]),
+    "gq_ctx_sync_status": (C.c_int, [_P, _P, C.POINTER(C.c_int32)]),
+    "gq_ctx_status_ptr": (_P, [_P]),
+    "gq_filter": (C.c_int, [_P, C.POINTER(GqBatch), C.POINTER(GqPred), C.c_int,
+                            C.POINTER(C.c_int32), C.c_int, C.POINTER(GqBatch), _P, _P]),
+    "gq_hash_partition": (C.c_int, [_P, C.POINTER(GqBatch), C.POINTER(C.c_int32), C.c_int,
+                                    C.c_int32, C.c_uint64, C.POINTER(GqBatch), _P, _P]),
+    "gq_join_build": (C.c_int, [_P, C.POINTER(GqBatch), C.POINTER(C.c_int32), C.c_int,
+                                C.POINTER(GqPred), C.c_int, C.POINTER(GqJoinOpts), _P,
+                                C.POINTER(_P)]),
+    "gq_join_probe": (C.c_int, [_P, _P, C.POINTER(GqBatch), C.POINTER(C.c_int32), C.c_int,
+                                C.POINTER(GqPred), C.c_int, _P, _P, C.c_int64, _P, _P]),
+    "gq_join_table_count_ptr": (_P, [_P]),
+    "gq_join_table_free": (C.c_int, [_P, _P, _P]),
+    "gq_gather": (C.c_int, [_P, C.POINTER(GqBatch), C.POINTER(C.c_int32), C.c_int, _P,
+                            C.c_int64, C.POINTER(GqBatch), _P]),
+    "gq_groupby_agg": (C.c_int, [_P, C.POINTER(GqBatch), C.POINTER(C.c_int32), C.c_int,
+                                 C.POINTER(GqPred), C.c_int, C.POINTER(GqAgg), C.c_int,
+                                 C.POINTER(GqGroupbyOpts), C.POINTER(GqBatch), _P, _P]),
+    "gq_pipeline": (C.c_int, [_P, C.POINTER(GqPlan), C.POINTER(GqBatch), C.POINTER(GqBatch),
+                              _P, _P]),
+}
+EXPORTS = tuple(_SIGS)
+
+for _name, (_res, _args) in _SIGS.items():
+    _fn = getattr(_lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+
+
+def lib():
+    return _lib
+
+
+class GqError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+# ---------------------------------------------------------------------------
+# Device tables
+# ---------------------------------------------------------------------------
+
+def bitmap_bytes(n: int) -> int:
+    return ((n + 63) // 64) * 8
+
+
+@dataclass
+class DevColumn:
+    data: torch.Tensor                   # 1-D int8/16/32/64 on the device
+    valid: torch.Tensor | None = None    # uint8 LSB-first bitmap, or None = all valid
+    offset: int = 0                      # Arrow slice offset (rows)
+    length: int | None = None            # rows (defaults to len(data) - offset)
+    scale: int = 0
+
+    @property
+    def type(self) -> int:
+        return _TORCH_TYPE[self.data.dtype]
+
+    @property
+    def nrows(self) -> int:
+        return self.data.numel() - self.offset if self.length is None else self.length
+
+    def abi(self) -> GqColumn:
+        return GqColumn(self.type, self.scale, self.nrows, self.offset,
+                        self.data.data_ptr() if self.data.numel() else None,
+                        self.valid.data_ptr() if self.valid is not None else None)
+
+
+@dataclass
+class DevTable:
+    cols: list = field(default_factory=list)
+    nrows_override: int | None = None
+
+    @property
+    def nrows(self) -> int:
+        if self.nrows_override is not None:
+            return self.nrows_override
+        return self.cols[0].nrows if self.cols else 0
+
+
+def to_device(table, device="cuda") -> DevTable:
+    """Upload a host table (objects with .data numpy array and .valid bool array)."""
+    out = DevTable()
+    for c in table.cols:
+        d = torch.from_numpy(np.ascontiguousarray(c.data)).to(device)
+        v = None
+        if c.valid is not None:
+            bm = np.zeros(bitmap_bytes(len(c.data)), dtype=np.uint8)
+            if len(c.data):
+                b = np.packbits(np.asarray(c.valid, dtype=np.uint8), bitorder="little")
+                bm[: len(b)] = b
+            v = torch.from_numpy(bm).to(device)
+        out.cols.append(DevColumn(d, v, scale=getattr(c, "scale", 0)))
+    return out
+
+
+def empty_like_cols(types, capacity, nullable, device="cuda") -> DevTable:
+    t = DevTable()
+    for ty, nl in zip(types, nullable):
+        d = torch.empty(max(1, capacity), dtype=_TYPE_TORCH[ty], device=device)[:capacity] \
+            if capacity > 0 else torch.empty(0, dtype=_TYPE_TORCH[ty], device=device)
+        v = torch.zeros(max(8, bitmap_bytes(capacity)), dtype=torch.uint8, device=device) if nl else None
+        t.cols.append(DevColumn(d, v))
+    return t
+
+
+class _BatchArg:
+    """Keeps the ctypes column array of a DevTable alive for one call."""
+
+    def __init__(self, table: DevTable, capacity: int | None = None):
+        n = len(table.cols)
+        self.arr = (GqColumn * max(1, n))()
+        for i, c in enumerate(table.cols):
+            self.arr[i] = c.abi()
+            if capacity is not None:
+                self.arr[i].length = capacity
+        nrows = table.nrows if capacity is None else capacity
+        self.batch = GqBatch(nrows, n, 0, C.cast(self.arr, C.POINTER(GqColumn)))
+
+    @property
+    def ref(self):
+        return C.byref(self.batch)
+
+
+def _preds(preds):
+    preds = list(preds or [])
+    arr = (GqPred * max(1, len(preds)))()
+    for i, p in enumerate(preds):
+        arr[i].op = _PRED_OPS[p[0]]
+        arr[i].col = p[1]
+        if p[0] == "range":
+            arr[i].lo, arr[i].hi = int(p[2]), int(p[3])
+        else:
+            arr[i].lo = arr[i].hi = int(p[2])
+    return arr, len(preds)
+
+
+def _ints(xs):
+    xs = list(xs or [])
+    return (C.c_int32 * max(1, len(xs)))(*xs), len(xs)
+
+
+def _aggs(aggs):
+    aggs = list(aggs or [])
+    arr = (GqAgg * max(1, len(aggs)))()
+    for i, a in enumerate(aggs):
+        arr[i].op = _AGGS[a[0]]
+        fs = a[1] if len(a) > 1 else []
+        arr[i].nfactors = len(fs)
+        for j, f in enumerate(fs):
+            arr[i].f[j].kind = _FACTORS[f[0]]
+            if f[0] == "col":
+                arr[i].f[j].col = f[1]
+            elif f[0] == "const":
+                arr[i].f[j].k = int(f[1])
+            else:
+                arr[i].f[j].k, arr[i].f[j].col = int(f[1]), f[2]
+    return arr, len(aggs)
+
+
+def _stream(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def agg_nullable(table: DevTable, agg) -> bool:
+    if agg[0] in ("count*", "count"):
+        return False
+    return True
+
+
+# ---------------------------------------------------------------------------
+# Context
+# ---------------------------------------------------------------------------
+
+class Context:
+    def __init__(self, device: int | None = None):
+        self.device = torch.cuda.current_device() if device is None else device
+        h = C.c_void_p()
+        rc = _lib.gq_ctx_create(self.device, None, C.byref(h))
+        if rc != GQ_OK:
+            raise GqError(rc, "gq_ctx_create failed")
+        self.h = h
+
+    def close(self):
+        if self.h:
+            _lib.gq_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def check(self, rc):
+        if rc != GQ_OK:
+            raise GqError(rc, _lib.gq_last_error(self.h).decode())
+
+    def sync_status(self, stream=None) -> int:
+        """Synchronise the stream; return the device status bits (and clear them)."""
+        bits = C.c_int32(0)
+        rc = _lib.gq_ctx_sync_status(self.h, _stream(stream), C.byref(bits))
+        if rc not in (GQ_OK, GQ_ERR_CAPACITY, GQ_ERR_TABLE_FULL):
+            self.check(rc)
+        return int(bits.value)
+
+    def raise_status(self, stream=None):
+        bits = C.c_int32(0)
+        self.check(_lib.gq_ctx_sync_status(self.h, _stream(stream), C.byref(bits)))
+
+    # -- operators ---------------------------------------------------------
+    def filter(self, table: DevTable, preds, proj, capacity: int | None = None, stream=None):
+        """Returns (output DevTable, device int64 count tensor)."""
+        cap = table.nrows if capacity is None else capacity
+        out = empty_like_cols([table.cols[j].type for j in proj], cap,
+                              [table.cols[j].valid is not None for j in proj])
+        cnt = torch.zeros(1, dtype=torch.int64, device=table.cols[0].data.device if table.cols else "cuda")
+        p, np_ = _preds(preds)
+        pj, npj = _ints(proj)
+        ib, ob = _BatchArg(table), _BatchArg(out, cap)
+        self.check(_lib.gq_filter(self.h, ib.ref, p, np_, pj, npj, ob.ref,
+                                  C.c_void_p(cnt.data_ptr()), _stream(stream)))
+        return out, cnt
+
+    def hash_partition(self, table: DevTable, keys, nparts: int, seed: int = 0, stream=None):
+        """Returns (output DevTable of all columns, device int64 offsets[nparts+1])."""
+        n = table.nrows
+        out = empty_like_cols([c.type for c in table.cols], n, [c.valid is not None for c in table.cols])
+        offs = torch.empty(nparts + 1, dtype=torch.int64, device="cuda")
+        k, nk = _ints(keys)
+        ib, ob = _BatchArg(table), _BatchArg(out, n)
+        self.check(_lib.gq_hash_partition(self.h, ib.ref, k, nk, nparts, seed & 0xFFFFFFFFFFFFFFFF,
+                                          ob.ref, C.c_void_p(offs.data_ptr()), _stream(stream)))
+        return out, offs
+
+    def join_build(self, table: DevTable, keys, preds=(), load_factor: float = 0.0,
+                   acc_slots: int = 0, stream=None) -> "JoinTable":
+        k, nk = _ints(keys)
+        p, np_ = _preds(preds)
+        opts = GqJoinOpts(load_factor, acc_slots)
+        h = C.c_void_p()
+        ib = _BatchArg(table)
+        self.check(_lib.gq_join_build(self.h, ib.ref, k, nk, p, np_, C.byref(opts),
+                                      _stream(stream), C.byref(h)))
+        return JoinTable(self, h)
+
+    def join_probe(self, jt: "JoinTable", table: DevTable, keys, preds=(), capacity: int | None = None,
+                   stream=None):
+        """Returns (probe_idx int32, build_idx int32, device count)."""
+        cap = table.nrows if capacity is None else capacity
+        pi = torch.empty(max(1, cap), dtype=torch.int32, device="cuda")
+        bi = torch.empty(max(1, cap), dtype=torch.int32, device="cuda")
+        cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+        k, nk = _ints(keys)
+        p, np_ = _preds(preds)
+        ib = _BatchArg(table)
+        self.check(_lib.gq_join_probe(self.h, jt.h, ib.ref, k, nk, p, np_,
+                                      C.c_void_p(pi.data_ptr()), C.c_void_p(bi.data_ptr()), cap,
+                                      C.c_void_p(cnt.data_ptr()), _stream(stream)))
+        return pi, bi, cnt
+
+    def gather(self, table: DevTable, cols, idx: torch.Tensor, n: int | None = None, stream=None):
+        n = idx.numel() if n is None else n
+        out = empty_like_cols([table.cols[j].type for j in cols], n,
+                              [table.cols[j].valid is not None for j in cols])
+        cs, nc = _ints(cols)
+        ib, ob = _BatchArg(table), _BatchArg(out, n)
+        self.check(_lib.gq_gather(self.h, ib.ref, cs, nc, C.c_void_p(idx.data_ptr()), n, ob.ref,
+                                  _stream(stream)))
+        return out
+
+    def _groupby_out(self, table, keys, aggs, capacity):
+        types = [table.cols[j].type for j in keys] + [GQ_I64] * len(aggs)
+        nullable = [table.cols[j].valid is not None for j in keys] + [agg_nullable(table, a) for a in aggs]
+        return empty_like_cols(types, capacity, nullable)
+
+    @staticmethod
+    def _opts(load_factor=0.0, strategy="auto", sorted=False, block_size=0, expected_groups=0):
+        return GqGroupbyOpts(load_factor, STRATEGY[strategy], GQ_SORTED if sorted else 0, block_size,
+                             expected_groups)
+
+    def groupby_agg(self, table: DevTable, keys, preds, aggs, capacity: int | None = None,
+                    load_factor=0.0, strategy="auto", sorted=False, block_size=0, expected_groups=0,
+                    stream=None):
+        """Returns (output DevTable: keys then aggregates, device int64 group count)."""
+        cap = max(1, table.nrows) if capacity is None else capacity
+        out = self._groupby_out(table, keys, aggs, cap)
+        cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+        k, nk = _ints(keys)
+        p, np_ = _preds(preds)
+        a, na = _aggs(aggs)
+        opts = self._opts(load_factor, strategy, sorted, block_size, expected_groups)
+        ib, ob = _BatchArg(table), _BatchArg(out, cap)
+        self.check(_lib.gq_groupby_agg(self.h, ib.ref, k, nk, p, np_, a, na, C.byref(opts), ob.ref,
+                                       C.c_void_p(cnt.data_ptr()), _stream(stream)))
+        return out, cnt
+
+    def pipeline(self, table: DevTable, preds, group_keys, aggs, join: "JoinTable | None" = None,
+                 probe_key: int = 0, capacity: int | None = None, load_factor=0.0,
+                 strategy="auto", sorted=False, block_size=0, expected_groups=0, stream=None):
+        cap = max(1, table.nrows) if capacity is None else capacity
+        out = self._groupby_out(table, group_keys, aggs, cap)
+        cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+        p, np_ = _preds(preds)
+        k, nk = _ints(group_keys)
+        a, na = _aggs(aggs)
+        plan = GqPlan(C.cast(p, C.POINTER(GqPred)), np_, probe_key, join.h if join else None,
+                      C.cast(k, C.POINTER(C.c_int32)), nk, na, C.cast(a, C.POINTER(GqAgg)),
+                      self._opts(load_factor, strategy, sorted, block_size, expected_groups))
+        ib, ob = _BatchArg(table), _BatchArg(out, cap)
+        self.check(_lib.gq_pipeline(self.h, C.byref(plan), ib.ref, ob.ref, C.c_void_p(cnt.data_ptr()),
+                                    _stream(stream)))
+        return out, cnt
+
+
+class JoinTable:
+    def __init__(self, ctx: Context, h):
+        self.ctx, self.h = ctx, h
+
+    def count_tensor(self):
+        """Device int64 with the number of inserted build rows (a 1-element view)."""
+        ptr = _lib.gq_join_table_count_ptr(self.h)
+        return ptr
+
+    def free(self, stream=None):
+        if self.h:
+            self.ctx.check(_lib.gq_join_table_free(self.ctx.h, self.h, _stream(stream)))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# Host-side readers (after a synchronisation)
+# ---------------------------------------------------------------------------
+
+def read_column(col: DevColumn, n: int):
+    """(values numpy, valid bool numpy or None) of the first n rows."""
+    v = col.data[:n].cpu().numpy()
+    if col.valid is None:
+        return v, None
+    bm = col.valid.cpu().numpy()
+    valid = np.unpackbits(bm, bitorder="little")[:n].astype(bool)
+    return v, valid
+
+
+def read_table(t: DevTable, n: int):
+    return [read_column(c, n) for c in t.cols]
