@@ -1,0 +1,319 @@
+#!/usr/bin/env python
+"""Benchmark of the columnar operator path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-operators]
+
+One step is the filter -> hash-join -> group-by pipeline over a 60M-row fact
+table and a 15M-row dimension (fkey U[1,15M], date filters keeping about half
+of each side, group by fkey, SUM(price*(100-disc)) and COUNT(*)): a join build
+over the filtered dimension followed by one fused pass over the fact table.
+Inputs are generated on the device before the timed region (synthetic,
+seeded).  The printed JSON line carries:
+
+* value: input rows (fact + dimension) per second over the timed steps;
+* roofline: the dominant kernel's algorithmic bytes per launch over its average
+  launch time (HIP events on its own stream), against 8 TB/s;
+* cpu_baseline: the CPU oracle on a 1/10-scale sample of the same workload;
+* operators: the other operators measured separately (filter + group-by on
+  the 1M-row table, hash partition of 60M rows into 64 and 256 partitions, the
+  standalone filter, the materialising probe).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_GBS = 8000.0          # MI355X HBM3E peak, GB/s
+REV = [("col", 1), ("k-col", 100, 2)]
+FACT_ROWS, DIM_ROWS = 60_000_000, 15_000_000
+DIM_PRED = [("range", 1, 0, 1202)]          # dim date < 1203  (half of [0, 2406))
+FACT_PRED = [("range", 3, 1278, 2555)]      # fact date >= 1278 (half of [0, 2556))
+C2_AGGS = [("sum", REV), ("count*",)]
+C1_AGGS = [("sum", [("col", 0)]), ("sum", [("col", 1)]), ("sum", [("col", 2)]), ("sum", REV), ("count*",)]
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def source_hash(*paths):
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel_name, sources, launches_per_step=1):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, or None
+    when the summary is missing or the kernel's sources changed since."""
+    path = os.path.join(ROOT, "profiles", f"{kernel_name}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("source_hash") != source_hash(*sources):
+        return None
+    return t.get("bytes_per_launch")
+
+
+class Timer:
+    """Device time of work enqueued on the current stream."""
+
+    def __init__(self, torch):
+        self.torch = torch
+        self.a = torch.cuda.Event(enable_timing=True)
+        self.b = torch.cuda.Event(enable_timing=True)
+
+    def __enter__(self):
+        self.a.record()
+        return self
+
+    def __exit__(self, *exc):
+        self.b.record()
+
+    def ms(self):
+        self.b.synchronize()
+        return self.a.elapsed_time(self.b)
+
+
+def flush_mall(torch, buf):
+    """Overwrite a 512 MB buffer so that earlier inputs leave the 256 MB Infinity Cache."""
+    buf.zero_()
+
+
+def median(xs):
+    s = sorted(xs)
+    return s[len(s) // 2]
+
+
+# ---------------------------------------------------------------------------
+# The pipeline step (fact 60M x dim 15M)
+# ---------------------------------------------------------------------------
+
+def c2_step(ctx, dim, fact, out_cap, lf):
+    jt = ctx.join_build(dim, [0], DIM_PRED, load_factor=lf, acc_slots=2)
+    out, cnt = ctx.pipeline(fact, FACT_PRED, [0], C2_AGGS, join=jt, probe_key=0, capacity=out_cap)
+    jt.free()
+    return out, cnt
+
+
+def run_c2(torch, gq, devgen, ctx, steps, warmup, lf):
+    log("generating fact 60M x 4 and dim 15M x 3 on the device")
+    dim = devgen.dim_c2(DIM_ROWS)
+    fact = devgen.fact_c2(FACT_ROWS, DIM_ROWS)
+    torch.cuda.synchronize()
+    out_cap = DIM_ROWS
+    for _ in range(warmup):
+        c2_step(ctx, dim, fact, out_cap, lf)
+    ctx.raise_status()
+    # Timed region, with per-kernel events recorded by the library on its stream.
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with Timer(torch) as tm:
+        for _ in range(steps):
+            out, cnt = c2_step(ctx, dim, fact, out_cap, lf)
+    ms_total = tm.ms()
+    wall = time.perf_counter() - t0
+    ctx.set_timing(False)
+    kernels = ctx.timing_report()
+    ctx.raise_status()
+    ngroups = int(cnt.item())
+    matched = int(out.cols[2].data[:ngroups].sum().item())
+    kept_fact = int((fact.cols[3].data >= 1278).sum().item())
+    kept_dim = int((dim.cols[1].data <= 1202).sum().item())
+    return dict(ms_per_step=ms_total / steps, wall_ms_per_step=1e3 * wall / steps, kernels=kernels,
+                ngroups=ngroups, matched=matched, kept_fact=kept_fact, kept_dim=kept_dim,
+                dim=dim, fact=fact)
+
+
+def c2_bytes(r):
+    """Algorithmic bytes of the whole step and of the fused fact pass."""
+    dim_read = DIM_ROWS * (8 + 4)                # pkey, date
+    inserts = r["kept_dim"] * 16
+    fact_read = FACT_ROWS * (8 + 8 + 8 + 4)      # fkey, price, disc, date
+    probes = r["kept_fact"] * 16
+    aggs = r["matched"] * 16
+    out = r["ngroups"] * (8 + 8 + 8)             # key, sum, count
+    return dim_read + inserts + fact_read + probes + aggs + out, fact_read + probes + aggs
+
+
+# ---------------------------------------------------------------------------
+# Other operators
+# ---------------------------------------------------------------------------
+
+def run_operators(torch, gq, devgen, ctx, c2, reps=5):
+    res = {}
+    scratch = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
+
+    def timed(fn, reps=reps, flush=True):
+        ts = []
+        for i in range(reps + 1):
+            if flush:
+                flush_mall(torch, scratch)
+            with Timer(torch) as tm:
+                out = fn()
+            t = tm.ms()
+            if i > 0:
+                ts.append(t)
+        ctx.raise_status()
+        return median(ts), out
+
+    def entry(rows, nbytes, ms, **extra):
+        d = {"rows": rows, "ms": round(ms, 4), "rows_per_s": rows / (ms * 1e-3),
+             "alg_bytes": nbytes, "GBps": nbytes / (ms * 1e-3) / 1e9,
+             "frac_hbm_peak": nbytes / (ms * 1e-3) / 1e9 / PEAK_GBS}
+        d.update(extra)
+        return d
+
+    # Filter + group-by over the 1M-row fact table (keep shipdate <= 2466; 6 groups).
+    log("operator: filter + group-by, 1M rows")
+    t1 = devgen.fact_c1(1_000_000)
+    for strat in ("lds", "global"):
+        ms, (out, cnt) = timed(lambda: ctx.groupby_agg(t1, [4, 5], [("range", 3, -(1 << 31), 2466)], C1_AGGS,
+                                                       capacity=16, strategy=strat, expected_groups=6))
+        res[f"c1_filter_groupby_{strat}"] = entry(1_000_000, 1_000_000 * 30, ms, groups=int(cnt.item()))
+    del t1
+
+    # Join build alone and the fused fact pass alone, on the 60M x 15M tables.
+    dim, fact = c2["dim"], c2["fact"]
+    log("operator: join build / probe")
+    ms, jt = timed(lambda: ctx.join_build(dim, [0], DIM_PRED, acc_slots=2))
+    res["c2_join_build"] = entry(DIM_ROWS, DIM_ROWS * 12 + c2["kept_dim"] * 16, ms)
+    jt.free()
+    jt = ctx.join_build(dim, [0], DIM_PRED, acc_slots=0)
+    cap = c2["matched"] + 1024
+    ms, (pi, bi, cnt) = timed(lambda: ctx.join_probe(jt, fact, [0], FACT_PRED, capacity=cap))
+    npairs = int(cnt.item())
+    res["c2_join_probe_pairs"] = entry(FACT_ROWS, FACT_ROWS * 12 + c2["kept_fact"] * 16 + npairs * 8, ms,
+                                       pairs=npairs)
+    del pi, bi
+    jt.free()
+
+    log("operator: filter, 60M rows")
+    ms, (fout, fcnt) = timed(lambda: ctx.filter(fact, FACT_PRED, [0, 1, 2, 3]))
+    kept = int(fcnt.item())
+    res["c2_filter_fact"] = entry(FACT_ROWS, FACT_ROWS * 28 + kept * 28, ms, kept=kept)
+    del fout
+    del c2["dim"], c2["fact"], dim, fact
+    torch.cuda.empty_cache()
+
+    log("operator: hash partition, 60M rows x 21 B")
+    t3 = devgen.batch_c3(60_000_000)
+    for P in (64, 256):
+        ms, (pout, offs) = timed(lambda: ctx.hash_partition(t3, [0], P), reps=3)
+        res[f"c3_partition_p{P}"] = entry(60_000_000, 60_000_000 * 21 * 2, ms)
+        del pout
+    del t3
+    torch.cuda.empty_cache()
+    return res
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline: the oracle on a sample
+# ---------------------------------------------------------------------------
+
+def cpu_baseline(scale=10):
+    import oracle
+    from paper_2606_24647_amd import datagen as dg
+    oracle.lib()
+    nf, nd = FACT_ROWS // scale, DIM_ROWS // scale
+    fact = dg.fact_c2(nf, nkeys=nd)
+    dim = dg.dim_c2(nd)
+    t0 = time.perf_counter()
+    r = oracle.pipeline(fact, FACT_PRED, [0], C2_AGGS, join_spec=(dim, [0], DIM_PRED, [0]))
+    dt = time.perf_counter() - t0
+    return {"value": (nf + nd) / dt, "unit": "rows/s", "cores": 1, "kind": "oracle",
+            "sample": f"the same pipeline at 1/{scale} scale: fact {nf} rows x dim {nd} rows "
+                      f"(fkey U[1,{nd}]), single-threaded C++ oracle, {dt:.1f} s, {r.nrows} groups"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--load-factor", type=float, default=0.5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-operators", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (the build targets a single MI355X); --gpus {args.gpus} "
+              "is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2606_24647_amd import devgen, gq
+
+    dev = torch.cuda.get_device_properties(0)
+    log(f"device: {dev.name} {dev.gcnArchName} CUs={dev.multi_processor_count}")
+    ctx = gq.Context()
+    c2 = run_c2(torch, gq, devgen, ctx, args.steps, args.warmup, args.load_factor)
+    total_bytes, fused_bytes = c2_bytes(c2)
+    ms = c2["ms_per_step"]
+    rows = FACT_ROWS + DIM_ROWS
+
+    kern = c2["kernels"]
+    dom = max(kern.items(), key=lambda kv: kv[1][0])
+    dom_name, (dom_ms, dom_launches) = dom
+    dom_avg = dom_ms / dom_launches
+    per_launch = {"groupjoin": fused_bytes}.get(dom_name)
+    roof = None
+    if per_launch is not None:
+        achieved = per_launch / (dom_avg * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / PEAK_GBS, 4),
+                "traffic": traffic_for(dom_name, ["paper_2606_24647_amd/csrc/groupby.hip",
+                                                  "paper_2606_24647_amd/csrc/table.h",
+                                                  "paper_2606_24647_amd/csrc/common.h"]),
+                "kernel": dom_name, "avg_launch_ms": round(dom_avg, 4), "alg_bytes_per_launch": per_launch}
+
+    operators = None
+    if not args.no_operators:
+        operators = run_operators(torch, gq, devgen, ctx, c2)
+    else:
+        del c2["dim"], c2["fact"]
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline: oracle on a 1/10 sample")
+        cpu = cpu_baseline()
+
+    line = {
+        "metric": "input rows/s (filter + hash join + group-by pipeline, fact 60M x dim 15M)",
+        "value": rows / (ms * 1e-3),
+        "unit": "rows/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic (seeded, generated on the device)",
+        "config": {"workload": "filter+hash join+group-by: fact 60M rows (fkey U[1,15M], price, disc, date) "
+                               "joined to dim 15M rows (pkey permutation of 1..15M); date filters ~50% each "
+                               "side; group by fkey: SUM(price*(100-disc)), COUNT(*)",
+                   "fact_rows": FACT_ROWS, "dim_rows": DIM_ROWS, "load_factor": args.load_factor,
+                   "groups": c2["ngroups"], "matched_rows": c2["matched"]},
+        "pipeline_hbm": {"alg_bytes": total_bytes, "GBps": round(total_bytes / (ms * 1e-3) / 1e9, 1),
+                         "frac": round(total_bytes / (ms * 1e-3) / 1e9 / PEAK_GBS, 4),
+                         "wall_ms_per_step": round(c2["wall_ms_per_step"], 4)},
+        "kernels_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in kern.items()},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "operators": operators,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

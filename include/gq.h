@@ -182,6 +182,18 @@ int gq_ctx_sync_status(gq_ctx* ctx, hipStream_t stream, int32_t* bits);
  * it themselves without a synchronisation. */
 int32_t* gq_ctx_status_ptr(gq_ctx* ctx);
 
+/* Per-kernel timing, a profiling aid.  While enabled, every kernel the context
+ * launches is bracketed by two HIP events recorded on the kernel's own stream.
+ * Not for use under HIP graph capture. */
+int gq_ctx_set_timing(gq_ctx* ctx, int enable);
+/* Wait for the recorded events, then report the totals per kernel name since
+ * the last report, largest first: up to `cap` entries of `names` (each
+ * name_len bytes, NUL-terminated), total_ms and launches.  Returns the number
+ * of distinct kernels (may exceed cap) or a negative gq_status.  Clears the
+ * records. */
+int gq_ctx_timing_report(gq_ctx* ctx, char* names, int name_len, double* total_ms, int64_t* launches,
+                         int cap);
+
 /* ---- filter -----------------------------------------------------------------
  * Stable stream compaction (Section 3.2, filter and projection on the GPU):
  * rows of `in` for which every predicate holds, in input order, projected to

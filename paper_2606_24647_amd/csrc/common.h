@@ -6,6 +6,8 @@
 #include <cstdint>
 #include <cstring>
 #include <string>
+#include <type_traits>
+#include <vector>
 
 #include "../../include/gq.h"
 
@@ -24,6 +26,14 @@ struct gq_ctx {
   bool default_alloc = true;
   int32_t* d_status = nullptr;
   std::string err;
+  // Per-kernel event timing (gq_ctx_set_timing).
+  struct TimingRec {
+    const char* name;
+    hipEvent_t a, b;
+  };
+  bool timing = false;
+  std::vector<TimingRec> recs;
+  std::vector<hipEvent_t> pool;
 };
 
 namespace gq {
@@ -37,6 +47,18 @@ void ctx_free(gq_ctx* ctx, void* p, size_t bytes, hipStream_t s);
   do {                                                             \
     hipError_t e_ = (expr);                                        \
     if (e_ != hipSuccess) return ::gq::hip_error((ctx), e_, #expr); \
+  } while (0)
+
+// Per-kernel timing: when enabled on the context, every launch is bracketed by
+// two events recorded on its stream.
+int timing_begin(gq_ctx* ctx, hipStream_t s, const char* name);
+void timing_end(gq_ctx* ctx, hipStream_t s, int idx);
+
+#define GQ_LAUNCH(ctx, name, kern, grid, block, shm, stream, ...)          \
+  do {                                                                     \
+    const int ti_ = ::gq::timing_begin((ctx), (stream), (name));           \
+    hipLaunchKernelGGL(kern, grid, block, shm, stream, __VA_ARGS__);       \
+    ::gq::timing_end((ctx), (stream), ti_);                                \
   } while (0)
 
 // Launch check: kernel launches report errors through hipGetLastError.
@@ -226,6 +248,16 @@ __host__ __device__ __forceinline__ uint64_t fmix64(uint64_t k) {
 
 __device__ __forceinline__ uint64_t mulhi64(uint64_t a, uint64_t b) { return __umul64hi(a, b); }
 
+// Compile-time loop: f(std::integral_constant<int, K>) for K = B..E-1, so that
+// register arrays indexed by K stay in registers.
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
 // Lane helpers (wave64).
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
@@ -308,6 +340,54 @@ __device__ inline int64_t lookback_exclusive(uint64_t* status, int64_t tile, int
   }
   if (lane == 0) status_store(&status[tile], kFlagPre | (uint64_t)(excl + agg));
   return excl;
+}
+
+// ---------------------------------------------------------------------------
+// LDS staging of output rows
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void stage_put(uint8_t* stage, int pos, int64_t v, int type) {
+  switch (type) {
+    case GQ_I8: stage[pos] = (uint8_t)v; break;
+    case GQ_I16: reinterpret_cast<int16_t*>(stage)[pos] = (int16_t)v; break;
+    case GQ_I32: reinterpret_cast<int32_t*>(stage)[pos] = (int32_t)v; break;
+    default: reinterpret_cast<int64_t*>(stage)[pos] = v; break;
+  }
+}
+
+__device__ __forceinline__ void copy_out(const uint8_t* stage, int i, uint8_t* out, int64_t g, int type) {
+  switch (type) {
+    case GQ_I8: out[g] = stage[i]; break;
+    case GQ_I16: reinterpret_cast<int16_t*>(out)[g] = reinterpret_cast<const int16_t*>(stage)[i]; break;
+    case GQ_I32: reinterpret_cast<int32_t*>(out)[g] = reinterpret_cast<const int32_t*>(stage)[i]; break;
+    default: reinterpret_cast<int64_t*>(out)[g] = reinterpret_cast<const int64_t*>(stage)[i]; break;
+  }
+}
+
+// Write the validity bits of output rows [g0, g0 + cnt) (clipped to cap) from
+// one byte per row in LDS.  Whole 32-bit words are stored; words shared with a
+// neighbouring tile are updated with an atomic AND (clear own bits) and OR.
+template <int BLOCK>
+__device__ void write_valid_bits(uint32_t* words, const uint8_t* vbytes, int64_t g0, int cnt, int64_t cap) {
+  int64_t g1 = g0 + cnt;
+  if (g1 > cap) g1 = cap;
+  if (g1 <= g0) return;
+  const int64_t w0 = g0 >> 5, w1 = (g1 - 1) >> 5;
+  for (int64_t w = w0 + threadIdx.x; w <= w1; w += BLOCK) {
+    uint32_t bits = 0, mask = 0;
+    for (int b = 0; b < 32; ++b) {
+      int64_t pos = w * 32 + b;
+      if (pos >= g0 && pos < g1) {
+        mask |= 1u << b;
+        bits |= (uint32_t)(vbytes[pos - g0] & 1) << b;
+      }
+    }
+    if (mask == 0xffffffffu) {
+      words[w] = bits;
+    } else {
+      atomicAnd(&words[w], ~mask);
+      atomicOr(&words[w], bits);
+    }
+  }
 }
 
 // Fill kernel (graph-capture safe replacement for hipMemsetAsync).

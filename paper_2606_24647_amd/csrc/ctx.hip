@@ -1,7 +1,9 @@
 // Context, allocator, device status word and shared host helpers of libgq.
 #include "common.h"
 
+#include <algorithm>
 #include <cstdio>
+#include <map>
 
 namespace gq {
 
@@ -46,7 +48,7 @@ int launch_fill_u32(gq_ctx* ctx, void* p, uint32_t v, int64_t nwords, hipStream_
   if (nwords <= 0) return GQ_OK;
   int64_t blocks = (nwords + 255) / 256;
   if (blocks > 8192) blocks = 8192;
-  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, s, (uint32_t*)p, v, nwords);
+  GQ_LAUNCH(ctx, "fill_u32", k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, s, (uint32_t*)p, v, nwords);
   GQ_LAUNCH_CHECK(ctx);
   return GQ_OK;
 }
@@ -66,6 +68,27 @@ int check_batch(gq_ctx* ctx, const gq_batch* b, const char* what) {
     if (b->nrows > 0 && !c.data) return set_error(ctx, GQ_ERR_INVALID, std::string(what) + ": NULL data");
   }
   return GQ_OK;
+}
+
+int timing_begin(gq_ctx* ctx, hipStream_t s, const char* name) {
+  if (!ctx || !ctx->timing) return -1;
+  hipEvent_t ev[2];
+  for (int i = 0; i < 2; ++i) {
+    if (!ctx->pool.empty()) {
+      ev[i] = ctx->pool.back();
+      ctx->pool.pop_back();
+    } else if (hipEventCreate(&ev[i]) != hipSuccess) {
+      return -1;
+    }
+  }
+  if (hipEventRecord(ev[0], s) != hipSuccess) return -1;
+  ctx->recs.push_back(gq_ctx::TimingRec{name, ev[0], ev[1]});
+  return (int)ctx->recs.size() - 1;
+}
+
+void timing_end(gq_ctx* ctx, hipStream_t s, int idx) {
+  if (!ctx || idx < 0 || idx >= (int)ctx->recs.size()) return;
+  (void)hipEventRecord(ctx->recs[idx].b, s);
 }
 
 DCol make_dcol(const gq_column& c) {
@@ -102,6 +125,15 @@ int gq_ctx_create(int device, const gq_allocator* alloc, gq_ctx** out) {
     delete ctx;
     return GQ_ERR_HIP;
   }
+  if (!alloc) {
+    // Keep freed blocks in the device's default pool: stream-ordered
+    // allocations then cost no driver call after the first use.
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
+      uint64_t threshold = UINT64_MAX;
+      (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &threshold);
+    }
+  }
   if (hipMalloc(&ctx->d_status, 256) != hipSuccess) {
     delete ctx;
     return GQ_ERR_NOMEM;
@@ -120,6 +152,11 @@ int gq_ctx_destroy(gq_ctx* ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
   (void)hipFree(ctx->d_status);
+  for (auto& r : ctx->recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto e : ctx->pool) (void)hipEventDestroy(e);
   delete ctx;
   return GQ_OK;
 }
@@ -142,6 +179,41 @@ int gq_ctx_sync_status(gq_ctx* ctx, hipStream_t stream, int32_t* bits) {
   if (h & GQ_DEV_CAPACITY) return set_error(ctx, GQ_ERR_CAPACITY, "output capacity exceeded");
   if (h & GQ_DEV_TABLE_FULL) return set_error(ctx, GQ_ERR_TABLE_FULL, "hash table full");
   return GQ_OK;
+}
+
+int gq_ctx_set_timing(gq_ctx* ctx, int enable) {
+  if (!ctx) return GQ_ERR_INVALID;
+  ctx->timing = enable != 0;
+  return GQ_OK;
+}
+
+int gq_ctx_timing_report(gq_ctx* ctx, char* names, int name_len, double* total_ms, int64_t* launches, int cap) {
+  if (!ctx || cap < 0 || (cap > 0 && (!names || !total_ms || !launches || name_len < 2))) return GQ_ERR_INVALID;
+  std::map<std::string, std::pair<double, int64_t>> acc;
+  int rc = GQ_OK;
+  for (auto& r : ctx->recs) {
+    float ms = 0.f;
+    if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) {
+      rc = set_error(ctx, GQ_ERR_HIP, "gq_ctx_timing_report: event query failed");
+      ms = 0.f;
+    }
+    auto& e = acc[r.name];
+    e.first += ms;
+    e.second += 1;
+    ctx->pool.push_back(r.a);
+    ctx->pool.push_back(r.b);
+  }
+  ctx->recs.clear();
+  if (rc != GQ_OK) return rc;
+  std::vector<std::pair<std::string, std::pair<double, int64_t>>> v(acc.begin(), acc.end());
+  std::sort(v.begin(), v.end(), [](const auto& x, const auto& y) { return x.second.first > y.second.first; });
+  const int n = (int)v.size() < cap ? (int)v.size() : cap;
+  for (int i = 0; i < n; ++i) {
+    std::snprintf(names + (size_t)i * name_len, (size_t)name_len, "%s", v[i].first.c_str());
+    total_ms[i] = v[i].second.first;
+    launches[i] = v[i].second.second;
+  }
+  return (int)v.size();
 }
 
 }  // extern "C"

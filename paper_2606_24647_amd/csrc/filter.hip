@@ -43,51 +43,6 @@ struct CountBits {
   static constexpr int value = ITEMS < 2 ? 1 : ITEMS < 4 ? 2 : ITEMS < 8 ? 3 : ITEMS < 16 ? 4 : ITEMS < 32 ? 5 : 6;
 };
 
-__device__ __forceinline__ void stage_put(uint8_t* stage, int pos, int64_t v, int type) {
-  switch (type) {
-    case GQ_I8: stage[pos] = (uint8_t)v; break;
-    case GQ_I16: reinterpret_cast<int16_t*>(stage)[pos] = (int16_t)v; break;
-    case GQ_I32: reinterpret_cast<int32_t*>(stage)[pos] = (int32_t)v; break;
-    default: reinterpret_cast<int64_t*>(stage)[pos] = v; break;
-  }
-}
-
-__device__ __forceinline__ void copy_out(const uint8_t* stage, int i, uint8_t* out, int64_t g, int type) {
-  switch (type) {
-    case GQ_I8: out[g] = stage[i]; break;
-    case GQ_I16: reinterpret_cast<int16_t*>(out)[g] = reinterpret_cast<const int16_t*>(stage)[i]; break;
-    case GQ_I32: reinterpret_cast<int32_t*>(out)[g] = reinterpret_cast<const int32_t*>(stage)[i]; break;
-    default: reinterpret_cast<int64_t*>(out)[g] = reinterpret_cast<const int64_t*>(stage)[i]; break;
-  }
-}
-
-// Write the validity bits of output rows [g0, g0 + cnt) (clipped to cap) from
-// one byte per row in LDS.  Whole 32-bit words are stored; words shared with a
-// neighbouring tile are updated with an atomic AND (clear own bits) and OR.
-template <int BLOCK>
-__device__ void write_valid_bits(uint32_t* words, const uint8_t* vbytes, int64_t g0, int cnt, int64_t cap) {
-  int64_t g1 = g0 + cnt;
-  if (g1 > cap) g1 = cap;
-  if (g1 <= g0) return;
-  const int64_t w0 = g0 >> 5, w1 = (g1 - 1) >> 5;
-  for (int64_t w = w0 + threadIdx.x; w <= w1; w += BLOCK) {
-    uint32_t bits = 0, mask = 0;
-    for (int b = 0; b < 32; ++b) {
-      int64_t pos = w * 32 + b;
-      if (pos >= g0 && pos < g1) {
-        mask |= 1u << b;
-        bits |= (uint32_t)(vbytes[pos - g0] & 1) << b;
-      }
-    }
-    if (mask == 0xffffffffu) {
-      words[w] = bits;
-    } else {
-      atomicAnd(&words[w], ~mask);
-      atomicOr(&words[w], bits);
-    }
-  }
-}
-
 template <int BLOCK, int ITEMS>
 __global__ __launch_bounds__(BLOCK) void k_filter(const FilterArgs a) {
   constexpr int TILE = BLOCK * ITEMS;
@@ -240,11 +195,11 @@ extern "C" int gq_filter(gq_ctx* ctx, const gq_batch* in, const gq_pred* preds, 
   int64_t iblocks = (ntiles + 255) / 256;
   if (iblocks < 1) iblocks = 1;
   if (iblocks > 4096) iblocks = 4096;
-  hipLaunchKernelGGL(k_filter_init, dim3((unsigned)iblocks), dim3(256), 0, stream, a.ticket, a.status,
+  GQ_LAUNCH(ctx, "filter_init", k_filter_init, dim3((unsigned)iblocks), dim3(256), 0, stream, a.ticket, a.status,
                      ntiles, d_count);
   GQ_LAUNCH_CHECK(ctx);
   if (ntiles > 0) {
-    hipLaunchKernelGGL((k_filter<kFilterBlock, kFilterItems>), dim3((unsigned)ntiles), dim3(kFilterBlock), 0,
+    GQ_LAUNCH(ctx, "filter", (k_filter<kFilterBlock, kFilterItems>), dim3((unsigned)ntiles), dim3(kFilterBlock), 0,
                        stream, a);
     GQ_LAUNCH_CHECK(ctx);
   }

@@ -1,0 +1,834 @@
+// Hash group-by (gq_groupby_agg) and the fused filter -> probe -> group-by
+// pipeline (gq_pipeline).
+//
+// Strategies (chosen per call, see gq_groupby_opts):
+//  - LDS-privatised: each block owns a small open-addressing table in LDS and
+//    aggregates its rows there with LDS atomics; at the end it merges every
+//    group it saw into the HBM table with one device-scope atomic per
+//    accumulator word.  Rows whose key finds no LDS slot within a few probes go
+//    straight to HBM.  For low-cardinality keys this turns one HBM atomic per
+//    row and aggregate into one per block and group.
+//  - Global: every row updates the HBM table directly (high cardinality).
+//  - Group-join (pipeline only): when the only group key is the probe key and
+//    the join table reserved accumulator words, a matching row accumulates into
+//    the join slot it found: the probe and the aggregation touch one slot.
+// In the pipeline a probe row that matches m build rows is accumulated with
+// weight m (SUM adds m*x, COUNT adds m), which equals aggregating the
+// materialised join.  All sums wrap modulo 2^64 and are therefore independent
+// of the order in which atomics land.
+#include "table.h"
+
+namespace gq {
+namespace {
+
+constexpr int kGbBlock = 256;
+constexpr int kGbItems = 4;
+constexpr int kLdsProbes = 16;
+constexpr size_t kLdsBudget = 32 * 1024;
+
+struct JoinRef {
+  const JoinHdr* hdr;
+  const uint64_t* slots;
+  uint64_t max_cap;
+  int32_t stride;
+  int32_t pad;
+  DCol key;  // probe key column
+};
+
+struct GbArgs {
+  int64_t n;
+  int64_t ntiles;
+  int32_t npreds;
+  int32_t lcap;      // LDS table slots (power of two), LDS strategy only
+  DPred preds[GQ_MAX_PREDS];
+  DCol pcols[GQ_MAX_PREDS];
+  KeyPlan kp;
+  AggPlan ap;
+  uint64_t* slots;   // HBM group table: cap hashed slots, then 2 extra slots
+  uint64_t cap;
+  int32_t stride;    // words per HBM slot
+  int32_t pad;
+  JoinRef join;
+  int32_t* dev_status;
+};
+
+// ---------------------------------------------------------------------------
+// Per-tile row evaluation shared by the kernels
+// ---------------------------------------------------------------------------
+template <int ITEMS>
+__device__ __forceinline__ uint32_t eval_preds(const GbArgs& a, int64_t r0) {
+  uint32_t keep = 0;
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k)
+    if (r0 + k < a.n) keep |= 1u << k;
+  for (int p = 0; p < a.npreds; ++p) {
+    int64_t v[ITEMS];
+    load_items<ITEMS>(a.pcols[p], r0, a.n, v);
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k)
+      if (!pred_pass(a.preds[p], v[k])) keep &= ~(1u << k);
+    if (a.pcols[p].valid) keep &= valid_items<ITEMS>(a.pcols[p], r0, a.n);
+  }
+  return keep;
+}
+
+// Join-table slot of a probe key, or nullptr.
+__device__ __forceinline__ const uint64_t* join_lookup(const JoinRef& j, uint64_t kv) {
+  if (kv == kEmpty) {
+    const uint64_t* s = j.slots + j.max_cap * j.stride;
+    return slot_count(s) ? s : nullptr;
+  }
+  return table_find(j.slots, j.hdr->cap, j.stride, kv);
+}
+
+// Match counts (weights) of the kept rows; rows without a match are dropped.
+template <int ITEMS>
+__device__ __forceinline__ void probe_weights(const GbArgs& a, int64_t r0, uint32_t& keep, uint32_t (&w)[ITEMS]) {
+  int64_t kv[ITEMS];
+  load_items<ITEMS>(a.join.key, r0, a.n, kv);
+  if (a.join.key.valid) keep &= valid_items<ITEMS>(a.join.key, r0, a.n);
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k) {
+    w[k] = 0;
+    if ((keep >> k) & 1u) {
+      const uint64_t* s = join_lookup(a.join, (uint64_t)kv[k]);
+      if (s) w[k] = slot_count(s);
+      if (w[k] == 0) keep &= ~(1u << k);
+    }
+  }
+}
+
+// Group keys of ITEMS rows.  special: 0 hashed, 1 EMPTY-valued raw key, 2 NULL raw key.
+template <int ITEMS>
+__device__ __forceinline__ void make_keys(const KeyPlan& kp, int64_t r0, int64_t n, uint64_t (&key)[ITEMS],
+                                          uint8_t (&special)[ITEMS]) {
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k) {
+    key[k] = 0;
+    special[k] = 0;
+  }
+#pragma unroll
+  for (int j = 0; j < GQ_MAX_KEYS; ++j) {
+    if (j < kp.nk) {
+      int64_t v[ITEMS];
+      load_items<ITEMS>(kp.cols[j], r0, n, v);
+      const uint32_t vm = kp.cols[j].valid ? valid_items<ITEMS>(kp.cols[j], r0, n) : 0xffffffffu;
+      if (kp.mode == KEY_RAW64) {
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) {
+          key[k] = (uint64_t)v[k];
+          special[k] = !((vm >> k) & 1u) ? 2 : (key[k] == kEmpty ? 1 : 0);
+        }
+      } else {
+        const int w = kp.bits[j];
+        const uint64_t mask = (w == 64) ? ~0ull : ((1ull << w) - 1);
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) {
+          uint64_t f = ((uint64_t)v[k] ^ (1ull << (w - 1))) & mask;
+          if (kp.nullable[j]) f = ((vm >> k) & 1u) ? (f | (1ull << w)) : 0ull;
+          key[k] |= f << kp.shift[j];
+        }
+      }
+    }
+  }
+}
+
+// Input of aggregate `ag` for ITEMS rows: x[k] = product of its factors
+// (wrapping).  Returns the mask of rows whose input is non-NULL.  Factor
+// columns are loaded per aggregate; a column shared by several aggregates is
+// re-read from cache, not from HBM.
+template <int ITEMS>
+__device__ __forceinline__ uint32_t agg_values(const DAgg& ag, const AggPlan& ap, int64_t r0, int64_t n,
+                                               uint64_t (&x)[ITEMS]) {
+  uint32_t nn = 0xffffffffu;
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k) x[k] = 1;
+  for (int f = 0; f < ag.nf; ++f) {
+    const DFactor& fa = ag.f[f];
+    if (fa.kind == GQ_F_CONST) {
+#pragma unroll
+      for (int k = 0; k < ITEMS; ++k) x[k] *= (uint64_t)fa.k;
+      continue;
+    }
+    const DCol& c = ap.vals[fa.v];
+    int64_t v[ITEMS];
+    load_items<ITEMS>(c, r0, n, v);
+    if (c.valid) nn &= valid_items<ITEMS>(c, r0, n);
+    const uint64_t kk = (uint64_t)fa.k;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      const uint64_t cv = (uint64_t)v[k];
+      const uint64_t t = fa.kind == GQ_F_COL ? cv : fa.kind == GQ_F_K_MINUS_COL ? kk - cv : kk + cv;
+      x[k] *= t;
+    }
+  }
+  return nn;
+}
+
+// Apply all aggregates of ITEMS rows to their slots.  Row k's words live in
+// LDS at lds + loff[k] (loff[k] >= 0) or in HBM at gsp[k]; word 1 is the
+// hidden row count.
+template <int ITEMS>
+__device__ __forceinline__ void apply_rows(const AggPlan& ap, int64_t r0, int64_t n, uint32_t keep,
+                                           const uint32_t (&w)[ITEMS], uint64_t* lds, const int (&loff)[ITEMS],
+                                           uint64_t* const (&gsp)[ITEMS]) {
+  static_for<0, ITEMS>([&](auto kk) {
+    constexpr int k = decltype(kk)::value;
+    if (!((keep >> k) & 1u)) return;
+    if (loff[k] >= 0) SharedAtomics::add(&lds[loff[k] + 1], w[k]);
+    else GlobalAtomics::add(&gsp[k][1], w[k]);
+  });
+  for (int i = 0; i < ap.naggs; ++i) {
+    const DAgg& ag = ap.aggs[i];
+    if (ag.op == GQ_COUNT_STAR) continue;
+    uint64_t x[ITEMS];
+    const uint32_t nn = agg_values<ITEMS>(ag, ap, r0, n, x) & keep;
+    static_for<0, ITEMS>([&](auto kk) {
+      constexpr int k = decltype(kk)::value;
+      if (!((nn >> k) & 1u)) return;
+      const uint64_t wk = w[k];
+      if (loff[k] >= 0) {
+        uint64_t* s = lds + loff[k];
+        switch (ag.op) {
+          case GQ_SUM: SharedAtomics::add(&s[ag.word], x[k] * wk); break;
+          case GQ_COUNT: SharedAtomics::add(&s[ag.word], wk); break;
+          case GQ_MIN: SharedAtomics::min(&s[ag.word], (int64_t)x[k]); break;
+          default: SharedAtomics::max(&s[ag.word], (int64_t)x[k]); break;
+        }
+        if (ag.cword >= 0) SharedAtomics::add(&s[ag.cword], wk);
+      } else {
+        uint64_t* s = gsp[k];
+        switch (ag.op) {
+          case GQ_SUM: GlobalAtomics::add(&s[ag.word], x[k] * wk); break;
+          case GQ_COUNT: GlobalAtomics::add(&s[ag.word], wk); break;
+          case GQ_MIN: GlobalAtomics::min(&s[ag.word], (int64_t)x[k]); break;
+          default: GlobalAtomics::max(&s[ag.word], (int64_t)x[k]); break;
+        }
+        if (ag.cword >= 0) GlobalAtomics::add(&s[ag.cword], wk);
+      }
+    });
+  }
+}
+
+// HBM slot of a row's group (hashed or extra), or nullptr if the table is full.
+__device__ __forceinline__ uint64_t* global_slot(const GbArgs& a, uint64_t key, int special) {
+  if (special) return a.slots + (a.cap + (uint64_t)(special - 1)) * a.stride;
+  uint64_t* s = table_find_insert(a.slots, a.cap, a.stride, key);
+  if (!s) atomicOr(a.dev_status, GQ_DEV_TABLE_FULL);
+  return s;
+}
+
+// Merge one set of accumulator words into HBM.
+__device__ __forceinline__ void merge_words(const AggPlan& ap, uint64_t* dst, const uint64_t* src) {
+  for (int w = 1; w < ap.nwords; ++w) {
+    const uint64_t v = src[w];
+    switch (ap.wop[w]) {
+      case WOP_ADD:
+        if (v) atomicAdd((unsigned long long*)&dst[w], (unsigned long long)v);
+        break;
+      case WOP_MIN:
+        if ((int64_t)v != INT64_MAX) atomicMin((long long*)&dst[w], (long long)v);
+        break;
+      default:
+        if ((int64_t)v != INT64_MIN) atomicMax((long long*)&dst[w], (long long)v);
+        break;
+    }
+  }
+}
+
+__host__ __device__ __forceinline__ uint64_t word_identity(int8_t wop) {
+  return (uint64_t)(wop == WOP_MIN ? INT64_MAX : wop == WOP_MAX ? INT64_MIN : 0);
+}
+
+// ---------------------------------------------------------------------------
+// Kernels
+// ---------------------------------------------------------------------------
+
+// Initialise `nslots` HBM slots: key EMPTY, accumulators at their identity.
+__global__ void k_gt_init(uint64_t* slots, int64_t nslots, int32_t stride, AggPlan ap) {
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t step = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = i0; i < nslots; i += step) {
+    uint64_t* s = slots + i * stride;
+    s[0] = kEmpty;
+    for (int w = 1; w < stride; ++w) s[w] = (w < ap.nwords) ? word_identity(ap.wop[w]) : 0ull;
+  }
+}
+
+// Group-join accumulator init in a join table: the acc words of slots [0, cap)
+// and of the extra slot.
+__global__ void k_gj_init(JoinRef j, AggPlan ap) {
+  const uint64_t cap = j.hdr->cap;
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t step = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = i0; i <= (int64_t)cap; i += step) {
+    const uint64_t s = (i == (int64_t)cap) ? j.max_cap : (uint64_t)i;
+    uint64_t* acc = const_cast<uint64_t*>(j.slots) + s * j.stride + 1;  // acc[1] = hidden count
+    for (int w = 1; w < ap.nwords; ++w) acc[w] = word_identity(ap.wop[w]);
+  }
+}
+
+template <int BLOCK, int ITEMS, bool JOIN>
+__global__ __launch_bounds__(BLOCK) void k_gb_global(const GbArgs a) {
+  constexpr int TILE = BLOCK * ITEMS;
+  const int64_t r0 = (int64_t)blockIdx.x * TILE + (int64_t)threadIdx.x * ITEMS;
+  uint32_t keep = eval_preds<ITEMS>(a, r0);
+  uint32_t w[ITEMS];
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k) w[k] = 1;
+  if (JOIN) probe_weights<ITEMS>(a, r0, keep, w);
+  if (!keep) return;
+  uint64_t key[ITEMS];
+  uint8_t special[ITEMS];
+  make_keys<ITEMS>(a.kp, r0, a.n, key, special);
+  int loff[ITEMS];
+  uint64_t* gsp[ITEMS];
+  static_for<0, ITEMS>([&](auto kk) {
+    constexpr int k = decltype(kk)::value;
+    loff[k] = -1;
+    gsp[k] = nullptr;
+    if ((keep >> k) & 1u) {
+      gsp[k] = global_slot(a, key[k], special[k]);
+      if (!gsp[k]) keep &= ~(1u << k);
+    }
+  });
+  apply_rows<ITEMS>(a.ap, r0, a.n, keep, w, nullptr, loff, gsp);
+}
+
+template <int BLOCK, int ITEMS, bool JOIN>
+__global__ __launch_bounds__(BLOCK) void k_gb_lds(const GbArgs a) {
+  constexpr int TILE = BLOCK * ITEMS;
+  extern __shared__ uint64_t s_tab[];
+  const int nw = a.ap.nwords;
+  const int lcap = a.lcap;
+  for (int i = threadIdx.x; i < lcap * nw; i += BLOCK) {
+    const int wi = i % nw;
+    s_tab[i] = wi == 0 ? kEmpty : word_identity(a.ap.wop[wi]);
+  }
+  __syncthreads();
+
+  for (int64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+    const int64_t r0 = tile * TILE + (int64_t)threadIdx.x * ITEMS;
+    uint32_t keep = eval_preds<ITEMS>(a, r0);
+    uint32_t w[ITEMS];
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) w[k] = 1;
+    if (JOIN) probe_weights<ITEMS>(a, r0, keep, w);
+    if (!keep) continue;
+    uint64_t key[ITEMS];
+    uint8_t special[ITEMS];
+    make_keys<ITEMS>(a.kp, r0, a.n, key, special);
+    int loff[ITEMS];
+    uint64_t* gsp[ITEMS];
+    static_for<0, ITEMS>([&](auto kk) {
+      constexpr int k = decltype(kk)::value;
+      loff[k] = -1;
+      gsp[k] = nullptr;
+      if (!((keep >> k) & 1u)) return;
+      if (!special[k]) {
+        uint32_t s = (uint32_t)slot_of(key[k], (uint64_t)lcap);
+        for (int p = 0; p < kLdsProbes; ++p) {
+          const int off = (int)s * nw;
+          const uint64_t kv = s_tab[off];
+          if (kv == key[k]) {
+            loff[k] = off;
+            break;
+          }
+          if (kv == kEmpty) {
+            const uint64_t prev = atomicCAS((unsigned long long*)&s_tab[off], (unsigned long long)kEmpty,
+                                            (unsigned long long)key[k]);
+            if (prev == kEmpty || prev == key[k]) {
+              loff[k] = off;
+              break;
+            }
+          }
+          s = (s + 1) & (uint32_t)(lcap - 1);
+        }
+      }
+      if (loff[k] < 0) {
+        gsp[k] = global_slot(a, key[k], special[k]);
+        if (!gsp[k]) keep &= ~(1u << k);
+      }
+    });
+    apply_rows<ITEMS>(a.ap, r0, a.n, keep, w, s_tab, loff, gsp);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < lcap; i += BLOCK) {
+    const uint64_t* ls = s_tab + (size_t)i * nw;
+    if (ls[0] == kEmpty) continue;
+    uint64_t* gs = global_slot(a, ls[0], 0);
+    if (gs) merge_words(a.ap, gs, ls);
+  }
+}
+
+template <int BLOCK, int ITEMS>
+__global__ __launch_bounds__(BLOCK) void k_groupjoin(const GbArgs a) {
+  constexpr int TILE = BLOCK * ITEMS;
+  const int64_t r0 = (int64_t)blockIdx.x * TILE + (int64_t)threadIdx.x * ITEMS;
+  uint32_t keep = eval_preds<ITEMS>(a, r0);
+  if (!keep) return;
+  int64_t kv[ITEMS];
+  load_items<ITEMS>(a.join.key, r0, a.n, kv);
+  if (a.join.key.valid) keep &= valid_items<ITEMS>(a.join.key, r0, a.n);
+  uint32_t w[ITEMS];
+  int loff[ITEMS];
+  uint64_t* gsp[ITEMS];
+  static_for<0, ITEMS>([&](auto kk) {
+    constexpr int k = decltype(kk)::value;
+    loff[k] = -1;
+    gsp[k] = nullptr;
+    w[k] = 0;
+    if (!((keep >> k) & 1u)) return;
+    const uint64_t* s = join_lookup(a.join, (uint64_t)kv[k]);
+    if (s) w[k] = slot_count(s);
+    if (w[k] == 0) {
+      keep &= ~(1u << k);
+      return;
+    }
+    gsp[k] = const_cast<uint64_t*>(s) + 1;  // acc[1] = slot word 2, the hidden count
+  });
+  if (!keep) return;
+  apply_rows<ITEMS>(a.ap, r0, a.n, keep, w, nullptr, loff, gsp);
+}
+
+// ---------------------------------------------------------------------------
+// Compaction of a table into the output batch
+// ---------------------------------------------------------------------------
+__global__ void k_compact_init(uint32_t* ticket, uint64_t* status, int64_t ntiles, int64_t* d_count) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  if (i == 0) {
+    *ticket = 0;
+    *d_count = 0;
+  }
+  for (; i < ntiles; i += stride) status[i] = 0;
+}
+
+template <int BLOCK, int ITEMS>
+__global__ __launch_bounds__(BLOCK) void k_compact(const CompactArgs a) {
+  constexpr int TILE = BLOCK * ITEMS;
+  constexpr int NW = BLOCK / kWave;
+  __shared__ uint32_t s_tile;
+  __shared__ uint32_t s_wave[NW];
+  __shared__ int64_t s_excl;
+  __shared__ __attribute__((aligned(16))) uint8_t s_stage[TILE * 8];
+  __shared__ uint8_t s_vbyte[TILE];
+
+  if (threadIdx.x == 0) s_tile = atomicAdd(a.ticket, 1u);
+  __syncthreads();
+  const int64_t tile = s_tile;
+  const uint64_t cap = a.d_cap ? *a.d_cap : a.cap;
+  const int64_t total_idx = (int64_t)cap + a.extra;
+  const int64_t i0 = tile * TILE + (int64_t)threadIdx.x * ITEMS;
+  const uint64_t* sp[ITEMS];
+  uint32_t keep = 0;
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k) {
+    const int64_t i = i0 + k;
+    sp[k] = nullptr;
+    if (i < total_idx) {
+      const bool extra = i >= (int64_t)cap;
+      const uint64_t s = extra ? a.max_cap + (uint64_t)(i - (int64_t)cap) : (uint64_t)i;
+      const uint64_t* slot = a.slots + s * a.stride;
+      const uint64_t* acc = slot + (a.acc_base - 1);
+      bool occ;
+      if (a.key_kind == 2) occ = acc[1] != 0;            // group-join: matched rows
+      else occ = extra ? acc[1] != 0 : slot[0] != kEmpty;
+      if (occ) {
+        keep |= 1u << k;
+        sp[k] = slot;
+      }
+    }
+  }
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  uint32_t wtot;
+  const uint32_t wpre = wave_prefix_small<4>((uint32_t)__popc(keep), &wtot);
+  if (lane == 0) s_wave[wave] = wtot;
+  __syncthreads();
+  uint32_t bpre = 0, btot = 0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) {
+    if (i < wave) bpre += s_wave[i];
+    btot += s_wave[i];
+  }
+  const int local = (int)(bpre + wpre);
+  if (wave == 0) {
+    int64_t e = lookback_exclusive(a.status, tile, (int64_t)btot);
+    if (lane == 0) s_excl = e;
+  }
+  __syncthreads();
+  const int64_t goff = s_excl;
+  const int nk = a.key_kind == 2 ? 1 : a.kp.nk;
+  const int ncols = nk + a.naggs;
+  if (tile == a.ntiles - 1 && threadIdx.x == 0) {
+    int64_t total = goff + btot;
+    if (total == 0 && a.global_agg) {
+      // SQL: an aggregate without GROUP BY returns one row even for no input.
+      for (int j = 0; j < a.naggs; ++j) {
+        const OCol& o = a.out[j];
+        const bool cnt = a.aggs[j].op == GQ_COUNT || a.aggs[j].op == GQ_COUNT_STAR;
+        if (a.out_cap >= 1) {
+          reinterpret_cast<int64_t*>(o.data)[0] = 0;
+          if (o.valid) o.valid[0] = cnt ? (o.valid[0] | 1u) : (o.valid[0] & ~1u);
+        }
+      }
+      total = 1;
+    }
+    *a.d_count = total;
+    if (total > a.out_cap) atomicOr(a.dev_status, GQ_DEV_CAPACITY);
+  }
+  if (btot == 0) return;
+
+  for (int j = 0; j < ncols; ++j) {
+    const OCol& o = a.out[j];
+    int pos = local;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      if (!((keep >> k) & 1u)) continue;
+      const uint64_t* slot = sp[k];
+      int64_t v = 0;
+      bool ok = true;
+      if (j < nk) {
+        const bool extra = slot >= a.slots + a.max_cap * a.stride;
+        if (a.key_kind == 2) {
+          v = extra ? -1 : (int64_t)slot[0];
+        } else if (a.kp.mode == KEY_RAW64) {
+          if (extra) {
+            const bool is_null = slot == a.slots + (a.max_cap + 1) * a.stride;
+            v = is_null ? 0 : -1;
+            ok = !is_null;
+          } else {
+            v = (int64_t)slot[0];
+          }
+        } else {
+          v = decode_field(a.kp, slot[0], j, &ok);
+        }
+      } else {
+        const DAgg& ag = a.aggs[j - nk];
+        const uint64_t* acc = slot + (a.acc_base - 1);
+        v = (int64_t)acc[ag.word];
+        if ((ag.op == GQ_SUM || ag.op == GQ_MIN || ag.op == GQ_MAX) && ag.cword >= 0) ok = acc[ag.cword] != 0;
+        if (!ok) v = 0;
+      }
+      stage_put(s_stage, pos, v, o.type);
+      s_vbyte[pos] = ok ? 1 : 0;
+      ++pos;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < (int)btot; i += BLOCK) {
+      const int64_t g = goff + i;
+      if (g < a.out_cap) copy_out(s_stage, i, o.data, g, o.type);
+    }
+    if (o.valid) write_valid_bits<BLOCK>(o.valid, s_vbyte, goff, (int)btot, a.out_cap);
+    __syncthreads();
+  }
+}
+
+constexpr int kCBlock = 256, kCItems = 8;
+
+// ---------------------------------------------------------------------------
+// Host-side plans
+// ---------------------------------------------------------------------------
+int make_preds(gq_ctx* ctx, GbArgs& a, const gq_batch* in, const gq_pred* preds, int npreds) {
+  if (npreds < 0 || npreds > GQ_MAX_PREDS || (npreds > 0 && !preds))
+    return set_error(ctx, GQ_ERR_INVALID, "group-by: bad predicate list");
+  a.npreds = npreds;
+  for (int p = 0; p < npreds; ++p) {
+    if (preds[p].col < 0 || preds[p].col >= in->ncols)
+      return set_error(ctx, GQ_ERR_INVALID, "group-by: predicate column out of range");
+    if (preds[p].op != GQ_RANGE && preds[p].op != GQ_NE)
+      return set_error(ctx, GQ_ERR_INVALID, "group-by: unknown predicate op");
+    a.preds[p] = DPred{preds[p].col, preds[p].op, preds[p].lo, preds[p].hi};
+    a.pcols[p] = make_dcol(in->cols[preds[p].col]);
+  }
+  return GQ_OK;
+}
+
+int make_key_plan(gq_ctx* ctx, KeyPlan& kp, const gq_batch* in, const int32_t* keys, int nk) {
+  if (nk < 0 || nk > GQ_MAX_KEYS || (nk > 0 && !keys))
+    return set_error(ctx, GQ_ERR_INVALID, "group-by: bad key list");
+  kp.nk = nk;
+  for (int j = 0; j < nk; ++j) {
+    if (keys[j] < 0 || keys[j] >= in->ncols) return set_error(ctx, GQ_ERR_INVALID, "group-by: key column out of range");
+    kp.cols[j] = make_dcol(in->cols[keys[j]]);
+  }
+  if (nk == 1 && in->cols[keys[0]].type == GQ_I64) {
+    kp.mode = KEY_RAW64;
+    kp.bits[0] = 64;
+    kp.shift[0] = 0;
+    kp.nullable[0] = in->cols[keys[0]].validity != nullptr;
+    return GQ_OK;
+  }
+  kp.mode = KEY_PACKED;
+  int shift = 0;
+  for (int j = nk - 1; j >= 0; --j) {
+    const gq_column& c = in->cols[keys[j]];
+    kp.bits[j] = 8 * type_width(c.type);
+    kp.nullable[j] = c.validity != nullptr;
+    kp.shift[j] = shift;
+    shift += kp.bits[j] + kp.nullable[j];
+  }
+  if (shift > 63)
+    return set_error(ctx, GQ_ERR_UNSUPPORTED,
+                     "group-by: key columns wider than 63 bits together (use one int64 key column)");
+  return GQ_OK;
+}
+
+int make_agg_plan(gq_ctx* ctx, AggPlan& ap, const gq_batch* in, const gq_agg* aggs, int na) {
+  if (na < 0 || na > GQ_MAX_AGGS || (na > 0 && !aggs))
+    return set_error(ctx, GQ_ERR_INVALID, "group-by: bad aggregate list");
+  ap.naggs = na;
+  ap.nvals = 0;
+  int cols[kMaxVals];
+  int word = 2;
+  ap.wop[1] = WOP_ADD;
+  for (int i = 0; i < na; ++i) {
+    const gq_agg& g = aggs[i];
+    DAgg& d = ap.aggs[i];
+    d.op = g.op;
+    d.nf = 0;
+    d.cword = -1;
+    if (g.op < GQ_SUM || g.op > GQ_MAX) return set_error(ctx, GQ_ERR_INVALID, "group-by: unknown aggregate");
+    if (g.op == GQ_COUNT_STAR) {
+      d.word = 1;
+      continue;
+    }
+    if (g.nfactors < 0 || g.nfactors > 3) return set_error(ctx, GQ_ERR_INVALID, "group-by: 0..3 factors");
+    bool nullable = false;
+    d.nf = g.nfactors;
+    for (int f = 0; f < g.nfactors; ++f) {
+      const gq_factor& fa = g.f[f];
+      if (fa.kind < GQ_F_COL || fa.kind > GQ_F_CONST) return set_error(ctx, GQ_ERR_INVALID, "group-by: bad factor");
+      d.f[f].kind = fa.kind;
+      d.f[f].k = fa.k;
+      d.f[f].v = 0;
+      if (fa.kind == GQ_F_CONST) continue;
+      if (fa.col < 0 || fa.col >= in->ncols) return set_error(ctx, GQ_ERR_INVALID, "group-by: factor column out of range");
+      int vi = -1;
+      for (int q = 0; q < ap.nvals; ++q)
+        if (cols[q] == fa.col) vi = q;
+      if (vi < 0) {
+        if (ap.nvals == kMaxVals) return set_error(ctx, GQ_ERR_UNSUPPORTED, "group-by: more than 8 value columns");
+        vi = ap.nvals++;
+        cols[vi] = fa.col;
+        ap.vals[vi] = make_dcol(in->cols[fa.col]);
+      }
+      d.f[f].v = vi;
+      if (in->cols[fa.col].validity) nullable = true;
+    }
+    d.word = word++;
+    ap.wop[d.word] = g.op == GQ_MIN ? WOP_MIN : g.op == GQ_MAX ? WOP_MAX : WOP_ADD;
+    if (nullable && g.op != GQ_COUNT) {
+      d.cword = word++;
+      ap.wop[d.cword] = WOP_ADD;
+    }
+  }
+  ap.nwords = word;
+  return GQ_OK;
+}
+
+int check_outputs(gq_ctx* ctx, const gq_batch* in, const KeyPlan& kp, const int32_t* keys, int nk_out, int na,
+                  gq_batch* out, CompactArgs& ca, const int* key_types) {
+  if (!out || out->ncols < nk_out + na || (nk_out + na > 0 && !out->cols))
+    return set_error(ctx, GQ_ERR_INVALID, "group-by: output needs key and aggregate columns");
+  int64_t cap = INT64_MAX;
+  for (int j = 0; j < nk_out + na; ++j) {
+    const gq_column& oc = out->cols[j];
+    const int want = j < nk_out ? key_types[j] : GQ_I64;
+    if (oc.type != want) return set_error(ctx, GQ_ERR_INVALID, "group-by: output column type mismatch");
+    if (oc.length < 0 || (oc.length > 0 && !oc.data)) return set_error(ctx, GQ_ERR_INVALID, "group-by: bad output column");
+    if (oc.validity && (reinterpret_cast<uintptr_t>(oc.validity) & 3))
+      return set_error(ctx, GQ_ERR_INVALID, "group-by: output bitmap must be 4-byte aligned");
+    if (oc.offset != 0) return set_error(ctx, GQ_ERR_INVALID, "group-by: output offset must be 0");
+    ca.out[j] = OCol{static_cast<uint8_t*>(oc.data), reinterpret_cast<uint32_t*>(oc.validity), oc.type, 0};
+    if (oc.length < cap) cap = oc.length;
+  }
+  ca.out_cap = cap;
+  return GQ_OK;
+}
+
+int compact_launch(gq_ctx* ctx, CompactArgs& ca, int64_t* d_groups, hipStream_t stream) {
+  constexpr int TILE = kCBlock * kCItems;
+  const int64_t nidx = (int64_t)ca.max_cap + ca.extra;
+  const int64_t ntiles = (nidx + TILE - 1) / TILE;
+  ca.ntiles = ntiles;
+  ca.d_count = d_groups;
+  ca.dev_status = ctx->d_status;
+  Scratch ws(ctx, stream);
+  if (!ws.get(256 + align_up((size_t)ntiles * 8, 256)))
+    return set_error(ctx, GQ_ERR_NOMEM, "group-by: compaction workspace allocation failed");
+  ca.ticket = ws.as<uint32_t>(0);
+  ca.status = ws.as<uint64_t>(256);
+  int64_t iblocks = (ntiles + 255) / 256;
+  if (iblocks < 1) iblocks = 1;
+  if (iblocks > 4096) iblocks = 4096;
+  GQ_LAUNCH(ctx, "compact_init", k_compact_init, dim3((unsigned)iblocks), dim3(256), 0, stream, ca.ticket, ca.status, ntiles,
+                     d_groups);
+  GQ_LAUNCH_CHECK(ctx);
+  GQ_LAUNCH(ctx, "compact", (k_compact<kCBlock, kCItems>), dim3((unsigned)ntiles), dim3(kCBlock), 0, stream, ca);
+  GQ_LAUNCH_CHECK(ctx);
+  return GQ_OK;
+}
+
+template <bool JOIN>
+int launch_aggregate(gq_ctx* ctx, GbArgs& a, int strategy, int block_size, hipStream_t stream) {
+  (void)block_size;
+  constexpr int TILE = kGbBlock * kGbItems;
+  a.ntiles = (a.n + TILE - 1) / TILE;
+  if (a.ntiles == 0) return GQ_OK;
+  if (strategy == GQ_STRATEGY_LDS) {
+    int lcap = 1;
+    while ((size_t)(lcap * 2) * a.ap.nwords * 8 <= kLdsBudget) lcap *= 2;
+    a.lcap = lcap;
+    const size_t lds = (size_t)lcap * a.ap.nwords * 8;
+    int64_t grid = a.ntiles < 512 ? a.ntiles : 512;
+    GQ_LAUNCH(ctx, "gb_lds", (k_gb_lds<kGbBlock, kGbItems, JOIN>), dim3((unsigned)grid), dim3(kGbBlock), lds, stream, a);
+  } else {
+    GQ_LAUNCH(ctx, "gb_global", (k_gb_global<kGbBlock, kGbItems, JOIN>), dim3((unsigned)a.ntiles), dim3(kGbBlock), 0, stream,
+                       a);
+  }
+  GQ_LAUNCH_CHECK(ctx);
+  return GQ_OK;
+}
+
+int run_groupby(gq_ctx* ctx, const gq_batch* in, const int32_t* keys, int nkeys, const gq_pred* preds, int npreds,
+                const gq_agg* aggs, int naggs, const gq_groupby_opts* opts, const gq_join_table* join,
+                int32_t probe_key, gq_batch* out, int64_t* d_groups, hipStream_t stream) {
+  if (!ctx) return GQ_ERR_INVALID;
+  int rc = check_batch(ctx, in, "group-by input");
+  if (rc) return rc;
+  if (!d_groups) return set_error(ctx, GQ_ERR_INVALID, "group-by: NULL group count");
+  gq_groupby_opts o{};
+  if (opts) o = *opts;
+  if (o.flags & GQ_SORTED) return set_error(ctx, GQ_ERR_UNSUPPORTED, "group-by: GQ_SORTED output is not implemented");
+  const float lf = o.load_factor > 0.f ? o.load_factor : 0.5f;
+  if (!(lf > 0.f && lf <= 0.9f)) return set_error(ctx, GQ_ERR_INVALID, "group-by: load factor outside (0, 0.9]");
+  if (o.strategy < GQ_STRATEGY_AUTO || o.strategy > GQ_STRATEGY_GLOBAL)
+    return set_error(ctx, GQ_ERR_INVALID, "group-by: unknown strategy");
+
+  GbArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.n = in->nrows;
+  a.dev_status = ctx->d_status;
+  rc = make_preds(ctx, a, in, preds, npreds);
+  if (rc) return rc;
+  rc = make_key_plan(ctx, a.kp, in, keys, nkeys);
+  if (rc) return rc;
+  rc = make_agg_plan(ctx, a.ap, in, aggs, naggs);
+  if (rc) return rc;
+  if (join) {
+    if (probe_key < 0 || probe_key >= in->ncols) return set_error(ctx, GQ_ERR_INVALID, "pipeline: probe key out of range");
+    if (join->device != ctx->device) return set_error(ctx, GQ_ERR_INVALID, "pipeline: join table on another device");
+    a.join.hdr = join->hdr;
+    a.join.slots = join->slots;
+    a.join.max_cap = join->max_cap;
+    a.join.stride = join->stride;
+    a.join.key = make_dcol(in->cols[probe_key]);
+  }
+
+  GQ_HIP_CHECK(ctx, hipSetDevice(ctx->device));
+  CompactArgs ca;
+  std::memset(&ca, 0, sizeof(ca));
+  ca.naggs = naggs;
+  for (int i = 0; i < naggs; ++i) ca.aggs[i] = a.ap.aggs[i];
+  ca.global_agg = nkeys == 0;
+
+  // Group-join: the only key is the probe key and the table has room.
+  const bool groupjoin = join && nkeys == 1 && keys[0] == probe_key && join->acc_slots >= a.ap.nwords - 1;
+  if (groupjoin) {
+    int kt[1] = {in->cols[probe_key].type};
+    rc = check_outputs(ctx, in, a.kp, keys, 1, naggs, out, ca, kt);
+    if (rc) return rc;
+    // A fresh table has zeroed accumulators; MIN/MAX identities or a table
+    // already used by a group-join need the init pass.
+    bool need_init = join->acc_dirty;
+    for (int w = 1; w < a.ap.nwords; ++w) need_init |= a.ap.wop[w] != WOP_ADD;
+    if (need_init) {
+      int64_t blocks = (int64_t)((join->max_cap + 1 + 255) / 256);
+      if (blocks > 8192) blocks = 8192;
+      GQ_LAUNCH(ctx, "gj_init", k_gj_init, dim3((unsigned)blocks), dim3(256), 0, stream, a.join, a.ap);
+      GQ_LAUNCH_CHECK(ctx);
+    }
+    const_cast<gq_join_table*>(join)->acc_dirty = true;
+    constexpr int TILE = kGbBlock * kGbItems;
+    a.ntiles = (a.n + TILE - 1) / TILE;
+    if (a.ntiles > 0) {
+      GQ_LAUNCH(ctx, "groupjoin", (k_groupjoin<kGbBlock, kGbItems>), dim3((unsigned)a.ntiles), dim3(kGbBlock), 0, stream, a);
+      GQ_LAUNCH_CHECK(ctx);
+    }
+    ca.slots = join->slots;
+    ca.d_cap = &join->hdr->cap;
+    ca.max_cap = join->max_cap;
+    ca.stride = join->stride;
+    ca.acc_base = 2;
+    ca.key_kind = 2;
+    ca.extra = 1;
+    ca.global_agg = 0;
+    return compact_launch(ctx, ca, d_groups, stream);
+  }
+
+  int key_types[GQ_MAX_KEYS];
+  for (int j = 0; j < nkeys; ++j) key_types[j] = in->cols[keys[j]].type;
+  rc = check_outputs(ctx, in, a.kp, keys, nkeys, naggs, out, ca, key_types);
+  if (rc) return rc;
+
+  // Table sizing.
+  int64_t expected = o.expected_groups > 0 ? o.expected_groups : in->nrows;
+  if (nkeys == 0) expected = 1;
+  uint64_t cap = (uint64_t)((double)expected / lf) + 1;
+  if (cap < 16) cap = 16;
+  int stride = 2;
+  while (stride < a.ap.nwords) stride *= 2;
+  if (stride > 8) stride = (a.ap.nwords + 7) / 8 * 8;
+  a.cap = cap;
+  a.stride = stride;
+  const size_t bytes = (size_t)(cap + 2) * stride * 8;
+  Scratch table(ctx, stream);
+  if (!table.get(bytes)) return set_error(ctx, GQ_ERR_NOMEM, "group-by: table allocation failed");
+  a.slots = table.as<uint64_t>(0);
+  int64_t iblocks = (int64_t)((cap + 2 + 255) / 256);
+  if (iblocks > 8192) iblocks = 8192;
+  GQ_LAUNCH(ctx, "gt_init", k_gt_init, dim3((unsigned)iblocks), dim3(256), 0, stream, a.slots, (int64_t)(cap + 2), stride,
+                     a.ap);
+  GQ_LAUNCH_CHECK(ctx);
+
+  int strategy = o.strategy;
+  if (strategy == GQ_STRATEGY_AUTO) strategy = expected <= 256 ? GQ_STRATEGY_LDS : GQ_STRATEGY_GLOBAL;
+  rc = join ? launch_aggregate<true>(ctx, a, strategy, o.block_size, stream)
+            : launch_aggregate<false>(ctx, a, strategy, o.block_size, stream);
+  if (rc) return rc;
+
+  ca.slots = a.slots;
+  ca.d_cap = nullptr;
+  ca.cap = cap;
+  ca.max_cap = cap;
+  ca.stride = stride;
+  ca.acc_base = 1;
+  ca.key_kind = a.kp.mode == KEY_RAW64 ? 1 : 0;
+  ca.kp = a.kp;
+  ca.extra = 2;
+  return compact_launch(ctx, ca, d_groups, stream);
+}
+
+}  // namespace
+}  // namespace gq
+
+using namespace gq;
+
+extern "C" {
+
+int gq_groupby_agg(gq_ctx* ctx, const gq_batch* in, const int32_t* keys, int nkeys, const gq_pred* preds, int npreds,
+                   const gq_agg* aggs, int naggs, const gq_groupby_opts* opts, gq_batch* out, int64_t* d_groups,
+                   hipStream_t stream) {
+  return run_groupby(ctx, in, keys, nkeys, preds, npreds, aggs, naggs, opts, nullptr, 0, out, d_groups, stream);
+}
+
+int gq_pipeline(gq_ctx* ctx, const gq_plan* plan, const gq_batch* in, gq_batch* out, int64_t* d_groups,
+                hipStream_t stream) {
+  if (!ctx) return GQ_ERR_INVALID;
+  if (!plan) return set_error(ctx, GQ_ERR_INVALID, "gq_pipeline: NULL plan");
+  return run_groupby(ctx, in, plan->group_keys, plan->ngroup_keys, plan->preds, plan->npreds, plan->aggs, plan->naggs,
+                     &plan->opts, plan->join, plan->probe_key, out, d_groups, stream);
+}
+
+}  // extern "C"

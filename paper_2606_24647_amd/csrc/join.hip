@@ -1,0 +1,698 @@
+// Hash join: gq_join_build, gq_join_probe, gq_gather.
+//
+// Build (all on the caller's stream, no host synchronisation):
+//  1. k_jcount       count build rows that pass the predicates with a non-NULL key
+//  2. k_jinit        size the table on the device from that count
+//                    (cap = ceil(count / load factor)) and clear its slots
+//  3. k_jinsert      CAS the key into its slot; the first inserter stores its row,
+//                    every inserter bumps the slot's count; a second inserter of a
+//                    key marks the table as having duplicates
+//  4. duplicates only (every kernel below returns at once otherwise):
+//     k_jdup_scan    exclusive scan of slot counts -> start of each key's run
+//     k_jdup_fill    place every build row in its key's run (atomic cursor)
+//     k_jdup_sort    sort each run by row: short runs in one thread, long runs
+//                    by a block-wide merge sort, so runs hold ascending rows
+// Probe: per probe row, the match count from the table, a decoupled look-back
+// scan of the counts, then (probe row, build row) pairs in canonical order.
+#include "table.h"
+
+namespace gq {
+namespace {
+
+constexpr int kJBlock = 256;
+constexpr int kJItems = 8;
+constexpr int kShortRun = 32;
+
+struct JoinBuildArgs {
+  int64_t n;
+  DCol key;
+  int32_t npreds;
+  int32_t lf_milli;  // load factor * 1000
+  DPred preds[GQ_MAX_PREDS];
+  DCol pcols[GQ_MAX_PREDS];
+  JoinHdr* hdr;
+  uint64_t* slots;
+  int32_t* rows;
+  uint32_t* aux;
+  int32_t* tmp;
+  uint64_t max_cap;
+  int32_t stride;
+  int32_t acc_slots;
+  int32_t* dev_status;
+};
+
+// Keep mask of rows r0..r0+ITEMS-1 (predicates and a non-NULL key); key values.
+template <int ITEMS>
+__device__ __forceinline__ uint32_t build_rows_keep(const JoinBuildArgs& a, int64_t r0, int64_t (&key)[ITEMS]) {
+  uint32_t keep = 0;
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k)
+    if (r0 + k < a.n) keep |= 1u << k;
+  for (int p = 0; p < a.npreds; ++p) {
+    int64_t v[ITEMS];
+    load_items<ITEMS>(a.pcols[p], r0, a.n, v);
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k)
+      if (!pred_pass(a.preds[p], v[k])) keep &= ~(1u << k);
+    if (a.pcols[p].valid) keep &= valid_items<ITEMS>(a.pcols[p], r0, a.n);
+  }
+  load_items<ITEMS>(a.key, r0, a.n, key);
+  if (a.key.valid) keep &= valid_items<ITEMS>(a.key, r0, a.n);
+  return keep;
+}
+
+__global__ void k_jhdr_init(JoinHdr* hdr) {
+  if (threadIdx.x == 0) {
+    hdr->cap = 0;
+    hdr->nrows = 0;
+    hdr->has_dups = 0;
+    hdr->full = 0;
+    hdr->pad[0] = 0;  // long-run count
+  }
+}
+
+template <int BLOCK, int ITEMS>
+__global__ __launch_bounds__(BLOCK) void k_jcount(const JoinBuildArgs a) {
+  __shared__ uint32_t s_cnt;
+  if (threadIdx.x == 0) s_cnt = 0;
+  __syncthreads();
+  const int64_t r0 = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) * ITEMS;
+  int64_t key[ITEMS];
+  const uint32_t keep = build_rows_keep<ITEMS>(a, r0, key);
+  uint32_t tot;
+  wave_prefix_small<5>((uint32_t)__popc(keep), &tot);
+  if ((threadIdx.x & (kWave - 1)) == 0 && tot) atomicAdd(&s_cnt, tot);
+  __syncthreads();
+  if (threadIdx.x == 0 && s_cnt) atomicAdd((unsigned long long*)&a.hdr->nrows, (unsigned long long)s_cnt);
+}
+
+__device__ __forceinline__ uint64_t cap_for(int64_t n, int lf_milli, uint64_t max_cap) {
+  uint64_t c = ((uint64_t)n * 1000 + lf_milli - 1) / (uint64_t)lf_milli;
+  if (c < 1) c = 1;
+  if (c > max_cap) c = max_cap;
+  return c;
+}
+
+// Clear slots [0, cap) and the extra slot (index max_cap): key EMPTY, then
+// zero words (row/count and accumulators, whose initial values are written by
+// the pipeline that uses them).
+__global__ void k_jinit(const JoinBuildArgs a) {
+  const uint64_t cap = cap_for(a.hdr->nrows, a.lf_milli, a.max_cap);
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  if (i0 == 0) a.hdr->cap = cap;
+  for (int64_t i = i0; i <= (int64_t)cap; i += stride) {
+    const uint64_t s = (i == (int64_t)cap) ? a.max_cap : (uint64_t)i;
+    uint64_t* slot = a.slots + s * a.stride;
+    slot[0] = kEmpty;
+    for (int w = 1; w < a.stride; ++w) slot[w] = 0;
+  }
+}
+
+template <int BLOCK, int ITEMS>
+__global__ __launch_bounds__(BLOCK) void k_jinsert(const JoinBuildArgs a) {
+  const int64_t r0 = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) * ITEMS;
+  int64_t key[ITEMS];
+  const uint32_t keep = build_rows_keep<ITEMS>(a, r0, key);
+  if (!keep) return;
+  const uint64_t cap = a.hdr->cap;
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k) {
+    if (!((keep >> k) & 1u)) continue;
+    const uint64_t kv = (uint64_t)key[k];
+    const uint64_t row = (uint64_t)(r0 + k);
+    uint64_t* slot = nullptr;
+    if (kv == kEmpty) {
+      slot = a.slots + a.max_cap * a.stride;
+    } else {
+      slot = table_find_insert(a.slots, cap, a.stride, kv);
+      if (!slot) {
+        a.hdr->full = 1;
+        atomicOr(a.dev_status, GQ_DEV_TABLE_FULL);
+        continue;
+      }
+    }
+    // Count in the high half, row in the low half (stored by the first inserter).
+    const uint64_t old = atomicAdd((unsigned long long*)&slot[1], 1ull << 32);
+    if ((old >> 32) == 0)
+      atomicAdd((unsigned long long*)&slot[1], row);
+    else
+      a.hdr->has_dups = 1;
+  }
+}
+
+// Exclusive scan of slot counts over [0, cap) and the extra slot (entry cap).
+template <int BLOCK, int ITEMS>
+__global__ __launch_bounds__(BLOCK) void k_jdup_scan(const JoinBuildArgs a, uint32_t* ticket, uint64_t* status,
+                                                     int64_t nblocks) {
+  if (!a.hdr->has_dups) return;
+  constexpr int TILE = BLOCK * ITEMS;
+  constexpr int NW = BLOCK / kWave;
+  __shared__ uint32_t s_tile;
+  __shared__ int64_t s_wave[NW];
+  __shared__ int64_t s_excl;
+  if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
+  __syncthreads();
+  const int64_t tile = s_tile;
+  const uint64_t cap = a.hdr->cap;
+  const int64_t i0 = tile * TILE + (int64_t)threadIdx.x * ITEMS;
+  uint32_t c[ITEMS];
+  int64_t tsum = 0;
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k) {
+    const int64_t i = i0 + k;
+    c[k] = 0;
+    if (i <= (int64_t)cap) {
+      const uint64_t s = (i == (int64_t)cap) ? a.max_cap : (uint64_t)i;
+      const uint64_t* slot = a.slots + s * a.stride;
+      if (slot[0] != kEmpty || s == a.max_cap) c[k] = slot_count(slot);
+    }
+    tsum += c[k];
+  }
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  int64_t incl = tsum;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    int64_t y = __shfl_up(incl, o, kWave);
+    if (lane >= o) incl += y;
+  }
+  if (lane == kWave - 1) s_wave[wave] = incl;
+  __syncthreads();
+  int64_t bpre = 0, btot = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    if (w < wave) bpre += s_wave[w];
+    btot += s_wave[w];
+  }
+  if (wave == 0) {
+    int64_t e = lookback_exclusive(status, tile, btot);
+    if (lane == 0) s_excl = e;
+  }
+  __syncthreads();
+  int64_t run = s_excl + bpre + incl - tsum;
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k) {
+    const int64_t i = i0 + k;
+    if (i <= (int64_t)cap && c[k] > 0) {
+      const uint64_t s = (i == (int64_t)cap) ? a.max_cap : (uint64_t)i;
+      uint64_t* slot = a.slots + s * a.stride;
+      slot[1] = ((uint64_t)c[k] << 32) | (uint64_t)(uint32_t)run;  // start replaces the row
+      a.aux[s == a.max_cap ? cap : s] = (uint32_t)run;              // fill cursor
+    }
+    run += c[k];
+  }
+}
+
+template <int BLOCK, int ITEMS>
+__global__ __launch_bounds__(BLOCK) void k_jdup_fill(const JoinBuildArgs a) {
+  if (!a.hdr->has_dups) return;
+  const int64_t r0 = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) * ITEMS;
+  int64_t key[ITEMS];
+  const uint32_t keep = build_rows_keep<ITEMS>(a, r0, key);
+  const uint64_t cap = a.hdr->cap;
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k) {
+    if (!((keep >> k) & 1u)) continue;
+    const uint64_t kv = (uint64_t)key[k];
+    uint64_t idx;
+    if (kv == kEmpty) {
+      idx = cap;
+    } else {
+      const uint64_t* slot = table_find(a.slots, cap, a.stride, kv);
+      if (!slot) continue;  // only after a full table, already reported
+      idx = (uint64_t)(slot - a.slots) / (uint64_t)a.stride;
+    }
+    const uint32_t pos = atomicAdd(&a.aux[idx], 1u);
+    a.rows[pos] = (int32_t)(r0 + k);
+  }
+}
+
+// Short runs: insertion sort by one thread.  Long runs go to a list in aux.
+__global__ void k_jdup_sort(const JoinBuildArgs a) {
+  if (!a.hdr->has_dups) return;
+  const uint64_t cap = a.hdr->cap;
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = i0; i <= (int64_t)cap; i += stride) {
+    const uint64_t s = (i == (int64_t)cap) ? a.max_cap : (uint64_t)i;
+    const uint64_t* slot = a.slots + s * a.stride;
+    if (s != a.max_cap && slot[0] == kEmpty) continue;
+    const uint32_t cnt = slot_count(slot);
+    if (cnt < 2) continue;
+    int32_t* r = a.rows + slot_row(slot);
+    if (cnt <= (uint32_t)kShortRun) {
+      for (uint32_t x = 1; x < cnt; ++x) {
+        const int32_t v = r[x];
+        int32_t y = (int32_t)x - 1;
+        while (y >= 0 && r[y] > v) {
+          r[y + 1] = r[y];
+          --y;
+        }
+        r[y + 1] = v;
+      }
+    } else {
+      const unsigned long long pos = atomicAdd((unsigned long long*)&a.hdr->pad[0], 1ull);
+      a.aux[pos] = (uint32_t)s;
+    }
+  }
+}
+
+// Long runs: one block per run, bottom-up merge sort between the run and tmp.
+// Each element finds its output place by binary search in the other half.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_jdup_sort_long(const JoinBuildArgs a) {
+  if (!a.hdr->has_dups) return;
+  const int64_t nlong = a.hdr->pad[0];
+  for (int64_t li = blockIdx.x; li < nlong; li += gridDim.x) {
+    const uint64_t s = a.aux[li];
+    const uint64_t* slot = a.slots + s * a.stride;
+    const uint32_t cnt = slot_count(slot);
+    const uint32_t start = slot_row(slot);
+    int32_t* src = a.rows + start;
+    int32_t* dst = a.tmp + start;
+    for (uint32_t w = 1; w < cnt; w <<= 1) {
+      for (uint32_t i = threadIdx.x; i < cnt; i += BLOCK) {
+        const uint32_t blk = i / (2 * w);
+        const uint32_t lo = blk * 2 * w;
+        const uint32_t mid = lo + w < cnt ? lo + w : cnt;
+        const uint32_t hi = lo + 2 * w < cnt ? lo + 2 * w : cnt;
+        const int32_t v = src[i];
+        uint32_t pos;
+        if (i < mid) {
+          // elements of the right half smaller than v
+          uint32_t l = mid, h = hi;
+          while (l < h) {
+            const uint32_t m = (l + h) >> 1;
+            if (src[m] < v) l = m + 1; else h = m;
+          }
+          pos = lo + (i - lo) + (l - mid);
+        } else {
+          uint32_t l = lo, h = mid;
+          while (l < h) {
+            const uint32_t m = (l + h) >> 1;
+            if (src[m] < v) l = m + 1; else h = m;
+          }
+          pos = lo + (i - mid) + (l - lo);
+        }
+        dst[pos] = v;
+      }
+      __syncthreads();
+      int32_t* t = src;
+      src = dst;
+      dst = t;
+    }
+    if (src != a.rows + start) {
+      for (uint32_t i = threadIdx.x; i < cnt; i += BLOCK) dst[i] = src[i];
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Probe
+// ---------------------------------------------------------------------------
+struct ProbeArgs {
+  int64_t n;
+  int64_t ntiles;
+  int64_t out_cap;
+  DCol key;
+  int32_t npreds;
+  int32_t stride;
+  DPred preds[GQ_MAX_PREDS];
+  DCol pcols[GQ_MAX_PREDS];
+  const JoinHdr* hdr;
+  const uint64_t* slots;
+  const int32_t* rows;
+  uint64_t max_cap;
+  int32_t* probe_idx;
+  int32_t* build_idx;
+  uint32_t* ticket;
+  uint64_t* status;
+  int64_t* d_count;
+  int32_t* dev_status;
+};
+
+__global__ void k_probe_init(uint32_t* ticket, uint64_t* status, int64_t ntiles, int64_t* d_count) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  if (i == 0) {
+    *ticket = 0;
+    *d_count = 0;
+  }
+  for (; i < ntiles; i += stride) status[i] = 0;
+}
+
+template <int BLOCK, int ITEMS>
+__global__ __launch_bounds__(BLOCK) void k_jprobe(const ProbeArgs a) {
+  constexpr int NW = BLOCK / kWave;
+  constexpr int TILE = BLOCK * ITEMS;
+  __shared__ uint32_t s_tile;
+  __shared__ int64_t s_wave[NW];
+  __shared__ int64_t s_excl;
+  if (threadIdx.x == 0) s_tile = atomicAdd(a.ticket, 1u);
+  __syncthreads();
+  const int64_t tile = s_tile;
+  const int64_t r0 = tile * TILE + (int64_t)threadIdx.x * ITEMS;
+
+  uint32_t keep = 0;
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k)
+    if (r0 + k < a.n) keep |= 1u << k;
+  for (int p = 0; p < a.npreds; ++p) {
+    int64_t v[ITEMS];
+    load_items<ITEMS>(a.pcols[p], r0, a.n, v);
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k)
+      if (!pred_pass(a.preds[p], v[k])) keep &= ~(1u << k);
+    if (a.pcols[p].valid) keep &= valid_items<ITEMS>(a.pcols[p], r0, a.n);
+  }
+  int64_t key[ITEMS];
+  load_items<ITEMS>(a.key, r0, a.n, key);
+  if (a.key.valid) keep &= valid_items<ITEMS>(a.key, r0, a.n);
+
+  const uint64_t cap = a.hdr->cap;
+  const bool dups = a.hdr->has_dups != 0;
+  uint32_t cnt[ITEMS], start[ITEMS];
+  int64_t tsum = 0;
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k) {
+    cnt[k] = 0;
+    start[k] = 0;
+    if ((keep >> k) & 1u) {
+      const uint64_t kv = (uint64_t)key[k];
+      const uint64_t* slot = kv == kEmpty ? a.slots + a.max_cap * a.stride : table_find(a.slots, cap, a.stride, kv);
+      if (slot) {
+        const uint64_t w1 = slot[1];
+        cnt[k] = (uint32_t)(w1 >> 32);
+        start[k] = (uint32_t)w1;
+      }
+    }
+    tsum += cnt[k];
+  }
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  int64_t incl = tsum;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    int64_t y = __shfl_up(incl, o, kWave);
+    if (lane >= o) incl += y;
+  }
+  if (lane == kWave - 1) s_wave[wave] = incl;
+  __syncthreads();
+  int64_t bpre = 0, btot = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    if (w < wave) bpre += s_wave[w];
+    btot += s_wave[w];
+  }
+  if (wave == 0) {
+    int64_t e = lookback_exclusive(a.status, tile, btot);
+    if (lane == 0) s_excl = e;
+  }
+  __syncthreads();
+  if (tile == a.ntiles - 1 && threadIdx.x == 0) {
+    const int64_t total = s_excl + btot;
+    *a.d_count = total;
+    if (total > a.out_cap) atomicOr(a.dev_status, GQ_DEV_CAPACITY);
+  }
+  int64_t pos = s_excl + bpre + incl - tsum;
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k) {
+    for (uint32_t j = 0; j < cnt[k]; ++j, ++pos) {
+      if (pos >= a.out_cap) break;
+      a.probe_idx[pos] = (int32_t)(r0 + k);
+      a.build_idx[pos] = dups ? a.rows[start[k] + j] : (int32_t)start[k];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Gather
+// ---------------------------------------------------------------------------
+struct GatherArgs {
+  int64_t n;
+  int32_t ncols;
+  int32_t pad;
+  const int32_t* idx;
+  DCol cols[GQ_MAX_COLS];
+  OCol out[GQ_MAX_COLS];
+};
+
+__global__ void k_gather(const GatherArgs a) {
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t r = i0; r < a.n; r += stride) {
+    const int64_t src = a.idx[r];
+    for (int j = 0; j < a.ncols; ++j) {
+      const int64_t v = load_one(a.cols[j], src);
+      switch (a.out[j].type) {
+        case GQ_I8: a.out[j].data[r] = (uint8_t)v; break;
+        case GQ_I16: reinterpret_cast<int16_t*>(a.out[j].data)[r] = (int16_t)v; break;
+        case GQ_I32: reinterpret_cast<int32_t*>(a.out[j].data)[r] = (int32_t)v; break;
+        default: reinterpret_cast<int64_t*>(a.out[j].data)[r] = v; break;
+      }
+    }
+  }
+  // Validity: one thread per 32-row output word.
+  const int64_t nwords = (a.n + 31) / 32;
+  for (int64_t w = i0; w < nwords; w += stride) {
+    for (int j = 0; j < a.ncols; ++j) {
+      if (!a.out[j].valid) continue;
+      uint32_t bits = 0;
+      for (int b = 0; b < 32; ++b) {
+        const int64_t r = w * 32 + b;
+        if (r < a.n && valid_one(a.cols[j], a.idx[r])) bits |= 1u << b;
+      }
+      a.out[j].valid[w] = bits;
+    }
+  }
+}
+
+int fill_build_args(gq_ctx* ctx, JoinBuildArgs& a, const gq_batch* b, const int32_t* keys, int nkeys,
+                    const gq_pred* preds, int npreds) {
+  if (nkeys != 1 || !keys)
+    return set_error(ctx, GQ_ERR_UNSUPPORTED, "join: exactly one key column is supported");
+  if (keys[0] < 0 || keys[0] >= b->ncols) return set_error(ctx, GQ_ERR_INVALID, "join: key column out of range");
+  if (npreds < 0 || npreds > GQ_MAX_PREDS || (npreds > 0 && !preds))
+    return set_error(ctx, GQ_ERR_INVALID, "join: bad predicate list");
+  a.n = b->nrows;
+  a.key = make_dcol(b->cols[keys[0]]);
+  a.npreds = npreds;
+  for (int p = 0; p < npreds; ++p) {
+    if (preds[p].col < 0 || preds[p].col >= b->ncols)
+      return set_error(ctx, GQ_ERR_INVALID, "join: predicate column out of range");
+    if (preds[p].op != GQ_RANGE && preds[p].op != GQ_NE)
+      return set_error(ctx, GQ_ERR_INVALID, "join: unknown predicate op");
+    a.preds[p] = DPred{preds[p].col, preds[p].op, preds[p].lo, preds[p].hi};
+    a.pcols[p] = make_dcol(b->cols[preds[p].col]);
+  }
+  return GQ_OK;
+}
+
+}  // namespace
+}  // namespace gq
+
+using namespace gq;
+
+extern "C" {
+
+int gq_join_build(gq_ctx* ctx, const gq_batch* build, const int32_t* keys, int nkeys, const gq_pred* preds,
+                  int npreds, const gq_join_opts* opts, hipStream_t stream, gq_join_table** out) {
+  if (!ctx || !out) return GQ_ERR_INVALID;
+  *out = nullptr;
+  int rc = check_batch(ctx, build, "gq_join_build input");
+  if (rc) return rc;
+  JoinBuildArgs a;
+  std::memset(&a, 0, sizeof(a));
+  rc = fill_build_args(ctx, a, build, keys, nkeys, preds, npreds);
+  if (rc) return rc;
+  float lf = opts && opts->load_factor > 0.f ? opts->load_factor : 0.5f;
+  if (!(lf > 0.f && lf <= 0.9f)) return set_error(ctx, GQ_ERR_INVALID, "gq_join_build: load factor outside (0, 0.9]");
+  const int acc = opts ? opts->acc_slots : 0;
+  if (acc != 0 && acc != 2 && acc != 6)
+    return set_error(ctx, GQ_ERR_INVALID, "gq_join_build: acc_slots must be 0, 2 or 6");
+  a.lf_milli = (int)(lf * 1000.f + 0.5f);
+  if (a.lf_milli < 1) a.lf_milli = 1;
+  const int64_t n = build->nrows;
+  uint64_t max_cap = ((uint64_t)n * 1000 + a.lf_milli - 1) / (uint64_t)a.lf_milli;
+  if (max_cap < 1) max_cap = 1;
+  a.max_cap = max_cap;
+  a.stride = 2 + acc;
+  a.acc_slots = acc;
+
+  const size_t off_hdr = 0;
+  const size_t off_slots = 256;
+  const size_t slot_bytes = (size_t)(max_cap + 1) * a.stride * 8;
+  const size_t off_rows = align_up(off_slots + slot_bytes, 256);
+  const size_t off_aux = align_up(off_rows + (size_t)n * 4, 256);
+  const size_t off_tmp = align_up(off_aux + (size_t)(max_cap + 1) * 4, 256);
+  const size_t total = align_up(off_tmp + (size_t)n * 4, 256);
+
+  GQ_HIP_CHECK(ctx, hipSetDevice(ctx->device));
+  gq_join_table* t = new (std::nothrow) gq_join_table;
+  if (!t) return GQ_ERR_NOMEM;
+  t->ctx = ctx;
+  t->mem = ctx_alloc(ctx, total, stream);
+  if (!t->mem) {
+    delete t;
+    return set_error(ctx, GQ_ERR_NOMEM, "gq_join_build: table allocation failed");
+  }
+  t->bytes = total;
+  char* base = static_cast<char*>(t->mem);
+  t->hdr = reinterpret_cast<JoinHdr*>(base + off_hdr);
+  t->slots = reinterpret_cast<uint64_t*>(base + off_slots);
+  t->rows = reinterpret_cast<int32_t*>(base + off_rows);
+  t->aux = reinterpret_cast<uint32_t*>(base + off_aux);
+  t->tmp = reinterpret_cast<int32_t*>(base + off_tmp);
+  t->max_cap = max_cap;
+  t->stride = a.stride;
+  t->acc_slots = acc;
+  t->build_rows = n;
+  t->key_type = build->cols[keys[0]].type;
+  t->device = ctx->device;
+  a.hdr = t->hdr;
+  a.slots = t->slots;
+  a.rows = t->rows;
+  a.aux = t->aux;
+  a.tmp = t->tmp;
+  a.dev_status = ctx->d_status;
+
+  constexpr int TILE = kJBlock * kJItems;
+  const int64_t nblk = (n + TILE - 1) / TILE;
+  GQ_LAUNCH(ctx, "jhdr_init", k_jhdr_init, dim3(1), dim3(64), 0, stream, t->hdr);
+  GQ_LAUNCH_CHECK(ctx);
+  if (nblk > 0) {
+    GQ_LAUNCH(ctx, "jcount", (k_jcount<kJBlock, kJItems>), dim3((unsigned)nblk), dim3(kJBlock), 0, stream, a);
+    GQ_LAUNCH_CHECK(ctx);
+  }
+  int64_t iblocks = (int64_t)((max_cap + 1 + 255) / 256);
+  if (iblocks > 8192) iblocks = 8192;
+  GQ_LAUNCH(ctx, "jinit", k_jinit, dim3((unsigned)iblocks), dim3(256), 0, stream, a);
+  GQ_LAUNCH_CHECK(ctx);
+  if (nblk > 0) {
+    GQ_LAUNCH(ctx, "jinsert", (k_jinsert<kJBlock, kJItems>), dim3((unsigned)nblk), dim3(kJBlock), 0, stream, a);
+    GQ_LAUNCH_CHECK(ctx);
+    // Duplicate handling (kernels return at once when every key is unique).
+    constexpr int STILE = 256 * 16;
+    const int64_t nscan = (int64_t)((max_cap + 1 + STILE - 1) / STILE);
+    Scratch ws(ctx, stream);
+    if (!ws.get(256 + align_up((size_t)nscan * 8, 256))) {
+      gq_join_table_free(ctx, t, stream);
+      return set_error(ctx, GQ_ERR_NOMEM, "gq_join_build: workspace allocation failed");
+    }
+    rc = launch_fill_u32(ctx, ws.p, 0u, 64 + 2 * nscan, stream);
+    if (rc) return rc;
+    GQ_LAUNCH(ctx, "jdup_scan", (k_jdup_scan<256, 16>), dim3((unsigned)nscan), dim3(256), 0, stream, a, ws.as<uint32_t>(0),
+                       ws.as<uint64_t>(256), nscan);
+    GQ_LAUNCH_CHECK(ctx);
+    GQ_LAUNCH(ctx, "jdup_fill", (k_jdup_fill<kJBlock, kJItems>), dim3((unsigned)nblk), dim3(kJBlock), 0, stream, a);
+    GQ_LAUNCH_CHECK(ctx);
+    GQ_LAUNCH(ctx, "jdup_sort", k_jdup_sort, dim3((unsigned)iblocks), dim3(256), 0, stream, a);
+    GQ_LAUNCH_CHECK(ctx);
+    GQ_LAUNCH(ctx, "jdup_sort_long", (k_jdup_sort_long<1024>), dim3(64), dim3(1024), 0, stream, a);
+    GQ_LAUNCH_CHECK(ctx);
+  }
+  *out = t;
+  return GQ_OK;
+}
+
+int gq_join_probe(gq_ctx* ctx, const gq_join_table* table, const gq_batch* probe, const int32_t* keys, int nkeys,
+                  const gq_pred* preds, int npreds, int32_t* probe_idx, int32_t* build_idx, int64_t out_cap,
+                  int64_t* d_count, hipStream_t stream) {
+  if (!ctx || !table) return GQ_ERR_INVALID;
+  int rc = check_batch(ctx, probe, "gq_join_probe input");
+  if (rc) return rc;
+  if (!d_count || out_cap < 0 || (out_cap > 0 && (!probe_idx || !build_idx)))
+    return set_error(ctx, GQ_ERR_INVALID, "gq_join_probe: bad output");
+  JoinBuildArgs b;
+  std::memset(&b, 0, sizeof(b));
+  rc = fill_build_args(ctx, b, probe, keys, nkeys, preds, npreds);
+  if (rc) return rc;
+  ProbeArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.n = probe->nrows;
+  a.out_cap = out_cap;
+  a.key = b.key;
+  a.npreds = b.npreds;
+  for (int p = 0; p < b.npreds; ++p) {
+    a.preds[p] = b.preds[p];
+    a.pcols[p] = b.pcols[p];
+  }
+  a.stride = table->stride;
+  a.hdr = table->hdr;
+  a.slots = table->slots;
+  a.rows = table->rows;
+  a.max_cap = table->max_cap;
+  a.probe_idx = probe_idx;
+  a.build_idx = build_idx;
+  a.d_count = d_count;
+  a.dev_status = ctx->d_status;
+  constexpr int TILE = kJBlock * kJItems;
+  const int64_t ntiles = (a.n + TILE - 1) / TILE;
+  a.ntiles = ntiles;
+  GQ_HIP_CHECK(ctx, hipSetDevice(ctx->device));
+  Scratch ws(ctx, stream);
+  if (!ws.get(256 + align_up((size_t)(ntiles > 0 ? ntiles : 1) * 8, 256)))
+    return set_error(ctx, GQ_ERR_NOMEM, "gq_join_probe: workspace allocation failed");
+  a.ticket = ws.as<uint32_t>(0);
+  a.status = ws.as<uint64_t>(256);
+  int64_t iblocks = (ntiles + 255) / 256;
+  if (iblocks < 1) iblocks = 1;
+  if (iblocks > 4096) iblocks = 4096;
+  GQ_LAUNCH(ctx, "probe_init", k_probe_init, dim3((unsigned)iblocks), dim3(256), 0, stream, a.ticket, a.status, ntiles,
+                     d_count);
+  GQ_LAUNCH_CHECK(ctx);
+  if (ntiles > 0) {
+    GQ_LAUNCH(ctx, "jprobe", (k_jprobe<kJBlock, kJItems>), dim3((unsigned)ntiles), dim3(kJBlock), 0, stream, a);
+    GQ_LAUNCH_CHECK(ctx);
+  }
+  return GQ_OK;
+}
+
+const int64_t* gq_join_table_count_ptr(const gq_join_table* table) {
+  return table ? &table->hdr->nrows : nullptr;
+}
+
+int gq_join_table_free(gq_ctx* ctx, gq_join_table* table, hipStream_t stream) {
+  if (!table) return GQ_OK;
+  if (!ctx) ctx = table->ctx;
+  ctx_free(ctx, table->mem, table->bytes, stream);
+  delete table;
+  return GQ_OK;
+}
+
+int gq_gather(gq_ctx* ctx, const gq_batch* in, const int32_t* cols, int ncols, const int32_t* idx, int64_t n,
+              gq_batch* out, hipStream_t stream) {
+  if (!ctx) return GQ_ERR_INVALID;
+  int rc = check_batch(ctx, in, "gq_gather input");
+  if (rc) return rc;
+  if (ncols < 0 || ncols > GQ_MAX_COLS || (ncols > 0 && !cols) || n < 0 || (n > 0 && !idx) || !out ||
+      out->ncols < ncols)
+    return set_error(ctx, GQ_ERR_INVALID, "gq_gather: bad arguments");
+  GatherArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.n = n;
+  a.ncols = ncols;
+  a.idx = idx;
+  for (int j = 0; j < ncols; ++j) {
+    if (cols[j] < 0 || cols[j] >= in->ncols) return set_error(ctx, GQ_ERR_INVALID, "gq_gather: column out of range");
+    const gq_column& ic = in->cols[cols[j]];
+    const gq_column& oc = out->cols[j];
+    if (oc.type != ic.type || oc.length < n || (n > 0 && !oc.data))
+      return set_error(ctx, GQ_ERR_INVALID, "gq_gather: bad output column");
+    if (ic.validity && !oc.validity)
+      return set_error(ctx, GQ_ERR_INVALID, "gq_gather: nullable input needs an output bitmap");
+    if (oc.validity && (reinterpret_cast<uintptr_t>(oc.validity) & 3))
+      return set_error(ctx, GQ_ERR_INVALID, "gq_gather: output bitmap must be 4-byte aligned");
+    a.cols[j] = make_dcol(ic);
+    a.out[j] = OCol{static_cast<uint8_t*>(oc.data), reinterpret_cast<uint32_t*>(oc.validity), oc.type, 0};
+  }
+  if (n == 0 || ncols == 0) return GQ_OK;
+  GQ_HIP_CHECK(ctx, hipSetDevice(ctx->device));
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  GQ_LAUNCH(ctx, "gather", k_gather, dim3((unsigned)blocks), dim3(256), 0, stream, a);
+  GQ_LAUNCH_CHECK(ctx);
+  return GQ_OK;
+}
+
+}  // extern "C"

@@ -139,24 +139,6 @@ __global__ __launch_bounds__(BLOCK) void k_scan_counts(const uint32_t* counts, i
   if (tile == nblocks - 1 && threadIdx.x == 0) offsets[nparts] = s_excl + btot;
 }
 
-__device__ __forceinline__ void stage_put(uint8_t* stage, int pos, int64_t v, int type) {
-  switch (type) {
-    case GQ_I8: stage[pos] = (uint8_t)v; break;
-    case GQ_I16: reinterpret_cast<int16_t*>(stage)[pos] = (int16_t)v; break;
-    case GQ_I32: reinterpret_cast<int32_t*>(stage)[pos] = (int32_t)v; break;
-    default: reinterpret_cast<int64_t*>(stage)[pos] = v; break;
-  }
-}
-
-__device__ __forceinline__ void copy_out(const uint8_t* stage, int i, uint8_t* out, int64_t g, int type) {
-  switch (type) {
-    case GQ_I8: out[g] = stage[i]; break;
-    case GQ_I16: reinterpret_cast<int16_t*>(out)[g] = reinterpret_cast<const int16_t*>(stage)[i]; break;
-    case GQ_I32: reinterpret_cast<int32_t*>(out)[g] = reinterpret_cast<const int32_t*>(stage)[i]; break;
-    default: reinterpret_cast<int64_t*>(out)[g] = reinterpret_cast<const int64_t*>(stage)[i]; break;
-  }
-}
-
 template <int BLOCK, int ITEMS, int PMAX>
 __global__ __launch_bounds__(BLOCK) void k_part_scatter(const PartArgs a) {
   constexpr int TILE = BLOCK * ITEMS;
@@ -366,18 +348,18 @@ extern "C" int gq_hash_partition(gq_ctx* ctx, const gq_batch* in, const int32_t*
   rc = launch_fill_u32(ctx, status, 0u, 2 * nscan, stream);
   if (rc) return rc;
 
-  hipLaunchKernelGGL((k_part_hist<kHistBlock, kHistItems>), dim3((unsigned)ntiles), dim3(kHistBlock), 0,
+  GQ_LAUNCH(ctx, "part_hist", (k_part_hist<kHistBlock, kHistItems>), dim3((unsigned)ntiles), dim3(kHistBlock), 0,
                      stream, a);
   GQ_LAUNCH_CHECK(ctx);
-  hipLaunchKernelGGL((k_scan_counts<kScanBlock, kScanItems>), dim3((unsigned)nscan), dim3(kScanBlock), 0,
+  GQ_LAUNCH(ctx, "scan_counts", (k_scan_counts<kScanBlock, kScanItems>), dim3((unsigned)nscan), dim3(kScanBlock), 0,
                      stream, (const uint32_t*)a.counts, m, a.starts, ntiles, (int64_t)nparts, d_offsets,
                      ticket, status, nscan);
   GQ_LAUNCH_CHECK(ctx);
   if (nparts <= 256) {
-    hipLaunchKernelGGL((k_part_scatter<kScatBlock, kScatItems, 256>), dim3((unsigned)ntiles),
+    GQ_LAUNCH(ctx, "part_scatter", (k_part_scatter<kScatBlock, kScatItems, 256>), dim3((unsigned)ntiles),
                        dim3(kScatBlock), 0, stream, a);
   } else {
-    hipLaunchKernelGGL((k_part_scatter<kScatBlock, kScatItems, kPartMax>), dim3((unsigned)ntiles),
+    GQ_LAUNCH(ctx, "part_scatter", (k_part_scatter<kScatBlock, kScatItems, kPartMax>), dim3((unsigned)ntiles),
                        dim3(kScatBlock), 0, stream, a);
   }
   GQ_LAUNCH_CHECK(ctx);

@@ -1,0 +1,110 @@
+"""Device twin of the seeded input generator (libgqgen.so, csrc/gen.hip).
+
+Produces the same columns as ``datagen`` directly in device memory, for
+workloads too large to generate on the host and upload.  Input generation only.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+from . import datagen as dg
+from .gq import DevColumn, DevTable
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+GEN_PATH = os.path.join(_PKG, "libgqgen.so")
+if not os.path.exists(GEN_PATH):
+    raise ImportError(f"{GEN_PATH} is not built; run `python -m paper_2606_24647_amd.build`")
+_gen = C.CDLL(GEN_PATH)
+_P = C.c_void_p
+_gen.gqgen_uniform.argtypes = [_P, C.c_int, C.c_int64, C.c_uint64, C.c_uint64, C.c_int64, C.c_int64, C.c_int64, _P]
+_gen.gqgen_powerlaw.argtypes = [_P, C.c_int64, C.c_uint64, C.c_uint64, C.c_int64, C.c_int64, C.c_uint64, _P]
+_gen.gqgen_permutation.argtypes = [_P, C.c_int64, C.c_uint64, C.c_uint64, C.c_int64, C.c_int64, C.c_int64, _P]
+
+_WIDTH = {torch.int8: 1, torch.int16: 2, torch.int32: 4, torch.int64: 8}
+_NP2T = {"int8": torch.int8, "int16": torch.int16, "int32": torch.int32, "int64": torch.int64}
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise RuntimeError(f"device generator failed: {what}")
+
+
+def uniform(seed, col, start, n, lo, hi, dtype=torch.int64, out=None):
+    t = out if out is not None else torch.empty(max(1, n), dtype=dtype, device="cuda")[:n]
+    _check(_gen.gqgen_uniform(t.data_ptr() if n else None, _WIDTH[t.dtype], n, seed, col, start, lo, hi, _stream()),
+           "uniform")
+    return t
+
+
+def powerlaw(seed, col, start, n, N):
+    t = torch.empty(max(1, n), dtype=torch.int64, device="cuda")[:n]
+    _check(_gen.gqgen_powerlaw(t.data_ptr() if n else None, n, seed, col, start, N, dg.powerlaw_t1(N), _stream()),
+           "powerlaw")
+    return t
+
+
+def permutation(seed, col, start, n, N, add=0):
+    t = torch.empty(max(1, n), dtype=torch.int64, device="cuda")[:n]
+    _check(_gen.gqgen_permutation(t.data_ptr() if n else None, n, seed, col, start, N, add, _stream()), "permutation")
+    return t
+
+
+def _table(cols):
+    return DevTable([DevColumn(d, None, scale=sc) for d, sc in cols])
+
+
+def fact_c1(n=1_000_000, start=0, seed=1) -> DevTable:
+    return _table([
+        (uniform(seed, 0, start, n, 1, 50), 0),
+        (uniform(seed, 1, start, n, dg.PRICE_LO, dg.PRICE_HI), 2),
+        (uniform(seed, 2, start, n, 0, 10), 2),
+        (uniform(seed, 3, start, n, 0, dg.DATE_DAYS - 1, torch.int32), 0),
+        (uniform(seed, 4, start, n, 0, 2, torch.int8), 0),
+        (uniform(seed, 5, start, n, 0, 1, torch.int8), 0),
+    ])
+
+
+def fact_c2(n=60_000_000, nkeys=15_000_000, start=0, seed=2) -> DevTable:
+    return _table([
+        (uniform(seed, 0, start, n, 1, nkeys), 0),
+        (uniform(seed, 1, start, n, dg.PRICE_LO, dg.PRICE_HI), 2),
+        (uniform(seed, 2, start, n, 0, 10), 2),
+        (uniform(seed, 3, start, n, 0, dg.DATE_DAYS - 1, torch.int32), 0),
+    ])
+
+
+def dim_c2(n=15_000_000, start=0, seed=2, ckeys=None) -> DevTable:
+    ckeys = ckeys if ckeys is not None else max(1, n // 10)
+    m = n - start
+    return _table([
+        (permutation(seed, 16, start, m, n, add=1), 0),
+        (uniform(seed, 17, start, m, 0, dg.DIM_DATE_DAYS - 1, torch.int32), 0),
+        (uniform(seed, 18, start, m, 1, ckeys), 0),
+    ])
+
+
+def batch_c3(n=60_000_000, nkeys=15_000_000, start=0, seed=3) -> DevTable:
+    return _table([
+        (powerlaw(seed, 0, start, n, nkeys), 0),
+        (uniform(seed, 1, start, n, dg.PRICE_LO, dg.PRICE_HI), 0),
+        (uniform(seed, 2, start, n, 0, dg.DATE_DAYS - 1, torch.int32), 0),
+        (uniform(seed, 3, start, n, 0, 2, torch.int8), 0),
+    ])
+
+
+def fragment_c4(f, rows, card, seed=4) -> DevTable:
+    s = dg.fragment_seed(f, seed)
+    return _table([
+        (uniform(s, 0, 0, rows, 1, 50), 0),
+        (uniform(s, 1, 0, rows, dg.PRICE_LO, dg.PRICE_HI), 2),
+        (uniform(s, 2, 0, rows, 0, 10), 2),
+        (uniform(s, 3, 0, rows, 0, dg.DATE_DAYS - 1, torch.int32), 0),
+        (uniform(s, 4, 0, rows, 0, card - 1, torch.int32), 0),
+    ])

@@ -101,6 +101,8 @@ _SIGS = {
     "gq_last_error": (C.c_char_p, [_P]),
     "gq_ctx_sync_status": (C.c_int, [_P, _P, C.POINTER(C.c_int32)]),
     "gq_ctx_status_ptr": (_P, [_P]),
+    "gq_ctx_set_timing": (C.c_int, [_P, C.c_int]),
+    "gq_ctx_timing_report": (C.c_int, [_P, C.c_char_p, C.c_int, _P, _P, C.c_int]),
     "gq_filter": (C.c_int, [_P, C.POINTER(GqBatch), C.POINTER(GqPred), C.c_int,
                             C.POINTER(C.c_int32), C.c_int, C.POINTER(GqBatch), _P, _P]),
     "gq_hash_partition": (C.c_int, [_P, C.POINTER(GqBatch), C.POINTER(C.c_int32), C.c_int,
@@ -306,6 +308,24 @@ class Context:
         if rc not in (GQ_OK, GQ_ERR_CAPACITY, GQ_ERR_TABLE_FULL):
             self.check(rc)
         return int(bits.value)
+
+    def set_timing(self, enable: bool):
+        self.check(_lib.gq_ctx_set_timing(self.h, 1 if enable else 0))
+
+    def timing_report(self) -> dict:
+        """{kernel name: (total ms, launches)} since the last report (synchronises)."""
+        cap, nl = 64, 64
+        names = C.create_string_buffer(cap * nl)
+        ms = np.zeros(cap, dtype=np.float64)
+        ln = np.zeros(cap, dtype=np.int64)
+        n = _lib.gq_ctx_timing_report(self.h, names, nl, ms.ctypes.data, ln.ctypes.data, cap)
+        if n < 0:
+            self.check(n)
+        out = {}
+        for i in range(min(n, cap)):
+            nm = names.raw[i * nl:(i + 1) * nl].split(b"\0", 1)[0].decode()
+            out[nm] = (float(ms[i]), int(ln[i]))
+        return out
 
     def raise_status(self, stream=None):
         bits = C.c_int32(0)

@@ -1,0 +1,129 @@
+"""gq_groupby_agg on the GPU against the oracle, bit-exact after canonical ordering."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2606_24647_amd import datagen as dg
+from tests.helpers import canon_groups, random_table, tbl
+
+pytestmark = pytest.mark.gpu
+
+REV = [("col", 1), ("k-col", 100, 2)]
+C1_AGGS = [("sum", [("col", 0)]), ("sum", [("col", 1)]), ("sum", [("col", 2)]), ("sum", REV), ("count*",)]
+
+
+@pytest.fixture(scope="module")
+def gq():
+    from paper_2606_24647_amd import gq as mod
+    return mod
+
+
+@pytest.fixture(scope="module")
+def ctx(gq):
+    return gq.Context()
+
+
+def gpu_groupby(gq, ctx, table, keys, preds, aggs, **kw):
+    dev = gq.to_device(table)
+    out, cnt = ctx.groupby_agg(dev, keys, preds, aggs, **kw)
+    bits = ctx.sync_status()
+    n = int(cnt.item())
+    cols = gq.read_table(out, n)
+    return cols[:len(keys)], cols[len(keys):], n, bits
+
+
+def check(gq, ctx, table, keys, preds, aggs, **kw):
+    gk, ga, n, bits = gpu_groupby(gq, ctx, table, keys, preds, aggs, **kw)
+    assert bits == 0, bits
+    exp = oracle.groupby(table, keys, preds, aggs)
+    assert n == exp.nrows
+    gk = [(v.astype(np.int64), ok) for v, ok in gk]
+    gk, ga = canon_groups(gk, ga)
+    ek, ea = canon_groups(exp.keys, exp.aggs)
+    for j, ((gv, gok), (ev, eok)) in enumerate(zip(gk, ek)):
+        assert np.array_equal(gok, eok), f"key {j} validity"
+        assert np.array_equal(gv, ev), f"key {j} values"
+    for j, ((gv, gok), (ev, eok)) in enumerate(zip(ga, ea)):
+        assert np.array_equal(gok, eok), f"agg {j} validity"
+        assert np.array_equal(gv, ev), f"agg {j} values"
+
+
+@pytest.mark.parametrize("strategy", ["lds", "global"])
+def test_config1_full(gq, ctx, strategy):
+    t = dg.fact_c1(1_000_000)
+    check(gq, ctx, t, [4, 5], [("range", 3, -(1 << 31), 2466)], C1_AGGS, strategy=strategy, expected_groups=6)
+
+
+@pytest.mark.parametrize("strategy", ["lds", "global", "auto"])
+@pytest.mark.parametrize("n", [0, 1, 63, 64, 65, 1023, 1024, 1025, 50_001])
+def test_sizes(gq, ctx, strategy, n):
+    rng = np.random.default_rng(n + 7)
+    t = random_table(rng, n, lo=-3, hi=3)
+    check(gq, ctx, t, [3, 2], [("range", 1, -2, 2)], [("count*",), ("sum", [("col", 0)]),
+                                                       ("min", [("col", 0)]), ("max", [("col", 1)])],
+          strategy=strategy)
+
+
+@pytest.mark.parametrize("strategy", ["lds", "global"])
+def test_nulls_everywhere(gq, ctx, strategy):
+    rng = np.random.default_rng(11)
+    t = random_table(rng, 80_000, null_frac=0.2, lo=-4, hi=4)
+    aggs = [("count*",), ("count", [("col", 0)]), ("sum", [("col", 0), ("k-col", 10, 1)]),
+            ("min", [("col", 2)]), ("max", [("k+col", 5, 3)]), ("sum", [("const", 7)])]
+    check(gq, ctx, t, [3, 1], [("ne", 2, 0)], aggs, strategy=strategy)
+
+
+@pytest.mark.parametrize("strategy", ["lds", "global"])
+def test_int64_key_high_cardinality(gq, ctx, strategy):
+    rng = np.random.default_rng(12)
+    n = 200_000
+    k = rng.integers(-50_000, 50_000, n)
+    k[::97] = -1                          # the key value that equals the empty-slot pattern
+    k[::101] = np.iinfo(np.int64).min
+    k[::103] = np.iinfo(np.int64).max
+    valid = rng.random(n) > 0.05
+    v = rng.integers(-(1 << 40), 1 << 40, n)
+    t = tbl(k=(k, valid), v=v)
+    check(gq, ctx, t, [0], [], [("sum", [("col", 1)]), ("count*",), ("min", [("col", 1)])], strategy=strategy)
+
+
+def test_wrapping_sums(gq, ctx):
+    big = np.iinfo(np.int64).max
+    n = 30_000
+    t = tbl(g=(np.arange(n) % 3).astype(np.int8), x=np.full(n, big - 5, dtype=np.int64))
+    check(gq, ctx, t, [0], [], [("sum", [("col", 1)]), ("sum", [("col", 1), ("col", 1)])], strategy="lds")
+
+
+def test_all_equal_keys_high_contention(gq, ctx):
+    n = 500_000
+    t = tbl(g=np.zeros(n, dtype=np.int32), x=np.arange(n, dtype=np.int64))
+    for strategy in ("lds", "global"):
+        check(gq, ctx, t, [0], [], [("sum", [("col", 1)]), ("count*",), ("max", [("col", 1)])],
+              strategy=strategy)
+
+
+def test_global_aggregate(gq, ctx):
+    rng = np.random.default_rng(3)
+    t = random_table(rng, 10_000, null_frac=0.1)
+    check(gq, ctx, t, [], [("range", 0, 0, 20)], [("count*",), ("sum", [("col", 1)]), ("min", [("col", 2)])])
+    e = random_table(rng, 0, null_frac=0.1)
+    check(gq, ctx, e, [], [], [("count*",), ("sum", [("col", 1)]), ("min", [("col", 2)])])
+
+
+def test_capacity_and_table_full(gq, ctx):
+    rng = np.random.default_rng(4)
+    t = tbl(k=rng.integers(0, 10_000, 100_000), v=np.ones(100_000, dtype=np.int64))
+    dev = gq.to_device(t)
+    out, cnt = ctx.groupby_agg(dev, [0], [], [("count*",)], capacity=10)
+    assert ctx.sync_status() & 1
+    exp = oracle.groupby(t, [0], [], [("count*",)])
+    assert int(cnt.item()) == exp.nrows
+    out, cnt = ctx.groupby_agg(dev, [0], [], [("count*",)], expected_groups=100, load_factor=0.9)
+    assert ctx.sync_status() & 2
+
+
+def test_unsupported_wide_keys(gq, ctx):
+    t = gq.to_device(tbl(a=np.zeros(4, dtype=np.int64), b=np.zeros(4, dtype=np.int32)))
+    with pytest.raises(gq.GqError) as e:
+        ctx.groupby_agg(t, [0, 1], [], [("count*",)])
+    assert e.value.code == gq.GQ_ERR_UNSUPPORTED
