@@ -103,6 +103,8 @@ struct DCol {
   int64_t voff;
   int32_t type;          // GQ_I8..GQ_I64
   int32_t align;         // largest power of two (<= 16) dividing the data address
+  int32_t nt;            // read once per kernel: use non-temporal loads
+  int32_t pad;
 };
 
 // Output column.
@@ -148,11 +150,32 @@ __device__ __forceinline__ bool valid_one(const DCol& c, int64_t i) {
   return (c.valid[b >> 3] >> (b & 7)) & 1;
 }
 
+// 16-, 8- and 4-byte loads; NT = non-temporal (streamed once: hint the caches
+// not to keep the line, so hash tables stay resident).
+typedef int gq_v4i __attribute__((ext_vector_type(4)));
+typedef int gq_v2i __attribute__((ext_vector_type(2)));
+
+template <bool NT>
+__device__ __forceinline__ gq_v4i ld16(const uint8_t* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(reinterpret_cast<const gq_v4i*>(p));
+  else return *reinterpret_cast<const gq_v4i*>(p);
+}
+template <bool NT>
+__device__ __forceinline__ gq_v2i ld8(const uint8_t* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(reinterpret_cast<const gq_v2i*>(p));
+  else return *reinterpret_cast<const gq_v2i*>(p);
+}
+template <bool NT>
+__device__ __forceinline__ int ld4(const uint8_t* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(reinterpret_cast<const int*>(p));
+  else return *reinterpret_cast<const int*>(p);
+}
+
 // Blocked load of ITEMS consecutive rows r0..r0+ITEMS-1 into int64 registers,
 // sign-extended.  Uses 128-bit loads (or the widest that covers ITEMS*width
 // bytes) when the whole group is in range and the slice is aligned for it;
 // rows past n read as 0.
-template <int ITEMS>
+template <int ITEMS, bool NT = false>
 __device__ __forceinline__ void load_items(const DCol& c, int64_t r0, int64_t n, int64_t (&v)[ITEMS]) {
   const int w = type_width(c.type);
   const int need = ITEMS * w < 16 ? ITEMS * w : 16;
@@ -160,27 +183,33 @@ __device__ __forceinline__ void load_items(const DCol& c, int64_t r0, int64_t n,
     const uint8_t* p = c.data + r0 * w;
     switch (c.type) {
       case GQ_I64: {
+        if constexpr (ITEMS % 2 == 0) {
 #pragma unroll
-        for (int k = 0; k < ITEMS; k += 2) {
-          int4 x = *reinterpret_cast<const int4*>(p + k * 8);
-          v[k] = (int64_t)(((uint64_t)(uint32_t)x.y << 32) | (uint32_t)x.x);
-          v[k + 1] = (int64_t)(((uint64_t)(uint32_t)x.w << 32) | (uint32_t)x.z);
+          for (int k = 0; k < ITEMS; k += 2) {
+            gq_v4i x = ld16<NT>(p + k * 8);
+            v[k] = (int64_t)(((uint64_t)(uint32_t)x.y << 32) | (uint32_t)x.x);
+            v[k + 1] = (int64_t)(((uint64_t)(uint32_t)x.w << 32) | (uint32_t)x.z);
+          }
+          return;
         }
-        return;
+        break;
       }
       case GQ_I32: {
+        if constexpr (ITEMS % 4 == 0) {
 #pragma unroll
-        for (int k = 0; k < ITEMS; k += 4) {
-          int4 x = *reinterpret_cast<const int4*>(p + k * 4);
-          v[k] = x.x; v[k + 1] = x.y; v[k + 2] = x.z; v[k + 3] = x.w;
+          for (int k = 0; k < ITEMS; k += 4) {
+            gq_v4i x = ld16<NT>(p + k * 4);
+            v[k] = x.x; v[k + 1] = x.y; v[k + 2] = x.z; v[k + 3] = x.w;
+          }
+          return;
         }
-        return;
+        break;
       }
       case GQ_I16: {
         if constexpr (ITEMS % 8 == 0) {
 #pragma unroll
           for (int k = 0; k < ITEMS; k += 8) {
-            int4 x = *reinterpret_cast<const int4*>(p + k * 2);
+            gq_v4i x = ld16<NT>(p + k * 2);
             int32_t q[4] = {x.x, x.y, x.z, x.w};
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -189,6 +218,11 @@ __device__ __forceinline__ void load_items(const DCol& c, int64_t r0, int64_t n,
             }
           }
           return;
+        } else if constexpr (ITEMS == 4) {
+          gq_v2i x = ld8<NT>(p);
+          v[0] = (int16_t)(x.x & 0xffff); v[1] = (int16_t)((uint32_t)x.x >> 16);
+          v[2] = (int16_t)(x.y & 0xffff); v[3] = (int16_t)((uint32_t)x.y >> 16);
+          return;
         }
         break;
       }
@@ -196,20 +230,20 @@ __device__ __forceinline__ void load_items(const DCol& c, int64_t r0, int64_t n,
         if constexpr (ITEMS % 16 == 0) {
 #pragma unroll
           for (int k = 0; k < ITEMS; k += 16) {
-            int4 x = *reinterpret_cast<const int4*>(p + k);
+            gq_v4i x = ld16<NT>(p + k);
             int32_t q[4] = {x.x, x.y, x.z, x.w};
 #pragma unroll
             for (int j = 0; j < 16; ++j) v[k + j] = (int8_t)((uint32_t)q[j >> 2] >> (8 * (j & 3)));
           }
           return;
         } else if constexpr (ITEMS == 8) {
-          int2 x = *reinterpret_cast<const int2*>(p);
+          gq_v2i x = ld8<NT>(p);
 #pragma unroll
           for (int j = 0; j < 8; ++j)
             v[j] = (int8_t)((uint32_t)(j < 4 ? x.x : x.y) >> (8 * (j & 3)));
           return;
         } else if constexpr (ITEMS == 4) {
-          int32_t x = *reinterpret_cast<const int32_t*>(p);
+          int32_t x = ld4<NT>(p);
 #pragma unroll
           for (int j = 0; j < 4; ++j) v[j] = (int8_t)((uint32_t)x >> (8 * j));
           return;
@@ -256,6 +290,17 @@ __device__ __forceinline__ void static_for(F&& f) {
     f(std::integral_constant<int, B>{});
     static_for<B + 1, E>(f);
   }
+}
+
+// A copy of a register value that the optimiser cannot see through.  Used on
+// hash-table words read ahead for several rows: without it the compiler may
+// merge the "first probe" value and the "next probe" load into one load
+// through a pointer chosen at run time, which moves the read-ahead array to
+// scratch memory.  Applied where the value is consumed, after all read-ahead
+// loads were issued, so they still overlap.
+__device__ __forceinline__ uint64_t opaque_copy(uint64_t x) {
+  asm volatile("" : "+v"(x));
+  return x;
 }
 
 // Lane helpers (wave64).

@@ -99,6 +99,8 @@ DCol make_dcol(const gq_column& c) {
   d.voff = c.offset;
   d.type = c.type;
   d.align = addr_align(d.data);
+  d.nt = 0;
+  d.pad = 0;
   return d;
 }
 

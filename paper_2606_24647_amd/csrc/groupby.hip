@@ -11,7 +11,8 @@
 //  - Global: every row updates the HBM table directly (high cardinality).
 //  - Group-join (pipeline only): when the only group key is the probe key and
 //    the join table reserved accumulator words, a matching row accumulates into
-//    the join slot it found: the probe and the aggregation touch one slot.
+//    the accumulators of the join slot it found, so the probe and the
+//    aggregation share one lookup.
 // In the pipeline a probe row that matches m build rows is accumulated with
 // weight m (SUM adds m*x, COUNT adds m), which equals aggregating the
 // materialised join.  All sums wrap modulo 2^64 and are therefore independent
@@ -23,14 +24,17 @@ namespace {
 
 constexpr int kGbBlock = 256;
 constexpr int kGbItems = 4;
+constexpr int kGjItems = 8;
 constexpr int kLdsProbes = 16;
 constexpr size_t kLdsBudget = 32 * 1024;
 
 struct JoinRef {
   const JoinHdr* hdr;
-  const uint64_t* slots;
-  uint64_t max_cap;
-  int32_t stride;
+  const uint64_t* keys;
+  const uint64_t* meta;
+  uint64_t* acc;
+  uint64_t cap_alloc;
+  int32_t acc_slots;
   int32_t pad;
   DCol key;  // probe key column
 };
@@ -44,13 +48,18 @@ struct GbArgs {
   DCol pcols[GQ_MAX_PREDS];
   KeyPlan kp;
   AggPlan ap;
-  uint64_t* slots;   // HBM group table: cap hashed slots, then 2 extra slots
+  uint64_t* keys;    // HBM group table: cap hashed slots, then 2 extra slots
+  uint64_t* acc;     // ap.nacc words per slot
   uint64_t cap;
-  int32_t stride;    // words per HBM slot
-  int32_t pad;
   JoinRef join;
   int32_t* dev_status;
 };
+
+template <int ITEMS>
+__device__ __forceinline__ void load_col(const DCol& c, int64_t r0, int64_t n, int64_t (&v)[ITEMS]) {
+  if (c.nt) load_items<ITEMS, true>(c, r0, n, v);
+  else load_items<ITEMS, false>(c, r0, n, v);
+}
 
 // ---------------------------------------------------------------------------
 // Per-tile row evaluation shared by the kernels
@@ -63,7 +72,7 @@ __device__ __forceinline__ uint32_t eval_preds(const GbArgs& a, int64_t r0) {
     if (r0 + k < a.n) keep |= 1u << k;
   for (int p = 0; p < a.npreds; ++p) {
     int64_t v[ITEMS];
-    load_items<ITEMS>(a.pcols[p], r0, a.n, v);
+    load_col<ITEMS>(a.pcols[p], r0, a.n, v);
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k)
       if (!pred_pass(a.preds[p], v[k])) keep &= ~(1u << k);
@@ -72,30 +81,45 @@ __device__ __forceinline__ uint32_t eval_preds(const GbArgs& a, int64_t r0) {
   return keep;
 }
 
-// Join-table slot of a probe key, or nullptr.
-__device__ __forceinline__ const uint64_t* join_lookup(const JoinRef& j, uint64_t kv) {
-  if (kv == kEmpty) {
-    const uint64_t* s = j.slots + j.max_cap * j.stride;
-    return slot_count(s) ? s : nullptr;
-  }
-  return table_find(j.slots, j.hdr->cap, j.stride, kv);
+// Join slots of the kept rows' probe keys (-1: no match), all first probes
+// issued before any is resolved.  Rows without a match are dropped from keep.
+template <int ITEMS>
+__device__ __forceinline__ void join_lookup(const JoinRef& j, int64_t r0, int64_t n, uint32_t& keep,
+                                            int64_t (&slot)[ITEMS]) {
+  int64_t kv[ITEMS];
+  load_col<ITEMS>(j.key, r0, n, kv);
+  if (j.key.valid) keep &= valid_items<ITEMS>(j.key, r0, n);
+  const uint64_t cap = j.hdr->cap;
+  uint64_t start[ITEMS], first[ITEMS];
+  static_for<0, ITEMS>([&](auto kk) __attribute__((always_inline)) {
+    constexpr int k = decltype(kk)::value;
+    start[k] = slot_of((uint64_t)kv[k], cap);
+    first[k] = ((keep >> k) & 1u) ? j.keys[start[k]] : kEmpty;
+  });
+  static_for<0, ITEMS>([&](auto kk) __attribute__((always_inline)) {
+    constexpr int k = decltype(kk)::value;
+    slot[k] = -1;
+    if (!((keep >> k) & 1u)) return;
+    const uint64_t key = (uint64_t)kv[k];
+    if (key == kEmpty) {
+      if (meta_count(j.meta[j.cap_alloc])) slot[k] = (int64_t)j.cap_alloc;
+    } else {
+      slot[k] = find_from(j.keys, cap, key, start[k], opaque_copy(first[k]));
+    }
+    if (slot[k] < 0) keep &= ~(1u << k);
+  });
 }
 
-// Match counts (weights) of the kept rows; rows without a match are dropped.
+// Match counts of found slots: 1 unless the build side had duplicate keys.
 template <int ITEMS>
-__device__ __forceinline__ void probe_weights(const GbArgs& a, int64_t r0, uint32_t& keep, uint32_t (&w)[ITEMS]) {
-  int64_t kv[ITEMS];
-  load_items<ITEMS>(a.join.key, r0, a.n, kv);
-  if (a.join.key.valid) keep &= valid_items<ITEMS>(a.join.key, r0, a.n);
-#pragma unroll
-  for (int k = 0; k < ITEMS; ++k) {
-    w[k] = 0;
-    if ((keep >> k) & 1u) {
-      const uint64_t* s = join_lookup(a.join, (uint64_t)kv[k]);
-      if (s) w[k] = slot_count(s);
-      if (w[k] == 0) keep &= ~(1u << k);
-    }
-  }
+__device__ __forceinline__ void join_weights(const JoinRef& j, uint32_t keep, const int64_t (&slot)[ITEMS],
+                                             uint32_t (&w)[ITEMS]) {
+  const bool dups = j.hdr->has_dups != 0;
+  static_for<0, ITEMS>([&](auto kk) __attribute__((always_inline)) {
+    constexpr int k = decltype(kk)::value;
+    w[k] = 1;
+    if (((keep >> k) & 1u) && (dups || slot[k] == (int64_t)j.cap_alloc)) w[k] = meta_count(j.meta[slot[k]]);
+  });
 }
 
 // Group keys of ITEMS rows.  special: 0 hashed, 1 EMPTY-valued raw key, 2 NULL raw key.
@@ -111,7 +135,7 @@ __device__ __forceinline__ void make_keys(const KeyPlan& kp, int64_t r0, int64_t
   for (int j = 0; j < GQ_MAX_KEYS; ++j) {
     if (j < kp.nk) {
       int64_t v[ITEMS];
-      load_items<ITEMS>(kp.cols[j], r0, n, v);
+      load_col<ITEMS>(kp.cols[j], r0, n, v);
       const uint32_t vm = kp.cols[j].valid ? valid_items<ITEMS>(kp.cols[j], r0, n) : 0xffffffffu;
       if (kp.mode == KEY_RAW64) {
 #pragma unroll
@@ -134,9 +158,8 @@ __device__ __forceinline__ void make_keys(const KeyPlan& kp, int64_t r0, int64_t
 }
 
 // Input of aggregate `ag` for ITEMS rows: x[k] = product of its factors
-// (wrapping).  Returns the mask of rows whose input is non-NULL.  Factor
-// columns are loaded per aggregate; a column shared by several aggregates is
-// re-read from cache, not from HBM.
+// (wrapping).  Returns the mask of rows whose input is non-NULL.  A column used
+// by several aggregates is re-read from cache (such columns use temporal loads).
 template <int ITEMS>
 __device__ __forceinline__ uint32_t agg_values(const DAgg& ag, const AggPlan& ap, int64_t r0, int64_t n,
                                                uint64_t (&x)[ITEMS]) {
@@ -152,7 +175,7 @@ __device__ __forceinline__ uint32_t agg_values(const DAgg& ag, const AggPlan& ap
     }
     const DCol& c = ap.vals[fa.v];
     int64_t v[ITEMS];
-    load_items<ITEMS>(c, r0, n, v);
+    load_col<ITEMS>(c, r0, n, v);
     if (c.valid) nn &= valid_items<ITEMS>(c, r0, n);
     const uint64_t kk = (uint64_t)fa.k;
 #pragma unroll
@@ -165,25 +188,24 @@ __device__ __forceinline__ uint32_t agg_values(const DAgg& ag, const AggPlan& ap
   return nn;
 }
 
-// Apply all aggregates of ITEMS rows to their slots.  Row k's words live in
-// LDS at lds + loff[k] (loff[k] >= 0) or in HBM at gsp[k]; word 1 is the
-// hidden row count.
+// Apply all aggregates of ITEMS rows.  Row k's accumulators are in LDS at
+// lds + loff[k] (loff[k] >= 0) or in HBM at gsp[k]; word 0 is the row count.
 template <int ITEMS>
 __device__ __forceinline__ void apply_rows(const AggPlan& ap, int64_t r0, int64_t n, uint32_t keep,
                                            const uint32_t (&w)[ITEMS], uint64_t* lds, const int (&loff)[ITEMS],
                                            uint64_t* const (&gsp)[ITEMS]) {
-  static_for<0, ITEMS>([&](auto kk) {
+  static_for<0, ITEMS>([&](auto kk) __attribute__((always_inline)) {
     constexpr int k = decltype(kk)::value;
     if (!((keep >> k) & 1u)) return;
-    if (loff[k] >= 0) SharedAtomics::add(&lds[loff[k] + 1], w[k]);
-    else GlobalAtomics::add(&gsp[k][1], w[k]);
+    if (loff[k] >= 0) SharedAtomics::add(&lds[loff[k]], w[k]);
+    else GlobalAtomics::add(&gsp[k][0], w[k]);
   });
   for (int i = 0; i < ap.naggs; ++i) {
     const DAgg& ag = ap.aggs[i];
     if (ag.op == GQ_COUNT_STAR) continue;
     uint64_t x[ITEMS];
     const uint32_t nn = agg_values<ITEMS>(ag, ap, r0, n, x) & keep;
-    static_for<0, ITEMS>([&](auto kk) {
+    static_for<0, ITEMS>([&](auto kk) __attribute__((always_inline)) {
       constexpr int k = decltype(kk)::value;
       if (!((nn >> k) & 1u)) return;
       const uint64_t wk = w[k];
@@ -210,17 +232,25 @@ __device__ __forceinline__ void apply_rows(const AggPlan& ap, int64_t r0, int64_
   }
 }
 
-// HBM slot of a row's group (hashed or extra), or nullptr if the table is full.
-__device__ __forceinline__ uint64_t* global_slot(const GbArgs& a, uint64_t key, int special) {
-  if (special) return a.slots + (a.cap + (uint64_t)(special - 1)) * a.stride;
-  uint64_t* s = table_find_insert(a.slots, a.cap, a.stride, key);
-  if (!s) atomicOr(a.dev_status, GQ_DEV_TABLE_FULL);
-  return s;
+// HBM accumulators of a row's group (hashed or extra), or nullptr if the table is full.
+__device__ __forceinline__ uint64_t* global_acc(const GbArgs& a, uint64_t key, int special) {
+  int64_t s;
+  if (special) {
+    s = (int64_t)(a.cap + (uint64_t)(special - 1));
+  } else {
+    bool ins;
+    s = find_insert(a.keys, a.cap, key, &ins);
+    if (s < 0) {
+      atomicOr(a.dev_status, GQ_DEV_TABLE_FULL);
+      return nullptr;
+    }
+  }
+  return a.acc + (uint64_t)s * a.ap.nacc;
 }
 
-// Merge one set of accumulator words into HBM.
+// Merge one group's accumulators into HBM.
 __device__ __forceinline__ void merge_words(const AggPlan& ap, uint64_t* dst, const uint64_t* src) {
-  for (int w = 1; w < ap.nwords; ++w) {
+  for (int w = 0; w < ap.nacc; ++w) {
     const uint64_t v = src[w];
     switch (ap.wop[w]) {
       case WOP_ADD:
@@ -236,35 +266,30 @@ __device__ __forceinline__ void merge_words(const AggPlan& ap, uint64_t* dst, co
   }
 }
 
-__host__ __device__ __forceinline__ uint64_t word_identity(int8_t wop) {
-  return (uint64_t)(wop == WOP_MIN ? INT64_MAX : wop == WOP_MAX ? INT64_MIN : 0);
-}
-
 // ---------------------------------------------------------------------------
 // Kernels
 // ---------------------------------------------------------------------------
 
 // Initialise `nslots` HBM slots: key EMPTY, accumulators at their identity.
-__global__ void k_gt_init(uint64_t* slots, int64_t nslots, int32_t stride, AggPlan ap) {
+__global__ void k_gt_init(uint64_t* keys, uint64_t* acc, int64_t nslots, AggPlan ap) {
   const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t step = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = i0; i < nslots; i += step) {
-    uint64_t* s = slots + i * stride;
-    s[0] = kEmpty;
-    for (int w = 1; w < stride; ++w) s[w] = (w < ap.nwords) ? word_identity(ap.wop[w]) : 0ull;
+    keys[i] = kEmpty;
+    for (int w = 0; w < ap.nacc; ++w) acc[i * ap.nacc + w] = word_identity(ap.wop[w]);
   }
 }
 
-// Group-join accumulator init in a join table: the acc words of slots [0, cap)
-// and of the extra slot.
+// Group-join accumulator init in a join table: occupied slots of [0, cap) and
+// the extra slot.
 __global__ void k_gj_init(JoinRef j, AggPlan ap) {
   const uint64_t cap = j.hdr->cap;
   const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t step = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = i0; i <= (int64_t)cap; i += step) {
-    const uint64_t s = (i == (int64_t)cap) ? j.max_cap : (uint64_t)i;
-    uint64_t* acc = const_cast<uint64_t*>(j.slots) + s * j.stride + 1;  // acc[1] = hidden count
-    for (int w = 1; w < ap.nwords; ++w) acc[w] = word_identity(ap.wop[w]);
+    const uint64_t s = (i == (int64_t)cap) ? j.cap_alloc : (uint64_t)i;
+    if (s != j.cap_alloc && j.keys[s] == kEmpty) continue;
+    for (int w = 0; w < ap.nacc; ++w) j.acc[s * j.acc_slots + w] = word_identity(ap.wop[w]);
   }
 }
 
@@ -276,19 +301,23 @@ __global__ __launch_bounds__(BLOCK) void k_gb_global(const GbArgs a) {
   uint32_t w[ITEMS];
 #pragma unroll
   for (int k = 0; k < ITEMS; ++k) w[k] = 1;
-  if (JOIN) probe_weights<ITEMS>(a, r0, keep, w);
+  if (JOIN) {
+    int64_t js[ITEMS];
+    join_lookup<ITEMS>(a.join, r0, a.n, keep, js);
+    join_weights<ITEMS>(a.join, keep, js, w);
+  }
   if (!keep) return;
   uint64_t key[ITEMS];
   uint8_t special[ITEMS];
   make_keys<ITEMS>(a.kp, r0, a.n, key, special);
   int loff[ITEMS];
   uint64_t* gsp[ITEMS];
-  static_for<0, ITEMS>([&](auto kk) {
+  static_for<0, ITEMS>([&](auto kk) __attribute__((always_inline)) {
     constexpr int k = decltype(kk)::value;
     loff[k] = -1;
     gsp[k] = nullptr;
     if ((keep >> k) & 1u) {
-      gsp[k] = global_slot(a, key[k], special[k]);
+      gsp[k] = global_acc(a, key[k], special[k]);
       if (!gsp[k]) keep &= ~(1u << k);
     }
   });
@@ -299,11 +328,11 @@ template <int BLOCK, int ITEMS, bool JOIN>
 __global__ __launch_bounds__(BLOCK) void k_gb_lds(const GbArgs a) {
   constexpr int TILE = BLOCK * ITEMS;
   extern __shared__ uint64_t s_tab[];
-  const int nw = a.ap.nwords;
+  const int sw = 1 + a.ap.nacc;  // LDS slot: key, then accumulators
   const int lcap = a.lcap;
-  for (int i = threadIdx.x; i < lcap * nw; i += BLOCK) {
-    const int wi = i % nw;
-    s_tab[i] = wi == 0 ? kEmpty : word_identity(a.ap.wop[wi]);
+  for (int i = threadIdx.x; i < lcap * sw; i += BLOCK) {
+    const int wi = i % sw;
+    s_tab[i] = wi == 0 ? kEmpty : word_identity(a.ap.wop[wi - 1]);
   }
   __syncthreads();
 
@@ -313,14 +342,18 @@ __global__ __launch_bounds__(BLOCK) void k_gb_lds(const GbArgs a) {
     uint32_t w[ITEMS];
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) w[k] = 1;
-    if (JOIN) probe_weights<ITEMS>(a, r0, keep, w);
+    if (JOIN) {
+      int64_t js[ITEMS];
+      join_lookup<ITEMS>(a.join, r0, a.n, keep, js);
+      join_weights<ITEMS>(a.join, keep, js, w);
+    }
     if (!keep) continue;
     uint64_t key[ITEMS];
     uint8_t special[ITEMS];
     make_keys<ITEMS>(a.kp, r0, a.n, key, special);
     int loff[ITEMS];
     uint64_t* gsp[ITEMS];
-    static_for<0, ITEMS>([&](auto kk) {
+    static_for<0, ITEMS>([&](auto kk) __attribute__((always_inline)) {
       constexpr int k = decltype(kk)::value;
       loff[k] = -1;
       gsp[k] = nullptr;
@@ -328,17 +361,17 @@ __global__ __launch_bounds__(BLOCK) void k_gb_lds(const GbArgs a) {
       if (!special[k]) {
         uint32_t s = (uint32_t)slot_of(key[k], (uint64_t)lcap);
         for (int p = 0; p < kLdsProbes; ++p) {
-          const int off = (int)s * nw;
+          const int off = (int)s * sw;
           const uint64_t kv = s_tab[off];
           if (kv == key[k]) {
-            loff[k] = off;
+            loff[k] = off + 1;
             break;
           }
           if (kv == kEmpty) {
             const uint64_t prev = atomicCAS((unsigned long long*)&s_tab[off], (unsigned long long)kEmpty,
                                             (unsigned long long)key[k]);
             if (prev == kEmpty || prev == key[k]) {
-              loff[k] = off;
+              loff[k] = off + 1;
               break;
             }
           }
@@ -346,7 +379,7 @@ __global__ __launch_bounds__(BLOCK) void k_gb_lds(const GbArgs a) {
         }
       }
       if (loff[k] < 0) {
-        gsp[k] = global_slot(a, key[k], special[k]);
+        gsp[k] = global_acc(a, key[k], special[k]);
         if (!gsp[k]) keep &= ~(1u << k);
       }
     });
@@ -354,10 +387,10 @@ __global__ __launch_bounds__(BLOCK) void k_gb_lds(const GbArgs a) {
   }
   __syncthreads();
   for (int i = threadIdx.x; i < lcap; i += BLOCK) {
-    const uint64_t* ls = s_tab + (size_t)i * nw;
+    const uint64_t* ls = s_tab + (size_t)i * sw;
     if (ls[0] == kEmpty) continue;
-    uint64_t* gs = global_slot(a, ls[0], 0);
-    if (gs) merge_words(a.ap, gs, ls);
+    uint64_t* gs = global_acc(a, ls[0], 0);
+    if (gs) merge_words(a.ap, gs, ls + 1);
   }
 }
 
@@ -367,25 +400,16 @@ __global__ __launch_bounds__(BLOCK) void k_groupjoin(const GbArgs a) {
   const int64_t r0 = (int64_t)blockIdx.x * TILE + (int64_t)threadIdx.x * ITEMS;
   uint32_t keep = eval_preds<ITEMS>(a, r0);
   if (!keep) return;
-  int64_t kv[ITEMS];
-  load_items<ITEMS>(a.join.key, r0, a.n, kv);
-  if (a.join.key.valid) keep &= valid_items<ITEMS>(a.join.key, r0, a.n);
+  int64_t js[ITEMS];
+  join_lookup<ITEMS>(a.join, r0, a.n, keep, js);
   uint32_t w[ITEMS];
+  join_weights<ITEMS>(a.join, keep, js, w);
   int loff[ITEMS];
   uint64_t* gsp[ITEMS];
-  static_for<0, ITEMS>([&](auto kk) {
+  static_for<0, ITEMS>([&](auto kk) __attribute__((always_inline)) {
     constexpr int k = decltype(kk)::value;
     loff[k] = -1;
-    gsp[k] = nullptr;
-    w[k] = 0;
-    if (!((keep >> k) & 1u)) return;
-    const uint64_t* s = join_lookup(a.join, (uint64_t)kv[k]);
-    if (s) w[k] = slot_count(s);
-    if (w[k] == 0) {
-      keep &= ~(1u << k);
-      return;
-    }
-    gsp[k] = const_cast<uint64_t*>(s) + 1;  // acc[1] = slot word 2, the hidden count
+    gsp[k] = ((keep >> k) & 1u) ? a.join.acc + (uint64_t)js[k] * a.join.acc_slots : nullptr;
   });
   if (!keep) return;
   apply_rows<ITEMS>(a.ap, r0, a.n, keep, w, nullptr, loff, gsp);
@@ -420,26 +444,24 @@ __global__ __launch_bounds__(BLOCK) void k_compact(const CompactArgs a) {
   const uint64_t cap = a.d_cap ? *a.d_cap : a.cap;
   const int64_t total_idx = (int64_t)cap + a.extra;
   const int64_t i0 = tile * TILE + (int64_t)threadIdx.x * ITEMS;
-  const uint64_t* sp[ITEMS];
+  int64_t sl[ITEMS];
   uint32_t keep = 0;
-#pragma unroll
-  for (int k = 0; k < ITEMS; ++k) {
+  static_for<0, ITEMS>([&](auto kk) __attribute__((always_inline)) {
+    constexpr int k = decltype(kk)::value;
     const int64_t i = i0 + k;
-    sp[k] = nullptr;
-    if (i < total_idx) {
-      const bool extra = i >= (int64_t)cap;
-      const uint64_t s = extra ? a.max_cap + (uint64_t)(i - (int64_t)cap) : (uint64_t)i;
-      const uint64_t* slot = a.slots + s * a.stride;
-      const uint64_t* acc = slot + (a.acc_base - 1);
-      bool occ;
-      if (a.key_kind == 2) occ = acc[1] != 0;            // group-join: matched rows
-      else occ = extra ? acc[1] != 0 : slot[0] != kEmpty;
-      if (occ) {
-        keep |= 1u << k;
-        sp[k] = slot;
-      }
+    sl[k] = -1;
+    if (i >= total_idx) return;
+    const bool extra = i >= (int64_t)cap;
+    const uint64_t s = extra ? a.cap_alloc + (uint64_t)(i - (int64_t)cap) : (uint64_t)i;
+    bool occ;
+    if (extra) occ = a.acc[s * a.aw] != 0;                       // extra slots: row count
+    else if (a.key_kind == 2) occ = a.keys[s] != kEmpty && a.acc[s * a.aw] != 0;  // group-join: matched
+    else occ = a.keys[s] != kEmpty;
+    if (occ) {
+      keep |= 1u << k;
+      sl[k] = (int64_t)s;
     }
-  }
+  });
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   uint32_t wtot;
   const uint32_t wpre = wave_prefix_small<4>((uint32_t)__popc(keep), &wtot);
@@ -482,30 +504,30 @@ __global__ __launch_bounds__(BLOCK) void k_compact(const CompactArgs a) {
   for (int j = 0; j < ncols; ++j) {
     const OCol& o = a.out[j];
     int pos = local;
-#pragma unroll
-    for (int k = 0; k < ITEMS; ++k) {
-      if (!((keep >> k) & 1u)) continue;
-      const uint64_t* slot = sp[k];
+    static_for<0, ITEMS>([&](auto kk) __attribute__((always_inline)) {
+      constexpr int k = decltype(kk)::value;
+      if (!((keep >> k) & 1u)) return;
+      const uint64_t s = (uint64_t)sl[k];
+      const bool extra = s >= a.cap_alloc;
       int64_t v = 0;
       bool ok = true;
       if (j < nk) {
-        const bool extra = slot >= a.slots + a.max_cap * a.stride;
         if (a.key_kind == 2) {
-          v = extra ? -1 : (int64_t)slot[0];
+          v = extra ? -1 : (int64_t)a.keys[s];
         } else if (a.kp.mode == KEY_RAW64) {
           if (extra) {
-            const bool is_null = slot == a.slots + (a.max_cap + 1) * a.stride;
+            const bool is_null = s == a.cap_alloc + 1;
             v = is_null ? 0 : -1;
             ok = !is_null;
           } else {
-            v = (int64_t)slot[0];
+            v = (int64_t)a.keys[s];
           }
         } else {
-          v = decode_field(a.kp, slot[0], j, &ok);
+          v = decode_field(a.kp, a.keys[s], j, &ok);
         }
       } else {
         const DAgg& ag = a.aggs[j - nk];
-        const uint64_t* acc = slot + (a.acc_base - 1);
+        const uint64_t* acc = a.acc + s * a.aw;
         v = (int64_t)acc[ag.word];
         if ((ag.op == GQ_SUM || ag.op == GQ_MIN || ag.op == GQ_MAX) && ag.cword >= 0) ok = acc[ag.cword] != 0;
         if (!ok) v = 0;
@@ -513,7 +535,7 @@ __global__ __launch_bounds__(BLOCK) void k_compact(const CompactArgs a) {
       stage_put(s_stage, pos, v, o.type);
       s_vbyte[pos] = ok ? 1 : 0;
       ++pos;
-    }
+    });
     __syncthreads();
     for (int i = threadIdx.x; i < (int)btot; i += BLOCK) {
       const int64_t g = goff + i;
@@ -540,6 +562,7 @@ int make_preds(gq_ctx* ctx, GbArgs& a, const gq_batch* in, const gq_pred* preds,
       return set_error(ctx, GQ_ERR_INVALID, "group-by: unknown predicate op");
     a.preds[p] = DPred{preds[p].col, preds[p].op, preds[p].lo, preds[p].hi};
     a.pcols[p] = make_dcol(in->cols[preds[p].col]);
+    a.pcols[p].nt = 1;
   }
   return GQ_OK;
 }
@@ -551,6 +574,7 @@ int make_key_plan(gq_ctx* ctx, KeyPlan& kp, const gq_batch* in, const int32_t* k
   for (int j = 0; j < nk; ++j) {
     if (keys[j] < 0 || keys[j] >= in->ncols) return set_error(ctx, GQ_ERR_INVALID, "group-by: key column out of range");
     kp.cols[j] = make_dcol(in->cols[keys[j]]);
+    kp.cols[j].nt = 1;
   }
   if (nk == 1 && in->cols[keys[0]].type == GQ_I64) {
     kp.mode = KEY_RAW64;
@@ -580,8 +604,9 @@ int make_agg_plan(gq_ctx* ctx, AggPlan& ap, const gq_batch* in, const gq_agg* ag
   ap.naggs = na;
   ap.nvals = 0;
   int cols[kMaxVals];
-  int word = 2;
-  ap.wop[1] = WOP_ADD;
+  int uses[kMaxVals] = {0};
+  int word = 1;
+  ap.wop[0] = WOP_ADD;
   for (int i = 0; i < na; ++i) {
     const gq_agg& g = aggs[i];
     DAgg& d = ap.aggs[i];
@@ -590,7 +615,7 @@ int make_agg_plan(gq_ctx* ctx, AggPlan& ap, const gq_batch* in, const gq_agg* ag
     d.cword = -1;
     if (g.op < GQ_SUM || g.op > GQ_MAX) return set_error(ctx, GQ_ERR_INVALID, "group-by: unknown aggregate");
     if (g.op == GQ_COUNT_STAR) {
-      d.word = 1;
+      d.word = 0;
       continue;
     }
     if (g.nfactors < 0 || g.nfactors > 3) return set_error(ctx, GQ_ERR_INVALID, "group-by: 0..3 factors");
@@ -613,6 +638,7 @@ int make_agg_plan(gq_ctx* ctx, AggPlan& ap, const gq_batch* in, const gq_agg* ag
         cols[vi] = fa.col;
         ap.vals[vi] = make_dcol(in->cols[fa.col]);
       }
+      uses[vi] += 1;
       d.f[f].v = vi;
       if (in->cols[fa.col].validity) nullable = true;
     }
@@ -623,12 +649,13 @@ int make_agg_plan(gq_ctx* ctx, AggPlan& ap, const gq_batch* in, const gq_agg* ag
       ap.wop[d.cword] = WOP_ADD;
     }
   }
-  ap.nwords = word;
+  // A value column read by one factor only is streamed with non-temporal loads.
+  for (int q = 0; q < ap.nvals; ++q) ap.vals[q].nt = uses[q] == 1 ? 1 : 0;
+  ap.nacc = word;
   return GQ_OK;
 }
 
-int check_outputs(gq_ctx* ctx, const gq_batch* in, const KeyPlan& kp, const int32_t* keys, int nk_out, int na,
-                  gq_batch* out, CompactArgs& ca, const int* key_types) {
+int check_outputs(gq_ctx* ctx, int nk_out, int na, gq_batch* out, CompactArgs& ca, const int* key_types) {
   if (!out || out->ncols < nk_out + na || (nk_out + na > 0 && !out->cols))
     return set_error(ctx, GQ_ERR_INVALID, "group-by: output needs key and aggregate columns");
   int64_t cap = INT64_MAX;
@@ -649,7 +676,7 @@ int check_outputs(gq_ctx* ctx, const gq_batch* in, const KeyPlan& kp, const int3
 
 int compact_launch(gq_ctx* ctx, CompactArgs& ca, int64_t* d_groups, hipStream_t stream) {
   constexpr int TILE = kCBlock * kCItems;
-  const int64_t nidx = (int64_t)ca.max_cap + ca.extra;
+  const int64_t nidx = (int64_t)ca.cap_alloc + ca.extra;
   const int64_t ntiles = (nidx + TILE - 1) / TILE;
   ca.ntiles = ntiles;
   ca.d_count = d_groups;
@@ -662,8 +689,8 @@ int compact_launch(gq_ctx* ctx, CompactArgs& ca, int64_t* d_groups, hipStream_t 
   int64_t iblocks = (ntiles + 255) / 256;
   if (iblocks < 1) iblocks = 1;
   if (iblocks > 4096) iblocks = 4096;
-  GQ_LAUNCH(ctx, "compact_init", k_compact_init, dim3((unsigned)iblocks), dim3(256), 0, stream, ca.ticket, ca.status, ntiles,
-                     d_groups);
+  GQ_LAUNCH(ctx, "compact_init", k_compact_init, dim3((unsigned)iblocks), dim3(256), 0, stream, ca.ticket, ca.status,
+            ntiles, d_groups);
   GQ_LAUNCH_CHECK(ctx);
   GQ_LAUNCH(ctx, "compact", (k_compact<kCBlock, kCItems>), dim3((unsigned)ntiles), dim3(kCBlock), 0, stream, ca);
   GQ_LAUNCH_CHECK(ctx);
@@ -671,21 +698,22 @@ int compact_launch(gq_ctx* ctx, CompactArgs& ca, int64_t* d_groups, hipStream_t 
 }
 
 template <bool JOIN>
-int launch_aggregate(gq_ctx* ctx, GbArgs& a, int strategy, int block_size, hipStream_t stream) {
-  (void)block_size;
+int launch_aggregate(gq_ctx* ctx, GbArgs& a, int strategy, hipStream_t stream) {
   constexpr int TILE = kGbBlock * kGbItems;
   a.ntiles = (a.n + TILE - 1) / TILE;
   if (a.ntiles == 0) return GQ_OK;
   if (strategy == GQ_STRATEGY_LDS) {
+    const int sw = 1 + a.ap.nacc;
     int lcap = 1;
-    while ((size_t)(lcap * 2) * a.ap.nwords * 8 <= kLdsBudget) lcap *= 2;
+    while ((size_t)(lcap * 2) * sw * 8 <= kLdsBudget) lcap *= 2;
     a.lcap = lcap;
-    const size_t lds = (size_t)lcap * a.ap.nwords * 8;
+    const size_t lds = (size_t)lcap * sw * 8;
     int64_t grid = a.ntiles < 512 ? a.ntiles : 512;
-    GQ_LAUNCH(ctx, "gb_lds", (k_gb_lds<kGbBlock, kGbItems, JOIN>), dim3((unsigned)grid), dim3(kGbBlock), lds, stream, a);
+    GQ_LAUNCH(ctx, "gb_lds", (k_gb_lds<kGbBlock, kGbItems, JOIN>), dim3((unsigned)grid), dim3(kGbBlock), lds, stream,
+              a);
   } else {
-    GQ_LAUNCH(ctx, "gb_global", (k_gb_global<kGbBlock, kGbItems, JOIN>), dim3((unsigned)a.ntiles), dim3(kGbBlock), 0, stream,
-                       a);
+    GQ_LAUNCH(ctx, "gb_global", (k_gb_global<kGbBlock, kGbItems, JOIN>), dim3((unsigned)a.ntiles), dim3(kGbBlock), 0,
+              stream, a);
   }
   GQ_LAUNCH_CHECK(ctx);
   return GQ_OK;
@@ -720,10 +748,16 @@ int run_groupby(gq_ctx* ctx, const gq_batch* in, const int32_t* keys, int nkeys,
     if (probe_key < 0 || probe_key >= in->ncols) return set_error(ctx, GQ_ERR_INVALID, "pipeline: probe key out of range");
     if (join->device != ctx->device) return set_error(ctx, GQ_ERR_INVALID, "pipeline: join table on another device");
     a.join.hdr = join->hdr;
-    a.join.slots = join->slots;
-    a.join.max_cap = join->max_cap;
-    a.join.stride = join->stride;
+    a.join.keys = join->keys;
+    a.join.meta = join->meta;
+    a.join.acc = join->acc;
+    a.join.cap_alloc = join->cap_alloc;
+    a.join.acc_slots = join->acc_slots;
     a.join.key = make_dcol(in->cols[probe_key]);
+    a.join.key.nt = 1;
+    // A group key that is also the probe key is read twice; keep it cached.
+    for (int j = 0; j < nkeys; ++j)
+      if (keys[j] == probe_key) a.kp.cols[j].nt = 0;
   }
 
   GQ_HIP_CHECK(ctx, hipSetDevice(ctx->device));
@@ -734,33 +768,34 @@ int run_groupby(gq_ctx* ctx, const gq_batch* in, const int32_t* keys, int nkeys,
   ca.global_agg = nkeys == 0;
 
   // Group-join: the only key is the probe key and the table has room.
-  const bool groupjoin = join && nkeys == 1 && keys[0] == probe_key && join->acc_slots >= a.ap.nwords - 1;
+  const bool groupjoin = join && nkeys == 1 && keys[0] == probe_key && join->acc_slots >= a.ap.nacc;
   if (groupjoin) {
     int kt[1] = {in->cols[probe_key].type};
-    rc = check_outputs(ctx, in, a.kp, keys, 1, naggs, out, ca, kt);
+    rc = check_outputs(ctx, 1, naggs, out, ca, kt);
     if (rc) return rc;
     // A fresh table has zeroed accumulators; MIN/MAX identities or a table
     // already used by a group-join need the init pass.
     bool need_init = join->acc_dirty;
-    for (int w = 1; w < a.ap.nwords; ++w) need_init |= a.ap.wop[w] != WOP_ADD;
+    for (int w = 0; w < a.ap.nacc; ++w) need_init |= a.ap.wop[w] != WOP_ADD;
     if (need_init) {
-      int64_t blocks = (int64_t)((join->max_cap + 1 + 255) / 256);
+      int64_t blocks = (int64_t)((join->cap_alloc + 1 + 255) / 256);
       if (blocks > 8192) blocks = 8192;
       GQ_LAUNCH(ctx, "gj_init", k_gj_init, dim3((unsigned)blocks), dim3(256), 0, stream, a.join, a.ap);
       GQ_LAUNCH_CHECK(ctx);
     }
     const_cast<gq_join_table*>(join)->acc_dirty = true;
-    constexpr int TILE = kGbBlock * kGbItems;
+    constexpr int TILE = kGbBlock * kGjItems;
     a.ntiles = (a.n + TILE - 1) / TILE;
     if (a.ntiles > 0) {
-      GQ_LAUNCH(ctx, "groupjoin", (k_groupjoin<kGbBlock, kGbItems>), dim3((unsigned)a.ntiles), dim3(kGbBlock), 0, stream, a);
+      GQ_LAUNCH(ctx, "groupjoin", (k_groupjoin<kGbBlock, kGjItems>), dim3((unsigned)a.ntiles), dim3(kGbBlock), 0,
+                stream, a);
       GQ_LAUNCH_CHECK(ctx);
     }
-    ca.slots = join->slots;
+    ca.keys = join->keys;
+    ca.acc = join->acc;
     ca.d_cap = &join->hdr->cap;
-    ca.max_cap = join->max_cap;
-    ca.stride = join->stride;
-    ca.acc_base = 2;
+    ca.cap_alloc = join->cap_alloc;
+    ca.aw = join->acc_slots;
     ca.key_kind = 2;
     ca.extra = 1;
     ca.global_agg = 0;
@@ -769,7 +804,7 @@ int run_groupby(gq_ctx* ctx, const gq_batch* in, const int32_t* keys, int nkeys,
 
   int key_types[GQ_MAX_KEYS];
   for (int j = 0; j < nkeys; ++j) key_types[j] = in->cols[keys[j]].type;
-  rc = check_outputs(ctx, in, a.kp, keys, nkeys, naggs, out, ca, key_types);
+  rc = check_outputs(ctx, nkeys, naggs, out, ca, key_types);
   if (rc) return rc;
 
   // Table sizing.
@@ -777,33 +812,36 @@ int run_groupby(gq_ctx* ctx, const gq_batch* in, const int32_t* keys, int nkeys,
   if (nkeys == 0) expected = 1;
   uint64_t cap = (uint64_t)((double)expected / lf) + 1;
   if (cap < 16) cap = 16;
-  int stride = 2;
-  while (stride < a.ap.nwords) stride *= 2;
-  if (stride > 8) stride = (a.ap.nwords + 7) / 8 * 8;
   a.cap = cap;
-  a.stride = stride;
-  const size_t bytes = (size_t)(cap + 2) * stride * 8;
+  const size_t nslot = (size_t)cap + 2;
+  const size_t off_acc = align_up(nslot * 8, 256);
+  const size_t bytes = off_acc + nslot * 8 * (size_t)a.ap.nacc;
   Scratch table(ctx, stream);
   if (!table.get(bytes)) return set_error(ctx, GQ_ERR_NOMEM, "group-by: table allocation failed");
-  a.slots = table.as<uint64_t>(0);
-  int64_t iblocks = (int64_t)((cap + 2 + 255) / 256);
+  a.keys = table.as<uint64_t>(0);
+  a.acc = table.as<uint64_t>(off_acc);
+  int64_t iblocks = (int64_t)((nslot + 255) / 256);
   if (iblocks > 8192) iblocks = 8192;
-  GQ_LAUNCH(ctx, "gt_init", k_gt_init, dim3((unsigned)iblocks), dim3(256), 0, stream, a.slots, (int64_t)(cap + 2), stride,
-                     a.ap);
+  GQ_LAUNCH(ctx, "gt_init", k_gt_init, dim3((unsigned)iblocks), dim3(256), 0, stream, a.keys, a.acc, (int64_t)nslot,
+            a.ap);
   GQ_LAUNCH_CHECK(ctx);
 
   int strategy = o.strategy;
-  if (strategy == GQ_STRATEGY_AUTO) strategy = expected <= 256 ? GQ_STRATEGY_LDS : GQ_STRATEGY_GLOBAL;
-  rc = join ? launch_aggregate<true>(ctx, a, strategy, o.block_size, stream)
-            : launch_aggregate<false>(ctx, a, strategy, o.block_size, stream);
+  if (strategy == GQ_STRATEGY_AUTO) {
+    // LDS privatisation unless the caller expects more groups than a block's
+    // LDS table holds comfortably; with no estimate, LDS first (rows that find
+    // no LDS slot fall through to HBM).
+    strategy = (o.expected_groups == 0 || o.expected_groups <= 256) ? GQ_STRATEGY_LDS : GQ_STRATEGY_GLOBAL;
+  }
+  rc = join ? launch_aggregate<true>(ctx, a, strategy, stream) : launch_aggregate<false>(ctx, a, strategy, stream);
   if (rc) return rc;
 
-  ca.slots = a.slots;
+  ca.keys = a.keys;
+  ca.acc = a.acc;
   ca.d_cap = nullptr;
   ca.cap = cap;
-  ca.max_cap = cap;
-  ca.stride = stride;
-  ca.acc_base = 1;
+  ca.cap_alloc = cap;
+  ca.aw = a.ap.nacc;
   ca.key_kind = a.kp.mode == KEY_RAW64 ? 1 : 0;
   ca.kp = a.kp;
   ca.extra = 2;

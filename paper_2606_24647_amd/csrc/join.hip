@@ -3,10 +3,11 @@
 // Build (all on the caller's stream, no host synchronisation):
 //  1. k_jcount       count build rows that pass the predicates with a non-NULL key
 //  2. k_jinit        size the table on the device from that count
-//                    (cap = ceil(count / load factor)) and clear its slots
-//  3. k_jinsert      CAS the key into its slot; the first inserter stores its row,
-//                    every inserter bumps the slot's count; a second inserter of a
-//                    key marks the table as having duplicates
+//                    (cap = ceil(count / load factor)) and clear keys and meta
+//  3. k_jinsert      CAS the key into the key array; one atomic add on the slot's
+//                    meta word records the count and, from the inserting row,
+//                    the row; a second inserter of a key marks duplicates.  The
+//                    inserting row also zeroes the slot's accumulator words.
 //  4. duplicates only (every kernel below returns at once otherwise):
 //     k_jdup_scan    exclusive scan of slot counts -> start of each key's run
 //     k_jdup_fill    place every build row in its key's run (atomic cursor)
@@ -14,6 +15,8 @@
 //                    by a block-wide merge sort, so runs hold ascending rows
 // Probe: per probe row, the match count from the table, a decoupled look-back
 // scan of the counts, then (probe row, build row) pairs in canonical order.
+// Each thread issues the first probe of all its rows before resolving any of
+// them, so the random reads of a thread overlap.
 #include "table.h"
 
 namespace gq {
@@ -31,13 +34,15 @@ struct JoinBuildArgs {
   DPred preds[GQ_MAX_PREDS];
   DCol pcols[GQ_MAX_PREDS];
   JoinHdr* hdr;
-  uint64_t* slots;
+  uint64_t* keys;
+  uint64_t* meta;
+  uint64_t* acc;
   int32_t* rows;
   uint32_t* aux;
   int32_t* tmp;
-  uint64_t max_cap;
-  int32_t stride;
+  uint64_t cap_alloc;
   int32_t acc_slots;
+  int32_t pad;
   int32_t* dev_status;
 };
 
@@ -50,13 +55,13 @@ __device__ __forceinline__ uint32_t build_rows_keep(const JoinBuildArgs& a, int6
     if (r0 + k < a.n) keep |= 1u << k;
   for (int p = 0; p < a.npreds; ++p) {
     int64_t v[ITEMS];
-    load_items<ITEMS>(a.pcols[p], r0, a.n, v);
+    load_items<ITEMS, true>(a.pcols[p], r0, a.n, v);
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k)
       if (!pred_pass(a.preds[p], v[k])) keep &= ~(1u << k);
     if (a.pcols[p].valid) keep &= valid_items<ITEMS>(a.pcols[p], r0, a.n);
   }
-  load_items<ITEMS>(a.key, r0, a.n, key);
+  load_items<ITEMS, true>(a.key, r0, a.n, key);
   if (a.key.valid) keep &= valid_items<ITEMS>(a.key, r0, a.n);
   return keep;
 }
@@ -67,7 +72,7 @@ __global__ void k_jhdr_init(JoinHdr* hdr) {
     hdr->nrows = 0;
     hdr->has_dups = 0;
     hdr->full = 0;
-    hdr->pad[0] = 0;  // long-run count
+    hdr->nlong = 0;
   }
 }
 
@@ -77,8 +82,19 @@ __global__ __launch_bounds__(BLOCK) void k_jcount(const JoinBuildArgs a) {
   if (threadIdx.x == 0) s_cnt = 0;
   __syncthreads();
   const int64_t r0 = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) * ITEMS;
-  int64_t key[ITEMS];
-  const uint32_t keep = build_rows_keep<ITEMS>(a, r0, key);
+  uint32_t keep = 0;
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k)
+    if (r0 + k < a.n) keep |= 1u << k;
+  for (int p = 0; p < a.npreds; ++p) {
+    int64_t v[ITEMS];
+    load_items<ITEMS>(a.pcols[p], r0, a.n, v);
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k)
+      if (!pred_pass(a.preds[p], v[k])) keep &= ~(1u << k);
+    if (a.pcols[p].valid) keep &= valid_items<ITEMS>(a.pcols[p], r0, a.n);
+  }
+  if (a.key.valid) keep &= valid_items<ITEMS>(a.key, r0, a.n);
   uint32_t tot;
   wave_prefix_small<5>((uint32_t)__popc(keep), &tot);
   if ((threadIdx.x & (kWave - 1)) == 0 && tot) atomicAdd(&s_cnt, tot);
@@ -86,26 +102,28 @@ __global__ __launch_bounds__(BLOCK) void k_jcount(const JoinBuildArgs a) {
   if (threadIdx.x == 0 && s_cnt) atomicAdd((unsigned long long*)&a.hdr->nrows, (unsigned long long)s_cnt);
 }
 
-__device__ __forceinline__ uint64_t cap_for(int64_t n, int lf_milli, uint64_t max_cap) {
+__device__ __forceinline__ uint64_t cap_for(int64_t n, int lf_milli, uint64_t cap_alloc) {
   uint64_t c = ((uint64_t)n * 1000 + lf_milli - 1) / (uint64_t)lf_milli;
   if (c < 1) c = 1;
-  if (c > max_cap) c = max_cap;
+  if (c > cap_alloc) c = cap_alloc;
   return c;
 }
 
-// Clear slots [0, cap) and the extra slot (index max_cap): key EMPTY, then
-// zero words (row/count and accumulators, whose initial values are written by
-// the pipeline that uses them).
+// Clear keys and meta of slots [0, cap) and of the extra slot (index
+// cap_alloc), plus the extra slot's accumulators.
 __global__ void k_jinit(const JoinBuildArgs a) {
-  const uint64_t cap = cap_for(a.hdr->nrows, a.lf_milli, a.max_cap);
+  const uint64_t cap = cap_for(a.hdr->nrows, a.lf_milli, a.cap_alloc);
   const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  if (i0 == 0) a.hdr->cap = cap;
-  for (int64_t i = i0; i <= (int64_t)cap; i += stride) {
-    const uint64_t s = (i == (int64_t)cap) ? a.max_cap : (uint64_t)i;
-    uint64_t* slot = a.slots + s * a.stride;
-    slot[0] = kEmpty;
-    for (int w = 1; w < a.stride; ++w) slot[w] = 0;
+  if (i0 == 0) {
+    a.hdr->cap = cap;
+    a.keys[a.cap_alloc] = kEmpty;
+    a.meta[a.cap_alloc] = 0;
+    for (int w = 0; w < a.acc_slots; ++w) a.acc[a.cap_alloc * a.acc_slots + w] = 0;
+  }
+  for (int64_t i = i0; i < (int64_t)cap; i += stride) {
+    a.keys[i] = kEmpty;
+    a.meta[i] = 0;
   }
 }
 
@@ -116,35 +134,50 @@ __global__ __launch_bounds__(BLOCK) void k_jinsert(const JoinBuildArgs a) {
   const uint32_t keep = build_rows_keep<ITEMS>(a, r0, key);
   if (!keep) return;
   const uint64_t cap = a.hdr->cap;
-#pragma unroll
-  for (int k = 0; k < ITEMS; ++k) {
-    if (!((keep >> k) & 1u)) continue;
+  uint64_t start[ITEMS], first[ITEMS];
+  static_for<0, ITEMS>([&](auto kk) __attribute__((always_inline)) {
+    constexpr int k = decltype(kk)::value;
+    start[k] = slot_of((uint64_t)key[k], cap);
+    first[k] = ((keep >> k) & 1u) ? a.keys[start[k]] : kEmpty;
+  });
+  static_for<0, ITEMS>([&](auto kk) __attribute__((always_inline)) {
+    constexpr int k = decltype(kk)::value;
+    if (!((keep >> k) & 1u)) return;
     const uint64_t kv = (uint64_t)key[k];
     const uint64_t row = (uint64_t)(r0 + k);
-    uint64_t* slot = nullptr;
+    int64_t s;
+    bool inserted = false;
     if (kv == kEmpty) {
-      slot = a.slots + a.max_cap * a.stride;
+      s = (int64_t)a.cap_alloc;
     } else {
-      slot = table_find_insert(a.slots, cap, a.stride, kv);
-      if (!slot) {
+      s = find_insert_from(a.keys, cap, kv, start[k], opaque_copy(first[k]), &inserted);
+      if (s < 0) {
         a.hdr->full = 1;
         atomicOr(a.dev_status, GQ_DEV_TABLE_FULL);
-        continue;
+        return;
       }
     }
-    // Count in the high half, row in the low half (stored by the first inserter).
-    const uint64_t old = atomicAdd((unsigned long long*)&slot[1], 1ull << 32);
-    if ((old >> 32) == 0)
-      atomicAdd((unsigned long long*)&slot[1], row);
-    else
-      a.hdr->has_dups = 1;
-  }
+    if (inserted) {
+      for (int w = 0; w < a.acc_slots; ++w) a.acc[(uint64_t)s * a.acc_slots + w] = 0;
+      // Count and row in one atomic.  Another inserter of the same key may have
+      // landed first; then the row sum is meaningless, but duplicates are
+      // flagged and the run construction below rewrites the word.
+      const uint64_t old = atomicAdd((unsigned long long*)&a.meta[s], (1ull << 32) | row);
+      if (meta_count(old) != 0) a.hdr->has_dups = 1;
+    } else {
+      // An existing key (or the extra slot): the first to arrive records its row.
+      const uint64_t old = atomicAdd((unsigned long long*)&a.meta[s], 1ull << 32);
+      if (meta_count(old) == 0)
+        atomicAdd((unsigned long long*)&a.meta[s], row);
+      else
+        a.hdr->has_dups = 1;
+    }
+  });
 }
 
 // Exclusive scan of slot counts over [0, cap) and the extra slot (entry cap).
 template <int BLOCK, int ITEMS>
-__global__ __launch_bounds__(BLOCK) void k_jdup_scan(const JoinBuildArgs a, uint32_t* ticket, uint64_t* status,
-                                                     int64_t nblocks) {
+__global__ __launch_bounds__(BLOCK) void k_jdup_scan(const JoinBuildArgs a, uint32_t* ticket, uint64_t* status) {
   if (!a.hdr->has_dups) return;
   constexpr int TILE = BLOCK * ITEMS;
   constexpr int NW = BLOCK / kWave;
@@ -163,9 +196,8 @@ __global__ __launch_bounds__(BLOCK) void k_jdup_scan(const JoinBuildArgs a, uint
     const int64_t i = i0 + k;
     c[k] = 0;
     if (i <= (int64_t)cap) {
-      const uint64_t s = (i == (int64_t)cap) ? a.max_cap : (uint64_t)i;
-      const uint64_t* slot = a.slots + s * a.stride;
-      if (slot[0] != kEmpty || s == a.max_cap) c[k] = slot_count(slot);
+      const uint64_t s = (i == (int64_t)cap) ? a.cap_alloc : (uint64_t)i;
+      if (s == a.cap_alloc || a.keys[s] != kEmpty) c[k] = meta_count(a.meta[s]);
     }
     tsum += c[k];
   }
@@ -194,10 +226,9 @@ __global__ __launch_bounds__(BLOCK) void k_jdup_scan(const JoinBuildArgs a, uint
   for (int k = 0; k < ITEMS; ++k) {
     const int64_t i = i0 + k;
     if (i <= (int64_t)cap && c[k] > 0) {
-      const uint64_t s = (i == (int64_t)cap) ? a.max_cap : (uint64_t)i;
-      uint64_t* slot = a.slots + s * a.stride;
-      slot[1] = ((uint64_t)c[k] << 32) | (uint64_t)(uint32_t)run;  // start replaces the row
-      a.aux[s == a.max_cap ? cap : s] = (uint32_t)run;              // fill cursor
+      const uint64_t s = (i == (int64_t)cap) ? a.cap_alloc : (uint64_t)i;
+      a.meta[s] = ((uint64_t)c[k] << 32) | (uint64_t)(uint32_t)run;  // run start replaces the row
+      a.aux[s == a.cap_alloc ? cap : s] = (uint32_t)run;             // fill cursor
     }
     run += c[k];
   }
@@ -218,9 +249,9 @@ __global__ __launch_bounds__(BLOCK) void k_jdup_fill(const JoinBuildArgs a) {
     if (kv == kEmpty) {
       idx = cap;
     } else {
-      const uint64_t* slot = table_find(a.slots, cap, a.stride, kv);
-      if (!slot) continue;  // only after a full table, already reported
-      idx = (uint64_t)(slot - a.slots) / (uint64_t)a.stride;
+      const int64_t s = find(a.keys, cap, kv);
+      if (s < 0) continue;  // only after a full table, already reported
+      idx = (uint64_t)s;
     }
     const uint32_t pos = atomicAdd(&a.aux[idx], 1u);
     a.rows[pos] = (int32_t)(r0 + k);
@@ -234,12 +265,12 @@ __global__ void k_jdup_sort(const JoinBuildArgs a) {
   const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = i0; i <= (int64_t)cap; i += stride) {
-    const uint64_t s = (i == (int64_t)cap) ? a.max_cap : (uint64_t)i;
-    const uint64_t* slot = a.slots + s * a.stride;
-    if (s != a.max_cap && slot[0] == kEmpty) continue;
-    const uint32_t cnt = slot_count(slot);
+    const uint64_t s = (i == (int64_t)cap) ? a.cap_alloc : (uint64_t)i;
+    if (s != a.cap_alloc && a.keys[s] == kEmpty) continue;
+    const uint64_t m = a.meta[s];
+    const uint32_t cnt = meta_count(m);
     if (cnt < 2) continue;
-    int32_t* r = a.rows + slot_row(slot);
+    int32_t* r = a.rows + meta_row(m);
     if (cnt <= (uint32_t)kShortRun) {
       for (uint32_t x = 1; x < cnt; ++x) {
         const int32_t v = r[x];
@@ -251,7 +282,7 @@ __global__ void k_jdup_sort(const JoinBuildArgs a) {
         r[y + 1] = v;
       }
     } else {
-      const unsigned long long pos = atomicAdd((unsigned long long*)&a.hdr->pad[0], 1ull);
+      const unsigned long long pos = atomicAdd((unsigned long long*)&a.hdr->nlong, 1ull);
       a.aux[pos] = (uint32_t)s;
     }
   }
@@ -262,12 +293,11 @@ __global__ void k_jdup_sort(const JoinBuildArgs a) {
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_jdup_sort_long(const JoinBuildArgs a) {
   if (!a.hdr->has_dups) return;
-  const int64_t nlong = a.hdr->pad[0];
+  const int64_t nlong = a.hdr->nlong;
   for (int64_t li = blockIdx.x; li < nlong; li += gridDim.x) {
-    const uint64_t s = a.aux[li];
-    const uint64_t* slot = a.slots + s * a.stride;
-    const uint32_t cnt = slot_count(slot);
-    const uint32_t start = slot_row(slot);
+    const uint64_t m = a.meta[a.aux[li]];
+    const uint32_t cnt = meta_count(m);
+    const uint32_t start = meta_row(m);
     int32_t* src = a.rows + start;
     int32_t* dst = a.tmp + start;
     for (uint32_t w = 1; w < cnt; w <<= 1) {
@@ -279,18 +309,17 @@ __global__ __launch_bounds__(BLOCK) void k_jdup_sort_long(const JoinBuildArgs a)
         const int32_t v = src[i];
         uint32_t pos;
         if (i < mid) {
-          // elements of the right half smaller than v
-          uint32_t l = mid, h = hi;
+          uint32_t l = mid, h = hi;  // right-half elements smaller than v
           while (l < h) {
-            const uint32_t m = (l + h) >> 1;
-            if (src[m] < v) l = m + 1; else h = m;
+            const uint32_t q = (l + h) >> 1;
+            if (src[q] < v) l = q + 1; else h = q;
           }
           pos = lo + (i - lo) + (l - mid);
         } else {
-          uint32_t l = lo, h = mid;
+          uint32_t l = lo, h = mid;  // left-half elements smaller than v
           while (l < h) {
-            const uint32_t m = (l + h) >> 1;
-            if (src[m] < v) l = m + 1; else h = m;
+            const uint32_t q = (l + h) >> 1;
+            if (src[q] < v) l = q + 1; else h = q;
           }
           pos = lo + (i - mid) + (l - lo);
         }
@@ -317,13 +346,14 @@ struct ProbeArgs {
   int64_t out_cap;
   DCol key;
   int32_t npreds;
-  int32_t stride;
+  int32_t pad;
   DPred preds[GQ_MAX_PREDS];
   DCol pcols[GQ_MAX_PREDS];
   const JoinHdr* hdr;
-  const uint64_t* slots;
+  const uint64_t* keys;
+  const uint64_t* meta;
   const int32_t* rows;
-  uint64_t max_cap;
+  uint64_t cap_alloc;
   int32_t* probe_idx;
   int32_t* build_idx;
   uint32_t* ticket;
@@ -360,35 +390,41 @@ __global__ __launch_bounds__(BLOCK) void k_jprobe(const ProbeArgs a) {
     if (r0 + k < a.n) keep |= 1u << k;
   for (int p = 0; p < a.npreds; ++p) {
     int64_t v[ITEMS];
-    load_items<ITEMS>(a.pcols[p], r0, a.n, v);
+    load_items<ITEMS, true>(a.pcols[p], r0, a.n, v);
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k)
       if (!pred_pass(a.preds[p], v[k])) keep &= ~(1u << k);
     if (a.pcols[p].valid) keep &= valid_items<ITEMS>(a.pcols[p], r0, a.n);
   }
   int64_t key[ITEMS];
-  load_items<ITEMS>(a.key, r0, a.n, key);
+  load_items<ITEMS, true>(a.key, r0, a.n, key);
   if (a.key.valid) keep &= valid_items<ITEMS>(a.key, r0, a.n);
 
   const uint64_t cap = a.hdr->cap;
   const bool dups = a.hdr->has_dups != 0;
-  uint32_t cnt[ITEMS], start[ITEMS];
+  uint64_t start[ITEMS], first[ITEMS];
+  static_for<0, ITEMS>([&](auto kk) __attribute__((always_inline)) {
+    constexpr int k = decltype(kk)::value;
+    start[k] = slot_of((uint64_t)key[k], cap);
+    first[k] = ((keep >> k) & 1u) ? a.keys[start[k]] : kEmpty;
+  });
+  uint32_t cnt[ITEMS], srow[ITEMS];
   int64_t tsum = 0;
-#pragma unroll
-  for (int k = 0; k < ITEMS; ++k) {
+  static_for<0, ITEMS>([&](auto kk) __attribute__((always_inline)) {
+    constexpr int k = decltype(kk)::value;
     cnt[k] = 0;
-    start[k] = 0;
+    srow[k] = 0;
     if ((keep >> k) & 1u) {
       const uint64_t kv = (uint64_t)key[k];
-      const uint64_t* slot = kv == kEmpty ? a.slots + a.max_cap * a.stride : table_find(a.slots, cap, a.stride, kv);
-      if (slot) {
-        const uint64_t w1 = slot[1];
-        cnt[k] = (uint32_t)(w1 >> 32);
-        start[k] = (uint32_t)w1;
+      const int64_t s = kv == kEmpty ? (int64_t)a.cap_alloc : find_from(a.keys, cap, kv, start[k], opaque_copy(first[k]));
+      if (s >= 0) {
+        const uint64_t m = a.meta[s];
+        cnt[k] = meta_count(m);
+        srow[k] = meta_row(m);
       }
     }
     tsum += cnt[k];
-  }
+  });
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   int64_t incl = tsum;
 #pragma unroll
@@ -415,14 +451,14 @@ __global__ __launch_bounds__(BLOCK) void k_jprobe(const ProbeArgs a) {
     if (total > a.out_cap) atomicOr(a.dev_status, GQ_DEV_CAPACITY);
   }
   int64_t pos = s_excl + bpre + incl - tsum;
-#pragma unroll
-  for (int k = 0; k < ITEMS; ++k) {
+  static_for<0, ITEMS>([&](auto kk) __attribute__((always_inline)) {
+    constexpr int k = decltype(kk)::value;
     for (uint32_t j = 0; j < cnt[k]; ++j, ++pos) {
       if (pos >= a.out_cap) break;
       a.probe_idx[pos] = (int32_t)(r0 + k);
-      a.build_idx[pos] = dups ? a.rows[start[k] + j] : (int32_t)start[k];
+      a.build_idx[pos] = dups ? a.rows[srow[k] + j] : (int32_t)srow[k];
     }
-  }
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -513,18 +549,18 @@ int gq_join_build(gq_ctx* ctx, const gq_batch* build, const int32_t* keys, int n
   a.lf_milli = (int)(lf * 1000.f + 0.5f);
   if (a.lf_milli < 1) a.lf_milli = 1;
   const int64_t n = build->nrows;
-  uint64_t max_cap = ((uint64_t)n * 1000 + a.lf_milli - 1) / (uint64_t)a.lf_milli;
-  if (max_cap < 1) max_cap = 1;
-  a.max_cap = max_cap;
-  a.stride = 2 + acc;
+  uint64_t cap_alloc = ((uint64_t)n * 1000 + a.lf_milli - 1) / (uint64_t)a.lf_milli;
+  if (cap_alloc < 1) cap_alloc = 1;
+  a.cap_alloc = cap_alloc;
   a.acc_slots = acc;
 
-  const size_t off_hdr = 0;
-  const size_t off_slots = 256;
-  const size_t slot_bytes = (size_t)(max_cap + 1) * a.stride * 8;
-  const size_t off_rows = align_up(off_slots + slot_bytes, 256);
+  const size_t nslot = (size_t)cap_alloc + 1;
+  const size_t off_keys = 256;
+  const size_t off_meta = align_up(off_keys + nslot * 8, 256);
+  const size_t off_acc = align_up(off_meta + nslot * 8, 256);
+  const size_t off_rows = align_up(off_acc + nslot * 8 * (size_t)acc, 256);
   const size_t off_aux = align_up(off_rows + (size_t)n * 4, 256);
-  const size_t off_tmp = align_up(off_aux + (size_t)(max_cap + 1) * 4, 256);
+  const size_t off_tmp = align_up(off_aux + nslot * 4, 256);
   const size_t total = align_up(off_tmp + (size_t)n * 4, 256);
 
   GQ_HIP_CHECK(ctx, hipSetDevice(ctx->device));
@@ -538,19 +574,22 @@ int gq_join_build(gq_ctx* ctx, const gq_batch* build, const int32_t* keys, int n
   }
   t->bytes = total;
   char* base = static_cast<char*>(t->mem);
-  t->hdr = reinterpret_cast<JoinHdr*>(base + off_hdr);
-  t->slots = reinterpret_cast<uint64_t*>(base + off_slots);
+  t->hdr = reinterpret_cast<JoinHdr*>(base);
+  t->keys = reinterpret_cast<uint64_t*>(base + off_keys);
+  t->meta = reinterpret_cast<uint64_t*>(base + off_meta);
+  t->acc = acc ? reinterpret_cast<uint64_t*>(base + off_acc) : nullptr;
   t->rows = reinterpret_cast<int32_t*>(base + off_rows);
   t->aux = reinterpret_cast<uint32_t*>(base + off_aux);
   t->tmp = reinterpret_cast<int32_t*>(base + off_tmp);
-  t->max_cap = max_cap;
-  t->stride = a.stride;
+  t->cap_alloc = cap_alloc;
   t->acc_slots = acc;
   t->build_rows = n;
   t->key_type = build->cols[keys[0]].type;
   t->device = ctx->device;
   a.hdr = t->hdr;
-  a.slots = t->slots;
+  a.keys = t->keys;
+  a.meta = t->meta;
+  a.acc = t->acc;
   a.rows = t->rows;
   a.aux = t->aux;
   a.tmp = t->tmp;
@@ -558,13 +597,17 @@ int gq_join_build(gq_ctx* ctx, const gq_batch* build, const int32_t* keys, int n
 
   constexpr int TILE = kJBlock * kJItems;
   const int64_t nblk = (n + TILE - 1) / TILE;
+  auto fail = [&](int code) {
+    gq_join_table_free(ctx, t, stream);
+    return code;
+  };
   GQ_LAUNCH(ctx, "jhdr_init", k_jhdr_init, dim3(1), dim3(64), 0, stream, t->hdr);
   GQ_LAUNCH_CHECK(ctx);
   if (nblk > 0) {
     GQ_LAUNCH(ctx, "jcount", (k_jcount<kJBlock, kJItems>), dim3((unsigned)nblk), dim3(kJBlock), 0, stream, a);
     GQ_LAUNCH_CHECK(ctx);
   }
-  int64_t iblocks = (int64_t)((max_cap + 1 + 255) / 256);
+  int64_t iblocks = (int64_t)((cap_alloc + 1 + 255) / 256);
   if (iblocks > 8192) iblocks = 8192;
   GQ_LAUNCH(ctx, "jinit", k_jinit, dim3((unsigned)iblocks), dim3(256), 0, stream, a);
   GQ_LAUNCH_CHECK(ctx);
@@ -573,16 +616,16 @@ int gq_join_build(gq_ctx* ctx, const gq_batch* build, const int32_t* keys, int n
     GQ_LAUNCH_CHECK(ctx);
     // Duplicate handling (kernels return at once when every key is unique).
     constexpr int STILE = 256 * 16;
-    const int64_t nscan = (int64_t)((max_cap + 1 + STILE - 1) / STILE);
+    const int64_t nscan = (int64_t)((cap_alloc + 1 + STILE - 1) / STILE);
     Scratch ws(ctx, stream);
     if (!ws.get(256 + align_up((size_t)nscan * 8, 256))) {
-      gq_join_table_free(ctx, t, stream);
-      return set_error(ctx, GQ_ERR_NOMEM, "gq_join_build: workspace allocation failed");
+      set_error(ctx, GQ_ERR_NOMEM, "gq_join_build: workspace allocation failed");
+      return fail(GQ_ERR_NOMEM);
     }
     rc = launch_fill_u32(ctx, ws.p, 0u, 64 + 2 * nscan, stream);
-    if (rc) return rc;
-    GQ_LAUNCH(ctx, "jdup_scan", (k_jdup_scan<256, 16>), dim3((unsigned)nscan), dim3(256), 0, stream, a, ws.as<uint32_t>(0),
-                       ws.as<uint64_t>(256), nscan);
+    if (rc) return fail(rc);
+    GQ_LAUNCH(ctx, "jdup_scan", (k_jdup_scan<256, 16>), dim3((unsigned)nscan), dim3(256), 0, stream, a,
+              ws.as<uint32_t>(0), ws.as<uint64_t>(256));
     GQ_LAUNCH_CHECK(ctx);
     GQ_LAUNCH(ctx, "jdup_fill", (k_jdup_fill<kJBlock, kJItems>), dim3((unsigned)nblk), dim3(kJBlock), 0, stream, a);
     GQ_LAUNCH_CHECK(ctx);
@@ -617,11 +660,11 @@ int gq_join_probe(gq_ctx* ctx, const gq_join_table* table, const gq_batch* probe
     a.preds[p] = b.preds[p];
     a.pcols[p] = b.pcols[p];
   }
-  a.stride = table->stride;
   a.hdr = table->hdr;
-  a.slots = table->slots;
+  a.keys = table->keys;
+  a.meta = table->meta;
   a.rows = table->rows;
-  a.max_cap = table->max_cap;
+  a.cap_alloc = table->cap_alloc;
   a.probe_idx = probe_idx;
   a.build_idx = build_idx;
   a.d_count = d_count;
@@ -638,8 +681,8 @@ int gq_join_probe(gq_ctx* ctx, const gq_join_table* table, const gq_batch* probe
   int64_t iblocks = (ntiles + 255) / 256;
   if (iblocks < 1) iblocks = 1;
   if (iblocks > 4096) iblocks = 4096;
-  GQ_LAUNCH(ctx, "probe_init", k_probe_init, dim3((unsigned)iblocks), dim3(256), 0, stream, a.ticket, a.status, ntiles,
-                     d_count);
+  GQ_LAUNCH(ctx, "probe_init", k_probe_init, dim3((unsigned)iblocks), dim3(256), 0, stream, a.ticket, a.status,
+            ntiles, d_count);
   GQ_LAUNCH_CHECK(ctx);
   if (ntiles > 0) {
     GQ_LAUNCH(ctx, "jprobe", (k_jprobe<kJBlock, kJItems>), dim3((unsigned)ntiles), dim3(kJBlock), 0, stream, a);

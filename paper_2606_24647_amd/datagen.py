@@ -88,6 +88,16 @@ def raw(seed: int, col: int, start: int, n: int) -> np.ndarray:
         return _mix(z)
 
 
+def raw_at(seed: int, col: int, rows: np.ndarray) -> np.ndarray:
+    """r(row) for arbitrary row indices (uint64)."""
+    s = stream_seed(seed, col)
+    with np.errstate(over="ignore"):
+        z = np.asarray(rows, dtype=np.uint64) + np.uint64(1)
+        z *= _U64(GAMMA)
+        z += _U64(s)
+        return _mix(z)
+
+
 def _mulhi_small(r: np.ndarray, m: int) -> np.ndarray:
     """floor(r * m / 2**64) for uint64 r and 0 < m <= 2**32, exact."""
     assert 0 < m <= (1 << 32)
@@ -107,6 +117,14 @@ def uniform(seed: int, col: int, start: int, n: int, lo: int, hi: int,
     assert hi >= lo and hi - lo + 1 <= (1 << 32)
     r = raw(seed, col, start, n)
     v = _mulhi_small(r, hi - lo + 1).astype(np.int64)
+    v += lo
+    return v.astype(dtype, copy=False)
+
+
+def uniform_at(seed: int, col: int, rows: np.ndarray, lo: int, hi: int, dtype=np.int64) -> np.ndarray:
+    """Uniform integers on [lo, hi] at arbitrary row indices (same values as uniform())."""
+    assert hi >= lo and hi - lo + 1 <= (1 << 32)
+    v = _mulhi_small(raw_at(seed, col, rows), hi - lo + 1).astype(np.int64)
     v += lo
     return v.astype(dtype, copy=False)
 
