@@ -27,6 +27,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -218,6 +220,129 @@ def run_operators(torch, gq, devgen, ctx, c2, reps=5):
 
 
 # ---------------------------------------------------------------------------
+# Batched fragments: 4096 filter + group-by fragments in one graph launch
+# ---------------------------------------------------------------------------
+
+def c4_device_fragments(torch, devgen, dg, nfrag, align=16):
+    """All fragments in five device columns, each fragment starting on a 16-row
+    boundary; returns (spec, list of DevTable views)."""
+    from paper_2606_24647_amd.gq import DevColumn, DevTable
+    spec = dg.fragments_c4(nfrag)
+    starts = np.zeros(nfrag + 1, dtype=np.int64)
+    for f in range(nfrag):
+        starts[f + 1] = starts[f] + (int(spec.rows[f]) + align - 1) // align * align
+    total = int(starts[-1])
+    cols = [torch.empty(total, dtype=dt, device="cuda") for dt in
+            (torch.int64, torch.int64, torch.int64, torch.int32, torch.int32)]
+    ranges = [(1, 50), (dg.PRICE_LO, dg.PRICE_HI), (0, 10), (0, dg.DATE_DAYS - 1), None]
+    tables = []
+    for f in range(nfrag):
+        n, card = int(spec.rows[f]), int(spec.card[f])
+        s0 = int(starts[f])
+        seed = dg.fragment_seed(f)
+        views = []
+        for c, (col, rg) in enumerate(zip(cols, ranges)):
+            lo, hi = rg if rg is not None else (0, card - 1)
+            v = col[s0:s0 + n]
+            devgen.uniform(seed, c, 0, n, lo, hi, out=v)
+            views.append(DevColumn(v))
+        tables.append(DevTable(views))
+    return spec, tables, cols
+
+
+def run_batched(torch, gq, devgen, ctx, steps=5, nfrag=4096, tune=True):
+    from paper_2606_24647_amd import datagen as dg
+    from paper_2606_24647_amd import autotune
+    log(f"generating {nfrag} fragments on the device")
+    spec, tables, cols = c4_device_fragments(torch, devgen, dg, nfrag)
+    torch.cuda.synchronize()
+    preds = [[("range", 3, 0, int(b))] for b in spec.bound]
+    frags = [(t, p, int(c)) for t, p, c in zip(tables, preds, spec.card)]
+    total_rows = int(spec.rows.sum())
+    cfg = autotune.best_batch_config(ctx, frags, [4], C1_AGGS) if tune else {}
+    log(f"batched config: {cfg}")
+    plan = gq.BatchPlan(ctx, frags, [4], C1_AGGS, **cfg)
+    plan.launch()
+    ctx.raise_status()
+    ts = []
+    for _ in range(steps):
+        with Timer(torch) as tm:
+            plan.launch()
+        ts.append(tm.ms())
+    ctx.raise_status()
+    groups_b = plan.d_groups.clone()
+    ms_b = median(ts)
+    # Plain: one gq_groupby_agg per fragment, back to back on one stream.
+    log("plain path: one call per fragment")
+    lat = []
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in frags]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with Timer(torch) as tm:
+        for (t, p, c), (a, b) in zip(frags, ev):
+            a.record()
+            ctx.groupby_agg(t, [4], p, C1_AGGS, capacity=max(1, min(t.nrows, c)), expected_groups=c)
+            b.record()
+    ms_p = tm.ms()
+    wall_p = time.perf_counter() - t0
+    ctx.raise_status()
+    lat = sorted(a.elapsed_time(b) for a, b in ev)
+    groups = int(groups_b.sum().item())
+    nbytes = total_rows * 32 + groups * (4 + 5 * 8)
+    plan.free()
+    del tables, cols
+    torch.cuda.empty_cache()
+    return {"fragments": nfrag, "rows": total_rows, "groups": groups, "config": cfg,
+            "batched": {"ms": round(ms_b, 3), "rows_per_s": total_rows / (ms_b * 1e-3),
+                        "GBps": nbytes / (ms_b * 1e-3) / 1e9, "frac_hbm_peak": nbytes / (ms_b * 1e-3) / 1e9 / PEAK_GBS,
+                        "fragment_latency_ms_p50": round(ms_b, 3), "fragment_latency_ms_p99": round(ms_b, 3)},
+            "plain": {"ms": round(ms_p, 3), "wall_ms": round(1e3 * wall_p, 3), "rows_per_s": total_rows / (ms_p * 1e-3),
+                      "fragment_latency_ms_p50": round(lat[len(lat) // 2], 4),
+                      "fragment_latency_ms_p99": round(lat[int(len(lat) * 0.99)], 4)},
+            "speedup_batched_vs_plain": ms_p / ms_b}
+
+
+# ---------------------------------------------------------------------------
+# Serving: Poisson arrivals against device-resident 600M x 150M tables
+# ---------------------------------------------------------------------------
+
+def run_serving(torch, gq, devgen, nq=150, qps_list=(50, 100, 200), budget_gb=120, slots=4, p99_bound_ms=250.0):
+    from paper_2606_24647_amd import datagen as dg
+    from paper_2606_24647_amd import serve
+    log("generating resident fact 600M x 7 and dim 150M x 3 on the device")
+    fact = devgen.fact_c5()
+    dim = devgen.dim_c5()
+    torch.cuda.synchronize()
+    budget = int(budget_gb) << 30
+    res = {"resident_gb": round((dg.C5_FACT_ROWS * 38 + dg.C5_DIM_ROWS * 20) / 1e9, 2), "queries_per_run": nq,
+           "slots": slots, "budget_gb": budget_gb, "runs": []}
+    plain_ex = serve.DeviceExecutor(gq, torch, fact, dim, nslots=1)
+    served_ex = serve.DeviceExecutor(gq, torch, fact, dim, nslots=slots)
+    # warm up every query kind on both executors
+    warm = [serve.Query(i, k, 0.0, p) for i, (k, p) in enumerate(
+        [("agg", {"b": 2000}), ("join", {"b_dim": 1200, "b_fact": 1300}), ("part", {"b": 1500, "P": 64})])]
+    serve.Scheduler(plain_ex, budget).run(warm)
+    serve.Scheduler(served_ex, budget).run(warm)
+    for qps in qps_list:
+        qs = serve.make_workload(nq, qps, seed=5)
+        for mode, ex in (("plain", plain_ex), ("served", served_ex)):
+            log(f"serving: {mode} at {qps} QPS, {nq} queries")
+            recs = serve.Scheduler(ex, budget).run(qs)
+            sm = serve.summarize(recs)
+            sm.update(mode=mode, qps=qps)
+            res["runs"].append({k: (round(v, 3) if isinstance(v, float) else v) for k, v in sm.items()})
+    best = {}
+    for mode in ("plain", "served"):
+        ok = [r for r in res["runs"] if r["mode"] == mode and r["p99_ms"] <= p99_bound_ms]
+        best[mode] = max((r["rows_per_s"] for r in ok), default=None)
+    res["p99_bound_ms"] = p99_bound_ms
+    res["best_rows_per_s_within_p99_bound"] = best
+    del fact, dim, plain_ex, served_ex
+    torch.cuda.empty_cache()
+    return res
+
+
+# ---------------------------------------------------------------------------
 # CPU baseline: the oracle on a sample
 # ---------------------------------------------------------------------------
 
@@ -244,6 +369,8 @@ def main():
     ap.add_argument("--load-factor", type=float, default=0.5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-operators", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the build targets a single MI355X); --gpus {args.gpus} "
@@ -281,6 +408,12 @@ def main():
         operators = run_operators(torch, gq, devgen, ctx, c2)
     else:
         del c2["dim"], c2["fact"]
+    batched = None
+    if not args.no_batched:
+        batched = run_batched(torch, gq, devgen, ctx)
+    serving = None
+    if not args.no_serving:
+        serving = run_serving(torch, gq, devgen)
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on a 1/10 sample")
@@ -311,6 +444,8 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "operators": operators,
+        "batched_fragments": batched,
+        "serving": serving,
     }
     print(json.dumps(line), flush=True)
 

@@ -331,6 +331,54 @@ typedef struct gq_plan {
 int gq_pipeline(gq_ctx* ctx, const gq_plan* plan, const gq_batch* in, gq_batch* out,
                 int64_t* d_groups, hipStream_t stream);
 
+/* ---- batched fragments ----------------------------------------------------------
+ * Many independent filter + group-by fragments of very different sizes run as
+ * one plan: one persistent launch over tiles of all fragments, captured once in
+ * a HIP graph and replayed by gq_batch_plan_launch.  (Section 2.3 finds that
+ * the largest batch that fits memory runs fastest; Section 3.3 that millions
+ * of small vectors degrade GPU libraries until merged.)  Every fragment has the
+ * same key and aggregate shape (spec) and its own columns, predicate bounds,
+ * output and cardinality hint.  Results equal one gq_groupby_agg call per
+ * fragment (output in slot order). */
+typedef struct gq_fragment {
+  gq_batch in;              /* the fragment's rows (device columns) */
+  const gq_pred* preds;     /* host array, read during plan creation */
+  int32_t npreds;
+  int32_t reserved;
+  int64_t expected_groups;  /* cardinality hint sizing the fragment's table;
+                               0 = its row count */
+  gq_batch out;             /* nkeys key columns then naggs int64 columns */
+  int64_t* d_groups;        /* device int64: the fragment's group count */
+} gq_fragment;
+
+typedef struct gq_batch_spec {
+  const int32_t* keys;
+  int32_t nkeys;
+  int32_t naggs;
+  const gq_agg* aggs;
+  float load_factor;        /* 0 = 0.5 */
+  int32_t lds_max_groups;   /* fragments expecting at most this many groups
+                               aggregate in LDS first; 0 = 256, -1 = never */
+  int32_t tile_rows;        /* rows per work item, multiple of 1024; 0 = 8192 */
+  int32_t blocks_per_cu;    /* persistent blocks per compute unit; 0 = 4 */
+} gq_batch_spec;
+
+typedef struct gq_batch_plan gq_batch_plan;
+
+/* Validate the fragments, allocate every fragment's table in one arena (via
+ * the context allocator), upload the descriptors and capture the graph.
+ * Synchronises `stream` once.  Inputs and outputs must stay valid while the
+ * plan is launched. */
+int gq_batch_plan_create(gq_ctx* ctx, const gq_fragment* frags, int nfrags, const gq_batch_spec* spec,
+                         hipStream_t stream, gq_batch_plan** out);
+/* Enqueue one execution of the plan (a graph launch) on `stream`. */
+int gq_batch_plan_launch(gq_batch_plan* plan, hipStream_t stream);
+/* Plan statistics (any pointer may be NULL). */
+int gq_batch_plan_info(const gq_batch_plan* plan, int64_t* total_rows, int64_t* tiles, int64_t* table_slots,
+                       int64_t* bytes);
+/* Wait for the device, then release the plan. */
+int gq_batch_plan_free(gq_batch_plan* plan);
+
 #ifdef __cplusplus
 }
 #endif

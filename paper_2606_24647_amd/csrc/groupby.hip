@@ -17,7 +17,7 @@
 // weight m (SUM adds m*x, COUNT adds m), which equals aggregating the
 // materialised join.  All sums wrap modulo 2^64 and are therefore independent
 // of the order in which atomics land.
-#include "table.h"
+#include "agg.h"
 
 namespace gq {
 namespace {
@@ -25,246 +25,7 @@ namespace {
 constexpr int kGbBlock = 256;
 constexpr int kGbItems = 4;
 constexpr int kGjItems = 8;
-constexpr int kLdsProbes = 16;
 constexpr size_t kLdsBudget = 32 * 1024;
-
-struct JoinRef {
-  const JoinHdr* hdr;
-  const uint64_t* keys;
-  const uint64_t* meta;
-  uint64_t* acc;
-  uint64_t cap_alloc;
-  int32_t acc_slots;
-  int32_t pad;
-  DCol key;  // probe key column
-};
-
-struct GbArgs {
-  int64_t n;
-  int64_t ntiles;
-  int32_t npreds;
-  int32_t lcap;      // LDS table slots (power of two), LDS strategy only
-  DPred preds[GQ_MAX_PREDS];
-  DCol pcols[GQ_MAX_PREDS];
-  KeyPlan kp;
-  AggPlan ap;
-  uint64_t* keys;    // HBM group table: cap hashed slots, then 2 extra slots
-  uint64_t* acc;     // ap.nacc words per slot
-  uint64_t cap;
-  JoinRef join;
-  int32_t* dev_status;
-};
-
-template <int ITEMS>
-__device__ __forceinline__ void load_col(const DCol& c, int64_t r0, int64_t n, int64_t (&v)[ITEMS]) {
-  if (c.nt) load_items<ITEMS, true>(c, r0, n, v);
-  else load_items<ITEMS, false>(c, r0, n, v);
-}
-
-// ---------------------------------------------------------------------------
-// Per-tile row evaluation shared by the kernels
-// ---------------------------------------------------------------------------
-template <int ITEMS>
-__device__ __forceinline__ uint32_t eval_preds(const GbArgs& a, int64_t r0) {
-  uint32_t keep = 0;
-#pragma unroll
-  for (int k = 0; k < ITEMS; ++k)
-    if (r0 + k < a.n) keep |= 1u << k;
-  for (int p = 0; p < a.npreds; ++p) {
-    int64_t v[ITEMS];
-    load_col<ITEMS>(a.pcols[p], r0, a.n, v);
-#pragma unroll
-    for (int k = 0; k < ITEMS; ++k)
-      if (!pred_pass(a.preds[p], v[k])) keep &= ~(1u << k);
-    if (a.pcols[p].valid) keep &= valid_items<ITEMS>(a.pcols[p], r0, a.n);
-  }
-  return keep;
-}
-
-// Join slots of the kept rows' probe keys (-1: no match), all first probes
-// issued before any is resolved.  Rows without a match are dropped from keep.
-template <int ITEMS>
-__device__ __forceinline__ void join_lookup(const JoinRef& j, int64_t r0, int64_t n, uint32_t& keep,
-                                            int64_t (&slot)[ITEMS]) {
-  int64_t kv[ITEMS];
-  load_col<ITEMS>(j.key, r0, n, kv);
-  if (j.key.valid) keep &= valid_items<ITEMS>(j.key, r0, n);
-  const uint64_t cap = j.hdr->cap;
-  uint64_t start[ITEMS], first[ITEMS];
-  static_for<0, ITEMS>([&](auto kk) __attribute__((always_inline)) {
-    constexpr int k = decltype(kk)::value;
-    start[k] = slot_of((uint64_t)kv[k], cap);
-    first[k] = ((keep >> k) & 1u) ? j.keys[start[k]] : kEmpty;
-  });
-  static_for<0, ITEMS>([&](auto kk) __attribute__((always_inline)) {
-    constexpr int k = decltype(kk)::value;
-    slot[k] = -1;
-    if (!((keep >> k) & 1u)) return;
-    const uint64_t key = (uint64_t)kv[k];
-    if (key == kEmpty) {
-      if (meta_count(j.meta[j.cap_alloc])) slot[k] = (int64_t)j.cap_alloc;
-    } else {
-      slot[k] = find_from(j.keys, cap, key, start[k], opaque_copy(first[k]));
-    }
-    if (slot[k] < 0) keep &= ~(1u << k);
-  });
-}
-
-// Match counts of found slots: 1 unless the build side had duplicate keys.
-template <int ITEMS>
-__device__ __forceinline__ void join_weights(const JoinRef& j, uint32_t keep, const int64_t (&slot)[ITEMS],
-                                             uint32_t (&w)[ITEMS]) {
-  const bool dups = j.hdr->has_dups != 0;
-  static_for<0, ITEMS>([&](auto kk) __attribute__((always_inline)) {
-    constexpr int k = decltype(kk)::value;
-    w[k] = 1;
-    if (((keep >> k) & 1u) && (dups || slot[k] == (int64_t)j.cap_alloc)) w[k] = meta_count(j.meta[slot[k]]);
-  });
-}
-
-// Group keys of ITEMS rows.  special: 0 hashed, 1 EMPTY-valued raw key, 2 NULL raw key.
-template <int ITEMS>
-__device__ __forceinline__ void make_keys(const KeyPlan& kp, int64_t r0, int64_t n, uint64_t (&key)[ITEMS],
-                                          uint8_t (&special)[ITEMS]) {
-#pragma unroll
-  for (int k = 0; k < ITEMS; ++k) {
-    key[k] = 0;
-    special[k] = 0;
-  }
-#pragma unroll
-  for (int j = 0; j < GQ_MAX_KEYS; ++j) {
-    if (j < kp.nk) {
-      int64_t v[ITEMS];
-      load_col<ITEMS>(kp.cols[j], r0, n, v);
-      const uint32_t vm = kp.cols[j].valid ? valid_items<ITEMS>(kp.cols[j], r0, n) : 0xffffffffu;
-      if (kp.mode == KEY_RAW64) {
-#pragma unroll
-        for (int k = 0; k < ITEMS; ++k) {
-          key[k] = (uint64_t)v[k];
-          special[k] = !((vm >> k) & 1u) ? 2 : (key[k] == kEmpty ? 1 : 0);
-        }
-      } else {
-        const int w = kp.bits[j];
-        const uint64_t mask = (w == 64) ? ~0ull : ((1ull << w) - 1);
-#pragma unroll
-        for (int k = 0; k < ITEMS; ++k) {
-          uint64_t f = ((uint64_t)v[k] ^ (1ull << (w - 1))) & mask;
-          if (kp.nullable[j]) f = ((vm >> k) & 1u) ? (f | (1ull << w)) : 0ull;
-          key[k] |= f << kp.shift[j];
-        }
-      }
-    }
-  }
-}
-
-// Input of aggregate `ag` for ITEMS rows: x[k] = product of its factors
-// (wrapping).  Returns the mask of rows whose input is non-NULL.  A column used
-// by several aggregates is re-read from cache (such columns use temporal loads).
-template <int ITEMS>
-__device__ __forceinline__ uint32_t agg_values(const DAgg& ag, const AggPlan& ap, int64_t r0, int64_t n,
-                                               uint64_t (&x)[ITEMS]) {
-  uint32_t nn = 0xffffffffu;
-#pragma unroll
-  for (int k = 0; k < ITEMS; ++k) x[k] = 1;
-  for (int f = 0; f < ag.nf; ++f) {
-    const DFactor& fa = ag.f[f];
-    if (fa.kind == GQ_F_CONST) {
-#pragma unroll
-      for (int k = 0; k < ITEMS; ++k) x[k] *= (uint64_t)fa.k;
-      continue;
-    }
-    const DCol& c = ap.vals[fa.v];
-    int64_t v[ITEMS];
-    load_col<ITEMS>(c, r0, n, v);
-    if (c.valid) nn &= valid_items<ITEMS>(c, r0, n);
-    const uint64_t kk = (uint64_t)fa.k;
-#pragma unroll
-    for (int k = 0; k < ITEMS; ++k) {
-      const uint64_t cv = (uint64_t)v[k];
-      const uint64_t t = fa.kind == GQ_F_COL ? cv : fa.kind == GQ_F_K_MINUS_COL ? kk - cv : kk + cv;
-      x[k] *= t;
-    }
-  }
-  return nn;
-}
-
-// Apply all aggregates of ITEMS rows.  Row k's accumulators are in LDS at
-// lds + loff[k] (loff[k] >= 0) or in HBM at gsp[k]; word 0 is the row count.
-template <int ITEMS>
-__device__ __forceinline__ void apply_rows(const AggPlan& ap, int64_t r0, int64_t n, uint32_t keep,
-                                           const uint32_t (&w)[ITEMS], uint64_t* lds, const int (&loff)[ITEMS],
-                                           uint64_t* const (&gsp)[ITEMS]) {
-  static_for<0, ITEMS>([&](auto kk) __attribute__((always_inline)) {
-    constexpr int k = decltype(kk)::value;
-    if (!((keep >> k) & 1u)) return;
-    if (loff[k] >= 0) SharedAtomics::add(&lds[loff[k]], w[k]);
-    else GlobalAtomics::add(&gsp[k][0], w[k]);
-  });
-  for (int i = 0; i < ap.naggs; ++i) {
-    const DAgg& ag = ap.aggs[i];
-    if (ag.op == GQ_COUNT_STAR) continue;
-    uint64_t x[ITEMS];
-    const uint32_t nn = agg_values<ITEMS>(ag, ap, r0, n, x) & keep;
-    static_for<0, ITEMS>([&](auto kk) __attribute__((always_inline)) {
-      constexpr int k = decltype(kk)::value;
-      if (!((nn >> k) & 1u)) return;
-      const uint64_t wk = w[k];
-      if (loff[k] >= 0) {
-        uint64_t* s = lds + loff[k];
-        switch (ag.op) {
-          case GQ_SUM: SharedAtomics::add(&s[ag.word], x[k] * wk); break;
-          case GQ_COUNT: SharedAtomics::add(&s[ag.word], wk); break;
-          case GQ_MIN: SharedAtomics::min(&s[ag.word], (int64_t)x[k]); break;
-          default: SharedAtomics::max(&s[ag.word], (int64_t)x[k]); break;
-        }
-        if (ag.cword >= 0) SharedAtomics::add(&s[ag.cword], wk);
-      } else {
-        uint64_t* s = gsp[k];
-        switch (ag.op) {
-          case GQ_SUM: GlobalAtomics::add(&s[ag.word], x[k] * wk); break;
-          case GQ_COUNT: GlobalAtomics::add(&s[ag.word], wk); break;
-          case GQ_MIN: GlobalAtomics::min(&s[ag.word], (int64_t)x[k]); break;
-          default: GlobalAtomics::max(&s[ag.word], (int64_t)x[k]); break;
-        }
-        if (ag.cword >= 0) GlobalAtomics::add(&s[ag.cword], wk);
-      }
-    });
-  }
-}
-
-// HBM accumulators of a row's group (hashed or extra), or nullptr if the table is full.
-__device__ __forceinline__ uint64_t* global_acc(const GbArgs& a, uint64_t key, int special) {
-  int64_t s;
-  if (special) {
-    s = (int64_t)(a.cap + (uint64_t)(special - 1));
-  } else {
-    bool ins;
-    s = find_insert(a.keys, a.cap, key, &ins);
-    if (s < 0) {
-      atomicOr(a.dev_status, GQ_DEV_TABLE_FULL);
-      return nullptr;
-    }
-  }
-  return a.acc + (uint64_t)s * a.ap.nacc;
-}
-
-// Merge one group's accumulators into HBM.
-__device__ __forceinline__ void merge_words(const AggPlan& ap, uint64_t* dst, const uint64_t* src) {
-  for (int w = 0; w < ap.nacc; ++w) {
-    const uint64_t v = src[w];
-    switch (ap.wop[w]) {
-      case WOP_ADD:
-        if (v) atomicAdd((unsigned long long*)&dst[w], (unsigned long long)v);
-        break;
-      case WOP_MIN:
-        if ((int64_t)v != INT64_MAX) atomicMin((long long*)&dst[w], (long long)v);
-        break;
-      default:
-        if ((int64_t)v != INT64_MIN) atomicMax((long long*)&dst[w], (long long)v);
-        break;
-    }
-  }
-}
 
 // ---------------------------------------------------------------------------
 // Kernels
@@ -297,7 +58,7 @@ template <int BLOCK, int ITEMS, bool JOIN>
 __global__ __launch_bounds__(BLOCK) void k_gb_global(const GbArgs a) {
   constexpr int TILE = BLOCK * ITEMS;
   const int64_t r0 = (int64_t)blockIdx.x * TILE + (int64_t)threadIdx.x * ITEMS;
-  uint32_t keep = eval_preds<ITEMS>(a, r0);
+  uint32_t keep = eval_preds<ITEMS>(a, r0, a.n);
   uint32_t w[ITEMS];
 #pragma unroll
   for (int k = 0; k < ITEMS; ++k) w[k] = 1;
@@ -338,7 +99,7 @@ __global__ __launch_bounds__(BLOCK) void k_gb_lds(const GbArgs a) {
 
   for (int64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
     const int64_t r0 = tile * TILE + (int64_t)threadIdx.x * ITEMS;
-    uint32_t keep = eval_preds<ITEMS>(a, r0);
+    uint32_t keep = eval_preds<ITEMS>(a, r0, a.n);
     uint32_t w[ITEMS];
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) w[k] = 1;
@@ -358,26 +119,7 @@ __global__ __launch_bounds__(BLOCK) void k_gb_lds(const GbArgs a) {
       loff[k] = -1;
       gsp[k] = nullptr;
       if (!((keep >> k) & 1u)) return;
-      if (!special[k]) {
-        uint32_t s = (uint32_t)slot_of(key[k], (uint64_t)lcap);
-        for (int p = 0; p < kLdsProbes; ++p) {
-          const int off = (int)s * sw;
-          const uint64_t kv = s_tab[off];
-          if (kv == key[k]) {
-            loff[k] = off + 1;
-            break;
-          }
-          if (kv == kEmpty) {
-            const uint64_t prev = atomicCAS((unsigned long long*)&s_tab[off], (unsigned long long)kEmpty,
-                                            (unsigned long long)key[k]);
-            if (prev == kEmpty || prev == key[k]) {
-              loff[k] = off + 1;
-              break;
-            }
-          }
-          s = (s + 1) & (uint32_t)(lcap - 1);
-        }
-      }
+      if (!special[k]) loff[k] = lds_find_insert(s_tab, lcap, sw, key[k]);
       if (loff[k] < 0) {
         gsp[k] = global_acc(a, key[k], special[k]);
         if (!gsp[k]) keep &= ~(1u << k);
@@ -398,7 +140,7 @@ template <int BLOCK, int ITEMS>
 __global__ __launch_bounds__(BLOCK) void k_groupjoin(const GbArgs a) {
   constexpr int TILE = BLOCK * ITEMS;
   const int64_t r0 = (int64_t)blockIdx.x * TILE + (int64_t)threadIdx.x * ITEMS;
-  uint32_t keep = eval_preds<ITEMS>(a, r0);
+  uint32_t keep = eval_preds<ITEMS>(a, r0, a.n);
   if (!keep) return;
   int64_t js[ITEMS];
   join_lookup<ITEMS>(a.join, r0, a.n, keep, js);
@@ -551,110 +293,6 @@ constexpr int kCBlock = 256, kCItems = 8;
 // ---------------------------------------------------------------------------
 // Host-side plans
 // ---------------------------------------------------------------------------
-int make_preds(gq_ctx* ctx, GbArgs& a, const gq_batch* in, const gq_pred* preds, int npreds) {
-  if (npreds < 0 || npreds > GQ_MAX_PREDS || (npreds > 0 && !preds))
-    return set_error(ctx, GQ_ERR_INVALID, "group-by: bad predicate list");
-  a.npreds = npreds;
-  for (int p = 0; p < npreds; ++p) {
-    if (preds[p].col < 0 || preds[p].col >= in->ncols)
-      return set_error(ctx, GQ_ERR_INVALID, "group-by: predicate column out of range");
-    if (preds[p].op != GQ_RANGE && preds[p].op != GQ_NE)
-      return set_error(ctx, GQ_ERR_INVALID, "group-by: unknown predicate op");
-    a.preds[p] = DPred{preds[p].col, preds[p].op, preds[p].lo, preds[p].hi};
-    a.pcols[p] = make_dcol(in->cols[preds[p].col]);
-    a.pcols[p].nt = 1;
-  }
-  return GQ_OK;
-}
-
-int make_key_plan(gq_ctx* ctx, KeyPlan& kp, const gq_batch* in, const int32_t* keys, int nk) {
-  if (nk < 0 || nk > GQ_MAX_KEYS || (nk > 0 && !keys))
-    return set_error(ctx, GQ_ERR_INVALID, "group-by: bad key list");
-  kp.nk = nk;
-  for (int j = 0; j < nk; ++j) {
-    if (keys[j] < 0 || keys[j] >= in->ncols) return set_error(ctx, GQ_ERR_INVALID, "group-by: key column out of range");
-    kp.cols[j] = make_dcol(in->cols[keys[j]]);
-    kp.cols[j].nt = 1;
-  }
-  if (nk == 1 && in->cols[keys[0]].type == GQ_I64) {
-    kp.mode = KEY_RAW64;
-    kp.bits[0] = 64;
-    kp.shift[0] = 0;
-    kp.nullable[0] = in->cols[keys[0]].validity != nullptr;
-    return GQ_OK;
-  }
-  kp.mode = KEY_PACKED;
-  int shift = 0;
-  for (int j = nk - 1; j >= 0; --j) {
-    const gq_column& c = in->cols[keys[j]];
-    kp.bits[j] = 8 * type_width(c.type);
-    kp.nullable[j] = c.validity != nullptr;
-    kp.shift[j] = shift;
-    shift += kp.bits[j] + kp.nullable[j];
-  }
-  if (shift > 63)
-    return set_error(ctx, GQ_ERR_UNSUPPORTED,
-                     "group-by: key columns wider than 63 bits together (use one int64 key column)");
-  return GQ_OK;
-}
-
-int make_agg_plan(gq_ctx* ctx, AggPlan& ap, const gq_batch* in, const gq_agg* aggs, int na) {
-  if (na < 0 || na > GQ_MAX_AGGS || (na > 0 && !aggs))
-    return set_error(ctx, GQ_ERR_INVALID, "group-by: bad aggregate list");
-  ap.naggs = na;
-  ap.nvals = 0;
-  int cols[kMaxVals];
-  int uses[kMaxVals] = {0};
-  int word = 1;
-  ap.wop[0] = WOP_ADD;
-  for (int i = 0; i < na; ++i) {
-    const gq_agg& g = aggs[i];
-    DAgg& d = ap.aggs[i];
-    d.op = g.op;
-    d.nf = 0;
-    d.cword = -1;
-    if (g.op < GQ_SUM || g.op > GQ_MAX) return set_error(ctx, GQ_ERR_INVALID, "group-by: unknown aggregate");
-    if (g.op == GQ_COUNT_STAR) {
-      d.word = 0;
-      continue;
-    }
-    if (g.nfactors < 0 || g.nfactors > 3) return set_error(ctx, GQ_ERR_INVALID, "group-by: 0..3 factors");
-    bool nullable = false;
-    d.nf = g.nfactors;
-    for (int f = 0; f < g.nfactors; ++f) {
-      const gq_factor& fa = g.f[f];
-      if (fa.kind < GQ_F_COL || fa.kind > GQ_F_CONST) return set_error(ctx, GQ_ERR_INVALID, "group-by: bad factor");
-      d.f[f].kind = fa.kind;
-      d.f[f].k = fa.k;
-      d.f[f].v = 0;
-      if (fa.kind == GQ_F_CONST) continue;
-      if (fa.col < 0 || fa.col >= in->ncols) return set_error(ctx, GQ_ERR_INVALID, "group-by: factor column out of range");
-      int vi = -1;
-      for (int q = 0; q < ap.nvals; ++q)
-        if (cols[q] == fa.col) vi = q;
-      if (vi < 0) {
-        if (ap.nvals == kMaxVals) return set_error(ctx, GQ_ERR_UNSUPPORTED, "group-by: more than 8 value columns");
-        vi = ap.nvals++;
-        cols[vi] = fa.col;
-        ap.vals[vi] = make_dcol(in->cols[fa.col]);
-      }
-      uses[vi] += 1;
-      d.f[f].v = vi;
-      if (in->cols[fa.col].validity) nullable = true;
-    }
-    d.word = word++;
-    ap.wop[d.word] = g.op == GQ_MIN ? WOP_MIN : g.op == GQ_MAX ? WOP_MAX : WOP_ADD;
-    if (nullable && g.op != GQ_COUNT) {
-      d.cword = word++;
-      ap.wop[d.cword] = WOP_ADD;
-    }
-  }
-  // A value column read by one factor only is streamed with non-temporal loads.
-  for (int q = 0; q < ap.nvals; ++q) ap.vals[q].nt = uses[q] == 1 ? 1 : 0;
-  ap.nacc = word;
-  return GQ_OK;
-}
-
 int check_outputs(gq_ctx* ctx, int nk_out, int na, gq_batch* out, CompactArgs& ca, const int* key_types) {
   if (!out || out->ncols < nk_out + na || (nk_out + na > 0 && !out->cols))
     return set_error(ctx, GQ_ERR_INVALID, "group-by: output needs key and aggregate columns");
@@ -849,6 +487,111 @@ int run_groupby(gq_ctx* ctx, const gq_batch* in, const int32_t* keys, int nkeys,
 }
 
 }  // namespace
+
+int make_preds(gq_ctx* ctx, GbArgs& a, const gq_batch* in, const gq_pred* preds, int npreds) {
+  if (npreds < 0 || npreds > GQ_MAX_PREDS || (npreds > 0 && !preds))
+    return set_error(ctx, GQ_ERR_INVALID, "group-by: bad predicate list");
+  a.npreds = npreds;
+  for (int p = 0; p < npreds; ++p) {
+    if (preds[p].col < 0 || preds[p].col >= in->ncols)
+      return set_error(ctx, GQ_ERR_INVALID, "group-by: predicate column out of range");
+    if (preds[p].op != GQ_RANGE && preds[p].op != GQ_NE)
+      return set_error(ctx, GQ_ERR_INVALID, "group-by: unknown predicate op");
+    a.preds[p] = DPred{preds[p].col, preds[p].op, preds[p].lo, preds[p].hi};
+    a.pcols[p] = make_dcol(in->cols[preds[p].col]);
+    a.pcols[p].nt = 1;
+  }
+  return GQ_OK;
+}
+
+int make_key_plan(gq_ctx* ctx, KeyPlan& kp, const gq_batch* in, const int32_t* keys, int nk) {
+  if (nk < 0 || nk > GQ_MAX_KEYS || (nk > 0 && !keys))
+    return set_error(ctx, GQ_ERR_INVALID, "group-by: bad key list");
+  kp.nk = nk;
+  for (int j = 0; j < nk; ++j) {
+    if (keys[j] < 0 || keys[j] >= in->ncols) return set_error(ctx, GQ_ERR_INVALID, "group-by: key column out of range");
+    kp.cols[j] = make_dcol(in->cols[keys[j]]);
+    kp.cols[j].nt = 1;
+  }
+  if (nk == 1 && in->cols[keys[0]].type == GQ_I64) {
+    kp.mode = KEY_RAW64;
+    kp.bits[0] = 64;
+    kp.shift[0] = 0;
+    kp.nullable[0] = in->cols[keys[0]].validity != nullptr;
+    return GQ_OK;
+  }
+  kp.mode = KEY_PACKED;
+  int shift = 0;
+  for (int j = nk - 1; j >= 0; --j) {
+    const gq_column& c = in->cols[keys[j]];
+    kp.bits[j] = 8 * type_width(c.type);
+    kp.nullable[j] = c.validity != nullptr;
+    kp.shift[j] = shift;
+    shift += kp.bits[j] + kp.nullable[j];
+  }
+  if (shift > 63)
+    return set_error(ctx, GQ_ERR_UNSUPPORTED,
+                     "group-by: key columns wider than 63 bits together (use one int64 key column)");
+  return GQ_OK;
+}
+
+int make_agg_plan(gq_ctx* ctx, AggPlan& ap, const gq_batch* in, const gq_agg* aggs, int na) {
+  if (na < 0 || na > GQ_MAX_AGGS || (na > 0 && !aggs))
+    return set_error(ctx, GQ_ERR_INVALID, "group-by: bad aggregate list");
+  ap.naggs = na;
+  ap.nvals = 0;
+  int cols[kMaxVals];
+  int uses[kMaxVals] = {0};
+  int word = 1;
+  ap.wop[0] = WOP_ADD;
+  for (int i = 0; i < na; ++i) {
+    const gq_agg& g = aggs[i];
+    DAgg& d = ap.aggs[i];
+    d.op = g.op;
+    d.nf = 0;
+    d.cword = -1;
+    if (g.op < GQ_SUM || g.op > GQ_MAX) return set_error(ctx, GQ_ERR_INVALID, "group-by: unknown aggregate");
+    if (g.op == GQ_COUNT_STAR) {
+      d.word = 0;
+      continue;
+    }
+    if (g.nfactors < 0 || g.nfactors > 3) return set_error(ctx, GQ_ERR_INVALID, "group-by: 0..3 factors");
+    bool nullable = false;
+    d.nf = g.nfactors;
+    for (int f = 0; f < g.nfactors; ++f) {
+      const gq_factor& fa = g.f[f];
+      if (fa.kind < GQ_F_COL || fa.kind > GQ_F_CONST) return set_error(ctx, GQ_ERR_INVALID, "group-by: bad factor");
+      d.f[f].kind = fa.kind;
+      d.f[f].k = fa.k;
+      d.f[f].v = 0;
+      if (fa.kind == GQ_F_CONST) continue;
+      if (fa.col < 0 || fa.col >= in->ncols) return set_error(ctx, GQ_ERR_INVALID, "group-by: factor column out of range");
+      int vi = -1;
+      for (int q = 0; q < ap.nvals; ++q)
+        if (cols[q] == fa.col) vi = q;
+      if (vi < 0) {
+        if (ap.nvals == kMaxVals) return set_error(ctx, GQ_ERR_UNSUPPORTED, "group-by: more than 8 value columns");
+        vi = ap.nvals++;
+        cols[vi] = fa.col;
+        ap.vals[vi] = make_dcol(in->cols[fa.col]);
+      }
+      uses[vi] += 1;
+      d.f[f].v = vi;
+      if (in->cols[fa.col].validity) nullable = true;
+    }
+    d.word = word++;
+    ap.wop[d.word] = g.op == GQ_MIN ? WOP_MIN : g.op == GQ_MAX ? WOP_MAX : WOP_ADD;
+    if (nullable && g.op != GQ_COUNT) {
+      d.cword = word++;
+      ap.wop[d.cword] = WOP_ADD;
+    }
+  }
+  // A value column read by one factor only is streamed with non-temporal loads.
+  for (int q = 0; q < ap.nvals; ++q) ap.vals[q].nt = uses[q] == 1 ? 1 : 0;
+  ap.nacc = word;
+  return GQ_OK;
+}
+
 }  // namespace gq
 
 using namespace gq;

@@ -302,6 +302,28 @@ def batch_c3(n: int = 60_000_000, nkeys: int = 15_000_000, start: int = 0, seed:
     return t
 
 
+# Serving tables: the join fact with the 1M-row fact's columns, 10x the keys --
+
+C5_FACT_ROWS, C5_DIM_ROWS = 600_000_000, 150_000_000
+
+
+def fact_c5(n: int = C5_FACT_ROWS, nkeys: int = C5_DIM_ROWS, start: int = 0, seed: int = 5) -> Table:
+    """Resident fact: fkey U[1,nkeys], qty, price, disc (int64), date int32, flag, status int8."""
+    spec = [("fkey", 0, 1, nkeys, np.int64, 0), ("qty", 1, 1, 50, np.int64, 0),
+            ("price", 2, PRICE_LO, PRICE_HI, np.int64, 2), ("disc", 3, 0, 10, np.int64, 2),
+            ("date", 4, 0, DATE_DAYS - 1, np.int32, 0), ("flag", 5, 0, 2, np.int8, 0),
+            ("status", 6, 0, 1, np.int8, 0)]
+    t = Table()
+    for name, c, lo, hi, dt, sc in spec:
+        t.cols.append(Column(name, uniform(seed, c, start, n, lo, hi, dt), None, sc))
+    return t
+
+
+def dim_c5(n: int = C5_DIM_ROWS, start: int = 0, seed: int = 5) -> Table:
+    """Resident dimension: the join dimension's recipe at the serving scale."""
+    return dim_c2(n, start=start, seed=seed, ckeys=max(1, n // 10))
+
+
 # Config-4 fragments -------------------------------------------------------
 
 FRAG_ROWS_LO, FRAG_ROWS_HI = 1_000, 4_000_000

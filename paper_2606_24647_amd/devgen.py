@@ -99,6 +99,22 @@ def batch_c3(n=60_000_000, nkeys=15_000_000, start=0, seed=3) -> DevTable:
     ])
 
 
+def fact_c5(n=dg.C5_FACT_ROWS, nkeys=dg.C5_DIM_ROWS, start=0, seed=5) -> DevTable:
+    return _table([
+        (uniform(seed, 0, start, n, 1, nkeys), 0),
+        (uniform(seed, 1, start, n, 1, 50), 0),
+        (uniform(seed, 2, start, n, dg.PRICE_LO, dg.PRICE_HI), 2),
+        (uniform(seed, 3, start, n, 0, 10), 2),
+        (uniform(seed, 4, start, n, 0, dg.DATE_DAYS - 1, torch.int32), 0),
+        (uniform(seed, 5, start, n, 0, 2, torch.int8), 0),
+        (uniform(seed, 6, start, n, 0, 1, torch.int8), 0),
+    ])
+
+
+def dim_c5(n=dg.C5_DIM_ROWS, start=0, seed=5) -> DevTable:
+    return dim_c2(n, start=start, seed=seed, ckeys=max(1, n // 10))
+
+
 def fragment_c4(f, rows, card, seed=4) -> DevTable:
     s = dg.fragment_seed(f, seed)
     return _table([

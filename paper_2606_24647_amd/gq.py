@@ -90,6 +90,18 @@ class GqPlan(C.Structure):
                 ("opts", GqGroupbyOpts)]
 
 
+class GqFragment(C.Structure):
+    _fields_ = [("inp", GqBatch), ("preds", C.POINTER(GqPred)), ("npreds", C.c_int32),
+                ("reserved", C.c_int32), ("expected_groups", C.c_int64), ("out", GqBatch),
+                ("d_groups", C.c_void_p)]
+
+
+class GqBatchSpec(C.Structure):
+    _fields_ = [("keys", C.POINTER(C.c_int32)), ("nkeys", C.c_int32), ("naggs", C.c_int32),
+                ("aggs", C.POINTER(GqAgg)), ("load_factor", C.c_float), ("lds_max_groups", C.c_int32),
+                ("tile_rows", C.c_int32), ("blocks_per_cu", C.c_int32)]
+
+
 class GqAllocator(C.Structure):
     _fields_ = [("alloc", C.c_void_p), ("free", C.c_void_p), ("user", C.c_void_p)]
 
@@ -121,6 +133,11 @@ _SIGS = {
                                  C.POINTER(GqGroupbyOpts), C.POINTER(GqBatch), _P, _P]),
     "gq_pipeline": (C.c_int, [_P, C.POINTER(GqPlan), C.POINTER(GqBatch), C.POINTER(GqBatch),
                               _P, _P]),
+    "gq_batch_plan_create": (C.c_int, [_P, C.POINTER(GqFragment), C.c_int, C.POINTER(GqBatchSpec), _P,
+                                       C.POINTER(_P)]),
+    "gq_batch_plan_launch": (C.c_int, [_P, _P]),
+    "gq_batch_plan_info": (C.c_int, [_P, _P, _P, _P, _P]),
+    "gq_batch_plan_free": (C.c_int, [_P]),
 }
 EXPORTS = tuple(_SIGS)
 
@@ -434,6 +451,71 @@ class Context:
         self.check(_lib.gq_pipeline(self.h, C.byref(plan), ib.ref, ob.ref, C.c_void_p(cnt.data_ptr()),
                                     _stream(stream)))
         return out, cnt
+
+
+class BatchPlan:
+    """Many filter + group-by fragments in one graph-captured persistent launch.
+
+    fragments: list of (DevTable, preds, expected_groups); every fragment uses
+    the same key columns and aggregates.  Outputs are allocated here, one
+    DevTable per fragment with capacity min(rows, expected_groups).
+    """
+
+    def __init__(self, ctx: "Context", fragments, keys, aggs, load_factor=0.0, lds_max_groups=0,
+                 tile_rows=0, blocks_per_cu=0, stream=None):
+        self.ctx = ctx
+        self.h = None
+        nf = len(fragments)
+        self._keep = []
+        self.outs = []
+        self.d_groups = torch.zeros(nf, dtype=torch.int64, device="cuda")
+        farr = (GqFragment * nf)()
+        for f, (tab, preds, expected) in enumerate(fragments):
+            cap = tab.nrows if not expected else min(tab.nrows, int(expected))
+            cap = max(cap, 1)
+            out = ctx._groupby_out(tab, keys, aggs, cap)
+            ib, ob = _BatchArg(tab), _BatchArg(out, cap)
+            p, np_ = _preds(preds)
+            self._keep += [ib, ob, p, out, tab]
+            self.outs.append(out)
+            farr[f].inp = ib.batch
+            farr[f].preds = C.cast(p, C.POINTER(GqPred))
+            farr[f].npreds = np_
+            farr[f].expected_groups = int(expected or 0)
+            farr[f].out = ob.batch
+            farr[f].d_groups = self.d_groups.data_ptr() + 8 * f
+        k, nk = _ints(keys)
+        a, na = _aggs(aggs)
+        self._keep += [k, a, farr]
+        spec = GqBatchSpec(C.cast(k, C.POINTER(C.c_int32)), nk, na, C.cast(a, C.POINTER(GqAgg)),
+                           load_factor, lds_max_groups, tile_rows, blocks_per_cu)
+        h = C.c_void_p()
+        ctx.check(_lib.gq_batch_plan_create(ctx.h, farr, nf, C.byref(spec), _stream(stream), C.byref(h)))
+        self.h = h
+
+    def launch(self, stream=None):
+        self.ctx.check(_lib.gq_batch_plan_launch(self.h, _stream(stream)))
+
+    def info(self) -> dict:
+        v = [C.c_int64() for _ in range(4)]
+        self.ctx.check(_lib.gq_batch_plan_info(self.h, *[C.byref(x) for x in v]))
+        return dict(zip(["total_rows", "tiles", "table_slots", "bytes"], [x.value for x in v]))
+
+    def result(self, f: int):
+        """Output columns of fragment f as [(values, valid)] and its group count (synchronises)."""
+        n = int(self.d_groups[f].item())
+        return read_table(self.outs[f], n), n
+
+    def free(self):
+        if self.h:
+            _lib.gq_batch_plan_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
 
 
 class JoinTable:

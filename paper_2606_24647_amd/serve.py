@@ -1,0 +1,274 @@
+"""Serving loop: continuous batching of analytical queries over device-resident tables.
+
+The paper keeps the working set in GPU memory for the whole query (Section 2,
+hypothesis 2), lets pipelines run concurrently on their own streams with
+synchronisation only at pipeline boundaries (Section 3), and blocks senders
+when queues exceed thresholds because the working set must fit in GPU memory
+(Section 3.3).  This module applies the same ideas to a request loop:
+
+* tables stay resident in HBM; queries only read them;
+* a single host thread drives everything asynchronously: it admits arriving
+  queries as soon as a slot (a stream with its own library context) and the
+  HBM budget allow, enqueues their kernels, and polls completion events;
+* each query is a small state machine (for example filter, then partition the
+  filtered rows once their count is known), advanced when its stage's event
+  completes, so no query ever blocks the loop;
+* queries that arrive while others run are admitted between their stages:
+  their work overlaps on the device;
+* over-budget queries wait in FIFO order; nothing is spilled.
+
+"plain" mode runs the same queries one at a time, in arrival order, on one
+stream: the baseline that serving must beat on throughput at a given p99.
+
+The scheduler is written against a small executor interface so that it can be
+tested on the CPU with a simulated executor (tests/test_serve.py).
+"""
+from __future__ import annotations
+
+import heapq
+import math
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# Resident fact columns: fkey, qty, price, disc, date, flag, status.
+F_FKEY, F_QTY, F_PRICE, F_DISC, F_DATE, F_FLAG, F_STATUS = range(7)
+# Resident dimension columns: pkey, date, ckey.
+D_PKEY, D_DATE, D_CKEY = range(3)
+
+REV = [("col", F_PRICE), ("k-col", 100, F_DISC)]
+AGG_AGGS = [("sum", [("col", F_QTY)]), ("sum", [("col", F_PRICE)]), ("sum", [("col", F_DISC)]), ("sum", REV),
+            ("count*",)]
+JOIN_AGGS = [("sum", REV), ("count*",)]
+PART_COLS = [F_FKEY, F_PRICE, F_DATE, F_FLAG]   # 8 + 8 + 4 + 1 = 21 B per row
+
+
+@dataclass
+class Query:
+    qid: int
+    kind: str            # "agg", "join" or "part"
+    arrival: float       # seconds after the start of the run
+    params: dict = field(default_factory=dict)
+
+
+def make_workload(n: int, qps: float, seed: int = 5, kinds=("agg", "join", "part")) -> list:
+    """Open-loop Poisson arrivals at `qps`, kinds uniform, random filter bounds."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / qps, n)
+    t = np.cumsum(gaps) - gaps[0]
+    out = []
+    for i in range(n):
+        kind = kinds[int(rng.integers(0, len(kinds)))]
+        if kind == "agg":
+            p = {"b": int(rng.integers(0, 2556))}
+        elif kind == "join":
+            p = {"b_dim": int(rng.integers(0, 2406)), "b_fact": int(rng.integers(0, 2556))}
+        else:
+            p = {"b": int(rng.integers(0, 2556)), "P": int(rng.choice([64, 256]))}
+        out.append(Query(i, kind, float(t[i]), p))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Scheduler
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Record:
+    qid: int
+    kind: str
+    arrival: float
+    admitted: float
+    done: float
+    rows: int
+    result: object = None
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+class Scheduler:
+    """Admission by slots and HBM budget, FIFO queue, non-blocking polling.
+
+    executor: object with nslots, footprint(q) -> bytes, start(q, slot) -> job,
+    step(job) -> bool (advance the job's state machine if its current stage has
+    finished; True once the query is complete), result(job), rows(q).
+    """
+
+    def __init__(self, executor, budget_bytes: int, nslots: int | None = None, clock=time.perf_counter,
+                 idle_sleep: float = 20e-6):
+        self.ex = executor
+        self.budget = budget_bytes
+        self.nslots = nslots if nslots is not None else executor.nslots
+        self.clock = clock
+        self.idle_sleep = idle_sleep
+
+    def run(self, queries: list, keep_results: bool = False) -> list:
+        pending = sorted(queries, key=lambda q: q.arrival)
+        queue: list = []
+        running: dict = {}      # slot -> (query, job, admitted, footprint)
+        free = list(range(self.nslots))
+        used = 0
+        records = []
+        i = 0
+        t0 = self.clock()
+        while i < len(pending) or queue or running:
+            now = self.clock() - t0
+            while i < len(pending) and pending[i].arrival <= now:
+                queue.append(pending[i])
+                i += 1
+            # Admit in FIFO order while a slot and the budget allow.
+            while queue and free:
+                q = queue[0]
+                fp = self.ex.footprint(q)
+                if fp > self.budget:
+                    raise ValueError(f"query {q.qid} needs {fp} bytes, more than the whole budget")
+                if used + fp > self.budget:
+                    break
+                queue.pop(0)
+                slot = free.pop(0)
+                used += fp
+                running[slot] = (q, self.ex.start(q, slot), self.clock() - t0, fp)
+            # Advance running queries.
+            progressed = False
+            for slot in list(running):
+                q, job, adm, fp = running[slot]
+                if self.ex.step(job):
+                    done = self.clock() - t0
+                    res = self.ex.result(job) if keep_results else None
+                    records.append(Record(q.qid, q.kind, q.arrival, adm, done, self.ex.rows(q), res))
+                    del running[slot]
+                    free.append(slot)
+                    free.sort()
+                    used -= fp
+                    progressed = True
+            if not progressed and self.idle_sleep:
+                if i < len(pending) and not queue and not running:
+                    wait = pending[i].arrival - (self.clock() - t0)
+                    if wait > 0:
+                        time.sleep(min(wait, 1e-3))
+                else:
+                    time.sleep(self.idle_sleep)
+        return records
+
+
+def summarize(records: list, wall: float | None = None) -> dict:
+    if not records:
+        return {"queries": 0}
+    lat = np.array([r.latency for r in records]) * 1e3
+    first = min(r.arrival for r in records)
+    last = max(r.done for r in records)
+    span = wall if wall is not None else (last - first)
+    rows = sum(r.rows for r in records)
+    return {"queries": len(records), "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "mean_ms": float(lat.mean()), "rows_per_s": rows / span if span > 0 else float("nan"),
+            "wall_s": span}
+
+
+# ---------------------------------------------------------------------------
+# Device executor (the real one)
+# ---------------------------------------------------------------------------
+
+class DeviceExecutor:
+    """Runs queries on a pool of streams, one library context per stream."""
+
+    def __init__(self, gq, torch, fact, dim, nslots: int = 4):
+        self.gq, self.torch = gq, torch
+        self.fact, self.dim = fact, dim
+        self.nslots = nslots
+        self.streams = [torch.cuda.Stream() for _ in range(nslots)]
+        self.ctxs = [gq.Context() for _ in range(nslots)]
+        self.nf, self.nd = fact.nrows, dim.nrows
+
+    # Upper bounds of the device memory a query allocates (tables, outputs, workspaces).
+    def footprint(self, q: Query) -> int:
+        if q.kind == "agg":
+            return 64 << 20
+        if q.kind == "join":
+            cap = 2 * self.nd + 1
+            return cap * (8 + 8 + 16) + self.nd * 12 + self.nd * 24 + (64 << 20)
+        return 2 * self.nf * 21 + (256 << 20)
+
+    def rows(self, q: Query) -> int:
+        return self.nf + (self.nd if q.kind == "join" else 0)
+
+    def _event(self, s):
+        e = self.torch.cuda.Event()
+        e.record(s)
+        return e
+
+    def start(self, q: Query, slot: int):
+        s, ctx = self.streams[slot], self.ctxs[slot]
+        job = {"q": q, "slot": slot, "stage": 0, "keep": []}
+        with self.torch.cuda.stream(s):
+            if q.kind == "agg":
+                out, cnt = ctx.groupby_agg(self.fact, [F_FLAG, F_STATUS], [("range", F_DATE, 0, q.params["b"])],
+                                           AGG_AGGS, capacity=16, strategy="lds", expected_groups=6, stream=s)
+                job.update(out=out, cnt=cnt, stage=9)
+            elif q.kind == "join":
+                jt = ctx.join_build(self.dim, [D_PKEY], [("range", D_DATE, 0, q.params["b_dim"])], acc_slots=2,
+                                    stream=s)
+                out, cnt = ctx.pipeline(self.fact, [("range", F_DATE, q.params["b_fact"], 2555)], [F_FKEY],
+                                        JOIN_AGGS, join=jt, probe_key=F_FKEY, capacity=self.nd, stream=s)
+                jt.free(stream=s)
+                job.update(out=out, cnt=cnt, stage=9)
+            else:
+                fout, fcnt = ctx.filter(self.fact, [("range", F_DATE, 0, q.params["b"])], PART_COLS, stream=s)
+                job.update(fout=fout, fcnt=fcnt, stage=1)
+            job["ev"] = self._event(s)
+        return job
+
+    def step(self, job) -> bool:
+        if not job["ev"].query():
+            return False
+        if job["stage"] == 9:
+            return True
+        # Partition query: the filter finished, so its row count can be read
+        # without waiting; partition the filtered rows.
+        s, ctx = self.streams[job["slot"]], self.ctxs[job["slot"]]
+        n = int(job["fcnt"].item())
+        fout = job["fout"]
+        for c in fout.cols:
+            c.length = n
+        with self.torch.cuda.stream(s):
+            out, offs = ctx.hash_partition(fout, [0], job["q"].params["P"], stream=s)
+            job.update(out=out, offs=offs, stage=9, n=n)
+            job["ev"] = self._event(s)
+        return False
+
+    def result(self, job):
+        """Host copy of the query's result, for checking (small runs only)."""
+        gq = self.gq
+        q = job["q"]
+        ctx = self.ctxs[job["slot"]]
+        ctx.raise_status(stream=self.streams[job["slot"]])
+        if q.kind in ("agg", "join"):
+            n = int(job["cnt"].item())
+            return ("groups", gq.read_table(job["out"], n))
+        n = job["n"]
+        return ("partition", job["offs"].cpu().numpy(), gq.read_table(job["out"], n))
+
+
+def canonical(result):
+    """Order-independent form of a group result (partition results are already canonical)."""
+    if result[0] != "groups":
+        return result
+    cols = result[1]
+    if not cols or len(cols[0][0]) == 0:
+        return ("groups", [])
+    keys = np.stack([c[0].astype(np.int64) for c in cols], axis=1)
+    order = np.lexsort(keys.T[::-1])
+    return ("groups", keys[order])
+
+
+def same_result(a, b) -> bool:
+    a, b = canonical(a), canonical(b)
+    if a[0] != b[0]:
+        return False
+    if a[0] == "groups":
+        return np.array_equal(a[1], b[1]) if len(a[1]) or len(b[1]) else True
+    if not np.array_equal(a[1], b[1]):
+        return False
+    return all(np.array_equal(x[0], y[0]) for x, y in zip(a[2], b[2]))

@@ -37,3 +37,8 @@ def test_fragment(devgen):
     for f in range(3):
         rows, card = int(spec.rows[f]), int(spec.card[f])
         same(devgen.fragment_c4(f, rows, card), dg.fragment_c4(f, rows, card))
+
+
+def test_serving_tables(devgen):
+    same(devgen.fact_c5(50_001, nkeys=10_000, start=77), dg.fact_c5(50_001, nkeys=10_000, start=77))
+    same(devgen.dim_c5(30_000), dg.dim_c5(30_000))
