@@ -156,23 +156,30 @@ def run_operators(torch, gq, devgen, ctx, c2, reps=5):
     res = {}
     scratch = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
 
+    kern_last = {}
+
     def timed(fn, reps=reps, flush=True):
         ts = []
         for i in range(reps + 1):
             if flush:
                 flush_mall(torch, scratch)
+            ctx.set_timing(i > 0)
             with Timer(torch) as tm:
                 out = fn()
             t = tm.ms()
             if i > 0:
                 ts.append(t)
+        ctx.set_timing(False)
+        rep = ctx.timing_report()
+        kern_last.clear()
+        kern_last.update({k: round(v[0] / reps, 4) for k, v in rep.items()})
         ctx.raise_status()
         return median(ts), out
 
     def entry(rows, nbytes, ms, **extra):
         d = {"rows": rows, "ms": round(ms, 4), "rows_per_s": rows / (ms * 1e-3),
              "alg_bytes": nbytes, "GBps": nbytes / (ms * 1e-3) / 1e9,
-             "frac_hbm_peak": nbytes / (ms * 1e-3) / 1e9 / PEAK_GBS}
+             "frac_hbm_peak": nbytes / (ms * 1e-3) / 1e9 / PEAK_GBS, "kernels_ms": dict(kern_last)}
         d.update(extra)
         return d
 
@@ -316,7 +323,7 @@ def run_serving(torch, gq, devgen, nq=150, qps_list=(50, 100, 200), budget_gb=12
     budget = int(budget_gb) << 30
     res = {"resident_gb": round((dg.C5_FACT_ROWS * 38 + dg.C5_DIM_ROWS * 20) / 1e9, 2), "queries_per_run": nq,
            "slots": slots, "budget_gb": budget_gb, "runs": []}
-    plain_ex = serve.DeviceExecutor(gq, torch, fact, dim, nslots=1)
+    plain_ex = serve.DeviceExecutor(gq, torch, fact, dim, nslots=1, share=False)
     served_ex = serve.DeviceExecutor(gq, torch, fact, dim, nslots=slots)
     # warm up every query kind on both executors
     warm = [serve.Query(i, k, 0.0, p) for i, (k, p) in enumerate(
@@ -371,7 +378,15 @@ def main():
     ap.add_argument("--no-operators", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--only", choices=["c2", "operators", "batched", "serving", "copy"],
+                    help="run one section only (profiling runs); 'copy' is a 1 GiB device copy used to "
+                         "calibrate hardware byte counters")
     args = ap.parse_args()
+    if args.only:
+        args.no_operators = args.only != "operators"
+        args.no_batched = args.only != "batched"
+        args.no_serving = args.only != "serving"
+        args.no_cpu_baseline = True
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the build targets a single MI355X); --gpus {args.gpus} "
               "is not supported", file=sys.stderr)
@@ -383,6 +398,17 @@ def main():
     dev = torch.cuda.get_device_properties(0)
     log(f"device: {dev.name} {dev.gcnArchName} CUs={dev.multi_processor_count}")
     ctx = gq.Context()
+    if args.only == "copy":
+        src = torch.ones(1 << 27, dtype=torch.int64, device="cuda")   # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(args.steps):
+            with Timer(torch) as tm:
+                dst.copy_(src)
+            log(f"copy 1 GiB: {tm.ms():.4f} ms")
+        print(json.dumps({"copy_bytes_read": 1 << 30, "copy_bytes_written": 1 << 30, "copies": args.steps}))
+        return
+    if args.only in ("batched", "serving"):
+        args.steps, args.warmup = 1, 0
     c2 = run_c2(torch, gq, devgen, ctx, args.steps, args.warmup, args.load_factor)
     total_bytes, fused_bytes = c2_bytes(c2)
     ms = c2["ms_per_step"]

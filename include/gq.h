@@ -307,6 +307,23 @@ int gq_groupby_agg(gq_ctx* ctx, const gq_batch* in, const int32_t* keys, int nke
                    const gq_groupby_opts* opts, gq_batch* out, int64_t* d_groups,
                    hipStream_t stream);
 
+/* ---- shared scan ------------------------------------------------------------------
+ * Up to GQ_MAX_SHARED filter + group-by queries over the same batch in one
+ * pass: every column is read once and each query aggregates its own kept rows
+ * into its own table.  The queries share key columns, aggregates and predicate
+ * columns and ops; only predicate bounds differ.  (Serving many queries
+ * against resident tables, Section 2 and Section 3.3.)
+ *  preds     nqueries * npreds predicates: query q's conjunction is
+ *            preds[q*npreds .. q*npreds + npreds)
+ *  outs      nqueries output batches, each as for gq_groupby_agg
+ *  d_groups  device int64[nqueries]
+ * Results equal one gq_groupby_agg call per query. */
+#define GQ_MAX_SHARED 8
+
+int gq_groupby_shared(gq_ctx* ctx, const gq_batch* in, const int32_t* keys, int nkeys, const gq_pred* preds,
+                      int npreds, int nqueries, const gq_agg* aggs, int naggs, const gq_groupby_opts* opts,
+                      gq_batch* outs, int64_t* d_groups, hipStream_t stream);
+
 /* ---- fused pipeline -------------------------------------------------------------
  * filter(in) [-> probe `join` on probe_key] -> group-by, in one pass over `in`
  * with nothing materialised between the steps (the fused per-batch operator

@@ -271,5 +271,8 @@ __device__ __forceinline__ int lds_find_insert(uint64_t* s_tab, int lcap, int sw
 int make_preds(gq_ctx* ctx, GbArgs& a, const gq_batch* in, const gq_pred* preds, int npreds);
 int make_key_plan(gq_ctx* ctx, KeyPlan& kp, const gq_batch* in, const int32_t* keys, int nk);
 int make_agg_plan(gq_ctx* ctx, AggPlan& ap, const gq_batch* in, const gq_agg* aggs, int na);
+// Output validation and table compaction (groupby.hip).
+int check_outputs(gq_ctx* ctx, int nk_out, int na, gq_batch* out, CompactArgs& ca, const int* key_types);
+int compact_launch(gq_ctx* ctx, CompactArgs& ca, int64_t* d_groups, hipStream_t stream);
 
 }  // namespace gq

@@ -293,48 +293,6 @@ constexpr int kCBlock = 256, kCItems = 8;
 // ---------------------------------------------------------------------------
 // Host-side plans
 // ---------------------------------------------------------------------------
-int check_outputs(gq_ctx* ctx, int nk_out, int na, gq_batch* out, CompactArgs& ca, const int* key_types) {
-  if (!out || out->ncols < nk_out + na || (nk_out + na > 0 && !out->cols))
-    return set_error(ctx, GQ_ERR_INVALID, "group-by: output needs key and aggregate columns");
-  int64_t cap = INT64_MAX;
-  for (int j = 0; j < nk_out + na; ++j) {
-    const gq_column& oc = out->cols[j];
-    const int want = j < nk_out ? key_types[j] : GQ_I64;
-    if (oc.type != want) return set_error(ctx, GQ_ERR_INVALID, "group-by: output column type mismatch");
-    if (oc.length < 0 || (oc.length > 0 && !oc.data)) return set_error(ctx, GQ_ERR_INVALID, "group-by: bad output column");
-    if (oc.validity && (reinterpret_cast<uintptr_t>(oc.validity) & 3))
-      return set_error(ctx, GQ_ERR_INVALID, "group-by: output bitmap must be 4-byte aligned");
-    if (oc.offset != 0) return set_error(ctx, GQ_ERR_INVALID, "group-by: output offset must be 0");
-    ca.out[j] = OCol{static_cast<uint8_t*>(oc.data), reinterpret_cast<uint32_t*>(oc.validity), oc.type, 0};
-    if (oc.length < cap) cap = oc.length;
-  }
-  ca.out_cap = cap;
-  return GQ_OK;
-}
-
-int compact_launch(gq_ctx* ctx, CompactArgs& ca, int64_t* d_groups, hipStream_t stream) {
-  constexpr int TILE = kCBlock * kCItems;
-  const int64_t nidx = (int64_t)ca.cap_alloc + ca.extra;
-  const int64_t ntiles = (nidx + TILE - 1) / TILE;
-  ca.ntiles = ntiles;
-  ca.d_count = d_groups;
-  ca.dev_status = ctx->d_status;
-  Scratch ws(ctx, stream);
-  if (!ws.get(256 + align_up((size_t)ntiles * 8, 256)))
-    return set_error(ctx, GQ_ERR_NOMEM, "group-by: compaction workspace allocation failed");
-  ca.ticket = ws.as<uint32_t>(0);
-  ca.status = ws.as<uint64_t>(256);
-  int64_t iblocks = (ntiles + 255) / 256;
-  if (iblocks < 1) iblocks = 1;
-  if (iblocks > 4096) iblocks = 4096;
-  GQ_LAUNCH(ctx, "compact_init", k_compact_init, dim3((unsigned)iblocks), dim3(256), 0, stream, ca.ticket, ca.status,
-            ntiles, d_groups);
-  GQ_LAUNCH_CHECK(ctx);
-  GQ_LAUNCH(ctx, "compact", (k_compact<kCBlock, kCItems>), dim3((unsigned)ntiles), dim3(kCBlock), 0, stream, ca);
-  GQ_LAUNCH_CHECK(ctx);
-  return GQ_OK;
-}
-
 template <bool JOIN>
 int launch_aggregate(gq_ctx* ctx, GbArgs& a, int strategy, hipStream_t stream) {
   constexpr int TILE = kGbBlock * kGbItems;
@@ -487,6 +445,48 @@ int run_groupby(gq_ctx* ctx, const gq_batch* in, const int32_t* keys, int nkeys,
 }
 
 }  // namespace
+
+int check_outputs(gq_ctx* ctx, int nk_out, int na, gq_batch* out, CompactArgs& ca, const int* key_types) {
+  if (!out || out->ncols < nk_out + na || (nk_out + na > 0 && !out->cols))
+    return set_error(ctx, GQ_ERR_INVALID, "group-by: output needs key and aggregate columns");
+  int64_t cap = INT64_MAX;
+  for (int j = 0; j < nk_out + na; ++j) {
+    const gq_column& oc = out->cols[j];
+    const int want = j < nk_out ? key_types[j] : GQ_I64;
+    if (oc.type != want) return set_error(ctx, GQ_ERR_INVALID, "group-by: output column type mismatch");
+    if (oc.length < 0 || (oc.length > 0 && !oc.data)) return set_error(ctx, GQ_ERR_INVALID, "group-by: bad output column");
+    if (oc.validity && (reinterpret_cast<uintptr_t>(oc.validity) & 3))
+      return set_error(ctx, GQ_ERR_INVALID, "group-by: output bitmap must be 4-byte aligned");
+    if (oc.offset != 0) return set_error(ctx, GQ_ERR_INVALID, "group-by: output offset must be 0");
+    ca.out[j] = OCol{static_cast<uint8_t*>(oc.data), reinterpret_cast<uint32_t*>(oc.validity), oc.type, 0};
+    if (oc.length < cap) cap = oc.length;
+  }
+  ca.out_cap = cap;
+  return GQ_OK;
+}
+
+int compact_launch(gq_ctx* ctx, CompactArgs& ca, int64_t* d_groups, hipStream_t stream) {
+  constexpr int TILE = kCBlock * kCItems;
+  const int64_t nidx = (int64_t)ca.cap_alloc + ca.extra;
+  const int64_t ntiles = (nidx + TILE - 1) / TILE;
+  ca.ntiles = ntiles;
+  ca.d_count = d_groups;
+  ca.dev_status = ctx->d_status;
+  Scratch ws(ctx, stream);
+  if (!ws.get(256 + align_up((size_t)ntiles * 8, 256)))
+    return set_error(ctx, GQ_ERR_NOMEM, "group-by: compaction workspace allocation failed");
+  ca.ticket = ws.as<uint32_t>(0);
+  ca.status = ws.as<uint64_t>(256);
+  int64_t iblocks = (ntiles + 255) / 256;
+  if (iblocks < 1) iblocks = 1;
+  if (iblocks > 4096) iblocks = 4096;
+  GQ_LAUNCH(ctx, "compact_init", k_compact_init, dim3((unsigned)iblocks), dim3(256), 0, stream, ca.ticket, ca.status,
+            ntiles, d_groups);
+  GQ_LAUNCH_CHECK(ctx);
+  GQ_LAUNCH(ctx, "compact", (k_compact<kCBlock, kCItems>), dim3((unsigned)ntiles), dim3(kCBlock), 0, stream, ca);
+  GQ_LAUNCH_CHECK(ctx);
+  return GQ_OK;
+}
 
 int make_preds(gq_ctx* ctx, GbArgs& a, const gq_batch* in, const gq_pred* preds, int npreds) {
   if (npreds < 0 || npreds > GQ_MAX_PREDS || (npreds > 0 && !preds))

@@ -133,6 +133,9 @@ _SIGS = {
                                  C.POINTER(GqGroupbyOpts), C.POINTER(GqBatch), _P, _P]),
     "gq_pipeline": (C.c_int, [_P, C.POINTER(GqPlan), C.POINTER(GqBatch), C.POINTER(GqBatch),
                               _P, _P]),
+    "gq_groupby_shared": (C.c_int, [_P, C.POINTER(GqBatch), C.POINTER(C.c_int32), C.c_int, C.POINTER(GqPred),
+                                    C.c_int, C.c_int, C.POINTER(GqAgg), C.c_int, C.POINTER(GqGroupbyOpts),
+                                    C.POINTER(GqBatch), _P, _P]),
     "gq_batch_plan_create": (C.c_int, [_P, C.POINTER(GqFragment), C.c_int, C.POINTER(GqBatchSpec), _P,
                                        C.POINTER(_P)]),
     "gq_batch_plan_launch": (C.c_int, [_P, _P]),
@@ -434,6 +437,27 @@ class Context:
         self.check(_lib.gq_groupby_agg(self.h, ib.ref, k, nk, p, np_, a, na, C.byref(opts), ob.ref,
                                        C.c_void_p(cnt.data_ptr()), _stream(stream)))
         return out, cnt
+
+    def groupby_shared(self, table: DevTable, keys, query_preds, aggs, capacity: int | None = None,
+                       load_factor=0.0, expected_groups=0, stream=None):
+        """Several filter + group-by queries in one pass (query_preds: one predicate
+        list per query, same columns and ops).  Returns (list of outputs, device counts)."""
+        nq = len(query_preds)
+        npreds = len(query_preds[0]) if nq else 0
+        cap = max(1, table.nrows) if capacity is None else capacity
+        outs = [self._groupby_out(table, keys, aggs, cap) for _ in range(nq)]
+        cnt = torch.zeros(max(1, nq), dtype=torch.int64, device="cuda")
+        flat = [p for q in query_preds for p in q]
+        p, _ = _preds(flat)
+        k, nk = _ints(keys)
+        a, na = _aggs(aggs)
+        obs = [_BatchArg(o, cap) for o in outs]
+        oarr = (GqBatch * max(1, nq))(*[ob.batch for ob in obs])
+        opts = self._opts(load_factor, "auto", False, 0, expected_groups)
+        ib = _BatchArg(table)
+        self.check(_lib.gq_groupby_shared(self.h, ib.ref, k, nk, p, npreds, nq, a, na, C.byref(opts), oarr,
+                                          C.c_void_p(cnt.data_ptr()), _stream(stream)))
+        return outs, cnt
 
     def pipeline(self, table: DevTable, preds, group_keys, aggs, join: "JoinTable | None" = None,
                  probe_key: int = 0, capacity: int | None = None, load_factor=0.0,

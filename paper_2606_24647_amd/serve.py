@@ -25,8 +25,6 @@ tested on the CPU with a simulated executor (tests/test_serve.py).
 """
 from __future__ import annotations
 
-import heapq
-import math
 import time
 from dataclasses import dataclass, field
 
@@ -119,7 +117,9 @@ class Scheduler:
             while i < len(pending) and pending[i].arrival <= now:
                 queue.append(pending[i])
                 i += 1
-            # Admit in FIFO order while a slot and the budget allow.
+            # Admit in FIFO order while a slot and the budget allow.  A query that
+            # can share its scan takes queued queries of the same kind along
+            # (shared scan), up to the executor's limit.
             while queue and free:
                 q = queue[0]
                 fp = self.ex.footprint(q)
@@ -127,18 +127,32 @@ class Scheduler:
                     raise ValueError(f"query {q.qid} needs {fp} bytes, more than the whole budget")
                 if used + fp > self.budget:
                     break
-                queue.pop(0)
+                group = [q]
+                key = self.ex.share_key(q) if hasattr(self.ex, "share_key") else None
+                if key is not None:
+                    for other in queue[1:]:
+                        if len(group) >= self.ex.max_share:
+                            break
+                        if self.ex.share_key(other) == key and used + fp + self.ex.footprint(other) <= self.budget:
+                            group.append(other)
+                            fp += self.ex.footprint(other)
+                for g in group:
+                    queue.remove(g)
                 slot = free.pop(0)
                 used += fp
-                running[slot] = (q, self.ex.start(q, slot), self.clock() - t0, fp)
+                job = self.ex.start(q, slot) if len(group) == 1 else self.ex.start_group(group, slot)
+                running[slot] = (group, job, self.clock() - t0, fp)
             # Advance running queries.
             progressed = False
             for slot in list(running):
-                q, job, adm, fp = running[slot]
+                group, job, adm, fp = running[slot]
                 if self.ex.step(job):
                     done = self.clock() - t0
-                    res = self.ex.result(job) if keep_results else None
-                    records.append(Record(q.qid, q.kind, q.arrival, adm, done, self.ex.rows(q), res))
+                    for j, q in enumerate(group):
+                        res = None
+                        if keep_results:
+                            res = self.ex.result(job) if len(group) == 1 else self.ex.result_of(job, j)
+                        records.append(Record(q.qid, q.kind, q.arrival, adm, done, self.ex.rows(q), res))
                     del running[slot]
                     free.append(slot)
                     free.sort()
@@ -174,10 +188,12 @@ def summarize(records: list, wall: float | None = None) -> dict:
 class DeviceExecutor:
     """Runs queries on a pool of streams, one library context per stream."""
 
-    def __init__(self, gq, torch, fact, dim, nslots: int = 4):
+    def __init__(self, gq, torch, fact, dim, nslots: int = 4, share: bool = True):
         self.gq, self.torch = gq, torch
         self.fact, self.dim = fact, dim
         self.nslots = nslots
+        self.share = share
+        self.max_share = 8
         self.streams = [torch.cuda.Stream() for _ in range(nslots)]
         self.ctxs = [gq.Context() for _ in range(nslots)]
         self.nf, self.nd = fact.nrows, dim.nrows
@@ -193,6 +209,26 @@ class DeviceExecutor:
 
     def rows(self, q: Query) -> int:
         return self.nf + (self.nd if q.kind == "join" else 0)
+
+    def share_key(self, q: Query):
+        """Aggregation queries over the fact table can share one scan."""
+        return "agg" if (self.share and q.kind == "agg") else None
+
+    def start_group(self, qs: list, slot: int):
+        s, ctx = self.streams[slot], self.ctxs[slot]
+        job = {"qs": qs, "slot": slot, "stage": 9, "q": qs[0]}
+        with self.torch.cuda.stream(s):
+            outs, cnt = ctx.groupby_shared(self.fact, [F_FLAG, F_STATUS],
+                                           [[("range", F_DATE, 0, q.params["b"])] for q in qs], AGG_AGGS,
+                                           capacity=16, expected_groups=6, stream=s)
+            job.update(outs=outs, cnt=cnt)
+            job["ev"] = self._event(s)
+        return job
+
+    def result_of(self, job, j: int):
+        self.ctxs[job["slot"]].raise_status(stream=self.streams[job["slot"]])
+        n = int(job["cnt"][j].item())
+        return ("groups", self.gq.read_table(job["outs"][j], n))
 
     def _event(self, s):
         e = self.torch.cuda.Event()

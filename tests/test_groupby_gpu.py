@@ -127,3 +127,30 @@ def test_unsupported_wide_keys(gq, ctx):
     with pytest.raises(gq.GqError) as e:
         ctx.groupby_agg(t, [0, 1], [], [("count*",)])
     assert e.value.code == gq.GQ_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("nq", [1, 3, 8])
+def test_shared_scan_equals_separate_queries(gq, ctx, nq):
+    t = dg.fact_c1(300_001, seed=31, null_permille=20)
+    rng = np.random.default_rng(nq)
+    qpreds = [[("range", 3, int(rng.integers(0, 1000)), int(rng.integers(1000, 2600))), ("ne", 0, int(q))]
+              for q in range(nq)]
+    aggs = C1_AGGS + [("min", [("col", 1)]), ("count", [("col", 2)])]
+    outs, cnt = ctx.groupby_shared(gq.to_device(t), [4, 5], qpreds, aggs, capacity=64, expected_groups=16)
+    assert ctx.sync_status() == 0
+    for q in range(nq):
+        n = int(cnt[q].item())
+        cols = gq.read_table(outs[q], n)
+        exp = oracle.groupby(t, [4, 5], qpreds[q], aggs)
+        assert n == exp.nrows
+        gk = [(v.astype(np.int64), ok) for v, ok in cols[:2]]
+        gk, ga = canon_groups(gk, cols[2:])
+        ek, ea = canon_groups(exp.keys, exp.aggs)
+        for (gv, gok), (ev, eok) in zip(gk + ga, ek + ea):
+            assert np.array_equal(gok, eok) and np.array_equal(gv, ev)
+
+
+def test_shared_scan_rejects_mixed_columns(gq, ctx):
+    t = gq.to_device(dg.fact_c1(1000))
+    with pytest.raises(gq.GqError):
+        ctx.groupby_shared(t, [4], [[("range", 3, 0, 5)], [("range", 0, 0, 5)]], [("count*",)])

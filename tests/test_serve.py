@@ -102,3 +102,43 @@ def test_workload_is_seeded_poisson():
     assert abs(mean - 1 / 50.0) < 0.002
     kinds = {k: sum(q.kind == k for q in a) for k in ("agg", "join", "part")}
     assert all(500 < v < 830 for v in kinds.values())
+
+
+class SharingExecutor(FakeExecutor):
+    max_share = 8
+
+    def share_key(self, q):
+        return "agg" if q.kind == "agg" else None
+
+    def start_group(self, qs, slot):
+        self.groups = getattr(self, "groups", []) + [[q.qid for q in qs]]
+        job = self.start(qs[0], slot)
+        for q in qs[1:]:
+            self.in_use += self.FOOT[q.kind]
+        job["extra"] = qs[1:]
+        return job
+
+    def step(self, job):
+        was = job["done"]
+        done = super().step(job)
+        if done and not was:
+            for q in job.get("extra", []):
+                self.in_use -= self.FOOT[q.kind]
+        return done
+
+    def result_of(self, job, j):
+        return "shared"
+
+
+def test_shared_scans_group_waiting_aggregations():
+    clock = VirtualClock()
+    ex = SharingExecutor(clock, 1)
+    qs = [Query(i, "agg" if i % 3 else "join", 0.001 * i, {"b": 5}) for i in range(30)]
+    recs = Scheduler(ex, 100, clock=clock, idle_sleep=0).run(qs, keep_results=True)
+    assert sorted(r.qid for r in recs) == list(range(30))
+    groups = getattr(ex, "groups", [])
+    assert groups and max(len(g) for g in groups) > 1
+    assert all(len(g) <= 8 for g in groups)
+    for g in groups:                                   # only aggregation queries share
+        assert all(i % 3 for i in g)
+    assert ex.in_use == 0
