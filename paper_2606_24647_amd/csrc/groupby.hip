@@ -193,8 +193,15 @@ __global__ __launch_bounds__(BLOCK) void k_compact(const CompactArgs a) {
     const int64_t i = i0 + k;
     sl[k] = -1;
     if (i >= total_idx) return;
-    const bool extra = i >= (int64_t)cap;
-    const uint64_t s = extra ? a.cap_alloc + (uint64_t)(i - (int64_t)cap) : (uint64_t)i;
+    bool extra;
+    uint64_t s;
+    if (a.extras_first) {  // extras in reverse (NULL key, then the EMPTY-valued key), then hashed slots
+      extra = i < a.extra;
+      s = extra ? a.cap_alloc + (uint64_t)(a.extra - 1 - i) : (uint64_t)(i - a.extra);
+    } else {
+      extra = i >= (int64_t)cap;
+      s = extra ? a.cap_alloc + (uint64_t)(i - (int64_t)cap) : (uint64_t)i;
+    }
     bool occ;
     if (extra) occ = a.acc[s * a.aw] != 0;                       // extra slots: row count
     else if (a.key_kind == 2) occ = a.keys[s] != kEmpty && a.acc[s * a.aw] != 0;  // group-join: matched
@@ -223,7 +230,7 @@ __global__ __launch_bounds__(BLOCK) void k_compact(const CompactArgs a) {
   __syncthreads();
   const int64_t goff = s_excl;
   const int nk = a.key_kind == 2 ? 1 : a.kp.nk;
-  const int ncols = nk + a.naggs;
+  const int ncols = nk + a.naggs + (a.sortkey.data ? 1 : 0);
   if (tile == a.ntiles - 1 && threadIdx.x == 0) {
     int64_t total = goff + btot;
     if (total == 0 && a.global_agg) {
@@ -244,7 +251,7 @@ __global__ __launch_bounds__(BLOCK) void k_compact(const CompactArgs a) {
   if (btot == 0) return;
 
   for (int j = 0; j < ncols; ++j) {
-    const OCol& o = a.out[j];
+    const OCol& o = j < nk + a.naggs ? a.out[j] : a.sortkey;
     int pos = local;
     static_for<0, ITEMS>([&](auto kk) __attribute__((always_inline)) {
       constexpr int k = decltype(kk)::value;
@@ -253,7 +260,14 @@ __global__ __launch_bounds__(BLOCK) void k_compact(const CompactArgs a) {
       const bool extra = s >= a.cap_alloc;
       int64_t v = 0;
       bool ok = true;
-      if (j < nk) {
+      if (j == nk + a.naggs) {
+        // Sort key: unsigned order = key order, NULL first.
+        constexpr uint64_t kSign = 1ull << 63;
+        if (a.key_kind == 0) v = (int64_t)a.keys[s];
+        else if (!extra) v = (int64_t)(a.keys[s] ^ kSign);
+        else if (a.key_kind == 1 && s == a.cap_alloc + 1) v = 0;  // NULL
+        else v = (int64_t)(~0ull ^ kSign);                         // the key -1
+      } else if (j < nk) {
         if (a.key_kind == 2) {
           v = extra ? -1 : (int64_t)a.keys[s];
         } else if (a.kp.mode == KEY_RAW64) {
@@ -324,7 +338,6 @@ int run_groupby(gq_ctx* ctx, const gq_batch* in, const int32_t* keys, int nkeys,
   if (!d_groups) return set_error(ctx, GQ_ERR_INVALID, "group-by: NULL group count");
   gq_groupby_opts o{};
   if (opts) o = *opts;
-  if (o.flags & GQ_SORTED) return set_error(ctx, GQ_ERR_UNSUPPORTED, "group-by: GQ_SORTED output is not implemented");
   const float lf = o.load_factor > 0.f ? o.load_factor : 0.5f;
   if (!(lf > 0.f && lf <= 0.9f)) return set_error(ctx, GQ_ERR_INVALID, "group-by: load factor outside (0, 0.9]");
   if (o.strategy < GQ_STRATEGY_AUTO || o.strategy > GQ_STRATEGY_GLOBAL)
@@ -395,7 +408,7 @@ int run_groupby(gq_ctx* ctx, const gq_batch* in, const int32_t* keys, int nkeys,
     ca.key_kind = 2;
     ca.extra = 1;
     ca.global_agg = 0;
-    return compact_launch(ctx, ca, d_groups, stream);
+    return finish_groups(ctx, ca, out, d_groups, (o.flags & GQ_SORTED) != 0, stream);
   }
 
   int key_types[GQ_MAX_KEYS];
@@ -441,7 +454,7 @@ int run_groupby(gq_ctx* ctx, const gq_batch* in, const int32_t* keys, int nkeys,
   ca.key_kind = a.kp.mode == KEY_RAW64 ? 1 : 0;
   ca.kp = a.kp;
   ca.extra = 2;
-  return compact_launch(ctx, ca, d_groups, stream);
+  return finish_groups(ctx, ca, out, d_groups, (o.flags & GQ_SORTED) != 0 && nkeys > 0, stream);
 }
 
 }  // namespace
@@ -487,6 +500,63 @@ int compact_launch(gq_ctx* ctx, CompactArgs& ca, int64_t* d_groups, hipStream_t 
   GQ_LAUNCH_CHECK(ctx);
   return GQ_OK;
 }
+
+int finish_groups(gq_ctx* ctx, CompactArgs& ca, const gq_batch* out, int64_t* d_groups, bool sorted,
+                  hipStream_t stream) {
+  if (!sorted) return compact_launch(ctx, ca, d_groups, stream);
+  // Compact into two scratch batches [sort key, keys..., aggregates...], then
+  // radix-sort by the key into [scratch key, caller's columns].
+  const int nk = ca.key_kind == 2 ? 1 : ca.kp.nk;
+  const int nc = nk + ca.naggs;
+  const int64_t cap = ca.out_cap;
+  int bits = 64;
+  if (ca.key_kind == 0) {
+    bits = 0;
+    for (int j = 0; j < ca.kp.nk; ++j) bits += ca.kp.bits[j] + ca.kp.nullable[j];
+  }
+  size_t bytes = 0;
+  size_t off[2][1 + GQ_MAX_KEYS + GQ_MAX_AGGS], voff[2][1 + GQ_MAX_KEYS + GQ_MAX_AGGS];
+  for (int b = 0; b < 2; ++b)
+    for (int j = 0; j <= nc; ++j) {
+      const int w = j == 0 ? 8 : type_width(ca.out[j - 1].type);
+      off[b][j] = bytes;
+      bytes = align_up(bytes + (size_t)(cap > 0 ? cap : 1) * w, 256);
+      voff[b][j] = bytes;
+      if (j > 0 && ca.out[j - 1].valid) bytes = align_up(bytes + (size_t)((cap + 63) / 64) * 8, 256);
+    }
+  const size_t key3 = bytes;
+  bytes = align_up(bytes + (size_t)(cap > 0 ? cap : 1) * 8, 256);
+  Scratch ws(ctx, stream);
+  if (!ws.get(bytes)) return set_error(ctx, GQ_ERR_NOMEM, "group-by: sort workspace allocation failed");
+  gq_column cols[3][1 + GQ_MAX_KEYS + GQ_MAX_AGGS];
+  std::memset(cols, 0, sizeof(cols));
+  for (int b = 0; b < 2; ++b)
+    for (int j = 0; j <= nc; ++j) {
+      gq_column& c = cols[b][j];
+      c.type = j == 0 ? GQ_I64 : ca.out[j - 1].type;
+      c.length = cap;
+      c.data = ws.as<void>(off[b][j]);
+      c.validity = (j > 0 && ca.out[j - 1].valid) ? ws.as<uint8_t>(voff[b][j]) : nullptr;
+    }
+  cols[2][0].type = GQ_I64;
+  cols[2][0].length = cap;
+  cols[2][0].data = ws.as<void>(key3);
+  for (int j = 1; j <= nc; ++j) cols[2][j] = out->cols[j - 1];
+  gq_batch bt[3];
+  for (int b = 0; b < 3; ++b) bt[b] = gq_batch{cap, nc + 1, 0, cols[b]};
+  // Compaction into buffer 0.
+  CompactArgs c2 = ca;
+  c2.sortkey = OCol{static_cast<uint8_t*>(cols[0][0].data), nullptr, GQ_I64, 0};
+  for (int j = 0; j < nc; ++j)
+    c2.out[j] = OCol{static_cast<uint8_t*>(cols[0][j + 1].data), reinterpret_cast<uint32_t*>(cols[0][j + 1].validity),
+                     cols[0][j + 1].type, 0};
+  c2.extras_first = 1;
+  int rc = compact_launch(ctx, c2, d_groups, stream);
+  if (rc) return rc;
+  gq_batch* bufs[2] = {&bt[1], &bt[0]};
+  return radix_sort_rows(ctx, &bt[0], bufs, &bt[2], bits, cap, d_groups, stream);
+}
+
 
 int make_preds(gq_ctx* ctx, GbArgs& a, const gq_batch* in, const gq_pred* preds, int npreds) {
   if (npreds < 0 || npreds > GQ_MAX_PREDS || (npreds > 0 && !preds))

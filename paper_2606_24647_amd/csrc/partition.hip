@@ -25,12 +25,15 @@ namespace {
 constexpr int kPartMax = 1024;
 
 struct PartArgs {
-  int64_t n;
+  int64_t n;             // rows (an upper bound when d_n is set)
+  const int64_t* d_n;    // device row count, or NULL
   int64_t ntiles;
   uint64_t seed;
   uint64_t nparts;
   int32_t nkeys;
   int32_t ncols;
+  int32_t digit;         // 0: hash partition; 1: radix digit (key >> shift) & (nparts - 1)
+  int32_t shift;
   DCol keys[GQ_MAX_KEYS];
   DCol cols[GQ_MAX_COLS];
   OCol out[GQ_MAX_COLS];
@@ -38,7 +41,14 @@ struct PartArgs {
   int64_t* starts;   // nparts * ntiles, exclusive scan of counts
 };
 
+__device__ __forceinline__ int64_t rows_of(const PartArgs& a) {
+  if (!a.d_n) return a.n;
+  const int64_t d = *a.d_n;
+  return d < a.n ? d : a.n;
+}
+
 __device__ __forceinline__ uint32_t part_of_row(const PartArgs& a, int64_t r) {
+  if (a.digit) return (uint32_t)(((uint64_t)load_one(a.keys[0], r) >> a.shift) & (a.nparts - 1));
   uint64_t h = a.seed;
   for (int j = 0; j < a.nkeys; ++j) {
     const DCol& c = a.keys[j];
@@ -49,15 +59,22 @@ __device__ __forceinline__ uint32_t part_of_row(const PartArgs& a, int64_t r) {
 }
 
 template <int ITEMS>
-__device__ __forceinline__ void part_of_items(const PartArgs& a, int64_t r0, uint32_t (&p)[ITEMS]) {
+__device__ __forceinline__ void part_of_items(const PartArgs& a, int64_t r0, int64_t n, uint32_t (&p)[ITEMS]) {
+  if (a.digit) {
+    int64_t v[ITEMS];
+    load_items<ITEMS>(a.keys[0], r0, n, v);
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) p[k] = (uint32_t)(((uint64_t)v[k] >> a.shift) & (a.nparts - 1));
+    return;
+  }
   uint64_t h[ITEMS];
 #pragma unroll
   for (int k = 0; k < ITEMS; ++k) h[k] = a.seed;
   for (int j = 0; j < a.nkeys; ++j) {
     const DCol& c = a.keys[j];
     int64_t v[ITEMS];
-    load_items<ITEMS>(c, r0, a.n, v);
-    uint32_t vm = c.valid ? valid_items<ITEMS>(c, r0, a.n) : 0xffffffffu;
+    load_items<ITEMS>(c, r0, n, v);
+    uint32_t vm = c.valid ? valid_items<ITEMS>(c, r0, n) : 0xffffffffu;
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) h[k] = fmix64(h[k] ^ (((vm >> k) & 1u) ? (uint64_t)v[k] : 0ull));
   }
@@ -73,12 +90,13 @@ __global__ __launch_bounds__(BLOCK) void k_part_hist(const PartArgs a) {
   for (int i = threadIdx.x; i < P; i += BLOCK) s_hist[i] = 0;
   __syncthreads();
   const int64_t tile = blockIdx.x;
+  const int64_t n = rows_of(a);
   const int64_t r0 = tile * TILE + (int64_t)threadIdx.x * ITEMS;
   uint32_t p[ITEMS];
-  part_of_items<ITEMS>(a, r0, p);
+  part_of_items<ITEMS>(a, r0, n, p);
 #pragma unroll
   for (int k = 0; k < ITEMS; ++k)
-    if (r0 + k < a.n) atomicAdd(&s_hist[p[k]], 1u);
+    if (r0 + k < n) atomicAdd(&s_hist[p[k]], 1u);
   __syncthreads();
   for (int i = threadIdx.x; i < P; i += BLOCK) a.counts[(int64_t)i * a.ntiles + tile] = s_hist[i];
 }
@@ -154,6 +172,7 @@ __global__ __launch_bounds__(BLOCK) void k_part_scatter(const PartArgs a) {
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const int64_t tile = blockIdx.x;
   const int64_t tbase = tile * TILE;
+  const int64_t n = rows_of(a);
   for (int i = threadIdx.x; i < NW * PMAX; i += BLOCK) (&s_whist[0][0])[i] = 0;
   __syncthreads();
 
@@ -166,7 +185,7 @@ __global__ __launch_bounds__(BLOCK) void k_part_scatter(const PartArgs a) {
 #pragma unroll
   for (int k = 0; k < ITEMS; ++k) {
     const int64_t r = tbase + ((int64_t)wave * ITEMS + k) * kWave + lane;
-    const bool in = r < a.n;
+    const bool in = r < n;
     const uint32_t p = in ? part_of_row(a, r) : 0u;
     uint64_t peers = ballot(in);
     for (int b = 0; b < nbits; ++b) {
@@ -233,12 +252,12 @@ __global__ __launch_bounds__(BLOCK) void k_part_scatter(const PartArgs a) {
   for (int k = 0; k < ITEMS; ++k) {
     const int64_t r = tbase + ((int64_t)wave * ITEMS + k) * kWave + lane;
     lpos[k] = -1;
-    if (r < a.n) {
+    if (r < n) {
       lpos[k] = (int)(s_pstart[pid[k]] + s_whist[wave][pid[k]] + rank[k]);
       s_pid[lpos[k]] = (uint16_t)pid[k];
     }
   }
-  const int tn = (int)((a.n - tbase) < TILE ? (a.n - tbase) : TILE);
+  const int tn = (int)((n - tbase) < TILE ? (n - tbase) : TILE);
   __syncthreads();
 
   for (int j = 0; j < a.ncols; ++j) {
@@ -275,6 +294,96 @@ constexpr int kHistBlock = 256, kHistItems = 16;
 constexpr int kScatBlock = 256, kScatItems = 16;
 constexpr int kScanBlock = 256, kScanItems = 16;
 
+// Histogram, scan and scatter for the rows of `a` (a.n, or at most a.n rows
+// counted on the device when a.d_n is set).  d_offsets receives nparts + 1
+// partition starts.
+int launch_partition(gq_ctx* ctx, PartArgs& a, int64_t* d_offsets, hipStream_t stream) {
+  const int64_t nparts = (int64_t)a.nparts;
+  int rc;
+  if (a.n == 0) return launch_fill_u32(ctx, d_offsets, 0u, 2 * (nparts + 1), stream);
+  constexpr int TILE = kScatBlock * kScatItems;
+  static_assert(TILE == kHistBlock * kHistItems, "histogram and scatter tiles must agree");
+  const int64_t ntiles = (a.n + TILE - 1) / TILE;
+  a.ntiles = ntiles;
+  const int64_t m = ntiles * nparts;
+  constexpr int STILE = kScanBlock * kScanItems;
+  const int64_t nscan = (m + STILE - 1) / STILE;
+
+  Scratch ws(ctx, stream);
+  const size_t off_counts = 256;
+  const size_t off_starts = off_counts + align_up((size_t)m * 4, 256);
+  const size_t off_status = off_starts + align_up((size_t)m * 8, 256);
+  const size_t total = off_status + align_up((size_t)nscan * 8, 256);
+  if (!ws.get(total)) return set_error(ctx, GQ_ERR_NOMEM, "partition: workspace allocation failed");
+  a.counts = ws.as<uint32_t>(off_counts);
+  a.starts = ws.as<int64_t>(off_starts);
+  uint32_t* ticket = ws.as<uint32_t>(0);
+  uint64_t* status = ws.as<uint64_t>(off_status);
+
+  // ticket (one word) and the scan status words start at zero.
+  rc = launch_fill_u32(ctx, ticket, 0u, 1, stream);
+  if (rc) return rc;
+  rc = launch_fill_u32(ctx, status, 0u, 2 * nscan, stream);
+  if (rc) return rc;
+
+  GQ_LAUNCH(ctx, "part_hist", (k_part_hist<kHistBlock, kHistItems>), dim3((unsigned)ntiles), dim3(kHistBlock), 0,
+            stream, a);
+  GQ_LAUNCH_CHECK(ctx);
+  GQ_LAUNCH(ctx, "scan_counts", (k_scan_counts<kScanBlock, kScanItems>), dim3((unsigned)nscan), dim3(kScanBlock), 0,
+            stream, (const uint32_t*)a.counts, m, a.starts, ntiles, nparts, d_offsets, ticket, status, nscan);
+  GQ_LAUNCH_CHECK(ctx);
+  if (nparts <= 256) {
+    GQ_LAUNCH(ctx, "part_scatter", (k_part_scatter<kScatBlock, kScatItems, 256>), dim3((unsigned)ntiles),
+              dim3(kScatBlock), 0, stream, a);
+  } else {
+    GQ_LAUNCH(ctx, "part_scatter", (k_part_scatter<kScatBlock, kScatItems, kPartMax>), dim3((unsigned)ntiles),
+              dim3(kScatBlock), 0, stream, a);
+  }
+  GQ_LAUNCH_CHECK(ctx);
+  return GQ_OK;
+}
+
+}  // namespace
+
+// Stable LSD radix sort of rows by an unsigned key (column 0 of `a`, int64):
+// one partition pass per 8-bit digit of the `bits` low key bits, ping-ponging
+// between `bufs[0]` and `bufs[1]` (both laid out like the output, every column
+// including the key); the result lands in `out`.  Row count: at most `n`,
+// exactly *d_n when d_n is set.
+int radix_sort_rows(gq_ctx* ctx, const gq_batch* in, gq_batch* const bufs[2], gq_batch* out, int bits, int64_t n,
+                    const int64_t* d_n, hipStream_t stream) {
+  if (bits < 1) bits = 1;
+  const int passes = (bits + 7) / 8;
+  Scratch offs(ctx, stream);
+  if (!offs.get(8 * 257)) return set_error(ctx, GQ_ERR_NOMEM, "radix sort: workspace allocation failed");
+  const gq_batch* src = in;
+  for (int pass = 0; pass < passes; ++pass) {
+    const bool last = pass == passes - 1;
+    gq_batch* dst = last ? out : bufs[pass & 1];
+    const int dbits = (pass == passes - 1) ? bits - 8 * pass : 8;
+    PartArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.n = n;
+    a.d_n = d_n;
+    a.nparts = 1ull << dbits;
+    a.digit = 1;
+    a.shift = 8 * pass;
+    a.nkeys = 1;
+    a.ncols = src->ncols;
+    a.keys[0] = make_dcol(src->cols[0]);
+    for (int j = 0; j < src->ncols; ++j) {
+      a.cols[j] = make_dcol(src->cols[j]);
+      const gq_column& oc = dst->cols[j];
+      a.out[j] = OCol{static_cast<uint8_t*>(oc.data), reinterpret_cast<uint32_t*>(oc.validity), oc.type, 0};
+    }
+    int rc = launch_partition(ctx, a, offs.as<int64_t>(0), stream);
+    if (rc) return rc;
+    src = dst;
+  }
+  return GQ_OK;
+}
+
+namespace {
 }  // namespace
 }  // namespace gq
 
@@ -321,47 +430,5 @@ extern "C" int gq_hash_partition(gq_ctx* ctx, const gq_batch* in, const int32_t*
     a.out[j] = OCol{static_cast<uint8_t*>(oc.data), reinterpret_cast<uint32_t*>(oc.validity), oc.type, 0};
   }
   GQ_HIP_CHECK(ctx, hipSetDevice(ctx->device));
-  if (a.n == 0) return launch_fill_u32(ctx, d_offsets, 0u, 2 * ((int64_t)nparts + 1), stream);
-
-  constexpr int TILE = kScatBlock * kScatItems;
-  static_assert(TILE == kHistBlock * kHistItems, "histogram and scatter tiles must agree");
-  const int64_t ntiles = (a.n + TILE - 1) / TILE;
-  a.ntiles = ntiles;
-  const int64_t m = ntiles * nparts;
-  constexpr int STILE = kScanBlock * kScanItems;
-  const int64_t nscan = (m + STILE - 1) / STILE;
-
-  Scratch ws(ctx, stream);
-  const size_t off_counts = 256;
-  const size_t off_starts = off_counts + align_up((size_t)m * 4, 256);
-  const size_t off_status = off_starts + align_up((size_t)m * 8, 256);
-  const size_t total = off_status + align_up((size_t)nscan * 8, 256);
-  if (!ws.get(total)) return set_error(ctx, GQ_ERR_NOMEM, "gq_hash_partition: workspace allocation failed");
-  a.counts = ws.as<uint32_t>(off_counts);
-  a.starts = ws.as<int64_t>(off_starts);
-  uint32_t* ticket = ws.as<uint32_t>(0);
-  uint64_t* status = ws.as<uint64_t>(off_status);
-
-  // ticket (one word) and the scan status words start at zero.
-  rc = launch_fill_u32(ctx, ticket, 0u, 1, stream);
-  if (rc) return rc;
-  rc = launch_fill_u32(ctx, status, 0u, 2 * nscan, stream);
-  if (rc) return rc;
-
-  GQ_LAUNCH(ctx, "part_hist", (k_part_hist<kHistBlock, kHistItems>), dim3((unsigned)ntiles), dim3(kHistBlock), 0,
-                     stream, a);
-  GQ_LAUNCH_CHECK(ctx);
-  GQ_LAUNCH(ctx, "scan_counts", (k_scan_counts<kScanBlock, kScanItems>), dim3((unsigned)nscan), dim3(kScanBlock), 0,
-                     stream, (const uint32_t*)a.counts, m, a.starts, ntiles, (int64_t)nparts, d_offsets,
-                     ticket, status, nscan);
-  GQ_LAUNCH_CHECK(ctx);
-  if (nparts <= 256) {
-    GQ_LAUNCH(ctx, "part_scatter", (k_part_scatter<kScatBlock, kScatItems, 256>), dim3((unsigned)ntiles),
-                       dim3(kScatBlock), 0, stream, a);
-  } else {
-    GQ_LAUNCH(ctx, "part_scatter", (k_part_scatter<kScatBlock, kScatItems, kPartMax>), dim3((unsigned)ntiles),
-                       dim3(kScatBlock), 0, stream, a);
-  }
-  GQ_LAUNCH_CHECK(ctx);
-  return GQ_OK;
+  return launch_partition(ctx, a, d_offsets, stream);
 }

@@ -188,7 +188,6 @@ extern "C" int gq_groupby_shared(gq_ctx* ctx, const gq_batch* in, const int32_t*
     return set_error(ctx, GQ_ERR_INVALID, "gq_groupby_shared: bad predicate list");
   gq_groupby_opts o{};
   if (opts) o = *opts;
-  if (o.flags & GQ_SORTED) return set_error(ctx, GQ_ERR_UNSUPPORTED, "gq_groupby_shared: GQ_SORTED is not implemented");
   const float lf = o.load_factor > 0.f ? o.load_factor : 0.5f;
   if (!(lf > 0.f && lf <= 0.9f)) return set_error(ctx, GQ_ERR_INVALID, "gq_groupby_shared: load factor outside (0, 0.9]");
 
@@ -272,7 +271,7 @@ extern "C" int gq_groupby_shared(gq_ctx* ctx, const gq_batch* in, const int32_t*
     ca[q].key_kind = a.kp.mode == KEY_RAW64 ? 1 : 0;
     ca[q].kp = a.kp;
     ca[q].extra = 2;
-    rc = compact_launch(ctx, ca[q], d_groups + q, stream);
+    rc = finish_groups(ctx, ca[q], &outs[q], d_groups + q, (o.flags & GQ_SORTED) != 0 && nkeys > 0, stream);
     if (rc) return rc;
   }
   return GQ_OK;

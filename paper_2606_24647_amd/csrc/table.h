@@ -200,10 +200,11 @@ struct CompactArgs {
   int32_t extra;           // number of extra slots to visit (1 or 2)
   int32_t naggs;
   int32_t global_agg;      // no key columns: one row even when nothing is occupied
-  int32_t pad;
+  int32_t extras_first;    // visit the extra slots first, NULL key first (sorted output)
   KeyPlan kp;
   DAgg aggs[GQ_MAX_AGGS];
   OCol out[GQ_MAX_KEYS + GQ_MAX_AGGS];
+  OCol sortkey;            // if data != NULL: an unsigned sort key per output row
   int64_t out_cap;
   int64_t ntiles;
   uint32_t* ticket;

@@ -439,7 +439,7 @@ class Context:
         return out, cnt
 
     def groupby_shared(self, table: DevTable, keys, query_preds, aggs, capacity: int | None = None,
-                       load_factor=0.0, expected_groups=0, stream=None):
+                       load_factor=0.0, expected_groups=0, sorted=False, stream=None):
         """Several filter + group-by queries in one pass (query_preds: one predicate
         list per query, same columns and ops).  Returns (list of outputs, device counts)."""
         nq = len(query_preds)
@@ -453,7 +453,7 @@ class Context:
         a, na = _aggs(aggs)
         obs = [_BatchArg(o, cap) for o in outs]
         oarr = (GqBatch * max(1, nq))(*[ob.batch for ob in obs])
-        opts = self._opts(load_factor, "auto", False, 0, expected_groups)
+        opts = self._opts(load_factor, "auto", sorted, 0, expected_groups)
         ib = _BatchArg(table)
         self.check(_lib.gq_groupby_shared(self.h, ib.ref, k, nk, p, npreds, nq, a, na, C.byref(opts), oarr,
                                           C.c_void_p(cnt.data_ptr()), _stream(stream)))

@@ -154,3 +154,65 @@ def test_shared_scan_rejects_mixed_columns(gq, ctx):
     t = gq.to_device(dg.fact_c1(1000))
     with pytest.raises(gq.GqError):
         ctx.groupby_shared(t, [4], [[("range", 3, 0, 5)], [("range", 0, 0, 5)]], [("count*",)])
+
+
+def check_sorted(gq, cols, exp, nk):
+    """GQ_SORTED output equals the oracle's canonical order directly (no host sort)."""
+    for j, (g, e) in enumerate(zip(cols, exp.keys + exp.aggs)):
+        gv, gok = g
+        ev, eok = e
+        gok = np.ones(len(gv), dtype=bool) if gok is None else gok
+        assert np.array_equal(gok, eok), f"col {j} validity"
+        assert np.array_equal(np.where(gok, gv.astype(np.int64), 0), np.where(eok, ev, 0)), f"col {j} values"
+
+
+@pytest.mark.parametrize("strategy", ["lds", "global"])
+def test_sorted_output_packed_keys(gq, ctx, strategy):
+    rng = np.random.default_rng(41)
+    t = random_table(rng, 60_000, null_frac=0.15, lo=-40, hi=40)
+    aggs = [("count*",), ("sum", [("col", 0)])]
+    out, cnt = ctx.groupby_agg(gq.to_device(t), [2, 3], [], aggs, strategy=strategy, sorted=True)
+    assert ctx.sync_status() == 0
+    n = int(cnt.item())
+    exp = oracle.groupby(t, [2, 3], [], aggs)
+    assert n == exp.nrows
+    check_sorted(gq, gq.read_table(out, n), exp, 2)
+
+
+def test_sorted_output_raw64_keys(gq, ctx):
+    rng = np.random.default_rng(42)
+    n = 100_000
+    k = rng.integers(-3_000, 3_000, n)
+    k[::89] = -1
+    k[::97] = np.iinfo(np.int64).min
+    k[::101] = np.iinfo(np.int64).max
+    t = tbl(k=(k, rng.random(n) > 0.05), v=rng.integers(0, 100, n))
+    aggs = [("sum", [("col", 1)]), ("count*",)]
+    out, cnt = ctx.groupby_agg(gq.to_device(t), [0], [], aggs, sorted=True)
+    assert ctx.sync_status() == 0
+    m = int(cnt.item())
+    exp = oracle.groupby(t, [0], [], aggs)
+    assert m == exp.nrows
+    check_sorted(gq, gq.read_table(out, m), exp, 1)
+
+
+def test_sorted_groupjoin_and_shared(gq, ctx):
+    dim = dg.dim_c2(50_000, seed=44)
+    fact = dg.fact_c2(200_000, nkeys=50_000, seed=44)
+    aggs = [("sum", REV), ("count*",)]
+    jt = ctx.join_build(gq.to_device(dim), [0], [("range", 1, 0, 1202)], acc_slots=2)
+    out, cnt = ctx.pipeline(gq.to_device(fact), [("range", 3, 1278, 2555)], [0], aggs, join=jt, probe_key=0,
+                            sorted=True)
+    assert ctx.sync_status() == 0
+    n = int(cnt.item())
+    exp = oracle.pipeline(fact, [("range", 3, 1278, 2555)], [0], aggs, join_spec=(dim, [0], [("range", 1, 0, 1202)], [0]))
+    assert n == exp.nrows
+    check_sorted(gq, gq.read_table(out, n), exp, 1)
+    t = dg.fact_c1(100_000, seed=45)
+    qp = [[("range", 3, 0, 1000)], [("range", 3, 500, 2555)]]
+    outs, cnts = ctx.groupby_shared(gq.to_device(t), [4, 5], qp, C1_AGGS, capacity=16, expected_groups=6,
+                                    sorted=True)
+    assert ctx.sync_status() == 0
+    for q in range(2):
+        m = int(cnts[q].item())
+        check_sorted(gq, gq.read_table(outs[q], m), oracle.groupby(t, [4, 5], qp[q], C1_AGGS), 2)
