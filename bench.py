@@ -212,7 +212,7 @@ def run_operators(torch, gq, devgen, ctx, c2, reps=5):
     kept = int(fcnt.item())
     res["c2_filter_fact"] = entry(FACT_ROWS, FACT_ROWS * 28 + kept * 28, ms, kept=kept)
     del fout
-    del c2["dim"], c2["fact"], dim, fact
+    del dim, fact
     torch.cuda.empty_cache()
 
     log("operator: hash partition, 60M rows x 21 B")
@@ -313,7 +313,7 @@ def run_batched(torch, gq, devgen, ctx, steps=5, nfrag=4096, tune=True):
 # Serving: Poisson arrivals against device-resident 600M x 150M tables
 # ---------------------------------------------------------------------------
 
-def run_serving(torch, gq, devgen, nq=150, qps_list=(50, 100, 200), budget_gb=120, slots=4, p99_bound_ms=250.0):
+def run_serving(torch, gq, devgen, nq=150, qps_list=(50, 100, 200), budget_gb=96, slots=4, p99_bound_ms=250.0):
     from paper_2606_24647_amd import datagen as dg
     from paper_2606_24647_amd import serve
     log("generating resident fact 600M x 7 and dim 150M x 3 on the device")
@@ -335,6 +335,8 @@ def run_serving(torch, gq, devgen, nq=150, qps_list=(50, 100, 200), budget_gb=12
         for mode, ex in (("plain", plain_ex), ("served", served_ex)):
             log(f"serving: {mode} at {qps} QPS, {nq} queries")
             recs = serve.Scheduler(ex, budget).run(qs)
+            torch.cuda.synchronize()
+            torch.cuda.empty_cache()
             sm = serve.summarize(recs)
             sm.update(mode=mode, qps=qps)
             res["runs"].append({k: (round(v, 3) if isinstance(v, float) else v) for k, v in sm.items()})
@@ -429,21 +431,34 @@ def main():
                                                   "paper_2606_24647_amd/csrc/common.h"]),
                 "kernel": dom_name, "avg_launch_ms": round(dom_avg, 4), "alg_bytes_per_launch": per_launch}
 
+    def section(name, fn):
+        """Run one optional section; a failure is reported in its place, not fatal."""
+        try:
+            r = fn()
+        except Exception as e:  # noqa: BLE001 - reported in the JSON line
+            log(f"{name} failed: {type(e).__name__}: {e}")
+            r = {"error": f"{type(e).__name__}: {e}"}
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        log(f"{name}: {json.dumps(r)[:2000]}")
+        return r
+
     operators = None
     if not args.no_operators:
-        operators = run_operators(torch, gq, devgen, ctx, c2)
-    else:
-        del c2["dim"], c2["fact"]
+        operators = section("operators", lambda: run_operators(torch, gq, devgen, ctx, c2))
+    c2.pop("dim", None)
+    c2.pop("fact", None)
+    torch.cuda.empty_cache()
     batched = None
     if not args.no_batched:
-        batched = run_batched(torch, gq, devgen, ctx)
+        batched = section("batched", lambda: run_batched(torch, gq, devgen, ctx))
     serving = None
     if not args.no_serving:
-        serving = run_serving(torch, gq, devgen)
+        serving = section("serving", lambda: run_serving(torch, gq, devgen))
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on a 1/10 sample")
-        cpu = cpu_baseline()
+        cpu = section("cpu_baseline", cpu_baseline)
 
     line = {
         "metric": "input rows/s (filter + hash join + group-by pipeline, fact 60M x dim 15M)",

@@ -203,9 +203,12 @@ class DeviceExecutor:
         if q.kind == "agg":
             return 64 << 20
         if q.kind == "join":
-            cap = 2 * self.nd + 1
-            return cap * (8 + 8 + 16) + self.nd * 12 + self.nd * 24 + (64 << 20)
-        return 2 * self.nf * 21 + (256 << 20)
+            cap = 2 * self.nd + 1       # load factor 0.5 over every dimension row
+            # keys, meta, 2 accumulators, run cursors per slot; rows and merge
+            # buffer per build row; the output at one group per build row.
+            return cap * (8 + 8 + 16 + 4) + self.nd * 8 + self.nd * 24 + (64 << 20)
+        # filter output and partition output at 21 B per row, plus workspace
+        return 2 * self.nf * 21 + (self.nf // 4096 + 1) * 256 * 12 + (256 << 20)
 
     def rows(self, q: Query) -> int:
         return self.nf + (self.nd if q.kind == "join" else 0)
