@@ -6,6 +6,8 @@
 
 #include "table.h"
 
+#include <functional>
+
 namespace gq {
 
 struct JoinRef {
@@ -275,8 +277,10 @@ int make_agg_plan(gq_ctx* ctx, AggPlan& ap, const gq_batch* in, const gq_agg* ag
 int check_outputs(gq_ctx* ctx, int nk_out, int na, gq_batch* out, CompactArgs& ca, const int* key_types);
 int compact_launch(gq_ctx* ctx, CompactArgs& ca, int64_t* d_groups, hipStream_t stream);
 // Compaction into `out`, key-sorted through a radix sort when `sorted` is set.
+// `emit`, when given, writes the groups into a CompactArgs' outputs in place
+// of the compaction of its table.
 int finish_groups(gq_ctx* ctx, CompactArgs& ca, const gq_batch* out, int64_t* d_groups, bool sorted,
-                  hipStream_t stream);
+                  hipStream_t stream, const std::function<int(CompactArgs&)>* emit = nullptr);
 // Stable LSD radix sort by the unsigned int64 key in column 0 (partition.hip).
 int radix_sort_rows(gq_ctx* ctx, const gq_batch* in, gq_batch* const bufs[2], gq_batch* out, int bits, int64_t n,
                     const int64_t* d_n, hipStream_t stream);

@@ -90,7 +90,7 @@ struct Scratch {
   }
 };
 
-inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+__host__ __device__ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // ---------------------------------------------------------------------------
 // Column descriptors as kernels see them
@@ -134,6 +134,19 @@ inline int addr_align(const void* p) {
 // ---------------------------------------------------------------------------
 // Device helpers
 // ---------------------------------------------------------------------------
+
+// Tile handled by block b of an nblocks grid such that every XCD works
+// through one contiguous range of tiles: workgroups are dispatched to the 8
+// XCDs round-robin (block b runs on XCD b % 8), so XCD x takes tiles
+// [x * per + min(x, rem), ...) in order.  Neighbouring tiles then run on the
+// same XCD at about the same time and their partial output lines meet in
+// that XCD's L2.  A bijection on [0, nblocks).
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nblocks) {
+  const int64_t x = b % kXcds, i = b / kXcds;
+  const int64_t per = nblocks / kXcds, rem = nblocks % kXcds;
+  return x * per + (x < rem ? x : rem) + i;
+}
 
 __device__ __forceinline__ int64_t load_one(const DCol& c, int64_t i) {
   switch (c.type) {
@@ -202,6 +215,10 @@ __device__ __forceinline__ void load_items(const DCol& c, int64_t r0, int64_t n,
             v[k] = x.x; v[k + 1] = x.y; v[k + 2] = x.z; v[k + 3] = x.w;
           }
           return;
+        } else if constexpr (ITEMS == 2) {
+          gq_v2i x = ld8<NT>(p);
+          v[0] = x.x; v[1] = x.y;
+          return;
         }
         break;
       }
@@ -222,6 +239,10 @@ __device__ __forceinline__ void load_items(const DCol& c, int64_t r0, int64_t n,
           gq_v2i x = ld8<NT>(p);
           v[0] = (int16_t)(x.x & 0xffff); v[1] = (int16_t)((uint32_t)x.x >> 16);
           v[2] = (int16_t)(x.y & 0xffff); v[3] = (int16_t)((uint32_t)x.y >> 16);
+          return;
+        } else if constexpr (ITEMS == 2) {
+          int32_t x = ld4<NT>(p);
+          v[0] = (int16_t)(x & 0xffff); v[1] = (int16_t)((uint32_t)x >> 16);
           return;
         }
         break;

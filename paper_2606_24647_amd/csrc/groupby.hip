@@ -18,6 +18,9 @@
 // materialised join.  All sums wrap modulo 2^64 and are therefore independent
 // of the order in which atomics land.
 #include "agg.h"
+#include "radix.h"
+
+#include <functional>
 
 namespace gq {
 namespace {
@@ -376,8 +379,25 @@ int run_groupby(gq_ctx* ctx, const gq_batch* in, const int32_t* keys, int nkeys,
   for (int i = 0; i < naggs; ++i) ca.aggs[i] = a.ap.aggs[i];
   ca.global_agg = nkeys == 0;
 
+  // Group-join of a partitioned (large) build side: radix path, no HBM table.
+  const bool gj_shape = join && nkeys == 1 && keys[0] == probe_key;
+  if (gj_shape && rj_usable(join, in, probe_key, preds, npreds, a.ap)) {
+    int kt[1] = {in->cols[probe_key].type};
+    rc = check_outputs(ctx, 1, naggs, out, ca, kt);
+    if (rc) return rc;
+    ca.key_kind = 2;
+    ca.extra = 1;
+    const std::function<int(CompactArgs&)> emit = [&](CompactArgs& target) {
+      return rj_groupjoin(ctx, in, probe_key, preds, npreds, a.ap, join, target, d_groups, stream);
+    };
+    return finish_groups(ctx, ca, out, d_groups, (o.flags & GQ_SORTED) != 0, stream, &emit);
+  }
+  if (join) {
+    rc = join_ensure_index(ctx, join, stream);
+    if (rc) return rc;
+  }
   // Group-join: the only key is the probe key and the table has room.
-  const bool groupjoin = join && nkeys == 1 && keys[0] == probe_key && join->acc_slots >= a.ap.nacc;
+  const bool groupjoin = gj_shape && join->acc_slots >= a.ap.nacc;
   if (groupjoin) {
     int kt[1] = {in->cols[probe_key].type};
     rc = check_outputs(ctx, 1, naggs, out, ca, kt);
@@ -502,8 +522,8 @@ int compact_launch(gq_ctx* ctx, CompactArgs& ca, int64_t* d_groups, hipStream_t 
 }
 
 int finish_groups(gq_ctx* ctx, CompactArgs& ca, const gq_batch* out, int64_t* d_groups, bool sorted,
-                  hipStream_t stream) {
-  if (!sorted) return compact_launch(ctx, ca, d_groups, stream);
+                  hipStream_t stream, const std::function<int(CompactArgs&)>* emit) {
+  if (!sorted) return emit ? (*emit)(ca) : compact_launch(ctx, ca, d_groups, stream);
   // Compact into two scratch batches [sort key, keys..., aggregates...], then
   // radix-sort by the key into [scratch key, caller's columns].
   const int nk = ca.key_kind == 2 ? 1 : ca.kp.nk;
@@ -551,7 +571,7 @@ int finish_groups(gq_ctx* ctx, CompactArgs& ca, const gq_batch* out, int64_t* d_
     c2.out[j] = OCol{static_cast<uint8_t*>(cols[0][j + 1].data), reinterpret_cast<uint32_t*>(cols[0][j + 1].validity),
                      cols[0][j + 1].type, 0};
   c2.extras_first = 1;
-  int rc = compact_launch(ctx, c2, d_groups, stream);
+  int rc = emit ? (*emit)(c2) : compact_launch(ctx, c2, d_groups, stream);
   if (rc) return rc;
   gq_batch* bufs[2] = {&bt[1], &bt[0]};
   return radix_sort_rows(ctx, &bt[0], bufs, &bt[2], bits, cap, d_groups, stream);

@@ -18,6 +18,7 @@
 // Each thread issues the first probe of all its rows before resolving any of
 // them, so the random reads of a thread overlap.
 #include "table.h"
+#include "radix.h"
 
 namespace gq {
 namespace {
@@ -44,25 +45,41 @@ struct JoinBuildArgs {
   int32_t acc_slots;
   int32_t pad;
   int32_t* dev_status;
+  const int32_t* rowmap;  // build row of input row r (NULL: r itself)
+  const int64_t* d_n;     // device row count (NULL: n); n is then an upper bound
+  int32_t key_hashed;     // the key column holds region hashes of the keys
+  int32_t pad2;
 };
+
+__device__ __forceinline__ int64_t jb_rows(const JoinBuildArgs& a) {
+  if (!a.d_n) return a.n;
+  const int64_t d = *a.d_n;
+  return d < a.n ? d : a.n;
+}
+__device__ __forceinline__ int64_t jb_row(const JoinBuildArgs& a, int64_t r) { return a.rowmap ? a.rowmap[r] : r; }
 
 // Keep mask of rows r0..r0+ITEMS-1 (predicates and a non-NULL key); key values.
 template <int ITEMS>
 __device__ __forceinline__ uint32_t build_rows_keep(const JoinBuildArgs& a, int64_t r0, int64_t (&key)[ITEMS]) {
+  const int64_t n = jb_rows(a);
   uint32_t keep = 0;
 #pragma unroll
   for (int k = 0; k < ITEMS; ++k)
-    if (r0 + k < a.n) keep |= 1u << k;
+    if (r0 + k < n) keep |= 1u << k;
   for (int p = 0; p < a.npreds; ++p) {
     int64_t v[ITEMS];
-    load_items<ITEMS, true>(a.pcols[p], r0, a.n, v);
+    load_items<ITEMS, true>(a.pcols[p], r0, n, v);
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k)
       if (!pred_pass(a.preds[p], v[k])) keep &= ~(1u << k);
-    if (a.pcols[p].valid) keep &= valid_items<ITEMS>(a.pcols[p], r0, a.n);
+    if (a.pcols[p].valid) keep &= valid_items<ITEMS>(a.pcols[p], r0, n);
   }
-  load_items<ITEMS, true>(a.key, r0, a.n, key);
-  if (a.key.valid) keep &= valid_items<ITEMS>(a.key, r0, a.n);
+  load_items<ITEMS, true>(a.key, r0, n, key);
+  if (a.key.valid) keep &= valid_items<ITEMS>(a.key, r0, n);
+  if (a.key_hashed) {
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) key[k] = (int64_t)region_unhash((uint64_t)key[k]);
+  }
   return keep;
 }
 
@@ -144,7 +161,7 @@ __global__ __launch_bounds__(BLOCK) void k_jinsert(const JoinBuildArgs a) {
     constexpr int k = decltype(kk)::value;
     if (!((keep >> k) & 1u)) return;
     const uint64_t kv = (uint64_t)key[k];
-    const uint64_t row = (uint64_t)(r0 + k);
+    const uint64_t row = (uint64_t)jb_row(a, r0 + k);
     int64_t s;
     bool inserted = false;
     if (kv == kEmpty) {
@@ -254,7 +271,7 @@ __global__ __launch_bounds__(BLOCK) void k_jdup_fill(const JoinBuildArgs a) {
       idx = (uint64_t)s;
     }
     const uint32_t pos = atomicAdd(&a.aux[idx], 1u);
-    a.rows[pos] = (int32_t)(r0 + k);
+    a.rows[pos] = (int32_t)jb_row(a, r0 + k);
   }
 }
 
@@ -524,7 +541,75 @@ int fill_build_args(gq_ctx* ctx, JoinBuildArgs& a, const gq_batch* b, const int3
   return GQ_OK;
 }
 
+// Probe index (keys/meta, and rows for duplicate keys) of t from the rows
+// described by a: the build input itself (count = true: count the kept rows
+// first), or the partitioned kept rows of a large build input.
+int build_index(gq_ctx* ctx, JoinBuildArgs& a, gq_join_table* t, bool count, hipStream_t stream) {
+  a.hdr = t->hdr;
+  a.keys = t->keys;
+  a.meta = t->meta;
+  a.acc = t->acc;
+  a.rows = t->rows;
+  a.aux = t->aux;
+  a.tmp = t->tmp;
+  a.cap_alloc = t->cap_alloc;
+  a.acc_slots = t->acc_slots;
+  a.lf_milli = t->lf_milli;
+  a.dev_status = ctx->d_status;
+  constexpr int TILE = kJBlock * kJItems;
+  const int64_t nblk = (a.n + TILE - 1) / TILE;
+  if (count && nblk > 0) {
+    GQ_LAUNCH(ctx, "jcount", (k_jcount<kJBlock, kJItems>), dim3((unsigned)nblk), dim3(kJBlock), 0, stream, a);
+    GQ_LAUNCH_CHECK(ctx);
+  }
+  int64_t iblocks = (int64_t)((t->cap_alloc + 1 + 255) / 256);
+  if (iblocks > 8192) iblocks = 8192;
+  GQ_LAUNCH(ctx, "jinit", k_jinit, dim3((unsigned)iblocks), dim3(256), 0, stream, a);
+  GQ_LAUNCH_CHECK(ctx);
+  if (nblk > 0) {
+    GQ_LAUNCH(ctx, "jinsert", (k_jinsert<kJBlock, kJItems>), dim3((unsigned)nblk), dim3(kJBlock), 0, stream, a);
+    GQ_LAUNCH_CHECK(ctx);
+    // Duplicate handling (kernels return at once when every key is unique).
+    constexpr int STILE = 256 * 16;
+    const int64_t nscan = (int64_t)((t->cap_alloc + 1 + STILE - 1) / STILE);
+    Scratch ws(ctx, stream);
+    if (!ws.get(256 + align_up((size_t)nscan * 8, 256)))
+      return set_error(ctx, GQ_ERR_NOMEM, "join: index workspace allocation failed");
+    int rc = launch_fill_u32(ctx, ws.p, 0u, 64 + 2 * nscan, stream);
+    if (rc) return rc;
+    GQ_LAUNCH(ctx, "jdup_scan", (k_jdup_scan<256, 16>), dim3((unsigned)nscan), dim3(256), 0, stream, a,
+              ws.as<uint32_t>(0), ws.as<uint64_t>(256));
+    GQ_LAUNCH_CHECK(ctx);
+    GQ_LAUNCH(ctx, "jdup_fill", (k_jdup_fill<kJBlock, kJItems>), dim3((unsigned)nblk), dim3(kJBlock), 0, stream, a);
+    GQ_LAUNCH_CHECK(ctx);
+    GQ_LAUNCH(ctx, "jdup_sort", k_jdup_sort, dim3((unsigned)iblocks), dim3(256), 0, stream, a);
+    GQ_LAUNCH_CHECK(ctx);
+    GQ_LAUNCH(ctx, "jdup_sort_long", (k_jdup_sort_long<1024>), dim3(64), dim3(1024), 0, stream, a);
+    GQ_LAUNCH_CHECK(ctx);
+  }
+  t->index_built = true;
+  return GQ_OK;
+}
+
 }  // namespace
+
+int join_ensure_index(gq_ctx* ctx, const gq_join_table* table, hipStream_t stream) {
+  gq_join_table* t = const_cast<gq_join_table*>(table);
+  if (t->index_built) return GQ_OK;
+  JoinBuildArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.n = t->build_rows;
+  a.key.data = reinterpret_cast<const uint8_t*>(t->rj_key);
+  a.key.type = GQ_I64;
+  a.key.align = 16;
+  a.npreds = 0;
+  a.rowmap = t->rj_row;
+  a.d_n = &t->hdr->nrows;
+  a.key_hashed = 1;
+  GQ_HIP_CHECK(ctx, hipSetDevice(ctx->device));
+  return build_index(ctx, a, t, false, stream);
+}
+
 }  // namespace gq
 
 using namespace gq;
@@ -553,6 +638,13 @@ int gq_join_build(gq_ctx* ctx, const gq_batch* build, const int32_t* keys, int n
   if (cap_alloc < 1) cap_alloc = 1;
   a.cap_alloc = cap_alloc;
   a.acc_slots = acc;
+  // Large build inputs are partitioned by region (radix group-join); their
+  // probe index is built from the partitioned rows when first needed.
+  const int rlog = opts ? opts->regions_log2 : 0;
+  if (rlog != 0 && (rlog < 4 || rlog > 10))
+    return set_error(ctx, GQ_ERR_INVALID, "gq_join_build: regions_log2 must be 0 or in [4, 10]");
+  const int pbits = rlog ? rlog : rj_choose_pbits(n);
+  const bool radix = n >= kRjMinBuild && n < ((int64_t)1 << 31) && rj_build_fits(build, keys[0], preds, npreds, pbits);
 
   const size_t nslot = (size_t)cap_alloc + 1;
   const size_t off_keys = 256;
@@ -561,7 +653,10 @@ int gq_join_build(gq_ctx* ctx, const gq_batch* build, const int32_t* keys, int n
   const size_t off_rows = align_up(off_acc + nslot * 8 * (size_t)acc, 256);
   const size_t off_aux = align_up(off_rows + (size_t)n * 4, 256);
   const size_t off_tmp = align_up(off_aux + nslot * 4, 256);
-  const size_t total = align_up(off_tmp + (size_t)n * 4, 256);
+  const size_t off_rjkey = align_up(off_tmp + (size_t)n * 4, 256);
+  const size_t off_rjrow = align_up(off_rjkey + (radix ? (size_t)n * 8 : 0), 256);
+  const size_t off_rjoff = align_up(off_rjrow + (radix ? (size_t)n * 4 : 0), 256);
+  const size_t total = align_up(off_rjoff + (radix ? ((size_t)1 << pbits) * 8 + 8 : 0), 256);
 
   GQ_HIP_CHECK(ctx, hipSetDevice(ctx->device));
   gq_join_table* t = new (std::nothrow) gq_join_table;
@@ -586,53 +681,26 @@ int gq_join_build(gq_ctx* ctx, const gq_batch* build, const int32_t* keys, int n
   t->build_rows = n;
   t->key_type = build->cols[keys[0]].type;
   t->device = ctx->device;
-  a.hdr = t->hdr;
-  a.keys = t->keys;
-  a.meta = t->meta;
-  a.acc = t->acc;
-  a.rows = t->rows;
-  a.aux = t->aux;
-  a.tmp = t->tmp;
-  a.dev_status = ctx->d_status;
-
-  constexpr int TILE = kJBlock * kJItems;
-  const int64_t nblk = (n + TILE - 1) / TILE;
+  t->lf_milli = a.lf_milli;
+  if (radix) {
+    t->rj_pbits = pbits;
+    t->rj_key = reinterpret_cast<uint64_t*>(base + off_rjkey);
+    t->rj_row = reinterpret_cast<int32_t*>(base + off_rjrow);
+    t->rj_off = reinterpret_cast<int64_t*>(base + off_rjoff);
+  }
   auto fail = [&](int code) {
     gq_join_table_free(ctx, t, stream);
     return code;
   };
   GQ_LAUNCH(ctx, "jhdr_init", k_jhdr_init, dim3(1), dim3(64), 0, stream, t->hdr);
   GQ_LAUNCH_CHECK(ctx);
-  if (nblk > 0) {
-    GQ_LAUNCH(ctx, "jcount", (k_jcount<kJBlock, kJItems>), dim3((unsigned)nblk), dim3(kJBlock), 0, stream, a);
-    GQ_LAUNCH_CHECK(ctx);
-  }
-  int64_t iblocks = (int64_t)((cap_alloc + 1 + 255) / 256);
-  if (iblocks > 8192) iblocks = 8192;
-  GQ_LAUNCH(ctx, "jinit", k_jinit, dim3((unsigned)iblocks), dim3(256), 0, stream, a);
-  GQ_LAUNCH_CHECK(ctx);
-  if (nblk > 0) {
-    GQ_LAUNCH(ctx, "jinsert", (k_jinsert<kJBlock, kJItems>), dim3((unsigned)nblk), dim3(kJBlock), 0, stream, a);
-    GQ_LAUNCH_CHECK(ctx);
-    // Duplicate handling (kernels return at once when every key is unique).
-    constexpr int STILE = 256 * 16;
-    const int64_t nscan = (int64_t)((cap_alloc + 1 + STILE - 1) / STILE);
-    Scratch ws(ctx, stream);
-    if (!ws.get(256 + align_up((size_t)nscan * 8, 256))) {
-      set_error(ctx, GQ_ERR_NOMEM, "gq_join_build: workspace allocation failed");
-      return fail(GQ_ERR_NOMEM);
-    }
-    rc = launch_fill_u32(ctx, ws.p, 0u, 64 + 2 * nscan, stream);
+  if (radix) {
+    rc = rj_build(ctx, build, keys[0], preds, npreds, t, stream);
     if (rc) return fail(rc);
-    GQ_LAUNCH(ctx, "jdup_scan", (k_jdup_scan<256, 16>), dim3((unsigned)nscan), dim3(256), 0, stream, a,
-              ws.as<uint32_t>(0), ws.as<uint64_t>(256));
-    GQ_LAUNCH_CHECK(ctx);
-    GQ_LAUNCH(ctx, "jdup_fill", (k_jdup_fill<kJBlock, kJItems>), dim3((unsigned)nblk), dim3(kJBlock), 0, stream, a);
-    GQ_LAUNCH_CHECK(ctx);
-    GQ_LAUNCH(ctx, "jdup_sort", k_jdup_sort, dim3((unsigned)iblocks), dim3(256), 0, stream, a);
-    GQ_LAUNCH_CHECK(ctx);
-    GQ_LAUNCH(ctx, "jdup_sort_long", (k_jdup_sort_long<1024>), dim3(64), dim3(1024), 0, stream, a);
-    GQ_LAUNCH_CHECK(ctx);
+    t->index_built = false;
+  } else {
+    rc = build_index(ctx, a, t, true, stream);
+    if (rc) return fail(rc);
   }
   *out = t;
   return GQ_OK;
@@ -660,6 +728,8 @@ int gq_join_probe(gq_ctx* ctx, const gq_join_table* table, const gq_batch* probe
     a.preds[p] = b.preds[p];
     a.pcols[p] = b.pcols[p];
   }
+  rc = join_ensure_index(ctx, table, stream);
+  if (rc) return rc;
   a.hdr = table->hdr;
   a.keys = table->keys;
   a.meta = table->meta;

@@ -170,7 +170,7 @@ __global__ __launch_bounds__(BLOCK) void k_part_scatter(const PartArgs a) {
 
   const int P = (int)a.nparts;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  const int64_t tile = blockIdx.x;
+  const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
   const int64_t tbase = tile * TILE;
   const int64_t n = rows_of(a);
   for (int i = threadIdx.x; i < NW * PMAX; i += BLOCK) (&s_whist[0][0])[i] = 0;

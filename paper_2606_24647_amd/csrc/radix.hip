@@ -1,0 +1,999 @@
+// Radix group-join: a join whose only group key is the join key, evaluated
+// without any HBM hash table.  Both sides are partitioned by a hash of the key
+// into P regions; every (region, sub-region) is then joined and aggregated by
+// one workgroup in an LDS hash table.
+//
+// Why this shape: on gfx950 a device-wide atomic add is served by one
+// chip-wide path (about 24 G atomics/s measured, independent of the table
+// size, even for a table that fits one XCD's L2), so a group-join that adds
+// into an HBM table pays two atomics per matched row and is bound by them, not
+// by HBM bandwidth.  Here every row is read and written with coalesced
+// streaming accesses, and the per-row atomics are LDS atomics.
+//
+// Build side (gq_join_build, large build inputs):
+//   k_rp_hist     per hist tile (16384 rows), histogram of the region ids of
+//                 the kept rows (predicates pass, key non-NULL); region = top
+//                 pbits of fmix64(key ^ kRegionSeed)
+//   k_rp_scan     exclusive scan of the (region, tile) counts, region-major
+//                 (decoupled look-back): where each tile's rows of each region
+//                 start, and the region offsets
+//   k_rp_scatter  each hist tile in sub-tiles of 2048 rows: rows staged in
+//                 LDS, ordered by region in LDS, then written region by region
+//                 with coalesced stores: build keys and build row ids grouped by
+//                 region (order inside a region is unspecified)
+// Probe side (gq_pipeline when the only group key is the probe key): the same
+// three kernels, the payload of a row being its aggregate inputs (one 64-bit
+// product expression per SUM/MIN/MAX, and a non-NULL mask where an input can
+// be NULL), then
+//   k_rj_plan     per region p, the number of sub-regions S_p so that each holds
+//                 at most kpr build rows, and per-XCD work lists of
+//                 (region, sub-region) items
+//   k_rj_join     persistent: a workgroup takes an item (p, s), inserts the build
+//                 keys of region p that fall in sub-region s into an LDS table
+//                 (counting duplicates: a key's build multiplicity weights its
+//                 matches), streams the probe tuples of region p through it,
+//                 accumulating the matches of sub-region s in LDS, and writes
+//                 its matched groups to the output (one atomic per item for the
+//                 output range).
+// Region p is queued on XCD p % 8 (workgroups are dispatched to XCDs
+// round-robin), so the S_p workgroups that re-read region p's tuples share one
+// L2.  A workgroup whose queue is empty takes items from the other queues, so
+// every item is processed whatever the placement.
+#include "agg.h"
+#include "radix.h"
+
+namespace gq {
+namespace {
+
+constexpr int kRpBlock = 256;
+constexpr int kRpSub = 1024;                     // rows per sub-tile
+constexpr int kRpRows = kRpSub / kRpBlock;       // rows per thread per sub-tile
+constexpr int kRpSubs = 16;                      // sub-tiles per hist tile
+constexpr int kRpTile = kRpSub * kRpSubs;        // 16384 rows per hist tile
+constexpr int kRpMaxStage = 8;                   // distinct input columns staged in LDS
+constexpr int kRjBlock = 1024;
+constexpr int kRjMaxVals = 2;                    // value words per probe tuple
+constexpr int kRjUnroll = 8;                     // tuples per thread per round in k_rj_join
+
+__device__ __forceinline__ uint32_t region_of(uint64_t h, int pbits) {
+  return pbits ? (uint32_t)(h >> (64 - pbits)) : 0u;
+}
+__device__ __forceinline__ uint32_t subregion_of(uint64_t h, int pbits, uint32_t S) {
+  return S > 1 ? (uint32_t)__umul64hi(h << pbits, (uint64_t)S) : 0u;
+}
+
+struct RpArgs {
+  int64_t n;               // input rows
+  int64_t ntiles;          // hist tiles
+  int32_t pbits;           // P = 1 << pbits regions
+  int32_t npreds;
+  int32_t probe;           // 0: build side (payload = row id), 1: probe side (aggregate inputs)
+  int32_t nv;              // probe: value words per tuple
+  int32_t need_nn;         // probe: tuples carry a non-NULL mask
+  int32_t naggs;
+  int32_t nst;             // staged input columns (predicates and key first, then values)
+  int32_t nst_hist;        // of which the histogram pass needs the first nst_hist
+  int32_t key_st;          // staged index of the key column
+  int32_t in_bytes;        // LDS bytes of the staged input of one sub-tile
+  DCol st[kRpMaxStage];
+  int32_t st_off[kRpMaxStage];   // LDS byte offset of staged column j
+  int32_t pred_st[GQ_MAX_PREDS];
+  int32_t val_st[kMaxVals];      // staged index of aggregate value column v
+  DPred preds[GQ_MAX_PREDS];
+  AggPlan ap;
+  int32_t vagg[kRjMaxVals];      // probe: aggregate whose input is value word j
+  uint32_t* counts;        // [p * ntiles + tile]
+  uint32_t* starts;        // exclusive scan of counts
+  uint64_t* okey;          // region hashes of the keys
+  int32_t* orow;           // build
+  uint64_t* oval;          // probe: value word j of tuple i at oval[j * ocap + i]
+  uint8_t* onn;            // probe: non-NULL mask (bit i = aggregate i)
+  int64_t ocap;
+};
+
+// Copy rows [sbase, sbase + kRpSub) (those below n) of the first nst staged
+// columns into LDS with 16-byte global-to-LDS loads (no register round trip:
+// every load of the sub-tile is in flight at once); slices that are not
+// 16-byte aligned, and the ragged end of a column, are copied byte by byte.
+// The caller waits and synchronises the block before reading.
+__device__ __forceinline__ void rp_stage(const RpArgs& a, int nst, int64_t sbase, uint8_t* s_in) {
+  const int64_t left = a.n - sbase;
+  const int nrows = left < kRpSub ? (int)left : kRpSub;
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  for (int j = 0; j < nst; ++j) {
+    const DCol& c = a.st[j];
+    const int w = type_width(c.type);
+    uint8_t* dst = s_in + a.st_off[j];
+    const uint8_t* src = c.data + sbase * w;
+    const int nb = nrows * w;
+    int done = 0;
+    if (c.align >= 16) {
+      const int nfull = nb >> 4;
+      for (int ch0 = wave * kWave; ch0 < nfull; ch0 += kRpBlock) {
+        if (ch0 + lane < nfull)
+          __builtin_amdgcn_global_load_lds(
+              (const __attribute__((address_space(1))) void*)(src + (size_t)(ch0 + lane) * 16),
+              (__attribute__((address_space(3))) void*)(dst + (size_t)ch0 * 16), 16, 0, 0);
+      }
+      done = nfull << 4;
+    }
+    for (int b = done + threadIdx.x; b < nb; b += kRpBlock) dst[b] = src[b];
+  }
+}
+
+// The kRpRows rows r = i * 256 + threadIdx.x of a staged column; one type
+// dispatch for all of them.
+__device__ __forceinline__ void lds_rows(const uint8_t* base, int type, int64_t (&v)[kRpRows]) {
+  const int t = threadIdx.x;
+  switch (type) {
+    case GQ_I8:
+#pragma unroll
+      for (int i = 0; i < kRpRows; ++i) v[i] = reinterpret_cast<const int8_t*>(base)[i * kRpBlock + t];
+      break;
+    case GQ_I16:
+#pragma unroll
+      for (int i = 0; i < kRpRows; ++i) v[i] = reinterpret_cast<const int16_t*>(base)[i * kRpBlock + t];
+      break;
+    case GQ_I32:
+#pragma unroll
+      for (int i = 0; i < kRpRows; ++i) v[i] = reinterpret_cast<const int32_t*>(base)[i * kRpBlock + t];
+      break;
+    default:
+#pragma unroll
+      for (int i = 0; i < kRpRows; ++i) v[i] = reinterpret_cast<const int64_t*>(base)[i * kRpBlock + t];
+      break;
+  }
+}
+
+// Rows r = i * 256 + threadIdx.x of the staged sub-tile at sbase: mask of the
+// kept ones (predicates pass, key non-NULL) and their keys.  Column-major: each
+// predicate is applied to all rows of the thread before the next.
+__device__ __forceinline__ uint32_t rp_rows_keep(const RpArgs& a, const uint8_t* s_in, int64_t sbase, int nrows,
+                                                 int64_t (&key)[kRpRows]) {
+  uint32_t keep = 0;
+#pragma unroll
+  for (int i = 0; i < kRpRows; ++i)
+    if (i * kRpBlock + (int)threadIdx.x < nrows) keep |= 1u << i;
+  for (int p = 0; p < a.npreds; ++p) {
+    const int j = a.pred_st[p];
+    const DCol& c = a.st[j];
+    int64_t v[kRpRows];
+    lds_rows(s_in + a.st_off[j], c.type, v);
+    const int64_t lo = a.preds[p].lo, hi = a.preds[p].hi;
+    if (a.preds[p].op == GQ_RANGE) {
+#pragma unroll
+      for (int i = 0; i < kRpRows; ++i)
+        if (v[i] < lo || v[i] > hi) keep &= ~(1u << i);
+    } else {
+#pragma unroll
+      for (int i = 0; i < kRpRows; ++i)
+        if (v[i] == lo) keep &= ~(1u << i);
+    }
+    if (c.valid) {
+#pragma unroll
+      for (int i = 0; i < kRpRows; ++i)
+        if (!valid_one(c, sbase + i * kRpBlock + threadIdx.x)) keep &= ~(1u << i);
+    }
+  }
+  const DCol& kc = a.st[a.key_st];
+  lds_rows(s_in + a.st_off[a.key_st], kc.type, key);
+  if (kc.valid) {
+#pragma unroll
+    for (int i = 0; i < kRpRows; ++i)
+      if (!valid_one(kc, sbase + i * kRpBlock + threadIdx.x)) keep &= ~(1u << i);
+  }
+  return keep;
+}
+
+// Aggregate input (product expression) of aggregate ag for the thread's rows.
+__device__ __forceinline__ void rp_rows_value(const RpArgs& a, const DAgg& ag, const uint8_t* s_in,
+                                              uint64_t (&x)[kRpRows]) {
+#pragma unroll
+  for (int i = 0; i < kRpRows; ++i) x[i] = 1;
+  for (int f = 0; f < ag.nf; ++f) {
+    const DFactor& fa = ag.f[f];
+    const uint64_t k = (uint64_t)fa.k;
+    if (fa.kind == GQ_F_CONST) {
+#pragma unroll
+      for (int i = 0; i < kRpRows; ++i) x[i] *= k;
+      continue;
+    }
+    const int j = a.val_st[fa.v];
+    int64_t v[kRpRows];
+    lds_rows(s_in + a.st_off[j], a.st[j].type, v);
+    if (fa.kind == GQ_F_COL) {
+#pragma unroll
+      for (int i = 0; i < kRpRows; ++i) x[i] *= (uint64_t)v[i];
+    } else if (fa.kind == GQ_F_K_MINUS_COL) {
+#pragma unroll
+      for (int i = 0; i < kRpRows; ++i) x[i] *= k - (uint64_t)v[i];
+    } else {
+#pragma unroll
+      for (int i = 0; i < kRpRows; ++i) x[i] *= k + (uint64_t)v[i];
+    }
+  }
+}
+
+__global__ __launch_bounds__(kRpBlock) void k_rp_hist(const RpArgs a) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t s_raw[];
+  const int P = 1 << a.pbits;
+  uint32_t* s_hist = reinterpret_cast<uint32_t*>(s_raw);
+  uint8_t* s_in = s_raw + align_up((size_t)P * 4, 16);
+  for (int i = threadIdx.x; i < P; i += kRpBlock) s_hist[i] = 0;
+  const int64_t tile = blockIdx.x;
+  for (int sub = 0; sub < kRpSubs; ++sub) {
+    const int64_t sbase = tile * kRpTile + (int64_t)sub * kRpSub;
+    if (sbase >= a.n) break;
+    const int nrows = a.n - sbase < kRpSub ? (int)(a.n - sbase) : kRpSub;
+    __syncthreads();  // previous sub-tile's rows read
+    rp_stage(a, a.nst_hist, sbase, s_in);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    int64_t key[kRpRows];
+    const uint32_t keep = rp_rows_keep(a, s_in, sbase, nrows, key);
+#pragma unroll
+    for (int i = 0; i < kRpRows; ++i)
+      if ((keep >> i) & 1u) atomicAdd(&s_hist[region_of(region_hash((uint64_t)key[i]), a.pbits)], 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < P; i += kRpBlock) a.counts[(int64_t)i * a.ntiles + tile] = s_hist[i];
+}
+
+// Exclusive scan of counts[0..m) (32-bit; the total fits because m counts rows
+// of a batch of fewer than 2^32 rows) into starts[], region offsets[q] =
+// starts[q * ntiles], offsets[P] = *total = the sum.
+template <int BLOCK, int ITEMS>
+__global__ __launch_bounds__(BLOCK) void k_rp_scan(const uint32_t* counts, int64_t m, uint32_t* starts, int64_t ntiles,
+                                                   int64_t P, int64_t* offsets, int64_t* total, uint32_t* ticket,
+                                                   uint64_t* status, int64_t nblocks) {
+  constexpr int NW = BLOCK / kWave;
+  __shared__ uint32_t s_tile;
+  __shared__ int64_t s_wave[NW];
+  __shared__ int64_t s_excl;
+  if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
+  __syncthreads();
+  const int64_t tile = s_tile;
+  const int64_t i0 = (tile * BLOCK + threadIdx.x) * ITEMS;
+  uint32_t c[ITEMS];
+  int64_t tsum = 0;
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k) {
+    c[k] = (i0 + k < m) ? counts[i0 + k] : 0u;
+    tsum += c[k];
+  }
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  int64_t incl = tsum;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int64_t y = __shfl_up(incl, o, kWave);
+    if (lane >= o) incl += y;
+  }
+  if (lane == kWave - 1) s_wave[wave] = incl;
+  __syncthreads();
+  int64_t bpre = 0, btot = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    if (w < wave) bpre += s_wave[w];
+    btot += s_wave[w];
+  }
+  if (wave == 0) {
+    const int64_t e = lookback_exclusive(status, tile, btot);
+    if (lane == 0) s_excl = e;
+  }
+  __syncthreads();
+  int64_t run = s_excl + bpre + incl - tsum;
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k) {
+    const int64_t i = i0 + k;
+    if (i < m) {
+      starts[i] = (uint32_t)run;
+      if (i % ntiles == 0) offsets[i / ntiles] = run;
+    }
+    run += c[k];
+  }
+  if (tile == nblocks - 1 && threadIdx.x == 0) {
+    offsets[P] = s_excl + btot;
+    if (total) *total = s_excl + btot;
+  }
+}
+
+// LDS layout of k_rp_scatter (dynamic): base[P], cnt[P] (u32), the staged
+// input (in_bytes), then per row of the sub-tile: hash (u64), payload (build:
+// u32 row; probe: nv u64 words, then a non-NULL mask byte), pp (u32: region
+// << 16 | rank in region, ~0 = dropped), src (u16).
+__host__ __device__ inline size_t rp_scatter_lds(int P, int in_bytes, int probe, int nv, int need_nn) {
+  size_t b = align_up((size_t)2 * P * 4, 16) + align_up((size_t)in_bytes, 16) + (size_t)kRpSub * 8;
+  b += probe ? (size_t)kRpSub * 8 * nv + (need_nn ? kRpSub : 0) : (size_t)kRpSub * 4;
+  b = align_up(b, 16);
+  b += (size_t)kRpSub * 4 + (size_t)kRpSub * 2;
+  return b;
+}
+
+__global__ __launch_bounds__(kRpBlock) void k_rp_scatter(const RpArgs a) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t s_raw[];
+  const int P = 1 << a.pbits;
+  uint32_t* s_base = reinterpret_cast<uint32_t*>(s_raw);
+  uint32_t* s_cnt = s_base + P;
+  uint8_t* s_in = s_raw + align_up((size_t)2 * P * 4, 16);
+  uint64_t* s_key = reinterpret_cast<uint64_t*>(s_in + align_up((size_t)a.in_bytes, 16));
+  uint8_t* pay = reinterpret_cast<uint8_t*>(s_key + kRpSub);
+  uint64_t* s_val = reinterpret_cast<uint64_t*>(pay);                  // probe
+  uint32_t* s_row = reinterpret_cast<uint32_t*>(pay);                  // build
+  uint8_t* s_nn = pay + (size_t)kRpSub * 8 * a.nv;                     // probe
+  const size_t off = a.probe ? (size_t)kRpSub * 8 * a.nv + (a.need_nn ? kRpSub : 0) : (size_t)kRpSub * 4;
+  uint32_t* s_pp = reinterpret_cast<uint32_t*>(pay + align_up(off, 16));
+  uint16_t* s_src = reinterpret_cast<uint16_t*>(s_pp + kRpSub);
+  __shared__ uint32_t s_wsum[kRpBlock / kWave];
+  __shared__ uint32_t s_total;
+
+  const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+  for (int q = threadIdx.x; q < P; q += kRpBlock) s_base[q] = a.starts[(int64_t)q * a.ntiles + tile];
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int per = (P + kRpBlock - 1) / kRpBlock;
+
+  for (int sub = 0; sub < kRpSubs; ++sub) {
+    const int64_t sbase = tile * kRpTile + (int64_t)sub * kRpSub;
+    if (sbase >= a.n) break;
+    const int nrows = a.n - sbase < kRpSub ? (int)(a.n - sbase) : kRpSub;
+    for (int q = threadIdx.x; q < P; q += kRpBlock) s_cnt[q] = 0;
+    rp_stage(a, a.nst, sbase, s_in);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    // Rows r = i * 256 + t of the sub-tile: keep, region, payload.
+    {
+      int64_t key[kRpRows];
+      const uint32_t keep = rp_rows_keep(a, s_in, sbase, nrows, key);
+      uint64_t hv[kRpRows];
+#pragma unroll
+      for (int i = 0; i < kRpRows; ++i) {
+        const int r = i * kRpBlock + threadIdx.x;
+        if (!((keep >> i) & 1u)) {
+          s_pp[r] = 0xffffffffu;
+          continue;
+        }
+        hv[i] = region_hash((uint64_t)key[i]);
+        const uint32_t p = region_of(hv[i], a.pbits);
+        s_pp[r] = (p << 16) | atomicAdd(&s_cnt[p], 1u);
+        s_key[r] = hv[i];
+      }
+      if (a.probe) {
+#pragma unroll
+        for (int v = 0; v < kRjMaxVals; ++v) {
+          if (v >= a.nv) break;
+          uint64_t x[kRpRows];
+          rp_rows_value(a, a.ap.aggs[a.vagg[v]], s_in, x);
+#pragma unroll
+          for (int i = 0; i < kRpRows; ++i) s_val[(size_t)v * kRpSub + i * kRpBlock + threadIdx.x] = x[i];
+        }
+        if (a.need_nn) {
+          uint32_t nnm[kRpRows];
+#pragma unroll
+          for (int i = 0; i < kRpRows; ++i) nnm[i] = 0;
+          for (int g = 0; g < a.naggs; ++g) {
+            const DAgg& ag = a.ap.aggs[g];
+            if (ag.op == GQ_COUNT_STAR) continue;
+            uint32_t ok = 0xffffffffu;
+            for (int f = 0; f < ag.nf; ++f) {
+              if (ag.f[f].kind == GQ_F_CONST) continue;
+              const DCol& c = a.ap.vals[ag.f[f].v];
+              if (!c.valid) continue;
+#pragma unroll
+              for (int i = 0; i < kRpRows; ++i)
+                if (!valid_one(c, sbase + i * kRpBlock + threadIdx.x)) ok &= ~(1u << i);
+            }
+#pragma unroll
+            for (int i = 0; i < kRpRows; ++i) nnm[i] |= ((ok >> i) & 1u) << g;
+          }
+#pragma unroll
+          for (int i = 0; i < kRpRows; ++i) s_nn[i * kRpBlock + threadIdx.x] = (uint8_t)nnm[i];
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < kRpRows; ++i)
+          s_row[i * kRpBlock + threadIdx.x] = (uint32_t)(sbase + i * kRpBlock + threadIdx.x);
+      }
+    }
+    __syncthreads();
+    // Exclusive scan of s_cnt over the P regions: thread t owns regions
+    // [t * per, (t + 1) * per).
+    uint32_t mysum = 0;
+    for (int j = 0; j < per; ++j) {
+      const int q = threadIdx.x * per + j;
+      if (q < P) mysum += s_cnt[q];
+    }
+    uint32_t incl = mysum;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const uint32_t y = __shfl_up(incl, o, kWave);
+      if (lane >= o) incl += y;
+    }
+    if (lane == kWave - 1) s_wsum[wave] = incl;
+    __syncthreads();
+    uint32_t wpre = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kRpBlock / kWave; ++w) {
+      if (w < wave) wpre += s_wsum[w];
+      tot += s_wsum[w];
+    }
+    uint32_t run = wpre + incl - mysum;
+    uint32_t cnt_own[4] = {0u, 0u, 0u, 0u};  // per <= 4 for P <= 1024
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int q = threadIdx.x * per + j;
+      if (j < per && q < P) {
+        cnt_own[j] = s_cnt[q];
+        s_cnt[q] = run;  // now the sub-tile-local start of region q
+        run += cnt_own[j];
+      }
+    }
+    if (threadIdx.x == 0) s_total = tot;
+    __syncthreads();
+    // Inverse permutation: sorted position -> row of the sub-tile.
+#pragma unroll
+    for (int i = 0; i < kRpRows; ++i) {
+      const int r = i * kRpBlock + threadIdx.x;
+      const uint32_t pp = s_pp[r];
+      if (pp != 0xffffffffu) s_src[s_cnt[pp >> 16] + (pp & 0xffffu)] = (uint16_t)r;
+    }
+    __syncthreads();
+    const int total = (int)s_total;
+    for (int i = threadIdx.x; i < total; i += kRpBlock) {
+      const int r = s_src[i];
+      const uint32_t q = s_pp[r] >> 16;
+      const int64_t g = (int64_t)s_base[q] + (i - (int)s_cnt[q]);
+      if (g < a.ocap) {
+        a.okey[g] = s_key[r];
+        if (a.probe) {
+#pragma unroll
+          for (int v = 0; v < kRjMaxVals; ++v)
+            if (v < a.nv) a.oval[(size_t)v * a.ocap + g] = s_val[(size_t)v * kRpSub + r];
+          if (a.need_nn) a.onn[g] = s_nn[r];
+        } else {
+          a.orow[g] = (int32_t)s_row[r];
+        }
+      }
+    }
+    __syncthreads();
+    // Advance each region's write position past this sub-tile's rows.
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int q = threadIdx.x * per + j;
+      if (j < per && q < P) s_base[q] += cnt_own[j];
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Join and aggregation of (region, sub-region) items
+// ---------------------------------------------------------------------------
+struct RjJoinArgs {
+  int32_t pbits;
+  int32_t P;
+  int32_t lcap;             // LDS table slots (plus one extra slot for the key EMPTY)
+  int32_t kpr;              // build rows per sub-region at most
+  int32_t nacc;
+  int32_t naggs;
+  int32_t nv;
+  int32_t need_nn;
+  AggPlan ap;
+  int32_t vword[GQ_MAX_AGGS];   // value word of aggregate i in the tuple, -1 if none
+  const uint64_t* bkey;     // build keys grouped by region
+  const int64_t* boff;      // P + 1
+  const uint64_t* tkey;     // probe tuples grouped by region
+  const uint64_t* tval;     // nv words per tuple, word j at tval[j * tcap + i]
+  const uint8_t* tnn;
+  int64_t tcap;
+  const int64_t* toff;      // P + 1
+  uint32_t* S;              // per region: sub-regions
+  uint32_t* qstart;         // per region: first item of the region in its XCD queue
+  uint32_t* qcount;         // per queue: items
+  uint32_t* qticket;        // per queue: next item
+  int32_t sorted;           // write the unsigned sort key column
+  int32_t key_type;
+  OCol out[1 + GQ_MAX_AGGS];
+  OCol sortkey;
+  int64_t out_cap;
+  int64_t* d_count;
+  int32_t* dev_status;
+};
+
+// Per region, the number of sub-regions, and the per-XCD work lists (region
+// p in queue p % 8, items in region order).  One block of 1024 threads, one
+// region per thread (P <= 1024).
+__global__ __launch_bounds__(1024) void k_rj_plan(const RjJoinArgs a) {
+  __shared__ uint32_t s_S[1024];
+  const int p = threadIdx.x;
+  uint32_t S = 0;
+  if (p < a.P) {
+    const int64_t nb = a.boff[p + 1] - a.boff[p];
+    S = (uint32_t)((nb + a.kpr - 1) / a.kpr);
+    if (S < 1) S = 1;
+    a.S[p] = S;
+  }
+  s_S[p] = S;
+  __syncthreads();
+  if (p < a.P) {
+    uint32_t before = 0;
+    for (int r = p % kXcds; r < p; r += kXcds) before += s_S[r];
+    a.qstart[p] = before;
+  }
+  if (p < kXcds) {
+    uint32_t tot = 0;
+    for (int r = p; r < a.P; r += kXcds) tot += s_S[r];
+    a.qcount[p] = tot;
+    a.qticket[p] = 0;
+  }
+  if (p == 0) *a.d_count = 0;
+}
+
+// LDS slot of a region hash: its low 32 bits scaled to the table (the high
+// bits chose the region and sub-region).
+__device__ __forceinline__ uint32_t rj_slot(uint64_t h, int lcap) {
+  return (uint32_t)(((uint64_t)(uint32_t)h * (uint64_t)lcap) >> 32);
+}
+
+__device__ __forceinline__ int rj_find_insert(uint64_t* s_keys, int lcap, uint64_t key) {
+  uint32_t s = rj_slot(key, lcap);
+  for (int probe = 0; probe < lcap; ++probe) {
+    const uint64_t kv = s_keys[s];
+    if (kv == key) return (int)s;
+    if (kv == kEmpty) {
+      const uint64_t prev =
+          atomicCAS((unsigned long long*)&s_keys[s], (unsigned long long)kEmpty, (unsigned long long)key);
+      if (prev == kEmpty || prev == key) return (int)s;
+    }
+    s = (s + 1 == (uint32_t)lcap) ? 0u : s + 1;
+  }
+  return -1;
+}
+
+__device__ __forceinline__ int rj_find(const uint64_t* s_keys, int lcap, uint64_t key) {
+  uint32_t s = rj_slot(key, lcap);
+  for (int probe = 0; probe < lcap; ++probe) {
+    const uint64_t kv = s_keys[s];
+    if (kv == key) return (int)s;
+    if (kv == kEmpty) return -1;
+    s = (s + 1 == (uint32_t)lcap) ? 0u : s + 1;
+  }
+  return -1;
+}
+
+// LDS of k_rj_join: keys[lcap + 1] (u64), acc[(lcap + 1) * nacc] (u64),
+// mult[lcap + 1] (u32).  Slot lcap holds the key EMPTY (all ones).
+__host__ __device__ inline size_t rj_join_lds(int lcap, int nacc) {
+  return (size_t)(lcap + 1) * (8 + 8 * (size_t)nacc + 4);
+}
+
+__device__ __forceinline__ void rj_write(const OCol& o, int64_t g, int64_t v) {
+  switch (o.type) {
+    case GQ_I8: o.data[g] = (uint8_t)v; break;
+    case GQ_I16: reinterpret_cast<int16_t*>(o.data)[g] = (int16_t)v; break;
+    case GQ_I32: reinterpret_cast<int32_t*>(o.data)[g] = (int32_t)v; break;
+    default: reinterpret_cast<int64_t*>(o.data)[g] = v; break;
+  }
+}
+
+__device__ __forceinline__ void rj_valid(const OCol& o, int64_t g, bool ok) {
+  if (!o.valid) return;
+  const uint32_t bit = 1u << (g & 31);
+  if (ok) atomicOr(&o.valid[g >> 5], bit);
+  else atomicAnd(&o.valid[g >> 5], ~bit);
+}
+
+__global__ __launch_bounds__(kRjBlock) void k_rj_join(const RjJoinArgs a) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t s_raw[];
+  const int L = a.lcap;
+  uint64_t* s_keys = reinterpret_cast<uint64_t*>(s_raw);
+  uint64_t* s_acc = s_keys + (L + 1);
+  uint32_t* s_mult = reinterpret_cast<uint32_t*>(s_acc + (size_t)(L + 1) * a.nacc);
+  __shared__ int32_t s_p, s_s;
+  __shared__ uint32_t s_S;
+  __shared__ uint32_t s_wcnt[kRjBlock / kWave];
+  __shared__ int64_t s_obase;
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int home = (int)(blockIdx.x % kXcds);
+  int qi = 0;
+  while (qi < kXcds) {
+    const int q = (home + qi) % kXcds;
+    if (threadIdx.x == 0) {
+      const uint32_t t = atomicAdd(&a.qticket[q], 1u);
+      int32_t p = -1, s = 0;
+      if (t < a.qcount[q]) {
+        // Regions of queue q: q, q + 8, ...; the last one whose first item <= t.
+        int lo = 0, hi = (a.P - 1 - q) / kXcds + 1;  // hi: number of regions in the queue
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (a.qstart[q + mid * kXcds] <= t) lo = mid; else hi = mid;
+        }
+        p = q + lo * kXcds;
+        s = (int32_t)(t - a.qstart[p]);
+      }
+      s_p = p;
+      s_s = s;
+      s_S = p >= 0 ? a.S[p] : 0u;
+    }
+    __syncthreads();
+    const int p = s_p, s = s_s;
+    const uint32_t S = s_S;
+    if (p < 0) {
+      ++qi;
+      __syncthreads();
+      continue;
+    }
+    // 1. Clear the table.
+    for (int i = threadIdx.x; i <= L; i += kRjBlock) {
+      s_keys[i] = kEmpty;
+      s_mult[i] = 0;
+    }
+    for (int i = threadIdx.x; i < (L + 1) * a.nacc; i += kRjBlock)
+      s_acc[i] = word_identity(a.ap.wop[i % a.nacc]);
+    __syncthreads();
+    // 2. Build keys of sub-region s, kRjUnroll per thread per round so that
+    // the loads of a round are in flight together.
+    const int64_t b0 = a.boff[p], b1 = a.boff[p + 1];
+    for (int64_t base = b0; base < b1; base += (int64_t)kRjBlock * kRjUnroll) {
+      uint64_t key[kRjUnroll];
+#pragma unroll
+      for (int u = 0; u < kRjUnroll; ++u) {
+        const int64_t i = base + (int64_t)u * kRjBlock + threadIdx.x;
+        key[u] = i < b1 ? a.bkey[i] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < kRjUnroll; ++u) {
+        const int64_t i = base + (int64_t)u * kRjBlock + threadIdx.x;
+        if (i >= b1 || subregion_of(key[u], a.pbits, S) != (uint32_t)s) continue;
+        const int slot = key[u] == kEmpty ? L : rj_find_insert(s_keys, L, key[u]);
+        if (slot < 0) {
+          atomicOr(a.dev_status, GQ_DEV_TABLE_FULL);
+          continue;
+        }
+        atomicAdd(&s_mult[slot], 1u);
+      }
+    }
+    __syncthreads();
+    // 3. Probe tuples of sub-region s, kRjUnroll per thread per round.
+    const int64_t t0 = a.toff[p], t1 = a.toff[p + 1];
+    for (int64_t base = t0; base < t1; base += (int64_t)kRjBlock * kRjUnroll) {
+      // All loads of the round first (values too, matched or not: they are
+      // contiguous and mostly L2 hits), then the LDS probes.
+      uint64_t key[kRjUnroll];
+      uint64_t xv[kRjUnroll][kRjMaxVals];
+#pragma unroll
+      for (int u = 0; u < kRjUnroll; ++u) {
+        const int64_t i = base + (int64_t)u * kRjBlock + threadIdx.x;
+        key[u] = i < t1 ? a.tkey[i] : 0;
+#pragma unroll
+        for (int v = 0; v < kRjMaxVals; ++v) xv[u][v] = (i < t1 && v < a.nv) ? a.tval[(size_t)v * a.tcap + i] : 0;
+      }
+      int slot[kRjUnroll];
+#pragma unroll
+      for (int u = 0; u < kRjUnroll; ++u) {
+        const int64_t i = base + (int64_t)u * kRjBlock + threadIdx.x;
+        slot[u] = -1;
+        if (i < t1 && subregion_of(key[u], a.pbits, S) == (uint32_t)s)
+          slot[u] = key[u] == kEmpty ? (s_mult[L] ? L : -1) : rj_find(s_keys, L, key[u]);
+      }
+      // Weighted updates, one aggregate at a time over the round's tuples.
+      uint64_t w[kRjUnroll];
+      uint32_t nnm[kRjUnroll];
+#pragma unroll
+      for (int u = 0; u < kRjUnroll; ++u) {
+        w[u] = slot[u] >= 0 ? s_mult[slot[u]] : 0;
+        const int64_t i = base + (int64_t)u * kRjBlock + threadIdx.x;
+        nnm[u] = (a.need_nn && slot[u] >= 0) ? a.tnn[i] : 0xffu;
+        if (slot[u] >= 0) atomicAdd((unsigned long long*)&s_acc[(size_t)slot[u] * a.nacc], (unsigned long long)w[u]);
+      }
+      for (int g = 0; g < a.naggs; ++g) {
+        const DAgg& ag = a.ap.aggs[g];
+        const int op = ag.op;
+        if (op == GQ_COUNT_STAR) continue;
+        const int vw = a.vword[g];
+        const int word = ag.word, cword = ag.cword;
+#pragma unroll
+        for (int u = 0; u < kRjUnroll; ++u) {
+          if (slot[u] < 0 || !((nnm[u] >> g) & 1u)) continue;
+          uint64_t* acc = s_acc + (size_t)slot[u] * a.nacc;
+          const uint64_t x = vw == 0 ? xv[u][0] : xv[u][kRjMaxVals - 1];
+          if (op == GQ_SUM) atomicAdd((unsigned long long*)&acc[word], (unsigned long long)(x * w[u]));
+          else if (op == GQ_COUNT) atomicAdd((unsigned long long*)&acc[word], (unsigned long long)w[u]);
+          else if (op == GQ_MIN) atomicMin((long long*)&acc[word], (long long)x);
+          else atomicMax((long long*)&acc[word], (long long)x);
+          if (cword >= 0) atomicAdd((unsigned long long*)&acc[cword], (unsigned long long)w[u]);
+        }
+      }
+    }
+    __syncthreads();
+    // 4. Matched groups (count word non-zero) to the output, in slot order.
+    uint32_t mine = 0;
+    for (int i = threadIdx.x; i <= L; i += kRjBlock) mine += s_acc[(size_t)i * a.nacc] != 0;
+    const uint32_t wtot = wave_sum(mine);
+    if (lane == 0) s_wcnt[wave] = wtot;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t tot = 0;
+      for (int w = 0; w < kRjBlock / kWave; ++w) tot += s_wcnt[w];
+      const int64_t base = tot ? (int64_t)atomicAdd((unsigned long long*)a.d_count, (unsigned long long)tot) : 0;
+      if (tot && base + tot > a.out_cap) atomicOr(a.dev_status, GQ_DEV_CAPACITY);
+      s_obase = base;
+    }
+    __syncthreads();
+    int64_t run = s_obase;
+    for (int c0 = 0; c0 <= L; c0 += kRjBlock) {
+      const int i = c0 + threadIdx.x;
+      const bool occ = i <= L && s_acc[(size_t)i * a.nacc] != 0;
+      const uint64_t m = ballot(occ);
+      if (lane == 0) s_wcnt[wave] = (uint32_t)__popcll(m);
+      __syncthreads();
+      uint32_t wpre = 0, ctot = 0;
+#pragma unroll
+      for (int w = 0; w < kRjBlock / kWave; ++w) {
+        if (w < wave) wpre += s_wcnt[w];
+        ctot += s_wcnt[w];
+      }
+      if (occ) {
+        const int64_t g = run + wpre + rank_in(m);
+        if (g < a.out_cap) {
+          // Slot L holds the key whose region hash is all ones.
+          const uint64_t key = region_unhash(s_keys[i]);
+          rj_write(a.out[0], g, (int64_t)key);
+          rj_valid(a.out[0], g, true);
+          if (a.sorted) reinterpret_cast<uint64_t*>(a.sortkey.data)[g] = key ^ (1ull << 63);
+          const uint64_t* acc = s_acc + (size_t)i * a.nacc;
+          for (int j = 0; j < a.naggs; ++j) {
+            const DAgg& ag = a.ap.aggs[j];
+            int64_t v = (int64_t)acc[ag.word];
+            bool ok = true;
+            if ((ag.op == GQ_SUM || ag.op == GQ_MIN || ag.op == GQ_MAX) && ag.cword >= 0) ok = acc[ag.cword] != 0;
+            if (!ok) v = 0;
+            rj_write(a.out[1 + j], g, v);
+            rj_valid(a.out[1 + j], g, ok);
+          }
+        }
+      }
+      run += ctot;
+      __syncthreads();
+    }
+  }
+}
+
+// Staged input columns: predicate columns and the key first (the histogram
+// pass reads only those), then aggregate value columns; each distinct column
+// once.  Returns false when they do not fit the staging limits.
+struct StageBuilder {
+  RpArgs& a;
+  bool ok = true;
+  int add(const DCol& c) {
+    for (int j = 0; j < a.nst; ++j)
+      if (a.st[j].data == c.data && a.st[j].type == c.type && a.st[j].valid == c.valid && a.st[j].voff == c.voff)
+        return j;
+    if (a.nst == kRpMaxStage) {
+      ok = false;
+      return 0;
+    }
+    a.st[a.nst] = c;
+    a.st_off[a.nst] = a.in_bytes;
+    a.in_bytes += (int)align_up((size_t)kRpSub * type_width(c.type), 16);
+    return a.nst++;
+  }
+};
+
+constexpr size_t kRpMaxLds = 80 * 1024;  // two partition workgroups per CU
+
+constexpr int kScanBlock = 256, kScanItems = 16;
+
+// Histogram, scan and scatter of one side; a.counts/starts/okey... set by the
+// caller except the workspace, allocated here.  offsets: P + 1 int64.
+int rp_run(gq_ctx* ctx, RpArgs& a, int64_t* offsets, int64_t* total, hipStream_t stream) {
+  const int64_t P = 1ll << a.pbits;
+  a.ntiles = (a.n + kRpTile - 1) / kRpTile;
+  if (a.ntiles == 0) {
+    // No rows: every offset 0.
+    int rc = launch_fill_u32(ctx, offsets, 0u, 2 * (P + 1), stream);
+    if (rc) return rc;
+    if (total) rc = launch_fill_u32(ctx, total, 0u, 2, stream);
+    return rc;
+  }
+  const int64_t m = a.ntiles * P;
+  constexpr int STILE = kScanBlock * kScanItems;
+  const int64_t nscan = (m + STILE - 1) / STILE;
+  Scratch ws(ctx, stream);
+  const size_t off_counts = 256;
+  const size_t off_starts = off_counts + align_up((size_t)m * 4, 256);
+  const size_t off_status = off_starts + align_up((size_t)m * 4, 256);
+  const size_t bytes = off_status + align_up((size_t)nscan * 8, 256);
+  if (!ws.get(bytes)) return set_error(ctx, GQ_ERR_NOMEM, "radix join: partition workspace allocation failed");
+  a.counts = ws.as<uint32_t>(off_counts);
+  a.starts = ws.as<uint32_t>(off_starts);
+  uint32_t* ticket = ws.as<uint32_t>(0);
+  uint64_t* status = ws.as<uint64_t>(off_status);
+  int rc = launch_fill_u32(ctx, ticket, 0u, 1, stream);
+  if (rc) return rc;
+  rc = launch_fill_u32(ctx, status, 0u, 2 * nscan, stream);
+  if (rc) return rc;
+  const size_t lds_hist = align_up((size_t)P * 4, 16) + (size_t)a.st_off[a.nst_hist - 1] +
+                         align_up((size_t)kRpSub * type_width(a.st[a.nst_hist - 1].type), 16);
+  GQ_LAUNCH(ctx, a.probe ? "rp_hist_probe" : "rp_hist_build", k_rp_hist, dim3((unsigned)a.ntiles), dim3(kRpBlock),
+            lds_hist, stream, a);
+  GQ_LAUNCH_CHECK(ctx);
+  GQ_LAUNCH(ctx, a.probe ? "rp_scan_probe" : "rp_scan_build", (k_rp_scan<kScanBlock, kScanItems>),
+            dim3((unsigned)nscan), dim3(kScanBlock), 0, stream, (const uint32_t*)a.counts, m, a.starts, a.ntiles, P,
+            offsets, total, ticket, status, nscan);
+  GQ_LAUNCH_CHECK(ctx);
+  const size_t lds = rp_scatter_lds((int)P, a.in_bytes, a.probe, a.nv, a.need_nn);
+  GQ_LAUNCH(ctx, a.probe ? "rp_scatter_probe" : "rp_scatter_build", k_rp_scatter, dim3((unsigned)a.ntiles),
+            dim3(kRpBlock), lds, stream, a);
+  GQ_LAUNCH_CHECK(ctx);
+  return GQ_OK;
+}
+
+}  // namespace
+
+int rj_choose_pbits(int64_t build_rows) {
+  // Regions of about 2 * kRjNominalKpr build rows (half of them kept by a
+  // typical predicate), between 256 and 1024 regions.
+  int pbits = 8;
+  while (pbits < 10 && ((int64_t)1 << pbits) * 2 * kRjNominalKpr < build_rows) ++pbits;
+  return pbits;
+}
+
+// Staging plan of the build side; false when it does not fit.
+static bool rj_build_plan(RpArgs& a, const gq_batch* build, int32_t key_col, const gq_pred* preds, int npreds,
+                          int pbits) {
+  std::memset(&a, 0, sizeof(a));
+  a.n = build->nrows;
+  a.pbits = pbits;
+  a.npreds = npreds;
+  a.probe = 0;
+  StageBuilder sb{a};
+  for (int p = 0; p < npreds; ++p) {
+    a.preds[p] = DPred{preds[p].col, preds[p].op, preds[p].lo, preds[p].hi};
+    a.pred_st[p] = sb.add(make_dcol(build->cols[preds[p].col]));
+  }
+  a.key_st = sb.add(make_dcol(build->cols[key_col]));
+  a.nst_hist = a.nst;
+  return sb.ok && rp_scatter_lds(1 << pbits, a.in_bytes, 0, 0, 0) <= kRpMaxLds;
+}
+
+bool rj_build_fits(const gq_batch* build, int32_t key_col, const gq_pred* preds, int npreds, int pbits) {
+  RpArgs a;
+  return rj_build_plan(a, build, key_col, preds, npreds, pbits);
+}
+
+int rj_build(gq_ctx* ctx, const gq_batch* build, int32_t key_col, const gq_pred* preds, int npreds,
+             gq_join_table* t, hipStream_t stream) {
+  RpArgs a;
+  if (!rj_build_plan(a, build, key_col, preds, npreds, t->rj_pbits))
+    return set_error(ctx, GQ_ERR_UNSUPPORTED, "radix join: build staging does not fit");
+  a.okey = t->rj_key;
+  a.orow = t->rj_row;
+  a.ocap = build->nrows;
+  return rp_run(ctx, a, t->rj_off, &t->hdr->nrows, stream);
+}
+
+// Staging plan and value words of the probe side; false when it does not fit.
+static bool rj_probe_plan(RpArgs& r, int32_t (&vword)[GQ_MAX_AGGS], const gq_batch* in, int32_t probe_key,
+                          const gq_pred* preds, int npreds, const AggPlan& ap, int pbits) {
+  std::memset(&r, 0, sizeof(r));
+  r.n = in->nrows;
+  r.pbits = pbits;
+  r.npreds = npreds;
+  r.probe = 1;
+  r.ap = ap;
+  r.naggs = ap.naggs;
+  StageBuilder sb{r};
+  for (int p = 0; p < npreds; ++p) {
+    r.preds[p] = DPred{preds[p].col, preds[p].op, preds[p].lo, preds[p].hi};
+    r.pred_st[p] = sb.add(make_dcol(in->cols[preds[p].col]));
+  }
+  r.key_st = sb.add(make_dcol(in->cols[probe_key]));
+  r.nst_hist = r.nst;
+  for (int v = 0; v < ap.nvals; ++v) r.val_st[v] = sb.add(ap.vals[v]);
+  for (int i = 0; i < ap.naggs; ++i) {
+    vword[i] = -1;
+    const int op = ap.aggs[i].op;
+    if (op == GQ_SUM || op == GQ_MIN || op == GQ_MAX) {
+      if (r.nv == kRjMaxVals) return false;
+      r.vagg[r.nv] = i;
+      vword[i] = r.nv++;
+    }
+    if (op != GQ_COUNT_STAR)
+      for (int f = 0; f < ap.aggs[i].nf; ++f)
+        if (ap.aggs[i].f[f].kind != GQ_F_CONST && ap.vals[ap.aggs[i].f[f].v].valid) r.need_nn = 1;
+  }
+  return sb.ok && rp_scatter_lds(1 << pbits, r.in_bytes, 1, r.nv, r.need_nn) <= kRpMaxLds;
+}
+
+bool rj_usable(const gq_join_table* t, const gq_batch* in, int32_t probe_key, const gq_pred* preds, int npreds,
+               const AggPlan& ap) {
+  if (!t || !t->rj_key) return false;
+  if (in->nrows >= ((int64_t)1 << 32)) return false;
+  RpArgs r;
+  int32_t vword[GQ_MAX_AGGS];
+  if (!rj_probe_plan(r, vword, in, probe_key, preds, npreds, ap, t->rj_pbits)) return false;
+  const int lcap = rj_lcap(ap.nacc);
+  if (lcap < 1024) return false;
+  // Sub-regions per region stay few when every build row is kept.
+  const int64_t per_region = t->build_rows >> t->rj_pbits;
+  return per_region <= (int64_t)16 * rj_kpr(lcap);
+}
+
+int rj_lcap(int nacc) {
+  const size_t per = 8 + 8 * (size_t)nacc + 4;
+  return (int)(kRjLdsBytes / per) - 1;
+}
+
+int rj_kpr(int lcap) { return (int)((int64_t)lcap * 13 / 20); }  // load factor 0.65
+
+int rj_groupjoin(gq_ctx* ctx, const gq_batch* in, int32_t probe_key, const gq_pred* preds, int npreds,
+                 const AggPlan& ap, const gq_join_table* t, const CompactArgs& ca, int64_t* d_groups,
+                 hipStream_t stream) {
+  const int pbits = t->rj_pbits;
+  const int64_t P = 1ll << pbits;
+  RpArgs r;
+  RjJoinArgs j;
+  std::memset(&j, 0, sizeof(j));
+  if (!rj_probe_plan(r, j.vword, in, probe_key, preds, npreds, ap, pbits))
+    return set_error(ctx, GQ_ERR_UNSUPPORTED, "radix join: probe staging does not fit");
+  const int64_t n = in->nrows;
+  const int64_t cap = n > 0 ? n : 1;
+  Scratch ws(ctx, stream);
+  const size_t off_key = 256;
+  const size_t off_val = off_key + align_up((size_t)cap * 8, 256);
+  const size_t off_nn = off_val + align_up((size_t)cap * 8 * (r.nv > 0 ? r.nv : 1), 256);
+  const size_t off_toff = off_nn + align_up(r.need_nn ? (size_t)cap : 1, 256);
+  const size_t off_S = off_toff + align_up((size_t)(P + 1) * 8, 256);
+  const size_t off_qs = off_S + align_up((size_t)P * 4, 256);
+  const size_t off_q = off_qs + align_up((size_t)P * 4, 256);
+  const size_t bytes = off_q + 256;
+  if (!ws.get(bytes)) return set_error(ctx, GQ_ERR_NOMEM, "radix join: probe workspace allocation failed");
+  r.okey = ws.as<uint64_t>(off_key);
+  r.oval = ws.as<uint64_t>(off_val);
+  r.onn = ws.as<uint8_t>(off_nn);
+  r.ocap = cap;
+  int64_t* toff = ws.as<int64_t>(off_toff);
+  int rc = rp_run(ctx, r, toff, nullptr, stream);
+  if (rc) return rc;
+
+  j.pbits = pbits;
+  j.P = (int32_t)P;
+  j.nacc = ap.nacc;
+  j.lcap = rj_lcap(ap.nacc);
+  j.kpr = rj_kpr(j.lcap);
+  j.naggs = ap.naggs;
+  j.nv = r.nv;
+  j.need_nn = r.need_nn;
+  j.ap = ap;
+  j.bkey = t->rj_key;
+  j.boff = t->rj_off;
+  j.tkey = r.okey;
+  j.tval = r.oval;
+  j.tnn = r.onn;
+  j.tcap = cap;
+  j.toff = toff;
+  j.S = ws.as<uint32_t>(off_S);
+  j.qstart = ws.as<uint32_t>(off_qs);
+  j.qcount = ws.as<uint32_t>(off_q);
+  j.qticket = ws.as<uint32_t>(off_q + 64);
+  j.sorted = ca.sortkey.data != nullptr;
+  j.sortkey = ca.sortkey;
+  j.key_type = ca.out[0].type;
+  for (int i = 0; i <= ap.naggs; ++i) j.out[i] = ca.out[i];
+  j.out_cap = ca.out_cap;
+  j.d_count = d_groups;
+  j.dev_status = ctx->d_status;
+  GQ_LAUNCH(ctx, "rj_plan", k_rj_plan, dim3(1), dim3(1024), 0, stream, j);
+  GQ_LAUNCH_CHECK(ctx);
+  int lds_max = 0;
+  GQ_HIP_CHECK(ctx, hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device));
+  if ((size_t)lds_max < rj_join_lds(j.lcap, j.nacc) + 256)
+    return set_error(ctx, GQ_ERR_UNSUPPORTED, "radix join: device LDS per workgroup too small");
+  int dev_cus = 256;
+  (void)hipDeviceGetAttribute(&dev_cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
+  GQ_LAUNCH(ctx, "rj_join", k_rj_join, dim3((unsigned)dev_cus), dim3(kRjBlock), rj_join_lds(j.lcap, j.nacc), stream,
+            j);
+  GQ_LAUNCH_CHECK(ctx);
+  return GQ_OK;
+}
+
+}  // namespace gq

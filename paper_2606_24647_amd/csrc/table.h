@@ -233,4 +233,15 @@ struct gq_join_table {
   int32_t key_type = GQ_I64;
   int32_t device = 0;
   bool acc_dirty = false;     // accumulators used by an earlier group-join
+  // Probe index (keys/meta/rows): built by gq_join_build for small build
+  // inputs, else on first use from the partitioned rows below.
+  bool index_built = false;
+  int32_t lf_milli = 500;     // load factor of the index, times 1000
+  // Partitioned build side (large build inputs): kept rows' keys and row ids
+  // grouped by region (top rj_pbits bits of the region hash), region r in
+  // [rj_off[r], rj_off[r + 1]).  NULL when the build input is small.
+  int32_t rj_pbits = 0;
+  uint64_t* rj_key = nullptr;
+  int32_t* rj_row = nullptr;
+  int64_t* rj_off = nullptr;
 };

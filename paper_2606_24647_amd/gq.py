@@ -75,7 +75,7 @@ class GqAgg(C.Structure):
 
 
 class GqJoinOpts(C.Structure):
-    _fields_ = [("load_factor", C.c_float), ("acc_slots", C.c_int32)]
+    _fields_ = [("load_factor", C.c_float), ("acc_slots", C.c_int32), ("regions_log2", C.c_int32)]
 
 
 class GqGroupbyOpts(C.Structure):
@@ -377,10 +377,10 @@ class Context:
         return out, offs
 
     def join_build(self, table: DevTable, keys, preds=(), load_factor: float = 0.0,
-                   acc_slots: int = 0, stream=None) -> "JoinTable":
+                   acc_slots: int = 0, regions_log2: int = 0, stream=None) -> "JoinTable":
         k, nk = _ints(keys)
         p, np_ = _preds(preds)
-        opts = GqJoinOpts(load_factor, acc_slots)
+        opts = GqJoinOpts(load_factor, acc_slots, regions_log2)
         h = C.c_void_p()
         ib = _BatchArg(table)
         self.check(_lib.gq_join_build(self.h, ib.ref, k, nk, p, np_, C.byref(opts),
