@@ -53,6 +53,11 @@ def source_hash(*paths):
     return h.hexdigest()[:16]
 
 
+# Every library source: a counter summary is stale once any of them changed.
+KERNEL_SOURCES = sorted(os.path.relpath(p, ROOT) for ext in ("hip", "h")
+                        for p in __import__("glob").glob(os.path.join(ROOT, "paper_2606_24647_amd", "csrc", f"*.{ext}")))
+
+
 def traffic_for(kernel_name, sources, launches_per_step=1):
     """HBM bytes per launch from a committed rocprofv3 counter summary, or None
     when the summary is missing or the kernel's sources changed since."""
@@ -138,14 +143,24 @@ def run_c2(torch, gq, devgen, ctx, steps, warmup, lf):
 
 
 def c2_bytes(r):
-    """Algorithmic bytes of the whole step and of the fused fact pass."""
+    """Algorithmic bytes of the whole step, and per launch of the kernels that
+    can dominate it (name -> bytes one launch must move at least)."""
     dim_read = DIM_ROWS * (8 + 4)                # pkey, date
     inserts = r["kept_dim"] * 16
     fact_read = FACT_ROWS * (8 + 8 + 8 + 4)      # fkey, price, disc, date
     probes = r["kept_fact"] * 16
     aggs = r["matched"] * 16
     out = r["ngroups"] * (8 + 8 + 8)             # key, sum, count
-    return dim_read + inserts + fact_read + probes + aggs + out, fact_read + probes + aggs
+    total = dim_read + inserts + fact_read + probes + aggs + out
+    tuples = r["kept_fact"] * 16                 # radix path: (key hash, revenue) per kept fact row
+    per_kernel = {
+        "groupjoin": fact_read + probes + aggs,                  # direct path: fused probe + aggregate
+        "rp_scatter_probe": fact_read + tuples,                  # read the fact columns, write the tuples
+        "rp_hist_probe": FACT_ROWS * (8 + 4),                    # key and predicate columns
+        "rj_join": tuples + r["kept_dim"] * 8 + out,             # tuples and build keys in, groups out
+        "rp_scatter_build": dim_read + r["kept_dim"] * 12,       # dim columns in, (hash, row) out
+    }
+    return total, per_kernel
 
 
 # ---------------------------------------------------------------------------
@@ -412,7 +427,7 @@ def main():
     if args.only in ("batched", "serving"):
         args.steps, args.warmup = 1, 0
     c2 = run_c2(torch, gq, devgen, ctx, args.steps, args.warmup, args.load_factor)
-    total_bytes, fused_bytes = c2_bytes(c2)
+    total_bytes, kernel_bytes = c2_bytes(c2)
     ms = c2["ms_per_step"]
     rows = FACT_ROWS + DIM_ROWS
 
@@ -420,15 +435,13 @@ def main():
     dom = max(kern.items(), key=lambda kv: kv[1][0])
     dom_name, (dom_ms, dom_launches) = dom
     dom_avg = dom_ms / dom_launches
-    per_launch = {"groupjoin": fused_bytes}.get(dom_name)
+    per_launch = kernel_bytes.get(dom_name)
     roof = None
     if per_launch is not None:
         achieved = per_launch / (dom_avg * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / PEAK_GBS, 4),
-                "traffic": traffic_for(dom_name, ["paper_2606_24647_amd/csrc/groupby.hip",
-                                                  "paper_2606_24647_amd/csrc/table.h",
-                                                  "paper_2606_24647_amd/csrc/common.h"]),
+                "traffic": traffic_for(dom_name, KERNEL_SOURCES),
                 "kernel": dom_name, "avg_launch_ms": round(dom_avg, 4), "alg_bytes_per_launch": per_launch}
 
     def section(name, fn):

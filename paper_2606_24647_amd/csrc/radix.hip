@@ -51,9 +51,14 @@ constexpr int kRpRows = kRpSub / kRpBlock;       // rows per thread per sub-tile
 constexpr int kRpSubs = 16;                      // sub-tiles per hist tile
 constexpr int kRpTile = kRpSub * kRpSubs;        // 16384 rows per hist tile
 constexpr int kRpMaxStage = 8;                   // distinct input columns staged in LDS
+// Cache policy of the staging loads: non-temporal, so the streamed input does
+// not push the partly written output lines out of L2.
+constexpr int kLoadNt = 2;
 constexpr int kRjBlock = 1024;
+constexpr int kRjPerCu = 1;                      // join workgroups per CU (the LDS table takes the CU)
 constexpr int kRjMaxVals = 2;                    // value words per probe tuple
-constexpr int kRjUnroll = 8;                     // tuples per thread per round in k_rj_join
+constexpr int kRjUnroll = 8;                     // build keys per thread per round in k_rj_join
+constexpr int kRjProbeUnroll = 6;                // probe tuples per thread per round in k_rj_join
 
 __device__ __forceinline__ uint32_t region_of(uint64_t h, int pbits) {
   return pbits ? (uint32_t)(h >> (64 - pbits)) : 0u;
@@ -84,9 +89,10 @@ struct RpArgs {
   int32_t vagg[kRjMaxVals];      // probe: aggregate whose input is value word j
   uint32_t* counts;        // [p * ntiles + tile]
   uint32_t* starts;        // exclusive scan of counts
-  uint64_t* okey;          // region hashes of the keys
+  uint64_t* okey;          // build: region hashes of the keys; probe: tuples
   int32_t* orow;           // build
-  uint64_t* oval;          // probe: value word j of tuple i at oval[j * ocap + i]
+  int32_t tw;              // probe: words per tuple (hash, then nv values), tuple i at okey[i * tw]
+  int32_t pad_tw;
   uint8_t* onn;            // probe: non-NULL mask (bit i = aggregate i)
   int64_t ocap;
 };
@@ -113,7 +119,7 @@ __device__ __forceinline__ void rp_stage(const RpArgs& a, int nst, int64_t sbase
         if (ch0 + lane < nfull)
           __builtin_amdgcn_global_load_lds(
               (const __attribute__((address_space(1))) void*)(src + (size_t)(ch0 + lane) * 16),
-              (__attribute__((address_space(3))) void*)(dst + (size_t)ch0 * 16), 16, 0, 0);
+              (__attribute__((address_space(3))) void*)(dst + (size_t)ch0 * 16), 16, 0, kLoadNt);
       }
       done = nfull << 4;
     }
@@ -442,13 +448,22 @@ __global__ __launch_bounds__(kRpBlock) void k_rp_scatter(const RpArgs a) {
       const uint32_t q = s_pp[r] >> 16;
       const int64_t g = (int64_t)s_base[q] + (i - (int)s_cnt[q]);
       if (g < a.ocap) {
-        a.okey[g] = s_key[r];
         if (a.probe) {
+          // Tuples are stored whole (hash and values side by side), so one
+          // tuple is one contiguous store.
+          uint64_t* t = a.okey + (size_t)g * a.tw;
+          if (a.nv == 1) {
+            typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+            *reinterpret_cast<u64x2*>(t) = u64x2{s_key[r], s_val[r]};
+          } else {
+            t[0] = s_key[r];
 #pragma unroll
-          for (int v = 0; v < kRjMaxVals; ++v)
-            if (v < a.nv) a.oval[(size_t)v * a.ocap + g] = s_val[(size_t)v * kRpSub + r];
+            for (int v = 0; v < kRjMaxVals; ++v)
+              if (v < a.nv) t[1 + v] = s_val[(size_t)v * kRpSub + r];
+          }
           if (a.need_nn) a.onn[g] = s_nn[r];
         } else {
+          a.okey[g] = s_key[r];
           a.orow[g] = (int32_t)s_row[r];
         }
       }
@@ -470,7 +485,7 @@ __global__ __launch_bounds__(kRpBlock) void k_rp_scatter(const RpArgs a) {
 struct RjJoinArgs {
   int32_t pbits;
   int32_t P;
-  int32_t lcap;             // LDS table slots (plus one extra slot for the key EMPTY)
+  int32_t lcap;             // LDS table slots; slot lcap holds the hash EMPTY
   int32_t kpr;              // build rows per sub-region at most
   int32_t nacc;
   int32_t naggs;
@@ -478,16 +493,15 @@ struct RjJoinArgs {
   int32_t need_nn;
   AggPlan ap;
   int32_t vword[GQ_MAX_AGGS];   // value word of aggregate i in the tuple, -1 if none
-  const uint64_t* bkey;     // build keys grouped by region
+  const uint64_t* bkey;     // build key hashes grouped by region
   const int64_t* boff;      // P + 1
-  const uint64_t* tkey;     // probe tuples grouped by region
-  const uint64_t* tval;     // nv words per tuple, word j at tval[j * tcap + i]
+  const uint64_t* tkey;     // probe tuple key hashes grouped by region
+  int32_t tw;               // words per probe tuple: hash, then nv values
+  int32_t pad_tw;
   const uint8_t* tnn;
-  int64_t tcap;
   const int64_t* toff;      // P + 1
-  uint32_t* S;              // per region: sub-regions
-  uint32_t* qstart;         // per region: first item of the region in its XCD queue
-  uint32_t* qcount;         // per queue: items
+  uint64_t* items;          // work items of all queues: region | sub-region << 16 | S << 40
+  uint32_t* qoff;           // kXcds + 1: queue q's items are items[qoff[q] .. qoff[q + 1])
   uint32_t* qticket;        // per queue: next item
   int32_t sorted;           // write the unsigned sort key column
   int32_t key_type;
@@ -498,32 +512,45 @@ struct RjJoinArgs {
   int32_t* dev_status;
 };
 
-// Per region, the number of sub-regions, and the per-XCD work lists (region
-// p in queue p % 8, items in region order).  One block of 1024 threads, one
-// region per thread (P <= 1024).
+constexpr uint64_t kNoItem = ~0ull;
+__device__ __forceinline__ uint32_t item_region(uint64_t it) { return (uint32_t)(it & 0xffffu); }
+__device__ __forceinline__ uint32_t item_sub(uint64_t it) { return (uint32_t)((it >> 16) & 0xffffffu); }
+__device__ __forceinline__ uint32_t item_nsub(uint64_t it) { return (uint32_t)(it >> 40); }
+
+// Per region, the number of sub-regions S_p, and the work items: region p's
+// S_p items in queue p % 8, queues one after another.  One block of 1024
+// threads, one region per thread (P <= 1024).
 __global__ __launch_bounds__(1024) void k_rj_plan(const RjJoinArgs a) {
   __shared__ uint32_t s_S[1024];
+  __shared__ uint32_t s_q[kXcds + 1];
   const int p = threadIdx.x;
   uint32_t S = 0;
   if (p < a.P) {
     const int64_t nb = a.boff[p + 1] - a.boff[p];
     S = (uint32_t)((nb + a.kpr - 1) / a.kpr);
     if (S < 1) S = 1;
-    a.S[p] = S;
   }
   s_S[p] = S;
+  __syncthreads();
+  if (p < kXcds) {
+    uint32_t tot = 0;
+    for (int r = p; r < a.P; r += kXcds) tot += s_S[r];
+    s_q[p + 1] = tot;
+  }
+  __syncthreads();
+  if (p == 0) {
+    s_q[0] = 0;
+    for (int q = 0; q < kXcds; ++q) s_q[q + 1] += s_q[q];
+  }
   __syncthreads();
   if (p < a.P) {
     uint32_t before = 0;
     for (int r = p % kXcds; r < p; r += kXcds) before += s_S[r];
-    a.qstart[p] = before;
+    const uint32_t base = s_q[p % kXcds] + before;
+    for (uint32_t j = 0; j < S; ++j) a.items[base + j] = (uint64_t)p | ((uint64_t)j << 16) | ((uint64_t)S << 40);
   }
-  if (p < kXcds) {
-    uint32_t tot = 0;
-    for (int r = p; r < a.P; r += kXcds) tot += s_S[r];
-    a.qcount[p] = tot;
-    a.qticket[p] = 0;
-  }
+  if (p <= kXcds) a.qoff[p] = s_q[p];
+  if (p < kXcds) a.qticket[p] = 0;
   if (p == 0) *a.d_count = 0;
 }
 
@@ -548,21 +575,13 @@ __device__ __forceinline__ int rj_find_insert(uint64_t* s_keys, int lcap, uint64
   return -1;
 }
 
-__device__ __forceinline__ int rj_find(const uint64_t* s_keys, int lcap, uint64_t key) {
-  uint32_t s = rj_slot(key, lcap);
-  for (int probe = 0; probe < lcap; ++probe) {
-    const uint64_t kv = s_keys[s];
-    if (kv == key) return (int)s;
-    if (kv == kEmpty) return -1;
-    s = (s + 1 == (uint32_t)lcap) ? 0u : s + 1;
-  }
-  return -1;
-}
-
-// LDS of k_rj_join: keys[lcap + 1] (u64), acc[(lcap + 1) * nacc] (u64),
-// mult[lcap + 1] (u32).  Slot lcap holds the key EMPTY (all ones).
+// LDS of k_rj_join: keys, accumulators and multiplicities of lcap table slots,
+// the slot of the hash EMPTY (index lcap) and 64 dump slots (one per lane:
+// updates of tuples without a match go there, so the update code has no
+// branches; their multiplicity stays 0).
+__host__ __device__ inline int rj_slots(int lcap) { return lcap + 1 + kWave; }
 __host__ __device__ inline size_t rj_join_lds(int lcap, int nacc) {
-  return (size_t)(lcap + 1) * (8 + 8 * (size_t)nacc + 4);
+  return (size_t)rj_slots(lcap) * (8 + 8 * (size_t)nacc + 4);
 }
 
 __device__ __forceinline__ void rj_write(const OCol& o, int64_t g, int64_t v) {
@@ -581,69 +600,73 @@ __device__ __forceinline__ void rj_valid(const OCol& o, int64_t g, bool ok) {
   else atomicAnd(&o.valid[g >> 5], ~bit);
 }
 
+constexpr int kRjChunks = 8;  // emission chunks of 1024 slots: lcap + 1 <= 8192
+
+// Next work item: queue q's ticket t (already taken) or, once q is used up,
+// tickets from the following queues.  Called by one thread.
+__device__ uint64_t rj_next(const RjJoinArgs& a, const uint32_t* s_qoff, int home, int& qi, uint32_t t) {
+  while (qi < kXcds) {
+    const int q = (home + qi) % kXcds;
+    if (t < s_qoff[q + 1] - s_qoff[q]) return a.items[s_qoff[q] + t];
+    if (++qi == kXcds) break;
+    t = atomicAdd(&a.qticket[(home + qi) % kXcds], 1u);
+  }
+  return kNoItem;
+}
+
 __global__ __launch_bounds__(kRjBlock) void k_rj_join(const RjJoinArgs a) {
   extern __shared__ __attribute__((aligned(16))) uint8_t s_raw[];
   const int L = a.lcap;
-  uint64_t* s_keys = reinterpret_cast<uint64_t*>(s_raw);
-  uint64_t* s_acc = s_keys + (L + 1);
-  uint32_t* s_mult = reinterpret_cast<uint32_t*>(s_acc + (size_t)(L + 1) * a.nacc);
-  __shared__ int32_t s_p, s_s;
-  __shared__ uint32_t s_S;
-  __shared__ uint32_t s_wcnt[kRjBlock / kWave];
-  __shared__ int64_t s_obase;
+  const int NS = rj_slots(L);
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const uint32_t dump = (uint32_t)(L + 1 + lane);
+  uint64_t* s_keys = reinterpret_cast<uint64_t*>(s_raw);
+  uint64_t* s_acc = s_keys + NS;
+  uint32_t* s_mult = reinterpret_cast<uint32_t*>(s_acc + (size_t)NS * a.nacc);
+  __shared__ uint64_t s_item;
+  __shared__ uint32_t s_qoff[kXcds + 1];
+  __shared__ uint32_t s_cc[kRjChunks][kRjBlock / kWave];
+  __shared__ int64_t s_obase;
   const int home = (int)(blockIdx.x % kXcds);
+  if (threadIdx.x <= kXcds) s_qoff[threadIdx.x] = a.qoff[threadIdx.x];
+  __syncthreads();
   int qi = 0;
-  while (qi < kXcds) {
-    const int q = (home + qi) % kXcds;
-    if (threadIdx.x == 0) {
-      const uint32_t t = atomicAdd(&a.qticket[q], 1u);
-      int32_t p = -1, s = 0;
-      if (t < a.qcount[q]) {
-        // Regions of queue q: q, q + 8, ...; the last one whose first item <= t.
-        int lo = 0, hi = (a.P - 1 - q) / kXcds + 1;  // hi: number of regions in the queue
-        while (hi - lo > 1) {
-          const int mid = (lo + hi) >> 1;
-          if (a.qstart[q + mid * kXcds] <= t) lo = mid; else hi = mid;
-        }
-        p = q + lo * kXcds;
-        s = (int32_t)(t - a.qstart[p]);
-      }
-      s_p = p;
-      s_s = s;
-      s_S = p >= 0 ? a.S[p] : 0u;
-    }
+  uint64_t cur = kNoItem;
+  if (threadIdx.x == 0) cur = rj_next(a, s_qoff, home, qi, atomicAdd(&a.qticket[home], 1u));
+  for (;;) {
+    if (threadIdx.x == 0) s_item = cur;
     __syncthreads();
-    const int p = s_p, s = s_s;
-    const uint32_t S = s_S;
-    if (p < 0) {
-      ++qi;
-      __syncthreads();
-      continue;
-    }
-    // 1. Clear the table.
-    for (int i = threadIdx.x; i <= L; i += kRjBlock) {
+    const uint64_t item = s_item;
+    if (item == kNoItem) break;
+    const uint32_t p = item_region(item), s = item_sub(item), S = item_nsub(item);
+    // The next ticket of the current queue, resolved after this item.
+    uint32_t tnext = 0;
+    if (threadIdx.x == 0 && qi < kXcds) tnext = atomicAdd(&a.qticket[(home + qi) % kXcds], 1u);
+
+    // 1. Clear the table (dump slots included).
+    for (int i = threadIdx.x; i < NS; i += kRjBlock) {
       s_keys[i] = kEmpty;
       s_mult[i] = 0;
     }
-    for (int i = threadIdx.x; i < (L + 1) * a.nacc; i += kRjBlock)
-      s_acc[i] = word_identity(a.ap.wop[i % a.nacc]);
+    for (int w = 0; w < a.nacc; ++w) {
+      const uint64_t id = word_identity(a.ap.wop[w]);
+      for (int i = threadIdx.x; i < NS; i += kRjBlock) s_acc[(size_t)i * a.nacc + w] = id;
+    }
     __syncthreads();
-    // 2. Build keys of sub-region s, kRjUnroll per thread per round so that
-    // the loads of a round are in flight together.
+    // 2. Build key hashes of sub-region s, counting duplicates.
     const int64_t b0 = a.boff[p], b1 = a.boff[p + 1];
     for (int64_t base = b0; base < b1; base += (int64_t)kRjBlock * kRjUnroll) {
-      uint64_t key[kRjUnroll];
+      uint64_t h[kRjUnroll];
 #pragma unroll
       for (int u = 0; u < kRjUnroll; ++u) {
         const int64_t i = base + (int64_t)u * kRjBlock + threadIdx.x;
-        key[u] = i < b1 ? a.bkey[i] : 0;
+        h[u] = a.bkey[i < b1 ? i : b1 - 1];
       }
 #pragma unroll
       for (int u = 0; u < kRjUnroll; ++u) {
         const int64_t i = base + (int64_t)u * kRjBlock + threadIdx.x;
-        if (i >= b1 || subregion_of(key[u], a.pbits, S) != (uint32_t)s) continue;
-        const int slot = key[u] == kEmpty ? L : rj_find_insert(s_keys, L, key[u]);
+        if (i >= b1 || subregion_of(h[u], a.pbits, S) != s) continue;
+        const int slot = h[u] == kEmpty ? L : rj_find_insert(s_keys, L, h[u]);
         if (slot < 0) {
           atomicOr(a.dev_status, GQ_DEV_TABLE_FULL);
           continue;
@@ -652,37 +675,68 @@ __global__ __launch_bounds__(kRjBlock) void k_rj_join(const RjJoinArgs a) {
       }
     }
     __syncthreads();
-    // 3. Probe tuples of sub-region s, kRjUnroll per thread per round.
+    // The next item, resolved while this one is probed.
+    if (threadIdx.x == 0) cur = rj_next(a, s_qoff, home, qi, tnext);
+    // 3. Probe tuples of sub-region s.  Per round, every load first, then the
+    // kRjProbeUnroll lookups of a thread advance together one probe step at a time.
     const int64_t t0 = a.toff[p], t1 = a.toff[p + 1];
-    for (int64_t base = t0; base < t1; base += (int64_t)kRjBlock * kRjUnroll) {
-      // All loads of the round first (values too, matched or not: they are
-      // contiguous and mostly L2 hits), then the LDS probes.
-      uint64_t key[kRjUnroll];
-      uint64_t xv[kRjUnroll][kRjMaxVals];
+    for (int64_t base = t0; base < t1; base += (int64_t)kRjBlock * kRjProbeUnroll) {
+      uint64_t h[kRjProbeUnroll];
+      uint64_t xv[kRjProbeUnroll][kRjMaxVals];
+      uint32_t nnm[kRjProbeUnroll];
+      uint32_t act = 0;
 #pragma unroll
-      for (int u = 0; u < kRjUnroll; ++u) {
+      for (int u = 0; u < kRjProbeUnroll; ++u) {
         const int64_t i = base + (int64_t)u * kRjBlock + threadIdx.x;
-        key[u] = i < t1 ? a.tkey[i] : 0;
+        const int64_t ic = i < t1 ? i : t1 - 1;
+        const uint64_t* tp = a.tkey + (size_t)ic * a.tw;
+        if (a.nv == 1) {
+          typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+          const u64x2 tv = *reinterpret_cast<const u64x2*>(tp);
+          h[u] = tv.x;
+          xv[u][0] = tv.y;
+          xv[u][kRjMaxVals - 1] = tv.y;
+        } else {
+          h[u] = tp[0];
 #pragma unroll
-        for (int v = 0; v < kRjMaxVals; ++v) xv[u][v] = (i < t1 && v < a.nv) ? a.tval[(size_t)v * a.tcap + i] : 0;
+          for (int v = 0; v < kRjMaxVals; ++v) xv[u][v] = v < a.nv ? tp[1 + v] : 0;
+        }
+        nnm[u] = a.need_nn ? a.tnn[ic] : 0xffu;
+        if (i < t1) act |= 1u << u;
       }
-      int slot[kRjUnroll];
+      uint32_t pos[kRjProbeUnroll];
+      int32_t res[kRjProbeUnroll];
 #pragma unroll
-      for (int u = 0; u < kRjUnroll; ++u) {
-        const int64_t i = base + (int64_t)u * kRjBlock + threadIdx.x;
-        slot[u] = -1;
-        if (i < t1 && subregion_of(key[u], a.pbits, S) == (uint32_t)s)
-          slot[u] = key[u] == kEmpty ? (s_mult[L] ? L : -1) : rj_find(s_keys, L, key[u]);
+      for (int u = 0; u < kRjProbeUnroll; ++u) {
+        res[u] = -1;
+        pos[u] = rj_slot(h[u], L);
+        if (subregion_of(h[u], a.pbits, S) != s) act &= ~(1u << u);
+        if (((act >> u) & 1u) && h[u] == kEmpty) {
+          res[u] = s_mult[L] ? L : -1;
+          act &= ~(1u << u);
+        }
       }
-      // Weighted updates, one aggregate at a time over the round's tuples.
-      uint64_t w[kRjUnroll];
-      uint32_t nnm[kRjUnroll];
+      for (int it = 0; act && it < L; ++it) {
+        uint64_t kv[kRjProbeUnroll];
 #pragma unroll
-      for (int u = 0; u < kRjUnroll; ++u) {
-        w[u] = slot[u] >= 0 ? s_mult[slot[u]] : 0;
-        const int64_t i = base + (int64_t)u * kRjBlock + threadIdx.x;
-        nnm[u] = (a.need_nn && slot[u] >= 0) ? a.tnn[i] : 0xffu;
-        if (slot[u] >= 0) atomicAdd((unsigned long long*)&s_acc[(size_t)slot[u] * a.nacc], (unsigned long long)w[u]);
+        for (int u = 0; u < kRjProbeUnroll; ++u) kv[u] = s_keys[pos[u]];
+#pragma unroll
+        for (int u = 0; u < kRjProbeUnroll; ++u) {
+          const bool on = (act >> u) & 1u;
+          const bool hit = kv[u] == h[u];
+          if (on && hit) res[u] = (int32_t)pos[u];
+          if (on && (hit || kv[u] == kEmpty)) act &= ~(1u << u);
+          pos[u] = pos[u] + 1 == (uint32_t)L ? 0u : pos[u] + 1;
+        }
+      }
+      // Updates: tuples without a match go to this lane's dump slot (weight 0).
+      uint32_t slot[kRjProbeUnroll];
+      uint64_t w[kRjProbeUnroll];
+#pragma unroll
+      for (int u = 0; u < kRjProbeUnroll; ++u) {
+        slot[u] = res[u] >= 0 ? (uint32_t)res[u] : dump;
+        w[u] = s_mult[slot[u]];
+        atomicAdd((unsigned long long*)&s_acc[(size_t)slot[u] * a.nacc], (unsigned long long)w[u]);
       }
       for (int g = 0; g < a.naggs; ++g) {
         const DAgg& ag = a.ap.aggs[g];
@@ -690,47 +744,62 @@ __global__ __launch_bounds__(kRjBlock) void k_rj_join(const RjJoinArgs a) {
         if (op == GQ_COUNT_STAR) continue;
         const int vw = a.vword[g];
         const int word = ag.word, cword = ag.cword;
+        if (op == GQ_SUM || op == GQ_COUNT) {
 #pragma unroll
-        for (int u = 0; u < kRjUnroll; ++u) {
-          if (slot[u] < 0 || !((nnm[u] >> g) & 1u)) continue;
-          uint64_t* acc = s_acc + (size_t)slot[u] * a.nacc;
-          const uint64_t x = vw == 0 ? xv[u][0] : xv[u][kRjMaxVals - 1];
-          if (op == GQ_SUM) atomicAdd((unsigned long long*)&acc[word], (unsigned long long)(x * w[u]));
-          else if (op == GQ_COUNT) atomicAdd((unsigned long long*)&acc[word], (unsigned long long)w[u]);
-          else if (op == GQ_MIN) atomicMin((long long*)&acc[word], (long long)x);
-          else atomicMax((long long*)&acc[word], (long long)x);
-          if (cword >= 0) atomicAdd((unsigned long long*)&acc[cword], (unsigned long long)w[u]);
+          for (int u = 0; u < kRjProbeUnroll; ++u) {
+            const uint64_t wk = ((nnm[u] >> g) & 1u) ? w[u] : 0;
+            const uint64_t x = vw == 0 ? xv[u][0] : xv[u][kRjMaxVals - 1];
+            uint64_t* acc = s_acc + (size_t)slot[u] * a.nacc;
+            atomicAdd((unsigned long long*)&acc[word], (unsigned long long)(op == GQ_SUM ? x * wk : wk));
+            if (cword >= 0) atomicAdd((unsigned long long*)&acc[cword], (unsigned long long)wk);
+          }
+        } else {
+#pragma unroll
+          for (int u = 0; u < kRjProbeUnroll; ++u) {
+            const bool ok = (nnm[u] >> g) & 1u;
+            const uint32_t sl = ok ? slot[u] : dump;
+            const uint64_t x = vw == 0 ? xv[u][0] : xv[u][kRjMaxVals - 1];
+            uint64_t* acc = s_acc + (size_t)sl * a.nacc;
+            if (op == GQ_MIN) atomicMin((long long*)&acc[word], (long long)x);
+            else atomicMax((long long*)&acc[word], (long long)x);
+            if (cword >= 0) atomicAdd((unsigned long long*)&acc[cword], (unsigned long long)(ok ? w[u] : 0));
+          }
         }
       }
     }
     __syncthreads();
-    // 4. Matched groups (count word non-zero) to the output, in slot order.
-    uint32_t mine = 0;
-    for (int i = threadIdx.x; i <= L; i += kRjBlock) mine += s_acc[(size_t)i * a.nacc] != 0;
-    const uint32_t wtot = wave_sum(mine);
-    if (lane == 0) s_wcnt[wave] = wtot;
+    // 4. Matched groups (count word non-zero) to the output, in slot order:
+    // per chunk of 1024 slots the wave counts, one output range for the item.
+    uint32_t occm = 0;
+    const int nchunks = (L + kRjBlock) / kRjBlock;  // chunks covering slots 0..L
+    for (int c = 0; c < nchunks; ++c) {
+      const int i = c * kRjBlock + threadIdx.x;
+      const bool occ = i <= L && s_acc[(size_t)i * a.nacc] != 0;
+      const uint64_t m = ballot(occ);
+      if (occ) occm |= 1u << c;
+      if (lane == 0) s_cc[c][wave] = (uint32_t)__popcll(m);
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
       uint32_t tot = 0;
-      for (int w = 0; w < kRjBlock / kWave; ++w) tot += s_wcnt[w];
+      for (int c = 0; c < nchunks; ++c)
+        for (int w = 0; w < kRjBlock / kWave; ++w) tot += s_cc[c][w];
       const int64_t base = tot ? (int64_t)atomicAdd((unsigned long long*)a.d_count, (unsigned long long)tot) : 0;
       if (tot && base + tot > a.out_cap) atomicOr(a.dev_status, GQ_DEV_CAPACITY);
       s_obase = base;
     }
     __syncthreads();
     int64_t run = s_obase;
-    for (int c0 = 0; c0 <= L; c0 += kRjBlock) {
-      const int i = c0 + threadIdx.x;
-      const bool occ = i <= L && s_acc[(size_t)i * a.nacc] != 0;
-      const uint64_t m = ballot(occ);
-      if (lane == 0) s_wcnt[wave] = (uint32_t)__popcll(m);
-      __syncthreads();
+    for (int c = 0; c < nchunks; ++c) {
       uint32_t wpre = 0, ctot = 0;
-#pragma unroll
       for (int w = 0; w < kRjBlock / kWave; ++w) {
-        if (w < wave) wpre += s_wcnt[w];
-        ctot += s_wcnt[w];
+        const uint32_t x = s_cc[c][w];
+        wpre += w < wave ? x : 0;
+        ctot += x;
       }
+      const int i = c * kRjBlock + threadIdx.x;
+      const bool occ = (occm >> c) & 1u;
+      const uint64_t m = ballot(occ);
       if (occ) {
         const int64_t g = run + wpre + rank_in(m);
         if (g < a.out_cap) {
@@ -752,14 +821,13 @@ __global__ __launch_bounds__(kRjBlock) void k_rj_join(const RjJoinArgs a) {
         }
       }
       run += ctot;
-      __syncthreads();
     }
   }
 }
 
 // Staged input columns: predicate columns and the key first (the histogram
 // pass reads only those), then aggregate value columns; each distinct column
-// once.  Returns false when they do not fit the staging limits.
+// once.  ok turns false when they do not fit the staging limits.
 struct StageBuilder {
   RpArgs& a;
   bool ok = true;
@@ -920,7 +988,9 @@ bool rj_usable(const gq_join_table* t, const gq_batch* in, int32_t probe_key, co
 
 int rj_lcap(int nacc) {
   const size_t per = 8 + 8 * (size_t)nacc + 4;
-  return (int)(kRjLdsBytes / per) - 1;
+  int l = (int)(kRjLdsBytes / per) - 1 - kWave;
+  if (l > kRjChunks * kRjBlock - 1) l = kRjChunks * kRjBlock - 1;
+  return l;
 }
 
 int rj_kpr(int lcap) { return (int)((int64_t)lcap * 13 / 20); }  // load factor 0.65
@@ -938,17 +1008,19 @@ int rj_groupjoin(gq_ctx* ctx, const gq_batch* in, int32_t probe_key, const gq_pr
   const int64_t n = in->nrows;
   const int64_t cap = n > 0 ? n : 1;
   Scratch ws(ctx, stream);
+  r.tw = 1 + r.nv;
   const size_t off_key = 256;
-  const size_t off_val = off_key + align_up((size_t)cap * 8, 256);
-  const size_t off_nn = off_val + align_up((size_t)cap * 8 * (r.nv > 0 ? r.nv : 1), 256);
+  const size_t off_nn = off_key + align_up((size_t)cap * 8 * r.tw, 256);
   const size_t off_toff = off_nn + align_up(r.need_nn ? (size_t)cap : 1, 256);
-  const size_t off_S = off_toff + align_up((size_t)(P + 1) * 8, 256);
-  const size_t off_qs = off_S + align_up((size_t)P * 4, 256);
-  const size_t off_q = off_qs + align_up((size_t)P * 4, 256);
+  // Work items: S_p = max(1, ceil(rows_p / kpr)) per region, so at most
+  // P + build_rows / kpr + 1 in all.
+  const int lcap = rj_lcap(ap.nacc);
+  const int64_t max_items = P + t->build_rows / rj_kpr(lcap) + 2;
+  const size_t off_items = off_toff + align_up((size_t)(P + 1) * 8, 256);
+  const size_t off_q = off_items + align_up((size_t)max_items * 8, 256);
   const size_t bytes = off_q + 256;
   if (!ws.get(bytes)) return set_error(ctx, GQ_ERR_NOMEM, "radix join: probe workspace allocation failed");
   r.okey = ws.as<uint64_t>(off_key);
-  r.oval = ws.as<uint64_t>(off_val);
   r.onn = ws.as<uint8_t>(off_nn);
   r.ocap = cap;
   int64_t* toff = ws.as<int64_t>(off_toff);
@@ -958,8 +1030,8 @@ int rj_groupjoin(gq_ctx* ctx, const gq_batch* in, int32_t probe_key, const gq_pr
   j.pbits = pbits;
   j.P = (int32_t)P;
   j.nacc = ap.nacc;
-  j.lcap = rj_lcap(ap.nacc);
-  j.kpr = rj_kpr(j.lcap);
+  j.lcap = lcap;
+  j.kpr = rj_kpr(lcap);
   j.naggs = ap.naggs;
   j.nv = r.nv;
   j.need_nn = r.need_nn;
@@ -967,13 +1039,11 @@ int rj_groupjoin(gq_ctx* ctx, const gq_batch* in, int32_t probe_key, const gq_pr
   j.bkey = t->rj_key;
   j.boff = t->rj_off;
   j.tkey = r.okey;
-  j.tval = r.oval;
+  j.tw = r.tw;
   j.tnn = r.onn;
-  j.tcap = cap;
   j.toff = toff;
-  j.S = ws.as<uint32_t>(off_S);
-  j.qstart = ws.as<uint32_t>(off_qs);
-  j.qcount = ws.as<uint32_t>(off_q);
+  j.items = ws.as<uint64_t>(off_items);
+  j.qoff = ws.as<uint32_t>(off_q);
   j.qticket = ws.as<uint32_t>(off_q + 64);
   j.sorted = ca.sortkey.data != nullptr;
   j.sortkey = ca.sortkey;
@@ -990,7 +1060,7 @@ int rj_groupjoin(gq_ctx* ctx, const gq_batch* in, int32_t probe_key, const gq_pr
     return set_error(ctx, GQ_ERR_UNSUPPORTED, "radix join: device LDS per workgroup too small");
   int dev_cus = 256;
   (void)hipDeviceGetAttribute(&dev_cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
-  GQ_LAUNCH(ctx, "rj_join", k_rj_join, dim3((unsigned)dev_cus), dim3(kRjBlock), rj_join_lds(j.lcap, j.nacc), stream,
+  GQ_LAUNCH(ctx, "rj_join", k_rj_join, dim3((unsigned)(dev_cus * kRjPerCu)), dim3(kRjBlock), rj_join_lds(j.lcap, j.nacc), stream,
             j);
   GQ_LAUNCH_CHECK(ctx);
   return GQ_OK;
