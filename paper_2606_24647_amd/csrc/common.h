@@ -291,6 +291,42 @@ __device__ __forceinline__ bool pred_pass(const DPred& p, int64_t v) {
   return p.op == GQ_RANGE ? (v >= p.lo && v <= p.hi) : (v != p.lo);
 }
 
+// Copy rows [sbase, sbase + nrows) of column c (nrows * width bytes) into LDS
+// at dst with 16-byte global-to-LDS loads issued by the whole block: no
+// register round trip, so every load of the block is in flight at once.
+// Slices that are not 16-byte aligned, and the bytes after the last whole
+// 16-byte chunk, are copied byte by byte.  dst is 16-byte aligned.  Returns
+// without waiting: the caller waits (s_waitcnt) and synchronises the block.
+template <int BLOCK>
+__device__ __forceinline__ void stage_col_lds(const DCol& c, int64_t sbase, int nrows, uint8_t* dst) {
+  const int w = type_width(c.type);
+  const uint8_t* src = c.data + sbase * w;
+  const int nb = nrows * w;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x & 63;
+  int done = 0;
+  if (c.align >= 16) {
+    const int nfull = nb >> 4;
+    for (int ch0 = wave * 64; ch0 < nfull; ch0 += BLOCK) {
+      if (ch0 + lane < nfull)
+        __builtin_amdgcn_global_load_lds(
+            (const __attribute__((address_space(1))) void*)(src + (size_t)(ch0 + lane) * 16),
+            (__attribute__((address_space(3))) void*)(dst + (size_t)ch0 * 16), 16, 0, 2 /* non-temporal */);
+    }
+    done = nfull << 4;
+  }
+  for (int b = done + threadIdx.x; b < nb; b += BLOCK) dst[b] = src[b];
+}
+
+// Value of row r of a column staged in LDS.
+__device__ __forceinline__ int64_t lds_value(const uint8_t* base, int r, int type) {
+  switch (type) {
+    case GQ_I8: return (int64_t)reinterpret_cast<const int8_t*>(base)[r];
+    case GQ_I16: return (int64_t)reinterpret_cast<const int16_t*>(base)[r];
+    case GQ_I32: return (int64_t)reinterpret_cast<const int32_t*>(base)[r];
+    default: return reinterpret_cast<const int64_t*>(base)[r];
+  }
+}
+
 // MurmurHash3 64-bit finaliser.
 __host__ __device__ __forceinline__ uint64_t fmix64(uint64_t k) {
   k ^= k >> 33;

@@ -1,22 +1,25 @@
 // gq_hash_partition: hash rows to partitions and write every partition
 // contiguously, rows in input order within each partition.
 //
-// Three kernels on the caller's stream:
-//  1. k_part_hist    per tile, an LDS histogram of partition ids, stored
+// Three kernels on the caller's stream, over hist tiles of 16384 rows cut into
+// sub-tiles of 1024 rows; each sub-tile's columns are first copied into LDS
+// with 16-byte global-to-LDS loads (every load of the sub-tile in flight at
+// once), and all row work reads LDS:
+//  1. k_part_hist    per hist tile, an LDS histogram of partition ids, stored
 //                    partition-major: counts[p * ntiles + tile].
 //  2. k_scan_counts  single-pass exclusive scan of that array (decoupled
 //                    look-back); entry (p, tile) becomes the output row where
 //                    tile's rows of partition p start.  Also writes offsets[].
-//  3. k_part_scatter per tile, a stable rank of each row within its partition:
-//                    rows are visited wave by wave in row order, lanes of a wave
-//                    holding 64 consecutive rows; lanes with the same partition
-//                    find each other with one ballot per bit of the partition id
-//                    and the lowest of them bumps the wave's LDS counter.  Every
-//                    column is then staged in LDS in partitioned order and
-//                    written out, consecutive lanes writing consecutive rows of
-//                    a partition.
-// The hash is recomputed in kernel 3 rather than stored: the key columns are
-// read again anyway because they are part of the output.
+//  3. k_part_scatter per sub-tile, a stable rank of each row within its
+//                    partition: wave w owns rows [256w, 256w + 256) of the
+//                    sub-tile in four steps of 64; lanes with the same partition
+//                    find each other with one ballot per bit of the partition
+//                    id and the lowest of them bumps the wave's LDS counter, so
+//                    ranks follow row order.  Then every column is written in
+//                    partitioned order from the staged copy, consecutive lanes
+//                    writing consecutive rows of a partition.
+// Consecutive hist tiles run on the same XCD (blocks are mapped to tiles per
+// XCD), so partial output lines of neighbouring tiles meet in its L2.
 #include "common.h"
 
 namespace gq {
@@ -39,7 +42,41 @@ struct PartArgs {
   OCol out[GQ_MAX_COLS];
   uint32_t* counts;  // nparts * ntiles
   int64_t* starts;   // nparts * ntiles, exclusive scan of counts
+  int32_t key_col[GQ_MAX_KEYS];   // column of cols[] holding key j
+  int32_t st_off[GQ_MAX_COLS];    // LDS offset of staged column j (scatter)
+  int32_t kst_off[GQ_MAX_KEYS];   // LDS offset of staged key j (histogram)
+  int32_t in_bytes;               // LDS bytes of the scatter's staged sub-tile
+  int32_t kin_bytes;              // LDS bytes of the histogram's staged keys
 };
+
+constexpr int kPBlock = 256;
+constexpr int kPSub = 1024;                  // rows per sub-tile
+constexpr int kPSubs = 16;                   // sub-tiles per hist tile
+constexpr int kPTile = kPSub * kPSubs;       // rows per hist tile
+constexpr int kPSteps = kPSub / kPBlock;     // rows per thread per sub-tile
+
+// Staged rows r0 + i * stride, i < kPSteps, of one column: one type dispatch.
+__device__ __forceinline__ void lds_rows_at(const uint8_t* base, int type, int r0, int stride,
+                                            int64_t (&v)[kPSteps]) {
+  switch (type) {
+    case GQ_I8:
+#pragma unroll
+      for (int i = 0; i < kPSteps; ++i) v[i] = reinterpret_cast<const int8_t*>(base)[r0 + i * stride];
+      break;
+    case GQ_I16:
+#pragma unroll
+      for (int i = 0; i < kPSteps; ++i) v[i] = reinterpret_cast<const int16_t*>(base)[r0 + i * stride];
+      break;
+    case GQ_I32:
+#pragma unroll
+      for (int i = 0; i < kPSteps; ++i) v[i] = reinterpret_cast<const int32_t*>(base)[r0 + i * stride];
+      break;
+    default:
+#pragma unroll
+      for (int i = 0; i < kPSteps; ++i) v[i] = reinterpret_cast<const int64_t*>(base)[r0 + i * stride];
+      break;
+  }
+}
 
 __device__ __forceinline__ int64_t rows_of(const PartArgs& a) {
   if (!a.d_n) return a.n;
@@ -47,58 +84,65 @@ __device__ __forceinline__ int64_t rows_of(const PartArgs& a) {
   return d < a.n ? d : a.n;
 }
 
-__device__ __forceinline__ uint32_t part_of_row(const PartArgs& a, int64_t r) {
-  if (a.digit) return (uint32_t)(((uint64_t)load_one(a.keys[0], r) >> a.shift) & (a.nparts - 1));
-  uint64_t h = a.seed;
-  for (int j = 0; j < a.nkeys; ++j) {
-    const DCol& c = a.keys[j];
-    uint64_t x = valid_one(c, r) ? (uint64_t)load_one(c, r) : 0;
-    h = fmix64(h ^ x);
-  }
-  return (uint32_t)mulhi64(h, a.nparts);
-}
-
-template <int ITEMS>
-__device__ __forceinline__ void part_of_items(const PartArgs& a, int64_t r0, int64_t n, uint32_t (&p)[ITEMS]) {
+// Partitions of the kPSteps staged rows r0 + i * stride (rows >= nrows get 0):
+// one type dispatch per key column for all of them.
+template <class KeyBase>
+__device__ __forceinline__ void part_of_rows(const PartArgs& a, int64_t sbase, int r0, int stride, int nrows,
+                                             KeyBase kbase, uint32_t (&p)[kPSteps]) {
+  uint64_t h[kPSteps];
   if (a.digit) {
-    int64_t v[ITEMS];
-    load_items<ITEMS>(a.keys[0], r0, n, v);
+    int64_t v[kPSteps];
+    lds_rows_at(kbase(0), a.keys[0].type, r0, stride, v);
 #pragma unroll
-    for (int k = 0; k < ITEMS; ++k) p[k] = (uint32_t)(((uint64_t)v[k] >> a.shift) & (a.nparts - 1));
+    for (int i = 0; i < kPSteps; ++i) p[i] = (uint32_t)(((uint64_t)v[i] >> a.shift) & (a.nparts - 1));
     return;
   }
-  uint64_t h[ITEMS];
 #pragma unroll
-  for (int k = 0; k < ITEMS; ++k) h[k] = a.seed;
+  for (int i = 0; i < kPSteps; ++i) h[i] = a.seed;
   for (int j = 0; j < a.nkeys; ++j) {
     const DCol& c = a.keys[j];
-    int64_t v[ITEMS];
-    load_items<ITEMS>(c, r0, n, v);
-    uint32_t vm = c.valid ? valid_items<ITEMS>(c, r0, n) : 0xffffffffu;
+    int64_t v[kPSteps];
+    lds_rows_at(kbase(j), c.type, r0, stride, v);
+    if (c.valid) {
 #pragma unroll
-    for (int k = 0; k < ITEMS; ++k) h[k] = fmix64(h[k] ^ (((vm >> k) & 1u) ? (uint64_t)v[k] : 0ull));
+      for (int i = 0; i < kPSteps; ++i) {
+        const int r = r0 + i * stride;
+        if (r < nrows && !valid_one(c, sbase + r)) v[i] = 0;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kPSteps; ++i) h[i] = fmix64(h[i] ^ (uint64_t)v[i]);
   }
 #pragma unroll
-  for (int k = 0; k < ITEMS; ++k) p[k] = (uint32_t)mulhi64(h[k], a.nparts);
+  for (int i = 0; i < kPSteps; ++i) p[i] = (uint32_t)mulhi64(h[i], a.nparts);
 }
 
-template <int BLOCK, int ITEMS>
-__global__ __launch_bounds__(BLOCK) void k_part_hist(const PartArgs a) {
-  constexpr int TILE = BLOCK * ITEMS;
-  __shared__ uint32_t s_hist[kPartMax];
+__global__ __launch_bounds__(kPBlock) void k_part_hist(const PartArgs a) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t s_raw[];
   const int P = (int)a.nparts;
-  for (int i = threadIdx.x; i < P; i += BLOCK) s_hist[i] = 0;
-  __syncthreads();
+  uint32_t* s_hist = reinterpret_cast<uint32_t*>(s_raw);
+  uint8_t* s_in = s_raw + align_up((size_t)P * 4, 16);
+  for (int i = threadIdx.x; i < P; i += kPBlock) s_hist[i] = 0;
   const int64_t tile = blockIdx.x;
   const int64_t n = rows_of(a);
-  const int64_t r0 = tile * TILE + (int64_t)threadIdx.x * ITEMS;
-  uint32_t p[ITEMS];
-  part_of_items<ITEMS>(a, r0, n, p);
+  auto kbase = [&](int j) { return (const uint8_t*)(s_in + a.kst_off[j]); };
+  for (int sub = 0; sub < kPSubs; ++sub) {
+    const int64_t sbase = tile * kPTile + (int64_t)sub * kPSub;
+    if (sbase >= n) break;
+    const int nrows = n - sbase < kPSub ? (int)(n - sbase) : kPSub;
+    __syncthreads();  // the previous sub-tile's keys are read
+    const int nk = a.digit ? 1 : a.nkeys;
+    for (int j = 0; j < nk; ++j) stage_col_lds<kPBlock>(a.keys[j], sbase, nrows, s_in + a.kst_off[j]);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    uint32_t pid[kPSteps];
+    part_of_rows(a, sbase, threadIdx.x, kPBlock, nrows, kbase, pid);
 #pragma unroll
-  for (int k = 0; k < ITEMS; ++k)
-    if (r0 + k < n) atomicAdd(&s_hist[p[k]], 1u);
+    for (int i = 0; i < kPSteps; ++i)
+      if (i * kPBlock + (int)threadIdx.x < nrows) atomicAdd(&s_hist[pid[i]], 1u);
+  }
   __syncthreads();
-  for (int i = threadIdx.x; i < P; i += BLOCK) a.counts[(int64_t)i * a.ntiles + tile] = s_hist[i];
+  for (int i = threadIdx.x; i < P; i += kPBlock) a.counts[(int64_t)i * a.ntiles + tile] = s_hist[i];
 }
 
 // Exclusive scan of counts[0..m) into starts[], with offsets[q] = starts[q * ntiles]
@@ -157,141 +201,188 @@ __global__ __launch_bounds__(BLOCK) void k_scan_counts(const uint32_t* counts, i
   if (tile == nblocks - 1 && threadIdx.x == 0) offsets[nparts] = s_excl + btot;
 }
 
-template <int BLOCK, int ITEMS, int PMAX>
-__global__ __launch_bounds__(BLOCK) void k_part_scatter(const PartArgs a) {
-  constexpr int TILE = BLOCK * ITEMS;
-  constexpr int NW = BLOCK / kWave;
-  __shared__ uint32_t s_whist[NW][PMAX];   // per-wave running counts, then wave-exclusive
-  __shared__ uint32_t s_pstart[PMAX];      // tile-local start of each partition
-  __shared__ int64_t s_gstart[PMAX];       // output row of the tile's first row of each partition
-  __shared__ __attribute__((aligned(16))) uint8_t s_stage[TILE * 8];
-  __shared__ uint16_t s_pid[TILE];
-  __shared__ uint32_t s_scan[BLOCK];
+// LDS of k_part_scatter (dynamic): staged columns (in_bytes), per-wave
+// counts [4][P] (u32), sub-tile starts [P + 1] (u32), write positions [P]
+// (i64), then per sorted position its partition and source row (u16 each).
+__host__ inline size_t part_scatter_lds(int P, int in_bytes) {
+  return align_up((size_t)in_bytes, 16) + align_up((size_t)4 * P * 4, 16) + align_up((size_t)(P + 1) * 4, 16) +
+         (size_t)P * 8 + (size_t)kPSub * 4;
+}
 
+__global__ __launch_bounds__(kPBlock) void k_part_scatter(const PartArgs a) {
+  constexpr int NW = kPBlock / kWave;
+  extern __shared__ __attribute__((aligned(16))) uint8_t s_raw[];
   const int P = (int)a.nparts;
+  uint8_t* s_in = s_raw;
+  uint32_t* s_whist = reinterpret_cast<uint32_t*>(s_raw + align_up((size_t)a.in_bytes, 16));
+  uint32_t* s_sub = reinterpret_cast<uint32_t*>(reinterpret_cast<uint8_t*>(s_whist) + align_up((size_t)4 * P * 4, 16));
+  int64_t* s_base = reinterpret_cast<int64_t*>(reinterpret_cast<uint8_t*>(s_sub) + align_up((size_t)(P + 1) * 4, 16));
+  uint16_t* s_pid = reinterpret_cast<uint16_t*>(s_base + P);
+  uint16_t* s_src = s_pid + kPSub;
+  __shared__ uint32_t s_wsum[NW];
+
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int64_t tbase = tile * TILE;
   const int64_t n = rows_of(a);
-  for (int i = threadIdx.x; i < NW * PMAX; i += BLOCK) (&s_whist[0][0])[i] = 0;
-  __syncthreads();
-
+  for (int q = threadIdx.x; q < P; q += kPBlock) s_base[q] = a.starts[(int64_t)q * a.ntiles + tile];
   int nbits = 0;
   while ((1 << nbits) < P) ++nbits;
+  auto kbase = [&](int j) { return (const uint8_t*)(s_in + a.st_off[a.key_col[j]]); };
+  const int per = (P + kPBlock - 1) / kPBlock;
 
-  // Rank pass: item k of lane l in wave w is row tbase + (w * ITEMS + k) * 64 + l.
-  uint32_t pid[ITEMS];
-  uint32_t rank[ITEMS];
+  for (int sub = 0; sub < kPSubs; ++sub) {
+    const int64_t sbase = tile * kPTile + (int64_t)sub * kPSub;
+    if (sbase >= n) break;
+    const int nrows = n - sbase < kPSub ? (int)(n - sbase) : kPSub;
+    for (int i = threadIdx.x; i < 4 * P; i += kPBlock) s_whist[i] = 0;
+    for (int j = 0; j < a.ncols; ++j) stage_col_lds<kPBlock>(a.cols[j], sbase, nrows, s_in + a.st_off[j]);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    // Stable ranks: wave w owns rows 256w + 64i + lane, i = 0..3, in order.
+    uint32_t pid[kPSteps], rank[kPSteps];
+    part_of_rows(a, sbase, wave * (kPSub / NW) + lane, kWave, nrows, kbase, pid);
 #pragma unroll
-  for (int k = 0; k < ITEMS; ++k) {
-    const int64_t r = tbase + ((int64_t)wave * ITEMS + k) * kWave + lane;
-    const bool in = r < n;
-    const uint32_t p = in ? part_of_row(a, r) : 0u;
-    uint64_t peers = ballot(in);
-    for (int b = 0; b < nbits; ++b) {
-      const bool bit = (p >> b) & 1u;
-      const uint64_t m = ballot(bit);
-      peers &= bit ? m : ~m;
+    for (int i = 0; i < kPSteps; ++i) {
+      const int r = wave * (kPSub / NW) + i * kWave + lane;
+      const bool in = r < nrows;
+      const uint32_t p = in ? pid[i] : 0u;
+      uint64_t peers = ballot(in);
+      for (int b = 0; b < nbits; ++b) {
+        const bool bit = (p >> b) & 1u;
+        const uint64_t m = ballot(bit);
+        peers &= bit ? m : ~m;
+      }
+      pid[i] = p;
+      rank[i] = 0;
+      if (in) {
+        uint32_t* cnt = s_whist + wave * P + p;
+        const uint32_t before = *cnt;
+        rank[i] = before + rank_in(peers);
+        // The lowest lane of the peer group advances the counter after every
+        // lane of the wave has read it (same wave, program order).
+        if (rank_in(peers) == 0) *cnt = before + (uint32_t)__popcll(peers);
+      }
     }
-    pid[k] = p;
-    rank[k] = 0;
-    if (in) {
-      const uint32_t before = s_whist[wave][p];
-      rank[k] = before + rank_in(peers);
-      // Lowest lane of the peer group advances the counter.  All lanes have
-      // read the old value above (same wave, program order).
-      if (rank_in(peers) == 0) s_whist[wave][p] = before + (uint32_t)__popcll(peers);
+    __syncthreads();
+    // Per partition: wave-exclusive counts, and the sub-tile total.
+    uint32_t mysum = 0;
+    uint32_t cnt_own[4] = {0u, 0u, 0u, 0u};  // per <= 4 for P <= 1024
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int q = threadIdx.x * per + j;
+      if (j < per && q < P) {
+        uint32_t run = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+          const uint32_t c = s_whist[w * P + q];
+          s_whist[w * P + q] = run;
+          run += c;
+        }
+        cnt_own[j] = run;
+        mysum += run;
+      }
     }
-  }
-  __syncthreads();
-
-  // Per partition: wave-exclusive counts and the tile total.
-  for (int q = threadIdx.x; q < P; q += BLOCK) {
-    uint32_t run = 0;
+    // Exclusive scan over partitions of the sub-tile totals.
+    uint32_t incl = mysum;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const uint32_t y = __shfl_up(incl, o, kWave);
+      if (lane >= o) incl += y;
+    }
+    if (lane == kWave - 1) s_wsum[wave] = incl;
+    __syncthreads();
+    uint32_t wpre = 0, tot = 0;
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
-      uint32_t c = s_whist[w][q];
-      s_whist[w][q] = run;
-      run += c;
+      if (w < wave) wpre += s_wsum[w];
+      tot += s_wsum[w];
     }
-    s_pstart[q] = run;  // tile total for now
-    s_gstart[q] = a.starts[(int64_t)q * a.ntiles + tile];
-  }
-  __syncthreads();
-  // Exclusive scan of tile totals over partitions (BLOCK threads, PMAX/BLOCK each).
-  {
-    constexpr int PER = (PMAX + BLOCK - 1) / BLOCK;
-    uint32_t loc[PER];
-    uint32_t sum = 0;
+    uint32_t run = wpre + incl - mysum;
 #pragma unroll
-    for (int j = 0; j < PER; ++j) {
-      const int q = threadIdx.x * PER + j;
-      loc[j] = q < P ? s_pstart[q] : 0u;
-      sum += loc[j];
+    for (int j = 0; j < 4; ++j) {
+      const int q = threadIdx.x * per + j;
+      if (j < per && q < P) {
+        s_sub[q] = run;
+        run += cnt_own[j];
+      }
     }
-    s_scan[threadIdx.x] = sum;
+    if (threadIdx.x == 0) s_sub[P] = tot;
     __syncthreads();
-    for (int o = 1; o < BLOCK; o <<= 1) {
-      uint32_t y = threadIdx.x >= (unsigned)o ? s_scan[threadIdx.x - o] : 0u;
-      __syncthreads();
-      s_scan[threadIdx.x] += y;
-      __syncthreads();
-    }
-    uint32_t run = s_scan[threadIdx.x] - sum;
 #pragma unroll
-    for (int j = 0; j < PER; ++j) {
-      const int q = threadIdx.x * PER + j;
-      if (q < P) s_pstart[q] = run;
-      run += loc[j];
+    for (int i = 0; i < kPSteps; ++i) {
+      const int r = wave * (kPSub / NW) + i * kWave + lane;
+      if (r < nrows) {
+        const uint32_t pos = s_sub[pid[i]] + s_whist[wave * P + pid[i]] + rank[i];
+        s_src[pos] = (uint16_t)r;
+        s_pid[pos] = (uint16_t)pid[i];
+      }
     }
-  }
-  __syncthreads();
-
-  int lpos[ITEMS];
+    __syncthreads();
+    const int total = (int)tot;
+    // Source row and output row of the sorted positions k = t + 256 i, once
+    // for all columns.
+    int srow[kPSteps];
+    int64_t grow[kPSteps];
 #pragma unroll
-  for (int k = 0; k < ITEMS; ++k) {
-    const int64_t r = tbase + ((int64_t)wave * ITEMS + k) * kWave + lane;
-    lpos[k] = -1;
-    if (r < n) {
-      lpos[k] = (int)(s_pstart[pid[k]] + s_whist[wave][pid[k]] + rank[k]);
-      s_pid[lpos[k]] = (uint16_t)pid[k];
+    for (int i = 0; i < kPSteps; ++i) {
+      const int k = i * kPBlock + threadIdx.x;
+      srow[i] = 0;
+      grow[i] = -1;
+      if (k < total) {
+        const uint32_t q = s_pid[k];
+        srow[i] = s_src[k];
+        grow[i] = s_base[q] + (k - (int)s_sub[q]);
+      }
     }
-  }
-  const int tn = (int)((n - tbase) < TILE ? (n - tbase) : TILE);
-  __syncthreads();
-
-  for (int j = 0; j < a.ncols; ++j) {
-    const DCol& c = a.cols[j];
-    const OCol& o = a.out[j];
+    for (int j = 0; j < a.ncols; ++j) {
+      const OCol& o = a.out[j];
+      const uint8_t* col = s_in + a.st_off[j];
+      switch (a.cols[j].type) {
+        case GQ_I8:
 #pragma unroll
-    for (int k = 0; k < ITEMS; ++k) {
-      if (lpos[k] >= 0) {
-        const int64_t r = tbase + ((int64_t)wave * ITEMS + k) * kWave + lane;
-        stage_put(s_stage, lpos[k], load_one(c, r), c.type);
-        if (o.valid) {
-          // Nullable column: set or clear the row's output bit directly.
-          const uint32_t q = pid[k];
-          const int64_t g = s_gstart[q] + (lpos[k] - (int)s_pstart[q]);
-          const uint32_t bit = 1u << (g & 31);
-          if (valid_one(c, r))
-            atomicOr(&o.valid[g >> 5], bit);
-          else
-            atomicAnd(&o.valid[g >> 5], ~bit);
+          for (int i = 0; i < kPSteps; ++i)
+            if (grow[i] >= 0) o.data[grow[i]] = col[srow[i]];
+          break;
+        case GQ_I16:
+#pragma unroll
+          for (int i = 0; i < kPSteps; ++i)
+            if (grow[i] >= 0)
+              reinterpret_cast<int16_t*>(o.data)[grow[i]] = reinterpret_cast<const int16_t*>(col)[srow[i]];
+          break;
+        case GQ_I32:
+#pragma unroll
+          for (int i = 0; i < kPSteps; ++i)
+            if (grow[i] >= 0)
+              reinterpret_cast<int32_t*>(o.data)[grow[i]] = reinterpret_cast<const int32_t*>(col)[srow[i]];
+          break;
+        default:
+#pragma unroll
+          for (int i = 0; i < kPSteps; ++i)
+            if (grow[i] >= 0)
+              reinterpret_cast<int64_t*>(o.data)[grow[i]] = reinterpret_cast<const int64_t*>(col)[srow[i]];
+          break;
+      }
+      if (o.valid) {
+        const DCol& c = a.cols[j];
+#pragma unroll
+        for (int i = 0; i < kPSteps; ++i) {
+          if (grow[i] < 0) continue;
+          const uint32_t bit = 1u << (grow[i] & 31);
+          if (valid_one(c, sbase + srow[i])) atomicOr(&o.valid[grow[i] >> 5], bit);
+          else atomicAnd(&o.valid[grow[i] >> 5], ~bit);
         }
       }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < tn; i += BLOCK) {
-      const uint32_t q = s_pid[i];
-      const int64_t g = s_gstart[q] + (i - (int)s_pstart[q]);
-      copy_out(s_stage, i, o.data, g, c.type);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int q = threadIdx.x * per + j;
+      if (j < per && q < P) s_base[q] += cnt_own[j];
     }
     __syncthreads();
   }
 }
 
-constexpr int kHistBlock = 256, kHistItems = 16;
-constexpr int kScatBlock = 256, kScatItems = 16;
 constexpr int kScanBlock = 256, kScanItems = 16;
 
 // Histogram, scan and scatter for the rows of `a` (a.n, or at most a.n rows
@@ -301,13 +392,29 @@ int launch_partition(gq_ctx* ctx, PartArgs& a, int64_t* d_offsets, hipStream_t s
   const int64_t nparts = (int64_t)a.nparts;
   int rc;
   if (a.n == 0) return launch_fill_u32(ctx, d_offsets, 0u, 2 * (nparts + 1), stream);
-  constexpr int TILE = kScatBlock * kScatItems;
-  static_assert(TILE == kHistBlock * kHistItems, "histogram and scatter tiles must agree");
-  const int64_t ntiles = (a.n + TILE - 1) / TILE;
+  const int64_t ntiles = (a.n + kPTile - 1) / kPTile;
   a.ntiles = ntiles;
   const int64_t m = ntiles * nparts;
   constexpr int STILE = kScanBlock * kScanItems;
   const int64_t nscan = (m + STILE - 1) / STILE;
+  // LDS layouts: every column for the scatter, the key columns for the histogram.
+  a.in_bytes = 0;
+  for (int j = 0; j < a.ncols; ++j) {
+    a.st_off[j] = a.in_bytes;
+    a.in_bytes += (int)align_up((size_t)kPSub * type_width(a.cols[j].type), 16);
+  }
+  a.kin_bytes = 0;
+  const int nk = a.digit ? 1 : a.nkeys;
+  for (int j = 0; j < nk; ++j) {
+    a.kst_off[j] = a.kin_bytes;
+    a.kin_bytes += (int)align_up((size_t)kPSub * type_width(a.keys[j].type), 16);
+  }
+  const size_t lds_hist = align_up((size_t)nparts * 4, 16) + (size_t)a.kin_bytes;
+  const size_t lds_scat = part_scatter_lds((int)nparts, a.in_bytes);
+  int lds_max = 0;
+  GQ_HIP_CHECK(ctx, hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device));
+  if (lds_scat + 256 > (size_t)lds_max || lds_hist + 256 > (size_t)lds_max)
+    return set_error(ctx, GQ_ERR_UNSUPPORTED, "partition: too many or too wide columns for one staged sub-tile");
 
   Scratch ws(ctx, stream);
   const size_t off_counts = 256;
@@ -326,19 +433,12 @@ int launch_partition(gq_ctx* ctx, PartArgs& a, int64_t* d_offsets, hipStream_t s
   rc = launch_fill_u32(ctx, status, 0u, 2 * nscan, stream);
   if (rc) return rc;
 
-  GQ_LAUNCH(ctx, "part_hist", (k_part_hist<kHistBlock, kHistItems>), dim3((unsigned)ntiles), dim3(kHistBlock), 0,
-            stream, a);
+  GQ_LAUNCH(ctx, "part_hist", k_part_hist, dim3((unsigned)ntiles), dim3(kPBlock), lds_hist, stream, a);
   GQ_LAUNCH_CHECK(ctx);
   GQ_LAUNCH(ctx, "scan_counts", (k_scan_counts<kScanBlock, kScanItems>), dim3((unsigned)nscan), dim3(kScanBlock), 0,
             stream, (const uint32_t*)a.counts, m, a.starts, ntiles, nparts, d_offsets, ticket, status, nscan);
   GQ_LAUNCH_CHECK(ctx);
-  if (nparts <= 256) {
-    GQ_LAUNCH(ctx, "part_scatter", (k_part_scatter<kScatBlock, kScatItems, 256>), dim3((unsigned)ntiles),
-              dim3(kScatBlock), 0, stream, a);
-  } else {
-    GQ_LAUNCH(ctx, "part_scatter", (k_part_scatter<kScatBlock, kScatItems, kPartMax>), dim3((unsigned)ntiles),
-              dim3(kScatBlock), 0, stream, a);
-  }
+  GQ_LAUNCH(ctx, "part_scatter", k_part_scatter, dim3((unsigned)ntiles), dim3(kPBlock), lds_scat, stream, a);
   GQ_LAUNCH_CHECK(ctx);
   return GQ_OK;
 }
@@ -371,6 +471,7 @@ int radix_sort_rows(gq_ctx* ctx, const gq_batch* in, gq_batch* const bufs[2], gq
     a.nkeys = 1;
     a.ncols = src->ncols;
     a.keys[0] = make_dcol(src->cols[0]);
+    a.key_col[0] = 0;
     for (int j = 0; j < src->ncols; ++j) {
       a.cols[j] = make_dcol(src->cols[j]);
       const gq_column& oc = dst->cols[j];
@@ -414,6 +515,7 @@ extern "C" int gq_hash_partition(gq_ctx* ctx, const gq_batch* in, const int32_t*
     if (keys[j] < 0 || keys[j] >= in->ncols)
       return set_error(ctx, GQ_ERR_INVALID, "gq_hash_partition: key column out of range");
     a.keys[j] = make_dcol(in->cols[keys[j]]);
+    a.key_col[j] = keys[j];
   }
   for (int j = 0; j < in->ncols; ++j) {
     const gq_column& ic = in->cols[j];

@@ -51,9 +51,7 @@ constexpr int kRpRows = kRpSub / kRpBlock;       // rows per thread per sub-tile
 constexpr int kRpSubs = 16;                      // sub-tiles per hist tile
 constexpr int kRpTile = kRpSub * kRpSubs;        // 16384 rows per hist tile
 constexpr int kRpMaxStage = 8;                   // distinct input columns staged in LDS
-// Cache policy of the staging loads: non-temporal, so the streamed input does
-// not push the partly written output lines out of L2.
-constexpr int kLoadNt = 2;
+
 constexpr int kRjBlock = 1024;
 constexpr int kRjPerCu = 1;                      // join workgroups per CU (the LDS table takes the CU)
 constexpr int kRjMaxVals = 2;                    // value words per probe tuple
@@ -105,26 +103,7 @@ struct RpArgs {
 __device__ __forceinline__ void rp_stage(const RpArgs& a, int nst, int64_t sbase, uint8_t* s_in) {
   const int64_t left = a.n - sbase;
   const int nrows = left < kRpSub ? (int)left : kRpSub;
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-  for (int j = 0; j < nst; ++j) {
-    const DCol& c = a.st[j];
-    const int w = type_width(c.type);
-    uint8_t* dst = s_in + a.st_off[j];
-    const uint8_t* src = c.data + sbase * w;
-    const int nb = nrows * w;
-    int done = 0;
-    if (c.align >= 16) {
-      const int nfull = nb >> 4;
-      for (int ch0 = wave * kWave; ch0 < nfull; ch0 += kRpBlock) {
-        if (ch0 + lane < nfull)
-          __builtin_amdgcn_global_load_lds(
-              (const __attribute__((address_space(1))) void*)(src + (size_t)(ch0 + lane) * 16),
-              (__attribute__((address_space(3))) void*)(dst + (size_t)ch0 * 16), 16, 0, kLoadNt);
-      }
-      done = nfull << 4;
-    }
-    for (int b = done + threadIdx.x; b < nb; b += kRpBlock) dst[b] = src[b];
-  }
+  for (int j = 0; j < nst; ++j) stage_col_lds<kRpBlock>(a.st[j], sbase, nrows, s_in + a.st_off[j]);
 }
 
 // The kRpRows rows r = i * 256 + threadIdx.x of a staged column; one type
