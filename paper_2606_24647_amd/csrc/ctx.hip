@@ -128,13 +128,13 @@ int gq_ctx_create(int device, const gq_allocator* alloc, gq_ctx** out) {
     return GQ_ERR_HIP;
   }
   if (!alloc) {
-    // Keep up to 2 GiB of freed blocks in the device's default pool, so that
+    // Keep up to 8 GiB of freed blocks in the device's default pool, so that
     // repeated stream-ordered allocations cost no driver call; larger amounts
     // go back to the device at the next synchronisation, where other
     // allocators (the caller's) can use them.
     hipMemPool_t pool;
     if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
-      uint64_t threshold = 2ull << 30;
+      uint64_t threshold = 8ull << 30;
       (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &threshold);
     }
   }

@@ -27,6 +27,8 @@ namespace {
 
 constexpr int kGbBlock = 256;
 constexpr int kGbItems = 4;
+constexpr int kGbLdsItems = 8;   // rows per thread per tile of the LDS strategy
+constexpr int kGbLdsBlocksPerCu = 4;
 constexpr int kGjItems = 8;
 constexpr size_t kLdsBudget = 32 * 1024;
 
@@ -312,19 +314,24 @@ constexpr int kCBlock = 256, kCItems = 8;
 // ---------------------------------------------------------------------------
 template <bool JOIN>
 int launch_aggregate(gq_ctx* ctx, GbArgs& a, int strategy, hipStream_t stream) {
-  constexpr int TILE = kGbBlock * kGbItems;
-  a.ntiles = (a.n + TILE - 1) / TILE;
-  if (a.ntiles == 0) return GQ_OK;
+  if (a.n == 0) return GQ_OK;
   if (strategy == GQ_STRATEGY_LDS) {
+    constexpr int LTILE = kGbBlock * kGbLdsItems;
+    a.ntiles = (a.n + LTILE - 1) / LTILE;
     const int sw = 1 + a.ap.nacc;
     int lcap = 1;
     while ((size_t)(lcap * 2) * sw * 8 <= kLdsBudget) lcap *= 2;
     a.lcap = lcap;
     const size_t lds = (size_t)lcap * sw * 8;
-    int64_t grid = a.ntiles < 512 ? a.ntiles : 512;
-    GQ_LAUNCH(ctx, "gb_lds", (k_gb_lds<kGbBlock, kGbItems, JOIN>), dim3((unsigned)grid), dim3(kGbBlock), lds, stream,
-              a);
+    int cus = 256;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
+    const int64_t max_grid = (int64_t)cus * kGbLdsBlocksPerCu;
+    int64_t grid = a.ntiles < max_grid ? a.ntiles : max_grid;
+    GQ_LAUNCH(ctx, "gb_lds", (k_gb_lds<kGbBlock, kGbLdsItems, JOIN>), dim3((unsigned)grid), dim3(kGbBlock), lds,
+              stream, a);
   } else {
+    constexpr int TILE = kGbBlock * kGbItems;
+    a.ntiles = (a.n + TILE - 1) / TILE;
     GQ_LAUNCH(ctx, "gb_global", (k_gb_global<kGbBlock, kGbItems, JOIN>), dim3((unsigned)a.ntiles), dim3(kGbBlock), 0,
               stream, a);
   }

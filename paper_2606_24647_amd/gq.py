@@ -297,11 +297,47 @@ def agg_nullable(table: DevTable, agg) -> bool:
 # Context
 # ---------------------------------------------------------------------------
 
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+
+
+class GqAllocator(C.Structure):
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("user", C.c_void_p)]
+
+
+def _torch_allocator(device: int) -> GqAllocator:
+    """gq_allocator over torch's caching allocator (stream-ordered per stream):
+    one cache for the library's scratch and the caller's tensors."""
+
+    def alloc(nbytes, stream, user):
+        try:
+            return torch.cuda.caching_allocator_alloc(max(1, int(nbytes)), device, stream or 0)
+        except Exception:  # noqa: BLE001 - reported by the library as GQ_ERR_NOMEM
+            return None
+
+    def free(ptr, nbytes, stream, user):
+        if ptr:
+            torch.cuda.caching_allocator_delete(ptr)
+
+    return GqAllocator(_ALLOC_FN(alloc), _FREE_FN(free), None)
+
+
 class Context:
-    def __init__(self, device: int | None = None):
+    """A library context.  allocator=None: hipMallocAsync on the device's pool;
+    allocator="torch": the library allocates through torch's caching allocator
+    (for callers that also hold large torch tensors: one cache instead of two)."""
+
+    def __init__(self, device: int | None = None, allocator: str | None = None):
         self.device = torch.cuda.current_device() if device is None else device
         h = C.c_void_p()
-        rc = _lib.gq_ctx_create(self.device, None, C.byref(h))
+        self._alloc = None
+        if allocator == "torch":
+            self._alloc = _torch_allocator(self.device)
+            rc = _lib.gq_ctx_create(self.device, C.byref(self._alloc), C.byref(h))
+        elif allocator is None:
+            rc = _lib.gq_ctx_create(self.device, None, C.byref(h))
+        else:
+            raise ValueError(f"unknown allocator {allocator!r}")
         if rc != GQ_OK:
             raise GqError(rc, "gq_ctx_create failed")
         self.h = h

@@ -195,7 +195,7 @@ class DeviceExecutor:
         self.share = share
         self.max_share = 8
         self.streams = [torch.cuda.Stream() for _ in range(nslots)]
-        self.ctxs = [gq.Context() for _ in range(nslots)]
+        self.ctxs = [gq.Context(allocator="torch") for _ in range(nslots)]
         self.nf, self.nd = fact.nrows, dim.nrows
 
     # Upper bounds of the device memory a query allocates (tables, outputs, workspaces).
