@@ -381,6 +381,10 @@ typedef struct gq_batch_spec {
                                aggregate in LDS first; 0 = 256, -1 = never */
   int32_t tile_rows;        /* rows per work item, multiple of 1024; 0 = 8192 */
   int32_t blocks_per_cu;    /* persistent blocks per compute unit; 0 = 4 */
+  int32_t radix_min_groups; /* fragments expecting at least this many groups are
+                               partitioned by key hash and aggregated in LDS
+                               region by region (no per-row HBM atomics);
+                               0 = 2048, -1 = never */
 } gq_batch_spec;
 
 typedef struct gq_batch_plan gq_batch_plan;

@@ -19,6 +19,9 @@
 //   3. k_batch_compact  one block per fragment: stable compaction of its table
 //                       into the fragment's output batch, in slot order.
 #include "agg.h"
+#include "batchrx.h"
+
+#include <vector>
 
 namespace gq {
 namespace {
@@ -27,12 +30,6 @@ constexpr int kBBlock = 256;
 constexpr int kBItems = 4;
 constexpr int kBCItems = 8;
 
-// Output of one fragment.
-struct BatchOut {
-  OCol out[GQ_MAX_KEYS + GQ_MAX_AGGS];
-  int64_t out_cap;
-  int64_t* d_groups;
-};
 
 struct BatchArgs {
   const GbArgs* frags;        // per-fragment plan, in device memory
@@ -146,7 +143,9 @@ __global__ __launch_bounds__(BLOCK) void k_batch_compact(const BatchArgs a) {
   const BatchOut& bo = a.outs[f];
   const int64_t total = (int64_t)g.cap + 2;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  int64_t run = 0;
+  // Radix fragments: the groups of the HBM table (special keys, overflow)
+  // follow those the radix aggregation already wrote.
+  int64_t run = bo.append ? *bo.d_groups : 0;
   for (int64_t c0 = 0; c0 < total; c0 += TILE) {
     const int64_t i0 = c0 + (int64_t)threadIdx.x * ITEMS;
     uint32_t keep = 0;
@@ -274,10 +273,13 @@ int gq_batch_plan_create(gq_ctx* ctx, const gq_fragment* frags, int nfrags, cons
     return set_error(ctx, GQ_ERR_INVALID, "gq_batch_plan_create: tile_rows must be a multiple of 1024");
   const int lds_max = spec->lds_max_groups >= 0 ? (spec->lds_max_groups ? spec->lds_max_groups : 256) : 0;
   const int bpc = spec->blocks_per_cu > 0 ? spec->blocks_per_cu : 4;
+  const int64_t radix_min = spec->radix_min_groups >= 0 ? (spec->radix_min_groups ? spec->radix_min_groups : 2048)
+                                                        : INT64_MAX;
 
   std::vector<GbArgs> plans((size_t)nfrags);
   std::vector<BatchOut> outs((size_t)nfrags);
   std::vector<int64_t> tstart((size_t)nfrags + 1, 0);
+  std::vector<char> is_radix((size_t)nfrags, 0);
   int64_t nslots = 0, total_rows = 0;
   int nacc = 0;
   for (int f = 0; f < nfrags; ++f) {
@@ -308,7 +310,8 @@ int gq_batch_plan_create(gq_ctx* ctx, const gq_fragment* frags, int nfrags, cons
     g.keys = reinterpret_cast<uint64_t*>((uintptr_t)nslots);  // offset for now
     nslots += (int64_t)cap + 2;
     total_rows += g.n;
-    tstart[f + 1] = tstart[f] + (g.n + tile_rows - 1) / tile_rows;
+    is_radix[f] = spec->nkeys > 0 && expected >= radix_min && g.n > 0 && g.n < ((int64_t)1 << 31);
+    tstart[f + 1] = tstart[f] + (is_radix[f] ? 0 : (g.n + tile_rows - 1) / tile_rows);
     // outputs
     BatchOut& bo = outs[f];
     std::memset(&bo, 0, sizeof(bo));
@@ -327,6 +330,80 @@ int gq_batch_plan_create(gq_ctx* ctx, const gq_fragment* frags, int nfrags, cons
     }
     bo.d_groups = fr.d_groups;
   }
+
+  // Radix fragments: regions of about half an LDS table each, tiles, counts.
+  BrxArgs rx;
+  std::memset(&rx, 0, sizeof(rx));
+  std::vector<BrxFrag> rfs;
+  int64_t rx_tiles = 0, rx_counts = 0, rx_items = 0, rx_rows = 0;
+  size_t rx_scatter_lds = 0, rx_hist_lds = 0;
+  {
+    const AggPlan& ap0 = plans[0].ap;
+    for (int i = 0; i < ap0.naggs; ++i) {
+      rx.vword[i] = -1;
+      const int op = ap0.aggs[i].op;
+      if (op == GQ_SUM || op == GQ_MIN || op == GQ_MAX) {
+        rx.vagg[rx.nv] = i;
+        rx.vword[i] = rx.nv++;
+      }
+    }
+    const int lcap_x = brx_lcap(nacc);
+    const int64_t per_region = lcap_x / 2;
+    for (int f = 0; f < nfrags; ++f) {
+      if (!is_radix[f]) continue;
+      const GbArgs& g = plans[f];
+      bool nullable = false;
+      for (int v = 0; v < g.ap.nvals; ++v) nullable |= g.ap.vals[v].valid != nullptr;
+      rx.need_nn |= nullable ? 1 : 0;
+      BrxFrag x;
+      std::memset(&x, 0, sizeof(x));
+      if (brx_stage_plan(x, g, rx.nv, rx.vagg, nullable) != 0) {
+        // Too many distinct columns to stage: this fragment stays on the tile path.
+        is_radix[f] = 0;
+        continue;
+      }
+      const int64_t expected = frags[f].expected_groups > 0 ? frags[f].expected_groups : g.n;
+      int rbits = 0;
+      while (rbits < 10 && ((int64_t)1 << rbits) * per_region < expected) ++rbits;
+      x.f = f;
+      x.rbits = rbits;
+      x.tiles = (g.n + brx_tile_rows() - 1) / brx_tile_rows();
+      x.tile0 = rx_tiles;
+      x.cbase = rx_counts;
+      x.item0 = rx_items;
+      rx_tiles += x.tiles;
+      rx_counts += x.tiles << rbits;
+      rx_items += (int64_t)1 << rbits;
+      rx_rows += g.n;
+      const size_t sl = brx_scatter_lds_bytes(rbits, x.in_bytes, rx.nv);
+      const size_t hl = align_up((size_t)4 << rbits, 16) + (size_t)x.in_bytes;
+      if (sl > rx_scatter_lds) rx_scatter_lds = sl;
+      if (hl > rx_hist_lds) rx_hist_lds = hl;
+      rfs.push_back(x);
+    }
+    // Fragments that fell back to the tile path need tiles again.
+    for (int f = 0; f < nfrags; ++f) {
+      const int64_t t = is_radix[f] ? 0 : (plans[f].n + tile_rows - 1) / tile_rows;
+      tstart[f + 1] = tstart[f] + t;
+    }
+    for (int f = 0; f < nfrags; ++f) outs[f].append = is_radix[f] ? 1 : 0;
+    rx.nrf = (int32_t)rfs.size();
+    rx.lcap = lcap_x;
+    rx.nacc = nacc;
+    rx.nk = spec->nkeys;
+    rx.nitems = rx_items;
+    if (rx_scatter_lds > 150 * 1024) {
+      // A staging layout this wide does not fit: every fragment takes the tile path.
+      rfs.clear();
+      rx.nrf = 0;
+      rx_tiles = rx_counts = rx_items = rx_rows = 0;
+      for (int f = 0; f < nfrags; ++f) {
+        is_radix[f] = 0;
+        outs[f].append = 0;
+        tstart[f + 1] = tstart[f] + (plans[f].n + tile_rows - 1) / tile_rows;
+      }
+    }
+  }
   const int sw = 1 + nacc;
   int lcap = 1;
   while ((size_t)(lcap * 2) * sw * 8 <= 32 * 1024) lcap *= 2;
@@ -338,7 +415,15 @@ int gq_batch_plan_create(gq_ctx* ctx, const gq_fragment* frags, int nfrags, cons
   const size_t off_outs = align_up(off_plans + sizeof(GbArgs) * nfrags, 256);
   const size_t off_ts = align_up(off_outs + sizeof(BatchOut) * nfrags, 256);
   const size_t off_ticket = align_up(off_ts + 8 * ((size_t)nfrags + 1), 256);
-  const size_t total = off_ticket + 256;
+  // Radix path: fragment descriptors, counts, starts, scan status, tuples.
+  const int64_t rx_nscan = (rx_counts + 4095) / 4096;
+  const size_t off_rf = off_ticket + 256;
+  const size_t off_cnt = align_up(off_rf + sizeof(BrxFrag) * rfs.size(), 256);
+  const size_t off_st = align_up(off_cnt + 4 * (size_t)rx_counts, 256);
+  const size_t off_ss = align_up(off_st + 8 * ((size_t)rx_counts + 1), 256);
+  const size_t off_tup = align_up(off_ss + 8 * (size_t)(rx_nscan + 1), 256);
+  const size_t off_tnn = align_up(off_tup + 8 * (size_t)(1 + rx.nv) * (size_t)rx_rows, 256);
+  const size_t total = align_up(off_tnn + (rx.need_nn ? (size_t)rx_rows : 0), 256) + 256;
 
   GQ_HIP_CHECK(ctx, hipSetDevice(ctx->device));
   gq_batch_plan* p = new (std::nothrow) gq_batch_plan;
@@ -377,6 +462,17 @@ int gq_batch_plan_create(gq_ctx* ctx, const gq_fragment* frags, int nfrags, cons
   a.nslots = nslots;
   a.ap = plans[0].ap;
   a.ticket = reinterpret_cast<uint32_t*>(base + off_ticket);
+  rx.frags = a.frags;
+  rx.outs = a.outs;
+  rx.rf = reinterpret_cast<const BrxFrag*>(base + off_rf);
+  rx.counts = reinterpret_cast<uint32_t*>(base + off_cnt);
+  rx.starts = reinterpret_cast<int64_t*>(base + off_st);
+  rx.scan_status = reinterpret_cast<uint64_t*>(base + off_ss);
+  rx.scan_ticket = reinterpret_cast<uint32_t*>(base + off_ticket + 64);
+  rx.item_ticket = reinterpret_cast<unsigned long long*>(base + off_ticket + 128);
+  rx.nscan = rx_nscan;
+  rx.tup = reinterpret_cast<uint64_t*>(base + off_tup);
+  rx.tnn = rx.need_nn ? reinterpret_cast<uint8_t*>(base + off_tnn) : nullptr;
   p->total_rows = total_rows;
   p->ntiles = a.ntiles;
   p->nslots = nslots;
@@ -393,6 +489,8 @@ int gq_batch_plan_create(gq_ctx* ctx, const gq_fragment* frags, int nfrags, cons
           hipSuccess ||
       hipMemcpyAsync(base + off_ts, tstart.data(), 8 * ((size_t)nfrags + 1), hipMemcpyHostToDevice, stream) !=
           hipSuccess ||
+      (!rfs.empty() && hipMemcpyAsync(base + off_rf, rfs.data(), sizeof(BrxFrag) * rfs.size(),
+                                      hipMemcpyHostToDevice, stream) != hipSuccess) ||
       hipStreamSynchronize(stream) != hipSuccess)
     return fail(GQ_ERR_HIP, "gq_batch_plan_create: descriptor upload failed");
 
@@ -409,6 +507,13 @@ int gq_batch_plan_create(gq_ctx* ctx, const gq_fragment* frags, int nfrags, cons
   int64_t iblocks = (nslots + 255) / 256;
   if (iblocks > 8192) iblocks = 8192;
   hipLaunchKernelGGL(k_batch_init, dim3((unsigned)iblocks), dim3(256), 0, p->cap_stream, a);
+  if (rx.nrf > 0 && brx_enqueue(rx, rx_tiles, rx_counts, rx_scatter_lds, rx_hist_lds, prop.multiProcessorCount,
+                                p->cap_stream) != GQ_OK) {
+    hipGraph_t g0 = nullptr;
+    (void)hipStreamEndCapture(p->cap_stream, &g0);
+    if (g0) (void)hipGraphDestroy(g0);
+    return fail(GQ_ERR_HIP, "gq_batch_plan_create: radix kernels failed to enqueue");
+  }
   hipLaunchKernelGGL((k_batch_agg<kBBlock, kBItems>), dim3((unsigned)p->grid), dim3(kBBlock), lds_bytes, p->cap_stream,
                      a);
   hipLaunchKernelGGL((k_batch_compact<kBBlock, kBCItems>), dim3((unsigned)nfrags), dim3(kBBlock), 0, p->cap_stream, a);

@@ -99,7 +99,7 @@ class GqFragment(C.Structure):
 class GqBatchSpec(C.Structure):
     _fields_ = [("keys", C.POINTER(C.c_int32)), ("nkeys", C.c_int32), ("naggs", C.c_int32),
                 ("aggs", C.POINTER(GqAgg)), ("load_factor", C.c_float), ("lds_max_groups", C.c_int32),
-                ("tile_rows", C.c_int32), ("blocks_per_cu", C.c_int32)]
+                ("tile_rows", C.c_int32), ("blocks_per_cu", C.c_int32), ("radix_min_groups", C.c_int32)]
 
 
 class GqAllocator(C.Structure):
@@ -516,13 +516,14 @@ class Context:
 class BatchPlan:
     """Many filter + group-by fragments in one graph-captured persistent launch.
 
-    fragments: list of (DevTable, preds, expected_groups); every fragment uses
-    the same key columns and aggregates.  Outputs are allocated here, one
-    DevTable per fragment with capacity min(rows, expected_groups).
+    fragments: list of (DevTable, preds, expected_groups[, out_capacity]);
+    every fragment uses the same key columns and aggregates.  Outputs are
+    allocated here, one DevTable per fragment with capacity out_capacity, by
+    default min(rows, expected_groups).
     """
 
     def __init__(self, ctx: "Context", fragments, keys, aggs, load_factor=0.0, lds_max_groups=0,
-                 tile_rows=0, blocks_per_cu=0, stream=None):
+                 tile_rows=0, blocks_per_cu=0, radix_min_groups=0, stream=None):
         self.ctx = ctx
         self.h = None
         nf = len(fragments)
@@ -530,8 +531,11 @@ class BatchPlan:
         self.outs = []
         self.d_groups = torch.zeros(nf, dtype=torch.int64, device="cuda")
         farr = (GqFragment * nf)()
-        for f, (tab, preds, expected) in enumerate(fragments):
+        for f, fr in enumerate(fragments):
+            tab, preds, expected = fr[:3]
             cap = tab.nrows if not expected else min(tab.nrows, int(expected))
+            if len(fr) > 3 and fr[3] is not None:
+                cap = int(fr[3])
             cap = max(cap, 1)
             out = ctx._groupby_out(tab, keys, aggs, cap)
             ib, ob = _BatchArg(tab), _BatchArg(out, cap)
@@ -548,7 +552,7 @@ class BatchPlan:
         a, na = _aggs(aggs)
         self._keep += [k, a, farr]
         spec = GqBatchSpec(C.cast(k, C.POINTER(C.c_int32)), nk, na, C.cast(a, C.POINTER(GqAgg)),
-                           load_factor, lds_max_groups, tile_rows, blocks_per_cu)
+                           load_factor, lds_max_groups, tile_rows, blocks_per_cu, radix_min_groups)
         h = C.c_void_p()
         ctx.check(_lib.gq_batch_plan_create(ctx.h, farr, nf, C.byref(spec), _stream(stream), C.byref(h)))
         self.h = h

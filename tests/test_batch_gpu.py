@@ -6,7 +6,7 @@ import torch
 
 import oracle
 from paper_2606_24647_amd import datagen as dg
-from tests.helpers import canon_groups
+from tests.helpers import canon_groups, tbl
 
 pytestmark = pytest.mark.gpu
 
@@ -101,3 +101,116 @@ def test_batch_rejects_mismatched_shapes(gq, ctx):
     b = gq.to_device(t)
     with pytest.raises(gq.GqError):
         gq.BatchPlan(ctx, [(a, [], 5), (b, [], 5)], [4], AGGS)
+
+
+# Fragments expecting at least radix_min_groups groups are partitioned by key
+# hash and aggregated region by region in LDS; these cases force that path.
+
+def _check_plan(gq, plan, frags, keys, preds, aggs, reps=1):
+    results = []
+    for _ in range(reps):
+        plan.launch()
+        gq_ctx = plan.ctx
+        gq_ctx.raise_status()
+        results.append([plan.result(f) for f in range(len(frags))])
+        _ = torch.arange(1000, device="cuda").sum().item()
+    for f, t in enumerate(frags):
+        exp = oracle.groupby(t, keys, preds[f], aggs)
+        ek, ea = canon_groups(exp.keys, exp.aggs)
+        for rep in range(reps):
+            cols, n = results[rep][f]
+            assert n == exp.nrows, (f, rep, n, exp.nrows)
+            gk, ga = canon(cols, len(keys))
+            for (gv, gok), (ev, eok) in zip(gk + ga, ek + ea):
+                assert np.array_equal(gv, ev) and np.array_equal(gok, eok), (f, rep)
+
+
+@pytest.mark.parametrize("radix_min", [1, 500])
+def test_batch_radix_vs_oracle(gq, ctx, radix_min):
+    # Mixed cardinalities: with radix_min=500 some fragments take the tile
+    # path (LDS or HBM table) and the rest the radix path, in one graph.
+    frags, rows, card, bound = make_fragments(40, seed=13, rows_hi=80_000, card_hi=30_000)
+    dev = [gq.to_device(t) for t in frags]
+    preds = [[("range", 3, 0, int(b))] for b in bound]
+    plan = gq.BatchPlan(ctx, [(d, p, int(c)) for d, p, c in zip(dev, preds, card)], [4], AGGS,
+                        radix_min_groups=radix_min)
+    _check_plan(gq, plan, frags, [4], preds, AGGS, reps=3)
+    plan.free()
+
+
+def _raw_key_hashing_to_empty():
+    # The one 64-bit key whose region hash is all ones (inverse of fmix64 of
+    # ~0, then the seed), computed here from the hash's definition.
+    m = (1 << 64) - 1
+    h = m
+    h ^= h >> 33
+    h = (h * pow(0xC4CEB9FE1A85EC53, -1, 1 << 64)) & m
+    h ^= h >> 33
+    h = (h * pow(0xFF51AFD7ED558CCD, -1, 1 << 64)) & m
+    h ^= h >> 33
+    k = h ^ 0x2545F4914F6CDD1D
+    # forward check
+    x = k ^ 0x2545F4914F6CDD1D
+    x ^= x >> 33
+    x = (x * 0xFF51AFD7ED558CCD) & m
+    x ^= x >> 33
+    x = (x * 0xC4CEB9FE1A85EC53) & m
+    x ^= x >> 33
+    assert x == m
+    return np.array([k], dtype=np.uint64).view(np.int64)[0]
+
+
+def test_batch_radix_raw_keys_nulls(gq, ctx):
+    # Nullable int64 keys (raw key mode) with the EMPTY key (-1), NULL keys and
+    # the key hashing to the LDS empty marker; nullable values under SUM, MIN,
+    # MAX and COUNT(col).
+    rng = np.random.default_rng(21)
+    special = _raw_key_hashing_to_empty()
+    frags, preds = [], []
+    # Every fragment holds a NULL key and a NULL value (all fragments of a plan
+    # share their column shapes, nullability included).
+    for f, n in enumerate([50_000, 7_000, 2, 33_333, 120_001]):
+        k = rng.integers(-2**62, 2**62, n)
+        k = np.where(rng.random(n) < 0.5, rng.integers(0, 4000, n), k)
+        k[::97] = -1
+        k[5::101] = special
+        kv, vv = rng.random(n) > 0.03, rng.random(n) > 0.1
+        kv[0], vv[-1] = False, False
+        frags.append(tbl(k=(k, kv), v=(rng.integers(-1000, 1000, n), vv),
+                         w=rng.integers(0, 50, n).astype(np.int16)))
+        preds.append([("range", 2, 0, 40)] if f % 2 else [])
+    aggs = [("sum", [("col", 1)]), ("min", [("col", 1)]), ("max", [("col", 1)]), ("count", [("col", 1)]),
+            ("count*",)]
+    dev = [gq.to_device(t) for t in frags]
+    plan = gq.BatchPlan(ctx, [(d, p, max(t.nrows, 1)) for d, p, t in zip(dev, preds, frags)], [0], aggs,
+                        radix_min_groups=1)
+    _check_plan(gq, plan, frags, [0], preds, aggs, reps=2)
+    plan.free()
+
+
+def test_batch_radix_packed_keys(gq, ctx):
+    # Two keys packed into one word, one of them nullable.
+    rng = np.random.default_rng(22)
+    frags, preds = [], []
+    for n in [90_000, 20_000, 3]:
+        frags.append(tbl(a=rng.integers(-3000, 3000, n).astype(np.int32),
+                         b=(rng.integers(-100, 100, n).astype(np.int8), rng.random(n) > 0.05),
+                         v=rng.integers(0, 10**9, n)))
+        preds.append([("ne", 1, 7)])
+    aggs = [("sum", [("col", 2)]), ("max", [("col", 2)]), ("count*",)]
+    dev = [gq.to_device(t) for t in frags]
+    plan = gq.BatchPlan(ctx, [(d, p, t.nrows) for d, p, t in zip(dev, preds, frags)], [0, 1], aggs,
+                        radix_min_groups=1)
+    _check_plan(gq, plan, frags, [0, 1], preds, aggs, reps=2)
+    plan.free()
+
+
+def test_batch_radix_underestimated_groups(gq, ctx):
+    # Three times more groups than expected: regions outgrow their LDS tables
+    # and the excess goes to the fragment's HBM table.
+    n, card, expected = 400_000, 60_000, 20_000
+    t = dg.fragment_c4(0, n, card, seed=23)
+    d = gq.to_device(t)
+    plan = gq.BatchPlan(ctx, [(d, [], expected, n)], [4], AGGS, radix_min_groups=1)
+    _check_plan(gq, plan, [t], [4], [[]], AGGS, reps=2)
+    plan.free()
