@@ -37,8 +37,8 @@ struct GbArgs {
   int32_t* dev_status;
 };
 
-template <int ITEMS>
-__device__ __forceinline__ void load_col(const DCol& c, int64_t r0, int64_t n, int64_t (&v)[ITEMS]) {
+template <int ITEMS, class C>
+__device__ __forceinline__ void load_col(const C& c, int64_t r0, int64_t n, int64_t (&v)[ITEMS]) {
   if (c.nt) load_items<ITEMS, true>(c, r0, n, v);
   else load_items<ITEMS, false>(c, r0, n, v);
 }
@@ -46,8 +46,8 @@ __device__ __forceinline__ void load_col(const DCol& c, int64_t r0, int64_t n, i
 // ---------------------------------------------------------------------------
 // Per-tile row evaluation shared by the kernels
 // ---------------------------------------------------------------------------
-template <int ITEMS>
-__device__ __forceinline__ uint32_t eval_preds(const GbArgs& a, int64_t r0, int64_t n) {
+template <int ITEMS, class GA>
+__device__ __forceinline__ uint32_t eval_preds(const GA& a, int64_t r0, int64_t n) {
   uint32_t keep = 0;
 #pragma unroll
   for (int k = 0; k < ITEMS; ++k)
@@ -105,8 +105,8 @@ __device__ __forceinline__ void join_weights(const JoinRef& j, uint32_t keep, co
 }
 
 // Group keys of ITEMS rows.  special: 0 hashed, 1 EMPTY-valued raw key, 2 NULL raw key.
-template <int ITEMS>
-__device__ __forceinline__ void make_keys(const KeyPlan& kp, int64_t r0, int64_t n, uint64_t (&key)[ITEMS],
+template <int ITEMS, class KP>
+__device__ __forceinline__ void make_keys(const KP& kp, int64_t r0, int64_t n, uint64_t (&key)[ITEMS],
                                           uint8_t (&special)[ITEMS]) {
 #pragma unroll
   for (int k = 0; k < ITEMS; ++k) {
@@ -142,20 +142,20 @@ __device__ __forceinline__ void make_keys(const KeyPlan& kp, int64_t r0, int64_t
 // Input of aggregate `ag` for ITEMS rows: x[k] = product of its factors
 // (wrapping).  Returns the mask of rows whose input is non-NULL.  A column used
 // by several aggregates is re-read from cache (such columns use temporal loads).
-template <int ITEMS>
-__device__ __forceinline__ uint32_t agg_values(const DAgg& ag, const AggPlan& ap, int64_t r0, int64_t n,
+template <int ITEMS, class AG, class AP>
+__device__ __forceinline__ uint32_t agg_values(const AG& ag, const AP& ap, int64_t r0, int64_t n,
                                                uint64_t (&x)[ITEMS]) {
   uint32_t nn = 0xffffffffu;
 #pragma unroll
   for (int k = 0; k < ITEMS; ++k) x[k] = 1;
   for (int f = 0; f < ag.nf; ++f) {
-    const DFactor& fa = ag.f[f];
+    const auto& fa = ag.f[f];
     if (fa.kind == GQ_F_CONST) {
 #pragma unroll
       for (int k = 0; k < ITEMS; ++k) x[k] *= (uint64_t)fa.k;
       continue;
     }
-    const DCol& c = ap.vals[fa.v];
+    const auto& c = ap.vals[fa.v];
     int64_t v[ITEMS];
     load_col<ITEMS>(c, r0, n, v);
     if (c.valid) nn &= valid_items<ITEMS>(c, r0, n);
@@ -172,8 +172,8 @@ __device__ __forceinline__ uint32_t agg_values(const DAgg& ag, const AggPlan& ap
 
 // Apply all aggregates of ITEMS rows.  Row k's accumulators are in LDS at
 // lds + loff[k] (loff[k] >= 0) or in HBM at gsp[k]; word 0 is the row count.
-template <int ITEMS>
-__device__ __forceinline__ void apply_rows(const AggPlan& ap, int64_t r0, int64_t n, uint32_t keep,
+template <int ITEMS, class AP>
+__device__ __forceinline__ void apply_rows(const AP& ap, int64_t r0, int64_t n, uint32_t keep,
                                            const uint32_t (&w)[ITEMS], uint64_t* lds, const int (&loff)[ITEMS],
                                            uint64_t* const (&gsp)[ITEMS]) {
   static_for<0, ITEMS>([&](auto kk) __attribute__((always_inline)) {
@@ -183,7 +183,7 @@ __device__ __forceinline__ void apply_rows(const AggPlan& ap, int64_t r0, int64_
     else GlobalAtomics::add(&gsp[k][0], w[k]);
   });
   for (int i = 0; i < ap.naggs; ++i) {
-    const DAgg& ag = ap.aggs[i];
+    const auto& ag = ap.aggs[i];
     if (ag.op == GQ_COUNT_STAR) continue;
     uint64_t x[ITEMS];
     const uint32_t nn = agg_values<ITEMS>(ag, ap, r0, n, x) & keep;
@@ -215,7 +215,8 @@ __device__ __forceinline__ void apply_rows(const AggPlan& ap, int64_t r0, int64_
 }
 
 // HBM accumulators of a row's group (hashed or extra), or nullptr if the table is full.
-__device__ __forceinline__ uint64_t* global_acc(const GbArgs& a, uint64_t key, int special) {
+template <class GA>
+__device__ __forceinline__ uint64_t* global_acc(const GA& a, uint64_t key, int special) {
   int64_t s;
   if (special) {
     s = (int64_t)(a.cap + (uint64_t)(special - 1));
@@ -231,7 +232,8 @@ __device__ __forceinline__ uint64_t* global_acc(const GbArgs& a, uint64_t key, i
 }
 
 // Merge one group's accumulators into HBM.
-__device__ __forceinline__ void merge_words(const AggPlan& ap, uint64_t* dst, const uint64_t* src) {
+template <class AP>
+__device__ __forceinline__ void merge_words(const AP& ap, uint64_t* dst, const uint64_t* src) {
   for (int w = 0; w < ap.nacc; ++w) {
     const uint64_t v = src[w];
     switch (ap.wop[w]) {

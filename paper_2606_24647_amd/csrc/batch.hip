@@ -84,8 +84,8 @@ __global__ __launch_bounds__(BLOCK) void k_batch_agg(const BatchArgs a) {
     const int64_t t = s_t;
     if (t >= a.ntiles) break;
     const int f = __builtin_amdgcn_readfirstlane(s_f);
-    const GbArgs& g = a.frags[f];
-    const int64_t row0 = (t - a.tile_start[f]) * a.tile_rows;
+    const GQ_CONST_AS GbArgs& g = cref(a.frags + f);
+    const int64_t row0 = (t - cref(a.tile_start + f)) * a.tile_rows;
     const int64_t row1 = row0 + a.tile_rows < g.n ? row0 + a.tile_rows : g.n;
     const bool lds = g.lcap > 0;
     if (lds) {
@@ -139,8 +139,8 @@ __global__ __launch_bounds__(BLOCK) void k_batch_compact(const BatchArgs a) {
   constexpr int TILE = BLOCK * ITEMS;
   __shared__ uint32_t s_wave[NW];
   const int f = blockIdx.x;
-  const GbArgs& g = a.frags[f];
-  const BatchOut& bo = a.outs[f];
+  const GQ_CONST_AS GbArgs& g = cref(a.frags + f);
+  const GQ_CONST_AS BatchOut& bo = cref(a.outs + f);
   const int64_t total = (int64_t)g.cap + 2;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   // Radix fragments: the groups of the HBM table (special keys, overflow)
@@ -176,7 +176,7 @@ __global__ __launch_bounds__(BLOCK) void k_batch_compact(const BatchArgs a) {
       if (pos < bo.out_cap) {
         const bool extra = s >= (int64_t)g.cap;
         for (int j = 0; j < a.nk + a.naggs; ++j) {
-          const OCol& o = bo.out[j];
+          const auto& o = bo.out[j];
           int64_t v = 0;
           bool ok = true;
           if (j < a.nk) {
@@ -191,7 +191,7 @@ __global__ __launch_bounds__(BLOCK) void k_batch_compact(const BatchArgs a) {
               v = decode_field(g.kp, g.keys[s], j, &ok);
             }
           } else {
-            const DAgg& ag = g.ap.aggs[j - a.nk];
+            const auto& ag = g.ap.aggs[j - a.nk];
             const uint64_t* acc = g.acc + s * a.nacc;
             v = (int64_t)acc[ag.word];
             if ((ag.op == GQ_SUM || ag.op == GQ_MIN || ag.op == GQ_MAX) && ag.cword >= 0) ok = acc[ag.cword] != 0;
@@ -335,6 +335,7 @@ int gq_batch_plan_create(gq_ctx* ctx, const gq_fragment* frags, int nfrags, cons
   BrxArgs rx;
   std::memset(&rx, 0, sizeof(rx));
   std::vector<BrxFrag> rfs;
+  std::vector<int32_t> tile_frag, item_frag;
   int64_t rx_tiles = 0, rx_counts = 0, rx_items = 0, rx_rows = 0;
   size_t rx_scatter_lds = 0, rx_hist_lds = 0;
   {
@@ -375,8 +376,10 @@ int gq_batch_plan_create(gq_ctx* ctx, const gq_fragment* frags, int nfrags, cons
       rx_counts += x.tiles << rbits;
       rx_items += (int64_t)1 << rbits;
       rx_rows += g.n;
-      const size_t sl = brx_scatter_lds_bytes(rbits, x.in_bytes, rx.nv);
-      const size_t hl = align_up((size_t)4 << rbits, 16) + (size_t)x.in_bytes;
+      tile_frag.insert(tile_frag.end(), (size_t)x.tiles, (int32_t)rfs.size());
+      item_frag.insert(item_frag.end(), (size_t)1 << rbits, (int32_t)rfs.size());
+      const size_t sl = brx_scatter_lds_bytes(x);
+      const size_t hl = brx_hist_lds_bytes(x);
       if (sl > rx_scatter_lds) rx_scatter_lds = sl;
       if (hl > rx_hist_lds) rx_hist_lds = hl;
       rfs.push_back(x);
@@ -392,9 +395,11 @@ int gq_batch_plan_create(gq_ctx* ctx, const gq_fragment* frags, int nfrags, cons
     rx.nacc = nacc;
     rx.nk = spec->nkeys;
     rx.nitems = rx_items;
-    if (rx_scatter_lds > 150 * 1024) {
+    if (rx_scatter_lds > 150 * 1024 || rx_hist_lds > 150 * 1024) {
       // A staging layout this wide does not fit: every fragment takes the tile path.
       rfs.clear();
+      tile_frag.clear();
+      item_frag.clear();
       rx.nrf = 0;
       rx_tiles = rx_counts = rx_items = rx_rows = 0;
       for (int f = 0; f < nfrags; ++f) {
@@ -418,7 +423,9 @@ int gq_batch_plan_create(gq_ctx* ctx, const gq_fragment* frags, int nfrags, cons
   // Radix path: fragment descriptors, counts, starts, scan status, tuples.
   const int64_t rx_nscan = (rx_counts + 4095) / 4096;
   const size_t off_rf = off_ticket + 256;
-  const size_t off_cnt = align_up(off_rf + sizeof(BrxFrag) * rfs.size(), 256);
+  const size_t off_tf = align_up(off_rf + sizeof(BrxFrag) * rfs.size(), 256);
+  const size_t off_if = align_up(off_tf + 4 * tile_frag.size(), 256);
+  const size_t off_cnt = align_up(off_if + 4 * item_frag.size(), 256);
   const size_t off_st = align_up(off_cnt + 4 * (size_t)rx_counts, 256);
   const size_t off_ss = align_up(off_st + 8 * ((size_t)rx_counts + 1), 256);
   const size_t off_tup = align_up(off_ss + 8 * (size_t)(rx_nscan + 1), 256);
@@ -465,6 +472,8 @@ int gq_batch_plan_create(gq_ctx* ctx, const gq_fragment* frags, int nfrags, cons
   rx.frags = a.frags;
   rx.outs = a.outs;
   rx.rf = reinterpret_cast<const BrxFrag*>(base + off_rf);
+  rx.tile_frag = reinterpret_cast<const int32_t*>(base + off_tf);
+  rx.item_frag = reinterpret_cast<const int32_t*>(base + off_if);
   rx.counts = reinterpret_cast<uint32_t*>(base + off_cnt);
   rx.starts = reinterpret_cast<int64_t*>(base + off_st);
   rx.scan_status = reinterpret_cast<uint64_t*>(base + off_ss);
@@ -489,8 +498,12 @@ int gq_batch_plan_create(gq_ctx* ctx, const gq_fragment* frags, int nfrags, cons
           hipSuccess ||
       hipMemcpyAsync(base + off_ts, tstart.data(), 8 * ((size_t)nfrags + 1), hipMemcpyHostToDevice, stream) !=
           hipSuccess ||
-      (!rfs.empty() && hipMemcpyAsync(base + off_rf, rfs.data(), sizeof(BrxFrag) * rfs.size(),
-                                      hipMemcpyHostToDevice, stream) != hipSuccess) ||
+      (!rfs.empty() && (hipMemcpyAsync(base + off_rf, rfs.data(), sizeof(BrxFrag) * rfs.size(),
+                                       hipMemcpyHostToDevice, stream) != hipSuccess ||
+                        hipMemcpyAsync(base + off_tf, tile_frag.data(), 4 * tile_frag.size(),
+                                       hipMemcpyHostToDevice, stream) != hipSuccess ||
+                        hipMemcpyAsync(base + off_if, item_frag.data(), 4 * item_frag.size(),
+                                       hipMemcpyHostToDevice, stream) != hipSuccess)) ||
       hipStreamSynchronize(stream) != hipSuccess)
     return fail(GQ_ERR_HIP, "gq_batch_plan_create: descriptor upload failed");
 

@@ -41,6 +41,8 @@ struct BrxArgs {
   const GbArgs* frags;     // every fragment's plan (device)
   const BatchOut* outs;    // every fragment's output (device)
   const BrxFrag* rf;       // radix fragments (device)
+  const int32_t* tile_frag;  // radix fragment of every hist tile
+  const int32_t* item_frag;  // radix fragment of every region item
   int32_t nrf;
   int32_t lcap;            // LDS table slots of k_brx_agg
   int32_t nacc;
@@ -63,7 +65,9 @@ struct BrxArgs {
 size_t brx_lds_budget();
 int brx_lcap(int nacc);
 int64_t brx_tile_rows();
-size_t brx_scatter_lds_bytes(int rbits, int in_bytes, int nv);
+// Dynamic LDS of the scatter and hist kernels for one radix fragment.
+size_t brx_scatter_lds_bytes(const BrxFrag& x);
+size_t brx_hist_lds_bytes(const BrxFrag& x);
 // LDS staging of a fragment's columns; -1 if they exceed kBrxMaxStage.
 int brx_stage_plan(BrxFrag& x, const GbArgs& g, int nv, const int32_t* vagg, bool need_nn);
 // Enqueue init, histogram, scan, scatter and aggregation (graph-capturable).

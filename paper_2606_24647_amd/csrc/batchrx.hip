@@ -29,102 +29,104 @@ namespace gq {
 namespace {
 
 constexpr int kXBlock = 256;
-constexpr int kXSub = 1024;
+constexpr int kXSub = 512;                // scatter sub-tile; unit of the staging layout
 constexpr int kXRows = kXSub / kXBlock;
-constexpr int kXSubs = 16;
-constexpr int kXTile = kXSub * kXSubs;
+constexpr int kXTile = 16384;             // hist tile (one count per region)
+constexpr int kXSubs = kXTile / kXSub;
+constexpr int kHSub = 2048;               // hist sub-tile
+constexpr int kHRows = kHSub / kXBlock;
+constexpr int kHScale = kHSub / kXSub;    // hist staging offsets = layout offsets * kHScale
 constexpr int kXJoinBlock = 1024;
+constexpr int kXU = 4;                    // tuples per thread and round of k_brx_agg
+constexpr int kXV = 4;                    // value words held in registers
 
 __device__ __forceinline__ uint32_t bx_region(uint64_t h, int rbits) {
   return rbits ? (uint32_t)(h >> (64 - rbits)) : 0u;
 }
 
-// Rows r = i * 256 + t (i < kXRows) of a staged column: one type dispatch.
-__device__ __forceinline__ void bx_rows(const uint8_t* base, int type, int64_t (&v)[kXRows]) {
+// Rows r = i * 256 + t (i < ROWS) of a staged column: one type dispatch.
+template <int ROWS>
+__device__ __forceinline__ void bx_rows(const uint8_t* base, int type, int64_t (&v)[ROWS]) {
   const int t = threadIdx.x;
   switch (type) {
     case GQ_I8:
 #pragma unroll
-      for (int i = 0; i < kXRows; ++i) v[i] = reinterpret_cast<const int8_t*>(base)[i * kXBlock + t];
+      for (int i = 0; i < ROWS; ++i) v[i] = reinterpret_cast<const int8_t*>(base)[i * kXBlock + t];
       break;
     case GQ_I16:
 #pragma unroll
-      for (int i = 0; i < kXRows; ++i) v[i] = reinterpret_cast<const int16_t*>(base)[i * kXBlock + t];
+      for (int i = 0; i < ROWS; ++i) v[i] = reinterpret_cast<const int16_t*>(base)[i * kXBlock + t];
       break;
     case GQ_I32:
 #pragma unroll
-      for (int i = 0; i < kXRows; ++i) v[i] = reinterpret_cast<const int32_t*>(base)[i * kXBlock + t];
+      for (int i = 0; i < ROWS; ++i) v[i] = reinterpret_cast<const int32_t*>(base)[i * kXBlock + t];
       break;
     default:
 #pragma unroll
-      for (int i = 0; i < kXRows; ++i) v[i] = reinterpret_cast<const int64_t*>(base)[i * kXBlock + t];
+      for (int i = 0; i < ROWS; ++i) v[i] = reinterpret_cast<const int64_t*>(base)[i * kXBlock + t];
       break;
   }
 }
 
-// Radix fragment f of the tile with global index t: the last fragment whose
-// first tile is at most t.
-__device__ __forceinline__ int bx_frag_of_tile(const BrxArgs& a, int64_t t) {
-  int lo = 0, hi = a.nrf;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (a.rf[mid].tile0 <= t) lo = mid; else hi = mid;
-  }
-  return lo;
-}
+// Stage the sub-tile's columns (the first nst of the fragment's list); column
+// j lands at s_in + st_off[j] * scale.
+typedef const GQ_CONST_AS BrxFrag CFrag;
+typedef const GQ_CONST_AS GbArgs CArgs;
+typedef const GQ_CONST_AS DAgg CAgg;
 
-// Stage the sub-tile's columns (the first nst of the fragment's list).
-__device__ __forceinline__ void bx_stage(const BrxFrag& x, int nst, int64_t sbase, int nrows, uint8_t* s_in) {
-  for (int j = 0; j < nst; ++j) stage_col_lds<kXBlock>(x.st[j], sbase, nrows, s_in + x.st_off[j]);
+__device__ __forceinline__ void bx_stage(CFrag& x, int nst, int scale, int64_t sbase, int nrows,
+                                         uint8_t* s_in) {
+  for (int j = 0; j < nst; ++j) stage_col_lds<kXBlock>(x.st[j], sbase, nrows, s_in + x.st_off[j] * scale);
 }
 
 // Kept rows of the staged sub-tile and their group keys (packed or raw, with
 // the special kinds of make_keys: 0 hashed, 1 raw key EMPTY, 2 NULL raw key).
-__device__ __forceinline__ uint32_t bx_keep_keys(const BrxFrag& x, const GbArgs& g, const uint8_t* s_in,
-                                                 int64_t sbase, int nrows, uint64_t (&key)[kXRows],
-                                                 uint8_t (&special)[kXRows]) {
+template <int ROWS>
+__device__ __forceinline__ uint32_t bx_keep_keys(CFrag& x, CArgs& g, const uint8_t* s_in, int scale,
+                                                 int64_t sbase, int nrows, uint64_t (&key)[ROWS],
+                                                 uint8_t (&special)[ROWS]) {
   uint32_t keep = 0;
 #pragma unroll
-  for (int i = 0; i < kXRows; ++i) {
+  for (int i = 0; i < ROWS; ++i) {
     if (i * kXBlock + (int)threadIdx.x < nrows) keep |= 1u << i;
     key[i] = 0;
     special[i] = 0;
   }
   for (int p = 0; p < g.npreds; ++p) {
     const int j = x.pred_st[p];
-    int64_t v[kXRows];
-    bx_rows(s_in + x.st_off[j], x.st[j].type, v);
+    int64_t v[ROWS];
+    bx_rows<ROWS>(s_in + x.st_off[j] * scale, x.st[j].type, v);
     const int64_t lo = g.preds[p].lo, hi = g.preds[p].hi;
     if (g.preds[p].op == GQ_RANGE) {
 #pragma unroll
-      for (int i = 0; i < kXRows; ++i)
+      for (int i = 0; i < ROWS; ++i)
         if (v[i] < lo || v[i] > hi) keep &= ~(1u << i);
     } else {
 #pragma unroll
-      for (int i = 0; i < kXRows; ++i)
+      for (int i = 0; i < ROWS; ++i)
         if (v[i] == lo) keep &= ~(1u << i);
     }
     if (x.st[j].valid) {
 #pragma unroll
-      for (int i = 0; i < kXRows; ++i)
+      for (int i = 0; i < ROWS; ++i)
         if (((keep >> i) & 1u) && !valid_one(x.st[j], sbase + i * kXBlock + threadIdx.x)) keep &= ~(1u << i);
     }
   }
-  const KeyPlan& kp = g.kp;
+  const GQ_CONST_AS KeyPlan& kp = g.kp;
   for (int j = 0; j < kp.nk; ++j) {
     const int c = x.key_st[j];
-    int64_t v[kXRows];
-    bx_rows(s_in + x.st_off[c], x.st[c].type, v);
+    int64_t v[ROWS];
+    bx_rows<ROWS>(s_in + x.st_off[c] * scale, x.st[c].type, v);
     uint32_t vm = 0xffffffffu;
     if (kp.cols[j].valid) {
       vm = 0;
 #pragma unroll
-      for (int i = 0; i < kXRows; ++i)
+      for (int i = 0; i < ROWS; ++i)
         if (((keep >> i) & 1u) && valid_one(kp.cols[j], sbase + i * kXBlock + threadIdx.x)) vm |= 1u << i;
     }
     if (kp.mode == KEY_RAW64) {
 #pragma unroll
-      for (int i = 0; i < kXRows; ++i) {
+      for (int i = 0; i < ROWS; ++i) {
         key[i] = (uint64_t)v[i];
         special[i] = !((vm >> i) & 1u) ? 2 : (key[i] == kEmpty ? 1 : 0);
       }
@@ -132,7 +134,7 @@ __device__ __forceinline__ uint32_t bx_keep_keys(const BrxFrag& x, const GbArgs&
       const int w = kp.bits[j];
       const uint64_t mask = (w == 64) ? ~0ull : ((1ull << w) - 1);
 #pragma unroll
-      for (int i = 0; i < kXRows; ++i) {
+      for (int i = 0; i < ROWS; ++i) {
         uint64_t f = ((uint64_t)v[i] ^ (1ull << (w - 1))) & mask;
         if (kp.nullable[j]) f = ((vm >> i) & 1u) ? (f | (1ull << w)) : 0ull;
         key[i] |= f << kp.shift[j];
@@ -142,42 +144,43 @@ __device__ __forceinline__ uint32_t bx_keep_keys(const BrxFrag& x, const GbArgs&
   return keep;
 }
 
-// Aggregate input of ag for the thread's rows (product expression) and the
-// mask of rows whose input is non-NULL.
-__device__ __forceinline__ uint32_t bx_values(const BrxFrag& x, const GbArgs& g, const DAgg& ag, const uint8_t* s_in,
-                                              int64_t sbase, int nrows, uint64_t (&xv)[kXRows]) {
-  uint32_t nn = 0xffffffffu;
-#pragma unroll
-  for (int i = 0; i < kXRows; ++i) xv[i] = 1;
+// Input of aggregate ag for staged row r (global row grow): the product of its
+// factors; *nn is cleared when a referenced column is NULL.
+__device__ __forceinline__ uint64_t bx_value_row(CFrag& x, CArgs& g, CAgg& ag,
+                                                 const uint8_t* s_in, int r, int64_t grow, bool* nn) {
+  uint64_t xv = 1;
   for (int f = 0; f < ag.nf; ++f) {
-    const DFactor& fa = ag.f[f];
+    const GQ_CONST_AS DFactor& fa = ag.f[f];
     const uint64_t k = (uint64_t)fa.k;
     if (fa.kind == GQ_F_CONST) {
-#pragma unroll
-      for (int i = 0; i < kXRows; ++i) xv[i] *= k;
+      xv *= k;
       continue;
     }
     const int j = x.val_st[fa.v];
-    int64_t v[kXRows];
-    bx_rows(s_in + x.st_off[j], x.st[j].type, v);
-    if (g.ap.vals[fa.v].valid) {
-#pragma unroll
-      for (int i = 0; i < kXRows; ++i)
-        if (i * kXBlock + (int)threadIdx.x < nrows && !valid_one(g.ap.vals[fa.v], sbase + i * kXBlock + threadIdx.x))
-          nn &= ~(1u << i);
-    }
-    if (fa.kind == GQ_F_COL) {
-#pragma unroll
-      for (int i = 0; i < kXRows; ++i) xv[i] *= (uint64_t)v[i];
-    } else if (fa.kind == GQ_F_K_MINUS_COL) {
-#pragma unroll
-      for (int i = 0; i < kXRows; ++i) xv[i] *= k - (uint64_t)v[i];
-    } else {
-#pragma unroll
-      for (int i = 0; i < kXRows; ++i) xv[i] *= k + (uint64_t)v[i];
-    }
+    const uint64_t v = (uint64_t)lds_value(s_in + x.st_off[j], r, x.st[j].type);
+    if (g.ap.vals[fa.v].valid && !valid_one(g.ap.vals[fa.v], grow)) *nn = false;
+    if (fa.kind == GQ_F_COL) xv *= v;
+    else if (fa.kind == GQ_F_K_MINUS_COL) xv *= k - v;
+    else xv *= k + v;
   }
-  return nn;
+  return xv;
+}
+
+// The aggregate inputs of staged row r as a tuple's value words (dst[vword])
+// and the mask of aggregates whose input is non-NULL.
+__device__ __forceinline__ uint32_t bx_tuple_values(const BrxArgs& a, CFrag& x, CArgs& g,
+                                                    const uint8_t* s_in, int r, int64_t grow, uint64_t* dst) {
+  uint32_t nnm = 0xffu;
+  for (int gi = 0; gi < g.ap.naggs; ++gi) {
+    CAgg& ag = g.ap.aggs[gi];
+    const int vw = a.vword[gi];
+    if (vw < 0 && !(a.need_nn && ag.op == GQ_COUNT)) continue;
+    bool nn = true;
+    const uint64_t xv = bx_value_row(x, g, ag, s_in, r, grow, &nn);
+    if (vw >= 0) dst[vw] = xv;
+    if (!nn) nnm &= ~(1u << gi);
+  }
+  return nnm;
 }
 
 // Add one row into the fragment's HBM table (special keys and overflow); tv
@@ -201,6 +204,28 @@ __device__ void bx_global_row(const GbArgs& g, const int32_t* vword, uint64_t ke
   }
 }
 
+// The same for staged row r of a sub-tile, its inputs read from LDS.
+__device__ void bx_global_row_staged(CFrag& x, CArgs& g, uint64_t key, int special,
+                                     const uint8_t* s_in, int r, int64_t grow) {
+  uint64_t* acc = global_acc(gref(g), key, special);
+  if (!acc) return;
+  GlobalAtomics::add(&acc[0], 1);
+  for (int i = 0; i < g.ap.naggs; ++i) {
+    CAgg& ag = g.ap.aggs[i];
+    if (ag.op == GQ_COUNT_STAR) continue;
+    bool nn = true;
+    const uint64_t xv = bx_value_row(x, g, ag, s_in, r, grow, &nn);
+    if (!nn) continue;
+    switch (ag.op) {
+      case GQ_SUM: GlobalAtomics::add(&acc[ag.word], xv); break;
+      case GQ_COUNT: GlobalAtomics::add(&acc[ag.word], 1); break;
+      case GQ_MIN: GlobalAtomics::min(&acc[ag.word], (int64_t)xv); break;
+      default: GlobalAtomics::max(&acc[ag.word], (int64_t)xv); break;
+    }
+    if (ag.cword >= 0) GlobalAtomics::add(&acc[ag.cword], 1);
+  }
+}
+
 // Reset the counters of one replay: scan status and tickets, item ticket, and
 // the group counts of the radix fragments.
 __global__ void k_brx_init(const BrxArgs a) {
@@ -214,30 +239,32 @@ __global__ void k_brx_init(const BrxArgs a) {
   for (int64_t i = i0; i < a.nrf; i += step) *a.outs[a.rf[i].f].d_groups = 0;
 }
 
+// Region counts of one hist tile, from 2048-row sub-tiles of the predicate and
+// key columns.
 __global__ __launch_bounds__(kXBlock) void k_brx_hist(const BrxArgs a) {
   extern __shared__ __attribute__((aligned(16))) uint8_t s_raw[];
   const int64_t t = blockIdx.x;
-  const int fi = bx_frag_of_tile(a, t);
-  const BrxFrag& x = a.rf[fi];
-  const GbArgs& g = a.frags[x.f];
+  const int fi = a.tile_frag[t];
+  CFrag& x = cref(a.rf + fi);
+  CArgs& g = cref(a.frags + x.f);
   const int R = 1 << x.rbits;
   uint32_t* s_hist = reinterpret_cast<uint32_t*>(s_raw);
   uint8_t* s_in = s_raw + align_up((size_t)R * 4, 16);
   for (int i = threadIdx.x; i < R; i += kXBlock) s_hist[i] = 0;
   const int64_t tl = t - x.tile0;
-  for (int sub = 0; sub < kXSubs; ++sub) {
-    const int64_t sbase = tl * kXTile + (int64_t)sub * kXSub;
+  for (int sub = 0; sub < kXTile / kHSub; ++sub) {
+    const int64_t sbase = tl * kXTile + (int64_t)sub * kHSub;
     if (sbase >= g.n) break;
-    const int nrows = g.n - sbase < kXSub ? (int)(g.n - sbase) : kXSub;
+    const int nrows = g.n - sbase < kHSub ? (int)(g.n - sbase) : kHSub;
     __syncthreads();
-    bx_stage(x, x.nst_hist, sbase, nrows, s_in);
+    bx_stage(x, x.nst_hist, kHScale, sbase, nrows, s_in);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    uint64_t key[kXRows];
-    uint8_t special[kXRows];
-    const uint32_t keep = bx_keep_keys(x, g, s_in, sbase, nrows, key, special);
+    uint64_t key[kHRows];
+    uint8_t special[kHRows];
+    const uint32_t keep = bx_keep_keys<kHRows>(x, g, s_in, kHScale, sbase, nrows, key, special);
 #pragma unroll
-    for (int i = 0; i < kXRows; ++i) {
+    for (int i = 0; i < kHRows; ++i) {
       const uint64_t h = region_hash(key[i]);
       if (((keep >> i) & 1u) && !special[i] && h != kEmpty) atomicAdd(&s_hist[bx_region(h, x.rbits)], 1u);
     }
@@ -294,33 +321,31 @@ __global__ __launch_bounds__(BLOCK) void k_brx_scan(const uint32_t* counts, int6
   if (tile == nblocks - 1 && threadIdx.x == 0) starts[m] = s_excl + btot;
 }
 
-// LDS of k_brx_scatter: R region counters and bases (u32), the staged input,
-// then per row: pp (u32: region << 16 | rank, ~0 = no tuple), src (u16), and
-// the tuple (key hash, nv value words) and its non-NULL mask.
-__host__ __device__ inline size_t bx_scatter_lds(int R, int in_bytes, int nv) {
-  return align_up((size_t)2 * R * 8, 16) + align_up((size_t)in_bytes, 16) + (size_t)kXSub * (4 + 2) +
-         (size_t)kXSub * 8 * (1 + nv) + (size_t)kXSub;
+// LDS of k_brx_scatter: R region bases (int64) and counters (u32), the staged
+// sub-tile, then per row: pp (u32: region << 16 | rank, ~0 = no tuple), src
+// (u16, rows in tuple order) and the key hash.
+__host__ __device__ inline size_t bx_scatter_lds(int R, int in_bytes) {
+  return align_up((size_t)R * 12, 16) + align_up((size_t)in_bytes, 16) + (size_t)kXSub * (4 + 2 + 8);
 }
 
 __global__ __launch_bounds__(kXBlock) void k_brx_scatter(const BrxArgs a) {
   extern __shared__ __attribute__((aligned(16))) uint8_t s_raw[];
   const int64_t t = blockIdx.x;
-  const int fi = bx_frag_of_tile(a, t);
-  const BrxFrag& x = a.rf[fi];
-  const GbArgs& g = a.frags[x.f];
+  const int fi = a.tile_frag[t];
+  CFrag& x = cref(a.rf + fi);
+  CArgs& g = cref(a.frags + x.f);
   const int R = 1 << x.rbits;
-  const int nv = a.nv;
   int64_t* s_base = reinterpret_cast<int64_t*>(s_raw);
   uint32_t* s_cnt = reinterpret_cast<uint32_t*>(s_base + R);
-  uint8_t* s_in = s_raw + align_up((size_t)2 * R * 8, 16);
-  uint32_t* s_pp = reinterpret_cast<uint32_t*>(s_in + align_up((size_t)x.in_bytes, 16));
+  uint8_t* s_in = s_raw + align_up((size_t)R * 12, 16);
+  uint64_t* s_h = reinterpret_cast<uint64_t*>(s_in + align_up((size_t)x.in_bytes, 16));
+  uint32_t* s_pp = reinterpret_cast<uint32_t*>(s_h + kXSub);
   uint16_t* s_src = reinterpret_cast<uint16_t*>(s_pp + kXSub);
-  uint64_t* s_tup = reinterpret_cast<uint64_t*>(align_up(reinterpret_cast<uintptr_t>(s_src + kXSub), 8));
-  uint8_t* s_nn = reinterpret_cast<uint8_t*>(s_tup + (size_t)kXSub * (1 + nv));
   __shared__ uint32_t s_wsum[kXBlock / kWave];
   __shared__ uint32_t s_total;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const int64_t tl = t - x.tile0;
+  const int tw = 1 + a.nv;
   for (int r = threadIdx.x; r < R; r += kXBlock) s_base[r] = a.starts[x.cbase + (int64_t)r * x.tiles + tl];
   const int per = (R + kXBlock - 1) / kXBlock;  // <= 4
 
@@ -329,38 +354,12 @@ __global__ __launch_bounds__(kXBlock) void k_brx_scatter(const BrxArgs a) {
     if (sbase >= g.n) break;
     const int nrows = g.n - sbase < kXSub ? (int)(g.n - sbase) : kXSub;
     for (int r = threadIdx.x; r < R; r += kXBlock) s_cnt[r] = 0;
-    bx_stage(x, x.nst, sbase, nrows, s_in);
+    bx_stage(x, x.nst, 1, sbase, nrows, s_in);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     uint64_t key[kXRows];
     uint8_t special[kXRows];
-    const uint32_t keep = bx_keep_keys(x, g, s_in, sbase, nrows, key, special);
-    // Tuples: key hash and the aggregate inputs, in the row's tuple slot.
-    uint32_t nnm[kXRows];
-#pragma unroll
-    for (int i = 0; i < kXRows; ++i) nnm[i] = 0xffu;
-    for (int v = 0; v < nv; ++v) {
-      const int gi = a.vagg[v];
-      uint64_t xv[kXRows];
-      const uint32_t nn = bx_values(x, g, g.ap.aggs[gi], s_in, sbase, nrows, xv);
-#pragma unroll
-      for (int i = 0; i < kXRows; ++i) {
-        s_tup[(size_t)(i * kXBlock + threadIdx.x) * (1 + nv) + 1 + v] = xv[i];
-        if (!((nn >> i) & 1u)) nnm[i] &= ~(1u << gi);
-      }
-    }
-    if (a.need_nn) {
-      // COUNT(col) inputs carry no value word, only their non-NULL bit.
-      for (int gi = 0; gi < g.ap.naggs; ++gi) {
-        const DAgg& ag = g.ap.aggs[gi];
-        if (ag.op != GQ_COUNT) continue;
-        uint64_t xv[kXRows];
-        const uint32_t nn = bx_values(x, g, ag, s_in, sbase, nrows, xv);
-#pragma unroll
-        for (int i = 0; i < kXRows; ++i)
-          if (!((nn >> i) & 1u)) nnm[i] &= ~(1u << gi);
-      }
-    }
+    const uint32_t keep = bx_keep_keys<kXRows>(x, g, s_in, 1, sbase, nrows, key, special);
 #pragma unroll
     for (int i = 0; i < kXRows; ++i) {
       const int r = i * kXBlock + threadIdx.x;
@@ -370,13 +369,11 @@ __global__ __launch_bounds__(kXBlock) void k_brx_scatter(const BrxArgs a) {
       if (special[i] || h == kEmpty) {
         // Raw key EMPTY or NULL, or the one key whose hash is the LDS table's
         // empty marker: straight into the fragment's HBM table.
-        bx_global_row(g, a.vword, key[i], special[i], s_tup + (size_t)r * (1 + nv) + 1, nnm[i]);
+        bx_global_row_staged(x, g, key[i], special[i], s_in, r, sbase + r);
         continue;
       }
-      const uint32_t reg = bx_region(h, x.rbits);
-      s_pp[r] = (reg << 16) | atomicAdd(&s_cnt[reg], 1u);
-      s_tup[(size_t)r * (1 + nv)] = h;
-      if (a.need_nn) s_nn[r] = (uint8_t)nnm[i];
+      s_pp[r] = (bx_region(h, x.rbits) << 16) | atomicAdd(&s_cnt[bx_region(h, x.rbits)], 1u);
+      s_h[r] = h;
     }
     __syncthreads();
     // Exclusive scan of the region counts.
@@ -422,16 +419,17 @@ __global__ __launch_bounds__(kXBlock) void k_brx_scatter(const BrxArgs a) {
       if (pp != 0xffffffffu) s_src[s_cnt[pp >> 16] + (pp & 0xffffu)] = (uint16_t)r;
     }
     __syncthreads();
+    // Tuples in region order: consecutive threads write consecutive tuples of
+    // a region's run; value words are computed here from the staged columns.
     const int total = (int)s_total;
-    const int tw = 1 + nv;
     for (int k = threadIdx.x; k < total; k += kXBlock) {
       const int r = s_src[k];
       const uint32_t q = s_pp[r] >> 16;
       const int64_t pos = s_base[q] + (k - (int)s_cnt[q]);
       uint64_t* dst = a.tup + (size_t)pos * tw;
-      const uint64_t* src = s_tup + (size_t)r * tw;
-      for (int w = 0; w < tw; ++w) dst[w] = src[w];
-      if (a.need_nn) a.tnn[pos] = s_nn[r];
+      dst[0] = s_h[r];
+      const uint32_t nnm = bx_tuple_values(a, x, g, s_in, r, sbase + r, dst + 1);
+      if (a.need_nn) a.tnn[pos] = (uint8_t)nnm;
     }
     __syncthreads();
 #pragma unroll
@@ -476,7 +474,7 @@ __device__ __forceinline__ int bx_find(const uint64_t* s_keys, int lcap, uint64_
   return -1;
 }
 
-__device__ __forceinline__ void bx_write(const OCol& o, int64_t g, int64_t v) {
+__device__ __forceinline__ void bx_write(const GQ_CONST_AS OCol& o, int64_t g, int64_t v) {
   switch (o.type) {
     case GQ_I8: o.data[g] = (uint8_t)v; break;
     case GQ_I16: reinterpret_cast<int16_t*>(o.data)[g] = (int16_t)v; break;
@@ -485,21 +483,11 @@ __device__ __forceinline__ void bx_write(const OCol& o, int64_t g, int64_t v) {
   }
 }
 
-__device__ __forceinline__ void bx_valid(const OCol& o, int64_t g, bool ok) {
+__device__ __forceinline__ void bx_valid(const GQ_CONST_AS OCol& o, int64_t g, bool ok) {
   if (!o.valid) return;
   const uint32_t bit = 1u << (g & 31);
   if (ok) atomicOr(&o.valid[g >> 5], bit);
   else atomicAnd(&o.valid[g >> 5], ~bit);
-}
-
-// Radix fragment of region item it: the last fragment whose first item <= it.
-__device__ __forceinline__ int bx_frag_of_item(const BrxArgs& a, int64_t it) {
-  int lo = 0, hi = a.nrf;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (a.rf[mid].item0 <= it) lo = mid; else hi = mid;
-  }
-  return lo;
 }
 
 __global__ __launch_bounds__(kXJoinBlock) void k_brx_agg(const BrxArgs a) {
@@ -518,10 +506,10 @@ __global__ __launch_bounds__(kXJoinBlock) void k_brx_agg(const BrxArgs a) {
     __syncthreads();
     const int64_t it = s_it;
     if (it >= a.nitems) break;
-    const int fi = bx_frag_of_item(a, it);
-    const BrxFrag& x = a.rf[fi];
-    const GbArgs& g = a.frags[x.f];
-    const BatchOutRef& bo = a.outs[x.f];
+    const int fi = a.item_frag[it];
+    CFrag& x = cref(a.rf + fi);
+    CArgs& g = cref(a.frags + x.f);
+    const GQ_CONST_AS BatchOut& bo = cref(a.outs + x.f);
     const int r = (int)(it - x.item0);
     const int64_t e0 = x.cbase + (int64_t)r * x.tiles;
     const int64_t t0 = a.starts[e0], t1 = a.starts[e0 + x.tiles];
@@ -535,38 +523,79 @@ __global__ __launch_bounds__(kXJoinBlock) void k_brx_agg(const BrxArgs a) {
     // 2. Tuples: insert or find in LDS, accumulate; a tuple whose key finds no
     // slot is retried after the round's barrier (another lane may have taken
     // the slot for the same key) and otherwise goes to the HBM table.
-    for (int64_t base = t0; base < t1; base += kXJoinBlock) {
-      const int64_t i = base + threadIdx.x;
-      int slot = -1;
-      uint64_t h = 0;
-      if (i < t1) {
-        h = a.tup[(size_t)i * tw];
-        slot = bx_find_insert(s_keys, L, h);
+    // kXU tuples per thread and round, all loads issued first; value words
+    // are held in registers when there are at most kXV of them.
+    const int nv = a.nv;
+    const bool regs = nv <= kXV;
+    for (int64_t base = t0; base < t1; base += (int64_t)kXJoinBlock * kXU) {
+      uint64_t h[kXU];
+      uint64_t v[kXU][kXV];
+      uint32_t nnm[kXU];
+      int slot[kXU];
+#pragma unroll
+      for (int u = 0; u < kXU; ++u) {
+        const int64_t i = base + (int64_t)u * kXJoinBlock + threadIdx.x;
+        h[u] = 0;
+        nnm[u] = 0xffu;
+#pragma unroll
+        for (int w = 0; w < kXV; ++w) v[u][w] = 0;
+        if (i < t1) {
+          const uint64_t* tp = a.tup + (size_t)i * tw;
+          h[u] = tp[0];
+          if (regs) {
+#pragma unroll
+            for (int w = 0; w < kXV; ++w)
+              if (w < nv) v[u][w] = tp[1 + w];
+          }
+          if (a.need_nn) nnm[u] = a.tnn[i];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kXU; ++u) {
+        const int64_t i = base + (int64_t)u * kXJoinBlock + threadIdx.x;
+        slot[u] = i < t1 ? bx_find_insert(s_keys, L, h[u]) : L;
       }
       __syncthreads();
-      const bool retry = i < t1 && slot < 0;
-      if (retry) slot = bx_find(s_keys, L, h);
-      if (i < t1) {
-        const uint32_t nnm = a.need_nn ? a.tnn[i] : 0xffu;
+#pragma unroll
+      for (int u = 0; u < kXU; ++u) {
+        if (slot[u] < 0) slot[u] = bx_find(s_keys, L, h[u]);
+        if (slot[u] == L) continue;  // no tuple
+        const int64_t i = base + (int64_t)u * kXJoinBlock + threadIdx.x;
         const uint64_t* tv = a.tup + (size_t)i * tw + 1;
-        if (slot >= 0) {
-          uint64_t* acc = s_acc + (size_t)slot * nacc;
-          atomicAdd((unsigned long long*)&acc[0], 1ull);
-          for (int gi = 0; gi < g.ap.naggs; ++gi) {
-            const DAgg& ag = g.ap.aggs[gi];
-            if (ag.op == GQ_COUNT_STAR || !((nnm >> gi) & 1u)) continue;
-            const int vw = a.vword[gi];
-            const uint64_t xv = vw >= 0 ? tv[vw] : 0;
+        if (slot[u] < 0) {
+          bx_global_row(gref(g), a.vword, region_unhash(h[u]), 0, tv, nnm[u]);
+          continue;
+        }
+        uint64_t* acc = s_acc + (size_t)slot[u] * nacc;
+        atomicAdd((unsigned long long*)&acc[0], 1ull);
+        if (regs) {
+#pragma unroll
+          for (int w = 0; w < kXV; ++w) {
+            if (w >= nv) break;
+            CAgg& ag = g.ap.aggs[a.vagg[w]];
+            if (!((nnm[u] >> a.vagg[w]) & 1u)) continue;
+            const uint64_t xv = v[u][w];
             switch (ag.op) {
               case GQ_SUM: atomicAdd((unsigned long long*)&acc[ag.word], (unsigned long long)xv); break;
-              case GQ_COUNT: atomicAdd((unsigned long long*)&acc[ag.word], 1ull); break;
               case GQ_MIN: atomicMin((long long*)&acc[ag.word], (long long)xv); break;
               default: atomicMax((long long*)&acc[ag.word], (long long)xv); break;
             }
-            if (ag.cword >= 0) atomicAdd((unsigned long long*)&acc[ag.cword], 1ull);
           }
-        } else {
-          bx_global_row(g, a.vword, region_unhash(h), 0, tv, nnm);
+        }
+        for (int gi = 0; gi < g.ap.naggs; ++gi) {
+          CAgg& ag = g.ap.aggs[gi];
+          if (ag.op == GQ_COUNT_STAR || !((nnm[u] >> gi) & 1u)) continue;
+          if (ag.op == GQ_COUNT) {
+            atomicAdd((unsigned long long*)&acc[ag.word], 1ull);
+          } else if (!regs) {
+            const uint64_t xv = tv[a.vword[gi]];
+            switch (ag.op) {
+              case GQ_SUM: atomicAdd((unsigned long long*)&acc[ag.word], (unsigned long long)xv); break;
+              case GQ_MIN: atomicMin((long long*)&acc[ag.word], (long long)xv); break;
+              default: atomicMax((long long*)&acc[ag.word], (long long)xv); break;
+            }
+          }
+          if (ag.cword >= 0) atomicAdd((unsigned long long*)&acc[ag.cword], 1ull);
         }
       }
     }
@@ -614,7 +643,7 @@ __global__ __launch_bounds__(kXJoinBlock) void k_brx_agg(const BrxArgs a) {
           }
           const uint64_t* acc = s_acc + (size_t)i * nacc;
           for (int j = 0; j < g.ap.naggs; ++j) {
-            const DAgg& ag = g.ap.aggs[j];
+            CAgg& ag = g.ap.aggs[j];
             int64_t v = (int64_t)acc[ag.word];
             bool ok = true;
             if ((ag.op == GQ_SUM || ag.op == GQ_MIN || ag.op == GQ_MAX) && ag.cword >= 0) ok = acc[ag.cword] != 0;
@@ -644,7 +673,12 @@ int brx_lcap(int nacc) {
 
 int64_t brx_tile_rows() { return kXTile; }
 
-size_t brx_scatter_lds_bytes(int rbits, int in_bytes, int nv) { return bx_scatter_lds(1 << rbits, in_bytes, nv); }
+size_t brx_scatter_lds_bytes(const BrxFrag& x) { return bx_scatter_lds(1 << x.rbits, x.in_bytes); }
+
+size_t brx_hist_lds_bytes(const BrxFrag& x) {
+  const int hist_in = x.nst_hist < x.nst ? x.st_off[x.nst_hist] : x.in_bytes;
+  return align_up((size_t)4 << x.rbits, 16) + (size_t)hist_in * kHScale;
+}
 
 int brx_stage_plan(BrxFrag& x, const GbArgs& g, int nv, const int32_t* vagg, bool need_nn) {
   std::memset(x.st_off, 0, sizeof(x.st_off));

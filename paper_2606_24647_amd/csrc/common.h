@@ -107,6 +107,21 @@ struct DCol {
   int32_t pad;
 };
 
+// Read-only descriptors in device memory (plans of batched fragments) are read
+// through the constant address space: uniform loads from it are scalar loads,
+// also after the kernel's own global stores, which would otherwise turn every
+// descriptor read into a vector load with a full memory round trip.
+#define GQ_CONST_AS __attribute__((address_space(4)))
+template <class T>
+__device__ __forceinline__ const GQ_CONST_AS T& cref(const T* p) {
+  return *(const GQ_CONST_AS T*)p;
+}
+// Back to a generic reference, for rarely taken paths.
+template <class T>
+__device__ __forceinline__ const T& gref(const GQ_CONST_AS T& r) {
+  return *(const T*)&r;
+}
+
 // Output column.
 struct OCol {
   uint8_t* data;
@@ -148,7 +163,8 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nblocks) {
   return x * per + (x < rem ? x : rem) + i;
 }
 
-__device__ __forceinline__ int64_t load_one(const DCol& c, int64_t i) {
+template <class C>
+__device__ __forceinline__ int64_t load_one(const C& c, int64_t i) {
   switch (c.type) {
     case GQ_I8: return (int64_t)((const int8_t*)c.data)[i];
     case GQ_I16: return (int64_t)((const int16_t*)c.data)[i];
@@ -157,7 +173,8 @@ __device__ __forceinline__ int64_t load_one(const DCol& c, int64_t i) {
   }
 }
 
-__device__ __forceinline__ bool valid_one(const DCol& c, int64_t i) {
+template <class C>
+__device__ __forceinline__ bool valid_one(const C& c, int64_t i) {
   if (c.valid == nullptr) return true;
   int64_t b = c.voff + i;
   return (c.valid[b >> 3] >> (b & 7)) & 1;
@@ -188,8 +205,8 @@ __device__ __forceinline__ int ld4(const uint8_t* p) {
 // sign-extended.  Uses 128-bit loads (or the widest that covers ITEMS*width
 // bytes) when the whole group is in range and the slice is aligned for it;
 // rows past n read as 0.
-template <int ITEMS, bool NT = false>
-__device__ __forceinline__ void load_items(const DCol& c, int64_t r0, int64_t n, int64_t (&v)[ITEMS]) {
+template <int ITEMS, bool NT = false, class C = DCol>
+__device__ __forceinline__ void load_items(const C& c, int64_t r0, int64_t n, int64_t (&v)[ITEMS]) {
   const int w = type_width(c.type);
   const int need = ITEMS * w < 16 ? ITEMS * w : 16;
   if (r0 + ITEMS <= n && c.align >= need) {
@@ -278,8 +295,8 @@ __device__ __forceinline__ void load_items(const DCol& c, int64_t r0, int64_t n,
 }
 
 // Validity bits of rows r0..r0+ITEMS-1 as a bit mask (bit k = row r0+k).
-template <int ITEMS>
-__device__ __forceinline__ uint32_t valid_items(const DCol& c, int64_t r0, int64_t n) {
+template <int ITEMS, class C>
+__device__ __forceinline__ uint32_t valid_items(const C& c, int64_t r0, int64_t n) {
   uint32_t m = 0;
 #pragma unroll
   for (int k = 0; k < ITEMS; ++k)
@@ -287,7 +304,8 @@ __device__ __forceinline__ uint32_t valid_items(const DCol& c, int64_t r0, int64
   return m;
 }
 
-__device__ __forceinline__ bool pred_pass(const DPred& p, int64_t v) {
+template <class P>
+__device__ __forceinline__ bool pred_pass(const P& p, int64_t v) {
   return p.op == GQ_RANGE ? (v >= p.lo && v <= p.hi) : (v != p.lo);
 }
 
@@ -297,8 +315,8 @@ __device__ __forceinline__ bool pred_pass(const DPred& p, int64_t v) {
 // Slices that are not 16-byte aligned, and the bytes after the last whole
 // 16-byte chunk, are copied byte by byte.  dst is 16-byte aligned.  Returns
 // without waiting: the caller waits (s_waitcnt) and synchronises the block.
-template <int BLOCK>
-__device__ __forceinline__ void stage_col_lds(const DCol& c, int64_t sbase, int nrows, uint8_t* dst) {
+template <int BLOCK, class C>
+__device__ __forceinline__ void stage_col_lds(const C& c, int64_t sbase, int nrows, uint8_t* dst) {
   const int w = type_width(c.type);
   const uint8_t* src = c.data + sbase * w;
   const int nb = nrows * w;

@@ -55,7 +55,8 @@ struct KeyPlan {
 };
 
 // Decode key column j of a packed key (value, valid).
-__device__ __forceinline__ int64_t decode_field(const KeyPlan& kp, uint64_t key, int j, bool* valid) {
+template <class KP>
+__device__ __forceinline__ int64_t decode_field(const KP& kp, uint64_t key, int j, bool* valid) {
   const int w = kp.bits[j];
   const uint64_t mask = (w == 64) ? ~0ull : ((1ull << w) - 1);
   uint64_t f = key >> kp.shift[j];
