@@ -384,7 +384,7 @@ typedef struct gq_batch_spec {
   int32_t radix_min_groups; /* fragments expecting at least this many groups are
                                partitioned by key hash and aggregated in LDS
                                region by region (no per-row HBM atomics);
-                               0 = 2048, -1 = never */
+                               0 = one more than lds_max_groups, -1 = never */
 } gq_batch_spec;
 
 typedef struct gq_batch_plan gq_batch_plan;

@@ -1,8 +1,10 @@
 """Autotuner for batched fragment plans.
 
-Chooses the hash-table load factor, the LDS-privatisation threshold, the tile
-size and the persistent grid size of a gq_batch_plan by timing candidate plans
-on a stratified sample of the fragments, and caches the choice in a JSON file
+Chooses the radix threshold (fragments expecting more groups are partitioned
+and aggregated in LDS region by region), the hash-table load factor, the
+LDS-privatisation threshold, the tile size and the persistent grid size of a
+gq_batch_plan by coordinate descent over candidate plans timed on a stratified
+sample of the fragments, and caches the choice in a JSON file
 keyed by the device name and a coarse shape bucket of the workload (number of
 fragments, total rows, median cardinality, each as a power of two).
 
@@ -10,7 +12,6 @@ Cache file: $GQ_AUTOTUNE_CACHE, else ~/.cache/gq/autotune.json.
 """
 from __future__ import annotations
 
-import itertools
 import json
 import math
 import os
@@ -21,11 +22,14 @@ import torch
 from . import gq
 
 CANDIDATES = {
+    "radix_min_groups": [-1, 257, 1024, 4096],
     "lds_max_groups": [-1, 64, 256],
     "load_factor": [0.5, 0.7],
     "tile_rows": [4096, 8192, 16384],
     "blocks_per_cu": [2, 4, 8],
 }
+# Starting point of the search (the library's defaults, radix from 257 groups).
+START = {"radix_min_groups": 257, "lds_max_groups": 256, "load_factor": 0.5, "tile_rows": 8192, "blocks_per_cu": 4}
 
 
 def cache_path() -> str:
@@ -60,7 +64,7 @@ def _save(d):
     os.replace(tmp, p)
 
 
-def sample_fragments(frags, k=256, seed=0):
+def sample_fragments(frags, k=512, seed=0):
     """Up to k fragments, stratified by row count so that every size class appears."""
     if len(frags) <= k:
         return list(frags)
@@ -95,16 +99,33 @@ def best_batch_config(ctx, frags, keys, aggs, use_cache=True) -> dict:
     if key in cache:
         return dict(cache[key]["config"])
     sample = sample_fragments(frags)
-    best, best_ms = None, float("inf")
-    results = []
-    names = list(CANDIDATES)
-    for values in itertools.product(*(CANDIDATES[n] for n in names)):
-        cfg = dict(zip(names, values))
-        ms = time_plan(ctx, sample, keys, aggs, cfg)
-        results.append((ms, cfg))
-        if ms < best_ms:
-            best, best_ms = cfg, ms
-    cache[key] = {"config": best, "sample_ms": best_ms, "sample_fragments": len(sample),
+    # Coordinate descent: each parameter in turn over its candidates, the others
+    # at their best so far; two sweeps.
+    best = dict(START)
+    best_ms = time_plan(ctx, sample, keys, aggs, best)
+    results = [(best_ms, dict(best))]
+    for _ in range(2):
+        changed = False
+        for name, values in CANDIDATES.items():
+            for v in values:
+                if v == best[name]:
+                    continue
+                cfg = dict(best, **{name: v})
+                ms = time_plan(ctx, sample, keys, aggs, cfg)
+                results.append((ms, cfg))
+                if ms < best_ms:
+                    best, best_ms, changed = cfg, ms, True
+        if not changed:
+            break
+    full_ms = None
+    if len(sample) < len(frags) and best != START:
+        # The sample's winner must also beat the starting point on the whole
+        # workload (fixed per-launch costs weigh more in a small sample).
+        full_ms = time_plan(ctx, frags, keys, aggs, best)
+        start_ms = time_plan(ctx, frags, keys, aggs, START)
+        if start_ms <= full_ms:
+            best, full_ms = dict(START), start_ms
+    cache[key] = {"config": best, "sample_ms": best_ms, "full_ms": full_ms, "sample_fragments": len(sample),
                   "tried": len(results)}
     if use_cache:
         _save(cache)

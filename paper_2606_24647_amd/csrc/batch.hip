@@ -273,8 +273,9 @@ int gq_batch_plan_create(gq_ctx* ctx, const gq_fragment* frags, int nfrags, cons
     return set_error(ctx, GQ_ERR_INVALID, "gq_batch_plan_create: tile_rows must be a multiple of 1024");
   const int lds_max = spec->lds_max_groups >= 0 ? (spec->lds_max_groups ? spec->lds_max_groups : 256) : 0;
   const int bpc = spec->blocks_per_cu > 0 ? spec->blocks_per_cu : 4;
-  const int64_t radix_min = spec->radix_min_groups >= 0 ? (spec->radix_min_groups ? spec->radix_min_groups : 2048)
-                                                        : INT64_MAX;
+  const int64_t radix_min = spec->radix_min_groups >= 0
+                                ? (spec->radix_min_groups ? spec->radix_min_groups : (int64_t)lds_max + 1)
+                                : INT64_MAX;
 
   std::vector<GbArgs> plans((size_t)nfrags);
   std::vector<BatchOut> outs((size_t)nfrags);
