@@ -240,7 +240,7 @@ typedef struct gq_join_opts {
                         group-by on the join key (0, 2 or 6); see gq_pipeline */
   int32_t regions_log2; /* build inputs of at least 2^20 rows are partitioned into
                            2^regions_log2 key-hash regions for the radix group-join
-                           of gq_pipeline: 0 = chosen from the row count, else 4..10 */
+                           of gq_pipeline: 0 = chosen from the row count, else 4..12 */
 } gq_join_opts;
 
 /* Build a table over the rows of `build` that pass `preds` and have a non-NULL

@@ -641,8 +641,8 @@ int gq_join_build(gq_ctx* ctx, const gq_batch* build, const int32_t* keys, int n
   // Large build inputs are partitioned by region (radix group-join); their
   // probe index is built from the partitioned rows when first needed.
   const int rlog = opts ? opts->regions_log2 : 0;
-  if (rlog != 0 && (rlog < 4 || rlog > 10))
-    return set_error(ctx, GQ_ERR_INVALID, "gq_join_build: regions_log2 must be 0 or in [4, 10]");
+  if (rlog != 0 && (rlog < 4 || rlog > 12))
+    return set_error(ctx, GQ_ERR_INVALID, "gq_join_build: regions_log2 must be 0 or in [4, 12]");
   const int pbits = rlog ? rlog : rj_choose_pbits(n);
   const bool radix = n >= kRjMinBuild && n < ((int64_t)1 << 31) && rj_build_fits(build, keys[0], preds, npreds, pbits);
 

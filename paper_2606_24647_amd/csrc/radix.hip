@@ -14,13 +14,16 @@
 //   k_rp_hist     per hist tile (16384 rows), histogram of the region ids of
 //                 the kept rows (predicates pass, key non-NULL); region = top
 //                 pbits of fmix64(key ^ kRegionSeed)
-//   k_rp_scan     exclusive scan of the (region, tile) counts, region-major
-//                 (decoupled look-back): where each tile's rows of each region
-//                 start, and the region offsets
-//   k_rp_scatter  each hist tile in sub-tiles of 2048 rows: rows staged in
-//                 LDS, ordered by region in LDS, then written region by region
-//                 with coalesced stores: build keys and build row ids grouped by
-//                 region (order inside a region is unspecified)
+//   k_cs_*        column scan of the (tile, region) counts, stored tile-major
+//                 so that every tile reads and writes its P counts coalesced:
+//                 per-chunk column sums, region totals and offsets (one
+//                 block), then the start of every (tile, region)
+//   k_rp_scatter  each hist tile in sub-tiles of 512 rows staged in LDS; a
+//                 kept row takes the next position of its region in the tile's
+//                 range with an LDS atomic and is written there: build keys and
+//                 build row ids grouped by region (order inside a region is
+//                 unspecified; with thousands of regions a tile holds only a few
+//                 rows per region, so there is no run of stores to coalesce)
 // Probe side (gq_pipeline when the only group key is the probe key): the same
 // three kernels, the payload of a row being its aggregate inputs (one 64-bit
 // product expression per SUM/MIN/MAX, and a non-NULL mask where an input can
@@ -46,10 +49,13 @@ namespace gq {
 namespace {
 
 constexpr int kRpBlock = 256;
-constexpr int kRpSub = 1024;                     // rows per sub-tile
-constexpr int kRpRows = kRpSub / kRpBlock;       // rows per thread per sub-tile
-constexpr int kRpSubs = 16;                      // sub-tiles per hist tile
-constexpr int kRpTile = kRpSub * kRpSubs;        // 16384 rows per hist tile
+constexpr int kRpSub = 512;                      // rows per scatter sub-tile (unit of the staging layout)
+constexpr int kRpRows = kRpSub / kRpBlock;       // rows per thread per scatter sub-tile
+constexpr int kRpTile = 16384;                   // rows per hist tile
+constexpr int kRpSubs = kRpTile / kRpSub;        // scatter sub-tiles per hist tile
+constexpr int kRpHSub = 2048;                    // rows per hist sub-tile
+constexpr int kRpHRows = kRpHSub / kRpBlock;
+constexpr int kRpHScale = kRpHSub / kRpSub;      // hist staging offsets = layout offsets * kRpHScale
 constexpr int kRpMaxStage = 8;                   // distinct input columns staged in LDS
 
 constexpr int kRjBlock = 1024;
@@ -100,32 +106,32 @@ struct RpArgs {
 // every load of the sub-tile is in flight at once); slices that are not
 // 16-byte aligned, and the ragged end of a column, are copied byte by byte.
 // The caller waits and synchronises the block before reading.
-__device__ __forceinline__ void rp_stage(const RpArgs& a, int nst, int64_t sbase, uint8_t* s_in) {
-  const int64_t left = a.n - sbase;
-  const int nrows = left < kRpSub ? (int)left : kRpSub;
-  for (int j = 0; j < nst; ++j) stage_col_lds<kRpBlock>(a.st[j], sbase, nrows, s_in + a.st_off[j]);
+__device__ __forceinline__ void rp_stage(const RpArgs& a, int nst, int scale, int64_t sbase, int nrows,
+                                         uint8_t* s_in) {
+  for (int j = 0; j < nst; ++j) stage_col_lds<kRpBlock>(a.st[j], sbase, nrows, s_in + a.st_off[j] * scale);
 }
 
-// The kRpRows rows r = i * 256 + threadIdx.x of a staged column; one type
+// The ROWS rows r = i * 256 + threadIdx.x of a staged column; one type
 // dispatch for all of them.
-__device__ __forceinline__ void lds_rows(const uint8_t* base, int type, int64_t (&v)[kRpRows]) {
+template <int ROWS>
+__device__ __forceinline__ void lds_rows(const uint8_t* base, int type, int64_t (&v)[ROWS]) {
   const int t = threadIdx.x;
   switch (type) {
     case GQ_I8:
 #pragma unroll
-      for (int i = 0; i < kRpRows; ++i) v[i] = reinterpret_cast<const int8_t*>(base)[i * kRpBlock + t];
+      for (int i = 0; i < ROWS; ++i) v[i] = reinterpret_cast<const int8_t*>(base)[i * kRpBlock + t];
       break;
     case GQ_I16:
 #pragma unroll
-      for (int i = 0; i < kRpRows; ++i) v[i] = reinterpret_cast<const int16_t*>(base)[i * kRpBlock + t];
+      for (int i = 0; i < ROWS; ++i) v[i] = reinterpret_cast<const int16_t*>(base)[i * kRpBlock + t];
       break;
     case GQ_I32:
 #pragma unroll
-      for (int i = 0; i < kRpRows; ++i) v[i] = reinterpret_cast<const int32_t*>(base)[i * kRpBlock + t];
+      for (int i = 0; i < ROWS; ++i) v[i] = reinterpret_cast<const int32_t*>(base)[i * kRpBlock + t];
       break;
     default:
 #pragma unroll
-      for (int i = 0; i < kRpRows; ++i) v[i] = reinterpret_cast<const int64_t*>(base)[i * kRpBlock + t];
+      for (int i = 0; i < ROWS; ++i) v[i] = reinterpret_cast<const int64_t*>(base)[i * kRpBlock + t];
       break;
   }
 }
@@ -133,70 +139,64 @@ __device__ __forceinline__ void lds_rows(const uint8_t* base, int type, int64_t 
 // Rows r = i * 256 + threadIdx.x of the staged sub-tile at sbase: mask of the
 // kept ones (predicates pass, key non-NULL) and their keys.  Column-major: each
 // predicate is applied to all rows of the thread before the next.
-__device__ __forceinline__ uint32_t rp_rows_keep(const RpArgs& a, const uint8_t* s_in, int64_t sbase, int nrows,
-                                                 int64_t (&key)[kRpRows]) {
+template <int ROWS>
+__device__ __forceinline__ uint32_t rp_rows_keep(const RpArgs& a, const uint8_t* s_in, int scale, int64_t sbase,
+                                                 int nrows, int64_t (&key)[ROWS]) {
   uint32_t keep = 0;
 #pragma unroll
-  for (int i = 0; i < kRpRows; ++i)
+  for (int i = 0; i < ROWS; ++i)
     if (i * kRpBlock + (int)threadIdx.x < nrows) keep |= 1u << i;
   for (int p = 0; p < a.npreds; ++p) {
     const int j = a.pred_st[p];
     const DCol& c = a.st[j];
-    int64_t v[kRpRows];
-    lds_rows(s_in + a.st_off[j], c.type, v);
+    int64_t v[ROWS];
+    lds_rows<ROWS>(s_in + a.st_off[j] * scale, c.type, v);
     const int64_t lo = a.preds[p].lo, hi = a.preds[p].hi;
     if (a.preds[p].op == GQ_RANGE) {
 #pragma unroll
-      for (int i = 0; i < kRpRows; ++i)
+      for (int i = 0; i < ROWS; ++i)
         if (v[i] < lo || v[i] > hi) keep &= ~(1u << i);
     } else {
 #pragma unroll
-      for (int i = 0; i < kRpRows; ++i)
+      for (int i = 0; i < ROWS; ++i)
         if (v[i] == lo) keep &= ~(1u << i);
     }
     if (c.valid) {
 #pragma unroll
-      for (int i = 0; i < kRpRows; ++i)
-        if (!valid_one(c, sbase + i * kRpBlock + threadIdx.x)) keep &= ~(1u << i);
+      for (int i = 0; i < ROWS; ++i)
+        if (((keep >> i) & 1u) && !valid_one(c, sbase + i * kRpBlock + threadIdx.x)) keep &= ~(1u << i);
     }
   }
   const DCol& kc = a.st[a.key_st];
-  lds_rows(s_in + a.st_off[a.key_st], kc.type, key);
+  lds_rows<ROWS>(s_in + a.st_off[a.key_st] * scale, kc.type, key);
   if (kc.valid) {
 #pragma unroll
-    for (int i = 0; i < kRpRows; ++i)
-      if (!valid_one(kc, sbase + i * kRpBlock + threadIdx.x)) keep &= ~(1u << i);
+    for (int i = 0; i < ROWS; ++i)
+      if (((keep >> i) & 1u) && !valid_one(kc, sbase + i * kRpBlock + threadIdx.x)) keep &= ~(1u << i);
   }
   return keep;
 }
 
-// Aggregate input (product expression) of aggregate ag for the thread's rows.
-__device__ __forceinline__ void rp_rows_value(const RpArgs& a, const DAgg& ag, const uint8_t* s_in,
-                                              uint64_t (&x)[kRpRows]) {
-#pragma unroll
-  for (int i = 0; i < kRpRows; ++i) x[i] = 1;
+// Aggregate input (product expression) of aggregate ag for staged row r; *nn
+// is cleared when a referenced column is NULL (global row grow).
+__device__ __forceinline__ uint64_t rp_value_row(const RpArgs& a, const DAgg& ag, const uint8_t* s_in, int r,
+                                                 int64_t grow, bool* nn) {
+  uint64_t x = 1;
   for (int f = 0; f < ag.nf; ++f) {
     const DFactor& fa = ag.f[f];
     const uint64_t k = (uint64_t)fa.k;
     if (fa.kind == GQ_F_CONST) {
-#pragma unroll
-      for (int i = 0; i < kRpRows; ++i) x[i] *= k;
+      x *= k;
       continue;
     }
     const int j = a.val_st[fa.v];
-    int64_t v[kRpRows];
-    lds_rows(s_in + a.st_off[j], a.st[j].type, v);
-    if (fa.kind == GQ_F_COL) {
-#pragma unroll
-      for (int i = 0; i < kRpRows; ++i) x[i] *= (uint64_t)v[i];
-    } else if (fa.kind == GQ_F_K_MINUS_COL) {
-#pragma unroll
-      for (int i = 0; i < kRpRows; ++i) x[i] *= k - (uint64_t)v[i];
-    } else {
-#pragma unroll
-      for (int i = 0; i < kRpRows; ++i) x[i] *= k + (uint64_t)v[i];
-    }
+    const uint64_t v = (uint64_t)lds_value(s_in + a.st_off[j], r, a.st[j].type);
+    if (a.ap.vals[fa.v].valid && !valid_one(a.ap.vals[fa.v], grow)) *nn = false;
+    if (fa.kind == GQ_F_COL) x *= v;
+    else if (fa.kind == GQ_F_K_MINUS_COL) x *= k - v;
+    else x *= k + v;
   }
+  return x;
 }
 
 __global__ __launch_bounds__(kRpBlock) void k_rp_hist(const RpArgs a) {
@@ -206,48 +206,63 @@ __global__ __launch_bounds__(kRpBlock) void k_rp_hist(const RpArgs a) {
   uint8_t* s_in = s_raw + align_up((size_t)P * 4, 16);
   for (int i = threadIdx.x; i < P; i += kRpBlock) s_hist[i] = 0;
   const int64_t tile = blockIdx.x;
-  for (int sub = 0; sub < kRpSubs; ++sub) {
-    const int64_t sbase = tile * kRpTile + (int64_t)sub * kRpSub;
+  for (int sub = 0; sub < kRpTile / kRpHSub; ++sub) {
+    const int64_t sbase = tile * kRpTile + (int64_t)sub * kRpHSub;
     if (sbase >= a.n) break;
-    const int nrows = a.n - sbase < kRpSub ? (int)(a.n - sbase) : kRpSub;
+    const int nrows = a.n - sbase < kRpHSub ? (int)(a.n - sbase) : kRpHSub;
     __syncthreads();  // previous sub-tile's rows read
-    rp_stage(a, a.nst_hist, sbase, s_in);
+    rp_stage(a, a.nst_hist, kRpHScale, sbase, nrows, s_in);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    int64_t key[kRpRows];
-    const uint32_t keep = rp_rows_keep(a, s_in, sbase, nrows, key);
+    int64_t key[kRpHRows];
+    const uint32_t keep = rp_rows_keep<kRpHRows>(a, s_in, kRpHScale, sbase, nrows, key);
 #pragma unroll
-    for (int i = 0; i < kRpRows; ++i)
+    for (int i = 0; i < kRpHRows; ++i)
       if ((keep >> i) & 1u) atomicAdd(&s_hist[region_of(region_hash((uint64_t)key[i]), a.pbits)], 1u);
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < P; i += kRpBlock) a.counts[(int64_t)i * a.ntiles + tile] = s_hist[i];
+  for (int i = threadIdx.x; i < P; i += kRpBlock) a.counts[tile * P + i] = s_hist[i];
 }
 
-// Exclusive scan of counts[0..m) (32-bit; the total fits because m counts rows
-// of a batch of fewer than 2^32 rows) into starts[], region offsets[q] =
-// starts[q * ntiles], offsets[P] = *total = the sum.
-template <int BLOCK, int ITEMS>
-__global__ __launch_bounds__(BLOCK) void k_rp_scan(const uint32_t* counts, int64_t m, uint32_t* starts, int64_t ntiles,
-                                                   int64_t P, int64_t* offsets, int64_t* total, uint32_t* ticket,
-                                                   uint64_t* status, int64_t nblocks) {
-  constexpr int NW = BLOCK / kWave;
-  __shared__ uint32_t s_tile;
+// Column scan of the tile-major counts (count of region q in tile t at
+// counts[t * P + q]; all of them fit 32 bits since a batch has fewer than 2^32
+// rows): starts[t * P + q] = offsets[q] + the counts of region q in tiles
+// before t, offsets[q] = the counts of all regions before q.
+constexpr int kCsChunk = 64;  // tiles per chunk
+
+// Per chunk of tiles and region: the sum of the chunk's counts.
+__global__ __launch_bounds__(256) void k_cs_chunk(const uint32_t* counts, int64_t ntiles, int P, uint32_t* csum) {
+  const int q = blockIdx.y * 256 + threadIdx.x;
+  if (q >= P) return;
+  const int64_t t0 = (int64_t)blockIdx.x * kCsChunk;
+  const int64_t t1 = t0 + kCsChunk < ntiles ? t0 + kCsChunk : ntiles;
+  uint32_t sum = 0;
+#pragma unroll 8
+  for (int64_t t = t0; t < t1; ++t) sum += counts[t * P + q];
+  csum[(int64_t)blockIdx.x * P + q] = sum;
+}
+
+// One block: region totals, their exclusive scan into offsets[0..P], total.
+__global__ __launch_bounds__(1024) void k_cs_base(const uint32_t* csum, int64_t nchunks, int P, int64_t* offsets,
+                                                  int64_t* total) {
+  constexpr int NW = 1024 / kWave;
   __shared__ int64_t s_wave[NW];
-  __shared__ int64_t s_excl;
-  if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
-  __syncthreads();
-  const int64_t tile = s_tile;
-  const int64_t i0 = (tile * BLOCK + threadIdx.x) * ITEMS;
-  uint32_t c[ITEMS];
-  int64_t tsum = 0;
+  const int per = (P + 1023) / 1024;  // <= 4
+  int64_t tot[4];
+  int64_t sum = 0;
 #pragma unroll
-  for (int k = 0; k < ITEMS; ++k) {
-    c[k] = (i0 + k < m) ? counts[i0 + k] : 0u;
-    tsum += c[k];
+  for (int j = 0; j < 4; ++j) {
+    const int q = (int)threadIdx.x * per + j;
+    tot[j] = 0;
+    if (j < per && q < P) {
+      uint32_t v = 0;
+      for (int64_t c = 0; c < nchunks; ++c) v += csum[c * P + q];
+      tot[j] = v;
+    }
+    sum += tot[j];
   }
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  int64_t incl = tsum;
+  int64_t incl = sum;
 #pragma unroll
   for (int o = 1; o < kWave; o <<= 1) {
     const int64_t y = __shfl_up(incl, o, kWave);
@@ -255,206 +270,110 @@ __global__ __launch_bounds__(BLOCK) void k_rp_scan(const uint32_t* counts, int64
   }
   if (lane == kWave - 1) s_wave[wave] = incl;
   __syncthreads();
-  int64_t bpre = 0, btot = 0;
-#pragma unroll
+  int64_t base = incl - sum, all = 0;
   for (int w = 0; w < NW; ++w) {
-    if (w < wave) bpre += s_wave[w];
-    btot += s_wave[w];
+    if (w < wave) base += s_wave[w];
+    all += s_wave[w];
   }
-  if (wave == 0) {
-    const int64_t e = lookback_exclusive(status, tile, btot);
-    if (lane == 0) s_excl = e;
-  }
-  __syncthreads();
-  int64_t run = s_excl + bpre + incl - tsum;
 #pragma unroll
-  for (int k = 0; k < ITEMS; ++k) {
-    const int64_t i = i0 + k;
-    if (i < m) {
-      starts[i] = (uint32_t)run;
-      if (i % ntiles == 0) offsets[i / ntiles] = run;
-    }
-    run += c[k];
+  for (int j = 0; j < 4; ++j) {
+    const int q = (int)threadIdx.x * per + j;
+    if (j < per && q < P) offsets[q] = base;
+    base += tot[j];
   }
-  if (tile == nblocks - 1 && threadIdx.x == 0) {
-    offsets[P] = s_excl + btot;
-    if (total) *total = s_excl + btot;
+  if (threadIdx.x == 0) {
+    offsets[P] = all;
+    if (total) *total = all;
   }
 }
 
-// LDS layout of k_rp_scatter (dynamic): base[P], cnt[P] (u32), the staged
-// input (in_bytes), then per row of the sub-tile: hash (u64), payload (build:
-// u32 row; probe: nv u64 words, then a non-NULL mask byte), pp (u32: region
-// << 16 | rank in region, ~0 = dropped), src (u16).
-__host__ __device__ inline size_t rp_scatter_lds(int P, int in_bytes, int probe, int nv, int need_nn) {
-  size_t b = align_up((size_t)2 * P * 4, 16) + align_up((size_t)in_bytes, 16) + (size_t)kRpSub * 8;
-  b += probe ? (size_t)kRpSub * 8 * nv + (need_nn ? kRpSub : 0) : (size_t)kRpSub * 4;
-  b = align_up(b, 16);
-  b += (size_t)kRpSub * 4 + (size_t)kRpSub * 2;
-  return b;
+// Per chunk of tiles and region: the start of the region's rows in each tile.
+__global__ __launch_bounds__(256) void k_cs_fill(const uint32_t* counts, const uint32_t* csum, const int64_t* offsets,
+                                                 int64_t ntiles, int P, uint32_t* starts) {
+  const int q = blockIdx.y * 256 + threadIdx.x;
+  if (q >= P) return;
+  const int64_t c = blockIdx.x;
+  uint32_t run = (uint32_t)offsets[q];
+  for (int64_t k = 0; k < c; ++k) run += csum[k * P + q];
+  const int64_t t0 = c * kCsChunk;
+  const int64_t t1 = t0 + kCsChunk < ntiles ? t0 + kCsChunk : ntiles;
+  for (int64_t t = t0; t < t1; ++t) {
+    const uint32_t v = counts[t * P + q];
+    starts[t * P + q] = run;
+    run += v;
+  }
+}
+
+// LDS layout of k_rp_scatter (dynamic): the tile's next write position of
+// every region (u32), then the staged input (in_bytes).
+__host__ __device__ inline size_t rp_scatter_lds(int P, int in_bytes) {
+  return align_up((size_t)P * 4, 16) + align_up((size_t)in_bytes, 16);
 }
 
 __global__ __launch_bounds__(kRpBlock) void k_rp_scatter(const RpArgs a) {
   extern __shared__ __attribute__((aligned(16))) uint8_t s_raw[];
   const int P = 1 << a.pbits;
-  uint32_t* s_base = reinterpret_cast<uint32_t*>(s_raw);
-  uint32_t* s_cnt = s_base + P;
-  uint8_t* s_in = s_raw + align_up((size_t)2 * P * 4, 16);
-  uint64_t* s_key = reinterpret_cast<uint64_t*>(s_in + align_up((size_t)a.in_bytes, 16));
-  uint8_t* pay = reinterpret_cast<uint8_t*>(s_key + kRpSub);
-  uint64_t* s_val = reinterpret_cast<uint64_t*>(pay);                  // probe
-  uint32_t* s_row = reinterpret_cast<uint32_t*>(pay);                  // build
-  uint8_t* s_nn = pay + (size_t)kRpSub * 8 * a.nv;                     // probe
-  const size_t off = a.probe ? (size_t)kRpSub * 8 * a.nv + (a.need_nn ? kRpSub : 0) : (size_t)kRpSub * 4;
-  uint32_t* s_pp = reinterpret_cast<uint32_t*>(pay + align_up(off, 16));
-  uint16_t* s_src = reinterpret_cast<uint16_t*>(s_pp + kRpSub);
-  __shared__ uint32_t s_wsum[kRpBlock / kWave];
-  __shared__ uint32_t s_total;
-
+  uint32_t* s_pos = reinterpret_cast<uint32_t*>(s_raw);
+  uint8_t* s_in = s_raw + align_up((size_t)P * 4, 16);
   const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
-  for (int q = threadIdx.x; q < P; q += kRpBlock) s_base[q] = a.starts[(int64_t)q * a.ntiles + tile];
-  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  const int per = (P + kRpBlock - 1) / kRpBlock;
-
+  for (int q = threadIdx.x; q < P; q += kRpBlock) s_pos[q] = a.starts[tile * P + q];
   for (int sub = 0; sub < kRpSubs; ++sub) {
     const int64_t sbase = tile * kRpTile + (int64_t)sub * kRpSub;
     if (sbase >= a.n) break;
     const int nrows = a.n - sbase < kRpSub ? (int)(a.n - sbase) : kRpSub;
-    for (int q = threadIdx.x; q < P; q += kRpBlock) s_cnt[q] = 0;
-    rp_stage(a, a.nst, sbase, s_in);
+    __syncthreads();  // previous sub-tile's rows written
+    rp_stage(a, a.nst, 1, sbase, nrows, s_in);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    // Rows r = i * 256 + t of the sub-tile: keep, region, payload.
-    {
-      int64_t key[kRpRows];
-      const uint32_t keep = rp_rows_keep(a, s_in, sbase, nrows, key);
-      uint64_t hv[kRpRows];
+    int64_t key[kRpRows];
+    const uint32_t keep = rp_rows_keep<kRpRows>(a, s_in, 1, sbase, nrows, key);
 #pragma unroll
-      for (int i = 0; i < kRpRows; ++i) {
-        const int r = i * kRpBlock + threadIdx.x;
-        if (!((keep >> i) & 1u)) {
-          s_pp[r] = 0xffffffffu;
-          continue;
-        }
-        hv[i] = region_hash((uint64_t)key[i]);
-        const uint32_t p = region_of(hv[i], a.pbits);
-        s_pp[r] = (p << 16) | atomicAdd(&s_cnt[p], 1u);
-        s_key[r] = hv[i];
-      }
+    for (int i = 0; i < kRpRows; ++i) {
+      if (!((keep >> i) & 1u)) continue;
+      const int r = i * kRpBlock + threadIdx.x;
+      const uint64_t h = region_hash((uint64_t)key[i]);
+      const int64_t g = atomicAdd(&s_pos[region_of(h, a.pbits)], 1u);
+      if (g >= a.ocap) continue;
       if (a.probe) {
+        // The tuple (hash and values side by side) is one contiguous store;
+        // values come from the staged input.
+        uint64_t* t = a.okey + (size_t)g * a.tw;
+        uint64_t x[kRjMaxVals] = {0, 0};
 #pragma unroll
         for (int v = 0; v < kRjMaxVals; ++v) {
           if (v >= a.nv) break;
-          uint64_t x[kRpRows];
-          rp_rows_value(a, a.ap.aggs[a.vagg[v]], s_in, x);
+          bool nn = true;
+          x[v] = rp_value_row(a, a.ap.aggs[a.vagg[v]], s_in, r, sbase + r, &nn);
+        }
+        if (a.nv == 1) {
+          typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+          *reinterpret_cast<u64x2*>(t) = u64x2{h, x[0]};
+        } else {
+          t[0] = h;
 #pragma unroll
-          for (int i = 0; i < kRpRows; ++i) s_val[(size_t)v * kRpSub + i * kRpBlock + threadIdx.x] = x[i];
+          for (int v = 0; v < kRjMaxVals; ++v)
+            if (v < a.nv) t[1 + v] = x[v];
         }
         if (a.need_nn) {
-          uint32_t nnm[kRpRows];
-#pragma unroll
-          for (int i = 0; i < kRpRows; ++i) nnm[i] = 0;
-          for (int g = 0; g < a.naggs; ++g) {
-            const DAgg& ag = a.ap.aggs[g];
+          uint32_t nnm = 0;
+          for (int gi = 0; gi < a.naggs; ++gi) {
+            const DAgg& ag = a.ap.aggs[gi];
             if (ag.op == GQ_COUNT_STAR) continue;
-            uint32_t ok = 0xffffffffu;
+            bool ok = true;
             for (int f = 0; f < ag.nf; ++f) {
               if (ag.f[f].kind == GQ_F_CONST) continue;
               const DCol& c = a.ap.vals[ag.f[f].v];
-              if (!c.valid) continue;
-#pragma unroll
-              for (int i = 0; i < kRpRows; ++i)
-                if (!valid_one(c, sbase + i * kRpBlock + threadIdx.x)) ok &= ~(1u << i);
+              if (c.valid && !valid_one(c, sbase + r)) ok = false;
             }
-#pragma unroll
-            for (int i = 0; i < kRpRows; ++i) nnm[i] |= ((ok >> i) & 1u) << g;
+            nnm |= (ok ? 1u : 0u) << gi;
           }
-#pragma unroll
-          for (int i = 0; i < kRpRows; ++i) s_nn[i * kRpBlock + threadIdx.x] = (uint8_t)nnm[i];
+          a.onn[g] = (uint8_t)nnm;
         }
       } else {
-#pragma unroll
-        for (int i = 0; i < kRpRows; ++i)
-          s_row[i * kRpBlock + threadIdx.x] = (uint32_t)(sbase + i * kRpBlock + threadIdx.x);
+        a.okey[g] = h;
+        a.orow[g] = (int32_t)(sbase + r);
       }
     }
-    __syncthreads();
-    // Exclusive scan of s_cnt over the P regions: thread t owns regions
-    // [t * per, (t + 1) * per).
-    uint32_t mysum = 0;
-    for (int j = 0; j < per; ++j) {
-      const int q = threadIdx.x * per + j;
-      if (q < P) mysum += s_cnt[q];
-    }
-    uint32_t incl = mysum;
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-      const uint32_t y = __shfl_up(incl, o, kWave);
-      if (lane >= o) incl += y;
-    }
-    if (lane == kWave - 1) s_wsum[wave] = incl;
-    __syncthreads();
-    uint32_t wpre = 0, tot = 0;
-#pragma unroll
-    for (int w = 0; w < kRpBlock / kWave; ++w) {
-      if (w < wave) wpre += s_wsum[w];
-      tot += s_wsum[w];
-    }
-    uint32_t run = wpre + incl - mysum;
-    uint32_t cnt_own[4] = {0u, 0u, 0u, 0u};  // per <= 4 for P <= 1024
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int q = threadIdx.x * per + j;
-      if (j < per && q < P) {
-        cnt_own[j] = s_cnt[q];
-        s_cnt[q] = run;  // now the sub-tile-local start of region q
-        run += cnt_own[j];
-      }
-    }
-    if (threadIdx.x == 0) s_total = tot;
-    __syncthreads();
-    // Inverse permutation: sorted position -> row of the sub-tile.
-#pragma unroll
-    for (int i = 0; i < kRpRows; ++i) {
-      const int r = i * kRpBlock + threadIdx.x;
-      const uint32_t pp = s_pp[r];
-      if (pp != 0xffffffffu) s_src[s_cnt[pp >> 16] + (pp & 0xffffu)] = (uint16_t)r;
-    }
-    __syncthreads();
-    const int total = (int)s_total;
-    for (int i = threadIdx.x; i < total; i += kRpBlock) {
-      const int r = s_src[i];
-      const uint32_t q = s_pp[r] >> 16;
-      const int64_t g = (int64_t)s_base[q] + (i - (int)s_cnt[q]);
-      if (g < a.ocap) {
-        if (a.probe) {
-          // Tuples are stored whole (hash and values side by side), so one
-          // tuple is one contiguous store.
-          uint64_t* t = a.okey + (size_t)g * a.tw;
-          if (a.nv == 1) {
-            typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
-            *reinterpret_cast<u64x2*>(t) = u64x2{s_key[r], s_val[r]};
-          } else {
-            t[0] = s_key[r];
-#pragma unroll
-            for (int v = 0; v < kRjMaxVals; ++v)
-              if (v < a.nv) t[1 + v] = s_val[(size_t)v * kRpSub + r];
-          }
-          if (a.need_nn) a.onn[g] = s_nn[r];
-        } else {
-          a.okey[g] = s_key[r];
-          a.orow[g] = (int32_t)s_row[r];
-        }
-      }
-    }
-    __syncthreads();
-    // Advance each region's write position past this sub-tile's rows.
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int q = threadIdx.x * per + j;
-      if (j < per && q < P) s_base[q] += cnt_own[j];
-    }
-    __syncthreads();
   }
 }
 
@@ -498,39 +417,60 @@ __device__ __forceinline__ uint32_t item_nsub(uint64_t it) { return (uint32_t)(i
 
 // Per region, the number of sub-regions S_p, and the work items: region p's
 // S_p items in queue p % 8, queues one after another.  One block of 1024
-// threads, one region per thread (P <= 1024).
+// threads: regions are ordered queue by queue (index q * P/8 + k for region
+// q + 8k), each thread takes up to four consecutive ones, and a block scan of
+// their S_p gives every region's first item.
 __global__ __launch_bounds__(1024) void k_rj_plan(const RjJoinArgs a) {
-  __shared__ uint32_t s_S[1024];
-  __shared__ uint32_t s_q[kXcds + 1];
-  const int p = threadIdx.x;
-  uint32_t S = 0;
-  if (p < a.P) {
-    const int64_t nb = a.boff[p + 1] - a.boff[p];
-    S = (uint32_t)((nb + a.kpr - 1) / a.kpr);
-    if (S < 1) S = 1;
+  constexpr int NW = 1024 / kWave;
+  __shared__ uint32_t s_wave[NW];
+  const int P = a.P;
+  const int Q = P / kXcds;                        // regions per queue (P >= 16)
+  const int per = (P + 1023) / 1024;              // <= 4
+  uint32_t S[4];
+  uint32_t sum = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int idx = (int)threadIdx.x * per + j;
+    S[j] = 0;
+    if (j < per && idx < P) {
+      const int p = (idx % Q) * kXcds + idx / Q;
+      const int64_t nb = a.boff[p + 1] - a.boff[p];
+      S[j] = (uint32_t)((nb + a.kpr - 1) / a.kpr);
+      if (S[j] < 1) S[j] = 1;
+    }
+    sum += S[j];
   }
-  s_S[p] = S;
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  uint32_t incl = sum;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const uint32_t y = __shfl_up(incl, o, kWave);
+    if (lane >= o) incl += y;
+  }
+  if (lane == kWave - 1) s_wave[wave] = incl;
   __syncthreads();
-  if (p < kXcds) {
-    uint32_t tot = 0;
-    for (int r = p; r < a.P; r += kXcds) tot += s_S[r];
-    s_q[p + 1] = tot;
+  uint32_t base = incl - sum, total = 0;
+  for (int w = 0; w < NW; ++w) {
+    if (w < wave) base += s_wave[w];
+    total += s_wave[w];
   }
-  __syncthreads();
-  if (p == 0) {
-    s_q[0] = 0;
-    for (int q = 0; q < kXcds; ++q) s_q[q + 1] += s_q[q];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int idx = (int)threadIdx.x * per + j;
+    if (j < per && idx < P) {
+      const int q = idx / Q, k = idx % Q;
+      const int p = k * kXcds + q;
+      if (k == 0) a.qoff[q] = base;
+      for (uint32_t u = 0; u < S[j]; ++u)
+        a.items[base + u] = (uint64_t)p | ((uint64_t)u << 16) | ((uint64_t)S[j] << 40);
+      base += S[j];
+    }
   }
-  __syncthreads();
-  if (p < a.P) {
-    uint32_t before = 0;
-    for (int r = p % kXcds; r < p; r += kXcds) before += s_S[r];
-    const uint32_t base = s_q[p % kXcds] + before;
-    for (uint32_t j = 0; j < S; ++j) a.items[base + j] = (uint64_t)p | ((uint64_t)j << 16) | ((uint64_t)S << 40);
+  if (threadIdx.x == 0) {
+    a.qoff[kXcds] = total;
+    *a.d_count = 0;
   }
-  if (p <= kXcds) a.qoff[p] = s_q[p];
-  if (p < kXcds) a.qticket[p] = 0;
-  if (p == 0) *a.d_count = 0;
+  if (threadIdx.x < kXcds) a.qticket[threadIdx.x] = 0;
 }
 
 // LDS slot of a region hash: its low 32 bits scaled to the table (the high
@@ -827,7 +767,6 @@ struct StageBuilder {
 
 constexpr size_t kRpMaxLds = 80 * 1024;  // two partition workgroups per CU
 
-constexpr int kScanBlock = 256, kScanItems = 16;
 
 // Histogram, scan and scatter of one side; a.counts/starts/okey... set by the
 // caller except the workspace, allocated here.  offsets: P + 1 int64.
@@ -842,32 +781,33 @@ int rp_run(gq_ctx* ctx, RpArgs& a, int64_t* offsets, int64_t* total, hipStream_t
     return rc;
   }
   const int64_t m = a.ntiles * P;
-  constexpr int STILE = kScanBlock * kScanItems;
-  const int64_t nscan = (m + STILE - 1) / STILE;
+  const int64_t nchunks = (a.ntiles + kCsChunk - 1) / kCsChunk;
   Scratch ws(ctx, stream);
   const size_t off_counts = 256;
   const size_t off_starts = off_counts + align_up((size_t)m * 4, 256);
-  const size_t off_status = off_starts + align_up((size_t)m * 4, 256);
-  const size_t bytes = off_status + align_up((size_t)nscan * 8, 256);
+  const size_t off_csum = off_starts + align_up((size_t)m * 4, 256);
+  const size_t bytes = off_csum + align_up((size_t)nchunks * P * 4, 256);
   if (!ws.get(bytes)) return set_error(ctx, GQ_ERR_NOMEM, "radix join: partition workspace allocation failed");
   a.counts = ws.as<uint32_t>(off_counts);
   a.starts = ws.as<uint32_t>(off_starts);
-  uint32_t* ticket = ws.as<uint32_t>(0);
-  uint64_t* status = ws.as<uint64_t>(off_status);
-  int rc = launch_fill_u32(ctx, ticket, 0u, 1, stream);
-  if (rc) return rc;
-  rc = launch_fill_u32(ctx, status, 0u, 2 * nscan, stream);
-  if (rc) return rc;
-  const size_t lds_hist = align_up((size_t)P * 4, 16) + (size_t)a.st_off[a.nst_hist - 1] +
-                         align_up((size_t)kRpSub * type_width(a.st[a.nst_hist - 1].type), 16);
+  uint32_t* csum = ws.as<uint32_t>(off_csum);
+  const size_t lds_hist = align_up((size_t)P * 4, 16) +
+                         ((size_t)a.st_off[a.nst_hist - 1] +
+                          align_up((size_t)kRpSub * type_width(a.st[a.nst_hist - 1].type), 16)) * kRpHScale;
   GQ_LAUNCH(ctx, a.probe ? "rp_hist_probe" : "rp_hist_build", k_rp_hist, dim3((unsigned)a.ntiles), dim3(kRpBlock),
             lds_hist, stream, a);
   GQ_LAUNCH_CHECK(ctx);
-  GQ_LAUNCH(ctx, a.probe ? "rp_scan_probe" : "rp_scan_build", (k_rp_scan<kScanBlock, kScanItems>),
-            dim3((unsigned)nscan), dim3(kScanBlock), 0, stream, (const uint32_t*)a.counts, m, a.starts, a.ntiles, P,
-            offsets, total, ticket, status, nscan);
+  const dim3 cgrid((unsigned)nchunks, (unsigned)((P + 255) / 256));
+  GQ_LAUNCH(ctx, a.probe ? "rp_scan_probe" : "rp_scan_build", k_cs_chunk, cgrid, dim3(256), 0, stream,
+            (const uint32_t*)a.counts, a.ntiles, (int)P, csum);
   GQ_LAUNCH_CHECK(ctx);
-  const size_t lds = rp_scatter_lds((int)P, a.in_bytes, a.probe, a.nv, a.need_nn);
+  GQ_LAUNCH(ctx, a.probe ? "rp_scan_probe" : "rp_scan_build", k_cs_base, dim3(1), dim3(1024), 0, stream,
+            (const uint32_t*)csum, nchunks, (int)P, offsets, total);
+  GQ_LAUNCH_CHECK(ctx);
+  GQ_LAUNCH(ctx, a.probe ? "rp_scan_probe" : "rp_scan_build", k_cs_fill, cgrid, dim3(256), 0, stream,
+            (const uint32_t*)a.counts, (const uint32_t*)csum, (const int64_t*)offsets, a.ntiles, (int)P, a.starts);
+  GQ_LAUNCH_CHECK(ctx);
+  const size_t lds = rp_scatter_lds((int)P, a.in_bytes);
   GQ_LAUNCH(ctx, a.probe ? "rp_scatter_probe" : "rp_scatter_build", k_rp_scatter, dim3((unsigned)a.ntiles),
             dim3(kRpBlock), lds, stream, a);
   GQ_LAUNCH_CHECK(ctx);
@@ -877,10 +817,11 @@ int rp_run(gq_ctx* ctx, RpArgs& a, int64_t* offsets, int64_t* total, hipStream_t
 }  // namespace
 
 int rj_choose_pbits(int64_t build_rows) {
-  // Regions of about 2 * kRjNominalKpr build rows (half of them kept by a
-  // typical predicate), between 256 and 1024 regions.
+  // Regions of at most about kRjNominalKpr build rows, so that one LDS table
+  // holds a region's kept rows (one sub-region) even when most rows are kept:
+  // each probe tuple is then read once.  Between 256 and 4096 regions.
   int pbits = 8;
-  while (pbits < 10 && ((int64_t)1 << pbits) * 2 * kRjNominalKpr < build_rows) ++pbits;
+  while (pbits < 12 && ((int64_t)1 << pbits) * kRjNominalKpr < build_rows) ++pbits;
   return pbits;
 }
 
@@ -899,7 +840,7 @@ static bool rj_build_plan(RpArgs& a, const gq_batch* build, int32_t key_col, con
   }
   a.key_st = sb.add(make_dcol(build->cols[key_col]));
   a.nst_hist = a.nst;
-  return sb.ok && rp_scatter_lds(1 << pbits, a.in_bytes, 0, 0, 0) <= kRpMaxLds;
+  return sb.ok && rp_scatter_lds(1 << pbits, a.in_bytes) <= kRpMaxLds;
 }
 
 bool rj_build_fits(const gq_batch* build, int32_t key_col, const gq_pred* preds, int npreds, int pbits) {
@@ -948,7 +889,7 @@ static bool rj_probe_plan(RpArgs& r, int32_t (&vword)[GQ_MAX_AGGS], const gq_bat
       for (int f = 0; f < ap.aggs[i].nf; ++f)
         if (ap.aggs[i].f[f].kind != GQ_F_CONST && ap.vals[ap.aggs[i].f[f].v].valid) r.need_nn = 1;
   }
-  return sb.ok && rp_scatter_lds(1 << pbits, r.in_bytes, 1, r.nv, r.need_nn) <= kRpMaxLds;
+  return sb.ok && rp_scatter_lds(1 << pbits, r.in_bytes) <= kRpMaxLds;
 }
 
 bool rj_usable(const gq_join_table* t, const gq_batch* in, int32_t probe_key, const gq_pred* preds, int npreds,
