@@ -62,7 +62,7 @@ constexpr int kRjBlock = 1024;
 constexpr int kRjPerCu = 1;                      // join workgroups per CU (the LDS table takes the CU)
 constexpr int kRjMaxVals = 2;                    // value words per probe tuple
 constexpr int kRjUnroll = 8;                     // build keys per thread per round in k_rj_join
-constexpr int kRjProbeUnroll = 6;                // probe tuples per thread per round in k_rj_join
+constexpr int kRjProbeUnroll = 4;                // probe tuples per thread per round in k_rj_join
 
 __device__ __forceinline__ uint32_t region_of(uint64_t h, int pbits) {
   return pbits ? (uint32_t)(h >> (64 - pbits)) : 0u;
@@ -473,14 +473,19 @@ __global__ __launch_bounds__(1024) void k_rj_plan(const RjJoinArgs a) {
   if (threadIdx.x < kXcds) a.qticket[threadIdx.x] = 0;
 }
 
-// LDS slot of a region hash: its low 32 bits scaled to the table (the high
-// bits chose the region and sub-region).
-__device__ __forceinline__ uint32_t rj_slot(uint64_t h, int lcap) {
-  return (uint32_t)(((uint64_t)(uint32_t)h * (uint64_t)lcap) >> 32);
+// The LDS table is probed linearly in buckets of four slots: a hash starts at
+// the first slot of its bucket (its low 32 bits scaled to the lcap / 4
+// buckets; the high bits chose the region and sub-region), and one probe step
+// reads a whole bucket (two 16-byte LDS reads).  Slots only go from empty to
+// taken, so a bucket with the key decides a hit, and one with an empty slot
+// and no key decides a miss.
+constexpr int kRjBucket = 4;
+__device__ __forceinline__ uint32_t rj_bucket0(uint64_t h, int lcap) {
+  return (uint32_t)(((uint64_t)(uint32_t)h * (uint64_t)(lcap / kRjBucket)) >> 32) * kRjBucket;
 }
 
 __device__ __forceinline__ int rj_find_insert(uint64_t* s_keys, int lcap, uint64_t key) {
-  uint32_t s = rj_slot(key, lcap);
+  uint32_t s = rj_bucket0(key, lcap);
   for (int probe = 0; probe < lcap; ++probe) {
     const uint64_t kv = s_keys[s];
     if (kv == key) return (int)s;
@@ -628,24 +633,32 @@ __global__ __launch_bounds__(kRjBlock) void k_rj_join(const RjJoinArgs a) {
 #pragma unroll
       for (int u = 0; u < kRjProbeUnroll; ++u) {
         res[u] = -1;
-        pos[u] = rj_slot(h[u], L);
+        pos[u] = rj_bucket0(h[u], L);
         if (subregion_of(h[u], a.pbits, S) != s) act &= ~(1u << u);
         if (((act >> u) & 1u) && h[u] == kEmpty) {
           res[u] = s_mult[L] ? L : -1;
           act &= ~(1u << u);
         }
       }
-      for (int it = 0; act && it < L; ++it) {
-        uint64_t kv[kRjProbeUnroll];
+      for (int it = 0; act && it < L / kRjBucket; ++it) {
+        typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+        u64x2 k01[kRjProbeUnroll], k23[kRjProbeUnroll];
 #pragma unroll
-        for (int u = 0; u < kRjProbeUnroll; ++u) kv[u] = s_keys[pos[u]];
+        for (int u = 0; u < kRjProbeUnroll; ++u) {
+          k01[u] = *reinterpret_cast<const u64x2*>(&s_keys[pos[u]]);
+          k23[u] = *reinterpret_cast<const u64x2*>(&s_keys[pos[u] + 2]);
+        }
 #pragma unroll
         for (int u = 0; u < kRjProbeUnroll; ++u) {
           const bool on = (act >> u) & 1u;
-          const bool hit = kv[u] == h[u];
-          if (on && hit) res[u] = (int32_t)pos[u];
-          if (on && (hit || kv[u] == kEmpty)) act &= ~(1u << u);
-          pos[u] = pos[u] + 1 == (uint32_t)L ? 0u : pos[u] + 1;
+          const bool m0 = k01[u].x == h[u], m1 = k01[u].y == h[u], m2 = k23[u].x == h[u], m3 = k23[u].y == h[u];
+          const bool hit = m0 | m1 | m2 | m3;
+          const bool empty = (k01[u].x == kEmpty) | (k01[u].y == kEmpty) | (k23[u].x == kEmpty) |
+                             (k23[u].y == kEmpty);
+          const int32_t at = (int32_t)pos[u] + (m0 ? 0 : m1 ? 1 : m2 ? 2 : 3);
+          res[u] = on && hit ? at : res[u];
+          if (on && (hit || empty)) act &= ~(1u << u);
+          pos[u] = pos[u] + kRjBucket == (uint32_t)L ? 0u : pos[u] + kRjBucket;
         }
       }
       // Updates: tuples without a match go to this lane's dump slot (weight 0).
@@ -910,7 +923,7 @@ int rj_lcap(int nacc) {
   const size_t per = 8 + 8 * (size_t)nacc + 4;
   int l = (int)(kRjLdsBytes / per) - 1 - kWave;
   if (l > kRjChunks * kRjBlock - 1) l = kRjChunks * kRjBlock - 1;
-  return l;
+  return l & ~(kRjBucket - 1);  // whole buckets
 }
 
 int rj_kpr(int lcap) { return (int)((int64_t)lcap * 13 / 20); }  // load factor 0.65
