@@ -48,9 +48,10 @@
 namespace gq {
 namespace {
 
-constexpr int kRpBlock = 256;
-constexpr int kRpSub = 512;                      // rows per scatter sub-tile (unit of the staging layout)
-constexpr int kRpRows = kRpSub / kRpBlock;       // rows per thread per scatter sub-tile
+constexpr int kRpBlock = 256;                    // hist workgroup
+constexpr int kRpSBlock = 1024;                  // scatter workgroup
+constexpr int kRpSub = 2048;                     // rows per scatter sub-tile (unit of the staging layout)
+constexpr int kRpRows = kRpSub / kRpSBlock;      // rows per thread per scatter sub-tile
 constexpr int kRpTile = 16384;                   // rows per hist tile
 constexpr int kRpSubs = kRpTile / kRpSub;        // scatter sub-tiles per hist tile
 constexpr int kRpHSub = 2048;                    // rows per hist sub-tile
@@ -106,32 +107,33 @@ struct RpArgs {
 // every load of the sub-tile is in flight at once); slices that are not
 // 16-byte aligned, and the ragged end of a column, are copied byte by byte.
 // The caller waits and synchronises the block before reading.
+template <int BLOCK>
 __device__ __forceinline__ void rp_stage(const RpArgs& a, int nst, int scale, int64_t sbase, int nrows,
                                          uint8_t* s_in) {
-  for (int j = 0; j < nst; ++j) stage_col_lds<kRpBlock>(a.st[j], sbase, nrows, s_in + a.st_off[j] * scale);
+  for (int j = 0; j < nst; ++j) stage_col_lds<BLOCK>(a.st[j], sbase, nrows, s_in + a.st_off[j] * scale);
 }
 
 // The ROWS rows r = i * 256 + threadIdx.x of a staged column; one type
 // dispatch for all of them.
-template <int ROWS>
+template <int ROWS, int BLOCK>
 __device__ __forceinline__ void lds_rows(const uint8_t* base, int type, int64_t (&v)[ROWS]) {
   const int t = threadIdx.x;
   switch (type) {
     case GQ_I8:
 #pragma unroll
-      for (int i = 0; i < ROWS; ++i) v[i] = reinterpret_cast<const int8_t*>(base)[i * kRpBlock + t];
+      for (int i = 0; i < ROWS; ++i) v[i] = reinterpret_cast<const int8_t*>(base)[i * BLOCK + t];
       break;
     case GQ_I16:
 #pragma unroll
-      for (int i = 0; i < ROWS; ++i) v[i] = reinterpret_cast<const int16_t*>(base)[i * kRpBlock + t];
+      for (int i = 0; i < ROWS; ++i) v[i] = reinterpret_cast<const int16_t*>(base)[i * BLOCK + t];
       break;
     case GQ_I32:
 #pragma unroll
-      for (int i = 0; i < ROWS; ++i) v[i] = reinterpret_cast<const int32_t*>(base)[i * kRpBlock + t];
+      for (int i = 0; i < ROWS; ++i) v[i] = reinterpret_cast<const int32_t*>(base)[i * BLOCK + t];
       break;
     default:
 #pragma unroll
-      for (int i = 0; i < ROWS; ++i) v[i] = reinterpret_cast<const int64_t*>(base)[i * kRpBlock + t];
+      for (int i = 0; i < ROWS; ++i) v[i] = reinterpret_cast<const int64_t*>(base)[i * BLOCK + t];
       break;
   }
 }
@@ -139,18 +141,18 @@ __device__ __forceinline__ void lds_rows(const uint8_t* base, int type, int64_t 
 // Rows r = i * 256 + threadIdx.x of the staged sub-tile at sbase: mask of the
 // kept ones (predicates pass, key non-NULL) and their keys.  Column-major: each
 // predicate is applied to all rows of the thread before the next.
-template <int ROWS>
+template <int ROWS, int BLOCK>
 __device__ __forceinline__ uint32_t rp_rows_keep(const RpArgs& a, const uint8_t* s_in, int scale, int64_t sbase,
                                                  int nrows, int64_t (&key)[ROWS]) {
   uint32_t keep = 0;
 #pragma unroll
   for (int i = 0; i < ROWS; ++i)
-    if (i * kRpBlock + (int)threadIdx.x < nrows) keep |= 1u << i;
+    if (i * BLOCK + (int)threadIdx.x < nrows) keep |= 1u << i;
   for (int p = 0; p < a.npreds; ++p) {
     const int j = a.pred_st[p];
     const DCol& c = a.st[j];
     int64_t v[ROWS];
-    lds_rows<ROWS>(s_in + a.st_off[j] * scale, c.type, v);
+    lds_rows<ROWS, BLOCK>(s_in + a.st_off[j] * scale, c.type, v);
     const int64_t lo = a.preds[p].lo, hi = a.preds[p].hi;
     if (a.preds[p].op == GQ_RANGE) {
 #pragma unroll
@@ -164,15 +166,15 @@ __device__ __forceinline__ uint32_t rp_rows_keep(const RpArgs& a, const uint8_t*
     if (c.valid) {
 #pragma unroll
       for (int i = 0; i < ROWS; ++i)
-        if (((keep >> i) & 1u) && !valid_one(c, sbase + i * kRpBlock + threadIdx.x)) keep &= ~(1u << i);
+        if (((keep >> i) & 1u) && !valid_one(c, sbase + i * BLOCK + threadIdx.x)) keep &= ~(1u << i);
     }
   }
   const DCol& kc = a.st[a.key_st];
-  lds_rows<ROWS>(s_in + a.st_off[a.key_st] * scale, kc.type, key);
+  lds_rows<ROWS, BLOCK>(s_in + a.st_off[a.key_st] * scale, kc.type, key);
   if (kc.valid) {
 #pragma unroll
     for (int i = 0; i < ROWS; ++i)
-      if (((keep >> i) & 1u) && !valid_one(kc, sbase + i * kRpBlock + threadIdx.x)) keep &= ~(1u << i);
+      if (((keep >> i) & 1u) && !valid_one(kc, sbase + i * BLOCK + threadIdx.x)) keep &= ~(1u << i);
   }
   return keep;
 }
@@ -211,11 +213,11 @@ __global__ __launch_bounds__(kRpBlock) void k_rp_hist(const RpArgs a) {
     if (sbase >= a.n) break;
     const int nrows = a.n - sbase < kRpHSub ? (int)(a.n - sbase) : kRpHSub;
     __syncthreads();  // previous sub-tile's rows read
-    rp_stage(a, a.nst_hist, kRpHScale, sbase, nrows, s_in);
+    rp_stage<kRpBlock>(a, a.nst_hist, kRpHScale, sbase, nrows, s_in);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     int64_t key[kRpHRows];
-    const uint32_t keep = rp_rows_keep<kRpHRows>(a, s_in, kRpHScale, sbase, nrows, key);
+    const uint32_t keep = rp_rows_keep<kRpHRows, kRpBlock>(a, s_in, kRpHScale, sbase, nrows, key);
 #pragma unroll
     for (int i = 0; i < kRpHRows; ++i)
       if ((keep >> i) & 1u) atomicAdd(&s_hist[region_of(region_hash((uint64_t)key[i]), a.pbits)], 1u);
@@ -310,27 +312,27 @@ __host__ __device__ inline size_t rp_scatter_lds(int P, int in_bytes) {
   return align_up((size_t)P * 4, 16) + align_up((size_t)in_bytes, 16);
 }
 
-__global__ __launch_bounds__(kRpBlock) void k_rp_scatter(const RpArgs a) {
+__global__ __launch_bounds__(kRpSBlock) void k_rp_scatter(const RpArgs a) {
   extern __shared__ __attribute__((aligned(16))) uint8_t s_raw[];
   const int P = 1 << a.pbits;
   uint32_t* s_pos = reinterpret_cast<uint32_t*>(s_raw);
   uint8_t* s_in = s_raw + align_up((size_t)P * 4, 16);
   const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
-  for (int q = threadIdx.x; q < P; q += kRpBlock) s_pos[q] = a.starts[tile * P + q];
+  for (int q = threadIdx.x; q < P; q += kRpSBlock) s_pos[q] = a.starts[tile * P + q];
   for (int sub = 0; sub < kRpSubs; ++sub) {
     const int64_t sbase = tile * kRpTile + (int64_t)sub * kRpSub;
     if (sbase >= a.n) break;
     const int nrows = a.n - sbase < kRpSub ? (int)(a.n - sbase) : kRpSub;
     __syncthreads();  // previous sub-tile's rows written
-    rp_stage(a, a.nst, 1, sbase, nrows, s_in);
+    rp_stage<kRpSBlock>(a, a.nst, 1, sbase, nrows, s_in);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     int64_t key[kRpRows];
-    const uint32_t keep = rp_rows_keep<kRpRows>(a, s_in, 1, sbase, nrows, key);
+    const uint32_t keep = rp_rows_keep<kRpRows, kRpSBlock>(a, s_in, 1, sbase, nrows, key);
 #pragma unroll
     for (int i = 0; i < kRpRows; ++i) {
       if (!((keep >> i) & 1u)) continue;
-      const int r = i * kRpBlock + threadIdx.x;
+      const int r = i * kRpSBlock + threadIdx.x;
       const uint64_t h = region_hash((uint64_t)key[i]);
       const int64_t g = atomicAdd(&s_pos[region_of(h, a.pbits)], 1u);
       if (g >= a.ocap) continue;
@@ -822,7 +824,7 @@ int rp_run(gq_ctx* ctx, RpArgs& a, int64_t* offsets, int64_t* total, hipStream_t
   GQ_LAUNCH_CHECK(ctx);
   const size_t lds = rp_scatter_lds((int)P, a.in_bytes);
   GQ_LAUNCH(ctx, a.probe ? "rp_scatter_probe" : "rp_scatter_build", k_rp_scatter, dim3((unsigned)a.ntiles),
-            dim3(kRpBlock), lds, stream, a);
+            dim3(kRpSBlock), lds, stream, a);
   GQ_LAUNCH_CHECK(ctx);
   return GQ_OK;
 }
