@@ -258,6 +258,7 @@ __global__ __launch_bounds__(1024) void k_cs_base(const uint32_t* csum, int64_t 
     tot[j] = 0;
     if (j < per && q < P) {
       uint32_t v = 0;
+#pragma unroll 8
       for (int64_t c = 0; c < nchunks; ++c) v += csum[c * P + q];
       tot[j] = v;
     }
@@ -296,9 +297,11 @@ __global__ __launch_bounds__(256) void k_cs_fill(const uint32_t* counts, const u
   if (q >= P) return;
   const int64_t c = blockIdx.x;
   uint32_t run = (uint32_t)offsets[q];
+#pragma unroll 8
   for (int64_t k = 0; k < c; ++k) run += csum[k * P + q];
   const int64_t t0 = c * kCsChunk;
   const int64_t t1 = t0 + kCsChunk < ntiles ? t0 + kCsChunk : ntiles;
+#pragma unroll 8
   for (int64_t t = t0; t < t1; ++t) {
     const uint32_t v = counts[t * P + q];
     starts[t * P + q] = run;
