@@ -232,8 +232,10 @@ __global__ __launch_bounds__(kRpBlock) void k_rp_hist(const RpArgs a) {
 // before t, offsets[q] = the counts of all regions before q.
 constexpr int kCsChunk = 64;  // tiles per chunk
 
-// Per chunk of tiles and region: the sum of the chunk's counts.
-__global__ __launch_bounds__(256) void k_cs_chunk(const uint32_t* counts, int64_t ntiles, int P, uint32_t* csum) {
+// Per chunk of tiles and region: the sum of the chunk's counts, also added to
+// the region's total (zeroed before).
+__global__ __launch_bounds__(256) void k_cs_chunk(const uint32_t* counts, int64_t ntiles, int P, uint32_t* csum,
+                                                  uint32_t* tot) {
   const int q = blockIdx.y * 256 + threadIdx.x;
   if (q >= P) return;
   const int64_t t0 = (int64_t)blockIdx.x * kCsChunk;
@@ -242,11 +244,11 @@ __global__ __launch_bounds__(256) void k_cs_chunk(const uint32_t* counts, int64_
 #pragma unroll 8
   for (int64_t t = t0; t < t1; ++t) sum += counts[t * P + q];
   csum[(int64_t)blockIdx.x * P + q] = sum;
+  if (sum) atomicAdd(&tot[q], sum);
 }
 
-// One block: region totals, their exclusive scan into offsets[0..P], total.
-__global__ __launch_bounds__(1024) void k_cs_base(const uint32_t* csum, int64_t nchunks, int P, int64_t* offsets,
-                                                  int64_t* total) {
+// One block: exclusive scan of the region totals into offsets[0..P], total.
+__global__ __launch_bounds__(1024) void k_cs_base(const uint32_t* rtot, int P, int64_t* offsets, int64_t* total) {
   constexpr int NW = 1024 / kWave;
   __shared__ int64_t s_wave[NW];
   const int per = (P + 1023) / 1024;  // <= 4
@@ -256,12 +258,7 @@ __global__ __launch_bounds__(1024) void k_cs_base(const uint32_t* csum, int64_t 
   for (int j = 0; j < 4; ++j) {
     const int q = (int)threadIdx.x * per + j;
     tot[j] = 0;
-    if (j < per && q < P) {
-      uint32_t v = 0;
-#pragma unroll 8
-      for (int64_t c = 0; c < nchunks; ++c) v += csum[c * P + q];
-      tot[j] = v;
-    }
+    if (j < per && q < P) tot[j] = rtot[q];
     sum += tot[j];
   }
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
@@ -396,6 +393,8 @@ struct RjJoinArgs {
   int32_t need_nn;
   AggPlan ap;
   int32_t vword[GQ_MAX_AGGS];   // value word of aggregate i in the tuple, -1 if none
+  int32_t sums_only;            // every aggregate is COUNT(*) or a SUM of a non-NULL input
+  int32_t sum_word[kRjMaxVals]; // then: accumulator word of value word v
   const uint64_t* bkey;     // build key hashes grouped by region
   const int64_t* boff;      // P + 1
   const uint64_t* tkey;     // probe tuple key hashes grouped by region
@@ -667,13 +666,32 @@ __global__ __launch_bounds__(kRjBlock) void k_rj_join(const RjJoinArgs a) {
         }
       }
       // Updates: tuples without a match go to this lane's dump slot (weight 0).
+      // Every multiplicity is read before the first update, so that the reads
+      // are in flight together.
       uint32_t slot[kRjProbeUnroll];
       uint64_t w[kRjProbeUnroll];
 #pragma unroll
       for (int u = 0; u < kRjProbeUnroll; ++u) {
         slot[u] = res[u] >= 0 ? (uint32_t)res[u] : dump;
         w[u] = s_mult[slot[u]];
+      }
+#pragma unroll
+      for (int u = 0; u < kRjProbeUnroll; ++u)
         atomicAdd((unsigned long long*)&s_acc[(size_t)slot[u] * a.nacc], (unsigned long long)w[u]);
+      if (a.sums_only) {
+        // Accumulator words at fixed kernel-argument offsets: no per-aggregate
+        // descriptor reads (whose waits would also wait for the updates).
+#pragma unroll
+        for (int v = 0; v < kRjMaxVals; ++v) {
+          if (v >= a.nv) break;
+          const int word = a.sum_word[v];
+#pragma unroll
+          for (int u = 0; u < kRjProbeUnroll; ++u) {
+            const uint64_t x = v == 0 ? xv[u][0] : xv[u][kRjMaxVals - 1];
+            atomicAdd((unsigned long long*)&s_acc[(size_t)slot[u] * a.nacc + word], (unsigned long long)(x * w[u]));
+          }
+        }
+        continue;
       }
       for (int g = 0; g < a.naggs; ++g) {
         const DAgg& ag = a.ap.aggs[g];
@@ -804,11 +822,13 @@ int rp_run(gq_ctx* ctx, RpArgs& a, int64_t* offsets, int64_t* total, hipStream_t
   const size_t off_counts = 256;
   const size_t off_starts = off_counts + align_up((size_t)m * 4, 256);
   const size_t off_csum = off_starts + align_up((size_t)m * 4, 256);
-  const size_t bytes = off_csum + align_up((size_t)nchunks * P * 4, 256);
+  const size_t off_tot = off_csum + align_up((size_t)nchunks * P * 4, 256);
+  const size_t bytes = off_tot + align_up((size_t)P * 4, 256);
   if (!ws.get(bytes)) return set_error(ctx, GQ_ERR_NOMEM, "radix join: partition workspace allocation failed");
   a.counts = ws.as<uint32_t>(off_counts);
   a.starts = ws.as<uint32_t>(off_starts);
   uint32_t* csum = ws.as<uint32_t>(off_csum);
+  uint32_t* rtot = ws.as<uint32_t>(off_tot);
   const size_t lds_hist = align_up((size_t)P * 4, 16) +
                          ((size_t)a.st_off[a.nst_hist - 1] +
                           align_up((size_t)kRpSub * type_width(a.st[a.nst_hist - 1].type), 16)) * kRpHScale;
@@ -816,11 +836,13 @@ int rp_run(gq_ctx* ctx, RpArgs& a, int64_t* offsets, int64_t* total, hipStream_t
             lds_hist, stream, a);
   GQ_LAUNCH_CHECK(ctx);
   const dim3 cgrid((unsigned)nchunks, (unsigned)((P + 255) / 256));
+  int rc = launch_fill_u32(ctx, rtot, 0u, P, stream);
+  if (rc) return rc;
   GQ_LAUNCH(ctx, a.probe ? "rp_scan_probe" : "rp_scan_build", k_cs_chunk, cgrid, dim3(256), 0, stream,
-            (const uint32_t*)a.counts, a.ntiles, (int)P, csum);
+            (const uint32_t*)a.counts, a.ntiles, (int)P, csum, rtot);
   GQ_LAUNCH_CHECK(ctx);
   GQ_LAUNCH(ctx, a.probe ? "rp_scan_probe" : "rp_scan_build", k_cs_base, dim3(1), dim3(1024), 0, stream,
-            (const uint32_t*)csum, nchunks, (int)P, offsets, total);
+            (const uint32_t*)rtot, (int)P, offsets, total);
   GQ_LAUNCH_CHECK(ctx);
   GQ_LAUNCH(ctx, a.probe ? "rp_scan_probe" : "rp_scan_build", k_cs_fill, cgrid, dim3(256), 0, stream,
             (const uint32_t*)a.counts, (const uint32_t*)csum, (const int64_t*)offsets, a.ntiles, (int)P, a.starts);
@@ -974,6 +996,13 @@ int rj_groupjoin(gq_ctx* ctx, const gq_batch* in, int32_t probe_key, const gq_pr
   j.nv = r.nv;
   j.need_nn = r.need_nn;
   j.ap = ap;
+  j.sums_only = 1;
+  for (int i = 0; i < ap.naggs; ++i) {
+    const DAgg& ag = ap.aggs[i];
+    if (ag.op == GQ_COUNT_STAR) continue;
+    if (ag.op != GQ_SUM || ag.cword >= 0 || j.vword[i] < 0) j.sums_only = 0;
+    else j.sum_word[j.vword[i]] = ag.word;
+  }
   j.bkey = t->rj_key;
   j.boff = t->rj_off;
   j.tkey = r.okey;
