@@ -35,6 +35,7 @@ struct GbArgs {
   uint64_t cap;
   JoinRef join;
   int32_t* dev_status;
+  int64_t tile_rows;  // batched plans: rows per work item of this fragment
 };
 
 template <int ITEMS, class C>

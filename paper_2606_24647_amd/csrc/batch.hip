@@ -29,6 +29,7 @@ namespace {
 constexpr int kBBlock = 256;
 constexpr int kBItems = 4;
 constexpr int kBCItems = 8;
+constexpr int kBLdsTileMul = 4;  // work item of an LDS fragment: this many tiles
 
 
 struct BatchArgs {
@@ -85,8 +86,9 @@ __global__ __launch_bounds__(BLOCK) void k_batch_agg(const BatchArgs a) {
     if (t >= a.ntiles) break;
     const int f = __builtin_amdgcn_readfirstlane(s_f);
     const GQ_CONST_AS GbArgs& g = cref(a.frags + f);
-    const int64_t row0 = (t - cref(a.tile_start + f)) * a.tile_rows;
-    const int64_t row1 = row0 + a.tile_rows < g.n ? row0 + a.tile_rows : g.n;
+    const int64_t tr = g.tile_rows;
+    const int64_t row0 = (t - cref(a.tile_start + f)) * tr;
+    const int64_t row1 = row0 + tr < g.n ? row0 + tr : g.n;
     const bool lds = g.lcap > 0;
     if (lds) {
       for (int i = threadIdx.x; i < a.lcap * sw; i += BLOCK) {
@@ -308,11 +310,14 @@ int gq_batch_plan_create(gq_ctx* ctx, const gq_fragment* frags, int nfrags, cons
     if (cap < 16) cap = 16;
     g.cap = cap;
     g.lcap = expected <= lds_max ? 1 : 0;  // LDS flag; the size is set below
+    // LDS fragments merge their table into HBM after every work item, with
+    // device-wide atomics that contend on few slots: larger items, fewer merges.
+    g.tile_rows = g.lcap ? (int64_t)tile_rows * kBLdsTileMul : tile_rows;
     g.keys = reinterpret_cast<uint64_t*>((uintptr_t)nslots);  // offset for now
     nslots += (int64_t)cap + 2;
     total_rows += g.n;
     is_radix[f] = spec->nkeys > 0 && expected >= radix_min && g.n > 0 && g.n < ((int64_t)1 << 31);
-    tstart[f + 1] = tstart[f] + (is_radix[f] ? 0 : (g.n + tile_rows - 1) / tile_rows);
+    tstart[f + 1] = tstart[f] + (is_radix[f] ? 0 : (g.n + g.tile_rows - 1) / g.tile_rows);
     // outputs
     BatchOut& bo = outs[f];
     std::memset(&bo, 0, sizeof(bo));
@@ -387,7 +392,7 @@ int gq_batch_plan_create(gq_ctx* ctx, const gq_fragment* frags, int nfrags, cons
     }
     // Fragments that fell back to the tile path need tiles again.
     for (int f = 0; f < nfrags; ++f) {
-      const int64_t t = is_radix[f] ? 0 : (plans[f].n + tile_rows - 1) / tile_rows;
+      const int64_t t = is_radix[f] ? 0 : (plans[f].n + plans[f].tile_rows - 1) / plans[f].tile_rows;
       tstart[f + 1] = tstart[f] + t;
     }
     for (int f = 0; f < nfrags; ++f) outs[f].append = is_radix[f] ? 1 : 0;
@@ -406,7 +411,7 @@ int gq_batch_plan_create(gq_ctx* ctx, const gq_fragment* frags, int nfrags, cons
       for (int f = 0; f < nfrags; ++f) {
         is_radix[f] = 0;
         outs[f].append = 0;
-        tstart[f + 1] = tstart[f] + (plans[f].n + tile_rows - 1) / tile_rows;
+        tstart[f + 1] = tstart[f] + (plans[f].n + plans[f].tile_rows - 1) / plans[f].tile_rows;
       }
     }
   }
