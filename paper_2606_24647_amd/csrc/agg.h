@@ -36,6 +36,9 @@ struct GbArgs {
   JoinRef join;
   int32_t* dev_status;
   int64_t tile_rows;  // batched plans: rows per work item of this fragment
+  int32_t nrep;       // LDS strategy: replicas of the HBM table the blocks merge into
+  int32_t pad_rep;
+  int64_t rep_slots;  // slots per replica (cap + 2)
 };
 
 template <int ITEMS, class C>

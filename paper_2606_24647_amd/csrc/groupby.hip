@@ -28,6 +28,8 @@ namespace {
 constexpr int kGbBlock = 256;
 constexpr int kGbItems = 4;
 constexpr int kGbLdsItems = 8;   // rows per thread per tile of the LDS strategy
+constexpr int kGbReplicas = 16;  // HBM table replicas of a small LDS-strategy table
+constexpr uint64_t kGbRepMaxCap = 1024;
 constexpr int kGbLdsBlocksPerCu = 4;
 constexpr int kGjItems = 8;
 constexpr size_t kLdsBudget = 32 * 1024;
@@ -133,11 +135,42 @@ __global__ __launch_bounds__(BLOCK) void k_gb_lds(const GbArgs a) {
     apply_rows<ITEMS>(a.ap, r0, a.n, keep, w, s_tab, loff, gsp);
   }
   __syncthreads();
+  // Block b merges into replica b % nrep of the HBM table (device-wide
+  // atomics on few group slots contend less); k_gb_rep_merge folds the
+  // replicas into the first.
+  const int rep = a.nrep > 1 ? (int)(blockIdx.x % a.nrep) : 0;
+  uint64_t* rkeys = a.keys + (size_t)rep * a.rep_slots;
+  uint64_t* racc = a.acc + (size_t)rep * a.rep_slots * a.ap.nacc;
   for (int i = threadIdx.x; i < lcap; i += BLOCK) {
     const uint64_t* ls = s_tab + (size_t)i * sw;
     if (ls[0] == kEmpty) continue;
-    uint64_t* gs = global_acc(a, ls[0], 0);
-    if (gs) merge_words(a.ap, gs, ls + 1);
+    bool ins;
+    const int64_t sl = find_insert(rkeys, a.cap, ls[0], &ins);
+    if (sl < 0) {
+      atomicOr(a.dev_status, GQ_DEV_TABLE_FULL);
+      continue;
+    }
+    merge_words(a.ap, racc + (size_t)sl * a.ap.nacc, ls + 1);
+  }
+}
+
+// Fold replicas 1..nrep-1 of the HBM table into replica 0.
+__global__ void k_gb_rep_merge(const GbArgs a) {
+  const int64_t total = (int64_t)(a.nrep - 1) * a.rep_slots;
+  const int64_t step = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += step) {
+    const int64_t r = 1 + idx / a.rep_slots, sl = idx % a.rep_slots;
+    const uint64_t* src = a.acc + ((size_t)r * a.rep_slots + sl) * a.ap.nacc;
+    uint64_t* dst;
+    if (sl < (int64_t)a.cap) {
+      const uint64_t key = a.keys[(size_t)r * a.rep_slots + sl];
+      if (key == kEmpty) continue;
+      dst = global_acc(a, key, 0);
+    } else {
+      if (src[0] == 0) continue;  // extra slot never used in this replica
+      dst = global_acc(a, 0, (int)(sl - (int64_t)a.cap) + 1);
+    }
+    if (dst) merge_words(a.ap, dst, src);
   }
 }
 
@@ -443,25 +476,6 @@ int run_groupby(gq_ctx* ctx, const gq_batch* in, const int32_t* keys, int nkeys,
   rc = check_outputs(ctx, nkeys, naggs, out, ca, key_types);
   if (rc) return rc;
 
-  // Table sizing.
-  int64_t expected = o.expected_groups > 0 ? o.expected_groups : in->nrows;
-  if (nkeys == 0) expected = 1;
-  uint64_t cap = (uint64_t)((double)expected / lf) + 1;
-  if (cap < 16) cap = 16;
-  a.cap = cap;
-  const size_t nslot = (size_t)cap + 2;
-  const size_t off_acc = align_up(nslot * 8, 256);
-  const size_t bytes = off_acc + nslot * 8 * (size_t)a.ap.nacc;
-  Scratch table(ctx, stream);
-  if (!table.get(bytes)) return set_error(ctx, GQ_ERR_NOMEM, "group-by: table allocation failed");
-  a.keys = table.as<uint64_t>(0);
-  a.acc = table.as<uint64_t>(off_acc);
-  int64_t iblocks = (int64_t)((nslot + 255) / 256);
-  if (iblocks > 8192) iblocks = 8192;
-  GQ_LAUNCH(ctx, "gt_init", k_gt_init, dim3((unsigned)iblocks), dim3(256), 0, stream, a.keys, a.acc, (int64_t)nslot,
-            a.ap);
-  GQ_LAUNCH_CHECK(ctx);
-
   int strategy = o.strategy;
   if (strategy == GQ_STRATEGY_AUTO) {
     // LDS privatisation unless the caller expects more groups than a block's
@@ -469,8 +483,37 @@ int run_groupby(gq_ctx* ctx, const gq_batch* in, const int32_t* keys, int nkeys,
     // no LDS slot fall through to HBM).
     strategy = (o.expected_groups == 0 || o.expected_groups <= 256) ? GQ_STRATEGY_LDS : GQ_STRATEGY_GLOBAL;
   }
+
+  // Table sizing.  A small table under the LDS strategy gets replicas for the
+  // blocks' merges.
+  int64_t expected = o.expected_groups > 0 ? o.expected_groups : in->nrows;
+  if (nkeys == 0) expected = 1;
+  uint64_t cap = (uint64_t)((double)expected / lf) + 1;
+  if (cap < 16) cap = 16;
+  a.cap = cap;
+  const size_t nslot = (size_t)cap + 2;
+  a.nrep = strategy == GQ_STRATEGY_LDS && cap <= kGbRepMaxCap ? kGbReplicas : 1;
+  a.rep_slots = (int64_t)nslot;
+  const size_t nslot_all = nslot * (size_t)a.nrep;
+  const size_t off_acc = align_up(nslot_all * 8, 256);
+  const size_t bytes = off_acc + nslot_all * 8 * (size_t)a.ap.nacc;
+  Scratch table(ctx, stream);
+  if (!table.get(bytes)) return set_error(ctx, GQ_ERR_NOMEM, "group-by: table allocation failed");
+  a.keys = table.as<uint64_t>(0);
+  a.acc = table.as<uint64_t>(off_acc);
+  int64_t iblocks = (int64_t)((nslot_all + 255) / 256);
+  if (iblocks > 8192) iblocks = 8192;
+  GQ_LAUNCH(ctx, "gt_init", k_gt_init, dim3((unsigned)iblocks), dim3(256), 0, stream, a.keys, a.acc,
+            (int64_t)nslot_all, a.ap);
+  GQ_LAUNCH_CHECK(ctx);
+
   rc = join ? launch_aggregate<true>(ctx, a, strategy, stream) : launch_aggregate<false>(ctx, a, strategy, stream);
   if (rc) return rc;
+  if (a.nrep > 1 && a.n > 0) {
+    const int64_t mblocks = ((int64_t)(a.nrep - 1) * a.rep_slots + 255) / 256;
+    GQ_LAUNCH(ctx, "gb_rep_merge", k_gb_rep_merge, dim3((unsigned)mblocks), dim3(256), 0, stream, a);
+    GQ_LAUNCH_CHECK(ctx);
+  }
 
   ca.keys = a.keys;
   ca.acc = a.acc;
