@@ -14,7 +14,6 @@ struct BatchOut {
   int32_t append;  // the compaction appends after groups already written (radix fragments)
   int32_t pad;
 };
-typedef BatchOut BatchOutRef;
 
 constexpr int kBrxMaxStage = 8;
 

@@ -18,7 +18,8 @@
 //                 so that every tile reads and writes its P counts coalesced:
 //                 per-chunk column sums, region totals and offsets (one
 //                 block), then the start of every (tile, region)
-//   k_rp_scatter  each hist tile in sub-tiles of 512 rows staged in LDS; a
+//   k_rp_scatter  each hist tile in sub-tiles of 2048 rows staged in LDS (one
+//                 1024-thread workgroup per tile); a
 //                 kept row takes the next position of its region in the tile's
 //                 range with an LDS atomic and is written there: build keys and
 //                 build row ids grouped by region (order inside a region is

@@ -174,3 +174,32 @@ def test_radix_reuse_table(gq, ctx):
     assert n == len(epi)
     assert np.array_equal(pi[:n].cpu().numpy(), epi) and np.array_equal(bi[:n].cpu().numpy(), ebi)
     jt.free()
+
+
+@pytest.mark.parametrize("rlog", [4, 9, 12])
+def test_radix_region_counts(gq, ctx, rlog):
+    # 16 regions (two per XCD queue), 512, and 4096 (about 256 build keys each).
+    n_dim, n_fact = MIN_BUILD + 4097, 1_200_007
+    dim = dg.dim_c2(n_dim, seed=42)
+    fact = dg.fact_c2(n_fact, nkeys=n_dim, seed=42)
+    jt = ctx.join_build(gq.to_device(dim), [0], [("range", 1, 0, 1202)], regions_log2=rlog)
+    out, cnt = ctx.pipeline(gq.to_device(fact), [("range", 3, 1278, 2555)], [0], [("sum", REV), ("count*",)],
+                            join=jt, probe_key=0)
+    assert ctx.sync_status() == 0
+    n = int(cnt.item())
+    cols = gq.read_table(out, n)
+    jt.free()
+    exp = oracle.pipeline(fact, [("range", 3, 1278, 2555)], [0], [("sum", REV), ("count*",)],
+                          join_spec=(dim, [0], [("range", 1, 0, 1202)], [0]))
+    assert n == exp.nrows
+    gk, ga = canon_groups([(cols[0][0].astype(np.int64), cols[0][1])], cols[1:])
+    ek, ea = canon_groups(exp.keys, exp.aggs)
+    for (gv, _), (ev, _) in zip(gk + ga, ek + ea):
+        assert np.array_equal(gv, ev)
+
+
+@pytest.mark.parametrize("rlog", [3, 13])
+def test_radix_region_count_out_of_range(gq, ctx, rlog):
+    dim = dg.dim_c2(1000, seed=43)
+    with pytest.raises(gq.GqError):
+        ctx.join_build(gq.to_device(dim), [0], [], regions_log2=rlog)
