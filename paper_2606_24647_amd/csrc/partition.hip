@@ -54,6 +54,9 @@ constexpr int kPSub = 1024;                  // rows per sub-tile
 constexpr int kPSubs = 16;                   // sub-tiles per hist tile
 constexpr int kPTile = kPSub * kPSubs;       // rows per hist tile
 constexpr int kPSteps = kPSub / kPBlock;     // rows per thread per sub-tile
+constexpr int kPWBlock = 1024;               // wide scatter variant: workgroup
+constexpr int kPWSub = kPSteps * kPWBlock;   // and sub-tile rows
+constexpr size_t kPWMaxLds = 150 * 1024;
 
 // Staged rows r0 + i * stride, i < kPSteps, of one column: one type dispatch.
 __device__ __forceinline__ void lds_rows_at(const uint8_t* base, int type, int r0, int stride,
@@ -204,46 +207,53 @@ __global__ __launch_bounds__(BLOCK) void k_scan_counts(const uint32_t* counts, i
 // LDS of k_part_scatter (dynamic): staged columns (in_bytes), per-wave
 // counts [4][P] (u32), sub-tile starts [P + 1] (u32), write positions [P]
 // (i64), then per sorted position its partition and source row (u16 each).
+template <int BLOCK, int SUB>
 __host__ inline size_t part_scatter_lds(int P, int in_bytes) {
-  return align_up((size_t)in_bytes, 16) + align_up((size_t)4 * P * 4, 16) + align_up((size_t)(P + 1) * 4, 16) +
-         (size_t)P * 8 + (size_t)kPSub * 4;
+  return align_up((size_t)in_bytes, 16) + align_up((size_t)(BLOCK / kWave) * P * 4, 16) +
+         align_up((size_t)(P + 1) * 4, 16) + (size_t)P * 8 + (size_t)SUB * 4;
 }
 
-__global__ __launch_bounds__(kPBlock) void k_part_scatter(const PartArgs a) {
-  constexpr int NW = kPBlock / kWave;
+// BLOCK threads stage SUB = 4 * BLOCK rows per sub-tile: the wide variant
+// (1024 threads, 4096 rows) writes longer runs per partition; the narrow one
+// (256, 1024) serves column sets too wide to stage 4096 rows.
+template <int BLOCK, int SUB>
+__global__ __launch_bounds__(BLOCK) void k_part_scatter(const PartArgs a) {
+  static_assert(SUB == kPSteps * BLOCK, "four rows per thread per sub-tile");
+  constexpr int NW = BLOCK / kWave;
+  constexpr int SUBS = kPTile / SUB;
   extern __shared__ __attribute__((aligned(16))) uint8_t s_raw[];
   const int P = (int)a.nparts;
   uint8_t* s_in = s_raw;
   uint32_t* s_whist = reinterpret_cast<uint32_t*>(s_raw + align_up((size_t)a.in_bytes, 16));
-  uint32_t* s_sub = reinterpret_cast<uint32_t*>(reinterpret_cast<uint8_t*>(s_whist) + align_up((size_t)4 * P * 4, 16));
+  uint32_t* s_sub = reinterpret_cast<uint32_t*>(reinterpret_cast<uint8_t*>(s_whist) + align_up((size_t)NW * P * 4, 16));
   int64_t* s_base = reinterpret_cast<int64_t*>(reinterpret_cast<uint8_t*>(s_sub) + align_up((size_t)(P + 1) * 4, 16));
   uint16_t* s_pid = reinterpret_cast<uint16_t*>(s_base + P);
-  uint16_t* s_src = s_pid + kPSub;
+  uint16_t* s_src = s_pid + SUB;
   __shared__ uint32_t s_wsum[NW];
 
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
   const int64_t n = rows_of(a);
-  for (int q = threadIdx.x; q < P; q += kPBlock) s_base[q] = a.starts[(int64_t)q * a.ntiles + tile];
+  for (int q = threadIdx.x; q < P; q += BLOCK) s_base[q] = a.starts[(int64_t)q * a.ntiles + tile];
   int nbits = 0;
   while ((1 << nbits) < P) ++nbits;
   auto kbase = [&](int j) { return (const uint8_t*)(s_in + a.st_off[a.key_col[j]]); };
-  const int per = (P + kPBlock - 1) / kPBlock;
+  const int per = (P + BLOCK - 1) / BLOCK;
 
-  for (int sub = 0; sub < kPSubs; ++sub) {
-    const int64_t sbase = tile * kPTile + (int64_t)sub * kPSub;
+  for (int sub = 0; sub < SUBS; ++sub) {
+    const int64_t sbase = tile * kPTile + (int64_t)sub * SUB;
     if (sbase >= n) break;
-    const int nrows = n - sbase < kPSub ? (int)(n - sbase) : kPSub;
-    for (int i = threadIdx.x; i < 4 * P; i += kPBlock) s_whist[i] = 0;
-    for (int j = 0; j < a.ncols; ++j) stage_col_lds<kPBlock>(a.cols[j], sbase, nrows, s_in + a.st_off[j]);
+    const int nrows = n - sbase < SUB ? (int)(n - sbase) : SUB;
+    for (int i = threadIdx.x; i < NW * P; i += BLOCK) s_whist[i] = 0;
+    for (int j = 0; j < a.ncols; ++j) stage_col_lds<BLOCK>(a.cols[j], sbase, nrows, s_in + a.st_off[j]);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     // Stable ranks: wave w owns rows 256w + 64i + lane, i = 0..3, in order.
     uint32_t pid[kPSteps], rank[kPSteps];
-    part_of_rows(a, sbase, wave * (kPSub / NW) + lane, kWave, nrows, kbase, pid);
+    part_of_rows(a, sbase, wave * (SUB / NW) + lane, kWave, nrows, kbase, pid);
 #pragma unroll
     for (int i = 0; i < kPSteps; ++i) {
-      const int r = wave * (kPSub / NW) + i * kWave + lane;
+      const int r = wave * (SUB / NW) + i * kWave + lane;
       const bool in = r < nrows;
       const uint32_t p = in ? pid[i] : 0u;
       uint64_t peers = ballot(in);
@@ -310,7 +320,7 @@ __global__ __launch_bounds__(kPBlock) void k_part_scatter(const PartArgs a) {
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < kPSteps; ++i) {
-      const int r = wave * (kPSub / NW) + i * kWave + lane;
+      const int r = wave * (SUB / NW) + i * kWave + lane;
       if (r < nrows) {
         const uint32_t pos = s_sub[pid[i]] + s_whist[wave * P + pid[i]] + rank[i];
         s_src[pos] = (uint16_t)r;
@@ -325,7 +335,7 @@ __global__ __launch_bounds__(kPBlock) void k_part_scatter(const PartArgs a) {
     int64_t grow[kPSteps];
 #pragma unroll
     for (int i = 0; i < kPSteps; ++i) {
-      const int k = i * kPBlock + threadIdx.x;
+      const int k = i * BLOCK + threadIdx.x;
       srow[i] = 0;
       grow[i] = -1;
       if (k < total) {
@@ -397,11 +407,20 @@ int launch_partition(gq_ctx* ctx, PartArgs& a, int64_t* d_offsets, hipStream_t s
   const int64_t m = ntiles * nparts;
   constexpr int STILE = kScanBlock * kScanItems;
   const int64_t nscan = (m + STILE - 1) / STILE;
-  // LDS layouts: every column for the scatter, the key columns for the histogram.
+  // LDS layouts: every column for the scatter (4096-row sub-tiles when they
+  // fit two workgroups' worth of LDS, else 1024), the key columns for the
+  // histogram.
+  int lds_max = 0;
+  GQ_HIP_CHECK(ctx, hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device));
+  size_t row_bytes = 0;
+  for (int j = 0; j < a.ncols; ++j) row_bytes += (size_t)type_width(a.cols[j].type);
+  const size_t wide_lds = part_scatter_lds<kPWBlock, kPWSub>((int)nparts, (int)(row_bytes * kPWSub + 16 * a.ncols));
+  const bool wide = wide_lds <= kPWMaxLds && wide_lds + 256 <= (size_t)lds_max;
+  const int ssub = wide ? kPWSub : kPSub;
   a.in_bytes = 0;
   for (int j = 0; j < a.ncols; ++j) {
     a.st_off[j] = a.in_bytes;
-    a.in_bytes += (int)align_up((size_t)kPSub * type_width(a.cols[j].type), 16);
+    a.in_bytes += (int)align_up((size_t)ssub * type_width(a.cols[j].type), 16);
   }
   a.kin_bytes = 0;
   const int nk = a.digit ? 1 : a.nkeys;
@@ -410,9 +429,8 @@ int launch_partition(gq_ctx* ctx, PartArgs& a, int64_t* d_offsets, hipStream_t s
     a.kin_bytes += (int)align_up((size_t)kPSub * type_width(a.keys[j].type), 16);
   }
   const size_t lds_hist = align_up((size_t)nparts * 4, 16) + (size_t)a.kin_bytes;
-  const size_t lds_scat = part_scatter_lds((int)nparts, a.in_bytes);
-  int lds_max = 0;
-  GQ_HIP_CHECK(ctx, hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device));
+  const size_t lds_scat = wide ? part_scatter_lds<kPWBlock, kPWSub>((int)nparts, a.in_bytes)
+                               : part_scatter_lds<kPBlock, kPSub>((int)nparts, a.in_bytes);
   if (lds_scat + 256 > (size_t)lds_max || lds_hist + 256 > (size_t)lds_max)
     return set_error(ctx, GQ_ERR_UNSUPPORTED, "partition: too many or too wide columns for one staged sub-tile");
 
@@ -438,7 +456,12 @@ int launch_partition(gq_ctx* ctx, PartArgs& a, int64_t* d_offsets, hipStream_t s
   GQ_LAUNCH(ctx, "scan_counts", (k_scan_counts<kScanBlock, kScanItems>), dim3((unsigned)nscan), dim3(kScanBlock), 0,
             stream, (const uint32_t*)a.counts, m, a.starts, ntiles, nparts, d_offsets, ticket, status, nscan);
   GQ_LAUNCH_CHECK(ctx);
-  GQ_LAUNCH(ctx, "part_scatter", k_part_scatter, dim3((unsigned)ntiles), dim3(kPBlock), lds_scat, stream, a);
+  if (wide)
+    GQ_LAUNCH(ctx, "part_scatter", (k_part_scatter<kPWBlock, kPWSub>), dim3((unsigned)ntiles), dim3(kPWBlock), lds_scat,
+              stream, a);
+  else
+    GQ_LAUNCH(ctx, "part_scatter", (k_part_scatter<kPBlock, kPSub>), dim3((unsigned)ntiles), dim3(kPBlock), lds_scat,
+              stream, a);
   GQ_LAUNCH_CHECK(ctx);
   return GQ_OK;
 }
