@@ -127,7 +127,7 @@ __global__ __launch_bounds__(BLOCK) void k_filter(const FilterArgs a) {
 }
 
 constexpr int kFilterBlock = 256;
-constexpr int kFilterItems = 8;
+constexpr int kFilterItems = 16;
 
 }  // namespace
 }  // namespace gq
