@@ -232,6 +232,8 @@ struct gq_batch_plan {
   void* mem = nullptr;  // arena + descriptors, one allocation
   size_t bytes = 0;
   hipStream_t cap_stream = nullptr;
+  hipStream_t side_stream = nullptr;  // capture only: the tile path beside the radix path
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int64_t total_rows = 0;
@@ -251,6 +253,9 @@ void plan_release(gq_batch_plan* p) {
     (void)hipStreamSynchronize(p->cap_stream);
     (void)hipStreamDestroy(p->cap_stream);
   }
+  if (p->side_stream) (void)hipStreamDestroy(p->side_stream);
+  if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+  if (p->ev_join) (void)hipEventDestroy(p->ev_join);
   if (p->mem) {
     (void)hipDeviceSynchronize();
     gq::ctx_free(p->ctx, p->mem, p->bytes, nullptr);
@@ -518,23 +523,44 @@ int gq_batch_plan_create(gq_ctx* ctx, const gq_fragment* frags, int nfrags, cons
   p->grid = prop.multiProcessorCount * bpc;
   const size_t lds_bytes = (size_t)lcap * sw * 8;
 
-  // Capture the three kernels on a private stream.
-  if (hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess)
+  // Capture the kernels on a private stream (and a second one for the branch
+  // of the tile path when radix fragments exist).
+  if (hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&p->side_stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming) != hipSuccess)
     return fail(GQ_ERR_HIP, "gq_batch_plan_create: stream creation failed");
   if (hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
     return fail(GQ_ERR_HIP, "gq_batch_plan_create: graph capture failed");
   int64_t iblocks = (nslots + 255) / 256;
   if (iblocks > 8192) iblocks = 8192;
   hipLaunchKernelGGL(k_batch_init, dim3((unsigned)iblocks), dim3(256), 0, p->cap_stream, a);
-  if (rx.nrf > 0 && brx_enqueue(rx, rx_tiles, rx_counts, rx_scatter_lds, rx_hist_lds, prop.multiProcessorCount,
-                                p->cap_stream) != GQ_OK) {
-    hipGraph_t g0 = nullptr;
-    (void)hipStreamEndCapture(p->cap_stream, &g0);
-    if (g0) (void)hipGraphDestroy(g0);
-    return fail(GQ_ERR_HIP, "gq_batch_plan_create: radix kernels failed to enqueue");
+  if (rx.nrf > 0) {
+    // The tile path (k_batch_agg) and the radix path touch disjoint fragments
+    // and counters: the graph runs them as two branches between the init and
+    // the compaction.
+    if (hipEventRecord(p->ev_fork, p->cap_stream) != hipSuccess ||
+        hipStreamWaitEvent(p->side_stream, p->ev_fork, 0) != hipSuccess) {
+      hipGraph_t g0 = nullptr;
+      (void)hipStreamEndCapture(p->cap_stream, &g0);
+      if (g0) (void)hipGraphDestroy(g0);
+      return fail(GQ_ERR_HIP, "gq_batch_plan_create: graph fork failed");
+    }
+    hipLaunchKernelGGL((k_batch_agg<kBBlock, kBItems>), dim3((unsigned)p->grid), dim3(kBBlock), lds_bytes,
+                       p->side_stream, a);
+    const bool rx_ok = brx_enqueue(rx, rx_tiles, rx_counts, rx_scatter_lds, rx_hist_lds, prop.multiProcessorCount,
+                                   p->cap_stream) == GQ_OK;
+    if (!rx_ok || hipEventRecord(p->ev_join, p->side_stream) != hipSuccess ||
+        hipStreamWaitEvent(p->cap_stream, p->ev_join, 0) != hipSuccess) {
+      hipGraph_t g0 = nullptr;
+      (void)hipStreamEndCapture(p->cap_stream, &g0);
+      if (g0) (void)hipGraphDestroy(g0);
+      return fail(GQ_ERR_HIP, "gq_batch_plan_create: radix kernels failed to enqueue");
+    }
+  } else {
+    hipLaunchKernelGGL((k_batch_agg<kBBlock, kBItems>), dim3((unsigned)p->grid), dim3(kBBlock), lds_bytes,
+                       p->cap_stream, a);
   }
-  hipLaunchKernelGGL((k_batch_agg<kBBlock, kBItems>), dim3((unsigned)p->grid), dim3(kBBlock), lds_bytes, p->cap_stream,
-                     a);
   hipLaunchKernelGGL((k_batch_compact<kBBlock, kBCItems>), dim3((unsigned)nfrags), dim3(kBBlock), 0, p->cap_stream, a);
   const hipError_t le = hipGetLastError();
   const hipError_t ce = hipStreamEndCapture(p->cap_stream, &p->graph);
