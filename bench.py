@@ -105,8 +105,20 @@ def median(xs):
 # The pipeline step (fact 60M x dim 15M)
 # ---------------------------------------------------------------------------
 
+_BUILD_STREAM = []
+
+
 def c2_step(ctx, dim, fact, out_cap, lf):
-    jt = ctx.join_build(dim, [0], DIM_PRED, load_factor=lf, acc_slots=2)
+    """Join build on a second stream (ordered after the current stream's work),
+    pipeline on the current stream: the library makes the pipeline wait for the
+    build only where it reads the table, so the probe side's partition overlaps
+    the build (the build -> probe hand-over is the step's only sync)."""
+    import torch
+    if not _BUILD_STREAM:
+        _BUILD_STREAM.append(torch.cuda.Stream())
+    bs = _BUILD_STREAM[0]
+    bs.wait_stream(torch.cuda.current_stream())
+    jt = ctx.join_build(dim, [0], DIM_PRED, load_factor=lf, acc_slots=2, stream=bs)
     out, cnt = ctx.pipeline(fact, FACT_PRED, [0], C2_AGGS, join=jt, probe_key=0, capacity=out_cap)
     jt.free()
     return out, cnt

@@ -244,10 +244,16 @@ typedef struct gq_join_opts {
 } gq_join_opts;
 
 /* Build a table over the rows of `build` that pass `preds` and have a non-NULL
- * key.  The table (library-owned, allocated through the context allocator) is
- * ready for probes enqueued after this call on the same stream, or on another
- * stream ordered after it by an event.  Its capacity is sized on the device
- * from the number of passing rows. */
+ * key.  The table (library-owned, allocated through the context allocator)
+ * records an event on `stream` after its build work; every call that reads it
+ * (gq_join_probe, gq_pipeline / gq_groupby_agg with a join,
+ * gq_join_table_free) makes its own stream wait for that event, and
+ * gq_pipeline's radix group-join waits only after partitioning its probe side.
+ * So a build enqueued on one stream overlaps the probe side of a pipeline
+ * enqueued on another (the build -> probe hand-over of Section 3 is the only
+ * synchronisation); the build input must stay unchanged until the build's work
+ * has run.  Its capacity is sized on the device from the number of passing
+ * rows. */
 int gq_join_build(gq_ctx* ctx, const gq_batch* build, const int32_t* keys, int nkeys,
                   const gq_pred* preds, int npreds, const gq_join_opts* opts,
                   hipStream_t stream, gq_join_table** out);

@@ -593,8 +593,15 @@ int build_index(gq_ctx* ctx, JoinBuildArgs& a, gq_join_table* t, bool count, hip
 
 }  // namespace
 
+int join_wait_ready(gq_ctx* ctx, const gq_join_table* t, hipStream_t stream) {
+  if (t && t->ready) GQ_HIP_CHECK(ctx, hipStreamWaitEvent(stream, t->ready, 0));
+  return GQ_OK;
+}
+
 int join_ensure_index(gq_ctx* ctx, const gq_join_table* table, hipStream_t stream) {
   gq_join_table* t = const_cast<gq_join_table*>(table);
+  int rc = join_wait_ready(ctx, t, stream);
+  if (rc) return rc;
   if (t->index_built) return GQ_OK;
   JoinBuildArgs a;
   std::memset(&a, 0, sizeof(a));
@@ -702,6 +709,11 @@ int gq_join_build(gq_ctx* ctx, const gq_batch* build, const int32_t* keys, int n
     rc = build_index(ctx, a, t, true, stream);
     if (rc) return fail(rc);
   }
+  if (hipEventCreateWithFlags(&t->ready, hipEventDisableTiming) != hipSuccess ||
+      hipEventRecord(t->ready, stream) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(set_error(ctx, GQ_ERR_HIP, "gq_join_build: event creation failed"));
+  }
   *out = t;
   return GQ_OK;
 }
@@ -768,6 +780,10 @@ const int64_t* gq_join_table_count_ptr(const gq_join_table* table) {
 int gq_join_table_free(gq_ctx* ctx, gq_join_table* table, hipStream_t stream) {
   if (!table) return GQ_OK;
   if (!ctx) ctx = table->ctx;
+  if (table->ready) {
+    (void)hipStreamWaitEvent(stream, table->ready, 0);
+    (void)hipEventDestroy(table->ready);
+  }
   ctx_free(ctx, table->mem, table->bytes, stream);
   delete table;
   return GQ_OK;

@@ -58,5 +58,7 @@ int rj_groupjoin(gq_ctx* ctx, const gq_batch* in, int32_t probe_key, const gq_pr
 // Build the probe index of a table whose build side was partitioned, if not
 // built yet (on `stream`; later users on other streams must be ordered after it).
 int join_ensure_index(gq_ctx* ctx, const gq_join_table* t, hipStream_t stream);
+// Make `stream` wait until the table's build work has run (join.hip).
+int join_wait_ready(gq_ctx* ctx, const gq_join_table* t, hipStream_t stream);
 
 }  // namespace gq

@@ -1020,6 +1020,9 @@ int rj_groupjoin(gq_ctx* ctx, const gq_batch* in, int32_t probe_key, const gq_pr
   j.out_cap = ca.out_cap;
   j.d_count = d_groups;
   j.dev_status = ctx->d_status;
+  // The probe side is partitioned; from here on the build side is read.
+  rc = join_wait_ready(ctx, t, stream);
+  if (rc) return rc;
   GQ_LAUNCH(ctx, "rj_plan", k_rj_plan, dim3(1), dim3(1024), 0, stream, j);
   GQ_LAUNCH_CHECK(ctx);
   int lds_max = 0;

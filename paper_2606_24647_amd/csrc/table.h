@@ -245,4 +245,7 @@ struct gq_join_table {
   uint64_t* rj_key = nullptr;
   int32_t* rj_row = nullptr;
   int64_t* rj_off = nullptr;
+  // Recorded on the build stream once the build work is enqueued; every call
+  // that reads the table waits for it on its own stream.
+  hipEvent_t ready = nullptr;
 };

@@ -203,3 +203,34 @@ def test_radix_region_count_out_of_range(gq, ctx, rlog):
     dim = dg.dim_c2(1000, seed=43)
     with pytest.raises(gq.GqError):
         ctx.join_build(gq.to_device(dim), [0], [], regions_log2=rlog)
+
+
+@pytest.mark.parametrize("radix", [True, False])
+def test_build_on_another_stream(gq, ctx, radix):
+    # The build is enqueued on a second stream behind a long kernel; the
+    # pipeline on the current stream must wait for it where it reads the table
+    # (radix path: after partitioning its probe side; index path: before it).
+    import torch
+    n_dim = MIN_BUILD + 3 if radix else 200_000
+    dim = dg.dim_c2(n_dim, seed=44)
+    fact = dg.fact_c2(900_001, nkeys=n_dim, seed=44)
+    bd, fd = gq.to_device(dim), gq.to_device(fact)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        x = torch.ones(1 << 24, device="cuda")
+        for _ in range(20):
+            x = x * 1.0001                     # delays the build on this stream
+    jt = ctx.join_build(bd, [0], [("range", 1, 0, 1202)], acc_slots=2, stream=s)
+    out, cnt = ctx.pipeline(fd, [("range", 3, 1278, 2555)], [0], [("sum", REV), ("count*",)], join=jt, probe_key=0)
+    jt.free()
+    assert ctx.sync_status() == 0
+    n = int(cnt.item())
+    cols = gq.read_table(out, n)
+    exp = oracle.pipeline(fact, [("range", 3, 1278, 2555)], [0], [("sum", REV), ("count*",)],
+                          join_spec=(dim, [0], [("range", 1, 0, 1202)], [0]))
+    assert n == exp.nrows
+    gk, ga = canon_groups([(cols[0][0].astype(np.int64), cols[0][1])], cols[1:])
+    ek, ea = canon_groups(exp.keys, exp.aggs)
+    for (gv, _), (ev, _) in zip(gk + ga, ek + ea):
+        assert np.array_equal(gv, ev)
