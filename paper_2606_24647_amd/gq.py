@@ -307,17 +307,33 @@ class GqAllocator(C.Structure):
 
 def _torch_allocator(device: int) -> GqAllocator:
     """gq_allocator over torch's caching allocator (stream-ordered per stream):
-    one cache for the library's scratch and the caller's tensors."""
+    one cache for the library's scratch and the caller's tensors.
+
+    torch reuses a freed block for later allocations on the stream it was
+    allocated on.  A block freed on another stream (a join table built on one
+    stream and freed on the stream that used it) first makes the allocation
+    stream wait for the freeing stream's work, so that reuse is ordered after
+    every use."""
+    owner = {}
 
     def alloc(nbytes, stream, user):
         try:
-            return torch.cuda.caching_allocator_alloc(max(1, int(nbytes)), device, stream or 0)
+            ptr = torch.cuda.caching_allocator_alloc(max(1, int(nbytes)), device, stream or 0)
         except Exception:  # noqa: BLE001 - reported by the library as GQ_ERR_NOMEM
             return None
+        owner[ptr] = stream or 0
+        return ptr
 
     def free(ptr, nbytes, stream, user):
-        if ptr:
-            torch.cuda.caching_allocator_delete(ptr)
+        if not ptr:
+            return
+        home = owner.pop(ptr, None)
+        if home is not None and (stream or 0) != home:
+            ev = torch.cuda.Event()
+            ev.record(torch.cuda.ExternalStream(stream or 0, device=device) if stream else
+                      torch.cuda.default_stream(device))
+            (torch.cuda.ExternalStream(home, device=device) if home else torch.cuda.default_stream(device)).wait_event(ev)
+        torch.cuda.caching_allocator_delete(ptr)
 
     return GqAllocator(_ALLOC_FN(alloc), _FREE_FN(free), None)
 

@@ -195,9 +195,6 @@ class DeviceExecutor:
         self.share = share
         self.max_share = 8
         self.streams = [torch.cuda.Stream() for _ in range(nslots)]
-        # Join builds run on a second stream per slot: the library makes the
-        # pipeline wait for the build only where it reads the table.
-        self.bstreams = [torch.cuda.Stream() for _ in range(nslots)]
         self.ctxs = [gq.Context(allocator="torch") for _ in range(nslots)]
         self.nf, self.nd = fact.nrows, dim.nrows
 
@@ -250,10 +247,8 @@ class DeviceExecutor:
                                            AGG_AGGS, capacity=16, strategy="lds", expected_groups=6, stream=s)
                 job.update(out=out, cnt=cnt, stage=9)
             elif q.kind == "join":
-                bs = self.bstreams[slot]
-                bs.wait_stream(s)
                 jt = ctx.join_build(self.dim, [D_PKEY], [("range", D_DATE, 0, q.params["b_dim"])], acc_slots=2,
-                                    stream=bs)
+                                    stream=s)
                 out, cnt = ctx.pipeline(self.fact, [("range", F_DATE, q.params["b_fact"], 2555)], [F_FKEY],
                                         JOIN_AGGS, join=jt, probe_key=F_FKEY, capacity=self.nd, stream=s)
                 jt.free(stream=s)

@@ -205,12 +205,14 @@ def test_radix_region_count_out_of_range(gq, ctx, rlog):
         ctx.join_build(gq.to_device(dim), [0], [], regions_log2=rlog)
 
 
-@pytest.mark.parametrize("radix", [True, False])
-def test_build_on_another_stream(gq, ctx, radix):
+@pytest.mark.parametrize("radix,alloc", [(True, None), (False, None), (True, "torch")])
+def test_build_on_another_stream(gq, ctx, radix, alloc):
     # The build is enqueued on a second stream behind a long kernel; the
     # pipeline on the current stream must wait for it where it reads the table
     # (radix path: after partitioning its probe side; index path: before it).
     import torch
+    if alloc:
+        ctx = gq.Context(allocator=alloc)   # the table is freed on another stream than its allocation
     n_dim = MIN_BUILD + 3 if radix else 200_000
     dim = dg.dim_c2(n_dim, seed=44)
     fact = dg.fact_c2(900_001, nkeys=n_dim, seed=44)
