@@ -340,7 +340,7 @@ def run_batched(torch, gq, devgen, ctx, steps=5, nfrag=4096, tune=True):
 # Serving: Poisson arrivals against device-resident 600M x 150M tables
 # ---------------------------------------------------------------------------
 
-def run_serving(torch, gq, devgen, nq=300, qps_list=(60, 70, 75, 80), budget_gb=96, slots=2, p99_bound_ms=250.0):
+def run_serving(torch, gq, devgen, nq=500, qps_list=(60, 70, 75, 80), budget_gb=96, slots=2, p99_bound_ms=250.0):
     from paper_2606_24647_amd import datagen as dg
     from paper_2606_24647_amd import serve
     log("generating resident fact 600M x 7 and dim 150M x 3 on the device")
