@@ -435,6 +435,10 @@ int run_groupby(gq_ctx* ctx, const gq_batch* in, const int32_t* keys, int nkeys,
   if (join) {
     rc = join_ensure_index(ctx, join, stream);
     if (rc) return rc;
+    // A partitioned table's index arrays exist from here on.
+    a.join.keys = join->keys;
+    a.join.meta = join->meta;
+    a.join.acc = join->acc;
   }
   // Group-join: the only key is the probe key and the table has room.
   const bool groupjoin = gj_shape && join->acc_slots >= a.ap.nacc;

@@ -593,6 +593,32 @@ int build_index(gq_ctx* ctx, JoinBuildArgs& a, gq_join_table* t, bool count, hip
 
 }  // namespace
 
+// Probe index arrays of a table: keys and meta (cap_alloc + 1 slots), the
+// accumulators of a fused group-join, build rows, fill cursors and the merge
+// buffer, in one block.
+struct IndexLayout {
+  size_t meta, acc, rows, aux, tmp, bytes;
+};
+IndexLayout index_layout(uint64_t cap_alloc, int64_t n, int acc) {
+  const size_t nslot = (size_t)cap_alloc + 1;
+  IndexLayout l;
+  l.meta = align_up(nslot * 8, 256);
+  l.acc = align_up(l.meta + nslot * 8, 256);
+  l.rows = align_up(l.acc + nslot * 8 * (size_t)acc, 256);
+  l.aux = align_up(l.rows + (size_t)n * 4, 256);
+  l.tmp = align_up(l.aux + nslot * 4, 256);
+  l.bytes = align_up(l.tmp + (size_t)n * 4, 256);
+  return l;
+}
+void set_index(gq_join_table* t, char* base, const IndexLayout& l, int acc) {
+  t->keys = reinterpret_cast<uint64_t*>(base);
+  t->meta = reinterpret_cast<uint64_t*>(base + l.meta);
+  t->acc = acc ? reinterpret_cast<uint64_t*>(base + l.acc) : nullptr;
+  t->rows = reinterpret_cast<int32_t*>(base + l.rows);
+  t->aux = reinterpret_cast<uint32_t*>(base + l.aux);
+  t->tmp = reinterpret_cast<int32_t*>(base + l.tmp);
+}
+
 int join_wait_ready(gq_ctx* ctx, const gq_join_table* t, hipStream_t stream) {
   if (t && t->ready) GQ_HIP_CHECK(ctx, hipStreamWaitEvent(stream, t->ready, 0));
   return GQ_OK;
@@ -603,6 +629,13 @@ int join_ensure_index(gq_ctx* ctx, const gq_join_table* table, hipStream_t strea
   int rc = join_wait_ready(ctx, t, stream);
   if (rc) return rc;
   if (t->index_built) return GQ_OK;
+  if (!t->keys) {
+    const IndexLayout il = index_layout(t->cap_alloc, t->build_rows, t->acc_slots);
+    t->imem = ctx_alloc(ctx, il.bytes, stream);
+    if (!t->imem) return set_error(ctx, GQ_ERR_NOMEM, "join: probe index allocation failed");
+    t->ibytes = il.bytes;
+    set_index(t, static_cast<char*>(t->imem), il, t->acc_slots);
+  }
   JoinBuildArgs a;
   std::memset(&a, 0, sizeof(a));
   a.n = t->build_rows;
@@ -653,14 +686,10 @@ int gq_join_build(gq_ctx* ctx, const gq_batch* build, const int32_t* keys, int n
   const int pbits = rlog ? rlog : rj_choose_pbits(n);
   const bool radix = n >= kRjMinBuild && n < ((int64_t)1 << 31) && rj_build_fits(build, keys[0], preds, npreds, pbits);
 
-  const size_t nslot = (size_t)cap_alloc + 1;
+  // Partitioned tables allocate their probe index (keys ... tmp) on first use.
   const size_t off_keys = 256;
-  const size_t off_meta = align_up(off_keys + nslot * 8, 256);
-  const size_t off_acc = align_up(off_meta + nslot * 8, 256);
-  const size_t off_rows = align_up(off_acc + nslot * 8 * (size_t)acc, 256);
-  const size_t off_aux = align_up(off_rows + (size_t)n * 4, 256);
-  const size_t off_tmp = align_up(off_aux + nslot * 4, 256);
-  const size_t off_rjkey = align_up(off_tmp + (size_t)n * 4, 256);
+  IndexLayout il = index_layout(cap_alloc, n, acc);
+  const size_t off_rjkey = radix ? off_keys : align_up(off_keys + il.bytes, 256);
   const size_t off_rjrow = align_up(off_rjkey + (radix ? (size_t)n * 8 : 0), 256);
   const size_t off_rjoff = align_up(off_rjrow + (radix ? (size_t)n * 4 : 0), 256);
   const size_t total = align_up(off_rjoff + (radix ? ((size_t)1 << pbits) * 8 + 8 : 0), 256);
@@ -677,12 +706,7 @@ int gq_join_build(gq_ctx* ctx, const gq_batch* build, const int32_t* keys, int n
   t->bytes = total;
   char* base = static_cast<char*>(t->mem);
   t->hdr = reinterpret_cast<JoinHdr*>(base);
-  t->keys = reinterpret_cast<uint64_t*>(base + off_keys);
-  t->meta = reinterpret_cast<uint64_t*>(base + off_meta);
-  t->acc = acc ? reinterpret_cast<uint64_t*>(base + off_acc) : nullptr;
-  t->rows = reinterpret_cast<int32_t*>(base + off_rows);
-  t->aux = reinterpret_cast<uint32_t*>(base + off_aux);
-  t->tmp = reinterpret_cast<int32_t*>(base + off_tmp);
+  if (!radix) set_index(t, base + off_keys, il, acc);
   t->cap_alloc = cap_alloc;
   t->acc_slots = acc;
   t->build_rows = n;
@@ -784,6 +808,7 @@ int gq_join_table_free(gq_ctx* ctx, gq_join_table* table, hipStream_t stream) {
     (void)hipStreamWaitEvent(stream, table->ready, 0);
     (void)hipEventDestroy(table->ready);
   }
+  if (table->imem) ctx_free(ctx, table->imem, table->ibytes, stream);
   ctx_free(ctx, table->mem, table->bytes, stream);
   delete table;
   return GQ_OK;

@@ -221,6 +221,8 @@ struct gq_join_table {
   gq_ctx* ctx = nullptr;
   void* mem = nullptr;        // one allocation from the context allocator
   size_t bytes = 0;
+  void* imem = nullptr;       // partitioned tables: the probe index, allocated on first use
+  size_t ibytes = 0;
   gq::JoinHdr* hdr = nullptr;
   uint64_t* keys = nullptr;   // cap_alloc + 1 words; slot cap_alloc holds the key EMPTY
   uint64_t* meta = nullptr;   // cap_alloc + 1 words
