@@ -355,7 +355,7 @@ def run_serving(torch, gq, devgen, nq=500, qps_list=(60, 70, 75, 80), budget_gb=
     # Warm up both executors with a short open-loop run of every query kind
     # (allocator caches and code objects reach their steady state before the
     # first measured run).
-    warm = serve.make_workload(60, 30, seed=99)
+    warm = serve.make_workload(120, 60, seed=99)  # busy enough to use every slot
     serve.Scheduler(plain_ex, budget).run(warm)
     serve.Scheduler(served_ex, budget).run(warm)
     torch.cuda.synchronize()
