@@ -61,3 +61,14 @@ def test_partition_bad_nparts(gq, ctx):
     for P in (0, 1025):
         with pytest.raises(gq.GqError):
             ctx.hash_partition(t, [0], P)
+
+
+@pytest.mark.parametrize("ncols", [4, 5, 12])
+def test_partition_wide_rows(gq, ctx, ncols):
+    # Rows of ncols int64 columns: 4 still fit the 4096-row staging of the
+    # 1024-thread scatter, 5 and 12 take the 1024-row variant.
+    rng = np.random.default_rng(ncols)
+    n = 70_001
+    cols = {f"c{j}": rng.integers(-10**12, 10**12, n) for j in range(ncols)}
+    cols["c1"] = (cols["c1"], rng.random(n) > 0.2)
+    check_partition(gq, ctx, tbl(**cols), [0, 1], 64, seed=3)
