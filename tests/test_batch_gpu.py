@@ -214,3 +214,22 @@ def test_batch_radix_underestimated_groups(gq, ctx):
     plan = gq.BatchPlan(ctx, [(d, [], expected, n)], [4], AGGS, radix_min_groups=1)
     _check_plan(gq, plan, [t], [4], [[]], AGGS, reps=2)
     plan.free()
+
+
+def test_batch_radix_too_many_columns_falls_back(gq, ctx):
+    # Ten distinct columns to stage (key, predicate, eight SUM inputs) exceed
+    # the radix path's staging: every fragment takes the tile path.
+    rng = np.random.default_rng(24)
+    frags, preds = [], []
+    for n in [40_000, 5_000]:
+        cols = {"k": rng.integers(0, 20_000, n), "p": rng.integers(0, 10, n).astype(np.int8)}
+        for j in range(8):
+            cols[f"v{j}"] = rng.integers(-1000, 1000, n)
+        frags.append(tbl(**cols))
+        preds.append([("range", 1, 0, 6)])
+    aggs = [("sum", [("col", 2 + j)]) for j in range(7)] + [("count*",)]
+    dev = [gq.to_device(t) for t in frags]
+    plan = gq.BatchPlan(ctx, [(d, p, t.nrows) for d, p, t in zip(dev, preds, frags)], [0], aggs,
+                        radix_min_groups=1)
+    _check_plan(gq, plan, frags, [0], preds, aggs, reps=2)
+    plan.free()
