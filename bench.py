@@ -340,7 +340,8 @@ def run_batched(torch, gq, devgen, ctx, steps=5, nfrag=4096, tune=True):
 # Serving: Poisson arrivals against device-resident 600M x 150M tables
 # ---------------------------------------------------------------------------
 
-def run_serving(torch, gq, devgen, nq=500, qps_list=(60, 70, 75, 80), budget_gb=96, slots=2, p99_bound_ms=250.0):
+def run_serving(torch, gq, devgen, nq=500, qps_list=(60, 70, 75, 80), budget_gb=96, slots=3, p99_bound_ms=250.0,
+                max_heavy=1):
     from paper_2606_24647_amd import datagen as dg
     from paper_2606_24647_amd import serve
     log("generating resident fact 600M x 7 and dim 150M x 3 on the device")
@@ -349,9 +350,9 @@ def run_serving(torch, gq, devgen, nq=500, qps_list=(60, 70, 75, 80), budget_gb=
     torch.cuda.synchronize()
     budget = int(budget_gb) << 30
     res = {"resident_gb": round((dg.C5_FACT_ROWS * 38 + dg.C5_DIM_ROWS * 20) / 1e9, 2), "queries_per_run": nq,
-           "slots": slots, "budget_gb": budget_gb, "runs": []}
+           "slots": slots, "max_heavy": max_heavy, "budget_gb": budget_gb, "runs": []}
     plain_ex = serve.DeviceExecutor(gq, torch, fact, dim, nslots=1, share=False)
-    served_ex = serve.DeviceExecutor(gq, torch, fact, dim, nslots=slots)
+    served_ex = serve.DeviceExecutor(gq, torch, fact, dim, nslots=slots, max_heavy=max_heavy)
     # Warm up both executors with a short open-loop run of every query kind
     # (allocator caches and code objects reach their steady state before the
     # first measured run).
@@ -409,6 +410,9 @@ def main():
     ap.add_argument("--no-operators", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-slots", type=int, default=3, help="streams of the served executor")
+    ap.add_argument("--serving-max-heavy", type=int, default=1,
+                    help="at most this many joins/partitions at once in the served executor")
     ap.add_argument("--only", choices=["c2", "operators", "batched", "serving", "copy"],
                     help="run one section only (profiling runs); 'copy' is a 1 GiB device copy used to "
                          "calibrate hardware byte counters")
@@ -481,7 +485,8 @@ def main():
         batched = section("batched", lambda: run_batched(torch, gq, devgen, ctx))
     serving = None
     if not args.no_serving:
-        serving = section("serving", lambda: run_serving(torch, gq, devgen))
+        serving = section("serving", lambda: run_serving(torch, gq, devgen, slots=args.serving_slots,
+                                                               max_heavy=args.serving_max_heavy))
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on a 1/10 sample")

@@ -119,9 +119,20 @@ class Scheduler:
                 i += 1
             # Admit in FIFO order while a slot and the budget allow.  A query that
             # can share its scan takes queued queries of the same kind along
-            # (shared scan), up to the executor's limit.
+            # (shared scan), up to the executor's limit.  With an executor that
+            # marks queries heavy (each one alone fills the device), at most
+            # max_heavy of them run at once: while that many do, the first light
+            # query in the queue is admitted instead (heavy ones stay FIFO).
+            max_heavy = getattr(self.ex, "max_heavy", None)
             while queue and free:
                 q = queue[0]
+                if max_heavy is not None and self.ex.heavy(q):
+                    nheavy = sum(1 for grp, _, _, _ in running.values() if self.ex.heavy(grp[0]))
+                    if nheavy >= max_heavy:
+                        light = next((x for x in queue if not self.ex.heavy(x)), None)
+                        if light is None:
+                            break
+                        q = light
                 fp = self.ex.footprint(q)
                 if fp > self.budget:
                     raise ValueError(f"query {q.qid} needs {fp} bytes, more than the whole budget")
@@ -130,7 +141,9 @@ class Scheduler:
                 group = [q]
                 key = self.ex.share_key(q) if hasattr(self.ex, "share_key") else None
                 if key is not None:
-                    for other in queue[1:]:
+                    for other in queue:
+                        if other is q:
+                            continue
                         if len(group) >= self.ex.max_share:
                             break
                         if self.ex.share_key(other) == key and used + fp + self.ex.footprint(other) <= self.budget:
@@ -188,12 +201,14 @@ def summarize(records: list, wall: float | None = None) -> dict:
 class DeviceExecutor:
     """Runs queries on a pool of streams, one library context per stream."""
 
-    def __init__(self, gq, torch, fact, dim, nslots: int = 4, share: bool = True):
+    def __init__(self, gq, torch, fact, dim, nslots: int = 4, share: bool = True, max_heavy: int | None = None):
         self.gq, self.torch = gq, torch
         self.fact, self.dim = fact, dim
         self.nslots = nslots
         self.share = share
         self.max_share = 8
+        if max_heavy is not None:
+            self.max_heavy = max_heavy
         self.streams = [torch.cuda.Stream() for _ in range(nslots)]
         self.ctxs = [gq.Context(allocator="torch") for _ in range(nslots)]
         self.nf, self.nd = fact.nrows, dim.nrows
@@ -209,6 +224,11 @@ class DeviceExecutor:
             return cap * (8 + 8 + 16 + 4) + self.nd * 8 + self.nd * 24 + (64 << 20)
         # filter output and partition output at 21 B per row, plus workspace
         return 2 * self.nf * 21 + (self.nf // 4096 + 1) * 256 * 12 + (256 << 20)
+
+    @staticmethod
+    def heavy(q: Query) -> bool:
+        """Joins and partitions each fill the device; aggregations are short."""
+        return q.kind != "agg"
 
     def rows(self, q: Query) -> int:
         return self.nf + (self.nd if q.kind == "join" else 0)

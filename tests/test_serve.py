@@ -142,3 +142,57 @@ def test_shared_scans_group_waiting_aggregations():
     for g in groups:                                   # only aggregation queries share
         assert all(i % 3 for i in g)
     assert ex.in_use == 0
+
+
+class CappedExecutor(FakeExecutor):
+    """Joins and partitions are heavy; at most max_heavy of them run at once."""
+
+    def __init__(self, clock, nslots, max_heavy):
+        super().__init__(clock, nslots)
+        self.max_heavy = max_heavy
+        self.heavy_now = 0
+        self.max_heavy_seen = 0
+        self.heavy_starts = []
+
+    @staticmethod
+    def heavy(q):
+        return q.kind != "agg"
+
+    def start(self, q, slot):
+        job = super().start(q, slot)
+        if self.heavy(q):
+            self.heavy_now += 1
+            self.max_heavy_seen = max(self.max_heavy_seen, self.heavy_now)
+            self.heavy_starts.append(q.qid)
+        return job
+
+    def step(self, job):
+        was = job["done"]
+        done = super().step(job)
+        if done and not was and self.heavy(job["q"]):
+            self.heavy_now -= 1
+        return done
+
+
+@pytest.mark.parametrize("max_heavy", [1, 2])
+def test_heavy_cap_light_queries_overtake(max_heavy):
+    clock = VirtualClock()
+    ex = CappedExecutor(clock, 4, max_heavy)
+    qs = make_workload(300, 150, seed=3)
+    recs = Scheduler(ex, 1000, clock=clock, idle_sleep=0).run(qs, keep_results=True)
+    assert sorted(r.qid for r in recs) == [q.qid for q in qs]
+    assert all(r.result == r.qid for r in recs)
+    assert ex.max_heavy_seen == max_heavy                # the cap binds and holds
+    assert ex.heavy_starts == sorted(ex.heavy_starts)    # heavy queries stay in arrival order
+    assert ex.starts != sorted(ex.starts)                # some light query went ahead
+    assert ex.max_active <= 4
+
+
+def test_heavy_cap_lowers_light_latency():
+    def light_p99(ex):
+        qs = make_workload(300, 150, seed=3)
+        recs = Scheduler(ex, 1000, clock=ex.clock, idle_sleep=0).run(qs)
+        return summarize([r for r in recs if r.kind == "agg"])["p99_ms"]
+    free = light_p99(FakeExecutor(VirtualClock(), 2))
+    capped = light_p99(CappedExecutor(VirtualClock(), 2, 1))
+    assert capped < free

@@ -22,10 +22,11 @@ def env():
     return gq, torch, fact, dim
 
 
-def test_alone_equals_mix(env):
+@pytest.mark.parametrize("max_heavy", [None, 1])
+def test_alone_equals_mix(env, max_heavy):
     gq, torch, fact, dim = env
     qs = serve.make_workload(36, qps=2000.0, seed=3)
-    mixed_ex = serve.DeviceExecutor(gq, torch, fact, dim, nslots=4)
+    mixed_ex = serve.DeviceExecutor(gq, torch, fact, dim, nslots=4, max_heavy=max_heavy)
     mixed = serve.Scheduler(mixed_ex, budget_bytes=1 << 40).run(qs, keep_results=True)
     assert len(mixed) == len(qs)
     alone_ex = serve.DeviceExecutor(gq, torch, fact, dim, nslots=1)
