@@ -257,38 +257,11 @@ def run_operators(torch, gq, devgen, ctx, c2, reps=5):
 # Batched fragments: 4096 filter + group-by fragments in one graph launch
 # ---------------------------------------------------------------------------
 
-def c4_device_fragments(torch, devgen, dg, nfrag, align=16):
-    """All fragments in five device columns, each fragment starting on a 16-row
-    boundary; returns (spec, list of DevTable views)."""
-    from paper_2606_24647_amd.gq import DevColumn, DevTable
-    spec = dg.fragments_c4(nfrag)
-    starts = np.zeros(nfrag + 1, dtype=np.int64)
-    for f in range(nfrag):
-        starts[f + 1] = starts[f] + (int(spec.rows[f]) + align - 1) // align * align
-    total = int(starts[-1])
-    cols = [torch.empty(total, dtype=dt, device="cuda") for dt in
-            (torch.int64, torch.int64, torch.int64, torch.int32, torch.int32)]
-    ranges = [(1, 50), (dg.PRICE_LO, dg.PRICE_HI), (0, 10), (0, dg.DATE_DAYS - 1), None]
-    tables = []
-    for f in range(nfrag):
-        n, card = int(spec.rows[f]), int(spec.card[f])
-        s0 = int(starts[f])
-        seed = dg.fragment_seed(f)
-        views = []
-        for c, (col, rg) in enumerate(zip(cols, ranges)):
-            lo, hi = rg if rg is not None else (0, card - 1)
-            v = col[s0:s0 + n]
-            devgen.uniform(seed, c, 0, n, lo, hi, out=v)
-            views.append(DevColumn(v))
-        tables.append(DevTable(views))
-    return spec, tables, cols
-
-
 def run_batched(torch, gq, devgen, ctx, steps=5, nfrag=4096, tune=True):
     from paper_2606_24647_amd import datagen as dg
     from paper_2606_24647_amd import autotune
     log(f"generating {nfrag} fragments on the device")
-    spec, tables, cols = c4_device_fragments(torch, devgen, dg, nfrag)
+    spec, tables, cols, _ = devgen.fragments_c4_resident(nfrag)
     torch.cuda.synchronize()
     preds = [[("range", 3, 0, int(b))] for b in spec.bound]
     frags = [(t, p, int(c)) for t, p, c in zip(tables, preds, spec.card)]

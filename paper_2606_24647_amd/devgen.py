@@ -124,3 +124,32 @@ def fragment_c4(f, rows, card, seed=4) -> DevTable:
         (uniform(s, 3, 0, rows, 0, dg.DATE_DAYS - 1, torch.int32), 0),
         (uniform(s, 4, 0, rows, 0, card - 1, torch.int32), 0),
     ])
+
+
+def fragments_c4_resident(nfrag=4096, seed=4, align=16):
+    """Every fragment of the batched workload resident at once: five device
+    columns holding all fragments back to back, fragment f starting on an
+    `align`-row boundary (so its 128-bit loads stay aligned).  Fragment f's
+    rows equal fragment_c4(f, ...).  Returns (spec, tables, cols, starts):
+    the host spec (rows, cardinality, filter bound per fragment), one DevTable
+    view per fragment, the five backing tensors and the fragment starts."""
+    import numpy as np
+    spec = dg.fragments_c4(nfrag, seed)
+    starts = np.zeros(nfrag + 1, dtype=np.int64)
+    for f in range(nfrag):
+        starts[f + 1] = starts[f] + (int(spec.rows[f]) + align - 1) // align * align
+    total = int(starts[-1])
+    layout = [(torch.int64, 1, 50, 0), (torch.int64, dg.PRICE_LO, dg.PRICE_HI, 2), (torch.int64, 0, 10, 2),
+              (torch.int32, 0, dg.DATE_DAYS - 1, 0), (torch.int32, 0, None, 0)]
+    cols = [torch.empty(max(1, total), dtype=dt, device="cuda") for dt, _, _, _ in layout]
+    tables = []
+    for f in range(nfrag):
+        n, card, s0 = int(spec.rows[f]), int(spec.card[f]), int(starts[f])
+        s = dg.fragment_seed(f, seed)
+        views = []
+        for c, (col, (_, lo, hi, sc)) in enumerate(zip(cols, layout)):
+            v = col[s0:s0 + n]
+            uniform(s, c, 0, n, lo, card - 1 if hi is None else hi, out=v)
+            views.append(DevColumn(v, None, scale=sc))
+        tables.append(DevTable(views))
+    return spec, tables, cols, starts

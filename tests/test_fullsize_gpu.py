@@ -108,3 +108,54 @@ def test_partition_60m(mods, c3_keys, P):
            dg.uniform_at(3, 3, rows, 0, 2, np.int8)]
     for g, e in zip(osamp, exp):
         assert np.array_equal(g, e)
+
+
+C1_AGGS = [("sum", [("col", 0)]), ("sum", [("col", 1)]), ("sum", [("col", 2)]), ("sum", REV), ("count*",)]
+
+
+def test_batched_4096_fragments(mods):
+    """The whole batched workload (4,096 fragments, about 2e9 rows resident) in
+    one plan with the default configuration, as the bench launches it: every
+    fragment's COUNT(*) total and group count against properties computed on
+    the device, and sampled fragments (the largest, the one with the most
+    groups, LDS- and radix-routed ones) against the oracle exactly."""
+    gq, devgen = mods
+    import torch
+    from tests.helpers import canon_groups
+    ctx = gq.Context()
+    spec, tables, cols, starts = devgen.fragments_c4_resident(4096)
+    preds = [[("range", 3, 0, int(b))] for b in spec.bound]
+    plan = gq.BatchPlan(ctx, [(t, p, int(c)) for t, p, c in zip(tables, preds, spec.card)], [4], C1_AGGS)
+    plan.launch()
+    plan.launch()          # a replay reproduces the first launch's results
+    ctx.raise_status()
+    ng = plan.d_groups.cpu().numpy()
+    assert (ng >= 0).all() and (ng <= np.minimum(spec.rows, spec.card)).all()
+    # COUNT(*) summed per fragment equals the rows that pass its filter.
+    got_cnt, exp_cnt, nonempty = [], [], []
+    for f, t in enumerate(tables):
+        n = int(spec.rows[f])
+        exp_cnt.append((cols[3][int(starts[f]):int(starts[f]) + n] <= int(spec.bound[f])).sum())
+        got_cnt.append(plan.outs[f].cols[-1].data[:int(ng[f])].sum())
+    got_cnt = torch.stack(got_cnt).cpu().numpy()
+    exp_cnt = torch.stack(exp_cnt).cpu().numpy()
+    assert np.array_equal(got_cnt, exp_cnt)
+    assert ((ng > 0) == (exp_cnt > 0)).all()
+
+    rng = np.random.default_rng(11)
+    lds = np.flatnonzero(spec.card <= 256)
+    rad = np.flatnonzero(spec.card > 256)
+    pick = {int(np.argmax(spec.rows)), int(np.argmax(spec.card)), int(np.argmin(spec.rows))}
+    pick |= set(rng.choice(lds, 4, replace=False).tolist()) | set(rng.choice(rad, 6, replace=False).tolist())
+    for f in sorted(pick):
+        host = dg.fragment_c4(f, int(spec.rows[f]), int(spec.card[f]))
+        exp = oracle.groupby(host, [4], preds[f], C1_AGGS)
+        ek, ea = canon_groups(exp.keys, exp.aggs)
+        res, n = plan.result(f)
+        assert n == exp.nrows, f
+        gk, ga = canon_groups([(v.astype(np.int64), ok) for v, ok in res[:1]], res[1:])
+        for (gv, gok), (ev, eok) in zip(gk + ga, ek + ea):
+            assert np.array_equal(gv, ev) and np.array_equal(gok, eok), f
+    plan.free()
+    del tables, cols
+    torch.cuda.empty_cache()
