@@ -13,10 +13,12 @@
 //     k_jdup_fill    place every build row in its key's run (atomic cursor)
 //     k_jdup_sort    sort each run by row: short runs in one thread, long runs
 //                    by a block-wide merge sort, so runs hold ascending rows
+//  5. k_jpack        copy keys and meta side by side (the probe's layout)
 // Probe: per probe row, the match count from the table, a decoupled look-back
 // scan of the counts, then (probe row, build row) pairs in canonical order.
 // Each thread issues the first probe of all its rows before resolving any of
-// them, so the random reads of a thread overlap.
+// them, so the random reads of a thread overlap; a probe step is one 16-byte
+// load of a (key, meta) pair.
 #include "table.h"
 #include "radix.h"
 
@@ -190,6 +192,18 @@ __global__ __launch_bounds__(BLOCK) void k_jinsert(const JoinBuildArgs a) {
         a.hdr->has_dups = 1;
     }
   });
+}
+
+// kv[2s], kv[2s+1] = keys[s], meta[s] for the hashed slots [0, cap) and the
+// extra slot (index cap_alloc), once meta holds its final count and row.
+__global__ void k_jpack(const JoinBuildArgs a, uint64_t* kv) {
+  typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+  const uint64_t cap = a.hdr->cap;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= (int64_t)a.cap_alloc; i += stride) {
+    if ((uint64_t)i >= cap && (uint64_t)i != a.cap_alloc) continue;
+    *reinterpret_cast<u64x2*>(kv + 2 * i) = u64x2{a.keys[i], a.meta[i]};
+  }
 }
 
 // Exclusive scan of slot counts over [0, cap) and the extra slot (entry cap).
@@ -367,8 +381,7 @@ struct ProbeArgs {
   DPred preds[GQ_MAX_PREDS];
   DCol pcols[GQ_MAX_PREDS];
   const JoinHdr* hdr;
-  const uint64_t* keys;
-  const uint64_t* meta;
+  const uint64_t* kv;       // (key, meta) pairs
   const int32_t* rows;
   uint64_t cap_alloc;
   int32_t* probe_idx;
@@ -417,13 +430,17 @@ __global__ __launch_bounds__(BLOCK) void k_jprobe(const ProbeArgs a) {
   load_items<ITEMS, true>(a.key, r0, a.n, key);
   if (a.key.valid) keep &= valid_items<ITEMS>(a.key, r0, a.n);
 
+  typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
   const uint64_t cap = a.hdr->cap;
   const bool dups = a.hdr->has_dups != 0;
-  uint64_t start[ITEMS], first[ITEMS];
+  const u64x2* kv = reinterpret_cast<const u64x2*>(a.kv);
+  // First probe of every row (the key EMPTY lives in the extra slot).
+  uint64_t pos0[ITEMS];
+  u64x2 e[ITEMS];
   static_for<0, ITEMS>([&](auto kk) __attribute__((always_inline)) {
     constexpr int k = decltype(kk)::value;
-    start[k] = slot_of((uint64_t)key[k], cap);
-    first[k] = ((keep >> k) & 1u) ? a.keys[start[k]] : kEmpty;
+    pos0[k] = (uint64_t)key[k] == kEmpty ? a.cap_alloc : slot_of((uint64_t)key[k], cap);
+    e[k] = ((keep >> k) & 1u) ? kv[pos0[k]] : u64x2{kEmpty, 0};
   });
   uint32_t cnt[ITEMS], srow[ITEMS];
   int64_t tsum = 0;
@@ -432,13 +449,27 @@ __global__ __launch_bounds__(BLOCK) void k_jprobe(const ProbeArgs a) {
     cnt[k] = 0;
     srow[k] = 0;
     if ((keep >> k) & 1u) {
-      const uint64_t kv = (uint64_t)key[k];
-      const int64_t s = kv == kEmpty ? (int64_t)a.cap_alloc : find_from(a.keys, cap, kv, start[k], opaque_copy(first[k]));
-      if (s >= 0) {
-        const uint64_t m = a.meta[s];
-        cnt[k] = meta_count(m);
-        srow[k] = meta_row(m);
+      const uint64_t kx = (uint64_t)key[k];
+      uint64_t meta = 0;
+      if (kx == kEmpty) {
+        meta = opaque_copy(e[k].y);
+      } else {
+        // Linear probing from the home slot: a hit gives the meta word with
+        // the key; an empty slot ends the search.
+        uint64_t s = pos0[k];
+        u64x2 x = u64x2{opaque_copy(e[k].x), opaque_copy(e[k].y)};
+        for (uint64_t n = 0; n < cap; ++n) {
+          if (x.x == kx) {
+            meta = x.y;
+            break;
+          }
+          if (x.x == kEmpty) break;
+          if (++s == cap) s = 0;
+          x = kv[s];
+        }
       }
+      cnt[k] = meta_count(meta);
+      srow[k] = meta_row(meta);
     }
     tsum += cnt[k];
   });
@@ -587,6 +618,8 @@ int build_index(gq_ctx* ctx, JoinBuildArgs& a, gq_join_table* t, bool count, hip
     GQ_LAUNCH(ctx, "jdup_sort_long", (k_jdup_sort_long<1024>), dim3(64), dim3(1024), 0, stream, a);
     GQ_LAUNCH_CHECK(ctx);
   }
+  GQ_LAUNCH(ctx, "jpack", k_jpack, dim3((unsigned)iblocks), dim3(256), 0, stream, a, t->kv);
+  GQ_LAUNCH_CHECK(ctx);
   t->index_built = true;
   return GQ_OK;
 }
@@ -597,13 +630,14 @@ int build_index(gq_ctx* ctx, JoinBuildArgs& a, gq_join_table* t, bool count, hip
 // accumulators of a fused group-join, build rows, fill cursors and the merge
 // buffer, in one block.
 struct IndexLayout {
-  size_t meta, acc, rows, aux, tmp, bytes;
+  size_t meta, kv, acc, rows, aux, tmp, bytes;
 };
 IndexLayout index_layout(uint64_t cap_alloc, int64_t n, int acc) {
   const size_t nslot = (size_t)cap_alloc + 1;
   IndexLayout l;
   l.meta = align_up(nslot * 8, 256);
-  l.acc = align_up(l.meta + nslot * 8, 256);
+  l.kv = align_up(l.meta + nslot * 8, 256);
+  l.acc = align_up(l.kv + nslot * 16, 256);
   l.rows = align_up(l.acc + nslot * 8 * (size_t)acc, 256);
   l.aux = align_up(l.rows + (size_t)n * 4, 256);
   l.tmp = align_up(l.aux + nslot * 4, 256);
@@ -613,6 +647,7 @@ IndexLayout index_layout(uint64_t cap_alloc, int64_t n, int acc) {
 void set_index(gq_join_table* t, char* base, const IndexLayout& l, int acc) {
   t->keys = reinterpret_cast<uint64_t*>(base);
   t->meta = reinterpret_cast<uint64_t*>(base + l.meta);
+  t->kv = reinterpret_cast<uint64_t*>(base + l.kv);
   t->acc = acc ? reinterpret_cast<uint64_t*>(base + l.acc) : nullptr;
   t->rows = reinterpret_cast<int32_t*>(base + l.rows);
   t->aux = reinterpret_cast<uint32_t*>(base + l.aux);
@@ -767,8 +802,7 @@ int gq_join_probe(gq_ctx* ctx, const gq_join_table* table, const gq_batch* probe
   rc = join_ensure_index(ctx, table, stream);
   if (rc) return rc;
   a.hdr = table->hdr;
-  a.keys = table->keys;
-  a.meta = table->meta;
+  a.kv = table->kv;
   a.rows = table->rows;
   a.cap_alloc = table->cap_alloc;
   a.probe_idx = probe_idx;

@@ -12,6 +12,10 @@
 //            run of rows once duplicates were found.
 //   acc[s*aw .. s*aw+aw)  accumulator words, touched only when a row lands in
 //            the slot (group-by), i.e. once per aggregated row.
+//   kv[2s], kv[2s+1]  (join tables) keys[s] and meta[s] side by side, copied
+//            once the index is complete: the pair probe reads a slot's key
+//            and its match count and row with one 16-byte load, where the two
+//            arrays cost two random cache lines per match.
 // Slot index = floor(fmix64(key ^ kTableSeed) * cap / 2^64): a different seed
 // from the partitioning hash, so a table built over one partition still spreads
 // over all of its slots.  Slots past the hashed range (index cap_alloc and
@@ -226,6 +230,7 @@ struct gq_join_table {
   gq::JoinHdr* hdr = nullptr;
   uint64_t* keys = nullptr;   // cap_alloc + 1 words; slot cap_alloc holds the key EMPTY
   uint64_t* meta = nullptr;   // cap_alloc + 1 words
+  uint64_t* kv = nullptr;     // cap_alloc + 1 pairs (keys[s], meta[s]), written once the index is complete
   uint64_t* acc = nullptr;    // (cap_alloc + 1) * acc_slots words, or NULL
   int32_t* rows = nullptr;    // build rows grouped by key once duplicates were found
   uint32_t* aux = nullptr;    // cap_alloc + 1 words: fill cursors, then the long-run list
