@@ -13,7 +13,7 @@ seeded).  The printed JSON line carries:
 * value: input rows (fact + dimension) per second over the timed steps;
 * roofline: the dominant kernel's algorithmic bytes per launch over its average
   launch time (HIP events on its own stream), against 8 TB/s;
-* cpu_baseline: the CPU oracle on a 1/10-scale sample of the same workload;
+* cpu_baseline: the CPU oracle on a 1/4-scale sample of the same workload;
 * operators: the other operators measured separately (filter + group-by on
   the 1M-row table, hash partition of 60M rows into 64 and 256 partitions, the
   standalone filter, the materialising probe).
@@ -358,7 +358,7 @@ def run_serving(torch, gq, devgen, nq=500, qps_list=(60, 70, 75, 80), budget_gb=
 # CPU baseline: the oracle on a sample
 # ---------------------------------------------------------------------------
 
-def cpu_baseline(scale=10):
+def cpu_baseline(scale=4):
     import oracle
     from paper_2606_24647_amd import datagen as dg
     oracle.lib()
@@ -462,7 +462,7 @@ def main():
                                                                max_heavy=args.serving_max_heavy))
     cpu = None
     if not args.no_cpu_baseline:
-        log("cpu baseline: oracle on a 1/10 sample")
+        log("cpu baseline: oracle on a 1/4 sample")
         cpu = section("cpu_baseline", cpu_baseline)
 
     line = {
