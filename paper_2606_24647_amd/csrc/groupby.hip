@@ -208,6 +208,52 @@ __global__ void k_compact_init(uint32_t* ticket, uint64_t* status, int64_t ntile
   for (; i < ntiles; i += stride) status[i] = 0;
 }
 
+// Output value of column j for occupied slot s (keys first, then aggregates,
+// then the optional unsigned sort key); *ok = false for NULL.
+__device__ __forceinline__ int64_t compact_value(const CompactArgs& a, int j, int nk, uint64_t s, bool* ok) {
+  const bool extra = s >= a.cap_alloc;
+  int64_t v = 0;
+  *ok = true;
+  if (j == nk + a.naggs) {
+    // Sort key: unsigned order = key order, NULL first.
+    constexpr uint64_t kSign = 1ull << 63;
+    if (a.key_kind == 0) v = (int64_t)a.keys[s];
+    else if (!extra) v = (int64_t)(a.keys[s] ^ kSign);
+    else if (a.key_kind == 1 && s == a.cap_alloc + 1) v = 0;  // NULL
+    else v = (int64_t)(~0ull ^ kSign);                         // the key -1
+  } else if (j < nk) {
+    if (a.key_kind == 2) {
+      v = extra ? -1 : (int64_t)a.keys[s];
+    } else if (a.kp.mode == KEY_RAW64) {
+      if (extra) {
+        const bool is_null = s == a.cap_alloc + 1;
+        v = is_null ? 0 : -1;
+        *ok = !is_null;
+      } else {
+        v = (int64_t)a.keys[s];
+      }
+    } else {
+      v = decode_field(a.kp, a.keys[s], j, ok);
+    }
+  } else {
+    const DAgg& ag = a.aggs[j - nk];
+    const uint64_t* acc = a.acc + s * a.aw;
+    v = (int64_t)acc[ag.word];
+    if ((ag.op == GQ_SUM || ag.op == GQ_MIN || ag.op == GQ_MAX) && ag.cword >= 0) *ok = acc[ag.cword] != 0;
+    if (!*ok) v = 0;
+  }
+  return v;
+}
+
+__device__ __forceinline__ void put_value(uint8_t* out, int64_t g, int64_t v, int type) {
+  switch (type) {
+    case GQ_I8: reinterpret_cast<int8_t*>(out)[g] = (int8_t)v; break;
+    case GQ_I16: reinterpret_cast<int16_t*>(out)[g] = (int16_t)v; break;
+    case GQ_I32: reinterpret_cast<int32_t*>(out)[g] = (int32_t)v; break;
+    default: reinterpret_cast<int64_t*>(out)[g] = v; break;
+  }
+}
+
 template <int BLOCK, int ITEMS>
 __global__ __launch_bounds__(BLOCK) void k_compact(const CompactArgs a) {
   constexpr int TILE = BLOCK * ITEMS;
@@ -217,6 +263,7 @@ __global__ __launch_bounds__(BLOCK) void k_compact(const CompactArgs a) {
   __shared__ int64_t s_excl;
   __shared__ __attribute__((aligned(16))) uint8_t s_stage[TILE * 8];
   __shared__ uint8_t s_vbyte[TILE];
+  __shared__ uint64_t s_slot[TILE];   // the tile's occupied slots in output order
 
   if (threadIdx.x == 0) s_tile = atomicAdd(a.ticket, 1u);
   __syncthreads();
@@ -261,6 +308,13 @@ __global__ __launch_bounds__(BLOCK) void k_compact(const CompactArgs a) {
     btot += s_wave[i];
   }
   const int local = (int)(bpre + wpre);
+  {
+    int pos = local;
+    static_for<0, ITEMS>([&](auto kk) __attribute__((always_inline)) {
+      constexpr int k = decltype(kk)::value;
+      if ((keep >> k) & 1u) s_slot[pos++] = (uint64_t)sl[k];
+    });
+  }
   if (wave == 0) {
     int64_t e = lookback_exclusive(a.status, tile, (int64_t)btot);
     if (lane == 0) s_excl = e;
@@ -288,44 +342,38 @@ __global__ __launch_bounds__(BLOCK) void k_compact(const CompactArgs a) {
   }
   if (btot == 0) return;
 
+  if ((int)btot * ncols <= TILE) {
+    // Few groups: every (row, column) value of the tile is read in one round,
+    // one per thread, so that the reads of all columns are in flight together
+    // (the general path below reads one column per round).
+    int64_t* s_val = reinterpret_cast<int64_t*>(s_stage);
+    const int nb = (int)btot;
+    for (int q = threadIdx.x; q < nb * ncols; q += BLOCK) {
+      const int j = q / nb;
+      bool ok;
+      s_val[q] = compact_value(a, j, nk, s_slot[q - j * nb], &ok);
+      s_vbyte[q] = ok ? 1 : 0;
+    }
+    __syncthreads();
+    for (int j = 0; j < ncols; ++j) {
+      const OCol& o = j < nk + a.naggs ? a.out[j] : a.sortkey;
+      for (int i = threadIdx.x; i < nb; i += BLOCK) {
+        const int64_t g = goff + i;
+        if (g < a.out_cap) put_value(o.data, g, s_val[j * nb + i], o.type);
+      }
+      if (o.valid) write_valid_bits<BLOCK>(o.valid, s_vbyte + j * nb, goff, nb, a.out_cap);
+    }
+    return;
+  }
+
   for (int j = 0; j < ncols; ++j) {
     const OCol& o = j < nk + a.naggs ? a.out[j] : a.sortkey;
     int pos = local;
     static_for<0, ITEMS>([&](auto kk) __attribute__((always_inline)) {
       constexpr int k = decltype(kk)::value;
       if (!((keep >> k) & 1u)) return;
-      const uint64_t s = (uint64_t)sl[k];
-      const bool extra = s >= a.cap_alloc;
-      int64_t v = 0;
-      bool ok = true;
-      if (j == nk + a.naggs) {
-        // Sort key: unsigned order = key order, NULL first.
-        constexpr uint64_t kSign = 1ull << 63;
-        if (a.key_kind == 0) v = (int64_t)a.keys[s];
-        else if (!extra) v = (int64_t)(a.keys[s] ^ kSign);
-        else if (a.key_kind == 1 && s == a.cap_alloc + 1) v = 0;  // NULL
-        else v = (int64_t)(~0ull ^ kSign);                         // the key -1
-      } else if (j < nk) {
-        if (a.key_kind == 2) {
-          v = extra ? -1 : (int64_t)a.keys[s];
-        } else if (a.kp.mode == KEY_RAW64) {
-          if (extra) {
-            const bool is_null = s == a.cap_alloc + 1;
-            v = is_null ? 0 : -1;
-            ok = !is_null;
-          } else {
-            v = (int64_t)a.keys[s];
-          }
-        } else {
-          v = decode_field(a.kp, a.keys[s], j, &ok);
-        }
-      } else {
-        const DAgg& ag = a.aggs[j - nk];
-        const uint64_t* acc = a.acc + s * a.aw;
-        v = (int64_t)acc[ag.word];
-        if ((ag.op == GQ_SUM || ag.op == GQ_MIN || ag.op == GQ_MAX) && ag.cword >= 0) ok = acc[ag.cword] != 0;
-        if (!ok) v = 0;
-      }
+      bool ok;
+      const int64_t v = compact_value(a, j, nk, (uint64_t)sl[k], &ok);
       stage_put(s_stage, pos, v, o.type);
       s_vbyte[pos] = ok ? 1 : 0;
       ++pos;
