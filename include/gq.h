@@ -186,6 +186,11 @@ int32_t* gq_ctx_status_ptr(gq_ctx* ctx);
  * launches is bracketed by two HIP events recorded on the kernel's own stream.
  * Not for use under HIP graph capture. */
 int gq_ctx_set_timing(gq_ctx* ctx, int enable);
+/* Restrict that timing to the launches named `name` (the names the report
+ * lists), so that a timed region carries events around one kernel only; NULL
+ * or "" times every launch again.  The name is copied.  Returns GQ_OK, or
+ * GQ_ERR_INVALID for a NULL context. */
+int gq_ctx_set_timing_only(gq_ctx* ctx, const char* name);
 /* Wait for the recorded events, then report the totals per kernel name since
  * the last report, largest first: up to `cap` entries of `names` (each
  * name_len bytes, NUL-terminated), total_ms and launches.  Returns the number

@@ -32,6 +32,7 @@ struct gq_ctx {
     hipEvent_t a, b;
   };
   bool timing = false;
+  std::string timing_only;   // non-empty: time only launches of this name
   std::vector<TimingRec> recs;
   std::vector<hipEvent_t> pool;
 };

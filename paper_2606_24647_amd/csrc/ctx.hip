@@ -72,6 +72,7 @@ int check_batch(gq_ctx* ctx, const gq_batch* b, const char* what) {
 
 int timing_begin(gq_ctx* ctx, hipStream_t s, const char* name) {
   if (!ctx || !ctx->timing) return -1;
+  if (!ctx->timing_only.empty() && ctx->timing_only != name) return -1;
   hipEvent_t ev[2];
   for (int i = 0; i < 2; ++i) {
     if (!ctx->pool.empty()) {
@@ -188,6 +189,12 @@ int gq_ctx_sync_status(gq_ctx* ctx, hipStream_t stream, int32_t* bits) {
 int gq_ctx_set_timing(gq_ctx* ctx, int enable) {
   if (!ctx) return GQ_ERR_INVALID;
   ctx->timing = enable != 0;
+  return GQ_OK;
+}
+
+int gq_ctx_set_timing_only(gq_ctx* ctx, const char* name) {
+  if (!ctx) return GQ_ERR_INVALID;
+  ctx->timing_only = name ? name : "";
   return GQ_OK;
 }
 

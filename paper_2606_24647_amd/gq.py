@@ -114,6 +114,7 @@ _SIGS = {
     "gq_ctx_sync_status": (C.c_int, [_P, _P, C.POINTER(C.c_int32)]),
     "gq_ctx_status_ptr": (_P, [_P]),
     "gq_ctx_set_timing": (C.c_int, [_P, C.c_int]),
+    "gq_ctx_set_timing_only": (C.c_int, [_P, C.c_char_p]),
     "gq_ctx_timing_report": (C.c_int, [_P, C.c_char_p, C.c_int, _P, _P, C.c_int]),
     "gq_filter": (C.c_int, [_P, C.POINTER(GqBatch), C.POINTER(GqPred), C.c_int,
                             C.POINTER(C.c_int32), C.c_int, C.POINTER(GqBatch), _P, _P]),
@@ -381,7 +382,9 @@ class Context:
             self.check(rc)
         return int(bits.value)
 
-    def set_timing(self, enable: bool):
+    def set_timing(self, enable: bool, only: str | None = None):
+        """Per-kernel events on (every launch, or only launches named `only`) or off."""
+        self.check(_lib.gq_ctx_set_timing_only(self.h, only.encode() if only else None))
         self.check(_lib.gq_ctx_set_timing(self.h, 1 if enable else 0))
 
     def timing_report(self) -> dict:
