@@ -16,8 +16,9 @@
 //                 pbits of fmix64(key ^ kRegionSeed)
 //   k_cs_*        column scan of the (tile, region) counts, stored tile-major
 //                 so that every tile reads and writes its P counts coalesced:
-//                 per-chunk column sums, region totals and offsets (one
-//                 block), then the start of every (tile, region)
+//                 per-chunk column sums and region totals, then the start of
+//                 every (tile, region), each block deriving its regions'
+//                 offsets from the totals
 //   k_rp_scatter  each hist tile in sub-tiles of 2048 rows staged in LDS (one
 //                 1024-thread workgroup per tile); a
 //                 kept row takes the next position of its region in the tile's
@@ -95,6 +96,7 @@ struct RpArgs {
   int32_t vagg[kRjMaxVals];      // probe: aggregate whose input is value word j
   uint32_t* counts;        // [p * ntiles + tile]
   uint32_t* starts;        // exclusive scan of counts
+  uint32_t* rtot;          // region totals of the column scan, zeroed by the histogram
   uint64_t* okey;          // build: region hashes of the keys; probe: tuples
   int32_t* orow;           // build
   int32_t tw;              // probe: words per tuple (hash, then nv values), tuple i at okey[i * tw]
@@ -208,6 +210,8 @@ __global__ __launch_bounds__(kRpBlock) void k_rp_hist(const RpArgs a) {
   uint32_t* s_hist = reinterpret_cast<uint32_t*>(s_raw);
   uint8_t* s_in = s_raw + align_up((size_t)P * 4, 16);
   for (int i = threadIdx.x; i < P; i += kRpBlock) s_hist[i] = 0;
+  if (blockIdx.x == 0)
+    for (int i = threadIdx.x; i < P; i += kRpBlock) a.rtot[i] = 0;
   const int64_t tile = blockIdx.x;
   for (int sub = 0; sub < kRpTile / kRpHSub; ++sub) {
     const int64_t sbase = tile * kRpTile + (int64_t)sub * kRpHSub;
@@ -248,53 +252,50 @@ __global__ __launch_bounds__(256) void k_cs_chunk(const uint32_t* counts, int64_
   if (sum) atomicAdd(&tot[q], sum);
 }
 
-// One block: exclusive scan of the region totals into offsets[0..P], total.
-__global__ __launch_bounds__(1024) void k_cs_base(const uint32_t* rtot, int P, int64_t* offsets, int64_t* total) {
-  constexpr int NW = 1024 / kWave;
+// Per chunk of tiles and region: the start of the region's rows in each tile.
+// Every block first derives its regions' offsets from the region totals (the
+// totals of the regions before its 256, then a block scan of its own); the
+// blocks of the first chunk also store offsets[0..P] and the total.
+__global__ __launch_bounds__(256) void k_cs_fill(const uint32_t* counts, const uint32_t* csum, const uint32_t* rtot,
+                                                 int64_t ntiles, int P, uint32_t* starts, int64_t* offsets,
+                                                 int64_t* total) {
+  constexpr int NW = 256 / kWave;
+  __shared__ int64_t s_before[NW];
   __shared__ int64_t s_wave[NW];
-  const int per = (P + 1023) / 1024;  // <= 4
-  int64_t tot[4];
-  int64_t sum = 0;
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int q = (int)threadIdx.x * per + j;
-    tot[j] = 0;
-    if (j < per && q < P) tot[j] = rtot[q];
-    sum += tot[j];
-  }
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  int64_t incl = sum;
+  const int q0 = blockIdx.y * 256;
+  const int q = q0 + (int)threadIdx.x;
+  int64_t before = 0;
+  for (int i = threadIdx.x; i < q0; i += 256) before += rtot[i];
+  const int64_t mine = q < P ? (int64_t)rtot[q] : 0;
+  int64_t incl = mine;
 #pragma unroll
   for (int o = 1; o < kWave; o <<= 1) {
     const int64_t y = __shfl_up(incl, o, kWave);
     if (lane >= o) incl += y;
+    before += __shfl_xor(before, o, kWave);
   }
   if (lane == kWave - 1) s_wave[wave] = incl;
+  if (lane == 0) s_before[wave] = before;
   __syncthreads();
-  int64_t base = incl - sum, all = 0;
-  for (int w = 0; w < NW; ++w) {
-    if (w < wave) base += s_wave[w];
-    all += s_wave[w];
-  }
+  int64_t base = 0, wpre = 0, btot = 0;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int q = (int)threadIdx.x * per + j;
-    if (j < per && q < P) offsets[q] = base;
-    base += tot[j];
+  for (int w = 0; w < NW; ++w) {
+    base += s_before[w];
+    if (w < wave) wpre += s_wave[w];
+    btot += s_wave[w];
   }
-  if (threadIdx.x == 0) {
-    offsets[P] = all;
-    if (total) *total = all;
+  const int64_t off = base + wpre + incl - mine;
+  if (blockIdx.x == 0) {
+    if (q < P) offsets[q] = off;
+    if (blockIdx.y == gridDim.y - 1 && threadIdx.x == 0) {
+      offsets[P] = base + btot;
+      if (total) *total = base + btot;
+    }
   }
-}
-
-// Per chunk of tiles and region: the start of the region's rows in each tile.
-__global__ __launch_bounds__(256) void k_cs_fill(const uint32_t* counts, const uint32_t* csum, const int64_t* offsets,
-                                                 int64_t ntiles, int P, uint32_t* starts) {
-  const int q = blockIdx.y * 256 + threadIdx.x;
   if (q >= P) return;
   const int64_t c = blockIdx.x;
-  uint32_t run = (uint32_t)offsets[q];
+  uint32_t run = (uint32_t)off;
 #pragma unroll 8
   for (int64_t k = 0; k < c; ++k) run += csum[k * P + q];
   const int64_t t0 = c * kCsChunk;
@@ -830,6 +831,7 @@ int rp_run(gq_ctx* ctx, RpArgs& a, int64_t* offsets, int64_t* total, hipStream_t
   a.starts = ws.as<uint32_t>(off_starts);
   uint32_t* csum = ws.as<uint32_t>(off_csum);
   uint32_t* rtot = ws.as<uint32_t>(off_tot);
+  a.rtot = rtot;
   const size_t lds_hist = align_up((size_t)P * 4, 16) +
                          ((size_t)a.st_off[a.nst_hist - 1] +
                           align_up((size_t)kRpSub * type_width(a.st[a.nst_hist - 1].type), 16)) * kRpHScale;
@@ -837,16 +839,12 @@ int rp_run(gq_ctx* ctx, RpArgs& a, int64_t* offsets, int64_t* total, hipStream_t
             lds_hist, stream, a);
   GQ_LAUNCH_CHECK(ctx);
   const dim3 cgrid((unsigned)nchunks, (unsigned)((P + 255) / 256));
-  int rc = launch_fill_u32(ctx, rtot, 0u, P, stream);
-  if (rc) return rc;
   GQ_LAUNCH(ctx, a.probe ? "rp_scan_probe" : "rp_scan_build", k_cs_chunk, cgrid, dim3(256), 0, stream,
             (const uint32_t*)a.counts, a.ntiles, (int)P, csum, rtot);
   GQ_LAUNCH_CHECK(ctx);
-  GQ_LAUNCH(ctx, a.probe ? "rp_scan_probe" : "rp_scan_build", k_cs_base, dim3(1), dim3(1024), 0, stream,
-            (const uint32_t*)rtot, (int)P, offsets, total);
-  GQ_LAUNCH_CHECK(ctx);
   GQ_LAUNCH(ctx, a.probe ? "rp_scan_probe" : "rp_scan_build", k_cs_fill, cgrid, dim3(256), 0, stream,
-            (const uint32_t*)a.counts, (const uint32_t*)csum, (const int64_t*)offsets, a.ntiles, (int)P, a.starts);
+            (const uint32_t*)a.counts, (const uint32_t*)csum, (const uint32_t*)rtot, a.ntiles, (int)P, a.starts,
+            offsets, total);
   GQ_LAUNCH_CHECK(ctx);
   const size_t lds = rp_scatter_lds((int)P, a.in_bytes);
   GQ_LAUNCH(ctx, a.probe ? "rp_scatter_probe" : "rp_scatter_build", k_rp_scatter, dim3((unsigned)a.ntiles),
