@@ -216,3 +216,17 @@ def test_sorted_groupjoin_and_shared(gq, ctx):
     for q in range(2):
         m = int(cnts[q].item())
         check_sorted(gq, gq.read_table(outs[q], m), oracle.groupby(t, [4, 5], qp[q], C1_AGGS), 2)
+
+
+@pytest.mark.parametrize("keys", [[0], [3, 4]])
+@pytest.mark.parametrize("sorted_out", [False, True])
+def test_few_groups_over_many_tiles(gq, ctx, keys, sorted_out):
+    """A large HBM table (sized for every row to be its own group) holding a
+    few hundred groups: every compaction tile has a handful of occupied slots,
+    at arbitrary output offsets, with NULL keys and NULL aggregate inputs."""
+    rng = np.random.default_rng(31 + len(keys) + 2 * sorted_out)
+    t = random_table(rng, 200_000, types=(np.int64, np.int64, np.int32, np.int16, np.int8), null_frac=0.3,
+                     lo=-150, hi=150)
+    aggs = [("sum", [("col", 1)]), ("count", [("col", 1)]), ("min", [("col", 2)]), ("max", [("col", 2)]),
+            ("count*",)]
+    check(gq, ctx, t, keys, [], aggs, strategy="global", expected_groups=200_000, sorted=sorted_out)
