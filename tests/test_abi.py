@@ -2,6 +2,8 @@
 import ctypes
 import os
 import re
+import shutil
+import subprocess
 
 import pytest
 
@@ -37,3 +39,14 @@ def test_library_exports_every_declared_symbol():
 def test_binding_covers_every_declared_symbol():
     from paper_2606_24647_amd import gq
     assert set(declared_symbols()) <= set(gq.EXPORTS)
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="no C compiler")
+def test_header_is_plain_c(tmp_path):
+    """include/gq.h compiles as C99 (no C++ or torch types in the boundary)."""
+    src = tmp_path / "use_header.c"
+    src.write_text('#include "gq.h"\nint main(void) { gq_ctx* c = 0; (void)c; return 0; }\n')
+    r = subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-fsyntax-only", "-I", os.path.join(ROOT, "include"),
+                        "-I", "/opt/rocm/include", "-D__HIP_PLATFORM_AMD__", str(src)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
