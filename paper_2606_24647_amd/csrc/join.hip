@@ -47,9 +47,8 @@ struct JoinBuildArgs {
   int32_t acc_slots;
   int32_t pad;
   int32_t* dev_status;
-  const int32_t* rowmap;  // build row of input row r (NULL: r itself)
   const int64_t* d_n;     // device row count (NULL: n); n is then an upper bound
-  int32_t key_hashed;     // the key column holds region hashes of the keys
+  int32_t key_hashed;     // the key column holds (region hash, row) pairs of a partitioned table
   int32_t pad2;
 };
 
@@ -58,7 +57,10 @@ __device__ __forceinline__ int64_t jb_rows(const JoinBuildArgs& a) {
   const int64_t d = *a.d_n;
   return d < a.n ? d : a.n;
 }
-__device__ __forceinline__ int64_t jb_row(const JoinBuildArgs& a, int64_t r) { return a.rowmap ? a.rowmap[r] : r; }
+__device__ __forceinline__ int64_t jb_row(const JoinBuildArgs& a, int64_t r) {
+  if (a.key_hashed) return (int64_t)reinterpret_cast<const uint64_t*>(a.key.data)[2 * r + 1];
+  return r;
+}
 
 // Keep mask of rows r0..r0+ITEMS-1 (predicates and a non-NULL key); key values.
 template <int ITEMS>
@@ -76,12 +78,14 @@ __device__ __forceinline__ uint32_t build_rows_keep(const JoinBuildArgs& a, int6
       if (!pred_pass(a.preds[p], v[k])) keep &= ~(1u << k);
     if (a.pcols[p].valid) keep &= valid_items<ITEMS>(a.pcols[p], r0, n);
   }
+  if (a.key_hashed) {
+    const uint64_t* kr = reinterpret_cast<const uint64_t*>(a.key.data);
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) key[k] = r0 + k < n ? (int64_t)region_unhash(kr[2 * (r0 + k)]) : 0;
+    return keep;
+  }
   load_items<ITEMS, true>(a.key, r0, n, key);
   if (a.key.valid) keep &= valid_items<ITEMS>(a.key, r0, n);
-  if (a.key_hashed) {
-#pragma unroll
-    for (int k = 0; k < ITEMS; ++k) key[k] = (int64_t)region_unhash((uint64_t)key[k]);
-  }
   return keep;
 }
 
@@ -674,11 +678,10 @@ int join_ensure_index(gq_ctx* ctx, const gq_join_table* table, hipStream_t strea
   JoinBuildArgs a;
   std::memset(&a, 0, sizeof(a));
   a.n = t->build_rows;
-  a.key.data = reinterpret_cast<const uint8_t*>(t->rj_key);
+  a.key.data = reinterpret_cast<const uint8_t*>(t->rj_kr);
   a.key.type = GQ_I64;
   a.key.align = 16;
   a.npreds = 0;
-  a.rowmap = t->rj_row;
   a.d_n = &t->hdr->nrows;
   a.key_hashed = 1;
   GQ_HIP_CHECK(ctx, hipSetDevice(ctx->device));
@@ -725,8 +728,7 @@ int gq_join_build(gq_ctx* ctx, const gq_batch* build, const int32_t* keys, int n
   const size_t off_keys = 256;
   IndexLayout il = index_layout(cap_alloc, n, acc);
   const size_t off_rjkey = radix ? off_keys : align_up(off_keys + il.bytes, 256);
-  const size_t off_rjrow = align_up(off_rjkey + (radix ? (size_t)n * 8 : 0), 256);
-  const size_t off_rjoff = align_up(off_rjrow + (radix ? (size_t)n * 4 : 0), 256);
+  const size_t off_rjoff = align_up(off_rjkey + (radix ? (size_t)n * 16 : 0), 256);
   const size_t total = align_up(off_rjoff + (radix ? ((size_t)1 << pbits) * 8 + 8 : 0), 256);
 
   GQ_HIP_CHECK(ctx, hipSetDevice(ctx->device));
@@ -750,8 +752,7 @@ int gq_join_build(gq_ctx* ctx, const gq_batch* build, const int32_t* keys, int n
   t->lf_milli = a.lf_milli;
   if (radix) {
     t->rj_pbits = pbits;
-    t->rj_key = reinterpret_cast<uint64_t*>(base + off_rjkey);
-    t->rj_row = reinterpret_cast<int32_t*>(base + off_rjrow);
+    t->rj_kr = reinterpret_cast<uint64_t*>(base + off_rjkey);
     t->rj_off = reinterpret_cast<int64_t*>(base + off_rjoff);
   }
   auto fail = [&](int code) {

@@ -40,7 +40,7 @@ int rj_choose_pbits(int64_t build_rows);
 int rj_lcap(int nacc);
 int rj_kpr(int lcap);
 // Partition the kept build rows (predicates pass, key non-NULL) by region into
-// t->rj_key / t->rj_row / t->rj_off; the kept count goes to t->hdr->nrows.
+// t->rj_kr / t->rj_off; the kept count goes to t->hdr->nrows.
 int rj_build(gq_ctx* ctx, const gq_batch* build, int32_t key_col, const gq_pred* preds, int npreds,
              gq_join_table* t, hipStream_t stream);
 // Whether a group-join of `in` with this aggregate plan can take the radix path.

@@ -22,10 +22,11 @@
 //   k_rp_scatter  each hist tile in sub-tiles of 2048 rows staged in LDS (one
 //                 1024-thread workgroup per tile); a
 //                 kept row takes the next position of its region in the tile's
-//                 range with an LDS atomic and is written there: build keys and
-//                 build row ids grouped by region (order inside a region is
-//                 unspecified; with thousands of regions a tile holds only a few
-//                 rows per region, so there is no run of stores to coalesce)
+//                 range with an LDS atomic and is written there: (key hash,
+//                 build row) pairs of 64-bit words grouped by region, one
+//                 16-byte store each (order inside a region is unspecified;
+//                 with thousands of regions a tile holds only a few rows per
+//                 region, so there is no run of stores to coalesce)
 // Probe side (gq_pipeline when the only group key is the probe key): the same
 // three kernels, the payload of a row being its aggregate inputs (one 64-bit
 // product expression per SUM/MIN/MAX, and a non-NULL mask where an input can
@@ -97,8 +98,7 @@ struct RpArgs {
   uint32_t* counts;        // [p * ntiles + tile]
   uint32_t* starts;        // exclusive scan of counts
   uint32_t* rtot;          // region totals of the column scan, zeroed by the histogram
-  uint64_t* okey;          // build: region hashes of the keys; probe: tuples
-  int32_t* orow;           // build
+  uint64_t* okey;          // build: (region hash, row) pairs; probe: tuples
   int32_t tw;              // probe: words per tuple (hash, then nv values), tuple i at okey[i * tw]
   int32_t pad_tw;
   uint8_t* onn;            // probe: non-NULL mask (bit i = aggregate i)
@@ -374,8 +374,8 @@ __global__ __launch_bounds__(kRpSBlock) void k_rp_scatter(const RpArgs a) {
           a.onn[g] = (uint8_t)nnm;
         }
       } else {
-        a.okey[g] = h;
-        a.orow[g] = (int32_t)(sbase + r);
+        typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+        *reinterpret_cast<u64x2*>(a.okey + 2 * (size_t)g) = u64x2{h, (uint64_t)(sbase + r)};
       }
     }
   }
@@ -397,7 +397,7 @@ struct RjJoinArgs {
   int32_t vword[GQ_MAX_AGGS];   // value word of aggregate i in the tuple, -1 if none
   int32_t sums_only;            // every aggregate is COUNT(*) or a SUM of a non-NULL input
   int32_t sum_word[kRjMaxVals]; // then: accumulator word of value word v
-  const uint64_t* bkey;     // build key hashes grouped by region
+  const uint64_t* bkey;     // build (key hash, row) pairs grouped by region
   const int64_t* boff;      // P + 1
   const uint64_t* tkey;     // probe tuple key hashes grouped by region
   int32_t tw;               // words per probe tuple: hash, then nv values
@@ -590,7 +590,7 @@ __global__ __launch_bounds__(kRjBlock) void k_rj_join(const RjJoinArgs a) {
 #pragma unroll
       for (int u = 0; u < kRjUnroll; ++u) {
         const int64_t i = base + (int64_t)u * kRjBlock + threadIdx.x;
-        h[u] = a.bkey[i < b1 ? i : b1 - 1];
+        h[u] = a.bkey[2 * (i < b1 ? i : b1 - 1)];
       }
 #pragma unroll
       for (int u = 0; u < kRjUnroll; ++u) {
@@ -892,8 +892,7 @@ int rj_build(gq_ctx* ctx, const gq_batch* build, int32_t key_col, const gq_pred*
   RpArgs a;
   if (!rj_build_plan(a, build, key_col, preds, npreds, t->rj_pbits))
     return set_error(ctx, GQ_ERR_UNSUPPORTED, "radix join: build staging does not fit");
-  a.okey = t->rj_key;
-  a.orow = t->rj_row;
+  a.okey = t->rj_kr;
   a.ocap = build->nrows;
   return rp_run(ctx, a, t->rj_off, &t->hdr->nrows, stream);
 }
@@ -933,7 +932,7 @@ static bool rj_probe_plan(RpArgs& r, int32_t (&vword)[GQ_MAX_AGGS], const gq_bat
 
 bool rj_usable(const gq_join_table* t, const gq_batch* in, int32_t probe_key, const gq_pred* preds, int npreds,
                const AggPlan& ap) {
-  if (!t || !t->rj_key) return false;
+  if (!t || !t->rj_kr) return false;
   if (in->nrows >= ((int64_t)1 << 32)) return false;
   RpArgs r;
   int32_t vword[GQ_MAX_AGGS];
@@ -1002,7 +1001,7 @@ int rj_groupjoin(gq_ctx* ctx, const gq_batch* in, int32_t probe_key, const gq_pr
     if (ag.op != GQ_SUM || ag.cword >= 0 || j.vword[i] < 0) j.sums_only = 0;
     else j.sum_word[j.vword[i]] = ag.word;
   }
-  j.bkey = t->rj_key;
+  j.bkey = t->rj_kr;
   j.boff = t->rj_off;
   j.tkey = r.okey;
   j.tw = r.tw;

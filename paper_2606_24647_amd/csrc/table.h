@@ -245,12 +245,12 @@ struct gq_join_table {
   // inputs, else on first use from the partitioned rows below.
   bool index_built = false;
   int32_t lf_milli = 500;     // load factor of the index, times 1000
-  // Partitioned build side (large build inputs): kept rows' keys and row ids
-  // grouped by region (top rj_pbits bits of the region hash), region r in
-  // [rj_off[r], rj_off[r + 1]).  NULL when the build input is small.
+  // Partitioned build side (large build inputs): kept rows as (region hash,
+  // row id) pairs of 64-bit words, grouped by region (top rj_pbits bits of
+  // the region hash), region r in pairs [rj_off[r], rj_off[r + 1]).  NULL when
+  // the build input is small.
   int32_t rj_pbits = 0;
-  uint64_t* rj_key = nullptr;
-  int32_t* rj_row = nullptr;
+  uint64_t* rj_kr = nullptr;
   int64_t* rj_off = nullptr;
   // Recorded on the build stream once the build work is enqueued; every call
   // that reads the table waits for it on its own stream.
