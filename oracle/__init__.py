@@ -13,6 +13,12 @@ Operator specs are plain tuples, the same ones the GPU binding accepts:
 * aggregate: ``("sum", factors)``, ``("count*",)``, ``("count", factors)``,
   ``("min", factors)``, ``("max", factors)``.
 
+Beyond the single-step operators it holds the aggregation modes and the
+streaming aggregation of Section 3.2 (``groupby_mode``, ``agg_stream``), the
+late-materialisation join + group-by over either side's columns of Section 2.3
+(``join_groupby``), expression programs (``eval_expr``, ``filter_expr``,
+``groupby_expr``) and ORDER BY / top-k (``order_by``).
+
 Parity status: every function here is pinned by the not-gpu tests in
 ``tests/test_oracle_pins.py`` (brute force, library routines, closed forms and
 invariants); none is "parity unpinned".
@@ -310,3 +316,235 @@ class _Table:
     @property
     def nrows(self):
         return len(self.cols[0].data) if self.cols else 0
+
+
+# ---------------------------------------------------------------------------
+# Aggregation modes and streaming aggregation (Section 3.2, HashAggregation)
+# ---------------------------------------------------------------------------
+# The paper's aggregation operator runs in one of four modes so that an
+# aggregation can be split across exchange stages: Partial turns input rows
+# into per-group partial states, Intermediate merges partial states into
+# partial states, Final merges partial states into final values, Single goes
+# from rows to final values in one step.  For the aggregates here a partial
+# state is one int64 value with validity:
+#   SUM      sum of the non-NULL inputs, NULL if there is none
+#   COUNT(*) number of rows;  COUNT  number of non-NULL inputs (never NULL)
+#   MIN/MAX  over the non-NULL inputs, NULL if there is none
+# so a partial state holds the same value as the aggregate itself, and merging
+# states is SUM for SUM, COUNT(*) and COUNT, and MIN or MAX for MIN and MAX.
+# In the merge modes an aggregate names its state column with one factor
+# ("col", c); its factor list is otherwise unused.
+
+MODES = {"single": 0, "partial": 1, "intermediate": 2, "final": 3}
+_MERGE_OP = {"sum": "sum", "count*": "sum", "count": "sum", "min": "min", "max": "max"}
+
+
+def merge_aggs(aggs):
+    """Aggregates over state columns that merge the states of `aggs`: the state of
+    aggregate i is column i of the aggregate block (column nk + i of a state batch)."""
+    return [(_MERGE_OP[a[0]],) + (a[1:] if len(a) > 1 else ()) for a in aggs]
+
+
+def groupby_mode(table, keys, preds, aggs, mode):
+    """One group-by step in the given mode.  Raw input (single, partial): `aggs`
+    read raw columns.  State input (intermediate, final): `aggs` are the
+    original aggregates, each with one factor ("col", c) naming its state
+    column, and no predicates apply."""
+    if mode in ("single", "partial"):
+        return groupby(table, keys, preds, aggs)
+    assert not preds, "merge modes take no predicates"
+    for a in aggs:
+        assert len(a) == 2 and len(a[1]) == 1 and a[1][0][0] == "col", "merge-mode aggregates name one state column"
+    return groupby(table, keys, [], merge_aggs(aggs))
+
+
+def result_table(res):
+    """A group result as a table: key columns, then one column per aggregate."""
+    return _Table([_Column(v, ok.copy()) for v, ok in res.keys + res.aggs])
+
+
+def concat_tables(tables):
+    """Row-wise concatenation of tables of equal column count."""
+    ncols = len(tables[0].cols)
+    cols = []
+    for j in range(ncols):
+        data = np.concatenate([t.cols[j].data for t in tables])
+        valid = None
+        if any(t.cols[j].valid is not None for t in tables):
+            valid = np.concatenate([np.ones(len(t.cols[j].data), dtype=bool) if t.cols[j].valid is None
+                                    else np.asarray(t.cols[j].valid, dtype=bool) for t in tables])
+        cols.append(_Column(data, valid))
+    return _Table(cols)
+
+
+def agg_stream(batches, keys, preds, aggs, mode="partial", emit_groups=None):
+    """Streaming aggregation over a sequence of batches, in the paper's order of
+    steps: each batch is aggregated on its own (Partial over raw rows, or a
+    merge over state rows), the result is concatenated with the results held
+    so far and the concatenation is aggregated again (Intermediate), and once
+    the held result reaches `emit_groups` groups it is emitted and the
+    operator starts over.  Only partial and intermediate streams emit early;
+    single and final streams emit once, after the last batch.
+
+    batches  list of tables (raw rows, or state rows for intermediate/final)
+    preds    one predicate list per batch (raw input only)
+    Returns the emitted results (GroupResult, canonical order each), in order;
+    a stream that received no batch emits nothing.
+    """
+    nk = len(keys)
+    raw = mode in ("single", "partial")
+    state_aggs = [(a[0], [("col", nk + i)]) for i, a in enumerate(aggs)]
+    held = None
+    emitted = []
+    for b, batch in enumerate(batches):
+        if raw:
+            part = groupby_mode(batch, keys, preds[b] if preds else [], aggs, "partial")
+        else:
+            part = groupby_mode(batch, keys, [], aggs, "intermediate")
+        if held is None:
+            held = part
+        else:
+            both = concat_tables([result_table(held), result_table(part)])
+            held = groupby_mode(both, list(range(nk)), [], state_aggs, "intermediate")
+        if mode in ("partial", "intermediate") and emit_groups is not None and held.nrows >= emit_groups:
+            emitted.append(held)
+            held = None
+    if held is not None:
+        emitted.append(held)
+    return emitted
+
+
+# ---------------------------------------------------------------------------
+# Late materialisation (Section 2.3): a key-only join gives gather maps, the
+# payload columns of both sides are gathered through them, then grouped
+# ---------------------------------------------------------------------------
+
+def join_groupby(probe, ppreds, pkeys, build, bpreds, bkeys, gkeys, aggs):
+    """Group-by over the materialised inner join of filter(probe) and
+    filter(build).  Column c of the joined rows is probe column c for
+    c < len(probe.cols), else build column c - len(probe.cols); group keys and
+    aggregate inputs may come from either side.  The steps are the paper's
+    late materialisation: the join on the key columns alone (pairs of row
+    ids), then the gather of every payload column through those ids, then
+    the group-by."""
+    pi, bi = join(build, bkeys, bpreds, probe, pkeys, ppreds)
+    cols = [_Column(c.data[pi], None if c.valid is None else np.asarray(c.valid, dtype=bool)[pi]) for c in probe.cols]
+    cols += [_Column(c.data[bi], None if c.valid is None else np.asarray(c.valid, dtype=bool)[bi]) for c in build.cols]
+    return groupby(_Table(cols), gkeys, [], aggs)
+
+
+# ---------------------------------------------------------------------------
+# Expression programs (Section 3.2: expressions evaluated fused, as cuDF's AST
+# compute_column) and ORDER BY / top-k (Section 3.1 names OrderBy among the
+# operators moved to the GPU)
+# ---------------------------------------------------------------------------
+# An expression is a tree of tuples:
+#   ("col", c)  ("const", k)  ("add", a, b)  ("sub", a, b)  ("mul", a, b)  ("neg", a)
+#   ("lt"|"le"|"eq"|"ne"|"gt"|"ge", a, b)      1 or 0
+#   ("case", cond, a, b)                        a where cond is non-NULL and non-zero, else b
+# Integer arithmetic wraps modulo 2^64.  An operand that is NULL makes add, sub,
+# mul, neg and the comparisons NULL; a CASE whose condition is NULL takes its
+# ELSE branch (SQL's CASE WHEN).  A predicate ("expr", e) keeps a row when e
+# is non-NULL and non-zero.
+
+_CMP = {"lt": np.less, "le": np.less_equal, "eq": np.equal, "ne": np.not_equal,
+        "gt": np.greater, "ge": np.greater_equal}
+
+
+def eval_expr(table, e):
+    """(values int64, valid bool) of expression e over every row of table."""
+    n = table.nrows
+    op = e[0]
+    if op == "col":
+        c = table.cols[e[1]]
+        v = np.asarray(c.data).astype(np.int64)
+        ok = np.ones(n, dtype=bool) if c.valid is None else np.asarray(c.valid, dtype=bool).copy()
+        return v, ok
+    if op == "const":
+        return np.full(n, np.int64(e[1]), dtype=np.int64), np.ones(n, dtype=bool)
+    if op == "neg":
+        a, ok = eval_expr(table, e[1])
+        with np.errstate(over="ignore"):
+            return (np.uint64(0) - a.astype(np.uint64)).astype(np.int64), ok
+    if op == "case":
+        c, cok = eval_expr(table, e[1])
+        a, aok = eval_expr(table, e[2])
+        b, bok = eval_expr(table, e[3])
+        take = cok & (c != 0)
+        return np.where(take, a, b), np.where(take, aok, bok)
+    a, aok = eval_expr(table, e[1])
+    b, bok = eval_expr(table, e[2])
+    ok = aok & bok
+    if op in _CMP:
+        return _CMP[op](a, b).astype(np.int64), ok
+    ua, ub = a.astype(np.uint64), b.astype(np.uint64)
+    with np.errstate(over="ignore"):
+        r = {"add": ua + ub, "sub": ua - ub, "mul": ua * ub}[op]
+    return r.astype(np.int64), ok
+
+
+def filter_expr(table, preds, exprs, proj):
+    """Filter where every range/ne predicate holds and every expression predicate
+    is non-NULL and non-zero; stable; projected columns."""
+    keep = np.zeros(table.nrows, dtype=bool)
+    keep[filter_rows(table, preds)] = True
+    for e in exprs:
+        v, ok = eval_expr(table, e)
+        keep &= ok & (v != 0)
+    rows = np.flatnonzero(keep)
+    return rows, [_take(table.cols[j], rows) for j in proj]
+
+
+def groupby_expr(table, keys, preds, exprs, aggs):
+    """Group-by whose aggregates read expression programs: aggs are
+    (op, expr) with op in sum/count/min/max, or ("count*",).  Each expression
+    is evaluated into a column first, then the plain group-by runs over them."""
+    keep = np.zeros(table.nrows, dtype=bool)
+    keep[filter_rows(table, preds)] = True
+    for e in exprs:
+        v, ok = eval_expr(table, e)
+        keep &= ok & (v != 0)
+    rows = np.flatnonzero(keep)
+    cols = [_Column(np.asarray(c.data)[rows], None if c.valid is None else np.asarray(c.valid, dtype=bool)[rows])
+            for c in table.cols]
+    plain = []
+    for a in aggs:
+        if a[0] == "count*":
+            plain.append(("count*",))
+            continue
+        v, ok = eval_expr(_Table(cols), a[1])
+        cols.append(_Column(v, ok))
+        plain.append((a[0], [("col", len(cols) - 1)]))
+    return groupby(_Table(cols), keys, [], plain)
+
+
+def order_by(table, keys, desc=None, nulls_first=None, limit=None):
+    """Row ids of `table` in ORDER BY order: key columns compared in turn, each
+    ascending unless desc[j], NULLs first or last per nulls_first[j] (default:
+    NULLs last, Presto's default); ties keep input order (a stable sort).  With
+    `limit`, the first `limit` of them (top-k)."""
+    nk = len(keys)
+    desc = list(desc or [False] * nk)
+    nulls_first = list(nulls_first or [False] * nk)
+    n = table.nrows
+    cols = []
+    for j, c in enumerate(keys):
+        col = table.cols[c]
+        v = [int(x) for x in np.asarray(col.data)]
+        ok = [True] * n if col.valid is None else [bool(x) for x in np.asarray(col.valid)]
+        cols.append((v, ok))
+
+    def sort_key(i):
+        parts = []
+        for j, (v, ok) in enumerate(cols):
+            null_rank = 0 if nulls_first[j] else 1
+            if not ok[i]:
+                parts.append((null_rank, 0))
+            else:
+                parts.append((1 - null_rank, -v[i] if desc[j] else v[i]))
+        return tuple(parts) + (i,)
+
+    rows = sorted(range(n), key=sort_key)
+    if limit is not None:
+        rows = rows[:limit]
+    return np.asarray(rows, dtype=np.int64)

@@ -424,3 +424,316 @@ def test_golden_c1_fixture():
         assert row["sum_disc"] == int(d.sum()) and row["sum_rev"] == int((p * (100 - d)).sum())
         assert row["count"] == int(sel.sum())
     assert sum(r["count"] for r in g["groups"]) == int(m.sum())
+
+
+# ---------------------------------------------------------------------------
+# Aggregation modes and streaming aggregation (Section 3.2): pinned by brute
+# force over the raw rows, independent of the concatenate / re-aggregate steps
+# ---------------------------------------------------------------------------
+
+STREAM_AGGS = [("sum", [("col", 2)]), ("count*",), ("count", [("col", 2)]), ("min", [("col", 3)]),
+               ("max", [("col", 2), ("k-col", 10, 3)])]
+
+
+def _stream_batch(rng, n):
+    k = rng.integers(0, 9, n).astype(np.int32)
+    kv = rng.random(n) > 0.1
+    k2 = rng.integers(-1, 2, n).astype(np.int8)
+    x = rng.integers(-(1 << 40), 1 << 40, n)
+    xv = rng.random(n) > 0.3
+    y = rng.integers(0, 7, n).astype(np.int16)
+    yv = rng.random(n) > 0.2
+    f = rng.integers(0, 100, n).astype(np.int32)
+    return tbl(k=(k, kv), k2=k2, x=(x, xv), y=(y, yv), f=f)
+
+
+def _brute_aggs(batches, preds):
+    """{key: [sum, count*, count, min, max]} over the kept raw rows, None = NULL."""
+    groups = {}
+    for t, pr in zip(batches, preds):
+        k, kv = t.cols[0].data, t.cols[0].valid
+        k2 = t.cols[1].data
+        x, xv = t.cols[2].data, t.cols[2].valid
+        y, yv = t.cols[3].data, t.cols[3].valid
+        f = t.cols[4].data
+        lo, hi = pr[0][2], pr[0][3]
+        for i in range(len(k)):
+            if not (lo <= f[i] <= hi):
+                continue
+            key = ((1, int(k[i])) if kv[i] else (0, 0), (1, int(k2[i])))
+            g = groups.setdefault(key, [None, 0, 0, None, None])
+            g[1] += 1
+            if xv[i]:
+                g[0] = ((g[0] or 0) + int(x[i])) & M64
+                g[2] += 1
+            if yv[i]:
+                g[3] = int(y[i]) if g[3] is None else min(g[3], int(y[i]))
+            if xv[i] and yv[i]:
+                v = (int(x[i]) * (10 - int(y[i]))) & M64
+                v = v - (1 << 64) if v >= (1 << 63) else v
+                g[4] = v if g[4] is None else max(g[4], v)
+    return dict(sorted(groups.items()))
+
+
+def _as_dict(res):
+    out = {}
+    for gi in range(res.nrows):
+        key = tuple((1, int(res.keys[j][0][gi])) if res.keys[j][1][gi] else (0, 0) for j in range(len(res.keys)))
+        vals = []
+        for a, (v, ok) in enumerate(res.aggs):
+            if not ok[gi]:
+                vals.append(None)
+            else:
+                vals.append(int(v[gi]) & M64 if a == 0 else int(v[gi]))
+        out[key] = vals
+    return out
+
+
+@pytest.mark.parametrize("seed,emit", [(0, 1), (1, 3), (2, 10), (3, None), (4, 6)])
+def test_stream_partial_emissions_brute_force(seed, emit):
+    """Every emission of a partial stream equals the brute-force aggregate of the
+    raw rows pushed since the previous one; it comes after the first batch at
+    which the distinct kept keys since the previous emission reach the
+    threshold; the final merge of all emissions equals the single-step result."""
+    rng = np.random.default_rng(700 + seed)
+    sizes = [0, 1, 57, 3, 250, 0, 19, 400, 2, 75]
+    batches = [_stream_batch(rng, n) for n in sizes]
+    preds = [[("range", 4, int(rng.integers(0, 30)), int(rng.integers(60, 100)))] for _ in sizes]
+    em = oracle.agg_stream(batches, [0, 1], preds, STREAM_AGGS, mode="partial", emit_groups=emit)
+    # Emission points by counting distinct keys (a set) since the last emission.
+    bounds, start, seen = [], 0, set()
+    for b, t in enumerate(batches):
+        k, kv, k2, f = t.cols[0].data, t.cols[0].valid, t.cols[1].data, t.cols[4].data
+        lo, hi = preds[b][0][2], preds[b][0][3]
+        for i in range(len(k)):
+            if lo <= f[i] <= hi:
+                seen.add(((1, int(k[i])) if kv[i] else (0, 0), int(k2[i])))
+        if emit is not None and len(seen) >= emit:
+            bounds.append((start, b + 1))
+            start, seen = b + 1, set()
+    if start < len(batches):
+        bounds.append((start, len(batches)))
+    assert len(em) == len(bounds)
+    for res, (b0, b1) in zip(em, bounds):
+        assert _as_dict(res) == _brute_aggs(batches[b0:b1], preds[b0:b1])
+    # Final over the concatenated emissions (as state batches) == single over every row.
+    states = [oracle.result_table(r) for r in em]
+    nk = 2
+    final_aggs = [(a[0], [("col", nk + i)]) for i, a in enumerate(STREAM_AGGS)]
+    fin = oracle.agg_stream(states, list(range(nk)), None, final_aggs, mode="final")
+    assert len(fin) == 1
+    assert _as_dict(fin[0]) == _brute_aggs(batches, preds)
+    single = oracle.agg_stream(batches, [0, 1], preds, STREAM_AGGS, mode="single", emit_groups=emit)
+    assert len(single) == 1 and _as_dict(single[0]) == _brute_aggs(batches, preds)
+
+
+def test_merge_modes_all_null_groups_and_counts():
+    """Intermediate over two partial results: SUM/MIN/MAX of a group whose inputs
+    are NULL in both halves stay NULL; COUNT(*) and COUNT add up and are never NULL."""
+    a = tbl(k=np.array([1, 1, 2], dtype=np.int64), x=(np.array([5, 0, 0]), np.array([True, False, False])),
+            f=np.zeros(3, dtype=np.int32))
+    b = tbl(k=np.array([2, 3], dtype=np.int64), x=(np.array([0, 7]), np.array([False, True])),
+            f=np.zeros(2, dtype=np.int32))
+    aggs = [("sum", [("col", 1)]), ("count*",), ("count", [("col", 1)]), ("min", [("col", 1)])]
+    pa = oracle.groupby_mode(a, [0], [], aggs, "partial")
+    pb = oracle.groupby_mode(b, [0], [], aggs, "partial")
+    both = oracle.concat_tables([oracle.result_table(pa), oracle.result_table(pb)])
+    st = [(x[0], [("col", 1 + i)]) for i, x in enumerate(aggs)]
+    m = oracle.groupby_mode(both, [0], [], st, "intermediate")
+    assert list(m.keys[0][0]) == [1, 2, 3]
+    assert list(m.aggs[0][1]) == [True, False, True] and m.aggs[0][0][0] == 5 and m.aggs[0][0][2] == 7
+    assert list(m.aggs[1][0]) == [2, 2, 1] and m.aggs[1][1].all()
+    assert list(m.aggs[2][0]) == [1, 0, 1] and m.aggs[2][1].all()
+    assert list(m.aggs[3][1]) == [True, False, True]
+
+
+# ---------------------------------------------------------------------------
+# Late materialisation: group-by over a build-side payload column
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", range(3))
+def test_join_groupby_build_payload_brute_force(seed):
+    """Nested loops over (probe, build) pairs, then a dict keyed by the build
+    side's payload column (NULL its own group), summing a probe-side product."""
+    rng = np.random.default_rng(900 + seed)
+    nb, npr = int(rng.integers(1, 120)), int(rng.integers(0, 300))
+    bk = rng.integers(0, 25, nb)
+    bkv = rng.random(nb) > 0.1
+    bd = rng.integers(0, 10, nb).astype(np.int32)
+    bc = rng.integers(0, 6, nb)
+    bcv = rng.random(nb) > 0.2
+    pk = rng.integers(0, 25, npr)
+    pkv = rng.random(npr) > 0.1
+    pp = rng.integers(1, 1000, npr)
+    pdisc = rng.integers(0, 11, npr)
+    pdate = rng.integers(0, 10, npr).astype(np.int32)
+    build = tbl(k=(bk, bkv), d=bd, c=(bc, bcv))
+    probe = tbl(k=(pk, pkv), p=pp, disc=pdisc, date=pdate)
+    bpred, ppred = [("range", 1, 0, 6)], [("range", 3, 3, 9)]
+    aggs = [("sum", [("col", 1), ("k-col", 100, 2)]), ("count*",), ("max", [("col", 1)])]
+    r = oracle.join_groupby(probe, ppred, [0], build, bpred, [0], [4 + 2], aggs)
+    groups = {}
+    for i in range(npr):
+        if not (pkv[i] and 3 <= pdate[i] <= 9):
+            continue
+        for j in range(nb):
+            if bkv[j] and 0 <= bd[j] <= 6 and bk[j] == pk[i]:
+                key = (1, int(bc[j])) if bcv[j] else (0, 0)
+                g = groups.setdefault(key, [0, 0, None])
+                g[0] = (g[0] + int(pp[i]) * (100 - int(pdisc[i]))) & M64
+                g[1] += 1
+                g[2] = int(pp[i]) if g[2] is None else max(g[2], int(pp[i]))
+    exp = dict(sorted(groups.items()))
+    got = {}
+    for gi in range(r.nrows):
+        key = (1, int(r.keys[0][0][gi])) if r.keys[0][1][gi] else (0, 0)
+        got[key] = [int(r.aggs[0][0][gi]) & M64, int(r.aggs[1][0][gi]), int(r.aggs[2][0][gi])]
+    assert got == {k: v for k, v in exp.items()}
+
+
+def test_join_groupby_dense_build_payload():
+    """C2-shaped tables grouped by the dimension's ckey: pkey is a permutation,
+    so fact row i joins dim row inv[fkey[i]] (if that row passes), and the
+    revenue per ckey is a dense np.add.at -- no hashing, no join."""
+    nd, nf = 3000, 20000
+    dim = dg.dim_c2(nd, seed=17, ckeys=50)
+    fact = dg.fact_c2(nf, nkeys=nd, seed=17)
+    dpred, fpred = [("range", 1, 0, 1202)], [("range", 3, 1278, 2555)]
+    rev = [("col", 1), ("k-col", 100, 2)]
+    r = oracle.join_groupby(fact, fpred, [0], dim, dpred, [0], [4 + 2], [("sum", rev), ("count*",)])
+    pkey, ddate, ckey = (dim.cols[j].data for j in range(3))
+    inv = np.empty(nd + 1, dtype=np.int64)
+    inv[pkey] = np.arange(nd)
+    fkey, price, disc, fdate = (fact.cols[j].data for j in range(4))
+    j = inv[fkey]
+    m = (fdate >= 1278) & (ddate[j] <= 1202)
+    tot = np.zeros(51, dtype=np.int64)
+    cnt = np.zeros(51, dtype=np.int64)
+    np.add.at(tot, ckey[j[m]], (price * (100 - disc))[m])
+    np.add.at(cnt, ckey[j[m]], 1)
+    nz = np.flatnonzero(cnt)
+    assert np.array_equal(r.keys[0][0], nz)
+    assert np.array_equal(r.aggs[0][0], tot[nz]) and np.array_equal(r.aggs[1][0], cnt[nz])
+
+
+# ---------------------------------------------------------------------------
+# Expression programs
+# ---------------------------------------------------------------------------
+
+def _expr_table(rng, n):
+    a = rng.integers(-(1 << 62), 1 << 62, n)
+    av = rng.random(n) > 0.2
+    b = rng.integers(-50, 50, n).astype(np.int32)
+    bv = rng.random(n) > 0.1
+    c = rng.integers(0, 3, n).astype(np.int8)
+    return tbl(a=(a, av), b=(b, bv), c=c)
+
+
+def _rand_expr(rng, depth):
+    if depth == 0 or rng.random() < 0.25:
+        return ("col", int(rng.integers(0, 3))) if rng.random() < 0.7 else ("const", int(rng.integers(-9, 9)))
+    op = ["add", "sub", "mul", "neg", "lt", "le", "eq", "ne", "gt", "ge", "case"][int(rng.integers(0, 11))]
+    if op == "neg":
+        return (op, _rand_expr(rng, depth - 1))
+    if op == "case":
+        return (op, _rand_expr(rng, depth - 1), _rand_expr(rng, depth - 1), _rand_expr(rng, depth - 1))
+    return (op, _rand_expr(rng, depth - 1), _rand_expr(rng, depth - 1))
+
+
+def _scalar_eval(t, e, i):
+    """One row, Python integers: None for NULL; arithmetic reduced modulo 2^64
+    into the signed range after every step."""
+    def s64(x):
+        x &= M64
+        return x - (1 << 64) if x >= (1 << 63) else x
+    op = e[0]
+    if op == "col":
+        c = t.cols[e[1]]
+        if c.valid is not None and not c.valid[i]:
+            return None
+        return int(c.data[i])
+    if op == "const":
+        return e[1]
+    if op == "neg":
+        x = _scalar_eval(t, e[1], i)
+        return None if x is None else s64(-x)
+    if op == "case":
+        c = _scalar_eval(t, e[1], i)
+        return _scalar_eval(t, e[2], i) if (c is not None and c != 0) else _scalar_eval(t, e[3], i)
+    x, y = _scalar_eval(t, e[1], i), _scalar_eval(t, e[2], i)
+    if x is None or y is None:
+        return None
+    return {"add": lambda: s64(x + y), "sub": lambda: s64(x - y), "mul": lambda: s64(x * y),
+            "lt": lambda: int(x < y), "le": lambda: int(x <= y), "eq": lambda: int(x == y),
+            "ne": lambda: int(x != y), "gt": lambda: int(x > y), "ge": lambda: int(x >= y)}[op]()
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_expr_eval_against_scalar_rows(seed):
+    rng = np.random.default_rng(1200 + seed)
+    t = _expr_table(rng, 200)
+    for _ in range(25):
+        e = _rand_expr(rng, 4)
+        v, ok = oracle.eval_expr(t, e)
+        for i in range(t.nrows):
+            x = _scalar_eval(t, e, i)
+            assert ok[i] == (x is not None), (e, i)
+            if x is not None:
+                assert int(v[i]) == x, (e, i)
+
+
+def test_expr_product_equals_factor_form_and_identities():
+    """price*(100-disc) as an expression equals the factor-list aggregate (pinned
+    above); (a+b)-b == a and a*(b+c) == a*b + a*c modulo 2^64."""
+    t1 = dg.fact_c1(5000, seed=3)
+    rev_e = ("mul", ("col", 1), ("sub", ("const", 100), ("col", 2)))
+    r_e = oracle.groupby_expr(t1, [4, 5], [("range", 3, 0, 2466)], [], [("sum", rev_e), ("count*",)])
+    r_f = oracle.groupby(t1, [4, 5], [("range", 3, 0, 2466)], [("sum", [("col", 1), ("k-col", 100, 2)]), ("count*",)])
+    assert np.array_equal(r_e.aggs[0][0], r_f.aggs[0][0]) and np.array_equal(r_e.aggs[1][0], r_f.aggs[1][0])
+    rng = np.random.default_rng(5)
+    t = _expr_table(rng, 500)
+    a, b, c = ("col", 0), ("col", 1), ("col", 2)
+    v1, ok1 = oracle.eval_expr(t, ("sub", ("add", a, b), b))
+    v0, ok0 = oracle.eval_expr(t, a)
+    assert np.array_equal(v1[ok1], v0[ok1]) and np.array_equal(ok1, ok0 & t.cols[1].valid)
+    l, lok = oracle.eval_expr(t, ("mul", a, ("add", b, c)))
+    r, rok = oracle.eval_expr(t, ("add", ("mul", a, b), ("mul", a, c)))
+    assert np.array_equal(lok, rok) and np.array_equal(l[lok], r[rok])
+
+
+def test_filter_expr_case_condition_null_takes_else():
+    t = tbl(x=(np.array([5, 5, 5, 0]), np.array([True, False, True, True])), y=np.array([1, 0, 0, 0]))
+    # CASE WHEN x > 3 THEN y ELSE 1 - y: row 1 (x NULL) takes the ELSE branch (1 - 0).
+    e = ("case", ("gt", ("col", 0), ("const", 3)), ("col", 1), ("sub", ("const", 1), ("col", 1)))
+    rows, _ = oracle.filter_expr(t, [], [e], [0])
+    assert list(rows) == [0, 1, 3]
+    # A comparison with a NULL operand is NULL, so the row is dropped.
+    rows, _ = oracle.filter_expr(t, [], [("gt", ("col", 0), ("const", -1))], [0])
+    assert list(rows) == [0, 2, 3]
+
+
+# ---------------------------------------------------------------------------
+# ORDER BY / top-k
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", range(4))
+def test_order_by_matches_pandas_stable_sort(seed):
+    rng = np.random.default_rng(1300 + seed)
+    n = int(rng.integers(0, 400))
+    k1 = rng.integers(-3, 3, n)
+    k1v = rng.random(n) > 0.2
+    k2 = rng.integers(-1000, 1000, n).astype(np.int32)
+    k2v = rng.random(n) > 0.1
+    t = tbl(k1=(k1, k1v), k2=(k2, k2v), row=np.arange(n))
+    for desc in ([False, False], [True, False], [False, True], [True, True]):
+        for nf in (False, True):
+            got = oracle.order_by(t, [0, 1], desc=desc, nulls_first=[nf, nf])
+            df = pd.DataFrame({"k1": pd.array(np.where(k1v, k1, 0), dtype="Int64"),
+                               "k2": pd.array(np.where(k2v, k2, 0), dtype="Int64")})
+            df.loc[~k1v, "k1"] = pd.NA
+            df.loc[~k2v, "k2"] = pd.NA
+            exp = df.sort_values(["k1", "k2"], ascending=[not d for d in desc], kind="stable",
+                                 na_position="first" if nf else "last").index.to_numpy()
+            assert np.array_equal(got, exp), (desc, nf)
+            top = oracle.order_by(t, [0, 1], desc=desc, nulls_first=[nf, nf], limit=7)
+            assert np.array_equal(top, exp[:7])
