@@ -140,46 +140,74 @@ def run_c2(torch, gq, devgen, ctx, steps, warmup, lf, breakdown_steps=5):
     ctx.set_timing(False)
     kernels = {k: (v[0] / breakdown_steps, v[1] / breakdown_steps) for k, v in ctx.timing_report().items()}
     dominant = max(kernels.items(), key=lambda kv: kv[1][0])[0]
-    # Timed region: events only around the dominant kernel's launches, on its
-    # stream (events around every launch cost about 3% of the step).
+    # Timed region: K steps, each bracketed by events on the current stream
+    # (the build stream joins it before the step ends), with the 256 MB
+    # Infinity Cache flushed before every step by overwriting a 512 MB buffer
+    # (outside the events).  Events are recorded only around the dominant
+    # kernel's launches, on its own stream (events around every launch cost
+    # about 3% of the step).
+    # The steps are enqueued back to back (no host synchronisation between
+    # them), so the device never waits for the host's launches.
+    scratch = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
     ctx.set_timing(True, only=dominant)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    with Timer(torch) as tm:
-        for _ in range(steps):
-            out, cnt = c2_step(ctx, dim, fact, out_cap, lf)
-    ms_total = tm.ms()
+    evs = []
+    for _ in range(steps):
+        flush_mall(torch, scratch)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        out, cnt = c2_step(ctx, dim, fact, out_cap, lf)
+        b.record()
+        evs.append((a, b))
+    torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    ts = [a.elapsed_time(b) for a, b in evs]
     ctx.set_timing(False)
     dom_total_ms, dom_launches = ctx.timing_report()[dominant]
     ctx.raise_status()
+    # Back to back, no flush: the steady state of a stream of such queries.
+    torch.cuda.synchronize()
+    with Timer(torch) as tm:
+        for _ in range(steps):
+            c2_step(ctx, dim, fact, out_cap, lf)
+    ms_b2b = tm.ms() / steps
+    del scratch
     ngroups = int(cnt.item())
     matched = int(out.cols[2].data[:ngroups].sum().item())
     kept_fact = int((fact.cols[3].data >= 1278).sum().item())
     kept_dim = int((dim.cols[1].data <= 1202).sum().item())
-    return dict(ms_per_step=ms_total / steps, wall_ms_per_step=1e3 * wall / steps, kernels=kernels,
+    st = sorted(ts)
+    return dict(ms_per_step=median(ts), ms_p90=st[min(len(st) - 1, int(0.9 * len(st)))], ms_mean=sum(ts) / len(ts),
+                ms_back_to_back=ms_b2b, wall_ms_per_step=1e3 * wall / steps, kernels=kernels,
                 dominant=dominant, dominant_avg_ms=dom_total_ms / dom_launches,
                 ngroups=ngroups, matched=matched, kept_fact=kept_fact, kept_dim=kept_dim,
                 dim=dim, fact=fact)
 
 
 def c2_bytes(r):
-    """Algorithmic bytes of the whole step, and per launch of the kernels that
-    can dominate it (name -> bytes one launch must move at least)."""
-    dim_read = DIM_ROWS * (8 + 4)                # pkey, date
+    """Algorithmic bytes of the step as the measurement plan defines them, and
+    per launch of the kernels that can dominate it (name -> algorithmic bytes
+    that kernel moves; None where a kernel moves only design overhead, such as
+    a histogram pass re-reading keys).  Per unit: dimension pkey + date read
+    (12 B per dim row), 16 B per inserted build key, fact fkey, price, disc,
+    date read (28 B per fact row), 16 B per probe (kept fact row), 16 B per
+    aggregated (matched) row, 16 B per output group (key and revenue sum).
+    Intermediates of the radix design (probe tuples, build pairs) are not
+    algorithmic."""
+    dim_read = DIM_ROWS * (8 + 4)
     inserts = r["kept_dim"] * 16
-    fact_read = FACT_ROWS * (8 + 8 + 8 + 4)      # fkey, price, disc, date
+    fact_read = FACT_ROWS * (8 + 8 + 8 + 4)
     probes = r["kept_fact"] * 16
     aggs = r["matched"] * 16
-    out = r["ngroups"] * (8 + 8 + 8)             # key, sum, count
+    out = r["ngroups"] * 16
     total = dim_read + inserts + fact_read + probes + aggs + out
-    tuples = r["kept_fact"] * 16                 # radix path: (key hash, revenue) per kept fact row
     per_kernel = {
-        "groupjoin": fact_read + probes + aggs,                  # direct path: fused probe + aggregate
-        "rp_scatter_probe": fact_read + tuples,                  # read the fact columns, write the tuples
-        "rp_hist_probe": FACT_ROWS * (8 + 4),                    # key and predicate columns
-        "rj_join": tuples + r["kept_dim"] * 8 + out,             # tuples and build keys in, groups out
-        "rp_scatter_build": dim_read + r["kept_dim"] * 12,       # dim columns in, (hash, row) out
+        "groupjoin": fact_read + probes + aggs,          # direct path: fused probe + aggregate
+        "rp_scatter_probe": fact_read,                   # reads the fact columns once
+        "rp_hist_probe": None,                           # key re-read: overhead
+        "rj_join": inserts + probes + aggs + out,        # LDS inserts, probes, aggregation, groups out
+        "rp_scatter_build": dim_read,                    # reads the dimension columns once
     }
     return total, per_kernel
 
@@ -496,6 +524,10 @@ def main():
                    "groups": c2["ngroups"], "matched_rows": c2["matched"]},
         "pipeline_hbm": {"alg_bytes": total_bytes, "GBps": round(total_bytes / (ms * 1e-3) / 1e9, 1),
                          "frac": round(total_bytes / (ms * 1e-3) / 1e9 / PEAK_GBS, 4),
+                         "ms_to_half_peak": round(total_bytes / (0.5 * PEAK_GBS * 1e9) * 1e3, 4),
+                         "step_ms_median": round(ms, 4), "step_ms_p90": round(c2["ms_p90"], 4),
+                         "step_ms_mean": round(c2["ms_mean"], 4),
+                         "step_ms_back_to_back_no_flush": round(c2["ms_back_to_back"], 4),
                          "wall_ms_per_step": round(c2["wall_ms_per_step"], 4)},
         "kernels_ms_per_step": {k: round(v[0], 4) for k, v in kern.items()},
         "roofline": roof,

@@ -307,6 +307,17 @@ int gq_batch_plan_create(gq_ctx* ctx, const gq_fragment* frags, int nfrags, cons
     if (f == 0) nacc = g.ap.nacc;
     if (g.ap.nacc != nacc || g.kp.mode != plans[0].kp.mode)
       return set_error(ctx, GQ_ERR_INVALID, "gq_batch_plan_create: fragments must share key and aggregate shapes");
+    // Every fragment's accumulators are initialised and merged with one word
+    // layout (the first fragment's), so the layouts must agree word for word:
+    // an aggregate input that can be NULL in one fragment and not in another
+    // moves the words that follow it.
+    bool same_words = true;
+    for (int w = 0; w < nacc; ++w) same_words &= g.ap.wop[w] == plans[0].ap.wop[w];
+    for (int i = 0; i < g.ap.naggs; ++i)
+      same_words &= g.ap.aggs[i].word == plans[0].ap.aggs[i].word && g.ap.aggs[i].cword == plans[0].ap.aggs[i].cword;
+    if (!same_words)
+      return set_error(ctx, GQ_ERR_INVALID,
+                       "gq_batch_plan_create: fragments must agree on which aggregate inputs can be NULL");
     for (int j = 0; j < spec->nkeys; ++j)
       if (g.kp.bits[j] != plans[0].kp.bits[j] || g.kp.nullable[j] != plans[0].kp.nullable[j])
         return set_error(ctx, GQ_ERR_INVALID, "gq_batch_plan_create: fragments must share key column types");

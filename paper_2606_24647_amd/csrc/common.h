@@ -379,6 +379,19 @@ __device__ __forceinline__ uint64_t opaque_copy(uint64_t x) {
   return x;
 }
 
+// Workgroup barrier that orders LDS accesses only.  __syncthreads() also
+// waits for every global load and store the wave has in flight (its release
+// fence); this one waits for LDS operations (lgkmcnt 0) and leaves global
+// loads in flight across the barrier, so loads issued before a phase that
+// only works in LDS overlap it.  The signal fences keep the compiler from
+// moving memory operations across the barrier.
+__device__ __forceinline__ void lds_barrier() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0); vmcnt and expcnt unconstrained
+  __builtin_amdgcn_s_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
 // Lane helpers (wave64).
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 

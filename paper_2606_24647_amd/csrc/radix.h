@@ -22,10 +22,11 @@ __host__ __device__ __forceinline__ uint64_t region_unhash(uint64_t h) {
   h ^= h >> 33;
   return h ^ kRegionSeed;
 }
-// LDS of the join workgroup: table keys, accumulators and multiplicities.
+// LDS of the join workgroup: table keys, accumulators, multiplicities and the
+// staging words of an output validity bitmap.
 constexpr size_t kRjLdsBytes = 150 * 1024;
 // Build rows per sub-region assumed when the regions are laid out (two
-// accumulator words: a count and one sum).
+// accumulator words: a count and one sum; about the kpr of such a table).
 constexpr int64_t kRjNominalKpr = 3500;
 // Build inputs from this many rows on are partitioned for the radix path.
 constexpr int64_t kRjMinBuild = 1 << 20;

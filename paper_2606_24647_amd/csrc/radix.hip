@@ -34,13 +34,14 @@
 //   k_rj_plan     per region p, the number of sub-regions S_p so that each holds
 //                 at most kpr build rows, and per-XCD work lists of
 //                 (region, sub-region) items
-//   k_rj_join     persistent: a workgroup takes an item (p, s), inserts the build
-//                 keys of region p that fall in sub-region s into an LDS table
-//                 (counting duplicates: a key's build multiplicity weights its
-//                 matches), streams the probe tuples of region p through it,
-//                 accumulating the matches of sub-region s in LDS, and writes
-//                 its matched groups to the output (one atomic per item for the
-//                 output range).
+//   k_rj_join     persistent, one workgroup per CU: a workgroup takes an item
+//                 (p, s), inserts the build keys of region p that fall in
+//                 sub-region s into an LDS table (with their multiplicities),
+//                 streams the probe tuples of region p through it, accumulating
+//                 the matches of sub-region s in LDS (unweighted; a key's build
+//                 multiplicity scales its sums and counts at emission), and
+//                 writes its matched groups to the output (one atomic per item
+//                 for the output range; validity words stored whole).
 // Region p is queued on XCD p % 8 (workgroups are dispatched to XCDs
 // round-robin), so the S_p workgroups that re-read region p's tuples share one
 // L2.  A workgroup whose queue is empty takes items from the other queues, so
@@ -55,7 +56,7 @@ constexpr int kRpBlock = 256;                    // hist workgroup
 constexpr int kRpSBlock = 1024;                  // scatter workgroup
 constexpr int kRpSub = 2048;                     // rows per scatter sub-tile (unit of the staging layout)
 constexpr int kRpRows = kRpSub / kRpSBlock;      // rows per thread per scatter sub-tile
-constexpr int kRpTile = 16384;                   // rows per hist tile
+constexpr int kRpTile = 32768;                   // rows per hist tile
 constexpr int kRpSubs = kRpTile / kRpSub;        // scatter sub-tiles per hist tile
 constexpr int kRpHSub = 2048;                    // rows per hist sub-tile
 constexpr int kRpHRows = kRpHSub / kRpBlock;
@@ -65,7 +66,7 @@ constexpr int kRpMaxStage = 8;                   // distinct input columns stage
 constexpr int kRjBlock = 1024;
 constexpr int kRjPerCu = 1;                      // join workgroups per CU (the LDS table takes the CU)
 constexpr int kRjMaxVals = 2;                    // value words per probe tuple
-constexpr int kRjUnroll = 8;                     // build keys per thread per round in k_rj_join
+constexpr int kRjUnroll = 4;                     // build keys per thread per round in k_rj_join
 constexpr int kRjProbeUnroll = 4;                // probe tuples per thread per round in k_rj_join
 
 __device__ __forceinline__ uint32_t region_of(uint64_t h, int pbits) {
@@ -397,6 +398,7 @@ struct RjJoinArgs {
   int32_t vword[GQ_MAX_AGGS];   // value word of aggregate i in the tuple, -1 if none
   int32_t sums_only;            // every aggregate is COUNT(*) or a SUM of a non-NULL input
   int32_t sum_word[kRjMaxVals]; // then: accumulator word of value word v
+  uint64_t ident[kMaxAcc];      // initial value of every accumulator word (word_identity of its wop)
   const uint64_t* bkey;     // build (key hash, row) pairs grouped by region
   const int64_t* boff;      // P + 1
   const uint64_t* tkey;     // probe tuple key hashes grouped by region
@@ -505,13 +507,14 @@ __device__ __forceinline__ int rj_find_insert(uint64_t* s_keys, int lcap, uint64
   return -1;
 }
 
-// LDS of k_rj_join: keys, accumulators and multiplicities of lcap table slots,
-// the slot of the hash EMPTY (index lcap) and 64 dump slots (one per lane:
-// updates of tuples without a match go there, so the update code has no
-// branches; their multiplicity stays 0).
+// LDS of k_rj_join: keys, accumulators and build multiplicities of lcap table
+// slots, the slot of the hash EMPTY (index lcap) and 64 dump slots (one per
+// lane: updates of tuples without a match go there, so the update code has no
+// branches), then the staging words of one output validity bitmap.
 __host__ __device__ inline int rj_slots(int lcap) { return lcap + 1 + kWave; }
+__host__ __device__ inline int rj_vwords(int lcap) { return (lcap + 1) / 32 + 3; }
 __host__ __device__ inline size_t rj_join_lds(int lcap, int nacc) {
-  return (size_t)rj_slots(lcap) * (8 + 8 * (size_t)nacc + 4);
+  return (size_t)rj_slots(lcap) * (8 + 8 * (size_t)nacc + 4) + 4 * (size_t)rj_vwords(lcap);
 }
 
 __device__ __forceinline__ void rj_write(const OCol& o, int64_t g, int64_t v) {
@@ -523,14 +526,7 @@ __device__ __forceinline__ void rj_write(const OCol& o, int64_t g, int64_t v) {
   }
 }
 
-__device__ __forceinline__ void rj_valid(const OCol& o, int64_t g, bool ok) {
-  if (!o.valid) return;
-  const uint32_t bit = 1u << (g & 31);
-  if (ok) atomicOr(&o.valid[g >> 5], bit);
-  else atomicAnd(&o.valid[g >> 5], ~bit);
-}
-
-constexpr int kRjChunks = 8;  // emission chunks of 1024 slots: lcap + 1 <= 8192
+constexpr int kRjChunks = 8;  // emission chunks of kRjBlock slots: lcap + 1 <= kRjChunks * kRjBlock
 
 // Next work item: queue q's ticket t (already taken) or, once q is used up,
 // tickets from the following queues.  Called by one thread.
@@ -544,59 +540,260 @@ __device__ uint64_t rj_next(const RjJoinArgs& a, const uint32_t* s_qoff, int hom
   return kNoItem;
 }
 
-__global__ __launch_bounds__(kRjBlock) void k_rj_join(const RjJoinArgs a) {
+// One round of probe tuples held in registers: kRjProbeUnroll per thread,
+// NV value words each.
+template <int NV>
+struct RjRound {
+  uint64_t h[kRjProbeUnroll];
+  uint64_t x[kRjProbeUnroll][NV > 0 ? NV : 1];
+  uint32_t nn[kRjProbeUnroll];
+  uint32_t act;
+};
+
+// Issue the loads of the tuples base + u * kRjBlock + tid (u < kRjProbeUnroll)
+// that lie below t1; the others re-read the last tuple (tuple 0 of the
+// buffer when t1 is 0) and are inactive.
+// Straight-line code (NV and NN fixed at compile time), so that every load of
+// the round is in flight before the first is used.
+template <int NV, bool NN>
+__device__ __forceinline__ void rj_load_round(const RjJoinArgs& a, int64_t base, int64_t t1, RjRound<NV>& r) {
+  r.act = 0;
+#pragma unroll
+  for (int u = 0; u < kRjProbeUnroll; ++u) {
+    const int64_t i = base + (int64_t)u * kRjBlock + threadIdx.x;
+    const int64_t ic = i < t1 ? i : (t1 > 0 ? t1 - 1 : 0);
+    const uint64_t* tp = a.tkey + (size_t)ic * (1 + NV);
+    if constexpr (NV == 0) {
+      r.h[u] = tp[0];
+      r.x[u][0] = 0;
+    } else if constexpr (NV == 1) {
+      typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+      const u64x2 tv = *reinterpret_cast<const u64x2*>(tp);
+      r.h[u] = tv.x;
+      r.x[u][0] = tv.y;
+    } else {
+      r.h[u] = tp[0];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) r.x[u][v] = tp[1 + v];
+    }
+    if constexpr (NN) r.nn[u] = a.tnn[ic];
+    else r.nn[u] = 0xffu;
+    if (i < t1) r.act |= 1u << u;
+  }
+}
+
+// Probe one round of tuples in the table and apply their updates.  A tuple
+// adds 1 to its group's row count and its plain (unweighted) inputs to the
+// SUM and COUNT words; the build multiplicity of the key multiplies these at
+// emission (every joined row of a probe tuple carries the same inputs).
+template <int NV>
+__device__ __forceinline__ void rj_probe_round(const RjJoinArgs& a, RjRound<NV>& r, const uint64_t* s_keys,
+                                               uint64_t* s_acc, const uint32_t* s_mult, int L, uint32_t s,
+                                               uint32_t S, uint32_t dump) {
+  uint32_t act = r.act;
+  uint32_t pos[kRjProbeUnroll];
+  int32_t res[kRjProbeUnroll];
+#pragma unroll
+  for (int u = 0; u < kRjProbeUnroll; ++u) {
+    res[u] = -1;
+    pos[u] = rj_bucket0(r.h[u], L);
+    if (subregion_of(r.h[u], a.pbits, S) != s) act &= ~(1u << u);
+    if (((act >> u) & 1u) && r.h[u] == kEmpty) {
+      res[u] = s_mult[L] ? L : -1;
+      act &= ~(1u << u);
+    }
+  }
+  typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+  // First bucket of every tuple, all reads in flight together; it decides
+  // almost every lookup (a hit, or an empty slot: a miss).
+  {
+    u64x2 k01[kRjProbeUnroll], k23[kRjProbeUnroll];
+#pragma unroll
+    for (int u = 0; u < kRjProbeUnroll; ++u) {
+      k01[u] = *reinterpret_cast<const u64x2*>(&s_keys[pos[u]]);
+      k23[u] = *reinterpret_cast<const u64x2*>(&s_keys[pos[u] + 2]);
+    }
+#pragma unroll
+    for (int u = 0; u < kRjProbeUnroll; ++u) {
+      const bool on = (act >> u) & 1u;
+      const uint64_t h = r.h[u];
+      const bool m0 = k01[u].x == h, m1 = k01[u].y == h, m2 = k23[u].x == h, m3 = k23[u].y == h;
+      const bool hit = m0 | m1 | m2 | m3;
+      const bool empty = (k01[u].x == kEmpty) | (k01[u].y == kEmpty) | (k23[u].x == kEmpty) |
+                         (k23[u].y == kEmpty);
+      const int32_t at = (int32_t)pos[u] + (m0 ? 0 : m1 ? 1 : m2 ? 2 : 3);
+      res[u] = on && hit ? at : res[u];
+      if (on && (hit || empty)) act &= ~(1u << u);
+      pos[u] = pos[u] + kRjBucket == (uint32_t)L ? 0u : pos[u] + kRjBucket;
+    }
+  }
+  // The rest walk on, one tuple at a time, reading buckets only for the
+  // lanes still searching.
+#pragma unroll
+  for (int u = 0; u < kRjProbeUnroll; ++u) {
+    for (int it = 1; ((act >> u) & 1u) && it < L / kRjBucket; ++it) {
+      const u64x2 k01 = *reinterpret_cast<const u64x2*>(&s_keys[pos[u]]);
+      const u64x2 k23 = *reinterpret_cast<const u64x2*>(&s_keys[pos[u] + 2]);
+      const uint64_t h = r.h[u];
+      const bool m0 = k01.x == h, m1 = k01.y == h, m2 = k23.x == h, m3 = k23.y == h;
+      const bool hit = m0 | m1 | m2 | m3;
+      const bool empty = (k01.x == kEmpty) | (k01.y == kEmpty) | (k23.x == kEmpty) | (k23.y == kEmpty);
+      if (hit) res[u] = (int32_t)pos[u] + (m0 ? 0 : m1 ? 1 : m2 ? 2 : 3);
+      if (hit || empty) act &= ~(1u << u);
+      pos[u] = pos[u] + kRjBucket == (uint32_t)L ? 0u : pos[u] + kRjBucket;
+    }
+  }
+  uint32_t slot[kRjProbeUnroll];
+#pragma unroll
+  for (int u = 0; u < kRjProbeUnroll; ++u) {
+    slot[u] = res[u] >= 0 ? (uint32_t)res[u] : dump;
+    atomicAdd((unsigned long long*)&s_acc[(size_t)slot[u] * a.nacc], 1ull);
+  }
+  if (a.sums_only) {
+    // Accumulator words at fixed kernel-argument offsets: no per-aggregate
+    // descriptor reads (whose waits would also wait for the updates).
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int word = a.sum_word[v];
+#pragma unroll
+      for (int u = 0; u < kRjProbeUnroll; ++u)
+        atomicAdd((unsigned long long*)&s_acc[(size_t)slot[u] * a.nacc + word], (unsigned long long)r.x[u][v]);
+    }
+    return;
+  }
+  for (int g = 0; g < a.naggs; ++g) {
+    const DAgg& ag = a.ap.aggs[g];
+    const int op = ag.op;
+    if (op == GQ_COUNT_STAR) continue;
+    const int vw = a.vword[g];
+    const int word = ag.word, cword = ag.cword;
+    if (op == GQ_SUM || op == GQ_COUNT) {
+#pragma unroll
+      for (int u = 0; u < kRjProbeUnroll; ++u) {
+        const uint64_t ok = (r.nn[u] >> g) & 1u;
+        const uint64_t x = vw <= 0 ? r.x[u][0] : r.x[u][NV > 1 ? NV - 1 : 0];
+        uint64_t* acc = s_acc + (size_t)slot[u] * a.nacc;
+        atomicAdd((unsigned long long*)&acc[word], (unsigned long long)(op == GQ_SUM ? (ok ? x : 0) : ok));
+        if (cword >= 0) atomicAdd((unsigned long long*)&acc[cword], (unsigned long long)ok);
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < kRjProbeUnroll; ++u) {
+        const bool ok = (r.nn[u] >> g) & 1u;
+        const uint32_t sl = ok ? slot[u] : dump;
+        const uint64_t x = vw <= 0 ? r.x[u][0] : r.x[u][NV > 1 ? NV - 1 : 0];
+        uint64_t* acc = s_acc + (size_t)sl * a.nacc;
+        if (op == GQ_MIN) atomicMin((long long*)&acc[word], (long long)x);
+        else atomicMax((long long*)&acc[word], (long long)x);
+        if (cword >= 0) atomicAdd((unsigned long long*)&acc[cword], (unsigned long long)(ok ? 1 : 0));
+      }
+    }
+  }
+}
+
+// Validity bits of output rows [obase, obase + tot) (clipped to out_cap) of
+// one output column: bit rel of the staging words (rel = row - (obase & ~31))
+// is the bit of row obase - (obase & 31) + rel.  Words wholly inside the range
+// are stored; the first and last words, shared with the neighbouring items'
+// rows, are updated with an atomic AND of the range's bits and an OR.
+__device__ __forceinline__ void rj_store_valid(uint32_t* words, const uint32_t* s_vw, int64_t obase, int64_t tot,
+                                               int64_t out_cap) {
+  int64_t end = obase + tot;
+  if (end > out_cap) end = out_cap;
+  if (end <= obase) return;
+  const int64_t w0 = obase >> 5, w1 = (end - 1) >> 5;
+  for (int64_t w = w0 + threadIdx.x; w <= w1; w += kRjBlock) {
+    const int64_t lo = w * 32 > obase ? w * 32 : obase;
+    const int64_t hi = w * 32 + 32 < end ? w * 32 + 32 : end;
+    const uint32_t mask = (hi - lo == 32) ? ~0u : (((1u << (uint32_t)(hi - lo)) - 1u) << (uint32_t)(lo - w * 32));
+    const uint32_t bits = s_vw[w - w0] & mask;
+    if (mask == ~0u) {
+      words[w] = bits;
+    } else {
+      atomicAnd(&words[w], ~mask);
+      if (bits) atomicOr(&words[w], bits);
+    }
+  }
+}
+
+// Persistent: workgroups (one per CU: the table takes the CU's LDS) take
+// (region, sub-region) items from their XCD's queue.  Per item: the loads of
+// the first build keys and probe tuples are issued, the table is cleared while
+// they are in flight, the build keys of the sub-region are inserted with their
+// multiplicities, the probe tuples streamed through the table in rounds (the
+// next round's loads issued before the current round is probed), and the
+// matched groups written in slot order to one output range per item.
+template <int NV, bool NN>
+__global__ __launch_bounds__(kRjBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_rj_join(const RjJoinArgs a) {
   extern __shared__ __attribute__((aligned(16))) uint8_t s_raw[];
   const int L = a.lcap;
   const int NS = rj_slots(L);
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  constexpr int NW = kRjBlock / kWave;
   const uint32_t dump = (uint32_t)(L + 1 + lane);
   uint64_t* s_keys = reinterpret_cast<uint64_t*>(s_raw);
   uint64_t* s_acc = s_keys + NS;
   uint32_t* s_mult = reinterpret_cast<uint32_t*>(s_acc + (size_t)NS * a.nacc);
+  uint32_t* s_vw = s_mult + NS;
+  const int VW = rj_vwords(L);
   __shared__ uint64_t s_item;
   __shared__ uint32_t s_qoff[kXcds + 1];
-  __shared__ uint32_t s_cc[kRjChunks][kRjBlock / kWave];
+  __shared__ uint32_t s_cc[kRjChunks][NW];
   __shared__ int64_t s_obase;
+  __shared__ int64_t s_tot;
   const int home = (int)(blockIdx.x % kXcds);
   if (threadIdx.x <= kXcds) s_qoff[threadIdx.x] = a.qoff[threadIdx.x];
-  __syncthreads();
+  lds_barrier();
   int qi = 0;
   uint64_t cur = kNoItem;
   if (threadIdx.x == 0) cur = rj_next(a, s_qoff, home, qi, atomicAdd(&a.qticket[home], 1u));
+  const int nchunks = (L + kRjBlock) / kRjBlock;  // chunks covering slots 0..L
   for (;;) {
     if (threadIdx.x == 0) s_item = cur;
-    __syncthreads();
+    lds_barrier();
     const uint64_t item = s_item;
     if (item == kNoItem) break;
     const uint32_t p = item_region(item), s = item_sub(item), S = item_nsub(item);
-    // The next ticket of the current queue, resolved after this item.
     uint32_t tnext = 0;
     if (threadIdx.x == 0 && qi < kXcds) tnext = atomicAdd(&a.qticket[(home + qi) % kXcds], 1u);
 
-    // 1. Clear the table (dump slots included).
+    // 1. Loads of the first build keys and the first probe round, in flight
+    // while the table is cleared.
+    const int64_t b0 = a.boff[p], b1 = a.boff[p + 1];
+    const int64_t t0 = a.toff[p], t1 = a.toff[p + 1];
+    // (Indices past the region re-read its last pair: unconditional loads
+    // stay in flight together.)
+    uint64_t bh[kRjUnroll];
+#pragma unroll
+    for (int u = 0; u < kRjUnroll; ++u) {
+      const int64_t i = b0 + (int64_t)u * kRjBlock + threadIdx.x;
+      bh[u] = a.bkey[2 * (i < b1 ? i : (b1 > 0 ? b1 - 1 : 0))];
+    }
+    RjRound<NV> ra, rb;
+    rj_load_round<NV, NN>(a, t0, t1, ra);
     for (int i = threadIdx.x; i < NS; i += kRjBlock) {
       s_keys[i] = kEmpty;
       s_mult[i] = 0;
     }
     for (int w = 0; w < a.nacc; ++w) {
-      const uint64_t id = word_identity(a.ap.wop[w]);
+      const uint64_t id = a.ident[w];
       for (int i = threadIdx.x; i < NS; i += kRjBlock) s_acc[(size_t)i * a.nacc + w] = id;
     }
-    __syncthreads();
-    // 2. Build key hashes of sub-region s, counting duplicates.
-    const int64_t b0 = a.boff[p], b1 = a.boff[p + 1];
+    lds_barrier();
+    // 2. Build keys of sub-region s, counting duplicates.
     for (int64_t base = b0; base < b1; base += (int64_t)kRjBlock * kRjUnroll) {
-      uint64_t h[kRjUnroll];
+      if (base != b0) {
 #pragma unroll
-      for (int u = 0; u < kRjUnroll; ++u) {
-        const int64_t i = base + (int64_t)u * kRjBlock + threadIdx.x;
-        h[u] = a.bkey[2 * (i < b1 ? i : b1 - 1)];
+        for (int u = 0; u < kRjUnroll; ++u) {
+          const int64_t i = base + (int64_t)u * kRjBlock + threadIdx.x;
+          bh[u] = a.bkey[2 * (i < b1 ? i : b1 - 1)];
+        }
       }
 #pragma unroll
       for (int u = 0; u < kRjUnroll; ++u) {
         const int64_t i = base + (int64_t)u * kRjBlock + threadIdx.x;
-        if (i >= b1 || subregion_of(h[u], a.pbits, S) != s) continue;
-        const int slot = h[u] == kEmpty ? L : rj_find_insert(s_keys, L, h[u]);
+        if (i >= b1 || subregion_of(bh[u], a.pbits, S) != s) continue;
+        const int slot = bh[u] == kEmpty ? L : rj_find_insert(s_keys, L, bh[u]);
         if (slot < 0) {
           atomicOr(a.dev_status, GQ_DEV_TABLE_FULL);
           continue;
@@ -604,131 +801,24 @@ __global__ __launch_bounds__(kRjBlock) void k_rj_join(const RjJoinArgs a) {
         atomicAdd(&s_mult[slot], 1u);
       }
     }
-    __syncthreads();
+    lds_barrier();
     // The next item, resolved while this one is probed.
     if (threadIdx.x == 0) cur = rj_next(a, s_qoff, home, qi, tnext);
-    // 3. Probe tuples of sub-region s.  Per round, every load first, then the
-    // kRjProbeUnroll lookups of a thread advance together one probe step at a time.
-    const int64_t t0 = a.toff[p], t1 = a.toff[p + 1];
-    for (int64_t base = t0; base < t1; base += (int64_t)kRjBlock * kRjProbeUnroll) {
-      uint64_t h[kRjProbeUnroll];
-      uint64_t xv[kRjProbeUnroll][kRjMaxVals];
-      uint32_t nnm[kRjProbeUnroll];
-      uint32_t act = 0;
-#pragma unroll
-      for (int u = 0; u < kRjProbeUnroll; ++u) {
-        const int64_t i = base + (int64_t)u * kRjBlock + threadIdx.x;
-        const int64_t ic = i < t1 ? i : t1 - 1;
-        const uint64_t* tp = a.tkey + (size_t)ic * a.tw;
-        if (a.nv == 1) {
-          typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
-          const u64x2 tv = *reinterpret_cast<const u64x2*>(tp);
-          h[u] = tv.x;
-          xv[u][0] = tv.y;
-          xv[u][kRjMaxVals - 1] = tv.y;
-        } else {
-          h[u] = tp[0];
-#pragma unroll
-          for (int v = 0; v < kRjMaxVals; ++v) xv[u][v] = v < a.nv ? tp[1 + v] : 0;
-        }
-        nnm[u] = a.need_nn ? a.tnn[ic] : 0xffu;
-        if (i < t1) act |= 1u << u;
-      }
-      uint32_t pos[kRjProbeUnroll];
-      int32_t res[kRjProbeUnroll];
-#pragma unroll
-      for (int u = 0; u < kRjProbeUnroll; ++u) {
-        res[u] = -1;
-        pos[u] = rj_bucket0(h[u], L);
-        if (subregion_of(h[u], a.pbits, S) != s) act &= ~(1u << u);
-        if (((act >> u) & 1u) && h[u] == kEmpty) {
-          res[u] = s_mult[L] ? L : -1;
-          act &= ~(1u << u);
-        }
-      }
-      for (int it = 0; act && it < L / kRjBucket; ++it) {
-        typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
-        u64x2 k01[kRjProbeUnroll], k23[kRjProbeUnroll];
-#pragma unroll
-        for (int u = 0; u < kRjProbeUnroll; ++u) {
-          k01[u] = *reinterpret_cast<const u64x2*>(&s_keys[pos[u]]);
-          k23[u] = *reinterpret_cast<const u64x2*>(&s_keys[pos[u] + 2]);
-        }
-#pragma unroll
-        for (int u = 0; u < kRjProbeUnroll; ++u) {
-          const bool on = (act >> u) & 1u;
-          const bool m0 = k01[u].x == h[u], m1 = k01[u].y == h[u], m2 = k23[u].x == h[u], m3 = k23[u].y == h[u];
-          const bool hit = m0 | m1 | m2 | m3;
-          const bool empty = (k01[u].x == kEmpty) | (k01[u].y == kEmpty) | (k23[u].x == kEmpty) |
-                             (k23[u].y == kEmpty);
-          const int32_t at = (int32_t)pos[u] + (m0 ? 0 : m1 ? 1 : m2 ? 2 : 3);
-          res[u] = on && hit ? at : res[u];
-          if (on && (hit || empty)) act &= ~(1u << u);
-          pos[u] = pos[u] + kRjBucket == (uint32_t)L ? 0u : pos[u] + kRjBucket;
-        }
-      }
-      // Updates: tuples without a match go to this lane's dump slot (weight 0).
-      // Every multiplicity is read before the first update, so that the reads
-      // are in flight together.
-      uint32_t slot[kRjProbeUnroll];
-      uint64_t w[kRjProbeUnroll];
-#pragma unroll
-      for (int u = 0; u < kRjProbeUnroll; ++u) {
-        slot[u] = res[u] >= 0 ? (uint32_t)res[u] : dump;
-        w[u] = s_mult[slot[u]];
-      }
-#pragma unroll
-      for (int u = 0; u < kRjProbeUnroll; ++u)
-        atomicAdd((unsigned long long*)&s_acc[(size_t)slot[u] * a.nacc], (unsigned long long)w[u]);
-      if (a.sums_only) {
-        // Accumulator words at fixed kernel-argument offsets: no per-aggregate
-        // descriptor reads (whose waits would also wait for the updates).
-#pragma unroll
-        for (int v = 0; v < kRjMaxVals; ++v) {
-          if (v >= a.nv) break;
-          const int word = a.sum_word[v];
-#pragma unroll
-          for (int u = 0; u < kRjProbeUnroll; ++u) {
-            const uint64_t x = v == 0 ? xv[u][0] : xv[u][kRjMaxVals - 1];
-            atomicAdd((unsigned long long*)&s_acc[(size_t)slot[u] * a.nacc + word], (unsigned long long)(x * w[u]));
-          }
-        }
-        continue;
-      }
-      for (int g = 0; g < a.naggs; ++g) {
-        const DAgg& ag = a.ap.aggs[g];
-        const int op = ag.op;
-        if (op == GQ_COUNT_STAR) continue;
-        const int vw = a.vword[g];
-        const int word = ag.word, cword = ag.cword;
-        if (op == GQ_SUM || op == GQ_COUNT) {
-#pragma unroll
-          for (int u = 0; u < kRjProbeUnroll; ++u) {
-            const uint64_t wk = ((nnm[u] >> g) & 1u) ? w[u] : 0;
-            const uint64_t x = vw == 0 ? xv[u][0] : xv[u][kRjMaxVals - 1];
-            uint64_t* acc = s_acc + (size_t)slot[u] * a.nacc;
-            atomicAdd((unsigned long long*)&acc[word], (unsigned long long)(op == GQ_SUM ? x * wk : wk));
-            if (cword >= 0) atomicAdd((unsigned long long*)&acc[cword], (unsigned long long)wk);
-          }
-        } else {
-#pragma unroll
-          for (int u = 0; u < kRjProbeUnroll; ++u) {
-            const bool ok = (nnm[u] >> g) & 1u;
-            const uint32_t sl = ok ? slot[u] : dump;
-            const uint64_t x = vw == 0 ? xv[u][0] : xv[u][kRjMaxVals - 1];
-            uint64_t* acc = s_acc + (size_t)sl * a.nacc;
-            if (op == GQ_MIN) atomicMin((long long*)&acc[word], (long long)x);
-            else atomicMax((long long*)&acc[word], (long long)x);
-            if (cword >= 0) atomicAdd((unsigned long long*)&acc[cword], (unsigned long long)(ok ? w[u] : 0));
-          }
-        }
-      }
+    // 3. Probe rounds, two register sets alternating: the loads of the next
+    // round are in flight while the current one is probed.
+    constexpr int64_t R = (int64_t)kRjBlock * kRjProbeUnroll;
+    for (int64_t base = t0; base < t1; base += 2 * R) {
+      if (base + R < t1) rj_load_round<NV, NN>(a, base + R, t1, rb);
+      else rb.act = 0;
+      rj_probe_round<NV>(a, ra, s_keys, s_acc, s_mult, L, s, S, dump);
+      if (base + 2 * R < t1) rj_load_round<NV, NN>(a, base + 2 * R, t1, ra);
+      else ra.act = 0;
+      if (base + R < t1) rj_probe_round<NV>(a, rb, s_keys, s_acc, s_mult, L, s, S, dump);
     }
-    __syncthreads();
-    // 4. Matched groups (count word non-zero) to the output, in slot order:
-    // per chunk of 1024 slots the wave counts, one output range for the item.
+    lds_barrier();
+    // 4. Matched groups (row count non-zero) to the output, in slot order:
+    // per chunk of kRjBlock slots the wave counts, one output range per item.
     uint32_t occm = 0;
-    const int nchunks = (L + kRjBlock) / kRjBlock;  // chunks covering slots 0..L
     for (int c = 0; c < nchunks; ++c) {
       const int i = c * kRjBlock + threadIdx.x;
       const bool occ = i <= L && s_acc[(size_t)i * a.nacc] != 0;
@@ -736,20 +826,23 @@ __global__ __launch_bounds__(kRjBlock) void k_rj_join(const RjJoinArgs a) {
       if (occ) occm |= 1u << c;
       if (lane == 0) s_cc[c][wave] = (uint32_t)__popcll(m);
     }
-    __syncthreads();
+    lds_barrier();
     if (threadIdx.x == 0) {
       uint32_t tot = 0;
       for (int c = 0; c < nchunks; ++c)
-        for (int w = 0; w < kRjBlock / kWave; ++w) tot += s_cc[c][w];
+        for (int w = 0; w < NW; ++w) tot += s_cc[c][w];
       const int64_t base = tot ? (int64_t)atomicAdd((unsigned long long*)a.d_count, (unsigned long long)tot) : 0;
       if (tot && base + tot > a.out_cap) atomicOr(a.dev_status, GQ_DEV_CAPACITY);
       s_obase = base;
+      s_tot = tot;
     }
-    __syncthreads();
-    int64_t run = s_obase;
+    lds_barrier();
+    const int64_t obase = s_obase, otot = s_tot;
+    int64_t run = 0;
     for (int c = 0; c < nchunks; ++c) {
       uint32_t wpre = 0, ctot = 0;
-      for (int w = 0; w < kRjBlock / kWave; ++w) {
+#pragma unroll
+      for (int w = 0; w < NW; ++w) {
         const uint32_t x = s_cc[c][w];
         wpre += w < wave ? x : 0;
         ctot += x;
@@ -758,26 +851,53 @@ __global__ __launch_bounds__(kRjBlock) void k_rj_join(const RjJoinArgs a) {
       const bool occ = (occm >> c) & 1u;
       const uint64_t m = ballot(occ);
       if (occ) {
-        const int64_t g = run + wpre + rank_in(m);
+        const int64_t rel = run + wpre + rank_in(m);
+        const int64_t g = obase + rel;
+        const uint64_t mult = s_mult[i];
+        s_mult[i] = (uint32_t)rel;  // the slot's output row, for the validity bits below
         if (g < a.out_cap) {
           // Slot L holds the key whose region hash is all ones.
           const uint64_t key = region_unhash(s_keys[i]);
           rj_write(a.out[0], g, (int64_t)key);
-          rj_valid(a.out[0], g, true);
           if (a.sorted) reinterpret_cast<uint64_t*>(a.sortkey.data)[g] = key ^ (1ull << 63);
           const uint64_t* acc = s_acc + (size_t)i * a.nacc;
           for (int j = 0; j < a.naggs; ++j) {
             const DAgg& ag = a.ap.aggs[j];
             int64_t v = (int64_t)acc[ag.word];
+            if (ag.op == GQ_SUM || ag.op == GQ_COUNT || ag.op == GQ_COUNT_STAR) v = (int64_t)((uint64_t)v * mult);
             bool ok = true;
             if ((ag.op == GQ_SUM || ag.op == GQ_MIN || ag.op == GQ_MAX) && ag.cword >= 0) ok = acc[ag.cword] != 0;
             if (!ok) v = 0;
             rj_write(a.out[1 + j], g, v);
-            rj_valid(a.out[1 + j], g, ok);
           }
         }
       }
       run += ctot;
+    }
+    // 5. Validity bitmaps of the nullable output columns: the item's bits are
+    // gathered in LDS, then stored word by word.
+    const int64_t shift = obase & 31;
+    for (int oc = 0; oc <= a.naggs; ++oc) {
+      if (!a.out[oc].valid || otot == 0) continue;
+      const int aop = oc ? a.ap.aggs[oc - 1].op : GQ_COUNT_STAR;
+      const int cword = oc ? a.ap.aggs[oc - 1].cword : -1;
+      const bool maybe_null = (aop == GQ_SUM || aop == GQ_MIN || aop == GQ_MAX) && cword >= 0;
+      lds_barrier();
+      if (maybe_null) {
+        for (int w = threadIdx.x; w < VW; w += kRjBlock) s_vw[w] = 0;
+        lds_barrier();
+        for (int c = 0; c < nchunks; ++c) {
+          const int i = c * kRjBlock + threadIdx.x;
+          if (!((occm >> c) & 1u)) continue;
+          if (s_acc[(size_t)i * a.nacc + cword] == 0) continue;
+          const int64_t b = shift + (int64_t)s_mult[i];
+          atomicOr(&s_vw[b >> 5], 1u << (b & 31));
+        }
+      } else {
+        for (int w = threadIdx.x; w < VW; w += kRjBlock) s_vw[w] = ~0u;
+      }
+      lds_barrier();
+      rj_store_valid(a.out[oc].valid, s_vw, obase, otot, a.out_cap);
     }
   }
 }
@@ -948,7 +1068,9 @@ int rj_lcap(int nacc) {
   const size_t per = 8 + 8 * (size_t)nacc + 4;
   int l = (int)(kRjLdsBytes / per) - 1 - kWave;
   if (l > kRjChunks * kRjBlock - 1) l = kRjChunks * kRjBlock - 1;
-  return l & ~(kRjBucket - 1);  // whole buckets
+  l &= ~(kRjBucket - 1);  // whole buckets
+  while (l > 0 && rj_join_lds(l, nacc) > kRjLdsBytes) l -= kRjBucket;
+  return l;
 }
 
 int rj_kpr(int lcap) { return (int)((int64_t)lcap * 13 / 20); }  // load factor 0.65
@@ -994,6 +1116,7 @@ int rj_groupjoin(gq_ctx* ctx, const gq_batch* in, int32_t probe_key, const gq_pr
   j.nv = r.nv;
   j.need_nn = r.need_nn;
   j.ap = ap;
+  for (int w = 0; w < ap.nacc; ++w) j.ident[w] = word_identity(ap.wop[w]);
   j.sums_only = 1;
   for (int i = 0; i < ap.naggs; ++i) {
     const DAgg& ag = ap.aggs[i];
@@ -1028,8 +1151,14 @@ int rj_groupjoin(gq_ctx* ctx, const gq_batch* in, int32_t probe_key, const gq_pr
     return set_error(ctx, GQ_ERR_UNSUPPORTED, "radix join: device LDS per workgroup too small");
   int dev_cus = 256;
   (void)hipDeviceGetAttribute(&dev_cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
-  GQ_LAUNCH(ctx, "rj_join", k_rj_join, dim3((unsigned)(dev_cus * kRjPerCu)), dim3(kRjBlock), rj_join_lds(j.lcap, j.nacc), stream,
-            j);
+  const dim3 jgrid((unsigned)(dev_cus * kRjPerCu));
+  const size_t jlds = rj_join_lds(j.lcap, j.nacc);
+  if (j.nv == 0 && !j.need_nn) GQ_LAUNCH(ctx, "rj_join", (k_rj_join<0, false>), jgrid, dim3(kRjBlock), jlds, stream, j);
+  else if (j.nv == 0) GQ_LAUNCH(ctx, "rj_join", (k_rj_join<0, true>), jgrid, dim3(kRjBlock), jlds, stream, j);
+  else if (j.nv == 1 && !j.need_nn) GQ_LAUNCH(ctx, "rj_join", (k_rj_join<1, false>), jgrid, dim3(kRjBlock), jlds, stream, j);
+  else if (j.nv == 1) GQ_LAUNCH(ctx, "rj_join", (k_rj_join<1, true>), jgrid, dim3(kRjBlock), jlds, stream, j);
+  else if (!j.need_nn) GQ_LAUNCH(ctx, "rj_join", (k_rj_join<2, false>), jgrid, dim3(kRjBlock), jlds, stream, j);
+  else GQ_LAUNCH(ctx, "rj_join", (k_rj_join<2, true>), jgrid, dim3(kRjBlock), jlds, stream, j);
   GQ_LAUNCH_CHECK(ctx);
   return GQ_OK;
 }

@@ -103,6 +103,26 @@ def test_batch_rejects_mismatched_shapes(gq, ctx):
         gq.BatchPlan(ctx, [(a, [], 5), (b, [], 5)], [4], AGGS)
 
 
+def test_batch_rejects_mismatched_nullable_inputs(gq, ctx):
+    # SUM(qty), MIN(price): qty nullable in fragment 0 only, price in fragment 1
+    # only; the accumulator words of the two fragments would not line up.
+    aggs = [("sum", [("col", 0)]), ("min", [("col", 1)]), ("count*",)]
+    t0 = dg.fragment_c4(0, 200, 5)
+    t1 = dg.fragment_c4(1, 200, 5)
+    t0.cols[0].valid = np.arange(200) % 3 != 0
+    t1.cols[1].valid = np.arange(200) % 5 != 0
+    a, b = gq.to_device(t0), gq.to_device(t1)
+    with pytest.raises(gq.GqError):
+        gq.BatchPlan(ctx, [(a, [], 5), (b, [], 5)], [4], aggs)
+    # The same nullability in every fragment is accepted and matches the oracle.
+    t1.cols[0].valid = np.arange(200) % 7 != 0
+    t0.cols[1].valid = np.arange(200) % 2 != 0
+    a, b = gq.to_device(t0), gq.to_device(t1)
+    plan = gq.BatchPlan(ctx, [(a, [], 5), (b, [], 5)], [4], aggs)
+    _check_plan(gq, plan, [t0, t1], [4], [[], []], aggs)
+    plan.free()
+
+
 # Fragments expecting at least radix_min_groups groups are partitioned by key
 # hash and aggregated region by region in LDS; these cases force that path.
 
