@@ -258,7 +258,11 @@ typedef struct gq_join_opts {
  * enqueued on another (the build -> probe hand-over of Section 3 is the only
  * synchronisation); the build input must stay unchanged until the build's work
  * has run.  Its capacity is sized on the device from the number of passing
- * rows. */
+ * rows.  A table over at least 2^20 build rows is stored partitioned; the
+ * first call that needs its probe index (gq_join_probe, or a pipeline that
+ * does not take the radix group-join) builds the index on its own stream and
+ * re-records the table's event there, so every later reader, on any stream,
+ * is ordered after the index build too. */
 int gq_join_build(gq_ctx* ctx, const gq_batch* build, const int32_t* keys, int nkeys,
                   const gq_pred* preds, int npreds, const gq_join_opts* opts,
                   hipStream_t stream, gq_join_table** out);
@@ -288,8 +292,8 @@ int gq_gather(gq_ctx* ctx, const gq_batch* in, const int32_t* cols, int ncols,
               const int32_t* idx, int64_t n, gq_batch* out, hipStream_t stream);
 
 /* ---- hash group-by ------------------------------------------------------------
- * SQL GROUP BY over the rows that pass `preds` (the Single aggregation mode of
- * Section 3.2).  Up to GQ_MAX_KEYS key columns whose combined width plus one
+ * SQL GROUP BY over the rows that pass `preds` (by default the Single
+ * aggregation mode of Section 3.2; see gq_agg_mode).  Up to GQ_MAX_KEYS key columns whose combined width plus one
  * NULL flag bit per nullable column fits 64 bits, or one int64 key column of
  * any nullability.  NULL keys form one group.  nkeys = 0 gives one global row,
  * also for an empty input (COUNT = 0, SUM NULL).
@@ -307,6 +311,27 @@ typedef enum gq_strategy {
   GQ_STRATEGY_GLOBAL = 2 /* one table in HBM, device-scope atomics */
 } gq_strategy;
 
+/* Aggregation modes (Section 3.2: the aggregation operator runs Single,
+ * Partial, Intermediate or Final, so that one aggregation can be split across
+ * batches and exchange stages).  A partial state of SUM, COUNT(*), COUNT, MIN
+ * and MAX is one int64 value with validity, the aggregate of the rows seen so
+ * far (SUM, MIN, MAX NULL when no non-NULL input was seen), so:
+ *  SINGLE, PARTIAL      raw rows in, predicates apply; out: values (= states)
+ *  INTERMEDIATE, FINAL  state rows in (key columns, then one state column per
+ *                       aggregate): aggs[i] names aggregate i's state column
+ *                       with one GQ_F_COL factor and keeps its original op;
+ *                       SUM, COUNT(*) and COUNT states are merged by SUM, MIN
+ *                       and MAX by MIN and MAX.  No predicates.
+ * For these aggregates Partial equals Single and Intermediate equals Final;
+ * they differ in the streaming object below, where Partial and Intermediate
+ * may emit before the input ends. */
+typedef enum gq_agg_mode {
+  GQ_MODE_SINGLE = 0,
+  GQ_MODE_PARTIAL = 1,
+  GQ_MODE_INTERMEDIATE = 2,
+  GQ_MODE_FINAL = 3
+} gq_agg_mode;
+
 typedef struct gq_groupby_opts {
   float load_factor;       /* 0 = 0.5 */
   int32_t strategy;        /* gq_strategy */
@@ -314,12 +339,146 @@ typedef struct gq_groupby_opts {
   int32_t block_size;      /* 0 = library choice; else 256 or 512 */
   int64_t expected_groups; /* sizing hint; 0 = number of input rows.  Fewer
                               slots than groups raises GQ_DEV_TABLE_FULL. */
+  int32_t mode;            /* gq_agg_mode; 0 = GQ_MODE_SINGLE */
+  int32_t reserved;
 } gq_groupby_opts;
 
 int gq_groupby_agg(gq_ctx* ctx, const gq_batch* in, const int32_t* keys, int nkeys,
                    const gq_pred* preds, int npreds, const gq_agg* aggs, int naggs,
                    const gq_groupby_opts* opts, gq_batch* out, int64_t* d_groups,
                    hipStream_t stream);
+
+/* Late materialisation (Section 2.3): group-by over the inner join of the rows
+ * of `probe` passing probe_preds with the table's build rows, computed as the
+ * paper's late-materialising join does it: the join on the key columns alone
+ * gives (probe row, build row) gather maps, the columns the group-by needs are
+ * gathered through them from either side, then grouped.  Column c of the
+ * joined rows is probe column c for c < probe->ncols, else column
+ * c - probe->ncols of `build`, the batch the table was built from (it must
+ * still be valid).  group_keys and aggregate factor columns index joined
+ * columns.  pair_capacity bounds the joined rows (0 = probe->nrows, enough
+ * when the build keys are unique); more raise GQ_DEV_CAPACITY and only the
+ * first pair_capacity are grouped.  Output as for gq_groupby_agg; opts.mode
+ * must be single or partial.  At most 16 joined columns. */
+int gq_join_groupby(gq_ctx* ctx, const gq_join_table* table, const gq_batch* build, const gq_batch* probe,
+                    const int32_t* probe_keys, int nprobe_keys, const gq_pred* probe_preds, int nprobe_preds,
+                    const int32_t* group_keys, int ngroup_keys, const gq_agg* aggs, int naggs,
+                    const gq_groupby_opts* opts, int64_t pair_capacity, gq_batch* out, int64_t* d_groups,
+                    hipStream_t stream);
+
+/* ---- expression programs ------------------------------------------------------
+ * An integer expression over the columns of a batch, evaluated for every row
+ * by one kernel for the whole expression (Section 3.2: fused expression
+ * evaluation, as cuDF's AST compute_column, rather than one kernel per
+ * operation).  A program is a list of instructions in postfix order;
+ * instruction i produces value i from earlier values (operand indices a, b, c
+ * below i); the program's result is its last value.  Arithmetic wraps modulo
+ * 2^64.  A NULL operand makes ADD, SUB, MUL, NEG and the comparisons NULL;
+ * CASE takes value b where value a is non-NULL and non-zero, else value c
+ * (SQL CASE WHEN ... THEN ... ELSE ... END). */
+typedef enum gq_expr_op {
+  GQ_E_COL = 1,   /* column a, sign-extended to int64, NULL where its bitmap says so */
+  GQ_E_CONST = 2, /* the constant k */
+  GQ_E_ADD = 3,   /* a + b */
+  GQ_E_SUB = 4,   /* a - b */
+  GQ_E_MUL = 5,   /* a * b */
+  GQ_E_NEG = 6,   /* -a */
+  GQ_E_LT = 7,    /* a < b: 1 or 0 */
+  GQ_E_LE = 8,
+  GQ_E_EQ = 9,
+  GQ_E_NE = 10,
+  GQ_E_GT = 11,
+  GQ_E_GE = 12,
+  GQ_E_CASE = 13  /* a (non-NULL, non-zero) ? b : c */
+} gq_expr_op;
+
+typedef struct gq_expr_instr {
+  int32_t op;
+  int32_t a;
+  int32_t b;
+  int32_t c;
+  int64_t k;
+} gq_expr_instr;
+
+#define GQ_MAX_EXPR 32  /* instructions per program */
+
+typedef struct gq_expr {
+  int32_t ninstr;
+  int32_t reserved;
+  const gq_expr_instr* instr;  /* host array, read during the call */
+} gq_expr;
+
+/* out: int64 column of capacity >= in->nrows; its validity bitmap, when
+ * present, receives the result's NULLs. */
+int gq_compute_column(gq_ctx* ctx, const gq_batch* in, const gq_expr* expr, gq_column* out, hipStream_t stream);
+
+/* gq_filter whose conjunction also holds every expression in `exprs` (a row
+ * passes an expression that is non-NULL and non-zero). */
+int gq_filter_expr(gq_ctx* ctx, const gq_batch* in, const gq_pred* preds, int npreds, const gq_expr* exprs,
+                   int nexprs, const int32_t* proj, int nproj, gq_batch* out, int64_t* d_count, hipStream_t stream);
+
+/* gq_groupby_agg over the rows passing preds and every expression in `exprs`,
+ * where aggregate i is agg_ops[i] (SUM, COUNT(*), COUNT, MIN, MAX) over the
+ * expression agg_exprs[i] (ignored for COUNT(*)). */
+int gq_groupby_expr(gq_ctx* ctx, const gq_batch* in, const int32_t* keys, int nkeys, const gq_pred* preds,
+                    int npreds, const gq_expr* exprs, int nexprs, const int32_t* agg_ops, const gq_expr* agg_exprs,
+                    int naggs, const gq_groupby_opts* opts, gq_batch* out, int64_t* d_groups, hipStream_t stream);
+
+/* ---- ORDER BY / top-k -------------------------------------------------------------
+ * Row ids of `in` in ORDER BY order (Section 3.1 lists OrderBy among the
+ * operators moved to the GPU): keys compared in turn, each ascending unless
+ * desc[j] != 0, NULLs first where nulls_first[j] != 0 else last; ties keep
+ * input order (stable).  With limit >= 0 only the first min(limit, nrows) ids
+ * are written (top-k).  out_rows: device int32[min(limit, nrows)] (all rows
+ * when limit < 0).  desc and nulls_first may be NULL (all 0). */
+int gq_order_by(gq_ctx* ctx, const gq_batch* in, const int32_t* keys, int nkeys, const int32_t* desc,
+                const int32_t* nulls_first, int64_t limit, int32_t* out_rows, hipStream_t stream);
+
+/* ---- streaming aggregation ------------------------------------------------------
+ * One aggregation over a sequence of batches (Section 3.2: a streaming
+ * group-by that holds its result across input batches and, in the Partial and
+ * Intermediate modes, emits it once it reaches a size threshold).  The paper's
+ * operator concatenates each batch's result with the held one and aggregates
+ * the concatenation again; here the held groups stay in one HBM hash table
+ * that every batch is aggregated into directly, which gives the same result
+ * without re-reading the held groups per batch.
+ *  push    aggregate the batch's rows (Single, Partial: raw rows passing
+ *          preds; Intermediate, Final: state rows, no preds) into the held
+ *          groups.  In the Partial and Intermediate modes with emit_groups > 0,
+ *          once the held groups number at least emit_groups they are written
+ *          to `out` and the stream starts over; *d_emitted (device int64)
+ *          receives the number of groups written (0: nothing emitted).
+ *  finish  write the held groups to `out` and start over.  d_groups is device
+ *          int64[2]: [0] groups written, [1] 1 if a result was emitted, 0 if no
+ *          batch was pushed since the last emission (then nothing is written).
+ * Outputs as for gq_groupby_agg (slot order), capacity >= max_groups (one row
+ * for nkeys = 0).  Every batch has the same key column types and the
+ * aggregates read the same columns (by index) of every batch.  Decisions are
+ * taken on the device: no call blocks.  Groups beyond the table raise
+ * GQ_DEV_TABLE_FULL. */
+typedef struct gq_agg_stream gq_agg_stream;
+
+typedef struct gq_agg_stream_spec {
+  int32_t mode;               /* gq_agg_mode */
+  int32_t nkeys;              /* key columns (0: one global group) */
+  const int32_t* keys;        /* key column indices of every batch */
+  const int32_t* key_nullable;/* nkeys flags: key j may be NULL in some batch
+                                 (a key column with a bitmap must be flagged) */
+  const gq_agg* aggs;         /* as for gq_groupby_agg in this mode */
+  int32_t naggs;
+  int32_t reserved;
+  int64_t max_groups;         /* most groups the stream holds at once; sizes the table */
+  int64_t emit_groups;        /* Partial / Intermediate: emit once this many groups are held; 0 = never early */
+  float load_factor;          /* 0 = 0.5 */
+  int32_t reserved2;
+} gq_agg_stream_spec;
+
+int gq_agg_stream_create(gq_ctx* ctx, const gq_agg_stream_spec* spec, hipStream_t stream, gq_agg_stream** out);
+int gq_agg_stream_push(gq_agg_stream* s, const gq_batch* in, const gq_pred* preds, int npreds, gq_batch* out,
+                       int64_t* d_emitted, hipStream_t stream);
+int gq_agg_stream_finish(gq_agg_stream* s, gq_batch* out, int64_t* d_groups, hipStream_t stream);
+/* Stream-ordered release. */
+int gq_agg_stream_free(gq_agg_stream* s, hipStream_t stream);
 
 /* ---- shared scan ------------------------------------------------------------------
  * Up to GQ_MAX_SHARED filter + group-by queries over the same batch in one
@@ -370,7 +529,10 @@ int gq_pipeline(gq_ctx* ctx, const gq_plan* plan, const gq_batch* in, gq_batch* 
  * of small vectors degrade GPU libraries until merged.)  Every fragment has the
  * same key and aggregate shape (spec) and its own columns, predicate bounds,
  * output and cardinality hint.  Results equal one gq_groupby_agg call per
- * fragment (output in slot order). */
+ * fragment (output in slot order).  The fragments' key columns must have the
+ * same types and nullability, and every aggregate input column must be
+ * nullable (has a validity bitmap) in all fragments or in none; otherwise
+ * plan creation returns GQ_ERR_INVALID. */
 typedef struct gq_fragment {
   gq_batch in;              /* the fragment's rows (device columns) */
   const gq_pred* preds;     /* host array, read during plan creation */

@@ -39,7 +39,17 @@ struct GbArgs {
   int32_t nrep;       // LDS strategy: replicas of the HBM table the blocks merge into
   int32_t pad_rep;
   int64_t rep_slots;  // slots per replica (cap + 2)
+  int64_t* d_inserted;  // if set: counts the groups inserted into the HBM table (streaming aggregation)
+  const int64_t* d_nrows;  // if set: rows at or past *d_nrows (a device count) are not read
 };
+
+// Rows of a group-by input: n, or fewer when a device-side count bounds it.
+template <class GA>
+__device__ __forceinline__ int64_t rows_of(const GA& a) {
+  if (!a.d_nrows) return a.n;
+  const int64_t d = *a.d_nrows;
+  return d < a.n ? d : a.n;
+}
 
 template <int ITEMS, class C>
 __device__ __forceinline__ void load_col(const C& c, int64_t r0, int64_t n, int64_t (&v)[ITEMS]) {
@@ -231,6 +241,7 @@ __device__ __forceinline__ uint64_t* global_acc(const GA& a, uint64_t key, int s
       atomicOr(a.dev_status, GQ_DEV_TABLE_FULL);
       return nullptr;
     }
+    if (ins && a.d_inserted) atomicAdd((unsigned long long*)a.d_inserted, 1ull);
   }
   return a.acc + (uint64_t)s * a.ap.nacc;
 }
@@ -277,8 +288,28 @@ __device__ __forceinline__ int lds_find_insert(uint64_t* s_tab, int lcap, int sw
 
 // Host-side plan builders (groupby.hip), shared with the batched path.
 int make_preds(gq_ctx* ctx, GbArgs& a, const gq_batch* in, const gq_pred* preds, int npreds);
-int make_key_plan(gq_ctx* ctx, KeyPlan& kp, const gq_batch* in, const int32_t* keys, int nk);
-int make_agg_plan(gq_ctx* ctx, AggPlan& ap, const gq_batch* in, const gq_agg* aggs, int na);
+// force_nullable (nk flags): the key packing reserves a NULL bit exactly for
+// the flagged columns whatever this batch's bitmaps say (a key column with a
+// bitmap must be flagged), so that batches of a stream pack keys alike.
+int make_key_plan(gq_ctx* ctx, KeyPlan& kp, const gq_batch* in, const int32_t* keys, int nk,
+                  const int32_t* force_nullable = nullptr);
+// all_nullable: every SUM/MIN/MAX gets a non-NULL count word, so that the
+// accumulator layout does not depend on which input columns have bitmaps.
+int make_agg_plan(gq_ctx* ctx, AggPlan& ap, const gq_batch* in, const gq_agg* aggs, int na,
+                  bool all_nullable = false);
+// Aggregates that merge partial states (the Intermediate and Final modes of
+// Section 3.2): each of `aggs` names its state column with one GQ_F_COL
+// factor; SUM, COUNT(*) and COUNT states merge by SUM, MIN and MAX by MIN and
+// MAX.  Writes na aggregates to merged.
+int merge_aggs(gq_ctx* ctx, const gq_agg* aggs, int na, int ncols, gq_agg* merged);
+// gq_groupby_agg over the first min(in->nrows, *d_nrows) rows of `in` (the
+// row count known only on the device), no predicates and no join.
+int groupby_rows(gq_ctx* ctx, const gq_batch* in, const int64_t* d_nrows, const int32_t* keys, int nkeys,
+                 const gq_agg* aggs, int naggs, const gq_groupby_opts* opts, gq_batch* out, int64_t* d_groups,
+                 hipStream_t stream);
+// Aggregate the rows of a.n (no join) into the HBM table a.keys / a.acc
+// (strategy GQ_STRATEGY_LDS or GQ_STRATEGY_GLOBAL); the table is not reset.
+int aggregate_into(gq_ctx* ctx, GbArgs& a, int strategy, hipStream_t stream);
 // Output validation and table compaction (groupby.hip).
 int check_outputs(gq_ctx* ctx, int nk_out, int na, gq_batch* out, CompactArgs& ca, const int* key_types);
 int compact_launch(gq_ctx* ctx, CompactArgs& ca, int64_t* d_groups, hipStream_t stream);

@@ -64,20 +64,21 @@ __global__ void k_gj_init(JoinRef j, AggPlan ap) {
 template <int BLOCK, int ITEMS, bool JOIN>
 __global__ __launch_bounds__(BLOCK) void k_gb_global(const GbArgs a) {
   constexpr int TILE = BLOCK * ITEMS;
+  const int64_t n = rows_of(a);
   const int64_t r0 = (int64_t)blockIdx.x * TILE + (int64_t)threadIdx.x * ITEMS;
-  uint32_t keep = eval_preds<ITEMS>(a, r0, a.n);
+  uint32_t keep = eval_preds<ITEMS>(a, r0, n);
   uint32_t w[ITEMS];
 #pragma unroll
   for (int k = 0; k < ITEMS; ++k) w[k] = 1;
   if (JOIN) {
     int64_t js[ITEMS];
-    join_lookup<ITEMS>(a.join, r0, a.n, keep, js);
+    join_lookup<ITEMS>(a.join, r0, n, keep, js);
     join_weights<ITEMS>(a.join, keep, js, w);
   }
   if (!keep) return;
   uint64_t key[ITEMS];
   uint8_t special[ITEMS];
-  make_keys<ITEMS>(a.kp, r0, a.n, key, special);
+  make_keys<ITEMS>(a.kp, r0, n, key, special);
   int loff[ITEMS];
   uint64_t* gsp[ITEMS];
   static_for<0, ITEMS>([&](auto kk) __attribute__((always_inline)) {
@@ -89,7 +90,7 @@ __global__ __launch_bounds__(BLOCK) void k_gb_global(const GbArgs a) {
       if (!gsp[k]) keep &= ~(1u << k);
     }
   });
-  apply_rows<ITEMS>(a.ap, r0, a.n, keep, w, nullptr, loff, gsp);
+  apply_rows<ITEMS>(a.ap, r0, n, keep, w, nullptr, loff, gsp);
 }
 
 template <int BLOCK, int ITEMS, bool JOIN>
@@ -104,21 +105,22 @@ __global__ __launch_bounds__(BLOCK) void k_gb_lds(const GbArgs a) {
   }
   __syncthreads();
 
+  const int64_t n = rows_of(a);
   for (int64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
     const int64_t r0 = tile * TILE + (int64_t)threadIdx.x * ITEMS;
-    uint32_t keep = eval_preds<ITEMS>(a, r0, a.n);
+    uint32_t keep = eval_preds<ITEMS>(a, r0, n);
     uint32_t w[ITEMS];
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) w[k] = 1;
     if (JOIN) {
       int64_t js[ITEMS];
-      join_lookup<ITEMS>(a.join, r0, a.n, keep, js);
+      join_lookup<ITEMS>(a.join, r0, n, keep, js);
       join_weights<ITEMS>(a.join, keep, js, w);
     }
     if (!keep) continue;
     uint64_t key[ITEMS];
     uint8_t special[ITEMS];
-    make_keys<ITEMS>(a.kp, r0, a.n, key, special);
+    make_keys<ITEMS>(a.kp, r0, n, key, special);
     int loff[ITEMS];
     uint64_t* gsp[ITEMS];
     static_for<0, ITEMS>([&](auto kk) __attribute__((always_inline)) {
@@ -132,7 +134,7 @@ __global__ __launch_bounds__(BLOCK) void k_gb_lds(const GbArgs a) {
         if (!gsp[k]) keep &= ~(1u << k);
       }
     });
-    apply_rows<ITEMS>(a.ap, r0, a.n, keep, w, s_tab, loff, gsp);
+    apply_rows<ITEMS>(a.ap, r0, n, keep, w, s_tab, loff, gsp);
   }
   __syncthreads();
   // Block b merges into replica b % nrep of the HBM table (device-wide
@@ -265,6 +267,7 @@ __global__ __launch_bounds__(BLOCK) void k_compact(const CompactArgs a) {
   __shared__ uint8_t s_vbyte[TILE];
   __shared__ uint64_t s_slot[TILE];   // the tile's occupied slots in output order
 
+  if (a.gate && *a.gate == 0) return;  // conditional compaction (streaming aggregation): nothing to emit
   if (threadIdx.x == 0) s_tile = atomicAdd(a.ticket, 1u);
   __syncthreads();
   const int64_t tile = s_tile;
@@ -422,13 +425,25 @@ int launch_aggregate(gq_ctx* ctx, GbArgs& a, int strategy, hipStream_t stream) {
 
 int run_groupby(gq_ctx* ctx, const gq_batch* in, const int32_t* keys, int nkeys, const gq_pred* preds, int npreds,
                 const gq_agg* aggs, int naggs, const gq_groupby_opts* opts, const gq_join_table* join,
-                int32_t probe_key, gq_batch* out, int64_t* d_groups, hipStream_t stream) {
+                int32_t probe_key, gq_batch* out, int64_t* d_groups, hipStream_t stream,
+                const int64_t* d_nrows = nullptr) {
   if (!ctx) return GQ_ERR_INVALID;
   int rc = check_batch(ctx, in, "group-by input");
   if (rc) return rc;
   if (!d_groups) return set_error(ctx, GQ_ERR_INVALID, "group-by: NULL group count");
   gq_groupby_opts o{};
   if (opts) o = *opts;
+  if (o.mode < GQ_MODE_SINGLE || o.mode > GQ_MODE_FINAL) return set_error(ctx, GQ_ERR_INVALID, "group-by: unknown mode");
+  gq_agg merged[GQ_MAX_AGGS];
+  if (o.mode == GQ_MODE_INTERMEDIATE || o.mode == GQ_MODE_FINAL) {
+    // Partial states in, merged states out: no predicates (the rows are
+    // groups already) and no join.
+    if (npreds != 0 || join)
+      return set_error(ctx, GQ_ERR_INVALID, "group-by: the intermediate and final modes take no predicates or join");
+    rc = merge_aggs(ctx, aggs, naggs, in->ncols, merged);
+    if (rc) return rc;
+    aggs = merged;
+  }
   const float lf = o.load_factor > 0.f ? o.load_factor : 0.5f;
   if (!(lf > 0.f && lf <= 0.9f)) return set_error(ctx, GQ_ERR_INVALID, "group-by: load factor outside (0, 0.9]");
   if (o.strategy < GQ_STRATEGY_AUTO || o.strategy > GQ_STRATEGY_GLOBAL)
@@ -437,6 +452,7 @@ int run_groupby(gq_ctx* ctx, const gq_batch* in, const int32_t* keys, int nkeys,
   GbArgs a;
   std::memset(&a, 0, sizeof(a));
   a.n = in->nrows;
+  a.d_nrows = d_nrows;
   a.dev_status = ctx->d_status;
   rc = make_preds(ctx, a, in, preds, npreds);
   if (rc) return rc;
@@ -696,7 +712,8 @@ int make_preds(gq_ctx* ctx, GbArgs& a, const gq_batch* in, const gq_pred* preds,
   return GQ_OK;
 }
 
-int make_key_plan(gq_ctx* ctx, KeyPlan& kp, const gq_batch* in, const int32_t* keys, int nk) {
+int make_key_plan(gq_ctx* ctx, KeyPlan& kp, const gq_batch* in, const int32_t* keys, int nk,
+                  const int32_t* force_nullable) {
   if (nk < 0 || nk > GQ_MAX_KEYS || (nk > 0 && !keys))
     return set_error(ctx, GQ_ERR_INVALID, "group-by: bad key list");
   kp.nk = nk;
@@ -710,6 +727,11 @@ int make_key_plan(gq_ctx* ctx, KeyPlan& kp, const gq_batch* in, const int32_t* k
     kp.bits[0] = 64;
     kp.shift[0] = 0;
     kp.nullable[0] = in->cols[keys[0]].validity != nullptr;
+    if (force_nullable) {
+      if (kp.nullable[0] && !force_nullable[0])
+        return set_error(ctx, GQ_ERR_INVALID, "group-by: key column has a bitmap but was declared non-nullable");
+      kp.nullable[0] = force_nullable[0] != 0;
+    }
     return GQ_OK;
   }
   kp.mode = KEY_PACKED;
@@ -718,6 +740,11 @@ int make_key_plan(gq_ctx* ctx, KeyPlan& kp, const gq_batch* in, const int32_t* k
     const gq_column& c = in->cols[keys[j]];
     kp.bits[j] = 8 * type_width(c.type);
     kp.nullable[j] = c.validity != nullptr;
+    if (force_nullable) {
+      if (kp.nullable[j] && !force_nullable[j])
+        return set_error(ctx, GQ_ERR_INVALID, "group-by: key column has a bitmap but was declared non-nullable");
+      kp.nullable[j] = force_nullable[j] != 0;
+    }
     kp.shift[j] = shift;
     shift += kp.bits[j] + kp.nullable[j];
   }
@@ -727,7 +754,7 @@ int make_key_plan(gq_ctx* ctx, KeyPlan& kp, const gq_batch* in, const int32_t* k
   return GQ_OK;
 }
 
-int make_agg_plan(gq_ctx* ctx, AggPlan& ap, const gq_batch* in, const gq_agg* aggs, int na) {
+int make_agg_plan(gq_ctx* ctx, AggPlan& ap, const gq_batch* in, const gq_agg* aggs, int na, bool all_nullable) {
   if (na < 0 || na > GQ_MAX_AGGS || (na > 0 && !aggs))
     return set_error(ctx, GQ_ERR_INVALID, "group-by: bad aggregate list");
   ap.naggs = na;
@@ -773,7 +800,7 @@ int make_agg_plan(gq_ctx* ctx, AggPlan& ap, const gq_batch* in, const gq_agg* ag
     }
     d.word = word++;
     ap.wop[d.word] = g.op == GQ_MIN ? WOP_MIN : g.op == GQ_MAX ? WOP_MAX : WOP_ADD;
-    if (nullable && g.op != GQ_COUNT) {
+    if ((nullable || all_nullable) && g.op != GQ_COUNT) {
       d.cword = word++;
       ap.wop[d.cword] = WOP_ADD;
     }
@@ -781,6 +808,37 @@ int make_agg_plan(gq_ctx* ctx, AggPlan& ap, const gq_batch* in, const gq_agg* ag
   // A value column read by one factor only is streamed with non-temporal loads.
   for (int q = 0; q < ap.nvals; ++q) ap.vals[q].nt = uses[q] == 1 ? 1 : 0;
   ap.nacc = word;
+  return GQ_OK;
+}
+
+int groupby_rows(gq_ctx* ctx, const gq_batch* in, const int64_t* d_nrows, const int32_t* keys, int nkeys,
+                 const gq_agg* aggs, int naggs, const gq_groupby_opts* opts, gq_batch* out, int64_t* d_groups,
+                 hipStream_t stream) {
+  return run_groupby(ctx, in, keys, nkeys, nullptr, 0, aggs, naggs, opts, nullptr, 0, out, d_groups, stream, d_nrows);
+}
+
+int aggregate_into(gq_ctx* ctx, GbArgs& a, int strategy, hipStream_t stream) {
+  return launch_aggregate<false>(ctx, a, strategy, stream);
+}
+
+int merge_aggs(gq_ctx* ctx, const gq_agg* aggs, int na, int ncols, gq_agg* merged) {
+  if (na < 0 || na > GQ_MAX_AGGS || (na > 0 && !aggs))
+    return set_error(ctx, GQ_ERR_INVALID, "group-by: bad aggregate list");
+  for (int i = 0; i < na; ++i) {
+    const gq_agg& g = aggs[i];
+    if (g.nfactors != 1 || g.f[0].kind != GQ_F_COL || g.f[0].col < 0 || g.f[0].col >= ncols)
+      return set_error(ctx, GQ_ERR_INVALID,
+                       "group-by: in the intermediate and final modes each aggregate names its state column "
+                       "(one GQ_F_COL factor)");
+    gq_agg m = g;
+    switch (g.op) {
+      case GQ_SUM: case GQ_COUNT_STAR: case GQ_COUNT: m.op = GQ_SUM; break;
+      case GQ_MIN: m.op = GQ_MIN; break;
+      case GQ_MAX: m.op = GQ_MAX; break;
+      default: return set_error(ctx, GQ_ERR_INVALID, "group-by: unknown aggregate");
+    }
+    merged[i] = m;
+  }
   return GQ_OK;
 }
 

@@ -19,7 +19,7 @@
 // Each thread issues the first probe of all its rows before resolving any of
 // them, so the random reads of a thread overlap; a probe step is one 16-byte
 // load of a (key, meta) pair.
-#include "table.h"
+#include "agg.h"
 #include "radix.h"
 
 namespace gq {
@@ -521,13 +521,15 @@ struct GatherArgs {
   int32_t ncols;
   int32_t pad;
   const int32_t* idx;
+  const int64_t* d_n;      // if set: only the first min(n, *d_n) rows (a device count)
   DCol cols[GQ_MAX_COLS];
   OCol out[GQ_MAX_COLS];
 };
 
-__global__ void k_gather(const GatherArgs a) {
+__global__ void k_gather(GatherArgs a) {
   const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  if (a.d_n && *a.d_n < a.n) a.n = *a.d_n > 0 ? *a.d_n : 0;
   for (int64_t r = i0; r < a.n; r += stride) {
     const int64_t src = a.idx[r];
     for (int j = 0; j < a.ncols; ++j) {
@@ -669,8 +671,9 @@ int join_ensure_index(gq_ctx* ctx, const gq_join_table* table, hipStream_t strea
   if (rc) return rc;
   if (t->index_built) return GQ_OK;
   if (!t->keys) {
+    // Allocated through the table's own context, which also frees it.
     const IndexLayout il = index_layout(t->cap_alloc, t->build_rows, t->acc_slots);
-    t->imem = ctx_alloc(ctx, il.bytes, stream);
+    t->imem = ctx_alloc(t->ctx ? t->ctx : ctx, il.bytes, stream);
     if (!t->imem) return set_error(ctx, GQ_ERR_NOMEM, "join: probe index allocation failed");
     t->ibytes = il.bytes;
     set_index(t, static_cast<char*>(t->imem), il, t->acc_slots);
@@ -685,7 +688,49 @@ int join_ensure_index(gq_ctx* ctx, const gq_join_table* table, hipStream_t strea
   a.d_n = &t->hdr->nrows;
   a.key_hashed = 1;
   GQ_HIP_CHECK(ctx, hipSetDevice(ctx->device));
-  return build_index(ctx, a, t, false, stream);
+  rc = build_index(ctx, a, t, false, stream);
+  if (rc) return rc;
+  // Readers on other streams wait for the table's ready event: from now on
+  // it also covers the index built here.
+  if (t->ready) GQ_HIP_CHECK(ctx, hipEventRecord(t->ready, stream));
+  return GQ_OK;
+}
+
+// Gather of gq_gather; with d_n, only rows below the device count *d_n.
+int gather_rows(gq_ctx* ctx, const gq_batch* in, const int32_t* cols, int ncols, const int32_t* idx, int64_t n,
+                const int64_t* d_n, gq_batch* out, hipStream_t stream) {
+  if (!ctx) return GQ_ERR_INVALID;
+  int rc = check_batch(ctx, in, "gq_gather input");
+  if (rc) return rc;
+  if (ncols < 0 || ncols > GQ_MAX_COLS || (ncols > 0 && !cols) || n < 0 || (n > 0 && !idx) || !out ||
+      out->ncols < ncols)
+    return set_error(ctx, GQ_ERR_INVALID, "gq_gather: bad arguments");
+  GatherArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.n = n;
+  a.ncols = ncols;
+  a.idx = idx;
+  a.d_n = d_n;
+  for (int j = 0; j < ncols; ++j) {
+    if (cols[j] < 0 || cols[j] >= in->ncols) return set_error(ctx, GQ_ERR_INVALID, "gq_gather: column out of range");
+    const gq_column& ic = in->cols[cols[j]];
+    const gq_column& oc = out->cols[j];
+    if (oc.type != ic.type || oc.length < n || (n > 0 && !oc.data))
+      return set_error(ctx, GQ_ERR_INVALID, "gq_gather: bad output column");
+    if (ic.validity && !oc.validity)
+      return set_error(ctx, GQ_ERR_INVALID, "gq_gather: nullable input needs an output bitmap");
+    if (oc.validity && (reinterpret_cast<uintptr_t>(oc.validity) & 3))
+      return set_error(ctx, GQ_ERR_INVALID, "gq_gather: output bitmap must be 4-byte aligned");
+    a.cols[j] = make_dcol(ic);
+    a.out[j] = OCol{static_cast<uint8_t*>(oc.data), reinterpret_cast<uint32_t*>(oc.validity), oc.type, 0};
+  }
+  if (n == 0 || ncols == 0) return GQ_OK;
+  GQ_HIP_CHECK(ctx, hipSetDevice(ctx->device));
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  GQ_LAUNCH(ctx, "gather", k_gather, dim3((unsigned)blocks), dim3(256), 0, stream, a);
+  GQ_LAUNCH_CHECK(ctx);
+  return GQ_OK;
 }
 
 }  // namespace gq
@@ -843,45 +888,112 @@ int gq_join_table_free(gq_ctx* ctx, gq_join_table* table, hipStream_t stream) {
     (void)hipStreamWaitEvent(stream, table->ready, 0);
     (void)hipEventDestroy(table->ready);
   }
-  if (table->imem) ctx_free(ctx, table->imem, table->ibytes, stream);
-  ctx_free(ctx, table->mem, table->bytes, stream);
+  // Both allocations came from the building context's allocator.
+  gq_ctx* actx = table->ctx ? table->ctx : ctx;
+  if (table->imem) ctx_free(actx, table->imem, table->ibytes, stream);
+  ctx_free(actx, table->mem, table->bytes, stream);
   delete table;
   return GQ_OK;
 }
 
 int gq_gather(gq_ctx* ctx, const gq_batch* in, const int32_t* cols, int ncols, const int32_t* idx, int64_t n,
               gq_batch* out, hipStream_t stream) {
+  return gather_rows(ctx, in, cols, ncols, idx, n, nullptr, out, stream);
+}
+
+int gq_join_groupby(gq_ctx* ctx, const gq_join_table* table, const gq_batch* build, const gq_batch* probe,
+                    const int32_t* probe_keys, int nprobe_keys, const gq_pred* probe_preds, int nprobe_preds,
+                    const int32_t* group_keys, int ngroup_keys, const gq_agg* aggs, int naggs,
+                    const gq_groupby_opts* opts, int64_t pair_capacity, gq_batch* out, int64_t* d_groups,
+                    hipStream_t stream) {
   if (!ctx) return GQ_ERR_INVALID;
-  int rc = check_batch(ctx, in, "gq_gather input");
+  if (!table || !build || !probe || !d_groups) return set_error(ctx, GQ_ERR_INVALID, "gq_join_groupby: NULL argument");
+  int rc = check_batch(ctx, probe, "gq_join_groupby probe");
   if (rc) return rc;
-  if (ncols < 0 || ncols > GQ_MAX_COLS || (ncols > 0 && !cols) || n < 0 || (n > 0 && !idx) || !out ||
-      out->ncols < ncols)
-    return set_error(ctx, GQ_ERR_INVALID, "gq_gather: bad arguments");
-  GatherArgs a;
-  std::memset(&a, 0, sizeof(a));
-  a.n = n;
-  a.ncols = ncols;
-  a.idx = idx;
-  for (int j = 0; j < ncols; ++j) {
-    if (cols[j] < 0 || cols[j] >= in->ncols) return set_error(ctx, GQ_ERR_INVALID, "gq_gather: column out of range");
-    const gq_column& ic = in->cols[cols[j]];
-    const gq_column& oc = out->cols[j];
-    if (oc.type != ic.type || oc.length < n || (n > 0 && !oc.data))
-      return set_error(ctx, GQ_ERR_INVALID, "gq_gather: bad output column");
-    if (ic.validity && !oc.validity)
-      return set_error(ctx, GQ_ERR_INVALID, "gq_gather: nullable input needs an output bitmap");
-    if (oc.validity && (reinterpret_cast<uintptr_t>(oc.validity) & 3))
-      return set_error(ctx, GQ_ERR_INVALID, "gq_gather: output bitmap must be 4-byte aligned");
-    a.cols[j] = make_dcol(ic);
-    a.out[j] = OCol{static_cast<uint8_t*>(oc.data), reinterpret_cast<uint32_t*>(oc.validity), oc.type, 0};
+  rc = check_batch(ctx, build, "gq_join_groupby build");
+  if (rc) return rc;
+  if (build->nrows != table->build_rows)
+    return set_error(ctx, GQ_ERR_INVALID, "gq_join_groupby: build batch is not the table's build input");
+  const int np = probe->ncols, nb = build->ncols;
+  if (np + nb > GQ_MAX_COLS) return set_error(ctx, GQ_ERR_UNSUPPORTED, "gq_join_groupby: more than 16 joined columns");
+  if (ngroup_keys < 0 || ngroup_keys > GQ_MAX_KEYS || (ngroup_keys > 0 && !group_keys) || naggs < 0 ||
+      naggs > GQ_MAX_AGGS || (naggs > 0 && !aggs))
+    return set_error(ctx, GQ_ERR_INVALID, "gq_join_groupby: bad key or aggregate list");
+  if (opts && opts->mode != GQ_MODE_SINGLE && opts->mode != GQ_MODE_PARTIAL)
+    return set_error(ctx, GQ_ERR_INVALID, "gq_join_groupby: aggregates read joined rows (single or partial mode)");
+  const int64_t cap = pair_capacity > 0 ? pair_capacity : probe->nrows;
+  // The joined columns the group-by reads: remap them to a gathered batch.
+  int used[GQ_MAX_COLS];
+  int nused = 0;
+  int remap[GQ_MAX_COLS];
+  for (int c = 0; c < GQ_MAX_COLS; ++c) remap[c] = -1;
+  auto use = [&](int c) -> int {
+    if (c < 0 || c >= np + nb) return -1;
+    if (remap[c] < 0) {
+      remap[c] = nused;
+      used[nused++] = c;
+    }
+    return remap[c];
+  };
+  int32_t gk[GQ_MAX_KEYS];
+  for (int j = 0; j < ngroup_keys; ++j) {
+    gk[j] = use(group_keys[j]);
+    if (gk[j] < 0) return set_error(ctx, GQ_ERR_INVALID, "gq_join_groupby: group key column out of range");
   }
-  if (n == 0 || ncols == 0) return GQ_OK;
-  GQ_HIP_CHECK(ctx, hipSetDevice(ctx->device));
-  int64_t blocks = (n + 255) / 256;
-  if (blocks > 16384) blocks = 16384;
-  GQ_LAUNCH(ctx, "gather", k_gather, dim3((unsigned)blocks), dim3(256), 0, stream, a);
-  GQ_LAUNCH_CHECK(ctx);
-  return GQ_OK;
+  gq_agg ga[GQ_MAX_AGGS];
+  for (int i = 0; i < naggs; ++i) {
+    ga[i] = aggs[i];
+    if (aggs[i].nfactors < 0 || aggs[i].nfactors > 3) return set_error(ctx, GQ_ERR_INVALID, "gq_join_groupby: 0..3 factors");
+    for (int f = 0; f < aggs[i].nfactors; ++f) {
+      if (aggs[i].f[f].kind == GQ_F_CONST) continue;
+      ga[i].f[f].col = use(aggs[i].f[f].col);
+      if (ga[i].f[f].col < 0) return set_error(ctx, GQ_ERR_INVALID, "gq_join_groupby: factor column out of range");
+    }
+  }
+  // Workspace: the gather maps, their device count, the gathered columns.
+  size_t off = 256;
+  const size_t off_pi = off;
+  off = align_up(off + (size_t)(cap > 0 ? cap : 1) * 4, 256);
+  const size_t off_bi = off;
+  off = align_up(off + (size_t)(cap > 0 ? cap : 1) * 4, 256);
+  size_t coff[GQ_MAX_COLS], voff[GQ_MAX_COLS];
+  for (int u = 0; u < nused; ++u) {
+    const gq_column& src = used[u] < np ? probe->cols[used[u]] : build->cols[used[u] - np];
+    coff[u] = off;
+    off = align_up(off + (size_t)(cap > 0 ? cap : 1) * type_width(src.type), 256);
+    voff[u] = off;
+    if (src.validity) off = align_up(off + (size_t)((cap + 63) / 64) * 8, 256);
+  }
+  Scratch ws(ctx, stream);
+  if (!ws.get(off)) return set_error(ctx, GQ_ERR_NOMEM, "gq_join_groupby: workspace allocation failed");
+  int64_t* d_pairs = ws.as<int64_t>(0);
+  int32_t* pi = ws.as<int32_t>(off_pi);
+  int32_t* bi = ws.as<int32_t>(off_bi);
+  // 1. Key-only join: the (probe row, build row) gather maps.
+  rc = gq_join_probe(ctx, table, probe, probe_keys, nprobe_keys, probe_preds, nprobe_preds, pi, bi, cap, d_pairs,
+                     stream);
+  if (rc) return rc;
+  // 2. Gather the columns the group-by reads, each from its side.
+  gq_column gcols[GQ_MAX_COLS];
+  std::memset(gcols, 0, sizeof(gcols));
+  for (int u = 0; u < nused; ++u) {
+    const bool from_probe = used[u] < np;
+    const gq_batch* side = from_probe ? probe : build;
+    const int32_t col = from_probe ? used[u] : used[u] - np;
+    const gq_column& src = side->cols[col];
+    gq_column& g = gcols[u];
+    g.type = src.type;
+    g.scale = src.scale;
+    g.length = cap;
+    g.data = ws.as<void>(coff[u]);
+    g.validity = src.validity ? ws.as<uint8_t>(voff[u]) : nullptr;
+    gq_batch gb{cap, 1, 0, &g};
+    rc = gather_rows(ctx, side, &col, 1, from_probe ? pi : bi, cap, d_pairs, &gb, stream);
+    if (rc) return rc;
+  }
+  // 3. Group-by over the gathered rows (their number is the device count).
+  gq_batch joined{cap, nused, 0, gcols};
+  return groupby_rows(ctx, &joined, d_pairs, gk, ngroup_keys, ga, naggs, opts, out, d_groups, stream);
 }
 
 }  // extern "C"

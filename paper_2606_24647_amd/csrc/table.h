@@ -216,6 +216,7 @@ struct CompactArgs {
   uint64_t* status;
   int64_t* d_count;
   int32_t* dev_status;
+  const int64_t* gate;     // if set and *gate == 0: write nothing (d_count stays 0)
 };
 
 }  // namespace gq

@@ -40,6 +40,8 @@ GQ_I8, GQ_I16, GQ_I32, GQ_I64 = 1, 2, 3, 4
 GQ_RANGE, GQ_NE = 1, 2
 GQ_SUM, GQ_COUNT_STAR, GQ_COUNT, GQ_MIN, GQ_MAX = 1, 2, 3, 4, 5
 GQ_SORTED = 1
+GQ_DEV_CAPACITY, GQ_DEV_TABLE_FULL = 1, 2
+DEV_CAPACITY, DEV_TABLE_FULL = GQ_DEV_CAPACITY, GQ_DEV_TABLE_FULL
 STRATEGY = {"auto": 0, "lds": 1, "global": 2}
 
 _STATUS_NAMES = {0: "GQ_OK", -1: "GQ_ERR_INVALID", -2: "GQ_ERR_UNSUPPORTED", -3: "GQ_ERR_NOMEM",
@@ -47,6 +49,13 @@ _STATUS_NAMES = {0: "GQ_OK", -1: "GQ_ERR_INVALID", -2: "GQ_ERR_UNSUPPORTED", -3:
 
 _TORCH_TYPE = {torch.int8: GQ_I8, torch.int16: GQ_I16, torch.int32: GQ_I32, torch.int64: GQ_I64}
 _TYPE_TORCH = {v: k for k, v in _TORCH_TYPE.items()}
+_NP_TYPE = {np.dtype(np.int8): GQ_I8, np.dtype(np.int16): GQ_I16, np.dtype(np.int32): GQ_I32,
+            np.dtype(np.int64): GQ_I64}
+
+
+def np_to_type(dtype) -> int:
+    """gq column type of a numpy integer dtype."""
+    return _NP_TYPE[np.dtype(dtype)]
 _PRED_OPS = {"range": GQ_RANGE, "ne": GQ_NE}
 _FACTORS = {"col": 1, "k-col": 2, "k+col": 3, "const": 4}
 _AGGS = {"sum": GQ_SUM, "count*": GQ_COUNT_STAR, "count": GQ_COUNT, "min": GQ_MIN, "max": GQ_MAX}
@@ -80,7 +89,68 @@ class GqJoinOpts(C.Structure):
 
 class GqGroupbyOpts(C.Structure):
     _fields_ = [("load_factor", C.c_float), ("strategy", C.c_int32), ("flags", C.c_int32),
-                ("block_size", C.c_int32), ("expected_groups", C.c_int64)]
+                ("block_size", C.c_int32), ("expected_groups", C.c_int64), ("mode", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+MODES = {"single": 0, "partial": 1, "intermediate": 2, "final": 3}
+
+
+class GqExprInstr(C.Structure):
+    _fields_ = [("op", C.c_int32), ("a", C.c_int32), ("b", C.c_int32), ("c", C.c_int32), ("k", C.c_int64)]
+
+
+class GqExpr(C.Structure):
+    _fields_ = [("ninstr", C.c_int32), ("reserved", C.c_int32), ("instr", C.POINTER(GqExprInstr))]
+
+
+_EXPR_OPS = {"col": 1, "const": 2, "add": 3, "sub": 4, "mul": 5, "neg": 6, "lt": 7, "le": 8, "eq": 9,
+             "ne": 10, "gt": 11, "ge": 12, "case": 13}
+
+
+def compile_expr(tree):
+    """An expression tree (("col", c), ("const", k), ("add", x, y), ...,
+    ("case", cond, then, else)) as the postfix instruction list of gq_expr:
+    operands are the indices of earlier instructions."""
+    prog = []
+
+    def emit(e):
+        op = e[0]
+        if op == "col":
+            prog.append((1, int(e[1]), 0, 0, 0))
+        elif op == "const":
+            prog.append((2, 0, 0, 0, int(e[1])))
+        else:
+            args = [emit(x) for x in e[1:]] + [0, 0]
+            prog.append((_EXPR_OPS[op], args[0], args[1], args[2], 0))
+        return len(prog) - 1
+
+    emit(tree)
+    return prog
+
+
+class _ExprArg:
+    """A list of expression trees as gq_expr structs kept alive for one call."""
+
+    def __init__(self, trees):
+        self.progs = []
+        self.arr = (GqExpr * max(1, len(trees)))()
+        for i, t in enumerate(trees):
+            prog = compile_expr(t)
+            ins = (GqExprInstr * len(prog))(*[GqExprInstr(*q) for q in prog])
+            self.progs.append(ins)
+            self.arr[i] = GqExpr(len(prog), 0, C.cast(ins, C.POINTER(GqExprInstr)))
+
+    @property
+    def ptr(self):
+        return C.cast(self.arr, C.POINTER(GqExpr))
+
+
+class GqAggStreamSpec(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("nkeys", C.c_int32), ("keys", C.POINTER(C.c_int32)),
+                ("key_nullable", C.POINTER(C.c_int32)), ("aggs", C.POINTER(GqAgg)), ("naggs", C.c_int32),
+                ("reserved", C.c_int32), ("max_groups", C.c_int64), ("emit_groups", C.c_int64),
+                ("load_factor", C.c_float), ("reserved2", C.c_int32)]
 
 
 class GqPlan(C.Structure):
@@ -142,6 +212,22 @@ _SIGS = {
     "gq_batch_plan_launch": (C.c_int, [_P, _P]),
     "gq_batch_plan_info": (C.c_int, [_P, _P, _P, _P, _P]),
     "gq_batch_plan_free": (C.c_int, [_P]),
+    "gq_join_groupby": (C.c_int, [_P, _P, C.POINTER(GqBatch), C.POINTER(GqBatch), C.POINTER(C.c_int32), C.c_int,
+                                  C.POINTER(GqPred), C.c_int, C.POINTER(C.c_int32), C.c_int, C.POINTER(GqAgg),
+                                  C.c_int, C.POINTER(GqGroupbyOpts), C.c_int64, C.POINTER(GqBatch), _P, _P]),
+    "gq_compute_column": (C.c_int, [_P, C.POINTER(GqBatch), C.POINTER(GqExpr), C.POINTER(GqColumn), _P]),
+    "gq_filter_expr": (C.c_int, [_P, C.POINTER(GqBatch), C.POINTER(GqPred), C.c_int, C.POINTER(GqExpr), C.c_int,
+                                 C.POINTER(C.c_int32), C.c_int, C.POINTER(GqBatch), _P, _P]),
+    "gq_groupby_expr": (C.c_int, [_P, C.POINTER(GqBatch), C.POINTER(C.c_int32), C.c_int, C.POINTER(GqPred), C.c_int,
+                                  C.POINTER(GqExpr), C.c_int, C.POINTER(C.c_int32), C.POINTER(GqExpr), C.c_int,
+                                  C.POINTER(GqGroupbyOpts), C.POINTER(GqBatch), _P, _P]),
+    "gq_order_by": (C.c_int, [_P, C.POINTER(GqBatch), C.POINTER(C.c_int32), C.c_int, C.POINTER(C.c_int32),
+                              C.POINTER(C.c_int32), C.c_int64, _P, _P]),
+    "gq_agg_stream_create": (C.c_int, [_P, C.POINTER(GqAggStreamSpec), _P, C.POINTER(_P)]),
+    "gq_agg_stream_push": (C.c_int, [_P, C.POINTER(GqBatch), C.POINTER(GqPred), C.c_int, C.POINTER(GqBatch),
+                                     _P, _P]),
+    "gq_agg_stream_finish": (C.c_int, [_P, C.POINTER(GqBatch), _P, _P]),
+    "gq_agg_stream_free": (C.c_int, [_P, _P]),
 }
 EXPORTS = tuple(_SIGS)
 
@@ -201,6 +287,10 @@ class DevTable:
         if self.nrows_override is not None:
             return self.nrows_override
         return self.cols[0].nrows if self.cols else 0
+
+    def head(self, n: int) -> "DevTable":
+        """The first n rows (a view: columns and bitmaps are shared)."""
+        return DevTable([DevColumn(c.data, c.valid, c.offset, n, c.scale) for c in self.cols])
 
 
 def to_device(table, device="cuda") -> DevTable:
@@ -467,27 +557,105 @@ class Context:
                                   _stream(stream)))
         return out
 
-    def _groupby_out(self, table, keys, aggs, capacity):
+    def compute_column(self, table: DevTable, tree, stream=None):
+        """(int64 values, bitmap) of an expression tree over every row."""
+        out = empty_like_cols([GQ_I64], table.nrows, [True])
+        e = _ExprArg([tree])
+        ib, ob = _BatchArg(table), _BatchArg(out, table.nrows)
+        self.check(_lib.gq_compute_column(self.h, ib.ref, e.ptr, ob.arr, _stream(stream)))
+        return out
+
+    def filter_expr(self, table: DevTable, preds, exprs, proj, capacity: int | None = None, stream=None):
+        """Filter by predicates and expression trees (non-NULL, non-zero);
+        returns (output DevTable, device count)."""
+        cap = table.nrows if capacity is None else capacity
+        out = empty_like_cols([table.cols[j].type for j in proj], cap, [table.cols[j].valid is not None for j in proj])
+        cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+        p, np_ = _preds(preds)
+        e = _ExprArg(exprs)
+        pj, npj = _ints(proj)
+        ib, ob = _BatchArg(table), _BatchArg(out, cap)
+        self.check(_lib.gq_filter_expr(self.h, ib.ref, p, np_, e.ptr, len(exprs), pj, npj, ob.ref,
+                                       C.c_void_p(cnt.data_ptr()), _stream(stream)))
+        return out, cnt
+
+    def groupby_expr(self, table: DevTable, keys, preds, exprs, aggs, capacity: int | None = None,
+                     expected_groups=0, stream=None):
+        """Group-by with expression aggregates: aggs are (op, tree) with op in
+        sum/count/min/max, or ("count*",).  Returns (output, device count)."""
+        cap = max(1, table.nrows) if capacity is None else capacity
         types = [table.cols[j].type for j in keys] + [GQ_I64] * len(aggs)
-        nullable = [table.cols[j].valid is not None for j in keys] + [agg_nullable(table, a) for a in aggs]
+        nullable = [table.cols[j].valid is not None for j in keys] + [a[0] not in ("count*", "count") for a in aggs]
+        out = empty_like_cols(types, cap, nullable)
+        cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+        k, nk = _ints(keys)
+        p, np_ = _preds(preds)
+        e = _ExprArg(exprs)
+        ops, _ = _ints([_AGGS[a[0]] for a in aggs])
+        ae = _ExprArg([a[1] if len(a) > 1 else ("const", 0) for a in aggs])
+        opts = self._opts(0.0, "auto", False, 0, expected_groups)
+        ib, ob = _BatchArg(table), _BatchArg(out, cap)
+        self.check(_lib.gq_groupby_expr(self.h, ib.ref, k, nk, p, np_, e.ptr, len(exprs), ops, ae.ptr, len(aggs),
+                                        C.byref(opts), ob.ref, C.c_void_p(cnt.data_ptr()), _stream(stream)))
+        return out, cnt
+
+    def order_by(self, table: DevTable, keys, desc=None, nulls_first=None, limit=None, stream=None):
+        """Row ids (device int32) in ORDER BY order; the first `limit` with a limit."""
+        n = table.nrows
+        take = n if limit is None else min(int(limit), n)
+        out = torch.empty(max(1, take), dtype=torch.int32, device="cuda")
+        k, nk = _ints(keys)
+        d, _ = _ints([1 if x else 0 for x in (desc or [False] * nk)])
+        nf, _ = _ints([1 if x else 0 for x in (nulls_first or [False] * nk)])
+        ib = _BatchArg(table)
+        self.check(_lib.gq_order_by(self.h, ib.ref, k, nk, d, nf, -1 if limit is None else int(limit),
+                                    C.c_void_p(out.data_ptr()), _stream(stream)))
+        return out[:take]
+
+    def join_groupby(self, jt: "JoinTable", build: DevTable, probe: DevTable, probe_keys, probe_preds, group_keys,
+                     aggs, capacity: int | None = None, pair_capacity: int = 0, load_factor=0.0, strategy="auto",
+                     expected_groups=0, stream=None):
+        """Group-by over the joined rows (late materialisation).  Column c of a
+        joined row is probe column c for c < len(probe.cols), else build column
+        c - len(probe.cols).  Returns (output DevTable, device group count)."""
+        joined = DevTable(list(probe.cols) + list(build.cols))
+        cap = max(1, pair_capacity or probe.nrows) if capacity is None else capacity
+        out = self._groupby_out(joined, group_keys, aggs, cap)
+        cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+        pk, npk = _ints(probe_keys)
+        p, np_ = _preds(probe_preds)
+        gk, ngk = _ints(group_keys)
+        a, na = _aggs(aggs)
+        opts = self._opts(load_factor, strategy, False, 0, expected_groups)
+        bb, pb, ob = _BatchArg(build), _BatchArg(probe), _BatchArg(out, cap)
+        self.check(_lib.gq_join_groupby(self.h, jt.h, bb.ref, pb.ref, pk, npk, p, np_, gk, ngk, a, na,
+                                        C.byref(opts), int(pair_capacity), ob.ref, C.c_void_p(cnt.data_ptr()),
+                                        _stream(stream)))
+        return out, cnt
+
+    def _groupby_out(self, table, keys, aggs, capacity, merge=False):
+        types = [table.cols[j].type for j in keys] + [GQ_I64] * len(aggs)
+        nullable = [table.cols[j].valid is not None for j in keys] + [merge or agg_nullable(table, a) for a in aggs]
         return empty_like_cols(types, capacity, nullable)
 
     @staticmethod
-    def _opts(load_factor=0.0, strategy="auto", sorted=False, block_size=0, expected_groups=0):
+    def _opts(load_factor=0.0, strategy="auto", sorted=False, block_size=0, expected_groups=0, mode="single"):
         return GqGroupbyOpts(load_factor, STRATEGY[strategy], GQ_SORTED if sorted else 0, block_size,
-                             expected_groups)
+                             expected_groups, MODES[mode], 0)
 
     def groupby_agg(self, table: DevTable, keys, preds, aggs, capacity: int | None = None,
                     load_factor=0.0, strategy="auto", sorted=False, block_size=0, expected_groups=0,
-                    stream=None):
-        """Returns (output DevTable: keys then aggregates, device int64 group count)."""
+                    stream=None, mode="single"):
+        """Returns (output DevTable: keys then aggregates, device int64 group count).
+        mode: "single" / "partial" (raw rows), "intermediate" / "final" (state
+        rows: each aggregate names its state column with one ("col", c) factor)."""
         cap = max(1, table.nrows) if capacity is None else capacity
-        out = self._groupby_out(table, keys, aggs, cap)
+        out = self._groupby_out(table, keys, aggs, cap, merge=mode in ("intermediate", "final"))
         cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
         k, nk = _ints(keys)
         p, np_ = _preds(preds)
         a, na = _aggs(aggs)
-        opts = self._opts(load_factor, strategy, sorted, block_size, expected_groups)
+        opts = self._opts(load_factor, strategy, sorted, block_size, expected_groups, mode)
         ib, ob = _BatchArg(table), _BatchArg(out, cap)
         self.check(_lib.gq_groupby_agg(self.h, ib.ref, k, nk, p, np_, a, na, C.byref(opts), ob.ref,
                                        C.c_void_p(cnt.data_ptr()), _stream(stream)))
@@ -530,6 +698,73 @@ class Context:
         self.check(_lib.gq_pipeline(self.h, C.byref(plan), ib.ref, ob.ref, C.c_void_p(cnt.data_ptr()),
                                     _stream(stream)))
         return out, cnt
+
+
+class AggStream:
+    """Streaming aggregation over a sequence of batches (gq_agg_stream_*).
+
+    mode: "single", "partial", "intermediate" or "final"; keys: key column
+    indices of every batch; key_types: their gq types; key_nullable: which key
+    columns may be NULL; aggs: as for groupby_agg in that mode; max_groups:
+    table size; emit_groups: Partial / Intermediate emit once this many
+    groups are held (0: only at finish).  push() returns (out, device emitted
+    count) for a stream that can emit early, else None; finish() returns
+    (out, device int64[2]: groups, emitted flag).  Call free() to release the
+    stream's table (there is no implicit release)."""
+
+    def __init__(self, ctx: "Context", mode, keys, key_types, key_nullable, aggs, max_groups, emit_groups=0,
+                 load_factor=0.0, stream=None):
+        self.ctx = ctx
+        self.h = None
+        self.mode = mode
+        self.keys = list(keys)
+        self.key_types = list(key_types)
+        self.key_nullable = [bool(x) for x in key_nullable]
+        self.aggs = list(aggs)
+        self.max_groups = int(max_groups) if self.keys else 1
+        self.emit_groups = int(emit_groups)
+        self._k, nk = _ints(self.keys)
+        self._kn, _ = _ints([1 if x else 0 for x in self.key_nullable])
+        self._a, na = _aggs(self.aggs)
+        spec = GqAggStreamSpec(MODES[mode], nk, C.cast(self._k, C.POINTER(C.c_int32)),
+                               C.cast(self._kn, C.POINTER(C.c_int32)), C.cast(self._a, C.POINTER(GqAgg)), na, 0,
+                               self.max_groups, self.emit_groups, load_factor, 0)
+        h = C.c_void_p()
+        ctx.check(_lib.gq_agg_stream_create(ctx.h, C.byref(spec), _stream(stream), C.byref(h)))
+        self.h = h
+
+    def _out(self):
+        types = self.key_types + [GQ_I64] * len(self.aggs)
+        return empty_like_cols(types, max(1, self.max_groups), self.key_nullable + [True] * len(self.aggs))
+
+    @property
+    def emits_early(self):
+        return self.mode in ("partial", "intermediate") and self.emit_groups > 0
+
+    def push(self, table: DevTable, preds=(), stream=None):
+        p, np_ = _preds(preds)
+        ib = _BatchArg(table)
+        if self.emits_early:
+            out = self._out()
+            ob = _BatchArg(out, max(1, self.max_groups))
+            cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+            self.ctx.check(_lib.gq_agg_stream_push(self.h, ib.ref, p, np_, ob.ref, C.c_void_p(cnt.data_ptr()),
+                                                   _stream(stream)))
+            return out, cnt
+        self.ctx.check(_lib.gq_agg_stream_push(self.h, ib.ref, p, np_, None, None, _stream(stream)))
+        return None
+
+    def finish(self, stream=None):
+        out = self._out()
+        ob = _BatchArg(out, max(1, self.max_groups))
+        cnt = torch.zeros(2, dtype=torch.int64, device="cuda")
+        self.ctx.check(_lib.gq_agg_stream_finish(self.h, ob.ref, C.c_void_p(cnt.data_ptr()), _stream(stream)))
+        return out, cnt
+
+    def free(self, stream=None):
+        if self.h:
+            self.ctx.check(_lib.gq_agg_stream_free(self.h, _stream(stream)))
+            self.h = None
 
 
 class BatchPlan:

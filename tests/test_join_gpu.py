@@ -172,3 +172,35 @@ def test_pipeline_without_join(gq, ctx):
     t = dg.fact_c1(300_000, seed=4)
     check_pipeline(gq, ctx, t, [("range", 3, 0, 2466)], [4, 5],
                    [("sum", [("col", 0)]), ("sum", REV), ("count*",)], strategy="lds")
+
+
+def test_partitioned_table_index_from_two_streams(gq, ctx):
+    # A build side of 2^20 rows is stored partitioned; the first probe builds
+    # its index lazily on its own stream.  A second probe, enqueued on another
+    # stream right after, must see the complete index (the table's event is
+    # re-recorded after the index build), and both must equal the oracle.
+    import torch
+    nd = 1 << 20
+    dim = dg.dim_c2(nd, seed=21)
+    fact = dg.fact_c2(600_000, nkeys=nd, seed=21)
+    bpred, ppred = [("range", 1, 0, 1202)], [("range", 3, 1278, 2555)]
+    bd, pd_ = gq.to_device(dim), gq.to_device(fact)
+    epi, ebi = oracle.join(dim, [0], bpred, fact, [0], ppred)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    s1.wait_stream(torch.cuda.current_stream())
+    s2.wait_stream(torch.cuda.current_stream())
+    jt = ctx.join_build(bd, [0], bpred)
+    cap = len(epi) + 16
+    with torch.cuda.stream(s1):
+        r1 = ctx.join_probe(jt, pd_, [0], ppred, capacity=cap, stream=s1)
+    with torch.cuda.stream(s2):
+        r2 = ctx.join_probe(jt, pd_, [0], ppred, capacity=cap, stream=s2)
+    torch.cuda.synchronize()
+    assert ctx.sync_status() == 0
+    for pi, bi, cnt in (r1, r2):
+        n = int(cnt.item())
+        assert n == len(epi)
+        assert np.array_equal(pi[:n].cpu().numpy(), epi) and np.array_equal(bi[:n].cpu().numpy(), ebi)
+    torch.cuda.current_stream().wait_stream(s1)
+    torch.cuda.current_stream().wait_stream(s2)
+    jt.free()
