@@ -215,6 +215,20 @@ int gq_filter(gq_ctx* ctx, const gq_batch* in, const gq_pred* preds, int npreds,
               const int32_t* proj, int nproj, gq_batch* out, int64_t* d_count,
               hipStream_t stream);
 
+/* gq_filter for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and results, with the workspace (a ticket word and one status
+ * word per 4,096-row tile) taken from a fixed 512 KiB array that the library
+ * holds on each device for the life of the process, instead of the context
+ * allocator.  No allocation of any kind happens in the call.  Inputs of more
+ * than 268,435,456 rows (65,536 tiles) give GQ_ERR_INVALID.  Every call on a
+ * device shares that device's array (the call clears it first): calls that
+ * may overlap on one device, on any streams or contexts, race and must be
+ * ordered by the caller. */
+int gq_filter_noalloc(gq_ctx* ctx, const gq_batch* in, const gq_pred* preds, int npreds,
+                      const int32_t* proj, int nproj, gq_batch* out, int64_t* d_count,
+                      hipStream_t stream);
+
 /* ---- hash partition -----------------------------------------------------------
  * Split `in` into `nparts` partitions by a hash of its key columns (the
  * partitioned-output operator of Section 3.3; the packed per-destination

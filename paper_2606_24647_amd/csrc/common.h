@@ -529,6 +529,10 @@ __global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n);
 
 int launch_fill_u32(gq_ctx* ctx, void* p, uint32_t v, int64_t nwords, hipStream_t s);
 
+// Device address of gq_filter_noalloc's fixed workspace on ctx's (current)
+// device, looked up once per device (filter.hip).
+int filter_scratch_init(gq_ctx* ctx);
+
 // Host-side validation helpers.
 int check_batch(gq_ctx* ctx, const gq_batch* b, const char* what);
 DCol make_dcol(const gq_column& c);

@@ -148,6 +148,13 @@ int gq_ctx_create(int device, const gq_allocator* alloc, gq_ctx** out) {
     delete ctx;
     return GQ_ERR_HIP;
   }
+  // Set-up of gq_filter_noalloc's fixed workspace on this device.
+  const int src = filter_scratch_init(ctx);
+  if (src != GQ_OK) {
+    (void)hipFree(ctx->d_status);
+    delete ctx;
+    return src;
+  }
   *out = ctx;
   return GQ_OK;
 }

@@ -9,6 +9,8 @@
 // out with consecutive lanes writing consecutive rows.
 #include "common.h"
 
+#include <mutex>
+
 namespace gq {
 namespace {
 
@@ -128,15 +130,26 @@ __global__ __launch_bounds__(BLOCK) void k_filter(const FilterArgs a) {
 
 constexpr int kFilterBlock = 256;
 constexpr int kFilterItems = 16;
+constexpr int64_t kFilterTile = (int64_t)kFilterBlock * kFilterItems;
 
-}  // namespace
-}  // namespace gq
+// Workspace of gq_filter_noalloc: the ticket word (first 256 bytes) and the
+// look-back status words of up to kScratchTiles tiles, in a file-scope device
+// array: each device holds its own copy for the life of the process.  Host
+// code never passes the array's name to a kernel (on the host it stands for a
+// host-side shadow, not the device address); it passes the address that
+// hipGetSymbolAddress returned for the device.
+constexpr int64_t kScratchTiles = 65536;
+constexpr size_t kScratchBytes = 256 + (size_t)kScratchTiles * 8;
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
 
-using namespace gq;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];  // device address of `scratch` per device, once looked up
 
-extern "C" int gq_filter(gq_ctx* ctx, const gq_batch* in, const gq_pred* preds, int npreds,
-                         const int32_t* proj, int nproj, gq_batch* out, int64_t* d_count,
-                         hipStream_t stream) {
+// Filter of `in` with the given workspace (256 + ntiles * 8 bytes), or one
+// allocated through the context allocator when ws is NULL.
+int filter_run(gq_ctx* ctx, const gq_batch* in, const gq_pred* preds, int npreds, const int32_t* proj, int nproj,
+               gq_batch* out, int64_t* d_count, hipStream_t stream, void* ws_fixed) {
   if (!ctx) return GQ_ERR_INVALID;
   int rc = check_batch(ctx, in, "gq_filter input");
   if (rc) return rc;
@@ -180,15 +193,18 @@ extern "C" int gq_filter(gq_ctx* ctx, const gq_batch* in, const gq_pred* preds, 
     if (oc.length < a.out_cap) a.out_cap = oc.length;
   }
 
-  constexpr int TILE = kFilterBlock * kFilterItems;
-  const int64_t ntiles = (a.n + TILE - 1) / TILE;
+  const int64_t ntiles = (a.n + kFilterTile - 1) / kFilterTile;
   a.ntiles = ntiles;
   GQ_HIP_CHECK(ctx, hipSetDevice(ctx->device));
   Scratch ws(ctx, stream);
-  if (!ws.get(256 + align_up((size_t)(ntiles > 0 ? ntiles : 1) * 8, 256)))
-    return set_error(ctx, GQ_ERR_NOMEM, "gq_filter: workspace allocation failed");
-  a.ticket = ws.as<uint32_t>(0);
-  a.status = ws.as<uint64_t>(256);
+  char* wbase = static_cast<char*>(ws_fixed);
+  if (!wbase) {
+    if (!ws.get(256 + align_up((size_t)(ntiles > 0 ? ntiles : 1) * 8, 256)))
+      return set_error(ctx, GQ_ERR_NOMEM, "gq_filter: workspace allocation failed");
+    wbase = ws.as<char>(0);
+  }
+  a.ticket = reinterpret_cast<uint32_t*>(wbase);
+  a.status = reinterpret_cast<uint64_t*>(wbase + 256);
   a.d_count = d_count;
   a.dev_status = ctx->d_status;
 
@@ -204,4 +220,43 @@ extern "C" int gq_filter(gq_ctx* ctx, const gq_batch* in, const gq_pred* preds, 
     GQ_LAUNCH_CHECK(ctx);
   }
   return GQ_OK;
+}
+
+}  // namespace
+
+// Looks up the device address of `scratch` on `device` (current), once per
+// device; called by gq_ctx_create.
+int filter_scratch_init(gq_ctx* ctx) {
+  if (ctx->device < 0 || ctx->device >= kMaxDevices)
+    return set_error(ctx, GQ_ERR_UNSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[ctx->device]) return GQ_OK;
+  void* p = nullptr;
+  GQ_HIP_CHECK(ctx, hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  if (!p) return set_error(ctx, GQ_ERR_HIP, "hipGetSymbolAddress returned no address for the filter scratch");
+  g_scratch_ptr[ctx->device] = p;
+  return GQ_OK;
+}
+
+}  // namespace gq
+
+using namespace gq;
+
+extern "C" int gq_filter(gq_ctx* ctx, const gq_batch* in, const gq_pred* preds, int npreds,
+                         const int32_t* proj, int nproj, gq_batch* out, int64_t* d_count,
+                         hipStream_t stream) {
+  return filter_run(ctx, in, preds, npreds, proj, nproj, out, d_count, stream, nullptr);
+}
+
+extern "C" int gq_filter_noalloc(gq_ctx* ctx, const gq_batch* in, const gq_pred* preds, int npreds,
+                                 const int32_t* proj, int nproj, gq_batch* out, int64_t* d_count,
+                                 hipStream_t stream) {
+  if (!ctx) return GQ_ERR_INVALID;
+  if (!in) return set_error(ctx, GQ_ERR_INVALID, "gq_filter_noalloc: NULL input");
+  if (in->nrows > kScratchTiles * kFilterTile)
+    return set_error(ctx, GQ_ERR_INVALID,
+                     "gq_filter_noalloc: more than 268,435,456 rows (the fixed workspace's limit); use gq_filter");
+  void* ws = (ctx->device >= 0 && ctx->device < kMaxDevices) ? g_scratch_ptr[ctx->device] : nullptr;
+  if (!ws) return set_error(ctx, GQ_ERR_HIP, "gq_filter_noalloc: the device's scratch address was not looked up");
+  return filter_run(ctx, in, preds, npreds, proj, nproj, out, d_count, stream, ws);
 }

@@ -188,6 +188,8 @@ _SIGS = {
     "gq_ctx_timing_report": (C.c_int, [_P, C.c_char_p, C.c_int, _P, _P, C.c_int]),
     "gq_filter": (C.c_int, [_P, C.POINTER(GqBatch), C.POINTER(GqPred), C.c_int,
                             C.POINTER(C.c_int32), C.c_int, C.POINTER(GqBatch), _P, _P]),
+    "gq_filter_noalloc": (C.c_int, [_P, C.POINTER(GqBatch), C.POINTER(GqPred), C.c_int,
+                                    C.POINTER(C.c_int32), C.c_int, C.POINTER(GqBatch), _P, _P]),
     "gq_hash_partition": (C.c_int, [_P, C.POINTER(GqBatch), C.POINTER(C.c_int32), C.c_int,
                                     C.c_int32, C.c_uint64, C.POINTER(GqBatch), _P, _P]),
     "gq_join_build": (C.c_int, [_P, C.POINTER(GqBatch), C.POINTER(C.c_int32), C.c_int,
@@ -396,6 +398,12 @@ class GqAllocator(C.Structure):
     _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("user", C.c_void_p)]
 
 
+def make_allocator(alloc, free) -> GqAllocator:
+    """A gq_allocator from two Python callables: alloc(nbytes, stream) -> int
+    device pointer or None, free(ptr, nbytes, stream)."""
+    return GqAllocator(_ALLOC_FN(lambda n, s, u: alloc(n, s)), _FREE_FN(lambda p, n, s, u: free(p, n, s)), None)
+
+
 def _torch_allocator(device: int) -> GqAllocator:
     """gq_allocator over torch's caching allocator (stream-ordered per stream):
     one cache for the library's scratch and the caller's tensors.
@@ -432,13 +440,17 @@ def _torch_allocator(device: int) -> GqAllocator:
 class Context:
     """A library context.  allocator=None: hipMallocAsync on the device's pool;
     allocator="torch": the library allocates through torch's caching allocator
-    (for callers that also hold large torch tensors: one cache instead of two)."""
+    (for callers that also hold large torch tensors: one cache instead of two);
+    a GqAllocator: the caller's own callbacks (see make_allocator)."""
 
-    def __init__(self, device: int | None = None, allocator: str | None = None):
+    def __init__(self, device: int | None = None, allocator=None):
         self.device = torch.cuda.current_device() if device is None else device
         h = C.c_void_p()
         self._alloc = None
-        if allocator == "torch":
+        if isinstance(allocator, GqAllocator):
+            self._alloc = allocator          # caller-built callbacks (kept alive here)
+            rc = _lib.gq_ctx_create(self.device, C.byref(self._alloc), C.byref(h))
+        elif allocator == "torch":
             self._alloc = _torch_allocator(self.device)
             rc = _lib.gq_ctx_create(self.device, C.byref(self._alloc), C.byref(h))
         elif allocator is None:
@@ -509,6 +521,17 @@ class Context:
         self.check(_lib.gq_filter(self.h, ib.ref, p, np_, pj, npj, ob.ref,
                                   C.c_void_p(cnt.data_ptr()), _stream(stream)))
         return out, cnt
+
+    def filter_noalloc(self, table: DevTable, preds, proj, out: DevTable, cnt: torch.Tensor, capacity: int,
+                       stream=None):
+        """gq_filter_noalloc into caller-provided outputs (no allocation in the
+        library): out must have the projected columns' types and `capacity`
+        rows; cnt is a device int64 tensor of one element."""
+        p, np_ = _preds(preds)
+        pj, npj = _ints(proj)
+        ib, ob = _BatchArg(table), _BatchArg(out, capacity)
+        self.check(_lib.gq_filter_noalloc(self.h, ib.ref, p, np_, pj, npj, ob.ref,
+                                          C.c_void_p(cnt.data_ptr()), _stream(stream)))
 
     def hash_partition(self, table: DevTable, keys, nparts: int, seed: int = 0, stream=None):
         """Returns (output DevTable of all columns, device int64 offsets[nparts+1])."""
