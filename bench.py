@@ -108,6 +108,9 @@ def median(xs):
 _BUILD_STREAM = []
 
 
+REGIONS_LOG2 = [0]   # join_build's regions_log2 (0: the library's choice)
+
+
 def c2_step(ctx, dim, fact, out_cap, lf):
     """Join build on a second stream (ordered after the current stream's work),
     pipeline on the current stream: the library makes the pipeline wait for the
@@ -118,7 +121,7 @@ def c2_step(ctx, dim, fact, out_cap, lf):
         _BUILD_STREAM.append(torch.cuda.Stream())
     bs = _BUILD_STREAM[0]
     bs.wait_stream(torch.cuda.current_stream())
-    jt = ctx.join_build(dim, [0], DIM_PRED, load_factor=lf, acc_slots=2, stream=bs)
+    jt = ctx.join_build(dim, [0], DIM_PRED, load_factor=lf, acc_slots=2, regions_log2=REGIONS_LOG2[0], stream=bs)
     out, cnt = ctx.pipeline(fact, FACT_PRED, [0], C2_AGGS, join=jt, probe_key=0, capacity=out_cap)
     jt.free()
     return out, cnt
@@ -419,6 +422,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--load-factor", type=float, default=0.5)
+    ap.add_argument("--regions-log2", type=int, default=0,
+                    help="radix regions of the join build (2^k, 4..12; 0 = library choice)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-operators", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
@@ -442,6 +447,7 @@ def main():
 
     import torch
     from paper_2606_24647_amd import devgen, gq
+    REGIONS_LOG2[0] = args.regions_log2
 
     dev = torch.cuda.get_device_properties(0)
     log(f"device: {dev.name} {dev.gcnArchName} CUs={dev.multi_processor_count}")

@@ -11,15 +11,18 @@
 // streaming accesses, and the per-row atomics are LDS atomics.
 //
 // Build side (gq_join_build, large build inputs):
-//   k_rp_hist     per hist tile (16384 rows), histogram of the region ids of
-//                 the kept rows (predicates pass, key non-NULL); region = top
-//                 pbits of fmix64(key ^ kRegionSeed)
+//   k_rp_hist_r   per tile (4,096 to 32,768 rows, about 2,048 tiles),
+//                 histogram of the region ids of the kept rows (predicates
+//                 pass, key non-NULL); region = top pbits of
+//                 fmix64(key ^ kRegionSeed); columns read straight into
+//                 registers (k_rp_hist stages them through LDS where one is
+//                 not 16-byte aligned)
 //   k_cs_*        column scan of the (tile, region) counts, stored tile-major
 //                 so that every tile reads and writes its P counts coalesced:
 //                 per-chunk column sums and region totals, then the start of
 //                 every (tile, region), each block deriving its regions'
 //                 offsets from the totals
-//   k_rp_scatter  each hist tile in sub-tiles of 2048 rows staged in LDS (one
+//   k_rp_scatter  each tile in sub-tiles of 2048 rows staged in LDS (one
 //                 1024-thread workgroup per tile); a
 //                 kept row takes the next position of its region in the tile's
 //                 range with an LDS atomic and is written there: (key hash,
@@ -56,8 +59,8 @@ constexpr int kRpBlock = 256;                    // hist workgroup
 constexpr int kRpSBlock = 1024;                  // scatter workgroup
 constexpr int kRpSub = 2048;                     // rows per scatter sub-tile (unit of the staging layout)
 constexpr int kRpRows = kRpSub / kRpSBlock;      // rows per thread per scatter sub-tile
-constexpr int kRpTile = 32768;                   // rows per hist tile
-constexpr int kRpSubs = kRpTile / kRpSub;        // scatter sub-tiles per hist tile
+constexpr int kRpMinTile = 4096;                 // rows per tile: a power of two in [kRpMinTile, kRpMaxTile],
+constexpr int kRpMaxTile = 32768;                //   a multiple of both sub-tiles
 constexpr int kRpHSub = 2048;                    // rows per hist sub-tile
 constexpr int kRpHRows = kRpHSub / kRpBlock;
 constexpr int kRpHScale = kRpHSub / kRpSub;      // hist staging offsets = layout offsets * kRpHScale
@@ -79,6 +82,7 @@ __device__ __forceinline__ uint32_t subregion_of(uint64_t h, int pbits, uint32_t
 struct RpArgs {
   int64_t n;               // input rows
   int64_t ntiles;          // hist tiles
+  int64_t tile_rows;       // rows per tile (histogram and scatter alike)
   int32_t pbits;           // P = 1 << pbits regions
   int32_t npreds;
   int32_t probe;           // 0: build side (payload = row id), 1: probe side (aggregate inputs)
@@ -214,8 +218,8 @@ __global__ __launch_bounds__(kRpBlock) void k_rp_hist(const RpArgs a) {
   if (blockIdx.x == 0)
     for (int i = threadIdx.x; i < P; i += kRpBlock) a.rtot[i] = 0;
   const int64_t tile = blockIdx.x;
-  for (int sub = 0; sub < kRpTile / kRpHSub; ++sub) {
-    const int64_t sbase = tile * kRpTile + (int64_t)sub * kRpHSub;
+  for (int64_t sub = 0; sub < a.tile_rows / kRpHSub; ++sub) {
+    const int64_t sbase = tile * a.tile_rows + sub * kRpHSub;
     if (sbase >= a.n) break;
     const int nrows = a.n - sbase < kRpHSub ? (int)(a.n - sbase) : kRpHSub;
     __syncthreads();  // previous sub-tile's rows read
@@ -322,8 +326,8 @@ __global__ __launch_bounds__(kRpSBlock) void k_rp_scatter(const RpArgs a) {
   uint8_t* s_in = s_raw + align_up((size_t)P * 4, 16);
   const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
   for (int q = threadIdx.x; q < P; q += kRpSBlock) s_pos[q] = a.starts[tile * P + q];
-  for (int sub = 0; sub < kRpSubs; ++sub) {
-    const int64_t sbase = tile * kRpTile + (int64_t)sub * kRpSub;
+  for (int64_t sub = 0; sub < a.tile_rows / kRpSub; ++sub) {
+    const int64_t sbase = tile * a.tile_rows + sub * kRpSub;
     if (sbase >= a.n) break;
     const int nrows = a.n - sbase < kRpSub ? (int)(a.n - sbase) : kRpSub;
     __syncthreads();  // previous sub-tile's rows written
@@ -380,6 +384,171 @@ __global__ __launch_bounds__(kRpSBlock) void k_rp_scatter(const RpArgs a) {
       }
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// Register-path histogram (every column it reads 16-byte aligned)
+// ---------------------------------------------------------------------------
+// A lane takes two consecutive rows per step and loads, for every column, the
+// aligned 16-byte chunk that holds both (one load instruction per column
+// whatever its width; no type-dependent branch before the loads, so the loads
+// of all columns are in flight together), then extracts the two values.  The
+// next step's chunks are loaded before the current step is processed, and
+// there is no barrier inside the row loop: the waves of a workgroup stream
+// through their tile independently, so the loads and LDS atomics of many
+// waves overlap.  Rows within 16 of the end of the input are loaded one by one
+// (a chunk there could pass the column's end).  The same scheme for the
+// scatter measured slower than staging through LDS (its scattered stores then
+// compete with the loads of every wave), so the scatter keeps the staged form.
+constexpr int kRpItems = 2;
+
+// Raw chunks of the NS staged columns for one step: halves lo[j], hi[j] of
+// column j's chunk, or (in the tail) the two rows' values.  Two plain arrays
+// rather than an array of structs, so that they stay in registers.
+template <int NS>
+struct RawStep {
+  uint64_t lo[NS];
+  uint64_t hi[NS];
+};
+
+// One branch around all loads (not one per column): on the usual path every
+// chunk load is issued back to back with no wait in between.
+template <int NS>
+__device__ __forceinline__ void rp_raw(const RpArgs& a, int64_t r0, bool full, RawStep<NS>& raw) {
+  if (full) {
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+      const DCol& c = a.st[j];
+      const int w = type_width(c.type);
+      const uint8_t* p = c.data + ((r0 * w) & ~(int64_t)15);
+      const gq_v4i x = __builtin_nontemporal_load(reinterpret_cast<const gq_v4i*>(p));
+      raw.lo[j] = ((uint64_t)(uint32_t)x.y << 32) | (uint32_t)x.x;
+      raw.hi[j] = ((uint64_t)(uint32_t)x.w << 32) | (uint32_t)x.z;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+      const DCol& c = a.st[j];
+      raw.lo[j] = r0 < a.n ? (uint64_t)load_one(c, r0) : 0;
+      raw.hi[j] = r0 + 1 < a.n ? (uint64_t)load_one(c, r0 + 1) : 0;
+    }
+  }
+}
+
+// The two rows' values of staged column j (sign-extended).
+__device__ __forceinline__ void rp_decode(const DCol& c, int64_t r0, bool full, uint64_t lo, uint64_t hi,
+                                          int64_t (&v)[2]) {
+  if (!full || c.type == GQ_I64) {
+    v[0] = (int64_t)lo;
+    v[1] = (int64_t)hi;
+    return;
+  }
+  const int w = type_width(c.type);
+  const int off = (int)((r0 * w) & 15);
+  const uint64_t u = ((off & 8) ? hi : lo) >> ((off & 7) * 8);
+  switch (c.type) {
+    case GQ_I8: v[0] = (int8_t)u; v[1] = (int8_t)(u >> 8); break;
+    case GQ_I16: v[0] = (int16_t)u; v[1] = (int16_t)(u >> 16); break;
+    default: v[0] = (int32_t)u; v[1] = (int32_t)(u >> 32); break;
+  }
+}
+
+// Rows r0, r0 + 1: the kept mask (below t1, predicates pass, key non-NULL)
+// and the region hashes of their keys.  The staged columns are visited in a
+// static loop and each role (predicate, key) tests whether it reads column j,
+// so that the register arrays are only ever indexed by compile-time constants
+// (an array indexed at run time would be placed in scratch memory).
+template <int NS>
+__device__ __forceinline__ uint32_t rp_eval_r(const RpArgs& a, int64_t r0, int64_t t1, bool full,
+                                              const RawStep<NS>& raw, uint64_t (&h)[2]) {
+  uint32_t keep = (r0 < t1 ? 1u : 0u) | (r0 + 1 < t1 ? 2u : 0u);
+  int64_t kv[2] = {0, 0};
+#pragma unroll
+  for (int j = 0; j < NS; ++j) {
+    const DCol& c = a.st[j];
+    int64_t v[2];
+    rp_decode(c, r0, full, raw.lo[j], raw.hi[j], v);
+    for (int p = 0; p < a.npreds; ++p) {
+      if (a.pred_st[p] != j) continue;
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+        if (!pred_pass(a.preds[p], v[k])) keep &= ~(1u << k);
+      if (c.valid) keep &= valid_items<2>(c, r0, a.n);
+    }
+    if (a.key_st == j) {
+      kv[0] = v[0];
+      kv[1] = v[1];
+      if (c.valid) keep &= valid_items<2>(c, r0, a.n);
+    }
+  }
+  h[0] = region_hash((uint64_t)kv[0]);
+  h[1] = region_hash((uint64_t)kv[1]);
+  return keep;
+}
+
+// One step of the histogram: the two rows' regions counted in LDS.
+template <int NS>
+__device__ __forceinline__ void rp_hist_step(const RpArgs& a, int64_t r0, int64_t t1, bool full,
+                                             const RawStep<NS>& raw, uint32_t* s_hist) {
+  uint64_t h[2];
+  const uint32_t keep = rp_eval_r<NS>(a, r0, t1, full, raw, h);
+#pragma unroll
+  for (int k = 0; k < 2; ++k)
+    if ((keep >> k) & 1u) atomicAdd(&s_hist[region_of(h[k], a.pbits)], 1u);
+}
+
+// The row loop of a tile: a lane's steps r0 = t0 + 2 * lane + k * 512.  In
+// every tile but the one that ends within 16 rows of the input's end, every
+// step reads whole chunks, and two register sets alternate: the loads of
+// step k + 1 (unconditional: past the tile they re-read step k's chunks, so
+// the number in flight is fixed and the wait before step k's use covers step
+// k's loads only) are issued before step k is processed, and no register copy
+// waits for loads in flight.  The last tile takes its steps one at a time.
+template <int NS>
+__device__ __forceinline__ void rp_hist_tile(const RpArgs& a, int64_t t0, int64_t t1, uint32_t* s_hist) {
+  constexpr int64_t STEP = (int64_t)kRpBlock * kRpItems;
+  int64_t r0 = t0 + (int64_t)threadIdx.x * kRpItems;
+  if (t1 + 16 > a.n) {
+    RawStep<NS> raw;
+    for (; r0 < t1; r0 += STEP) {
+      const bool full = r0 + 16 <= a.n;
+      rp_raw<NS>(a, r0, full, raw);
+      rp_hist_step<NS>(a, r0, t1, full, raw, s_hist);
+    }
+    return;
+  }
+  RawStep<NS> ra, rb;
+  if (r0 >= t1) return;
+  rp_raw<NS>(a, r0, true, ra);
+  for (;;) {
+    int64_t rn = r0 + STEP;
+    rp_raw<NS>(a, rn < t1 ? rn : r0, true, rb);
+    rp_hist_step<NS>(a, r0, t1, true, ra, s_hist);
+    if (rn >= t1) break;
+    r0 = rn;
+    rn = r0 + STEP;
+    rp_raw<NS>(a, rn < t1 ? rn : r0, true, ra);
+    rp_hist_step<NS>(a, r0, t1, true, rb, s_hist);
+    if (rn >= t1) break;
+    r0 = rn;
+  }
+}
+
+// Per tile, the histogram of the kept rows' regions (see k_rp_hist).
+template <int NS>
+__global__ __launch_bounds__(kRpBlock) void k_rp_hist_r(const RpArgs a) {
+  extern __shared__ __attribute__((aligned(16))) uint32_t s_hist[];
+  const int P = 1 << a.pbits;
+  for (int i = threadIdx.x; i < P; i += kRpBlock) s_hist[i] = 0;
+  if (blockIdx.x == 0)
+    for (int i = threadIdx.x; i < P; i += kRpBlock) a.rtot[i] = 0;
+  __syncthreads();
+  const int64_t tile = blockIdx.x;
+  const int64_t t0 = tile * a.tile_rows;
+  const int64_t t1 = t0 + a.tile_rows < a.n ? t0 + a.tile_rows : a.n;
+  rp_hist_tile<NS>(a, t0, t1, s_hist);
+  __syncthreads();
+  for (int i = threadIdx.x; i < P; i += kRpBlock) a.counts[tile * P + i] = s_hist[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -928,9 +1097,37 @@ constexpr size_t kRpMaxLds = 80 * 1024;  // two partition workgroups per CU
 
 // Histogram, scan and scatter of one side; a.counts/starts/okey... set by the
 // caller except the workspace, allocated here.  offsets: P + 1 int64.
+constexpr int kRpMaxReg = 5;  // columns of the register-path histogram
+
+template <int NS>
+int rp_launch_hist_reg(gq_ctx* ctx, const RpArgs& a, size_t lds, hipStream_t stream) {
+  GQ_LAUNCH(ctx, a.probe ? "rp_hist_probe" : "rp_hist_build", k_rp_hist_r<NS>, dim3((unsigned)a.ntiles),
+            dim3(kRpBlock), lds, stream, a);
+  GQ_LAUNCH_CHECK(ctx);
+  return GQ_OK;
+}
+
+int rp_launch_hist_reg_n(gq_ctx* ctx, const RpArgs& a, int ns, size_t lds, hipStream_t stream) {
+  switch (ns) {
+    case 1: return rp_launch_hist_reg<1>(ctx, a, lds, stream);
+    case 2: return rp_launch_hist_reg<2>(ctx, a, lds, stream);
+    case 3: return rp_launch_hist_reg<3>(ctx, a, lds, stream);
+    case 4: return rp_launch_hist_reg<4>(ctx, a, lds, stream);
+    default: return rp_launch_hist_reg<5>(ctx, a, lds, stream);
+  }
+}
+
 int rp_run(gq_ctx* ctx, RpArgs& a, int64_t* offsets, int64_t* total, hipStream_t stream) {
   const int64_t P = 1ll << a.pbits;
-  a.ntiles = (a.n + kRpTile - 1) / kRpTile;
+  // Tiles sized for about 2,048 workgroups.  The histogram reads its columns
+  // straight into registers when every one of them is 16-byte aligned (the
+  // usual case), else through LDS like the scatter.
+  int64_t t = kRpMinTile;
+  while (t < kRpMaxTile && t * 2048 < a.n) t *= 2;
+  a.tile_rows = t;
+  bool reg = a.nst_hist <= kRpMaxReg;
+  for (int j = 0; j < a.nst_hist; ++j) reg = reg && a.st[j].align >= 16;
+  a.ntiles = (a.n + a.tile_rows - 1) / a.tile_rows;
   if (a.ntiles == 0) {
     // No rows: every offset 0.
     int rc = launch_fill_u32(ctx, offsets, 0u, 2 * (P + 1), stream);
@@ -952,12 +1149,17 @@ int rp_run(gq_ctx* ctx, RpArgs& a, int64_t* offsets, int64_t* total, hipStream_t
   uint32_t* csum = ws.as<uint32_t>(off_csum);
   uint32_t* rtot = ws.as<uint32_t>(off_tot);
   a.rtot = rtot;
-  const size_t lds_hist = align_up((size_t)P * 4, 16) +
-                         ((size_t)a.st_off[a.nst_hist - 1] +
-                          align_up((size_t)kRpSub * type_width(a.st[a.nst_hist - 1].type), 16)) * kRpHScale;
-  GQ_LAUNCH(ctx, a.probe ? "rp_hist_probe" : "rp_hist_build", k_rp_hist, dim3((unsigned)a.ntiles), dim3(kRpBlock),
-            lds_hist, stream, a);
-  GQ_LAUNCH_CHECK(ctx);
+  if (reg) {
+    int rc = rp_launch_hist_reg_n(ctx, a, a.nst_hist, (size_t)P * 4, stream);
+    if (rc) return rc;
+  } else {
+    const size_t lds_hist = align_up((size_t)P * 4, 16) +
+                           ((size_t)a.st_off[a.nst_hist - 1] +
+                            align_up((size_t)kRpSub * type_width(a.st[a.nst_hist - 1].type), 16)) * kRpHScale;
+    GQ_LAUNCH(ctx, a.probe ? "rp_hist_probe" : "rp_hist_build", k_rp_hist, dim3((unsigned)a.ntiles), dim3(kRpBlock),
+              lds_hist, stream, a);
+    GQ_LAUNCH_CHECK(ctx);
+  }
   const dim3 cgrid((unsigned)nchunks, (unsigned)((P + 255) / 256));
   GQ_LAUNCH(ctx, a.probe ? "rp_scan_probe" : "rp_scan_build", k_cs_chunk, cgrid, dim3(256), 0, stream,
             (const uint32_t*)a.counts, a.ntiles, (int)P, csum, rtot);

@@ -42,6 +42,27 @@ JOIN_AGGS = [("sum", REV), ("count*",)]
 PART_COLS = [F_FKEY, F_PRICE, F_DATE, F_FLAG]   # 8 + 8 + 4 + 1 = 21 B per row
 
 
+# Radix group-join sizing of the library (a build side of at least 2^20 rows
+# is partitioned into 2^k regions of about 3,500 rows, k in 8..12; partition
+# tiles of 4,096 to 32,768 rows, about 2,048 of them), used to bound a join
+# query's memory.
+RADIX_MIN_BUILD = 1 << 20
+
+
+def radix_regions(build_rows: int) -> int:
+    k = 8
+    while k < 12 and (1 << k) * 3500 < build_rows:
+        k += 1
+    return 1 << k
+
+
+def radix_tiles(rows: int) -> int:
+    t = 4096
+    while t < 32768 and t * 2048 < rows:
+        t *= 2
+    return rows // t + 1
+
+
 @dataclass
 class Query:
     qid: int
@@ -218,10 +239,21 @@ class DeviceExecutor:
         if q.kind == "agg":
             return 64 << 20
         if q.kind == "join":
+            out = self.nd * 24 + (self.nd // 8 + 64) * 2      # key, sum, count per group; bitmaps
+            if self.nd >= RADIX_MIN_BUILD:
+                # Radix group-join: the build side's (hash, row) pairs and its
+                # per-(tile, region) counts, starts and chunk sums; the probe
+                # side's (hash, value) tuples at 16 B per fact row and the same
+                # count arrays; work items.
+                P = radix_regions(self.nd)
+                tf, td = radix_tiles(self.nf), radix_tiles(self.nd)
+                build = self.nd * 16 + td * P * 4 * 3 + P * 8
+                probe = self.nf * 16 + tf * P * 4 * 3 + (P + self.nd) * 8
+                return build + probe + out + (64 << 20)
             cap = 2 * self.nd + 1       # load factor 0.5 over every dimension row
             # keys, meta, 2 accumulators, run cursors per slot; rows and merge
             # buffer per build row; the output at one group per build row.
-            return cap * (8 + 8 + 16 + 4) + self.nd * 8 + self.nd * 24 + (64 << 20)
+            return cap * (8 + 8 + 16 + 4) + self.nd * 8 + out + (64 << 20)
         # filter output and partition output at 21 B per row, plus workspace
         return 2 * self.nf * 21 + (self.nf // 4096 + 1) * 256 * 12 + (256 << 20)
 

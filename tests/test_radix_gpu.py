@@ -236,3 +236,55 @@ def test_build_on_another_stream(gq, ctx, radix, alloc):
     ek, ea = canon_groups(exp.keys, exp.aggs)
     for (gv, _), (ev, _) in zip(gk + ga, ek + ea):
         assert np.array_equal(gv, ev)
+
+
+def test_radix_register_path_column_types(gq, ctx):
+    # The register-path histogram loads its columns as 16-byte chunks and
+    # extracts two rows per lane: int8 and int16 predicate columns and an
+    # int16 key on the probe side (with int32 and nullable int64 values for the
+    # scatter), an int8 predicate on the build side; both sides end in a
+    # ragged tail.
+    rng = np.random.default_rng(41)
+    nb, npr = MIN_BUILD + 13, 1_700_009
+    build = tbl(k=rng.integers(-30_000, 30_000, nb).astype(np.int16),
+                f=rng.integers(-3, 4, nb).astype(np.int8))
+    probe = tbl(k=rng.integers(-32_000, 32_000, npr).astype(np.int16),
+                p8=rng.integers(-100, 100, npr).astype(np.int8),
+                p16=rng.integers(-1000, 1000, npr).astype(np.int16),
+                v32=rng.integers(-10**9, 10**9, npr).astype(np.int32),
+                v64=(rng.integers(-10**15, 10**15, npr), rng.random(npr) > 0.07))
+    aggs = [("sum", [("col", 3), ("k-col", 7, 1)]), ("max", [("col", 4)]), ("count*",), ("count", [("col", 4)])]
+    check_pipeline(gq, ctx, probe, [("range", 1, -60, 90), ("ne", 2, 5)], [0], aggs,
+                   join_spec=(build, [0], [("range", 1, -2, 3)], 0))
+
+
+def test_radix_staged_path_unaligned_and_wide(gq, ctx):
+    # Columns that are not 16-byte aligned (slices starting at row 1): the
+    # histogram stages them through LDS like the scatter, on both sides.
+    rng = np.random.default_rng(42)
+    nb, npr = MIN_BUILD + 3, 1_200_001
+    build = tbl(k=rng.integers(0, 500_000, nb + 1), d=rng.integers(0, 10, nb + 1).astype(np.int32))
+    probe = tbl(k=rng.integers(0, 600_000, npr + 1), a=rng.integers(0, 9, npr + 1).astype(np.int8),
+                b=rng.integers(0, 9, npr + 1).astype(np.int16), c=rng.integers(0, 9, npr + 1).astype(np.int32),
+                d=rng.integers(0, 9, npr + 1), v=rng.integers(-99, 99, npr + 1))
+    # Row-1 slices on the device, and the matching host tables for the oracle.
+    from paper_2606_24647_amd.datagen import Column, Table
+    hb = Table([Column(c.name, c.data[1:]) for c in build.cols])
+    hp = Table([Column(c.name, c.data[1:]) for c in probe.cols])
+    bd, pd_ = gq.to_device(build), gq.to_device(probe)
+    for c in bd.cols + pd_.cols:
+        c.offset = 1
+    preds = [("range", 1, 1, 8), ("range", 2, 0, 7), ("ne", 3, 4), ("range", 4, 1, 8)]
+    aggs = [("sum", [("col", 5)]), ("max", [("col", 5), ("col", 4)]), ("count*",)]
+    jt = ctx.join_build(bd, [0], [("range", 1, 0, 7)], acc_slots=2)
+    out, cnt = ctx.pipeline(pd_, preds, [0], aggs, join=jt, probe_key=0)
+    ctx.raise_status()
+    n = int(cnt.item())
+    cols = gq.read_table(out, n)
+    jt.free()
+    exp = oracle.pipeline(hp, preds, [0], aggs, join_spec=(hb, [0], [("range", 1, 0, 7)], [0]))
+    assert n == exp.nrows
+    gk, ga = canon_groups([(cols[0][0].astype(np.int64), cols[0][1])], cols[1:])
+    ek, ea = canon_groups(exp.keys, exp.aggs)
+    for (gv, gok), (ev, eok) in zip(gk + ga, ek + ea):
+        assert np.array_equal(gok, eok) and np.array_equal(gv, ev)

@@ -9,7 +9,10 @@ from paper_2606_24647_amd import serve
 
 pytestmark = pytest.mark.gpu
 
-NF, ND = 2_000_000, 400_000
+# A dimension of more than 2^20 rows: every join query takes the radix
+# group-join (probe partition, build on its own stream, LDS join), the path the
+# full-size serving run takes.
+NF, ND = 3_000_000, 1_200_000
 
 
 @pytest.fixture(scope="module")
@@ -27,8 +30,15 @@ def test_alone_equals_mix(env, max_heavy):
     gq, torch, fact, dim = env
     qs = serve.make_workload(36, qps=2000.0, seed=3)
     mixed_ex = serve.DeviceExecutor(gq, torch, fact, dim, nslots=4, max_heavy=max_heavy)
+    for c in mixed_ex.ctxs:
+        c.set_timing(True)
     mixed = serve.Scheduler(mixed_ex, budget_bytes=1 << 40).run(qs, keep_results=True)
     assert len(mixed) == len(qs)
+    launched = set()
+    for c in mixed_ex.ctxs:
+        launched |= set(c.timing_report())
+        c.set_timing(False)
+    assert "rj_join" in launched and "rp_scatter_probe" in launched, sorted(launched)
     alone_ex = serve.DeviceExecutor(gq, torch, fact, dim, nslots=1)
     by_id = {r.qid: r for r in mixed}
     for q in qs:
