@@ -314,26 +314,38 @@ __global__ __launch_bounds__(256) void k_cs_fill(const uint32_t* counts, const u
 }
 
 // LDS layout of k_rp_scatter (dynamic): the tile's next write position of
-// every region (u32), then the staged input (in_bytes).
+// every region (u32), then two buffers of staged input (in_bytes each).
 __host__ __device__ inline size_t rp_scatter_lds(int P, int in_bytes) {
-  return align_up((size_t)P * 4, 16) + align_up((size_t)in_bytes, 16);
+  return align_up((size_t)P * 4, 16) + 2 * align_up((size_t)in_bytes, 16);
 }
 
+// Per tile, sub-tiles of kRpSub rows staged in LDS, double-buffered: the
+// global-to-LDS loads of sub-tile k + 1 are issued before sub-tile k is
+// processed, so they are in flight during its LDS atomics and scattered
+// stores; one wait and one barrier per sub-tile.
 __global__ __launch_bounds__(kRpSBlock) void k_rp_scatter(const RpArgs a) {
   extern __shared__ __attribute__((aligned(16))) uint8_t s_raw[];
   const int P = 1 << a.pbits;
   uint32_t* s_pos = reinterpret_cast<uint32_t*>(s_raw);
-  uint8_t* s_in = s_raw + align_up((size_t)P * 4, 16);
+  uint8_t* s_buf0 = s_raw + align_up((size_t)P * 4, 16);
+  const size_t bstride = align_up((size_t)a.in_bytes, 16);
   const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int64_t tbase = tile * a.tile_rows;
+  const int64_t trows = a.n - tbase < a.tile_rows ? a.n - tbase : a.tile_rows;
+  const int64_t nsub = (trows + kRpSub - 1) / kRpSub;
   for (int q = threadIdx.x; q < P; q += kRpSBlock) s_pos[q] = a.starts[tile * P + q];
-  for (int64_t sub = 0; sub < a.tile_rows / kRpSub; ++sub) {
-    const int64_t sbase = tile * a.tile_rows + sub * kRpSub;
-    if (sbase >= a.n) break;
+  rp_stage<kRpSBlock>(a, a.nst, 1, tbase, trows < kRpSub ? (int)trows : kRpSub, s_buf0);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  for (int64_t sub = 0; sub < nsub; ++sub) {
+    const int64_t sbase = tbase + sub * kRpSub;
     const int nrows = a.n - sbase < kRpSub ? (int)(a.n - sbase) : kRpSub;
-    __syncthreads();  // previous sub-tile's rows written
-    rp_stage<kRpSBlock>(a, a.nst, 1, sbase, nrows, s_in);
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
+    const uint8_t* s_in = s_buf0 + (sub & 1) * bstride;
+    if (sub + 1 < nsub) {
+      const int64_t nbase = sbase + kRpSub;
+      rp_stage<kRpSBlock>(a, a.nst, 1, nbase, a.n - nbase < kRpSub ? (int)(a.n - nbase) : kRpSub,
+                          s_buf0 + ((sub + 1) & 1) * bstride);
+    }
     int64_t key[kRpRows];
     const uint32_t keep = rp_rows_keep<kRpRows, kRpSBlock>(a, s_in, 1, sbase, nrows, key);
 #pragma unroll
@@ -383,6 +395,10 @@ __global__ __launch_bounds__(kRpSBlock) void k_rp_scatter(const RpArgs a) {
         *reinterpret_cast<u64x2*>(a.okey + 2 * (size_t)g) = u64x2{h, (uint64_t)(sbase + r)};
       }
     }
+    // The next sub-tile's loads have landed (every thread's), and every thread
+    // is done with this buffer before it is refilled.
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
   }
 }
 
@@ -1092,7 +1108,7 @@ struct StageBuilder {
   }
 };
 
-constexpr size_t kRpMaxLds = 80 * 1024;  // two partition workgroups per CU
+constexpr size_t kRpMaxLds = 160 * 1024;  // LDS of one workgroup
 
 
 // Histogram, scan and scatter of one side; a.counts/starts/okey... set by the
