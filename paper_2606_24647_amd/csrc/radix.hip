@@ -583,6 +583,15 @@ struct RjJoinArgs {
   int32_t vword[GQ_MAX_AGGS];   // value word of aggregate i in the tuple, -1 if none
   int32_t sums_only;            // every aggregate is COUNT(*) or a SUM of a non-NULL input
   int32_t sum_word[kRjMaxVals]; // then: accumulator word of value word v
+  // Emission of aggregate i (all output columns 8 bytes wide: emit64): its
+  // accumulator word, whether the build multiplicity scales it (SUM, COUNT,
+  // COUNT(*)), and the count word that makes it NULL when zero (-1: never).
+  // Plain arrays read at constant offsets, so that they stay in scalar
+  // registers for the whole item instead of being re-read per slot.
+  int32_t emit64;
+  int32_t e_word[GQ_MAX_AGGS];
+  int32_t e_mul[GQ_MAX_AGGS];
+  int32_t e_cword[GQ_MAX_AGGS];
   uint64_t ident[kMaxAcc];      // initial value of every accumulator word (word_identity of its wop)
   const uint64_t* bkey;     // build (key hash, row) pairs grouped by region
   const int64_t* boff;      // P + 1
@@ -878,9 +887,10 @@ __device__ __forceinline__ void rj_probe_round(const RjJoinArgs& a, RjRound<NV>&
 
 // Validity bits of output rows [obase, obase + tot) (clipped to out_cap) of
 // one output column: bit rel of the staging words (rel = row - (obase & ~31))
-// is the bit of row obase - (obase & 31) + rel.  Words wholly inside the range
-// are stored; the first and last words, shared with the neighbouring items'
-// rows, are updated with an atomic AND of the range's bits and an OR.
+// is the bit of row obase - (obase & 31) + rel (s_vw NULL: every row valid).
+// Words wholly inside the range are stored; the first and last words, shared
+// with the neighbouring items' rows, are updated with an atomic AND of the
+// range's bits and an OR.
 __device__ __forceinline__ void rj_store_valid(uint32_t* words, const uint32_t* s_vw, int64_t obase, int64_t tot,
                                                int64_t out_cap) {
   int64_t end = obase + tot;
@@ -891,7 +901,7 @@ __device__ __forceinline__ void rj_store_valid(uint32_t* words, const uint32_t* 
     const int64_t lo = w * 32 > obase ? w * 32 : obase;
     const int64_t hi = w * 32 + 32 < end ? w * 32 + 32 : end;
     const uint32_t mask = (hi - lo == 32) ? ~0u : (((1u << (uint32_t)(hi - lo)) - 1u) << (uint32_t)(lo - w * 32));
-    const uint32_t bits = s_vw[w - w0] & mask;
+    const uint32_t bits = (s_vw ? s_vw[w - w0] : ~0u) & mask;
     if (mask == ~0u) {
       words[w] = bits;
     } else {
@@ -933,29 +943,37 @@ __global__ __launch_bounds__(kRjBlock) __attribute__((amdgpu_waves_per_eu(4))) v
   uint64_t cur = kNoItem;
   if (threadIdx.x == 0) cur = rj_next(a, s_qoff, home, qi, atomicAdd(&a.qticket[home], 1u));
   const int nchunks = (L + kRjBlock) / kRjBlock;  // chunks covering slots 0..L
-  for (;;) {
-    if (threadIdx.x == 0) s_item = cur;
-    lds_barrier();
-    const uint64_t item = s_item;
-    if (item == kNoItem) break;
-    const uint32_t p = item_region(item), s = item_sub(item), S = item_nsub(item);
-    uint32_t tnext = 0;
-    if (threadIdx.x == 0 && qi < kXcds) tnext = atomicAdd(&a.qticket[(home + qi) % kXcds], 1u);
-
-    // 1. Loads of the first build keys and the first probe round, in flight
-    // while the table is cleared.
-    const int64_t b0 = a.boff[p], b1 = a.boff[p + 1];
-    const int64_t t0 = a.toff[p], t1 = a.toff[p + 1];
-    // (Indices past the region re-read its last pair: unconditional loads
-    // stay in flight together.)
-    uint64_t bh[kRjUnroll];
+  if (threadIdx.x == 0) s_item = cur;
+  lds_barrier();
+  uint64_t item = s_item;
+  // The loads of an item (its region's offsets, its first build keys and its
+  // first probe round) are issued as soon as the item is known: for the first
+  // item here, for every later one right after the previous item's probe, so
+  // that they are in flight while that item's groups are written out.
+  // (Indices past the region re-read its last pair: unconditional loads stay
+  // in flight together.)
+  uint64_t bh[kRjUnroll];
+  RjRound<NV> ra, rb;
+  int64_t b0 = 0, b1 = 0, t0 = 0, t1 = 0;
+  if (item != kNoItem) {
+    const uint32_t p = item_region(item);
+    b0 = a.boff[p];
+    b1 = a.boff[p + 1];
+    t0 = a.toff[p];
+    t1 = a.toff[p + 1];
 #pragma unroll
     for (int u = 0; u < kRjUnroll; ++u) {
       const int64_t i = b0 + (int64_t)u * kRjBlock + threadIdx.x;
       bh[u] = a.bkey[2 * (i < b1 ? i : (b1 > 0 ? b1 - 1 : 0))];
     }
-    RjRound<NV> ra, rb;
     rj_load_round<NV, NN>(a, t0, t1, ra);
+  }
+  while (item != kNoItem) {
+    const uint32_t s = item_sub(item), S = item_nsub(item);
+    uint32_t tnext = 0;
+    if (threadIdx.x == 0 && qi < kXcds) tnext = atomicAdd(&a.qticket[(home + qi) % kXcds], 1u);
+
+    // 1. The table is cleared while the item's loads are in flight.
     for (int i = threadIdx.x; i < NS; i += kRjBlock) {
       s_keys[i] = kEmpty;
       s_mult[i] = 0;
@@ -987,8 +1005,12 @@ __global__ __launch_bounds__(kRjBlock) __attribute__((amdgpu_waves_per_eu(4))) v
       }
     }
     lds_barrier();
-    // The next item, resolved while this one is probed.
-    if (threadIdx.x == 0) cur = rj_next(a, s_qoff, home, qi, tnext);
+    // The next item, resolved while this one is probed (every thread reads it
+    // after the barrier that ends the probe).
+    if (threadIdx.x == 0) {
+      cur = rj_next(a, s_qoff, home, qi, tnext);
+      s_item = cur;
+    }
     // 3. Probe rounds, two register sets alternating: the loads of the next
     // round are in flight while the current one is probed.
     constexpr int64_t R = (int64_t)kRjBlock * kRjProbeUnroll;
@@ -1001,6 +1023,21 @@ __global__ __launch_bounds__(kRjBlock) __attribute__((amdgpu_waves_per_eu(4))) v
       if (base + R < t1) rj_probe_round<NV>(a, rb, s_keys, s_acc, s_mult, L, s, S, dump);
     }
     lds_barrier();
+    // The next item's loads, in flight while this item's groups are written.
+    item = s_item;
+    if (item != kNoItem) {
+      const uint32_t p = item_region(item);
+      b0 = a.boff[p];
+      b1 = a.boff[p + 1];
+      t0 = a.toff[p];
+      t1 = a.toff[p + 1];
+#pragma unroll
+      for (int u = 0; u < kRjUnroll; ++u) {
+        const int64_t i = b0 + (int64_t)u * kRjBlock + threadIdx.x;
+        bh[u] = a.bkey[2 * (i < b1 ? i : (b1 > 0 ? b1 - 1 : 0))];
+      }
+      rj_load_round<NV, NN>(a, t0, t1, ra);
+    }
     // 4. Matched groups (row count non-zero) to the output, in slot order:
     // per chunk of kRjBlock slots the wave counts, one output range per item.
     uint32_t occm = 0;
@@ -1040,8 +1077,21 @@ __global__ __launch_bounds__(kRjBlock) __attribute__((amdgpu_waves_per_eu(4))) v
         const int64_t g = obase + rel;
         const uint64_t mult = s_mult[i];
         s_mult[i] = (uint32_t)rel;  // the slot's output row, for the validity bits below
-        if (g < a.out_cap) {
+        if (g < a.out_cap && a.emit64) {
           // Slot L holds the key whose region hash is all ones.
+          const uint64_t key = region_unhash(s_keys[i]);
+          reinterpret_cast<uint64_t*>(a.out[0].data)[g] = key;
+          if (a.sorted) reinterpret_cast<uint64_t*>(a.sortkey.data)[g] = key ^ (1ull << 63);
+          const uint64_t* acc = s_acc + (size_t)i * a.nacc;
+#pragma unroll
+          for (int j = 0; j < GQ_MAX_AGGS; ++j) {
+            if (j >= a.naggs) break;
+            uint64_t v = acc[a.e_word[j]];
+            if (a.e_mul[j]) v *= mult;
+            if (a.e_cword[j] >= 0 && acc[a.e_cword[j]] == 0) v = 0;
+            reinterpret_cast<uint64_t*>(a.out[1 + j].data)[g] = v;
+          }
+        } else if (g < a.out_cap) {
           const uint64_t key = region_unhash(s_keys[i]);
           rj_write(a.out[0], g, (int64_t)key);
           if (a.sorted) reinterpret_cast<uint64_t*>(a.sortkey.data)[g] = key ^ (1ull << 63);
@@ -1067,23 +1117,26 @@ __global__ __launch_bounds__(kRjBlock) __attribute__((amdgpu_waves_per_eu(4))) v
       const int aop = oc ? a.ap.aggs[oc - 1].op : GQ_COUNT_STAR;
       const int cword = oc ? a.ap.aggs[oc - 1].cword : -1;
       const bool maybe_null = (aop == GQ_SUM || aop == GQ_MIN || aop == GQ_MAX) && cword >= 0;
+      if (!maybe_null) {
+        // Every row of the item valid: the words are written directly.
+        rj_store_valid(a.out[oc].valid, nullptr, obase, otot, a.out_cap);
+        continue;
+      }
       lds_barrier();
-      if (maybe_null) {
-        for (int w = threadIdx.x; w < VW; w += kRjBlock) s_vw[w] = 0;
-        lds_barrier();
-        for (int c = 0; c < nchunks; ++c) {
-          const int i = c * kRjBlock + threadIdx.x;
-          if (!((occm >> c) & 1u)) continue;
-          if (s_acc[(size_t)i * a.nacc + cword] == 0) continue;
-          const int64_t b = shift + (int64_t)s_mult[i];
-          atomicOr(&s_vw[b >> 5], 1u << (b & 31));
-        }
-      } else {
-        for (int w = threadIdx.x; w < VW; w += kRjBlock) s_vw[w] = ~0u;
+      for (int w = threadIdx.x; w < VW; w += kRjBlock) s_vw[w] = 0;
+      lds_barrier();
+      for (int c = 0; c < nchunks; ++c) {
+        const int i = c * kRjBlock + threadIdx.x;
+        if (!((occm >> c) & 1u)) continue;
+        if (s_acc[(size_t)i * a.nacc + cword] == 0) continue;
+        const int64_t b = shift + (int64_t)s_mult[i];
+        atomicOr(&s_vw[b >> 5], 1u << (b & 31));
       }
       lds_barrier();
       rj_store_valid(a.out[oc].valid, s_vw, obase, otot, a.out_cap);
     }
+    // Every thread is done reading this item's table before it is cleared.
+    lds_barrier();
   }
 }
 
@@ -1341,6 +1394,14 @@ int rj_groupjoin(gq_ctx* ctx, const gq_batch* in, int32_t probe_key, const gq_pr
     if (ag.op == GQ_COUNT_STAR) continue;
     if (ag.op != GQ_SUM || ag.cword >= 0 || j.vword[i] < 0) j.sums_only = 0;
     else j.sum_word[j.vword[i]] = ag.word;
+  }
+  j.emit64 = type_width(ca.out[0].type) == 8;
+  for (int i = 0; i < ap.naggs; ++i) {
+    const DAgg& ag = ap.aggs[i];
+    j.emit64 = j.emit64 && type_width(ca.out[1 + i].type) == 8;
+    j.e_word[i] = ag.word;
+    j.e_mul[i] = ag.op == GQ_SUM || ag.op == GQ_COUNT || ag.op == GQ_COUNT_STAR;
+    j.e_cword[i] = (ag.op == GQ_SUM || ag.op == GQ_MIN || ag.op == GQ_MAX) ? ag.cword : -1;
   }
   j.bkey = t->rj_kr;
   j.boff = t->rj_off;
