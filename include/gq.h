@@ -535,6 +535,30 @@ typedef struct gq_plan {
 int gq_pipeline(gq_ctx* ctx, const gq_plan* plan, const gq_batch* in, gq_batch* out,
                 int64_t* d_groups, hipStream_t stream);
 
+/* Shared probe side: nq filter -> group-join pipelines over one probe input
+ * that differ only in their join table and in one range predicate on the
+ * probe side (Section 3: the pipelines of concurrent queries run side by side
+ * over the same resident tables; here they also share the probe side's scan
+ * and partition).  Query i equals gq_pipeline with preds = plan->preds plus
+ * ranges[i] and join = tables[i], output outs[i] and group count d_groups[i]
+ * (device int64).  The probe side is partitioned once, keeping the rows that
+ * pass plan->preds and lie in the hull of the ranges, each kept row's value of
+ * the range column carried in its tuple; each query's join takes only the
+ * tuples whose carried value lies in its own range.
+ *  plan     preds, probe_key, group_keys = {probe_key} (the group-join shape),
+ *           aggs, opts (single mode; GQ_SORTED honoured); plan->join must be
+ *           NULL (the tables are per query).
+ *  tables   nq tables from gq_join_build, each partitioned (built over at
+ *           least 2^20 rows) with the same region count (same build input row
+ *           count and regions_log2).
+ *  ranges   nq GQ_RANGE predicates, all on the same column of `in`.
+ * Everything runs on `stream`; each query's join waits for its own table's
+ * build.  Errors: GQ_ERR_INVALID (arguments), GQ_ERR_UNSUPPORTED (shape,
+ * unpartitioned or mismatched tables; nothing enqueued), GQ_ERR_NOMEM. */
+int gq_pipeline_shared(gq_ctx* ctx, const gq_plan* plan, const gq_batch* in, int32_t nq,
+                       const gq_join_table* const* tables, const gq_pred* ranges, gq_batch* const* outs,
+                       int64_t* const* d_groups, hipStream_t stream);
+
 /* ---- batched fragments ----------------------------------------------------------
  * Many independent filter + group-by fragments of very different sizes run as
  * one plan: one persistent launch over tiles of all fragments, captured once in

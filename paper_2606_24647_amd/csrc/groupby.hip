@@ -862,4 +862,75 @@ int gq_pipeline(gq_ctx* ctx, const gq_plan* plan, const gq_batch* in, gq_batch* 
                      &plan->opts, plan->join, plan->probe_key, out, d_groups, stream);
 }
 
+int gq_pipeline_shared(gq_ctx* ctx, const gq_plan* plan, const gq_batch* in, int32_t nq,
+                       const gq_join_table* const* tables, const gq_pred* ranges, gq_batch* const* outs,
+                       int64_t* const* d_groups, hipStream_t stream) {
+  if (!ctx) return GQ_ERR_INVALID;
+  if (!plan || nq < 1 || !tables || !ranges || !outs || !d_groups)
+    return set_error(ctx, GQ_ERR_INVALID, "gq_pipeline_shared: NULL argument or no query");
+  int rc = check_batch(ctx, in, "shared pipeline input");
+  if (rc) return rc;
+  if (plan->join) return set_error(ctx, GQ_ERR_INVALID, "gq_pipeline_shared: the tables are passed per query");
+  const int32_t pk = plan->probe_key;
+  if (pk < 0 || pk >= in->ncols) return set_error(ctx, GQ_ERR_INVALID, "gq_pipeline_shared: probe key out of range");
+  if (plan->ngroup_keys != 1 || !plan->group_keys || plan->group_keys[0] != pk)
+    return set_error(ctx, GQ_ERR_UNSUPPORTED, "gq_pipeline_shared: the only group key must be the probe key");
+  if (plan->opts.mode != GQ_MODE_SINGLE)
+    return set_error(ctx, GQ_ERR_UNSUPPORTED, "gq_pipeline_shared: single-mode aggregation only");
+  if (plan->npreds < 0 || plan->npreds + 1 > GQ_MAX_PREDS || (plan->npreds > 0 && !plan->preds))
+    return set_error(ctx, GQ_ERR_INVALID, "gq_pipeline_shared: too many predicates");
+  const int32_t rcol = ranges[0].col;
+  int64_t lo = INT64_MAX, hi = INT64_MIN;
+  for (int i = 0; i < nq; ++i) {
+    if (ranges[i].op != GQ_RANGE || ranges[i].col != rcol)
+      return set_error(ctx, GQ_ERR_INVALID, "gq_pipeline_shared: every query range is a GQ_RANGE on one column");
+    if (ranges[i].lo < lo) lo = ranges[i].lo;
+    if (ranges[i].hi > hi) hi = ranges[i].hi;
+    const gq_join_table* t = tables[i];
+    if (!t || !d_groups[i]) return set_error(ctx, GQ_ERR_INVALID, "gq_pipeline_shared: NULL table or group count");
+    if (t->device != ctx->device) return set_error(ctx, GQ_ERR_INVALID, "gq_pipeline_shared: table on another device");
+    if (!t->rj_kr || t->rj_pbits != tables[0]->rj_pbits)
+      return set_error(ctx, GQ_ERR_UNSUPPORTED,
+                       "gq_pipeline_shared: every table must be partitioned with the same region count");
+  }
+  // The probe side keeps the rows of the hull of the ranges.
+  gq_pred preds[GQ_MAX_PREDS];
+  for (int p = 0; p < plan->npreds; ++p) preds[p] = plan->preds[p];
+  preds[plan->npreds] = gq_pred{rcol, GQ_RANGE, lo, hi};
+  const int npreds = plan->npreds + 1;
+  GbArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.n = in->nrows;
+  rc = make_preds(ctx, a, in, preds, npreds);
+  if (rc) return rc;
+  rc = make_agg_plan(ctx, a.ap, in, plan->aggs, plan->naggs);
+  if (rc) return rc;
+  if (!rj_usable(tables[0], in, pk, preds, npreds, a.ap, rcol))
+    return set_error(ctx, GQ_ERR_UNSUPPORTED, "gq_pipeline_shared: the radix group-join does not take this input");
+  std::vector<CompactArgs> ca(nq);
+  const int kt[1] = {in->cols[pk].type};
+  for (int i = 0; i < nq; ++i) {
+    std::memset(&ca[i], 0, sizeof(CompactArgs));
+    ca[i].naggs = plan->naggs;
+    for (int g = 0; g < plan->naggs; ++g) ca[i].aggs[g] = a.ap.aggs[g];
+    rc = check_outputs(ctx, 1, plan->naggs, outs[i], ca[i], kt);
+    if (rc) return rc;
+    ca[i].key_kind = 2;
+    ca[i].extra = 1;
+  }
+  GQ_HIP_CHECK(ctx, hipSetDevice(ctx->device));
+  RjPart* part = nullptr;
+  rc = rj_part_create(ctx, in, pk, preds, npreds, rcol, a.ap, tables[0]->rj_pbits, stream, &part);
+  if (rc) return rc;
+  const bool sorted = (plan->opts.flags & GQ_SORTED) != 0;
+  for (int i = 0; i < nq && rc == GQ_OK; ++i) {
+    const std::function<int(CompactArgs&)> emit = [&](CompactArgs& target) {
+      return rj_part_join(ctx, part, a.ap, tables[i], ranges[i].lo, ranges[i].hi, target, d_groups[i], stream);
+    };
+    rc = finish_groups(ctx, ca[i], outs[i], d_groups[i], sorted, stream, &emit);
+  }
+  rj_part_destroy(part);
+  return rc;
+}
+
 }  // extern "C"

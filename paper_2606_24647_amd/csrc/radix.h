@@ -44,9 +44,10 @@ int rj_kpr(int lcap);
 // t->rj_kr / t->rj_off; the kept count goes to t->hdr->nrows.
 int rj_build(gq_ctx* ctx, const gq_batch* build, int32_t key_col, const gq_pred* preds, int npreds,
              gq_join_table* t, hipStream_t stream);
-// Whether a group-join of `in` with this aggregate plan can take the radix path.
+// Whether a group-join of `in` with this aggregate plan can take the radix
+// path (carry_col: a column whose value every probe tuple carries, or -1).
 bool rj_usable(const gq_join_table* t, const gq_batch* in, int32_t probe_key, const gq_pred* preds, int npreds,
-               const AggPlan& ap);
+               const AggPlan& ap, int32_t carry_col = -1);
 // Whether the build side's partition pass fits its staging limits.
 bool rj_build_fits(const gq_batch* build, int32_t key_col, const gq_pred* preds, int npreds, int pbits);
 // Group-join of `in` (rows passing preds, keyed by column probe_key) with the
@@ -55,6 +56,21 @@ bool rj_build_fits(const gq_batch* build, int32_t key_col, const gq_pred* preds,
 int rj_groupjoin(gq_ctx* ctx, const gq_batch* in, int32_t probe_key, const gq_pred* preds, int npreds,
                  const AggPlan& ap, const gq_join_table* t, const CompactArgs& ca, int64_t* d_groups,
                  hipStream_t stream);
+
+// A probe side partitioned once and joined with several tables (every table
+// built over an input of the same row count, hence the same region count):
+// rj_part_create partitions the rows of `in` that pass preds, each tuple
+// carrying the value of column carry_col when carry_col >= 0; rj_part_join
+// group-joins it with t, only tuples whose carried value lies in
+// [carry_lo, carry_hi] taking part (bounds ignored without a carried column);
+// rj_part_destroy releases the workspace, stream-ordered on the creating
+// stream, so joins enqueued on that stream may still read it.
+struct RjPart;
+int rj_part_create(gq_ctx* ctx, const gq_batch* in, int32_t probe_key, const gq_pred* preds, int npreds,
+                   int32_t carry_col, const AggPlan& ap, int pbits, hipStream_t stream, RjPart** out);
+int rj_part_join(gq_ctx* ctx, const RjPart* part, const AggPlan& ap, const gq_join_table* t, int64_t carry_lo,
+                 int64_t carry_hi, const CompactArgs& ca, int64_t* d_groups, hipStream_t stream);
+void rj_part_destroy(RjPart* part);
 
 // Build the probe index of a table whose build side was partitioned, if not
 // built yet (on `stream`; later users on other streams must be ordered after it).

@@ -100,6 +100,8 @@ struct RpArgs {
   DPred preds[GQ_MAX_PREDS];
   AggPlan ap;
   int32_t vagg[kRjMaxVals];      // probe: aggregate whose input is value word j
+  int32_t carry_st;              // probe: staged column whose value is the tuple's last word (-1: none)
+  int32_t pad_carry;
   uint32_t* counts;        // [p * ntiles + tile]
   uint32_t* starts;        // exclusive scan of counts
   uint32_t* rtot;          // region totals of the column scan, zeroed by the histogram
@@ -366,7 +368,14 @@ __global__ __launch_bounds__(kRpSBlock) void k_rp_scatter(const RpArgs a) {
           bool nn = true;
           x[v] = rp_value_row(a, a.ap.aggs[a.vagg[v]], s_in, r, sbase + r, &nn);
         }
-        if (a.nv == 1) {
+        if (a.carry_st >= 0) {
+          // Hash, values, then the carried column's value.
+          t[0] = h;
+#pragma unroll
+          for (int v = 0; v < kRjMaxVals; ++v)
+            if (v < a.nv) t[1 + v] = x[v];
+          t[1 + a.nv] = (uint64_t)lds_value(s_in + a.st_off[a.carry_st], r, a.st[a.carry_st].type);
+        } else if (a.nv == 1) {
           typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
           *reinterpret_cast<u64x2*>(t) = u64x2{h, x[0]};
         } else {
@@ -596,8 +605,10 @@ struct RjJoinArgs {
   const uint64_t* bkey;     // build (key hash, row) pairs grouped by region
   const int64_t* boff;      // P + 1
   const uint64_t* tkey;     // probe tuple key hashes grouped by region
-  int32_t tw;               // words per probe tuple: hash, then nv values
+  int32_t tw;               // words per probe tuple: hash, then nv values (then the carried value)
   int32_t pad_tw;
+  int64_t carry_lo;         // with a carried value: only tuples whose value lies in
+  int64_t carry_hi;         //   [carry_lo, carry_hi] take part
   const uint8_t* tnn;
   const int64_t* toff;      // P + 1
   uint64_t* items;          // work items of all queues: region | sub-region << 16 | S << 40
@@ -746,22 +757,25 @@ struct RjRound {
 
 // Issue the loads of the tuples base + u * kRjBlock + tid (u < kRjProbeUnroll)
 // that lie below t1; the others re-read the last tuple (tuple 0 of the
-// buffer when t1 is 0) and are inactive.
-// Straight-line code (NV and NN fixed at compile time), so that every load of
-// the round is in flight before the first is used.
-template <int NV, bool NN>
+// buffer when t1 is 0) and are inactive.  With CARRY the tuple's last word is
+// a carried column value, and a tuple whose value lies outside
+// [carry_lo, carry_hi] is inactive too.
+// Straight-line code (NV, NN and CARRY fixed at compile time), so that every
+// load of the round is in flight before the first is used.
+template <int NV, bool NN, bool CARRY>
 __device__ __forceinline__ void rj_load_round(const RjJoinArgs& a, int64_t base, int64_t t1, RjRound<NV>& r) {
+  typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
   r.act = 0;
+  int64_t cv[kRjProbeUnroll];
 #pragma unroll
   for (int u = 0; u < kRjProbeUnroll; ++u) {
     const int64_t i = base + (int64_t)u * kRjBlock + threadIdx.x;
     const int64_t ic = i < t1 ? i : (t1 > 0 ? t1 - 1 : 0);
-    const uint64_t* tp = a.tkey + (size_t)ic * (1 + NV);
+    const uint64_t* tp = a.tkey + (size_t)ic * (1 + NV + (CARRY ? 1 : 0));
     if constexpr (NV == 0) {
       r.h[u] = tp[0];
       r.x[u][0] = 0;
     } else if constexpr (NV == 1) {
-      typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
       const u64x2 tv = *reinterpret_cast<const u64x2*>(tp);
       r.h[u] = tv.x;
       r.x[u][0] = tv.y;
@@ -770,9 +784,16 @@ __device__ __forceinline__ void rj_load_round(const RjJoinArgs& a, int64_t base,
 #pragma unroll
       for (int v = 0; v < NV; ++v) r.x[u][v] = tp[1 + v];
     }
+    cv[u] = CARRY ? (int64_t)tp[1 + NV] : 0;
     if constexpr (NN) r.nn[u] = a.tnn[ic];
     else r.nn[u] = 0xffu;
-    if (i < t1) r.act |= 1u << u;
+  }
+#pragma unroll
+  for (int u = 0; u < kRjProbeUnroll; ++u) {
+    const int64_t i = base + (int64_t)u * kRjBlock + threadIdx.x;
+    bool on = i < t1;
+    if constexpr (CARRY) on = on && cv[u] >= a.carry_lo && cv[u] <= a.carry_hi;
+    if (on) r.act |= 1u << u;
   }
 }
 
@@ -918,7 +939,7 @@ __device__ __forceinline__ void rj_store_valid(uint32_t* words, const uint32_t* 
 // multiplicities, the probe tuples streamed through the table in rounds (the
 // next round's loads issued before the current round is probed), and the
 // matched groups written in slot order to one output range per item.
-template <int NV, bool NN>
+template <int NV, bool NN, bool CARRY>
 __global__ __launch_bounds__(kRjBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_rj_join(const RjJoinArgs a) {
   extern __shared__ __attribute__((aligned(16))) uint8_t s_raw[];
   const int L = a.lcap;
@@ -966,7 +987,7 @@ __global__ __launch_bounds__(kRjBlock) __attribute__((amdgpu_waves_per_eu(4))) v
       const int64_t i = b0 + (int64_t)u * kRjBlock + threadIdx.x;
       bh[u] = a.bkey[2 * (i < b1 ? i : (b1 > 0 ? b1 - 1 : 0))];
     }
-    rj_load_round<NV, NN>(a, t0, t1, ra);
+    rj_load_round<NV, NN, CARRY>(a, t0, t1, ra);
   }
   while (item != kNoItem) {
     const uint32_t s = item_sub(item), S = item_nsub(item);
@@ -1015,10 +1036,10 @@ __global__ __launch_bounds__(kRjBlock) __attribute__((amdgpu_waves_per_eu(4))) v
     // round are in flight while the current one is probed.
     constexpr int64_t R = (int64_t)kRjBlock * kRjProbeUnroll;
     for (int64_t base = t0; base < t1; base += 2 * R) {
-      if (base + R < t1) rj_load_round<NV, NN>(a, base + R, t1, rb);
+      if (base + R < t1) rj_load_round<NV, NN, CARRY>(a, base + R, t1, rb);
       else rb.act = 0;
       rj_probe_round<NV>(a, ra, s_keys, s_acc, s_mult, L, s, S, dump);
-      if (base + 2 * R < t1) rj_load_round<NV, NN>(a, base + 2 * R, t1, ra);
+      if (base + 2 * R < t1) rj_load_round<NV, NN, CARRY>(a, base + 2 * R, t1, ra);
       else ra.act = 0;
       if (base + R < t1) rj_probe_round<NV>(a, rb, s_keys, s_acc, s_mult, L, s, S, dump);
     }
@@ -1036,7 +1057,7 @@ __global__ __launch_bounds__(kRjBlock) __attribute__((amdgpu_waves_per_eu(4))) v
         const int64_t i = b0 + (int64_t)u * kRjBlock + threadIdx.x;
         bh[u] = a.bkey[2 * (i < b1 ? i : (b1 > 0 ? b1 - 1 : 0))];
       }
-      rj_load_round<NV, NN>(a, t0, t1, ra);
+      rj_load_round<NV, NN, CARRY>(a, t0, t1, ra);
     }
     // 4. Matched groups (row count non-zero) to the output, in slot order:
     // per chunk of kRjBlock slots the wave counts, one output range per item.
@@ -1259,6 +1280,7 @@ int rj_choose_pbits(int64_t build_rows) {
 static bool rj_build_plan(RpArgs& a, const gq_batch* build, int32_t key_col, const gq_pred* preds, int npreds,
                           int pbits) {
   std::memset(&a, 0, sizeof(a));
+  a.carry_st = -1;
   a.n = build->nrows;
   a.pbits = pbits;
   a.npreds = npreds;
@@ -1290,8 +1312,9 @@ int rj_build(gq_ctx* ctx, const gq_batch* build, int32_t key_col, const gq_pred*
 
 // Staging plan and value words of the probe side; false when it does not fit.
 static bool rj_probe_plan(RpArgs& r, int32_t (&vword)[GQ_MAX_AGGS], const gq_batch* in, int32_t probe_key,
-                          const gq_pred* preds, int npreds, const AggPlan& ap, int pbits) {
+                          const gq_pred* preds, int npreds, const AggPlan& ap, int pbits, int32_t carry_col = -1) {
   std::memset(&r, 0, sizeof(r));
+  r.carry_st = -1;
   r.n = in->nrows;
   r.pbits = pbits;
   r.npreds = npreds;
@@ -1318,16 +1341,17 @@ static bool rj_probe_plan(RpArgs& r, int32_t (&vword)[GQ_MAX_AGGS], const gq_bat
       for (int f = 0; f < ap.aggs[i].nf; ++f)
         if (ap.aggs[i].f[f].kind != GQ_F_CONST && ap.vals[ap.aggs[i].f[f].v].valid) r.need_nn = 1;
   }
+  if (carry_col >= 0) r.carry_st = sb.add(make_dcol(in->cols[carry_col]));
   return sb.ok && rp_scatter_lds(1 << pbits, r.in_bytes) <= kRpMaxLds;
 }
 
 bool rj_usable(const gq_join_table* t, const gq_batch* in, int32_t probe_key, const gq_pred* preds, int npreds,
-               const AggPlan& ap) {
+               const AggPlan& ap, int32_t carry_col) {
   if (!t || !t->rj_kr) return false;
   if (in->nrows >= ((int64_t)1 << 32)) return false;
   RpArgs r;
   int32_t vword[GQ_MAX_AGGS];
-  if (!rj_probe_plan(r, vword, in, probe_key, preds, npreds, ap, t->rj_pbits)) return false;
+  if (!rj_probe_plan(r, vword, in, probe_key, preds, npreds, ap, t->rj_pbits, carry_col)) return false;
   const int lcap = rj_lcap(ap.nacc);
   if (lcap < 1024) return false;
   // Sub-regions per region stay few when every build row is kept.
@@ -1346,39 +1370,89 @@ int rj_lcap(int nacc) {
 
 int rj_kpr(int lcap) { return (int)((int64_t)lcap * 13 / 20); }  // load factor 0.65
 
-int rj_groupjoin(gq_ctx* ctx, const gq_batch* in, int32_t probe_key, const gq_pred* preds, int npreds,
-                 const AggPlan& ap, const gq_join_table* t, const CompactArgs& ca, int64_t* d_groups,
-                 hipStream_t stream) {
-  const int pbits = t->rj_pbits;
-  const int64_t P = 1ll << pbits;
+// A partitioned probe side: its tuples, region offsets and plan, in a
+// workspace released (stream-ordered) with it.
+struct RjPart {
+  Scratch ws;
   RpArgs r;
-  RjJoinArgs j;
-  std::memset(&j, 0, sizeof(j));
-  if (!rj_probe_plan(r, j.vword, in, probe_key, preds, npreds, ap, pbits))
+  int32_t vword[GQ_MAX_AGGS];
+  int64_t* toff;
+  int pbits;
+  RjPart(gq_ctx* ctx, hipStream_t stream) : ws(ctx, stream) {}
+};
+
+int rj_part_create(gq_ctx* ctx, const gq_batch* in, int32_t probe_key, const gq_pred* preds, int npreds,
+                   int32_t carry_col, const AggPlan& ap, int pbits, hipStream_t stream, RjPart** out) {
+  *out = nullptr;
+  RjPart* part = new RjPart(ctx, stream);
+  RpArgs& r = part->r;
+  if (!rj_probe_plan(r, part->vword, in, probe_key, preds, npreds, ap, pbits, carry_col)) {
+    delete part;
     return set_error(ctx, GQ_ERR_UNSUPPORTED, "radix join: probe staging does not fit");
-  const int64_t n = in->nrows;
-  const int64_t cap = n > 0 ? n : 1;
-  Scratch ws(ctx, stream);
-  r.tw = 1 + r.nv;
+  }
+  const int64_t P = 1ll << pbits;
+  const int64_t cap = in->nrows > 0 ? in->nrows : 1;
+  r.tw = 1 + r.nv + (carry_col >= 0 ? 1 : 0);
   const size_t off_key = 256;
   const size_t off_nn = off_key + align_up((size_t)cap * 8 * r.tw, 256);
   const size_t off_toff = off_nn + align_up(r.need_nn ? (size_t)cap : 1, 256);
+  const size_t bytes = off_toff + align_up((size_t)(P + 1) * 8, 256);
+  if (!part->ws.get(bytes)) {
+    delete part;
+    return set_error(ctx, GQ_ERR_NOMEM, "radix join: probe workspace allocation failed");
+  }
+  r.okey = part->ws.as<uint64_t>(off_key);
+  r.onn = part->ws.as<uint8_t>(off_nn);
+  r.ocap = cap;
+  part->toff = part->ws.as<int64_t>(off_toff);
+  part->pbits = pbits;
+  const int rc = rp_run(ctx, r, part->toff, nullptr, stream);
+  if (rc) {
+    delete part;
+    return rc;
+  }
+  *out = part;
+  return GQ_OK;
+}
+
+void rj_part_destroy(RjPart* part) { delete part; }
+
+template <int NV, bool NN, bool CARRY>
+static int rj_launch_join(gq_ctx* ctx, const RjJoinArgs& j, dim3 grid, size_t lds, hipStream_t stream) {
+  GQ_LAUNCH(ctx, "rj_join", (k_rj_join<NV, NN, CARRY>), grid, dim3(kRjBlock), lds, stream, j);
+  GQ_LAUNCH_CHECK(ctx);
+  return GQ_OK;
+}
+
+template <bool CARRY>
+static int rj_launch_join_nv(gq_ctx* ctx, const RjJoinArgs& j, dim3 grid, size_t lds, hipStream_t stream) {
+  if (j.nv == 0) return j.need_nn ? rj_launch_join<0, true, CARRY>(ctx, j, grid, lds, stream)
+                                  : rj_launch_join<0, false, CARRY>(ctx, j, grid, lds, stream);
+  if (j.nv == 1) return j.need_nn ? rj_launch_join<1, true, CARRY>(ctx, j, grid, lds, stream)
+                                  : rj_launch_join<1, false, CARRY>(ctx, j, grid, lds, stream);
+  return j.need_nn ? rj_launch_join<2, true, CARRY>(ctx, j, grid, lds, stream)
+                   : rj_launch_join<2, false, CARRY>(ctx, j, grid, lds, stream);
+}
+
+int rj_part_join(gq_ctx* ctx, const RjPart* part, const AggPlan& ap, const gq_join_table* t, int64_t carry_lo,
+                 int64_t carry_hi, const CompactArgs& ca, int64_t* d_groups, hipStream_t stream) {
+  const RpArgs& r = part->r;
+  if (t->rj_pbits != part->pbits)
+    return set_error(ctx, GQ_ERR_UNSUPPORTED, "radix join: table and probe side have different region counts");
+  const int64_t P = 1ll << part->pbits;
+  RjJoinArgs j;
+  std::memset(&j, 0, sizeof(j));
+  for (int i = 0; i < GQ_MAX_AGGS; ++i) j.vword[i] = part->vword[i];
   // Work items: S_p = max(1, ceil(rows_p / kpr)) per region, so at most
   // P + build_rows / kpr + 1 in all.
   const int lcap = rj_lcap(ap.nacc);
   const int64_t max_items = P + t->build_rows / rj_kpr(lcap) + 2;
-  const size_t off_items = off_toff + align_up((size_t)(P + 1) * 8, 256);
+  Scratch ws(ctx, stream);
+  const size_t off_items = 256;
   const size_t off_q = off_items + align_up((size_t)max_items * 8, 256);
-  const size_t bytes = off_q + 256;
-  if (!ws.get(bytes)) return set_error(ctx, GQ_ERR_NOMEM, "radix join: probe workspace allocation failed");
-  r.okey = ws.as<uint64_t>(off_key);
-  r.onn = ws.as<uint8_t>(off_nn);
-  r.ocap = cap;
-  int64_t* toff = ws.as<int64_t>(off_toff);
-  int rc = rp_run(ctx, r, toff, nullptr, stream);
-  if (rc) return rc;
+  if (!ws.get(off_q + 256)) return set_error(ctx, GQ_ERR_NOMEM, "radix join: work item allocation failed");
 
-  j.pbits = pbits;
+  j.pbits = part->pbits;
   j.P = (int32_t)P;
   j.nacc = ap.nacc;
   j.lcap = lcap;
@@ -1408,7 +1482,9 @@ int rj_groupjoin(gq_ctx* ctx, const gq_batch* in, int32_t probe_key, const gq_pr
   j.tkey = r.okey;
   j.tw = r.tw;
   j.tnn = r.onn;
-  j.toff = toff;
+  j.toff = part->toff;
+  j.carry_lo = carry_lo;
+  j.carry_hi = carry_hi;
   j.items = ws.as<uint64_t>(off_items);
   j.qoff = ws.as<uint32_t>(off_q);
   j.qticket = ws.as<uint32_t>(off_q + 64);
@@ -1420,7 +1496,7 @@ int rj_groupjoin(gq_ctx* ctx, const gq_batch* in, int32_t probe_key, const gq_pr
   j.d_count = d_groups;
   j.dev_status = ctx->d_status;
   // The probe side is partitioned; from here on the build side is read.
-  rc = join_wait_ready(ctx, t, stream);
+  int rc = join_wait_ready(ctx, t, stream);
   if (rc) return rc;
   GQ_LAUNCH(ctx, "rj_plan", k_rj_plan, dim3(1), dim3(1024), 0, stream, j);
   GQ_LAUNCH_CHECK(ctx);
@@ -1432,14 +1508,19 @@ int rj_groupjoin(gq_ctx* ctx, const gq_batch* in, int32_t probe_key, const gq_pr
   (void)hipDeviceGetAttribute(&dev_cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
   const dim3 jgrid((unsigned)(dev_cus * kRjPerCu));
   const size_t jlds = rj_join_lds(j.lcap, j.nacc);
-  if (j.nv == 0 && !j.need_nn) GQ_LAUNCH(ctx, "rj_join", (k_rj_join<0, false>), jgrid, dim3(kRjBlock), jlds, stream, j);
-  else if (j.nv == 0) GQ_LAUNCH(ctx, "rj_join", (k_rj_join<0, true>), jgrid, dim3(kRjBlock), jlds, stream, j);
-  else if (j.nv == 1 && !j.need_nn) GQ_LAUNCH(ctx, "rj_join", (k_rj_join<1, false>), jgrid, dim3(kRjBlock), jlds, stream, j);
-  else if (j.nv == 1) GQ_LAUNCH(ctx, "rj_join", (k_rj_join<1, true>), jgrid, dim3(kRjBlock), jlds, stream, j);
-  else if (!j.need_nn) GQ_LAUNCH(ctx, "rj_join", (k_rj_join<2, false>), jgrid, dim3(kRjBlock), jlds, stream, j);
-  else GQ_LAUNCH(ctx, "rj_join", (k_rj_join<2, true>), jgrid, dim3(kRjBlock), jlds, stream, j);
-  GQ_LAUNCH_CHECK(ctx);
-  return GQ_OK;
+  return r.carry_st >= 0 ? rj_launch_join_nv<true>(ctx, j, jgrid, jlds, stream)
+                         : rj_launch_join_nv<false>(ctx, j, jgrid, jlds, stream);
+}
+
+int rj_groupjoin(gq_ctx* ctx, const gq_batch* in, int32_t probe_key, const gq_pred* preds, int npreds,
+                 const AggPlan& ap, const gq_join_table* t, const CompactArgs& ca, int64_t* d_groups,
+                 hipStream_t stream) {
+  RjPart* part = nullptr;
+  int rc = rj_part_create(ctx, in, probe_key, preds, npreds, -1, ap, t->rj_pbits, stream, &part);
+  if (rc) return rc;
+  rc = rj_part_join(ctx, part, ap, t, 0, 0, ca, d_groups, stream);
+  rj_part_destroy(part);
+  return rc;
 }
 
 }  // namespace gq

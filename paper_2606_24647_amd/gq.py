@@ -206,6 +206,8 @@ _SIGS = {
                                  C.POINTER(GqGroupbyOpts), C.POINTER(GqBatch), _P, _P]),
     "gq_pipeline": (C.c_int, [_P, C.POINTER(GqPlan), C.POINTER(GqBatch), C.POINTER(GqBatch),
                               _P, _P]),
+    "gq_pipeline_shared": (C.c_int, [_P, C.POINTER(GqPlan), C.POINTER(GqBatch), C.c_int32, C.POINTER(_P),
+                                     C.POINTER(GqPred), C.POINTER(C.POINTER(GqBatch)), C.POINTER(_P), _P]),
     "gq_groupby_shared": (C.c_int, [_P, C.POINTER(GqBatch), C.POINTER(C.c_int32), C.c_int, C.POINTER(GqPred),
                                     C.c_int, C.c_int, C.POINTER(GqAgg), C.c_int, C.POINTER(GqGroupbyOpts),
                                     C.POINTER(GqBatch), _P, _P]),
@@ -721,6 +723,31 @@ class Context:
         self.check(_lib.gq_pipeline(self.h, C.byref(plan), ib.ref, ob.ref, C.c_void_p(cnt.data_ptr()),
                                     _stream(stream)))
         return out, cnt
+
+    def pipeline_shared(self, table: DevTable, preds, probe_key, aggs, joins, ranges, capacity: int | None = None,
+                        sorted=False, stream=None):
+        """gq_pipeline_shared: one group-join pipeline per (join table, range)
+        pair, the probe side partitioned once.  ranges: ("range", col, lo, hi)
+        tuples on one column.  Returns a list of (out, device count)."""
+        joins, ranges = list(joins), list(ranges)
+        nq = len(joins)
+        cap = max(1, table.nrows) if capacity is None else capacity
+        outs = [self._groupby_out(table, [probe_key], aggs, cap) for _ in range(nq)]
+        cnt = torch.zeros(max(1, nq), dtype=torch.int64, device="cuda")
+        p, np_ = _preds(preds)
+        r, nr = _preds(ranges)
+        k, nk = _ints([probe_key])
+        a, na = _aggs(aggs)
+        plan = GqPlan(C.cast(p, C.POINTER(GqPred)), np_, probe_key, None, C.cast(k, C.POINTER(C.c_int32)), nk, na,
+                      C.cast(a, C.POINTER(GqAgg)), self._opts(0.0, "auto", sorted, 0, 0))
+        ib = _BatchArg(table)
+        obs = [_BatchArg(o, cap) for o in outs]
+        oarr = (C.POINTER(GqBatch) * max(1, nq))(*[C.pointer(ob.batch) for ob in obs])
+        tarr = (_P * max(1, nq))(*[j.h.value if isinstance(j.h, C.c_void_p) else j.h for j in joins])
+        carr = (_P * max(1, nq))(*[cnt.data_ptr() + 8 * i for i in range(nq)])
+        self.check(_lib.gq_pipeline_shared(self.h, C.byref(plan), ib.ref, nq, tarr, C.cast(r, C.POINTER(GqPred)),
+                                           oarr, carr, _stream(stream)))
+        return [(outs[i], cnt[i:i + 1]) for i in range(nq)]
 
 
 class AggStream:

@@ -244,7 +244,9 @@ class DeviceExecutor:
                 # Radix group-join: the build side's (hash, row) pairs and its
                 # per-(tile, region) counts, starts and chunk sums; the probe
                 # side's (hash, value) tuples at 16 B per fact row and the same
-                # count arrays; work items.
+                # count arrays; work items.  (Joins sharing one fact partition
+                # have 24-byte tuples, once for the group: the sum of their
+                # footprints bounds it.)
                 P = radix_regions(self.nd)
                 tf, td = radix_tiles(self.nf), radix_tiles(self.nd)
                 build = self.nd * 16 + td * P * 4 * 3 + P * 8
@@ -266,23 +268,42 @@ class DeviceExecutor:
         return self.nf + (self.nd if q.kind == "join" else 0)
 
     def share_key(self, q: Query):
-        """Aggregation queries over the fact table can share one scan."""
-        return "agg" if (self.share and q.kind == "agg") else None
+        """Aggregation queries over the fact table share one scan; join queries
+        (radix group-joins against the dimension) share the fact side's
+        partition, each applying its own date range to the date carried in
+        the partitioned tuples."""
+        if not self.share:
+            return None
+        if q.kind == "agg":
+            return "agg"
+        if q.kind == "join" and self.nd >= RADIX_MIN_BUILD:
+            return "join"
+        return None
 
     def start_group(self, qs: list, slot: int):
         s, ctx = self.streams[slot], self.ctxs[slot]
         job = {"qs": qs, "slot": slot, "stage": 9, "q": qs[0]}
         with self.torch.cuda.stream(s):
-            outs, cnt = ctx.groupby_shared(self.fact, [F_FLAG, F_STATUS],
-                                           [[("range", F_DATE, 0, q.params["b"])] for q in qs], AGG_AGGS,
-                                           capacity=16, expected_groups=6, stream=s)
-            job.update(outs=outs, cnt=cnt)
+            if qs[0].kind == "join":
+                tables = [ctx.join_build(self.dim, [D_PKEY], [("range", D_DATE, 0, q.params["b_dim"])], stream=s)
+                          for q in qs]
+                res = ctx.pipeline_shared(self.fact, [], F_FKEY, JOIN_AGGS, tables,
+                                          [("range", F_DATE, q.params["b_fact"], 2555) for q in qs],
+                                          capacity=self.nd, stream=s)
+                for jt in tables:
+                    jt.free(stream=s)
+                job.update(outs=[o for o, _ in res], cnts=[c for _, c in res])
+            else:
+                outs, cnt = ctx.groupby_shared(self.fact, [F_FLAG, F_STATUS],
+                                               [[("range", F_DATE, 0, q.params["b"])] for q in qs], AGG_AGGS,
+                                               capacity=16, expected_groups=6, stream=s)
+                job.update(outs=outs, cnts=[cnt[j:j + 1] for j in range(len(qs))])
             job["ev"] = self._event(s)
         return job
 
     def result_of(self, job, j: int):
         self.ctxs[job["slot"]].raise_status(stream=self.streams[job["slot"]])
-        n = int(job["cnt"][j].item())
+        n = int(job["cnts"][j].item())
         return ("groups", self.gq.read_table(job["outs"][j], n))
 
     def _event(self, s):
