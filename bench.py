@@ -356,8 +356,12 @@ def run_batched(torch, gq, devgen, ctx, steps=5, nfrag=4096, tune=True):
 # Serving: Poisson arrivals against device-resident 600M x 150M tables
 # ---------------------------------------------------------------------------
 
-def run_serving(torch, gq, devgen, nq=500, qps_list=(60, 70, 75, 80), budget_gb=96, slots=3, p99_bound_ms=250.0,
-                max_heavy=1):
+def run_serving(torch, gq, devgen, nq=500, qps_list=(70, 80, 90), budget_gb=96, slots=3, p99_bound_ms=250.0,
+                max_heavy=1, configured=(50.0, 3000)):
+    """Open-loop serving runs, plain (one query at a time, one stream) and
+    served (slots, shared scans and shared join partitions), on the same
+    arrivals (seed 5): first the configured point (50 QPS, 3,000 queries),
+    then `nq` queries at each rate of qps_list."""
     from paper_2606_24647_amd import datagen as dg
     from paper_2606_24647_amd import serve
     log("generating resident fact 600M x 7 and dim 150M x 3 on the device")
@@ -366,6 +370,7 @@ def run_serving(torch, gq, devgen, nq=500, qps_list=(60, 70, 75, 80), budget_gb=
     torch.cuda.synchronize()
     budget = int(budget_gb) << 30
     res = {"resident_gb": round((dg.C5_FACT_ROWS * 38 + dg.C5_DIM_ROWS * 20) / 1e9, 2), "queries_per_run": nq,
+           "configured": {"qps": configured[0], "queries": configured[1], "seed": 5} if configured else None,
            "slots": slots, "max_heavy": max_heavy, "budget_gb": budget_gb, "runs": []}
     plain_ex = serve.DeviceExecutor(gq, torch, fact, dim, nslots=1, share=False)
     served_ex = serve.DeviceExecutor(gq, torch, fact, dim, nslots=slots, max_heavy=max_heavy)
@@ -376,10 +381,11 @@ def run_serving(torch, gq, devgen, nq=500, qps_list=(60, 70, 75, 80), budget_gb=
     serve.Scheduler(plain_ex, budget).run(warm)
     serve.Scheduler(served_ex, budget).run(warm)
     torch.cuda.synchronize()
-    for qps in qps_list:
-        qs = serve.make_workload(nq, qps, seed=5)
+    points = ([configured] if configured else []) + [(q, nq) for q in qps_list]
+    for qps, n in points:
+        qs = serve.make_workload(n, qps, seed=5)
         for mode, ex in (("plain", plain_ex), ("served", served_ex)):
-            log(f"serving: {mode} at {qps} QPS, {nq} queries")
+            log(f"serving: {mode} at {qps} QPS, {n} queries")
             recs = serve.Scheduler(ex, budget).run(qs)
             torch.cuda.synchronize()
             torch.cuda.empty_cache()
@@ -431,6 +437,10 @@ def main():
     ap.add_argument("--serving-slots", type=int, default=3, help="streams of the served executor")
     ap.add_argument("--serving-max-heavy", type=int, default=1,
                     help="at most this many joins/partitions at once in the served executor")
+    ap.add_argument("--serving-qps", default="70,80,90",
+                    help="comma-separated arrival rates of the serving runs after the configured point "
+                         "(50 QPS, 3,000 queries)")
+    ap.add_argument("--serving-queries", type=int, default=500, help="queries per serving run")
     ap.add_argument("--only", choices=["c2", "operators", "batched", "serving", "copy"],
                     help="run one section only (profiling runs); 'copy' is a 1 GiB device copy used to "
                          "calibrate hardware byte counters")
@@ -503,7 +513,9 @@ def main():
         batched = section("batched", lambda: run_batched(torch, gq, devgen, ctx))
     serving = None
     if not args.no_serving:
-        serving = section("serving", lambda: run_serving(torch, gq, devgen, slots=args.serving_slots,
+        qps_list = tuple(float(x) for x in args.serving_qps.split(","))
+        serving = section("serving", lambda: run_serving(torch, gq, devgen, nq=args.serving_queries,
+                                                               qps_list=qps_list, slots=args.serving_slots,
                                                                max_heavy=args.serving_max_heavy))
     cpu = None
     if not args.no_cpu_baseline:

@@ -210,9 +210,14 @@ def summarize(records: list, wall: float | None = None) -> dict:
     last = max(r.done for r in records)
     span = wall if wall is not None else (last - first)
     rows = sum(r.rows for r in records)
-    return {"queries": len(records), "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-            "mean_ms": float(lat.mean()), "rows_per_s": rows / span if span > 0 else float("nan"),
-            "wall_s": span}
+    out = {"queries": len(records), "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+           "mean_ms": float(lat.mean()), "rows_per_s": rows / span if span > 0 else float("nan"),
+           "wall_s": span}
+    for kind in sorted({r.kind for r in records}):
+        kl = np.array([r.latency for r in records if r.kind == kind]) * 1e3
+        out[f"{kind}_p50_ms"] = float(np.percentile(kl, 50))
+        out[f"{kind}_p99_ms"] = float(np.percentile(kl, 99))
+    return out
 
 
 # ---------------------------------------------------------------------------
