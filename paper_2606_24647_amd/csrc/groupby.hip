@@ -197,6 +197,297 @@ __global__ __launch_bounds__(BLOCK) void k_groupjoin(const GbArgs a) {
   apply_rows<ITEMS>(a.ap, r0, a.n, keep, w, nullptr, loff, gsp);
 }
 
+__device__ __forceinline__ void put_value(uint8_t* out, int64_t g, int64_t v, int type) {
+  switch (type) {
+    case GQ_I8: reinterpret_cast<int8_t*>(out)[g] = (int8_t)v; break;
+    case GQ_I16: reinterpret_cast<int16_t*>(out)[g] = (int16_t)v; break;
+    case GQ_I32: reinterpret_cast<int32_t*>(out)[g] = (int32_t)v; break;
+    default: reinterpret_cast<int64_t*>(out)[g] = v; break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Small group-by in two launches
+// ---------------------------------------------------------------------------
+// For a cardinality hint of at most kGbSmallMax groups (packed keys, unsorted
+// output): every block aggregates its tiles in an LDS table and stores its
+// groups as a partial (no HBM table, no atomics outside LDS); the last block
+// to finish, found with a ticket, merges all partials in its LDS and writes
+// the output rows and the group count.  One launch zeroes the ticket, one does
+// everything else, instead of table init, aggregation, replica merge and two
+// compaction passes.
+// The table has as many slots as the HBM table the hint would size (so the
+// same inputs overflow it), and each slot's accumulators are replicated R
+// times, lane l updating replica l % R: with a handful of groups, the lanes of
+// a wave would otherwise serialise on the same few LDS words.
+constexpr int64_t kGbSmallMax = 256;
+constexpr int kGbSmallItems = 8;       // rows per thread per tile
+constexpr int kGbSmallGrid = 256;      // blocks at most (each stores one partial; at most the block size)
+constexpr size_t kGbSmallLds = 64 * 1024;
+constexpr int kGbSmallVw = 1024 / 32;  // validity staging words (tables of at most 1024 slots)
+
+struct SmallArgs {
+  uint64_t* part;       // per block: word 0 the entry count, then entries of 1 + nacc words (key, accumulators)
+  int64_t part_words;   // words per block
+  uint32_t* ticket;     // zeroed by k_gb_small_init
+  int32_t lcap;         // table slots (power of two, at most 1024)
+  int32_t reps;         // accumulator replicas per slot (power of two)
+  CompactArgs ca;       // output columns, key plan, aggregates, out_cap, d_count, dev_status
+};
+
+__global__ void k_gb_small_init(uint32_t* ticket) {
+  if (threadIdx.x == 0) *ticket = 0;
+}
+
+// Slot of `key` in a key array of lcap slots, inserting it; -1 when full.
+__device__ __forceinline__ int small_insert(uint64_t* s_keys, int lcap, uint64_t key) {
+  uint32_t s = (uint32_t)slot_of(key, (uint64_t)lcap);
+  for (int p = 0; p < lcap; ++p) {
+    const uint64_t kv = s_keys[s];
+    if (kv == key) return (int)s;
+    if (kv == kEmpty) {
+      const uint64_t prev =
+          atomicCAS((unsigned long long*)&s_keys[s], (unsigned long long)kEmpty, (unsigned long long)key);
+      if (prev == kEmpty || prev == key) return (int)s;
+    }
+    s = (s + 1) & (uint32_t)(lcap - 1);
+  }
+  return -1;
+}
+
+template <int BLOCK>
+__device__ __forceinline__ void small_table_init(uint64_t* s_keys, uint64_t* s_acc, int lcap, int reps,
+                                                 const AggPlan& ap) {
+  for (int i = threadIdx.x; i < lcap; i += BLOCK) s_keys[i] = kEmpty;
+  const int nw = lcap * reps * ap.nacc;
+  for (int i = threadIdx.x; i < nw; i += BLOCK) s_acc[i] = word_identity(ap.wop[i % ap.nacc]);
+}
+
+// Word w of slot i, its replicas combined.
+__device__ __forceinline__ uint64_t small_word(const uint64_t* s_acc, int i, int reps, const AggPlan& ap, int w) {
+  const uint64_t* p = s_acc + (size_t)i * reps * ap.nacc + w;
+  uint64_t v = p[0];
+  for (int r = 1; r < reps; ++r) {
+    const uint64_t x = p[(size_t)r * ap.nacc];
+    switch (ap.wop[w]) {
+      case WOP_ADD: v += x; break;
+      case WOP_MIN: v = (int64_t)x < (int64_t)v ? x : v; break;
+      default: v = (int64_t)x > (int64_t)v ? x : v; break;
+    }
+  }
+  return v;
+}
+
+template <int BLOCK, int ITEMS>
+__global__ __launch_bounds__(BLOCK) void k_gb_small(const GbArgs a, const SmallArgs sa) {
+  constexpr int TILE = BLOCK * ITEMS;
+  constexpr int NW = BLOCK / kWave;
+  extern __shared__ uint64_t s_mem[];
+  __shared__ uint32_t s_n;
+  __shared__ uint32_t s_last;
+  __shared__ uint32_t s_wave[NW];
+  __shared__ uint32_t s_vw[kGbSmallVw];
+  __shared__ uint32_t s_pbase[kGbSmallGrid + 1];
+  const int lcap = sa.lcap, reps = sa.reps, nacc = a.ap.nacc;
+  uint64_t* s_keys = s_mem;
+  uint64_t* s_acc = s_mem + lcap;
+  const int rep = (int)(threadIdx.x & (uint32_t)(reps - 1));
+  small_table_init<BLOCK>(s_keys, s_acc, lcap, reps, a.ap);
+  if (threadIdx.x == 0) s_n = 0;
+  __syncthreads();
+
+  // 1. This block's tiles into its LDS table.
+  const int64_t n = a.n;
+  for (int64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+    const int64_t r0 = tile * TILE + (int64_t)threadIdx.x * ITEMS;
+    uint32_t keep = eval_preds<ITEMS>(a, r0, n);
+    if (!keep) continue;
+    uint32_t w[ITEMS];
+    uint64_t key[ITEMS];
+    uint8_t special[ITEMS];
+    make_keys<ITEMS>(a.kp, r0, n, key, special);
+    int loff[ITEMS];
+    uint64_t* gsp[ITEMS];
+    static_for<0, ITEMS>([&](auto kk) __attribute__((always_inline)) {
+      constexpr int k = decltype(kk)::value;
+      w[k] = 1;
+      gsp[k] = nullptr;
+      loff[k] = -1;
+      if (!((keep >> k) & 1u)) return;
+      const int sl = small_insert(s_keys, lcap, key[k]);
+      if (sl < 0) {
+        atomicOr(a.dev_status, GQ_DEV_TABLE_FULL);
+        keep &= ~(1u << k);
+        return;
+      }
+      loff[k] = (sl * reps + rep) * nacc;
+    });
+    apply_rows<ITEMS>(a.ap, r0, n, keep, w, s_acc, loff, gsp);
+  }
+  __syncthreads();
+
+  // 2. Its groups as a partial; the last block to get here merges them all.
+  const int ew = 1 + nacc;
+  uint64_t* part = sa.part + (size_t)blockIdx.x * sa.part_words;
+  // The partial's words are agent-scope stores (written through to where
+  // every XCD reads them) and complete (vmcnt 0) before the block's ticket is
+  // taken; the last block reads them with agent-scope loads.  No device-wide
+  // fence: on this GPU that would write back or invalidate whole L2 caches.
+  for (int i = threadIdx.x; i < lcap; i += BLOCK) {
+    if (s_keys[i] == kEmpty) continue;
+    uint64_t* dst = part + 1 + (size_t)atomicAdd(&s_n, 1u) * ew;
+    status_store(&dst[0], s_keys[i]);
+    for (int k = 0; k < nacc; ++k) status_store(&dst[1 + k], small_word(s_acc, i, reps, a.ap, k));
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) status_store(&part[0], (uint64_t)s_n);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) s_last = atomicAdd(sa.ticket, 1u) == gridDim.x - 1;
+  __syncthreads();
+  if (!s_last) return;
+
+  // 3. Last block: every partial merged into a fresh LDS table.  The
+  // partials' counts are read at once (a thread each) and scanned, then the
+  // entries are spread over the threads, every word of an entry loaded before
+  // the first is used (one round trip per entry, not one per word).
+  small_table_init<BLOCK>(s_keys, s_acc, lcap, reps, a.ap);
+  const int nb = (int)gridDim.x;  // <= kGbSmallGrid <= BLOCK
+  const uint32_t pc = threadIdx.x < (uint32_t)nb
+                          ? (uint32_t)status_load(sa.part + (size_t)threadIdx.x * sa.part_words) : 0u;
+  {
+    uint32_t wt;
+    const uint32_t wp = wave_prefix_small<11>(pc, &wt);  // counts <= lcap <= 1024
+    if (lane_id() == 0) s_wave[threadIdx.x / kWave] = wt;
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+      before += k < (int)(threadIdx.x / kWave) ? s_wave[k] : 0;
+      total += s_wave[k];
+    }
+    if (threadIdx.x < (uint32_t)nb) s_pbase[threadIdx.x] = before + wp;
+    if (threadIdx.x == 0) {
+      s_pbase[nb] = total;
+      s_n = total;
+    }
+  }
+  __syncthreads();
+  const uint32_t nent = s_n;
+  for (uint32_t e = threadIdx.x; e < nent; e += BLOCK) {
+    int lo = 0, hi = nb - 1;  // the partial b with s_pbase[b] <= e < s_pbase[b + 1]
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (s_pbase[mid] <= e) lo = mid;
+      else hi = mid - 1;
+    }
+    uint64_t* src = sa.part + (size_t)lo * sa.part_words + 1 + (size_t)(e - s_pbase[lo]) * ew;
+    uint64_t v[1 + kMaxAcc];
+#pragma unroll
+    for (int k = 0; k <= kMaxAcc; ++k) v[k] = k <= nacc ? status_load(&src[k]) : 0;
+    const int sl = small_insert(s_keys, lcap, v[0]);
+    if (sl < 0) {
+      atomicOr(a.dev_status, GQ_DEV_TABLE_FULL);
+      continue;
+    }
+    uint64_t* dst = s_acc + ((size_t)sl * reps + rep) * nacc;
+#pragma unroll
+    for (int k = 0; k < kMaxAcc; ++k) {
+      if (k >= nacc) break;
+      switch (a.ap.wop[k]) {
+        case WOP_ADD: SharedAtomics::add(&dst[k], v[1 + k]); break;
+        case WOP_MIN: SharedAtomics::min(&dst[k], (int64_t)v[1 + k]); break;
+        default: SharedAtomics::max(&dst[k], (int64_t)v[1 + k]); break;
+      }
+    }
+  }
+  __syncthreads();
+
+  // 4. Occupied slots in slot order to the output rows, and the validity
+  // bits of the first min(groups, out_cap) rows staged in LDS.
+  const CompactArgs& ca = sa.ca;
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int nk = ca.kp.nk, ncol = nk + ca.naggs;
+  int64_t base = 0;
+  for (int c0 = 0; c0 < lcap; c0 += BLOCK) {
+    const int i = c0 + (int)threadIdx.x;
+    const bool occ = i < lcap && s_keys[i] != kEmpty;
+    const uint64_t m = ballot(occ);
+    if (lane == 0) s_wave[wave] = (uint32_t)__popcll(m);
+    __syncthreads();
+    uint32_t wpre = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+      wpre += k < wave ? s_wave[k] : 0;
+      tot += s_wave[k];
+    }
+    if (occ) {
+      const int64_t g = base + wpre + rank_in(m);
+      if (g < ca.out_cap) {
+        for (int j = 0; j < ncol; ++j) {
+          bool ok = true;
+          int64_t v;
+          if (j < nk) {
+            v = decode_field(ca.kp, s_keys[i], j, &ok);
+          } else {
+            const DAgg& ag = ca.aggs[j - nk];
+            v = (int64_t)small_word(s_acc, i, reps, a.ap, ag.word);
+            if ((ag.op == GQ_SUM || ag.op == GQ_MIN || ag.op == GQ_MAX) && ag.cword >= 0)
+              ok = small_word(s_acc, i, reps, a.ap, ag.cword) != 0;
+            if (!ok) v = 0;
+          }
+          put_value(ca.out[j].data, g, v, ca.out[j].type);
+        }
+      }
+    }
+    base += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    *ca.d_count = base;
+    if (base > ca.out_cap) atomicOr(a.dev_status, GQ_DEV_CAPACITY);
+  }
+  // 5. Validity bitmaps of the rows [0, min(groups, out_cap)), word by word
+  // (the last word's bits past the rows are 0).
+  const int64_t rows = base < ca.out_cap ? base : ca.out_cap;
+  const int vw = (int)((rows + 31) / 32);
+  for (int j = 0; j < ncol; ++j) {
+    if (!ca.out[j].valid) continue;
+    for (int k = threadIdx.x; k < vw; k += BLOCK) s_vw[k] = 0;
+    __syncthreads();
+    int64_t run = 0;
+    for (int c0 = 0; c0 < lcap; c0 += BLOCK) {
+      const int i = c0 + (int)threadIdx.x;
+      const bool occ = i < lcap && s_keys[i] != kEmpty;
+      const uint64_t m = ballot(occ);
+      if (lane == 0) s_wave[wave] = (uint32_t)__popcll(m);
+      __syncthreads();
+      uint32_t wpre = 0, tot = 0;
+#pragma unroll
+      for (int k = 0; k < NW; ++k) {
+        wpre += k < wave ? s_wave[k] : 0;
+        tot += s_wave[k];
+      }
+      if (occ) {
+        const int64_t g = run + wpre + rank_in(m);
+        bool ok = true;
+        if (j < nk) {
+          (void)decode_field(ca.kp, s_keys[i], j, &ok);
+        } else {
+          const DAgg& ag = ca.aggs[j - nk];
+          if ((ag.op == GQ_SUM || ag.op == GQ_MIN || ag.op == GQ_MAX) && ag.cword >= 0)
+            ok = small_word(s_acc, i, reps, a.ap, ag.cword) != 0;
+        }
+        if (ok && g < rows) atomicOr(&s_vw[g >> 5], 1u << (g & 31));
+      }
+      run += tot;
+      __syncthreads();
+    }
+    for (int k = threadIdx.x; k < vw; k += BLOCK) ca.out[j].valid[k] = s_vw[k];
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Compaction of a table into the output batch
 // ---------------------------------------------------------------------------
@@ -247,14 +538,6 @@ __device__ __forceinline__ int64_t compact_value(const CompactArgs& a, int j, in
   return v;
 }
 
-__device__ __forceinline__ void put_value(uint8_t* out, int64_t g, int64_t v, int type) {
-  switch (type) {
-    case GQ_I8: reinterpret_cast<int8_t*>(out)[g] = (int8_t)v; break;
-    case GQ_I16: reinterpret_cast<int16_t*>(out)[g] = (int16_t)v; break;
-    case GQ_I32: reinterpret_cast<int32_t*>(out)[g] = (int32_t)v; break;
-    default: reinterpret_cast<int64_t*>(out)[g] = v; break;
-  }
-}
 
 template <int BLOCK, int ITEMS>
 __global__ __launch_bounds__(BLOCK) void k_compact(const CompactArgs a) {
@@ -423,6 +706,57 @@ int launch_aggregate(gq_ctx* ctx, GbArgs& a, int strategy, hipStream_t stream) {
   return GQ_OK;
 }
 
+static_assert(sizeof(GbArgs) + sizeof(SmallArgs) <= 4000, "k_gb_small kernel arguments exceed the kernarg limit");
+
+// Table slots and accumulator replicas of a small group-by for this hint and
+// load factor (the slots of the HBM table the hint would size, rounded up to
+// a power of two); false when it does not fit the small path's LDS.
+static bool small_shape(int64_t expected, float lf, int nacc, int* lcap, int* reps) {
+  uint64_t cap = (uint64_t)((double)expected / lf) + 1;
+  if (cap < 16) cap = 16;
+  int l = 16;
+  while ((uint64_t)l < cap) l *= 2;
+  if (l > kGbSmallVw * 32) return false;
+  int r = 8;
+  while (r > 1 && (size_t)l * 8 * (1 + (size_t)r * nacc) > kGbSmallLds) r /= 2;
+  if ((size_t)l * 8 * (1 + (size_t)r * nacc) > kGbSmallLds) return false;
+  *lcap = l;
+  *reps = r;
+  return true;
+}
+
+static_assert(sizeof(GbArgs) + sizeof(SmallArgs) <= 4000, "k_gb_small kernel arguments exceed the kernarg limit");
+
+// The two launches of a small group-by (k_gb_small); ca holds the checked
+// outputs and the aggregate list.
+static int run_small(gq_ctx* ctx, GbArgs& a, CompactArgs& ca, int lcap, int reps, int64_t* d_groups,
+                     hipStream_t stream) {
+  constexpr int LTILE = kGbBlock * kGbSmallItems;
+  a.ntiles = (a.n + LTILE - 1) / LTILE;
+  const int64_t grid = a.ntiles < kGbSmallGrid ? a.ntiles : kGbSmallGrid;
+  SmallArgs sa;
+  std::memset(&sa, 0, sizeof(sa));
+  sa.lcap = lcap;
+  sa.reps = reps;
+  sa.part_words = 1 + (int64_t)lcap * (1 + a.ap.nacc);
+  Scratch ws(ctx, stream);
+  if (!ws.get(256 + (size_t)grid * (size_t)sa.part_words * 8))
+    return set_error(ctx, GQ_ERR_NOMEM, "group-by: partial table allocation failed");
+  sa.ticket = ws.as<uint32_t>(0);
+  sa.part = ws.as<uint64_t>(256);
+  ca.kp = a.kp;
+  ca.d_count = d_groups;
+  ca.dev_status = ctx->d_status;
+  sa.ca = ca;
+  const size_t lds = (size_t)lcap * 8 * (1 + (size_t)reps * a.ap.nacc);
+  GQ_LAUNCH(ctx, "gb_small_init", k_gb_small_init, dim3(1), dim3(64), 0, stream, sa.ticket);
+  GQ_LAUNCH_CHECK(ctx);
+  GQ_LAUNCH(ctx, "gb_small", (k_gb_small<kGbBlock, kGbSmallItems>), dim3((unsigned)grid), dim3(kGbBlock), lds,
+            stream, a, sa);
+  GQ_LAUNCH_CHECK(ctx);
+  return GQ_OK;
+}
+
 int run_groupby(gq_ctx* ctx, const gq_batch* in, const int32_t* keys, int nkeys, const gq_pred* preds, int npreds,
                 const gq_agg* aggs, int naggs, const gq_groupby_opts* opts, const gq_join_table* join,
                 int32_t probe_key, gq_batch* out, int64_t* d_groups, hipStream_t stream,
@@ -550,6 +884,16 @@ int run_groupby(gq_ctx* ctx, const gq_batch* in, const int32_t* keys, int nkeys,
     // LDS table holds comfortably; with no estimate, LDS first (rows that find
     // no LDS slot fall through to HBM).
     strategy = (o.expected_groups == 0 || o.expected_groups <= 256) ? GQ_STRATEGY_LDS : GQ_STRATEGY_GLOBAL;
+  }
+
+  // A small group-by (a hint of at most kGbSmallMax groups, packed keys,
+  // unsorted output) takes two launches.
+  int small_lcap = 0, small_reps = 0;
+  if (strategy == GQ_STRATEGY_LDS && !join && nkeys > 0 && a.kp.mode != KEY_RAW64 && o.expected_groups > 0 &&
+      o.expected_groups <= kGbSmallMax && (o.flags & GQ_SORTED) == 0 && !d_nrows && o.mode == GQ_MODE_SINGLE &&
+      a.n > 0 && small_shape(o.expected_groups, lf, a.ap.nacc, &small_lcap, &small_reps)) {
+    GQ_HIP_CHECK(ctx, hipSetDevice(ctx->device));
+    return run_small(ctx, a, ca, small_lcap, small_reps, d_groups, stream);
   }
 
   // Table sizing.  A small table under the LDS strategy gets replicas for the

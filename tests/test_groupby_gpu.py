@@ -230,3 +230,51 @@ def test_few_groups_over_many_tiles(gq, ctx, keys, sorted_out):
     aggs = [("sum", [("col", 1)]), ("count", [("col", 1)]), ("min", [("col", 2)]), ("max", [("col", 2)]),
             ("count*",)]
     check(gq, ctx, t, keys, [], aggs, strategy="global", expected_groups=200_000, sorted=sorted_out)
+
+
+# Two-launch small group-by (a hint of at most 256 groups, packed keys,
+# unsorted output): every block's partial merged by the last block.
+@pytest.mark.parametrize("n", [1, 777, 2048, 65_537, 1_000_003])
+def test_small_path_nulls_minmax(gq, ctx, n):
+    rng = np.random.default_rng(n + 91)
+    t = tbl(g=(rng.integers(-3, 4, n).astype(np.int8), rng.random(n) > 0.1),
+            h=rng.integers(0, 5, n).astype(np.int16),
+            v=(rng.integers(-10**12, 10**12, n), rng.random(n) > 0.2),
+            w=rng.integers(-100, 100, n).astype(np.int32))
+    aggs = [("sum", [("col", 2)]), ("min", [("col", 2)]), ("max", [("col", 3)]), ("count", [("col", 2)]),
+            ("count*",), ("sum", [("col", 3), ("k-col", 7, 3)])]
+    check(gq, ctx, t, [0, 1], [("range", 3, -90, 95)], aggs, strategy="lds", expected_groups=40)
+    check(gq, ctx, t, [1, 0], [], aggs, expected_groups=256)
+
+
+def test_small_path_capacity_and_table_full(gq, ctx):
+    rng = np.random.default_rng(92)
+    n = 300_000
+    # 40 groups into an output of 16 rows: the count is still the group count.
+    t = tbl(a=rng.integers(0, 8, n).astype(np.int8), b=rng.integers(0, 5, n).astype(np.int8),
+            v=np.ones(n, dtype=np.int64))
+    dev = gq.to_device(t)
+    out, cnt = ctx.groupby_agg(dev, [0, 1], [], [("count*",)], capacity=16, expected_groups=40)
+    assert ctx.sync_status() == 1
+    assert int(cnt.item()) == 40
+    # More groups than the table the hint sizes (as for the HBM table of the
+    # general path): reported as a full table, never a wrong result without a
+    # status.
+    out, cnt = ctx.groupby_agg(dev, [0, 1], [], [("count*",)], capacity=64, expected_groups=10)
+    assert ctx.sync_status() & 2
+    t2 = tbl(a=rng.integers(0, 200, n).astype(np.int16), b=rng.integers(0, 200, n).astype(np.int16))
+    out, cnt = ctx.groupby_agg(gq.to_device(t2), [0, 1], [], [("count*",)], expected_groups=100)
+    assert ctx.sync_status() & 2
+
+
+def test_small_path_equals_global(gq, ctx):
+    rng = np.random.default_rng(93)
+    t = dg.fact_c1(500_000, seed=93)
+    a_small = gpu_groupby(gq, ctx, t, [4, 5], [("range", 3, 100, 2000)], C1_AGGS, expected_groups=6)
+    a_glob = gpu_groupby(gq, ctx, t, [4, 5], [("range", 3, 100, 2000)], C1_AGGS, strategy="global",
+                         expected_groups=6)
+    assert a_small[2] == a_glob[2] and a_small[3] == 0 and a_glob[3] == 0
+    gk, ga = canon_groups([(v.astype(np.int64), ok) for v, ok in a_small[0]], a_small[1])
+    hk, ha = canon_groups([(v.astype(np.int64), ok) for v, ok in a_glob[0]], a_glob[1])
+    for (gv, gok), (hv, hok) in zip(gk + ga, hk + ha):
+        assert np.array_equal(gv, hv) and np.array_equal(gok, hok)
