@@ -300,7 +300,7 @@ def run_operators(torch, gq, devgen, ctx, c2, reps=5):
 # Batched fragments: 4096 filter + group-by fragments in one graph launch
 # ---------------------------------------------------------------------------
 
-def run_batched(torch, gq, devgen, ctx, steps=5, nfrag=4096, tune=True):
+def run_batched(torch, gq, devgen, ctx, steps=5, nfrag=4096, tune=True, plain=True):
     from paper_2606_24647_amd import datagen as dg
     from paper_2606_24647_amd import autotune
     log(f"generating {nfrag} fragments on the device")
@@ -322,6 +322,10 @@ def run_batched(torch, gq, devgen, ctx, steps=5, nfrag=4096, tune=True):
     ctx.raise_status()
     groups_b = plan.d_groups.clone()
     ms_b = median(ts)
+    if not plain:
+        plan.free()
+        return {"fragments": nfrag, "rows": total_rows, "config": cfg,
+                "batched": {"ms": round(ms_b, 3), "rows_per_s": total_rows / (ms_b * 1e-3)}}
     # Plain: one gq_groupby_agg per fragment, back to back on one stream.
     log("plain path: one call per fragment")
     lat = []
@@ -434,6 +438,8 @@ def main():
     ap.add_argument("--no-operators", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--batched-profile", action="store_true",
+                    help="batched section for counter runs: default configuration, no autotuner, no plain path")
     ap.add_argument("--serving-slots", type=int, default=3, help="streams of the served executor")
     ap.add_argument("--serving-max-heavy", type=int, default=1,
                     help="at most this many joins/partitions at once in the served executor")
@@ -510,7 +516,8 @@ def main():
     torch.cuda.empty_cache()
     batched = None
     if not args.no_batched:
-        batched = section("batched", lambda: run_batched(torch, gq, devgen, ctx))
+        batched = section("batched", lambda: run_batched(torch, gq, devgen, ctx, tune=not args.batched_profile,
+                                                         plain=not args.batched_profile))
     serving = None
     if not args.no_serving:
         qps_list = tuple(float(x) for x in args.serving_qps.split(","))
