@@ -211,6 +211,7 @@ __device__ __forceinline__ uint64_t rp_value_row(const RpArgs& a, const DAgg& ag
   return x;
 }
 
+template <bool PROBE>  // a.probe; only names each side apart in kernel traces
 __global__ __launch_bounds__(kRpBlock) void k_rp_hist(const RpArgs a) {
   extern __shared__ __attribute__((aligned(16))) uint8_t s_raw[];
   const int P = 1 << a.pbits;
@@ -325,6 +326,9 @@ __host__ __device__ inline size_t rp_scatter_lds(int P, int in_bytes) {
 // global-to-LDS loads of sub-tile k + 1 are issued before sub-tile k is
 // processed, so they are in flight during its LDS atomics and scattered
 // stores; one wait and one barrier per sub-tile.
+// PROBE is a.probe fixed at compile time: each side gets its own code (and
+// its own name in kernel traces).
+template <bool PROBE>
 __global__ __launch_bounds__(kRpSBlock) void k_rp_scatter(const RpArgs a) {
   extern __shared__ __attribute__((aligned(16))) uint8_t s_raw[];
   const int P = 1 << a.pbits;
@@ -357,7 +361,7 @@ __global__ __launch_bounds__(kRpSBlock) void k_rp_scatter(const RpArgs a) {
       const uint64_t h = region_hash((uint64_t)key[i]);
       const int64_t g = atomicAdd(&s_pos[region_of(h, a.pbits)], 1u);
       if (g >= a.ocap) continue;
-      if (a.probe) {
+      if constexpr (PROBE) {
         // The tuple (hash and values side by side) is one contiguous store;
         // values come from the staged input.
         uint64_t* t = a.okey + (size_t)g * a.tw;
@@ -560,7 +564,7 @@ __device__ __forceinline__ void rp_hist_tile(const RpArgs& a, int64_t t0, int64_
 }
 
 // Per tile, the histogram of the kept rows' regions (see k_rp_hist).
-template <int NS>
+template <int NS, bool PROBE>  // PROBE = a.probe; only names each side apart in kernel traces
 __global__ __launch_bounds__(kRpBlock) void k_rp_hist_r(const RpArgs a) {
   extern __shared__ __attribute__((aligned(16))) uint32_t s_hist[];
   const int P = 1 << a.pbits;
@@ -1191,8 +1195,11 @@ constexpr int kRpMaxReg = 5;  // columns of the register-path histogram
 
 template <int NS>
 int rp_launch_hist_reg(gq_ctx* ctx, const RpArgs& a, size_t lds, hipStream_t stream) {
-  GQ_LAUNCH(ctx, a.probe ? "rp_hist_probe" : "rp_hist_build", k_rp_hist_r<NS>, dim3((unsigned)a.ntiles),
-            dim3(kRpBlock), lds, stream, a);
+  if (a.probe)
+    GQ_LAUNCH(ctx, "rp_hist_probe", (k_rp_hist_r<NS, true>), dim3((unsigned)a.ntiles), dim3(kRpBlock), lds, stream, a);
+  else
+    GQ_LAUNCH(ctx, "rp_hist_build", (k_rp_hist_r<NS, false>), dim3((unsigned)a.ntiles), dim3(kRpBlock), lds, stream,
+              a);
   GQ_LAUNCH_CHECK(ctx);
   return GQ_OK;
 }
@@ -1246,8 +1253,10 @@ int rp_run(gq_ctx* ctx, RpArgs& a, int64_t* offsets, int64_t* total, hipStream_t
     const size_t lds_hist = align_up((size_t)P * 4, 16) +
                            ((size_t)a.st_off[a.nst_hist - 1] +
                             align_up((size_t)kRpSub * type_width(a.st[a.nst_hist - 1].type), 16)) * kRpHScale;
-    GQ_LAUNCH(ctx, a.probe ? "rp_hist_probe" : "rp_hist_build", k_rp_hist, dim3((unsigned)a.ntiles), dim3(kRpBlock),
-              lds_hist, stream, a);
+    if (a.probe)
+      GQ_LAUNCH(ctx, "rp_hist_probe", k_rp_hist<true>, dim3((unsigned)a.ntiles), dim3(kRpBlock), lds_hist, stream, a);
+    else
+      GQ_LAUNCH(ctx, "rp_hist_build", k_rp_hist<false>, dim3((unsigned)a.ntiles), dim3(kRpBlock), lds_hist, stream, a);
     GQ_LAUNCH_CHECK(ctx);
   }
   const dim3 cgrid((unsigned)nchunks, (unsigned)((P + 255) / 256));
@@ -1259,8 +1268,10 @@ int rp_run(gq_ctx* ctx, RpArgs& a, int64_t* offsets, int64_t* total, hipStream_t
             offsets, total);
   GQ_LAUNCH_CHECK(ctx);
   const size_t lds = rp_scatter_lds((int)P, a.in_bytes);
-  GQ_LAUNCH(ctx, a.probe ? "rp_scatter_probe" : "rp_scatter_build", k_rp_scatter, dim3((unsigned)a.ntiles),
-            dim3(kRpSBlock), lds, stream, a);
+  if (a.probe)
+    GQ_LAUNCH(ctx, "rp_scatter_probe", k_rp_scatter<true>, dim3((unsigned)a.ntiles), dim3(kRpSBlock), lds, stream, a);
+  else
+    GQ_LAUNCH(ctx, "rp_scatter_build", k_rp_scatter<false>, dim3((unsigned)a.ntiles), dim3(kRpSBlock), lds, stream, a);
   GQ_LAUNCH_CHECK(ctx);
   return GQ_OK;
 }

@@ -57,6 +57,13 @@ def test_pipeline_fact60m_dim15m(mods):
     ok = (fdate >= 1278) & (ddate[inv[fkey]] <= 1202)
     assert int(gcnt.sum()) == int(ok.sum())
     assert n == len(np.unique(fkey[ok]))
+    # Complete and hash-free: the revenue sums of all groups add up to the
+    # revenue of all joined rows (int64, wrapping as the device does).
+    price = dg.uniform(2, 1, 0, FACT, dg.PRICE_LO, dg.PRICE_HI)
+    disc = dg.uniform(2, 2, 0, FACT, 0, 10)
+    rev = price[ok] * (100 - disc[ok])
+    assert int(np.sum(gsum, dtype=np.int64)) == int(np.sum(rev, dtype=np.int64))
+    del price, disc, rev
 
     # Sampled groups, exactly, by the oracle on the rows that can reach them.
     rng = np.random.default_rng(0)
