@@ -360,7 +360,7 @@ def run_batched(torch, gq, devgen, ctx, steps=5, nfrag=4096, tune=True, plain=Tr
 # Serving: Poisson arrivals against device-resident 600M x 150M tables
 # ---------------------------------------------------------------------------
 
-def run_serving(torch, gq, devgen, nq=500, qps_list=(70, 80, 90), budget_gb=96, slots=3, p99_bound_ms=250.0,
+def run_serving(torch, gq, devgen, nq=500, qps_list=(60, 70, 80), budget_gb=96, slots=3, p99_bound_ms=250.0,
                 max_heavy=1, configured=(50.0, 3000)):
     """Open-loop serving runs, plain (one query at a time, one stream) and
     served (slots, shared scans and shared join partitions), on the same
@@ -421,9 +421,17 @@ def cpu_baseline(scale=4):
     t0 = time.perf_counter()
     r = oracle.pipeline(fact, FACT_PRED, [0], C2_AGGS, join_spec=(dim, [0], DIM_PRED, [0]))
     dt = time.perf_counter() - t0
-    return {"value": (nf + nd) / dt, "unit": "rows/s", "cores": 1, "kind": "oracle",
+    cpu = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), cpu)
+    except OSError:
+        pass
+    return {"value": (nf + nd) / dt, "unit": "rows/s", "cores": 1, "kind": "oracle", "cpu_model": cpu,
+            "host_threads": os.cpu_count(),
             "sample": f"the same pipeline at 1/{scale} scale: fact {nf} rows x dim {nd} rows "
-                      f"(fkey U[1,{nd}]), single-threaded C++ oracle, {dt:.1f} s, {r.nrows} groups"}
+                      f"(fkey U[1,{nd}]), single-threaded C++ oracle on one core of a {cpu}, {dt:.1f} s, "
+                      f"{r.nrows} groups"}
 
 
 def main():
@@ -443,7 +451,7 @@ def main():
     ap.add_argument("--serving-slots", type=int, default=3, help="streams of the served executor")
     ap.add_argument("--serving-max-heavy", type=int, default=1,
                     help="at most this many joins/partitions at once in the served executor")
-    ap.add_argument("--serving-qps", default="70,80,90",
+    ap.add_argument("--serving-qps", default="60,70,80",
                     help="comma-separated arrival rates of the serving runs after the configured point "
                          "(50 QPS, 3,000 queries)")
     ap.add_argument("--serving-queries", type=int, default=500, help="queries per serving run")

@@ -165,7 +165,8 @@ class Scheduler:
                     for other in queue:
                         if other is q:
                             continue
-                        if len(group) >= self.ex.max_share:
+                        limit = self.ex.share_limit(q) if hasattr(self.ex, "share_limit") else self.ex.max_share
+                        if len(group) >= limit:
                             break
                         if self.ex.share_key(other) == key and used + fp + self.ex.footprint(other) <= self.budget:
                             group.append(other)
@@ -232,7 +233,8 @@ class DeviceExecutor:
         self.fact, self.dim = fact, dim
         self.nslots = nslots
         self.share = share
-        self.max_share = 8
+        self.max_share = 8        # aggregation queries sharing one scan
+        self.max_share_join = 3   # join queries sharing one fact partition: all of a group complete together
         if max_heavy is not None:
             self.max_heavy = max_heavy
         self.streams = [torch.cuda.Stream() for _ in range(nslots)]
@@ -284,6 +286,9 @@ class DeviceExecutor:
         if q.kind == "join" and self.nd >= RADIX_MIN_BUILD:
             return "join"
         return None
+
+    def share_limit(self, q: Query) -> int:
+        return self.max_share_join if q.kind == "join" else self.max_share
 
     def start_group(self, qs: list, slot: int):
         s, ctx = self.streams[slot], self.ctxs[slot]
