@@ -40,8 +40,8 @@ def cache_path() -> str:
 
 
 def shape_key(frags) -> str:
-    rows = np.array([t.nrows for t, _, _ in frags], dtype=np.int64)
-    card = np.array([max(1, int(c or 1)) for _, _, c in frags], dtype=np.int64)
+    rows = np.array([fr[0].nrows for fr in frags], dtype=np.int64)
+    card = np.array([max(1, int(fr[2] or 1)) for fr in frags], dtype=np.int64)
     dev = torch.cuda.get_device_properties(torch.cuda.current_device())
     b = lambda x: int(round(math.log2(max(1, x))))  # noqa: E731
     return f"{dev.gcnArchName}|cu{dev.multi_processor_count}|f{b(len(frags))}|r{b(rows.sum())}|c{b(np.median(card))}"
@@ -68,7 +68,7 @@ def sample_fragments(frags, k=512, seed=0):
     """Up to k fragments, stratified by row count so that every size class appears."""
     if len(frags) <= k:
         return list(frags)
-    order = np.argsort([t.nrows for t, _, _ in frags], kind="stable")
+    order = np.argsort([fr[0].nrows for fr in frags], kind="stable")
     idx = order[np.linspace(0, len(order) - 1, k).astype(np.int64)]
     return [frags[i] for i in sorted(set(idx.tolist()))]
 
@@ -91,6 +91,11 @@ def time_plan(ctx, frags, keys, aggs, cfg, reps=3) -> float:
         return float(sorted(ts)[len(ts) // 2])
     finally:
         plan.free()
+        # A plan over the whole workload holds tens of GB; hand them back to
+        # the device so that the next candidate (or the caller's plan) can
+        # allocate its own size.
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
 
 
 def best_batch_config(ctx, frags, keys, aggs, use_cache=True) -> dict:

@@ -461,7 +461,9 @@ int gq_batch_plan_create(gq_ctx* ctx, const gq_fragment* frags, int nfrags, cons
   p->mem = ctx_alloc(ctx, total, stream);
   if (!p->mem) {
     delete p;
-    return set_error(ctx, GQ_ERR_NOMEM, "gq_batch_plan_create: allocation failed");
+    const std::string msg = "gq_batch_plan_create: allocation of " + std::to_string(total) + " bytes failed (" +
+                            std::to_string(nslots) + " table slots, " + std::to_string(rx_rows) + " radix rows)";
+    return set_error(ctx, GQ_ERR_NOMEM, msg.c_str());
   }
   p->bytes = total;
   char* base = static_cast<char*>(p->mem);
