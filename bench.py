@@ -208,7 +208,9 @@ def c2_bytes(r):
     total = dim_read + inserts + fact_read + probes + aggs + out
     per_kernel = {
         "groupjoin": fact_read + probes + aggs,          # direct path: fused probe + aggregate
-        "rp_scatter_probe": fact_read,                   # reads the fact columns once
+        "rp1_probe": fact_read,                          # two-level probe partition: reads the fact columns once
+        "rp2_probe": None,                               # moves the first level's tuples: design intermediate
+        "rp_scatter_probe": fact_read,                   # single-level probe partition: reads the fact columns once
         "rp_hist_probe": None,                           # key re-read: overhead
         "rj_join": inserts + probes + aggs + out,        # LDS inserts, probes, aggregation, groups out
         "rp_scatter_build": dim_read,                    # reads the dimension columns once

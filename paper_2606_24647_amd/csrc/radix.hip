@@ -30,10 +30,13 @@
 //                 16-byte store each (order inside a region is unspecified;
 //                 with thousands of regions a tile holds only a few rows per
 //                 region, so there is no run of stores to coalesce)
-// Probe side (gq_pipeline when the only group key is the probe key): the same
-// three kernels, the payload of a row being its aggregate inputs (one 64-bit
-// product expression per SUM/MIN/MAX, and a non-NULL mask where an input can
-// be NULL), then
+// Probe side (gq_pipeline when the only group key is the probe key): the
+// payload of a row is its aggregate inputs (one 64-bit product expression per
+// SUM/MIN/MAX, and a non-NULL mask where an input can be NULL).  Without a
+// mask it is partitioned in two levels (k_rp1, k_cs_*, k_rp2, described with
+// the kernels below: a sort into 32 first-level regions inside every
+// sub-tile, written out whole, then every first-level region moved to its
+// final regions), else by the same three kernels as the build side; then
 //   k_rj_plan     per region p, the number of sub-regions S_p so that each holds
 //                 at most kpr build rows, and per-XCD work lists of
 //                 (region, sub-region) items
@@ -110,6 +113,10 @@ struct RpArgs {
   int32_t pad_tw;
   uint8_t* onn;            // probe: non-NULL mask (bit i = aggregate i)
   int64_t ocap;
+  // Two-level probe partition (k_rp1, k_rp2): the first level's tuples, a
+  // slot of kRp1Sub tuples per sub-tile, and every sub-tile's run offsets.
+  uint64_t* slots;
+  uint16_t* roff;          // per sub-tile: kR1 + 1 offsets (the last the total)
 };
 
 // Copy rows [sbase, sbase + kRpSub) (those below n) of the first nst staged
@@ -411,6 +418,383 @@ __global__ __launch_bounds__(kRpSBlock) void k_rp_scatter(const RpArgs a) {
     // The next sub-tile's loads have landed (every thread's), and every thread
     // is done with this buffer before it is refilled.
     __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Two-level probe partition
+// ---------------------------------------------------------------------------
+// With thousands of regions a sub-tile of the single-level scatter holds a row
+// or two per region, so it writes one 16-byte tuple per region and sub-tile,
+// and those scattered stores, not the bytes, set its time; its histogram pass
+// also re-reads the key and predicate columns.  The probe side (tuples without
+// a non-NULL mask, P >= 256) instead sorts by kR1 = 32 first-level regions
+// (the top 5 bits of the region hash) inside each sub-tile, and then moves
+// every first-level region's tuples to their final regions:
+//   k_rp1      per tile, sub-tiles of SUB = 1024 rows staged in LDS (512
+//              threads, several workgroups per CU): the kept rows' tuples
+//              sorted by first-level region in LDS and written out whole, one
+//              contiguous store stream per sub-tile, into the sub-tile's own
+//              slot of SUB tuples, with the sub-tile's kR1 + 1 run offsets;
+//              the tile's tuple count per final region is counted in LDS on
+//              the way and stored at the end.  No device atomics and no
+//              histogram pass.
+//   k_cs_*     the column scan of those (tile, region) counts (as for the
+//              single-level path): the start of every (tile, region) and the
+//              region offsets.
+//   k_rp2      one workgroup per (first-level region, group of G tiles): the
+//              group's runs of that region (one per sub-tile, about 16 tuples
+//              each) gathered in rounds of up to kRp2Round tuples, ranked by
+//              final region in LDS and written out sorted: the group's tuples
+//              of final region q go to [start(first tile, q), ...), so every
+//              position is exact (no atomics) and the stores form runs.
+// The order of tuples inside a region is unspecified, as with the
+// single-level scatter.
+constexpr int kR1Bits = 5;
+constexpr int kR1 = 1 << kR1Bits;       // first-level regions
+constexpr int kRp1Block = 512;
+constexpr int kRp1Sub = 2 * kRp1Block;   // rows per sub-tile (and tuples per slot)
+constexpr int kRp2Block = 256;
+constexpr int kRp2Round = 2048;          // tuples per round of k_rp2
+constexpr int kRp2Items = kRp2Round / kRp2Block;
+constexpr int kRp2MaxRuns = kRp2Block;   // runs per k_rp2 workgroup (G * sub-tiles per tile): one per thread
+
+// A probe tuple of up to four words (named fields: no indexed array, so it
+// stays in registers).
+struct Tup4 {
+  uint64_t w0, w1, w2, w3;
+};
+
+// The tuples carry no non-NULL mask, so a value's NULL inputs are not looked
+// up (its value is then unspecified and never aggregated).
+__device__ __forceinline__ uint64_t rp_value_nn(const RpArgs& a, const DAgg& ag, const uint8_t* s_in, int r) {
+  uint64_t x = 1;
+  for (int f = 0; f < ag.nf; ++f) {
+    const DFactor& fa = ag.f[f];
+    const uint64_t k = (uint64_t)fa.k;
+    if (fa.kind == GQ_F_CONST) {
+      x *= k;
+      continue;
+    }
+    const int j = a.val_st[fa.v];
+    const uint64_t v = (uint64_t)lds_value(s_in + a.st_off[j], r, a.st[j].type);
+    if (fa.kind == GQ_F_COL) x *= v;
+    else if (fa.kind == GQ_F_K_MINUS_COL) x *= k - v;
+    else x *= k + v;
+  }
+  return x;
+}
+
+// Tuple words of staged row r: hash, value words, carried value.
+__device__ __forceinline__ Tup4 rp_tuple(const RpArgs& a, const uint8_t* s_in, int r, uint64_t h) {
+  Tup4 t{h, 0, 0, 0};
+  if (a.nv >= 1) t.w1 = rp_value_nn(a, a.ap.aggs[a.vagg[0]], s_in, r);
+  if (a.nv >= 2) t.w2 = rp_value_nn(a, a.ap.aggs[a.vagg[1]], s_in, r);
+  if (a.carry_st >= 0) {
+    const uint64_t cv = (uint64_t)lds_value(s_in + a.st_off[a.carry_st], r, a.st[a.carry_st].type);
+    if (a.nv == 0) t.w1 = cv;
+    else if (a.nv == 1) t.w2 = cv;
+    else t.w3 = cv;
+  }
+  return t;
+}
+
+__device__ __forceinline__ void rp_put_tuple(uint64_t* dst, const Tup4& t, int tw) {
+  typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+  *reinterpret_cast<u64x2*>(dst) = u64x2{t.w0, t.w1};
+  if (tw >= 3) dst[2] = t.w2;
+  if (tw >= 4) dst[3] = t.w3;
+}
+
+__device__ __forceinline__ Tup4 rp_get_tuple(const uint64_t* src, int tw) {
+  typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+  const u64x2 v = *reinterpret_cast<const u64x2*>(src);
+  Tup4 t{v.x, v.y, 0, 0};
+  if (tw >= 3) t.w2 = src[2];
+  if (tw >= 4) t.w3 = src[3];
+  return t;
+}
+
+// The same with the tuple width known at compile time (unused words stay 0
+// and take no registers).
+template <int TW>
+__device__ __forceinline__ Tup4 rp_get_tuple_t(const uint64_t* src) {
+  return rp_get_tuple(src, TW);
+}
+template <int TW>
+__device__ __forceinline__ void rp_put_tuple_t(uint64_t* dst, const Tup4& t) {
+  rp_put_tuple(dst, t, TW);
+}
+
+// Kept rows (predicates pass, key non-NULL) of the staged sub-tile and their
+// keys, as rp_rows_keep; NULLABLE = false drops the bitmap lookups (no staged
+// column has one).
+template <int ROWS, int BLOCK, bool NULLABLE>
+__device__ __forceinline__ uint32_t rp1_keep(const RpArgs& a, const uint8_t* s_in, int64_t sbase, int nrows,
+                                             int64_t (&key)[ROWS]) {
+  if constexpr (NULLABLE) return rp_rows_keep<ROWS, BLOCK>(a, s_in, 1, sbase, nrows, key);
+  uint32_t keep = 0;
+#pragma unroll
+  for (int i = 0; i < ROWS; ++i)
+    if (i * BLOCK + (int)threadIdx.x < nrows) keep |= 1u << i;
+  for (int p = 0; p < a.npreds; ++p) {
+    const int j = a.pred_st[p];
+    int64_t v[ROWS];
+    lds_rows<ROWS, BLOCK>(s_in + a.st_off[j], a.st[j].type, v);
+    const int64_t lo = a.preds[p].lo, hi = a.preds[p].hi;
+    if (a.preds[p].op == GQ_RANGE) {
+#pragma unroll
+      for (int i = 0; i < ROWS; ++i)
+        if (v[i] < lo || v[i] > hi) keep &= ~(1u << i);
+    } else {
+#pragma unroll
+      for (int i = 0; i < ROWS; ++i)
+        if (v[i] == lo) keep &= ~(1u << i);
+    }
+  }
+  lds_rows<ROWS, BLOCK>(s_in + a.st_off[a.key_st], a.st[a.key_st].type, key);
+  return keep;
+}
+
+// Dynamic LDS of k_rp1: packed 16-bit tuple counts of the P final regions,
+// the staged input (laid out for kRp1Sub rows) and the sorted tuples.
+__host__ __device__ inline size_t rp1_lds(int P, int in_bytes, int tw) {
+  return align_up((size_t)P * 2, 16) + align_up((size_t)in_bytes, 16) + (size_t)kRp1Sub * tw * 8;
+}
+
+// With NPF > 0 (every staged column 16-byte aligned, NPF of them) the next
+// sub-tile is loaded into registers while the current one is processed (a column of a
+// sub-tile is at most kRp1Block 16-byte chunks: one per thread) and written
+// to LDS once the current input is no longer read, before any store of the
+// sub-tile is issued.  (Global-to-LDS loads would not overlap: every LDS write
+// or atomic issued after one waits for it.)  Barriers order LDS only, so the
+// stores of a sub-tile stay in flight while the next one is processed.
+constexpr int kRp1MaxPf = 5;  // staged columns prefetched through registers at most
+
+template <bool NULLABLE, int NPF>  // NPF: staged columns (all 16-byte aligned) prefetched; 0: none
+__global__ __launch_bounds__(kRp1Block) __attribute__((amdgpu_waves_per_eu(6))) void k_rp1(const RpArgs a) {
+  constexpr int BLOCK = kRp1Block, SUB = kRp1Sub, ROWS = 2;
+  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+  extern __shared__ __attribute__((aligned(16))) uint8_t s_raw[];
+  __shared__ uint32_t s_cnt[kR1], s_off[kR1 + 1];
+  const int P = 1 << a.pbits;
+  const int tw = a.tw;
+  uint32_t* s_fin = reinterpret_cast<uint32_t*>(s_raw);
+  uint8_t* s_in = s_raw + align_up((size_t)P * 2, 16);
+  uint64_t* s_tup = reinterpret_cast<uint64_t*>(s_in + align_up((size_t)a.in_bytes, 16));
+  const int64_t tile = blockIdx.x;
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  const int64_t tbase = tile * a.tile_rows;
+  const int64_t trows = a.n - tbase < a.tile_rows ? a.n - tbase : a.tile_rows;
+  const int64_t nsub = (trows + SUB - 1) / SUB;
+  const int64_t subs = a.tile_rows / SUB;
+  for (int i = threadIdx.x; i < P / 2; i += BLOCK) s_fin[i] = 0;
+  if (threadIdx.x < kR1) s_cnt[threadIdx.x] = 0;
+  if (tile == 0)
+    for (int q = threadIdx.x; q < P; q += BLOCK) a.rtot[q] = 0;
+  rp_stage<BLOCK>(a, a.nst, 1, tbase, trows < SUB ? (int)trows : SUB, s_in);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  for (int64_t sub = 0; sub < nsub; ++sub) {
+    const int64_t sbase = tbase + sub * SUB;
+    const int nrows = a.n - sbase < SUB ? (int)(a.n - sbase) : SUB;
+    const int64_t nbase = sbase + SUB;
+    const bool has_next = sub + 1 < nsub;
+    const bool pf = NPF > 0 && has_next && a.n - nbase >= SUB;
+    u32x4 pfv[NPF > 0 ? NPF : 1];
+#pragma unroll
+    for (int j = 0; j < (NPF > 0 ? NPF : 1); ++j) pfv[j] = u32x4{0u, 0u, 0u, 0u};
+    if (pf) {
+#pragma unroll
+      for (int j = 0; j < NPF; ++j) {
+        const int w = type_width(a.st[j].type);
+        if ((int)threadIdx.x < SUB * w / 16)
+          pfv[j] = *reinterpret_cast<const u32x4*>(a.st[j].data + nbase * w + (int64_t)threadIdx.x * 16);
+      }
+    }
+    int64_t key[ROWS];
+    const uint32_t keep = rp1_keep<ROWS, BLOCK, NULLABLE>(a, s_in, sbase, nrows, key);
+    uint64_t h[ROWS];
+    uint32_t rank[ROWS];
+#pragma unroll
+    for (int i = 0; i < ROWS; ++i) {
+      h[i] = 0;
+      rank[i] = 0;
+      if (!((keep >> i) & 1u)) continue;
+      h[i] = region_hash((uint64_t)key[i]);
+      const uint32_t q = region_of(h[i], a.pbits);
+      atomicAdd(&s_fin[q >> 1], 1u << ((q & 1u) << 4));
+      rank[i] = atomicAdd(&s_cnt[(uint32_t)(h[i] >> (64 - kR1Bits))], 1u);
+    }
+    lds_barrier();
+    // Run offsets of the sub-tile (kR1 + 1 of them, the last the total).
+    if (wave == 0) {
+      const uint32_t c = lane < kR1 ? s_cnt[lane] : 0u;
+      uint32_t tot;
+      const uint32_t pre = wave_prefix_small<12>(c, &tot);
+      if (lane <= kR1) s_off[lane] = lane < kR1 ? pre : tot;
+      if (lane < kR1) s_cnt[lane] = 0;
+    }
+    lds_barrier();
+#pragma unroll
+    for (int i = 0; i < ROWS; ++i) {
+      if (!((keep >> i) & 1u)) continue;
+      const int r = i * BLOCK + threadIdx.x;
+      const uint32_t pos = s_off[(uint32_t)(h[i] >> (64 - kR1Bits))] + rank[i];
+      rp_put_tuple(s_tup + (size_t)pos * tw, rp_tuple(a, s_in, r, h[i]), tw);
+    }
+    // The sorted tuples are complete and the staged input is no longer read.
+    lds_barrier();
+    if (pf) {
+#pragma unroll
+      for (int j = 0; j < NPF; ++j) {
+        const int w = type_width(a.st[j].type);
+        if ((int)threadIdx.x < SUB * w / 16)
+          *reinterpret_cast<u32x4*>(s_in + a.st_off[j] + (int64_t)threadIdx.x * 16) = pfv[j];
+      }
+    } else if (has_next) {
+      rp_stage<BLOCK>(a, a.nst, 1, nbase, a.n - nbase < SUB ? (int)(a.n - nbase) : SUB, s_in);
+    }
+    // The sorted tuples leave as one contiguous stream into the slot.
+    const int64_t slot = tile * subs + sub;
+    const int total = (int)s_off[kR1];
+    if ((int)threadIdx.x <= kR1) a.roff[slot * (kR1 + 1) + threadIdx.x] = (uint16_t)s_off[threadIdx.x];
+    uint64_t* dst = a.slots + (size_t)slot * SUB * tw;
+    if (tw == 2) {
+      typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+      for (int k = threadIdx.x; k < total; k += BLOCK)
+        reinterpret_cast<u64x2*>(dst)[k] = reinterpret_cast<const u64x2*>(s_tup)[k];
+    } else {
+      for (int k = threadIdx.x; k < total * tw; k += BLOCK) dst[k] = s_tup[k];
+    }
+    if (!pf && has_next) __builtin_amdgcn_s_waitcnt(0);
+    // The next sub-tile is in LDS and the sorted buffer is free.
+    lds_barrier();
+  }
+  // Sub-tiles past the end of the input: empty runs.
+  for (int64_t sub = nsub; sub < subs; ++sub)
+    if (threadIdx.x <= kR1) a.roff[(tile * subs + sub) * (kR1 + 1) + threadIdx.x] = 0;
+  __syncthreads();
+  for (int q = threadIdx.x; q < P; q += BLOCK)
+    a.counts[tile * P + q] = (s_fin[q >> 1] >> ((q & 1) << 4)) & 0xffffu;
+}
+
+// Dynamic LDS of k_rp2: the sorted tuples of a round and their sub-regions.
+__host__ __device__ inline size_t rp2_lds(int tw) { return (size_t)kRp2Round * tw * 8 + kRp2Round; }
+
+// Workgroup b: first-level region r1 = b % kR1, tiles [g G, g G + G) with
+// g = b / kR1.  Its tuples of final region q = r1 * S2 + s go to consecutive
+// positions from start(first tile, q): within a region, tuples are ordered by
+// tile, and the group's tiles are consecutive.
+template <int TW>
+__global__ __launch_bounds__(kRp2Block) void k_rp2(const RpArgs a, int32_t group) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t s_raw[];
+  __shared__ uint32_t s_rbeg[kRp2MaxRuns];      // first tuple of every run (slot index * SUB + offset)
+  __shared__ uint32_t s_rpre[kRp2MaxRuns + 1];  // exclusive prefix of the run lengths
+  __shared__ uint32_t s_cnt[1 << (12 - kR1Bits)], s_off[1 << (12 - kR1Bits)];
+  __shared__ uint32_t s_cur[1 << (12 - kR1Bits)];
+  __shared__ uint32_t s_wsum[kRp2Block / kWave];
+  constexpr int tw = TW;
+  const int S2 = 1 << (a.pbits - kR1Bits);
+  const int P = 1 << a.pbits;
+  uint64_t* s_tup = reinterpret_cast<uint64_t*>(s_raw);
+  uint8_t* s_sid = reinterpret_cast<uint8_t*>(s_tup + (size_t)kRp2Round * tw);
+  const int r1 = (int)(blockIdx.x % kR1);
+  const int64_t t0 = (int64_t)(blockIdx.x / kR1) * group;
+  const int64_t t1 = t0 + group < a.ntiles ? t0 + group : a.ntiles;
+  const int64_t subs = a.tile_rows / kRp1Sub;
+  const int nruns = (int)((t1 - t0) * subs);
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  // Runs: lengths, then their prefix (one run per thread).
+  uint32_t len = 0;
+  if ((int)threadIdx.x < nruns) {
+    const int64_t slot = t0 * subs + threadIdx.x;
+    const uint16_t* ro = a.roff + slot * (kR1 + 1) + r1;
+    const uint32_t b = ro[0];
+    len = (uint32_t)ro[1] - b;
+    s_rbeg[threadIdx.x] = (uint32_t)(slot * kRp1Sub) + b;
+  }
+  uint32_t incl = len;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const uint32_t y = __shfl_up(incl, o, kWave);
+    if (lane >= o) incl += y;
+  }
+  if (lane == kWave - 1) s_wsum[wave] = incl;
+  for (int s = threadIdx.x; s < S2; s += kRp2Block) {
+    s_cnt[s] = 0;
+    s_cur[s] = a.starts[t0 * P + r1 * S2 + s];
+  }
+  __syncthreads();
+  uint32_t wpre = 0, total = 0;
+  for (int w = 0; w < kRp2Block / kWave; ++w) {
+    if (w < wave) wpre += s_wsum[w];
+    total += s_wsum[w];
+  }
+  if ((int)threadIdx.x < nruns) s_rpre[threadIdx.x] = wpre + incl - len;
+  if (threadIdx.x == 0) s_rpre[nruns] = total;
+  __syncthreads();
+  for (uint32_t base = 0; base < total; base += kRp2Round) {
+    const uint32_t nr = total - base < (uint32_t)kRp2Round ? total - base : (uint32_t)kRp2Round;
+    Tup4 t[kRp2Items];
+    uint32_t sid[kRp2Items], rk[kRp2Items];
+#pragma unroll
+    for (int i = 0; i < kRp2Items; ++i) {
+      const uint32_t k = (uint32_t)(i * kRp2Block + threadIdx.x);
+      t[i] = Tup4{0, 0, 0, 0};
+      if (k < nr) {
+        // The run holding tuple base + k: the last run starting at or before it.
+        const uint32_t x = base + k;
+        int lo = 0, hi = nruns - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (s_rpre[mid] <= x) lo = mid;
+          else hi = mid - 1;
+        }
+        t[i] = rp_get_tuple_t<TW>(a.slots + (size_t)(s_rbeg[lo] + (x - s_rpre[lo])) * tw);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kRp2Items; ++i) {
+      const uint32_t k = (uint32_t)(i * kRp2Block + threadIdx.x);
+      sid[i] = 0;
+      rk[i] = 0;
+      if (k >= nr) continue;
+      sid[i] = region_of(t[i].w0, a.pbits) & (uint32_t)(S2 - 1);
+      rk[i] = atomicAdd(&s_cnt[sid[i]], 1u);
+    }
+    __syncthreads();
+    if (wave == 0) {
+      // Exclusive prefix of the S2 <= 128 counts, two per lane.
+      const uint32_t c0 = 2 * lane < S2 ? s_cnt[2 * lane] : 0u;
+      const uint32_t c1 = 2 * lane + 1 < S2 ? s_cnt[2 * lane + 1] : 0u;
+      uint32_t tot;
+      const uint32_t pre = wave_prefix_small<14>(c0 + c1, &tot);
+      if (2 * lane < S2) s_off[2 * lane] = pre;
+      if (2 * lane + 1 < S2) s_off[2 * lane + 1] = pre + c0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kRp2Items; ++i) {
+      const uint32_t k = (uint32_t)(i * kRp2Block + threadIdx.x);
+      if (k >= nr) continue;
+      const uint32_t pos = s_off[sid[i]] + rk[i];
+      rp_put_tuple_t<TW>(s_tup + (size_t)pos * tw, t[i]);
+      s_sid[pos] = (uint8_t)sid[i];
+    }
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < nr; k += kRp2Block) {
+      const uint32_t s = s_sid[k];
+      const int64_t dst = (int64_t)s_cur[s] + (int64_t)(k - s_off[s]);
+      if (dst >= a.ocap) continue;
+      rp_put_tuple_t<TW>(a.okey + (size_t)dst * tw, rp_get_tuple_t<TW>(s_tup + (size_t)k * tw));
+    }
+    __syncthreads();
+    for (int s = threadIdx.x; s < S2; s += kRp2Block) {
+      s_cur[s] += s_cnt[s];
+      s_cnt[s] = 0;
+    }
     __syncthreads();
   }
 }
@@ -1276,6 +1660,101 @@ int rp_run(gq_ctx* ctx, RpArgs& a, int64_t* offsets, int64_t* total, hipStream_t
   return GQ_OK;
 }
 
+
+// Two-level partition of the probe side: tuples without a non-NULL mask, 256
+// to 4096 regions, and LDS room for both kernels (k_rp1 stages its columns for
+// kRp1Sub rows, half the layout built for kRpSub).
+static bool rp2_applies(const RpArgs& a) {
+  if (!a.probe || a.need_nn || a.pbits < 8 || a.pbits > 12 || a.tw < 2 || a.tw > 4) return false;
+  const int P = 1 << a.pbits;
+  return rp1_lds(P, a.in_bytes / 2, a.tw) + 512 <= kRpMaxLds && rp2_lds(a.tw) + 6144 <= kRpMaxLds;
+}
+
+template <bool NULLABLE>
+static int rp1_launch(gq_ctx* ctx, const RpArgs& h, int npf, size_t lds, hipStream_t stream) {
+  const dim3 grid((unsigned)h.ntiles), block(kRp1Block);
+  switch (npf) {
+    case 1: GQ_LAUNCH(ctx, "rp1_probe", (k_rp1<NULLABLE, 1>), grid, block, lds, stream, h); break;
+    case 2: GQ_LAUNCH(ctx, "rp1_probe", (k_rp1<NULLABLE, 2>), grid, block, lds, stream, h); break;
+    case 3: GQ_LAUNCH(ctx, "rp1_probe", (k_rp1<NULLABLE, 3>), grid, block, lds, stream, h); break;
+    case 4: GQ_LAUNCH(ctx, "rp1_probe", (k_rp1<NULLABLE, 4>), grid, block, lds, stream, h); break;
+    case 5: GQ_LAUNCH(ctx, "rp1_probe", (k_rp1<NULLABLE, 5>), grid, block, lds, stream, h); break;
+    default: GQ_LAUNCH(ctx, "rp1_probe", (k_rp1<NULLABLE, 0>), grid, block, lds, stream, h); break;
+  }
+  GQ_LAUNCH_CHECK(ctx);
+  return GQ_OK;
+}
+
+// k_rp1, the column scan and k_rp2 for the probe side; offsets: P + 1 int64.
+int rp_run2(gq_ctx* ctx, RpArgs& a, int64_t* offsets, hipStream_t stream) {
+  const int64_t P = 1ll << a.pbits;
+  // Tiles of at most kRpMaxTile rows (a multiple of kRp1Sub), as many as fill
+  // whole rounds of the workgroups resident at once (three per CU), so that
+  // the last round is not mostly idle.
+  int dev_cus = 256;
+  (void)hipDeviceGetAttribute(&dev_cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
+  const int64_t resident = (int64_t)dev_cus * 3;
+  int64_t rounds = (a.n + resident * kRpMaxTile - 1) / (resident * kRpMaxTile);
+  if (rounds < 1) rounds = 1;
+  int64_t t = (a.n + resident * rounds - 1) / (resident * rounds);
+  t = (t + kRp1Sub - 1) / kRp1Sub * kRp1Sub;
+  if (t < kRpMinTile) t = kRpMinTile;
+  a.tile_rows = t;
+  a.ntiles = (a.n + a.tile_rows - 1) / a.tile_rows;
+  if (a.ntiles == 0) return launch_fill_u32(ctx, offsets, 0u, 2 * (P + 1), stream);
+  const int64_t subs = t / kRp1Sub;
+  // k_rp2 workgroups of about kRp2Round * kR1 input rows (a round or less of
+  // tuples each), at most kRp2MaxRuns runs.
+  int64_t group = (int64_t)kRp2Round * kR1 / t;
+  if (group < 1) group = 1;
+  if (group * subs > kRp2MaxRuns) group = kRp2MaxRuns / subs;
+  const int64_t ngroups = (a.ntiles + group - 1) / group;
+  const int64_t m = a.ntiles * P;
+  const int64_t nchunks = (a.ntiles + kCsChunk - 1) / kCsChunk;
+  const int64_t nslots = a.ntiles * subs;
+  Scratch ws(ctx, stream);
+  const size_t off_counts = 256;
+  const size_t off_starts = off_counts + align_up((size_t)m * 4, 256);
+  const size_t off_csum = off_starts + align_up((size_t)m * 4, 256);
+  const size_t off_tot = off_csum + align_up((size_t)nchunks * P * 4, 256);
+  const size_t off_roff = off_tot + align_up((size_t)P * 4, 256);
+  const size_t off_slots = off_roff + align_up((size_t)nslots * (kR1 + 1) * 2, 256);
+  const size_t bytes = off_slots + (size_t)nslots * kRp1Sub * a.tw * 8;
+  if (!ws.get(bytes)) return set_error(ctx, GQ_ERR_NOMEM, "radix join: probe workspace allocation failed");
+  a.counts = ws.as<uint32_t>(off_counts);
+  a.starts = ws.as<uint32_t>(off_starts);
+  uint32_t* csum = ws.as<uint32_t>(off_csum);
+  a.rtot = ws.as<uint32_t>(off_tot);
+  a.roff = ws.as<uint16_t>(off_roff);
+  a.slots = ws.as<uint64_t>(off_slots);
+  // k_rp1 stages kRp1Sub rows: every column in half the space.
+  RpArgs h = a;
+  for (int j = 0; j < h.nst; ++j) h.st_off[j] = a.st_off[j] / 2;
+  h.in_bytes = a.in_bytes / 2;
+  bool nullable = false, aligned = true;
+  for (int j = 0; j < a.nst; ++j) {
+    nullable = nullable || a.st[j].valid != nullptr;
+    aligned = aligned && a.st[j].align >= 16;
+  }
+  const int npf = aligned && a.nst <= kRp1MaxPf ? a.nst : 0;
+  const size_t lds1 = rp1_lds((int)P, h.in_bytes, a.tw);
+  int rc = nullable ? rp1_launch<true>(ctx, h, npf, lds1, stream) : rp1_launch<false>(ctx, h, npf, lds1, stream);
+  if (rc) return rc;
+  const dim3 cgrid((unsigned)nchunks, (unsigned)((P + 255) / 256));
+  GQ_LAUNCH(ctx, "rp_scan_probe", k_cs_chunk, cgrid, dim3(256), 0, stream, (const uint32_t*)a.counts, a.ntiles,
+            (int)P, csum, a.rtot);
+  GQ_LAUNCH_CHECK(ctx);
+  GQ_LAUNCH(ctx, "rp_scan_probe", k_cs_fill, cgrid, dim3(256), 0, stream, (const uint32_t*)a.counts,
+            (const uint32_t*)csum, (const uint32_t*)a.rtot, a.ntiles, (int)P, a.starts, offsets, (int64_t*)nullptr);
+  GQ_LAUNCH_CHECK(ctx);
+  const dim3 g2((unsigned)(kR1 * ngroups)), b2(kRp2Block);
+  if (a.tw == 2) GQ_LAUNCH(ctx, "rp2_probe", k_rp2<2>, g2, b2, rp2_lds(2), stream, a, (int32_t)group);
+  else if (a.tw == 3) GQ_LAUNCH(ctx, "rp2_probe", k_rp2<3>, g2, b2, rp2_lds(3), stream, a, (int32_t)group);
+  else GQ_LAUNCH(ctx, "rp2_probe", k_rp2<4>, g2, b2, rp2_lds(4), stream, a, (int32_t)group);
+  GQ_LAUNCH_CHECK(ctx);
+  return GQ_OK;
+}
+
 }  // namespace
 
 int rj_choose_pbits(int64_t build_rows) {
@@ -1417,7 +1896,7 @@ int rj_part_create(gq_ctx* ctx, const gq_batch* in, int32_t probe_key, const gq_
   r.ocap = cap;
   part->toff = part->ws.as<int64_t>(off_toff);
   part->pbits = pbits;
-  const int rc = rp_run(ctx, r, part->toff, nullptr, stream);
+  const int rc = rp2_applies(r) ? rp_run2(ctx, r, part->toff, stream) : rp_run(ctx, r, part->toff, nullptr, stream);
   if (rc) {
     delete part;
     return rc;

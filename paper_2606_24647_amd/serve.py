@@ -250,14 +250,15 @@ class DeviceExecutor:
             if self.nd >= RADIX_MIN_BUILD:
                 # Radix group-join: the build side's (hash, row) pairs and its
                 # per-(tile, region) counts, starts and chunk sums; the probe
-                # side's (hash, value) tuples at 16 B per fact row and the same
-                # count arrays; work items.  (Joins sharing one fact partition
-                # have 24-byte tuples, once for the group: the sum of their
-                # footprints bounds it.)
+                # side's (hash, value) tuples at 16 B per fact row, twice (the
+                # first level's slots and the final regions), the same count
+                # arrays and the first level's run offsets; work items.  (Joins
+                # sharing one fact partition have 24-byte tuples, once for the
+                # group: the sum of their footprints bounds it.)
                 P = radix_regions(self.nd)
                 tf, td = radix_tiles(self.nf), radix_tiles(self.nd)
                 build = self.nd * 16 + td * P * 4 * 3 + P * 8
-                probe = self.nf * 16 + tf * P * 4 * 3 + (P + self.nd) * 8
+                probe = self.nf * 32 + tf * P * 4 * 3 + (self.nf // 1024 + 1) * 66 + (P + self.nd) * 8
                 return build + probe + out + (64 << 20)
             cap = 2 * self.nd + 1       # load factor 0.5 over every dimension row
             # keys, meta, 2 accumulators, run cursors per slot; rows and merge

@@ -10,8 +10,8 @@ from paper_2606_24647_amd import serve
 pytestmark = pytest.mark.gpu
 
 # A dimension of more than 2^20 rows: every join query takes the radix
-# group-join (probe partition, build on its own stream, LDS join), the path the
-# full-size serving run takes.
+# group-join (two-level probe partition, build on its own stream, LDS join),
+# the path the full-size serving run takes.
 NF, ND = 3_000_000, 1_200_000
 
 
@@ -38,7 +38,7 @@ def test_alone_equals_mix(env, max_heavy):
     for c in mixed_ex.ctxs:
         launched |= set(c.timing_report())
         c.set_timing(False)
-    assert "rj_join" in launched and "rp_scatter_probe" in launched, sorted(launched)
+    assert "rj_join" in launched and "rp1_probe" in launched, sorted(launched)
     alone_ex = serve.DeviceExecutor(gq, torch, fact, dim, nslots=1)
     by_id = {r.qid: r for r in mixed}
     for q in qs:
