@@ -393,7 +393,241 @@ __global__ __launch_bounds__(BLOCK) void k_part_scatter(const PartArgs a) {
   }
 }
 
+// Prefetching form of the scatter (both shapes), for every column 16-byte
+// aligned and without a bitmap, at most kPPfMax columns, the row count known
+// on the host.  The next sub-tile's columns are loaded into
+// registers (at most two 16-byte chunks per column and thread) while the
+// current one is ranked, and written to LDS once its rows have left.
+// Barriers order LDS only, so the loads and the row stores stay in flight
+// across them (a full barrier also waits for every outstanding global access
+// of the wave).
+constexpr int kPPfMax = 4;
+
+template <int BLOCK, int SUB, int NPF>
+__global__ __launch_bounds__(BLOCK) void k_part_scatter_pf(const PartArgs a) {
+  static_assert(SUB == kPSteps * BLOCK, "four rows per thread per sub-tile");
+  constexpr int NW = BLOCK / kWave, SUBS = kPTile / SUB;
+  constexpr int CH = SUB * 8 / 16 / BLOCK;  // 16-byte chunks per thread of an 8-byte column
+  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+  extern __shared__ __attribute__((aligned(16))) uint8_t s_raw[];
+  const int P = (int)a.nparts;
+  uint8_t* s_in = s_raw;
+  uint32_t* s_whist = reinterpret_cast<uint32_t*>(s_raw + align_up((size_t)a.in_bytes, 16));
+  uint32_t* s_sub = reinterpret_cast<uint32_t*>(reinterpret_cast<uint8_t*>(s_whist) + align_up((size_t)NW * P * 4, 16));
+  int64_t* s_base = reinterpret_cast<int64_t*>(reinterpret_cast<uint8_t*>(s_sub) + align_up((size_t)(P + 1) * 4, 16));
+  uint16_t* s_pid = reinterpret_cast<uint16_t*>(s_base + P);
+  uint16_t* s_src = s_pid + SUB;
+  __shared__ uint32_t s_wsum[NW];
+
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int64_t n = a.n;
+  const int64_t tbase = tile * kPTile;
+  for (int q = threadIdx.x; q < P; q += BLOCK) s_base[q] = a.starts[(int64_t)q * a.ntiles + tile];
+  for (int i = threadIdx.x; i < NW * P; i += BLOCK) s_whist[i] = 0;
+  int nbits = 0;
+  while ((1 << nbits) < P) ++nbits;
+  auto kbase = [&](int j) { return (const uint8_t*)(s_in + a.st_off[a.key_col[j]]); };
+  const int per = (P + BLOCK - 1) / BLOCK;
+  {
+    const int nrows0 = n - tbase < SUB ? (int)(n - tbase) : SUB;
+    for (int j = 0; j < a.ncols; ++j) stage_col_lds<BLOCK>(a.cols[j], tbase, nrows0, s_in + a.st_off[j]);
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+
+  for (int sub = 0; sub < SUBS; ++sub) {
+    const int64_t sbase = tbase + (int64_t)sub * SUB;
+    if (sbase >= n) break;
+    const int nrows = n - sbase < SUB ? (int)(n - sbase) : SUB;
+    const int64_t nbase = sbase + SUB;
+    const bool has_next = sub + 1 < SUBS && nbase < n;
+    const bool pf = has_next && n - nbase >= SUB;
+    u32x4 pfv[NPF][CH];
+#pragma unroll
+    for (int j = 0; j < NPF; ++j)
+#pragma unroll
+      for (int c = 0; c < CH; ++c) pfv[j][c] = u32x4{0u, 0u, 0u, 0u};
+    if (pf) {
+#pragma unroll
+      for (int j = 0; j < NPF; ++j) {
+        const int w = type_width(a.cols[j].type);
+        const int nch = SUB * w / 16;
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+          const int idx = (int)threadIdx.x + c * BLOCK;
+          if (idx < nch)
+            pfv[j][c] = *reinterpret_cast<const u32x4*>(a.cols[j].data + nbase * w + (int64_t)idx * 16);
+        }
+      }
+    }
+    // Stable ranks: wave w owns rows 256w + 64i + lane, i = 0..3, in order;
+    // lanes of one partition find each other with one ballot per bit of its
+    // id, and the lowest of them advances the wave's counter.
+    uint32_t pid[kPSteps], rank[kPSteps];
+    part_of_rows(a, sbase, wave * (SUB / NW) + lane, kWave, nrows, kbase, pid);
+#pragma unroll
+    for (int i = 0; i < kPSteps; ++i) {
+      const int r = wave * (SUB / NW) + i * kWave + lane;
+      const bool in = r < nrows;
+      const uint32_t p = in ? pid[i] : 0u;
+      uint64_t peers = ballot(in);
+      for (int b = 0; b < nbits; ++b) {
+        const bool bit = (p >> b) & 1u;
+        const uint64_t m = ballot(bit);
+        peers &= bit ? m : ~m;
+      }
+      pid[i] = p;
+      rank[i] = 0;
+      if (in) {
+        uint32_t* cnt = s_whist + wave * P + p;
+        const uint32_t before = *cnt;
+        rank[i] = before + rank_in(peers);
+        if (rank_in(peers) == 0) *cnt = before + (uint32_t)__popcll(peers);
+      }
+    }
+    lds_barrier();
+    // Per partition: wave-exclusive counts and the sub-tile total; then the
+    // exclusive scan of the totals over partitions.
+    uint32_t mysum = 0;
+    uint32_t cnt_own[4] = {0u, 0u, 0u, 0u};  // per <= 4 for P <= 1024
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int q = threadIdx.x * per + j;
+      if (j < per && q < P) {
+        uint32_t run = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+          const uint32_t c = s_whist[w * P + q];
+          s_whist[w * P + q] = run;
+          run += c;
+        }
+        cnt_own[j] = run;
+        mysum += run;
+      }
+    }
+    uint32_t incl = mysum;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const uint32_t y = __shfl_up(incl, o, kWave);
+      if (lane >= o) incl += y;
+    }
+    if (lane == kWave - 1) s_wsum[wave] = incl;
+    lds_barrier();
+    uint32_t wpre = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      if (w < wave) wpre += s_wsum[w];
+      tot += s_wsum[w];
+    }
+    uint32_t run = wpre + incl - mysum;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int q = threadIdx.x * per + j;
+      if (j < per && q < P) {
+        s_sub[q] = run;
+        run += cnt_own[j];
+      }
+    }
+    lds_barrier();
+#pragma unroll
+    for (int i = 0; i < kPSteps; ++i) {
+      const int r = wave * (SUB / NW) + i * kWave + lane;
+      if (r < nrows) {
+        const uint32_t pos = s_sub[pid[i]] + s_whist[wave * P + pid[i]] + rank[i];
+        s_src[pos] = (uint16_t)r;
+        s_pid[pos] = (uint16_t)pid[i];
+      }
+    }
+    lds_barrier();
+    const int total = (int)tot;
+    int srow[kPSteps];
+    int64_t grow[kPSteps];
+#pragma unroll
+    for (int i = 0; i < kPSteps; ++i) {
+      const int k = i * BLOCK + threadIdx.x;
+      srow[i] = 0;
+      grow[i] = -1;
+      if (k < total) {
+        const uint32_t q = s_pid[k];
+        srow[i] = s_src[k];
+        grow[i] = s_base[q] + (k - (int)s_sub[q]);
+      }
+    }
+    // The next sub-tile's loads have landed (and the previous sub-tile's
+    // stores left) before this one's stores are issued, so that refilling LDS
+    // below waits for nothing.
+    __builtin_amdgcn_s_waitcnt(0);
+    for (int j = 0; j < a.ncols; ++j) {
+      const OCol& o = a.out[j];
+      const uint8_t* col = s_in + a.st_off[j];
+      switch (a.cols[j].type) {
+        case GQ_I8:
+#pragma unroll
+          for (int i = 0; i < kPSteps; ++i)
+            if (grow[i] >= 0) o.data[grow[i]] = col[srow[i]];
+          break;
+        case GQ_I16:
+#pragma unroll
+          for (int i = 0; i < kPSteps; ++i)
+            if (grow[i] >= 0)
+              reinterpret_cast<int16_t*>(o.data)[grow[i]] = reinterpret_cast<const int16_t*>(col)[srow[i]];
+          break;
+        case GQ_I32:
+#pragma unroll
+          for (int i = 0; i < kPSteps; ++i)
+            if (grow[i] >= 0)
+              reinterpret_cast<int32_t*>(o.data)[grow[i]] = reinterpret_cast<const int32_t*>(col)[srow[i]];
+          break;
+        default:
+#pragma unroll
+          for (int i = 0; i < kPSteps; ++i)
+            if (grow[i] >= 0)
+              reinterpret_cast<int64_t*>(o.data)[grow[i]] = reinterpret_cast<const int64_t*>(col)[srow[i]];
+          break;
+      }
+    }
+    // Every row has left the staged input; the next sub-tile replaces it.
+    lds_barrier();
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int q = threadIdx.x * per + j;
+      if (j < per && q < P) s_base[q] += cnt_own[j];
+    }
+    for (int i = threadIdx.x; i < NW * P; i += BLOCK) s_whist[i] = 0;
+    if (pf) {
+#pragma unroll
+      for (int j = 0; j < NPF; ++j) {
+        const int nch = SUB * type_width(a.cols[j].type) / 16;
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+          const int idx = (int)threadIdx.x + c * BLOCK;
+          if (idx < nch) *reinterpret_cast<u32x4*>(s_in + a.st_off[j] + (int64_t)idx * 16) = pfv[j][c];
+        }
+      }
+    } else if (has_next) {
+      const int nr = n - nbase < SUB ? (int)(n - nbase) : SUB;
+      for (int j = 0; j < a.ncols; ++j) stage_col_lds<BLOCK>(a.cols[j], nbase, nr, s_in + a.st_off[j]);
+      __builtin_amdgcn_s_waitcnt(0);
+    }
+    lds_barrier();
+  }
+}
+
 constexpr int kScanBlock = 256, kScanItems = 16;
+
+template <int BLOCK, int SUB>
+int launch_scatter_pf(gq_ctx* ctx, const PartArgs& a, int64_t ntiles, size_t lds, hipStream_t stream) {
+  const dim3 g((unsigned)ntiles), b(BLOCK);
+  switch (a.ncols) {
+    case 1: GQ_LAUNCH(ctx, "part_scatter", (k_part_scatter_pf<BLOCK, SUB, 1>), g, b, lds, stream, a); break;
+    case 2: GQ_LAUNCH(ctx, "part_scatter", (k_part_scatter_pf<BLOCK, SUB, 2>), g, b, lds, stream, a); break;
+    case 3: GQ_LAUNCH(ctx, "part_scatter", (k_part_scatter_pf<BLOCK, SUB, 3>), g, b, lds, stream, a); break;
+    default: GQ_LAUNCH(ctx, "part_scatter", (k_part_scatter_pf<BLOCK, SUB, 4>), g, b, lds, stream, a); break;
+  }
+  GQ_LAUNCH_CHECK(ctx);
+  return GQ_OK;
+}
 
 // Histogram, scan and scatter for the rows of `a` (a.n, or at most a.n rows
 // counted on the device when a.d_n is set).  d_offsets receives nparts + 1
@@ -414,6 +648,11 @@ int launch_partition(gq_ctx* ctx, PartArgs& a, int64_t* d_offsets, hipStream_t s
   GQ_HIP_CHECK(ctx, hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device));
   size_t row_bytes = 0;
   for (int j = 0; j < a.ncols; ++j) row_bytes += (size_t)type_width(a.cols[j].type);
+  // The wide shape (4096-row sub-tiles, longer runs per partition) where its
+  // LDS fits, else the narrow one; each in its prefetching form where that
+  // applies.
+  bool pf = !a.d_n && a.ncols >= 1 && a.ncols <= kPPfMax;
+  for (int j = 0; j < a.ncols; ++j) pf = pf && a.cols[j].align >= 16 && !a.cols[j].valid;
   const size_t wide_lds = part_scatter_lds<kPWBlock, kPWSub>((int)nparts, (int)(row_bytes * kPWSub + 16 * a.ncols));
   const bool wide = wide_lds <= kPWMaxLds && wide_lds + 256 <= (size_t)lds_max;
   const int ssub = wide ? kPWSub : kPSub;
@@ -456,7 +695,11 @@ int launch_partition(gq_ctx* ctx, PartArgs& a, int64_t* d_offsets, hipStream_t s
   GQ_LAUNCH(ctx, "scan_counts", (k_scan_counts<kScanBlock, kScanItems>), dim3((unsigned)nscan), dim3(kScanBlock), 0,
             stream, (const uint32_t*)a.counts, m, a.starts, ntiles, nparts, d_offsets, ticket, status, nscan);
   GQ_LAUNCH_CHECK(ctx);
-  if (wide)
+  if (pf) {
+    int rc2 = wide ? launch_scatter_pf<kPWBlock, kPWSub>(ctx, a, ntiles, lds_scat, stream)
+                   : launch_scatter_pf<kPBlock, kPSub>(ctx, a, ntiles, lds_scat, stream);
+    if (rc2) return rc2;
+  } else if (wide)
     GQ_LAUNCH(ctx, "part_scatter", (k_part_scatter<kPWBlock, kPWSub>), dim3((unsigned)ntiles), dim3(kPWBlock), lds_scat,
               stream, a);
   else
