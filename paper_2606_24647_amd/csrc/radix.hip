@@ -1703,9 +1703,9 @@ int rp_run2(gq_ctx* ctx, RpArgs& a, int64_t* offsets, hipStream_t stream) {
   a.ntiles = (a.n + a.tile_rows - 1) / a.tile_rows;
   if (a.ntiles == 0) return launch_fill_u32(ctx, offsets, 0u, 2 * (P + 1), stream);
   const int64_t subs = t / kRp1Sub;
-  // k_rp2 workgroups of about kRp2Round * kR1 input rows (a round or less of
-  // tuples each), at most kRp2MaxRuns runs.
-  int64_t group = (int64_t)kRp2Round * kR1 / t;
+  // k_rp2 workgroups of about 2 * kRp2Round * kR1 input rows (a round of
+  // tuples when half the rows are kept), at most kRp2MaxRuns runs.
+  int64_t group = (int64_t)2 * kRp2Round * kR1 / t;
   if (group < 1) group = 1;
   if (group * subs > kRp2MaxRuns) group = kRp2MaxRuns / subs;
   const int64_t ngroups = (a.ntiles + group - 1) / group;
