@@ -328,7 +328,18 @@ __host__ __device__ inline size_t bx_scatter_lds(int R, int in_bytes) {
   return align_up((size_t)R * 12, 16) + align_up((size_t)in_bytes, 16) + (size_t)kXSub * (4 + 2 + 8);
 }
 
+// With every staged column 16-byte aligned (at most kXPfMax of them) the next
+// sub-tile is loaded into registers while the current one is counted and
+// ranked (a column of a sub-tile is at most kXBlock 16-byte chunks), waited
+// for before the current tuples are stored, and written to LDS once they have
+// left.  Barriers inside the loop order LDS only: a full barrier waits for
+// every outstanding load and store of the wave, and every LDS write after a
+// global-to-LDS load waits for it, so neither would let loads overlap the row
+// work.
+constexpr int kXPfMax = 5;
+
 __global__ __launch_bounds__(kXBlock) void k_brx_scatter(const BrxArgs a) {
+  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
   extern __shared__ __attribute__((aligned(16))) uint8_t s_raw[];
   const int64_t t = blockIdx.x;
   const int fi = a.tile_frag[t];
@@ -346,17 +357,39 @@ __global__ __launch_bounds__(kXBlock) void k_brx_scatter(const BrxArgs a) {
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const int64_t tl = t - x.tile0;
   const int tw = 1 + a.nv;
-  for (int r = threadIdx.x; r < R; r += kXBlock) s_base[r] = a.starts[x.cbase + (int64_t)r * x.tiles + tl];
+  for (int r = threadIdx.x; r < R; r += kXBlock) {
+    s_base[r] = a.starts[x.cbase + (int64_t)r * x.tiles + tl];
+    s_cnt[r] = 0;
+  }
   const int per = (R + kXBlock - 1) / kXBlock;  // <= 4
+  bool pf_ok = x.nst <= kXPfMax;
+  for (int j = 0; j < x.nst; ++j) pf_ok = pf_ok && x.st[j].align >= 16;
+  {
+    const int64_t sbase = tl * kXTile;
+    if (sbase < g.n) bx_stage(x, x.nst, 1, sbase, g.n - sbase < kXSub ? (int)(g.n - sbase) : kXSub, s_in);
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
 
   for (int sub = 0; sub < kXSubs; ++sub) {
     const int64_t sbase = tl * kXTile + (int64_t)sub * kXSub;
     if (sbase >= g.n) break;
     const int nrows = g.n - sbase < kXSub ? (int)(g.n - sbase) : kXSub;
-    for (int r = threadIdx.x; r < R; r += kXBlock) s_cnt[r] = 0;
-    bx_stage(x, x.nst, 1, sbase, nrows, s_in);
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
+    const int64_t nbase = sbase + kXSub;
+    const bool has_next = sub + 1 < kXSubs && nbase < g.n;
+    const bool pf = pf_ok && has_next && g.n - nbase >= kXSub;
+    u32x4 pfv[kXPfMax];
+#pragma unroll
+    for (int j = 0; j < kXPfMax; ++j) pfv[j] = u32x4{0u, 0u, 0u, 0u};
+    if (pf) {
+#pragma unroll
+      for (int j = 0; j < kXPfMax; ++j) {
+        if (j >= x.nst) continue;
+        const int w = type_width(x.st[j].type);
+        if ((int)threadIdx.x < kXSub * w / 16)
+          pfv[j] = *reinterpret_cast<const u32x4*>(x.st[j].data + nbase * w + (int64_t)threadIdx.x * 16);
+      }
+    }
     uint64_t key[kXRows];
     uint8_t special[kXRows];
     const uint32_t keep = bx_keep_keys<kXRows>(x, g, s_in, 1, sbase, nrows, key, special);
@@ -375,7 +408,7 @@ __global__ __launch_bounds__(kXBlock) void k_brx_scatter(const BrxArgs a) {
       s_pp[r] = (bx_region(h, x.rbits) << 16) | atomicAdd(&s_cnt[bx_region(h, x.rbits)], 1u);
       s_h[r] = h;
     }
-    __syncthreads();
+    lds_barrier();
     // Exclusive scan of the region counts.
     uint32_t mysum = 0;
     uint32_t cnt_own[4] = {0u, 0u, 0u, 0u};
@@ -394,7 +427,7 @@ __global__ __launch_bounds__(kXBlock) void k_brx_scatter(const BrxArgs a) {
       if (lane >= o) incl += y;
     }
     if (lane == kWave - 1) s_wsum[wave] = incl;
-    __syncthreads();
+    lds_barrier();
     uint32_t wpre = 0, tot = 0;
 #pragma unroll
     for (int w = 0; w < kXBlock / kWave; ++w) {
@@ -411,14 +444,18 @@ __global__ __launch_bounds__(kXBlock) void k_brx_scatter(const BrxArgs a) {
       }
     }
     if (threadIdx.x == 0) s_total = tot;
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int i = 0; i < kXRows; ++i) {
       const int r = i * kXBlock + threadIdx.x;
       const uint32_t pp = s_pp[r];
       if (pp != 0xffffffffu) s_src[s_cnt[pp >> 16] + (pp & 0xffffu)] = (uint16_t)r;
     }
-    __syncthreads();
+    lds_barrier();
+    // The next sub-tile's loads have landed (and the previous sub-tile's
+    // stores left) before this one's tuples are stored, so that refilling LDS
+    // below waits for nothing.
+    __builtin_amdgcn_s_waitcnt(0);
     // Tuples in region order: consecutive threads write consecutive tuples of
     // a region's run; value words are computed here from the staged columns.
     const int total = (int)s_total;
@@ -431,13 +468,28 @@ __global__ __launch_bounds__(kXBlock) void k_brx_scatter(const BrxArgs a) {
       const uint32_t nnm = bx_tuple_values(a, x, g, s_in, r, sbase + r, dst + 1);
       if (a.need_nn) a.tnn[pos] = (uint8_t)nnm;
     }
-    __syncthreads();
+    // Every tuple has left the staged input; the next sub-tile replaces it.
+    lds_barrier();
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int q = threadIdx.x * per + j;
-      if (j < per && q < R) s_base[q] += cnt_own[j];
+      if (j < per && q < R) {
+        s_base[q] += cnt_own[j];
+        s_cnt[q] = 0;
+      }
     }
-    __syncthreads();
+    if (pf) {
+#pragma unroll
+      for (int j = 0; j < kXPfMax; ++j) {
+        if (j >= x.nst) continue;
+        if ((int)threadIdx.x < kXSub * type_width(x.st[j].type) / 16)
+          *reinterpret_cast<u32x4*>(s_in + x.st_off[j] + (int64_t)threadIdx.x * 16) = pfv[j];
+      }
+    } else if (has_next) {
+      bx_stage(x, x.nst, 1, nbase, g.n - nbase < kXSub ? (int)(g.n - nbase) : kXSub, s_in);
+      __builtin_amdgcn_s_waitcnt(0);
+    }
+    lds_barrier();
   }
 }
 
