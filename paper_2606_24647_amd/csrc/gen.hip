@@ -6,7 +6,8 @@
 //   mix     SplitMix64 finaliser (Steele, Lea and Flood, OOPSLA 2014)
 //   stream  s_c = mix(seed ^ c*GAMMA), r(row) = mix(s_c + (row+1)*GAMMA)
 //   uniform lo + mulhi64(r, hi-lo+1)
-//   powerlaw  t = uniform on [2^20, T1), key = (t*t) >> 40
+//   zipf     k = 1 + #{j : T[j] <= r >> 1}, T the host's table of 63-bit
+//            thresholds of the distribution function (P(k) ~ k^-0.5)
 //   permutation  4-round Feistel over an even bit width, cycle walking
 #include <hip/hip_runtime.h>
 
@@ -37,14 +38,20 @@ __global__ void k_uniform(T* out, int64_t n, uint64_t s, int64_t start, int64_t 
   }
 }
 
-__global__ void k_powerlaw(int64_t* out, int64_t n, uint64_t s, int64_t start, uint64_t t0, uint64_t range,
-                           int64_t N) {
+// Zipf keys by inversion: the number of thresholds at or below the 63-bit
+// draw (binary search over the nthr ascending thresholds), plus one.
+__global__ void k_zipf(int64_t* out, int64_t n, uint64_t s, int64_t start, const uint64_t* thr, int64_t nthr) {
   const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t step = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = i0; i < n; i += step) {
-    const uint64_t t = t0 + __umul64hi(draw(s, start + i), range);
-    int64_t k = (int64_t)((t * t) >> 40);
-    out[i] = k > N ? N : k;
+    const uint64_t r = draw(s, start + i) >> 1;
+    int64_t lo = 0, hi = nthr;  // first index with thr[index] > r
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (thr[mid] <= r) lo = mid + 1;
+      else hi = mid;
+    }
+    out[i] = lo + 1;
   }
 }
 
@@ -107,14 +114,13 @@ int gqgen_uniform(void* out, int width, int64_t n, uint64_t seed, uint64_t col, 
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-// Power-law keys on 1..N (int64), t1 = isqrt((N+1) << 40) computed by the caller.
-int gqgen_powerlaw(int64_t* out, int64_t n, uint64_t seed, uint64_t col, int64_t start, int64_t N, uint64_t t1,
-                   hipStream_t stream) {
-  const uint64_t t0 = 1ull << 20;
-  if (n < 0 || t1 <= t0 || t1 - t0 > (1ull << 32)) return -1;
+// Zipf keys on 1..N (int64); thr: the N - 1 thresholds (device memory).
+int gqgen_zipf(int64_t* out, int64_t n, uint64_t seed, uint64_t col, int64_t start, int64_t N, const uint64_t* thr,
+               hipStream_t stream) {
+  if (n < 0 || N < 1 || (N > 1 && !thr)) return -1;
   if (n == 0) return 0;
-  hipLaunchKernelGGL(k_powerlaw, dim3(grid_for(n)), dim3(256), 0, stream, out, n, stream_seed(seed, col), start, t0,
-                     t1 - t0, N);
+  hipLaunchKernelGGL(k_zipf, dim3(grid_for(n)), dim3(256), 0, stream, out, n, stream_seed(seed, col), start, thr,
+                     N - 1);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -20,10 +20,12 @@ Building blocks (all mod 2**64):
   with ``GAMMA = 0x9e3779b97f4a7c15``.
 * uniform integer on ``[lo, hi]``: ``lo + mulhi64(r, hi - lo + 1)`` (Lemire's
   multiply-shift range reduction; the range is at most 2**32 here).
-* power-law keys on ``1..N`` with density proportional to ``k**-0.5``: draw an
-  integer ``t`` uniformly on ``[2**20, T1)`` with ``T1 = isqrt((N + 1) << 40)``
-  and return ``(t * t) >> 40``.  P(k) is proportional to sqrt(k+1) - sqrt(k),
-  the continuous form of a Zipf law with exponent s = 0.5.
+* Zipf keys on ``1..N`` with P(k) proportional to ``k**-0.5`` (exponent
+  s = 0.5), by inversion: the thresholds ``T[k-1] = floor(2**63 * F(k))`` for
+  k = 1..N-1, F the distribution function (float64 cumulative sums, computed
+  once per N on the host and handed to the device generator as a table), and
+  a 63-bit draw ``r >> 1`` maps to ``1 + #{k : T[k] <= r >> 1}``.  Host and
+  device search the same table, so they agree bit for bit.
 * permutation of ``0..N-1``: a 4-round balanced Feistel network over the
   smallest even bit width covering N, with cycle walking until the value falls
   below N (Black and Rogaway, "Ciphers with arbitrary finite domains", 2002).
@@ -129,18 +131,32 @@ def uniform_at(seed: int, col: int, rows: np.ndarray, lo: int, hi: int, dtype=np
     return v.astype(dtype, copy=False)
 
 
-def powerlaw_t1(N: int) -> int:
-    return math.isqrt((N + 1) << 40)
+_ZIPF_THRESHOLDS = {}
 
 
-def powerlaw(seed: int, col: int, start: int, n: int, N: int) -> np.ndarray:
-    """Keys on 1..N with P(k) proportional to sqrt(k+1)-sqrt(k) (Zipf s=0.5 form)."""
-    t0 = 1 << 20
-    t1 = powerlaw_t1(N)
-    t = uniform(seed, col, start, n, t0, t1 - 1, np.int64).astype(np.uint64)
-    with np.errstate(over="ignore"):
-        k = (t * t) >> _U64(40)
-    return np.minimum(k.astype(np.int64), N)
+def zipf_thresholds(N: int) -> np.ndarray:
+    """uint64 T[0..N-2]: T[k-1] = floor(2**63 * F(k)), F the distribution
+    function of P(k) proportional to k**-0.5 on 1..N (cached per N)."""
+    t = _ZIPF_THRESHOLDS.get(N)
+    if t is None:
+        w = 1.0 / np.sqrt(np.arange(1, N + 1, dtype=np.float64))
+        cdf = np.cumsum(w)
+        t = np.floor(cdf[:-1] / cdf[-1] * 2.0 ** 63).astype(np.uint64)
+        _ZIPF_THRESHOLDS.clear()
+        _ZIPF_THRESHOLDS[N] = t
+    return t
+
+
+def zipf(seed: int, col: int, start: int, n: int, N: int) -> np.ndarray:
+    """Keys on 1..N with P(k) proportional to k**-0.5 (Zipf, s = 0.5).  The
+    draws are searched in sorted order (the table is 8 N bytes; random probes
+    into it would be memory-latency bound) and the keys put back in row order."""
+    t = zipf_thresholds(N)
+    r = raw(seed, col, start, n) >> _U64(1)
+    order = np.argsort(r)
+    k = np.empty(n, dtype=np.int64)
+    k[order] = np.searchsorted(t, r[order], side="right") + 1
+    return k
 
 
 def _feistel_bits(N: int) -> int:
@@ -290,9 +306,9 @@ def dim_c2(n: int = 15_000_000, start: int = 0, seed: int = 2, ckeys: int | None
 
 def batch_c3(n: int = 60_000_000, nkeys: int = 15_000_000, start: int = 0, seed: int = 3,
              null_permille: int = 0) -> Table:
-    """Exchange batch: power-law int64 key, int64, int32, int8."""
+    """Exchange batch: Zipf (s = 0.5) int64 key, int64, int32, int8."""
     t = Table()
-    t.cols.append(Column("key", powerlaw(seed, 0, start, n, nkeys),
+    t.cols.append(Column("key", zipf(seed, 0, start, n, nkeys),
                          validity(seed, 0, start, n, null_permille) if null_permille else None))
     spec = [("v64", 1, PRICE_LO, PRICE_HI, np.int64), ("v32", 2, 0, DATE_DAYS - 1, np.int32),
             ("v8", 3, 0, 2, np.int8)]

@@ -8,6 +8,7 @@ from __future__ import annotations
 import ctypes as C
 import os
 
+import numpy as np
 import torch
 
 from . import datagen as dg
@@ -20,7 +21,7 @@ if not os.path.exists(GEN_PATH):
 _gen = C.CDLL(GEN_PATH)
 _P = C.c_void_p
 _gen.gqgen_uniform.argtypes = [_P, C.c_int, C.c_int64, C.c_uint64, C.c_uint64, C.c_int64, C.c_int64, C.c_int64, _P]
-_gen.gqgen_powerlaw.argtypes = [_P, C.c_int64, C.c_uint64, C.c_uint64, C.c_int64, C.c_int64, C.c_uint64, _P]
+_gen.gqgen_zipf.argtypes = [_P, C.c_int64, C.c_uint64, C.c_uint64, C.c_int64, C.c_int64, _P, _P]
 _gen.gqgen_permutation.argtypes = [_P, C.c_int64, C.c_uint64, C.c_uint64, C.c_int64, C.c_int64, C.c_int64, _P]
 
 _WIDTH = {torch.int8: 1, torch.int16: 2, torch.int32: 4, torch.int64: 8}
@@ -43,10 +44,20 @@ def uniform(seed, col, start, n, lo, hi, dtype=torch.int64, out=None):
     return t
 
 
-def powerlaw(seed, col, start, n, N):
+_ZIPF_DEV = {}
+
+
+def zipf(seed, col, start, n, N):
+    """Device twin of datagen.zipf: the host's threshold table, uploaded once
+    per N, searched on the device."""
+    thr = _ZIPF_DEV.get(N)
+    if thr is None:
+        _ZIPF_DEV.clear()
+        thr = torch.from_numpy(dg.zipf_thresholds(N).view(np.int64)).cuda() if N > 1 else None
+        _ZIPF_DEV[N] = thr
     t = torch.empty(max(1, n), dtype=torch.int64, device="cuda")[:n]
-    _check(_gen.gqgen_powerlaw(t.data_ptr() if n else None, n, seed, col, start, N, dg.powerlaw_t1(N), _stream()),
-           "powerlaw")
+    _check(_gen.gqgen_zipf(t.data_ptr() if n else None, n, seed, col, start, N,
+                           thr.data_ptr() if thr is not None else None, _stream()), "zipf")
     return t
 
 
@@ -92,7 +103,7 @@ def dim_c2(n=15_000_000, start=0, seed=2, ckeys=None) -> DevTable:
 
 def batch_c3(n=60_000_000, nkeys=15_000_000, start=0, seed=3) -> DevTable:
     return _table([
-        (powerlaw(seed, 0, start, n, nkeys), 0),
+        (zipf(seed, 0, start, n, nkeys), 0),
         (uniform(seed, 1, start, n, dg.PRICE_LO, dg.PRICE_HI), 0),
         (uniform(seed, 2, start, n, 0, dg.DATE_DAYS - 1, torch.int32), 0),
         (uniform(seed, 3, start, n, 0, 2, torch.int8), 0),

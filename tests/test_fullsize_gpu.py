@@ -87,7 +87,7 @@ def test_pipeline_fact60m_dim15m(mods):
 
 @pytest.fixture(scope="module")
 def c3_keys():
-    return dg.powerlaw(3, 0, 0, FACT, DIM)
+    return dg.zipf(3, 0, 0, FACT, DIM)
 
 
 @pytest.mark.parametrize("P", [64, 256])
