@@ -642,7 +642,9 @@ __global__ __launch_bounds__(kRp1Block) __attribute__((amdgpu_waves_per_eu(6))) 
       if (!((keep >> i) & 1u)) continue;
       const int r = i * BLOCK + threadIdx.x;
       const uint32_t pos = s_off[(uint32_t)(h[i] >> (64 - kR1Bits))] + rank[i];
-      rp_put_tuple(s_tup + (size_t)pos * tw, rp_tuple(a, s_in, r, h[i]), tw);
+      // Probe: hash and aggregate inputs; build: hash and row.
+      const Tup4 tup = a.probe ? rp_tuple(a, s_in, r, h[i]) : Tup4{h[i], (uint64_t)(sbase + r), 0, 0};
+      rp_put_tuple(s_tup + (size_t)pos * tw, tup, tw);
     }
     // The sorted tuples are complete and the staged input is no longer read.
     lds_barrier();
@@ -1665,7 +1667,7 @@ int rp_run(gq_ctx* ctx, RpArgs& a, int64_t* offsets, int64_t* total, hipStream_t
 // to 4096 regions, and LDS room for both kernels (k_rp1 stages its columns for
 // kRp1Sub rows, half the layout built for kRpSub).
 static bool rp2_applies(const RpArgs& a) {
-  if (!a.probe || a.need_nn || a.pbits < 8 || a.pbits > 12 || a.tw < 2 || a.tw > 4) return false;
+  if (a.need_nn || a.pbits < 8 || a.pbits > 12 || a.tw < 2 || a.tw > 4 || (!a.probe && a.tw != 2)) return false;
   const int P = 1 << a.pbits;
   return rp1_lds(P, a.in_bytes / 2, a.tw) + 512 <= kRpMaxLds && rp2_lds(a.tw) + 6144 <= kRpMaxLds;
 }
@@ -1673,20 +1675,21 @@ static bool rp2_applies(const RpArgs& a) {
 template <bool NULLABLE>
 static int rp1_launch(gq_ctx* ctx, const RpArgs& h, int npf, size_t lds, hipStream_t stream) {
   const dim3 grid((unsigned)h.ntiles), block(kRp1Block);
+  const char* nm = h.probe ? "rp1_probe" : "rp1_build";
   switch (npf) {
-    case 1: GQ_LAUNCH(ctx, "rp1_probe", (k_rp1<NULLABLE, 1>), grid, block, lds, stream, h); break;
-    case 2: GQ_LAUNCH(ctx, "rp1_probe", (k_rp1<NULLABLE, 2>), grid, block, lds, stream, h); break;
-    case 3: GQ_LAUNCH(ctx, "rp1_probe", (k_rp1<NULLABLE, 3>), grid, block, lds, stream, h); break;
-    case 4: GQ_LAUNCH(ctx, "rp1_probe", (k_rp1<NULLABLE, 4>), grid, block, lds, stream, h); break;
-    case 5: GQ_LAUNCH(ctx, "rp1_probe", (k_rp1<NULLABLE, 5>), grid, block, lds, stream, h); break;
-    default: GQ_LAUNCH(ctx, "rp1_probe", (k_rp1<NULLABLE, 0>), grid, block, lds, stream, h); break;
+    case 1: GQ_LAUNCH(ctx, nm, (k_rp1<NULLABLE, 1>), grid, block, lds, stream, h); break;
+    case 2: GQ_LAUNCH(ctx, nm, (k_rp1<NULLABLE, 2>), grid, block, lds, stream, h); break;
+    case 3: GQ_LAUNCH(ctx, nm, (k_rp1<NULLABLE, 3>), grid, block, lds, stream, h); break;
+    case 4: GQ_LAUNCH(ctx, nm, (k_rp1<NULLABLE, 4>), grid, block, lds, stream, h); break;
+    case 5: GQ_LAUNCH(ctx, nm, (k_rp1<NULLABLE, 5>), grid, block, lds, stream, h); break;
+    default: GQ_LAUNCH(ctx, nm, (k_rp1<NULLABLE, 0>), grid, block, lds, stream, h); break;
   }
   GQ_LAUNCH_CHECK(ctx);
   return GQ_OK;
 }
 
 // k_rp1, the column scan and k_rp2 for the probe side; offsets: P + 1 int64.
-int rp_run2(gq_ctx* ctx, RpArgs& a, int64_t* offsets, hipStream_t stream) {
+int rp_run2(gq_ctx* ctx, RpArgs& a, int64_t* offsets, int64_t* total, hipStream_t stream) {
   const int64_t P = 1ll << a.pbits;
   // Tiles of at most kRpMaxTile rows (a multiple of kRp1Sub), as many as fill
   // whole rounds of the workgroups resident at once (three per CU), so that
@@ -1701,7 +1704,11 @@ int rp_run2(gq_ctx* ctx, RpArgs& a, int64_t* offsets, hipStream_t stream) {
   if (t < kRpMinTile) t = kRpMinTile;
   a.tile_rows = t;
   a.ntiles = (a.n + a.tile_rows - 1) / a.tile_rows;
-  if (a.ntiles == 0) return launch_fill_u32(ctx, offsets, 0u, 2 * (P + 1), stream);
+  if (a.ntiles == 0) {
+    int rc = launch_fill_u32(ctx, offsets, 0u, 2 * (P + 1), stream);
+    if (!rc && total) rc = launch_fill_u32(ctx, total, 0u, 2, stream);
+    return rc;
+  }
   const int64_t subs = t / kRp1Sub;
   // k_rp2 workgroups of about 2 * kRp2Round * kR1 input rows (a round of
   // tuples when half the rows are kept), at most kRp2MaxRuns runs.
@@ -1741,16 +1748,17 @@ int rp_run2(gq_ctx* ctx, RpArgs& a, int64_t* offsets, hipStream_t stream) {
   int rc = nullable ? rp1_launch<true>(ctx, h, npf, lds1, stream) : rp1_launch<false>(ctx, h, npf, lds1, stream);
   if (rc) return rc;
   const dim3 cgrid((unsigned)nchunks, (unsigned)((P + 255) / 256));
-  GQ_LAUNCH(ctx, "rp_scan_probe", k_cs_chunk, cgrid, dim3(256), 0, stream, (const uint32_t*)a.counts, a.ntiles,
-            (int)P, csum, a.rtot);
+  GQ_LAUNCH(ctx, a.probe ? "rp_scan_probe" : "rp_scan_build", k_cs_chunk, cgrid, dim3(256), 0, stream,
+            (const uint32_t*)a.counts, a.ntiles, (int)P, csum, a.rtot);
   GQ_LAUNCH_CHECK(ctx);
-  GQ_LAUNCH(ctx, "rp_scan_probe", k_cs_fill, cgrid, dim3(256), 0, stream, (const uint32_t*)a.counts,
-            (const uint32_t*)csum, (const uint32_t*)a.rtot, a.ntiles, (int)P, a.starts, offsets, (int64_t*)nullptr);
+  GQ_LAUNCH(ctx, a.probe ? "rp_scan_probe" : "rp_scan_build", k_cs_fill, cgrid, dim3(256), 0, stream, (const uint32_t*)a.counts,
+            (const uint32_t*)csum, (const uint32_t*)a.rtot, a.ntiles, (int)P, a.starts, offsets, total);
   GQ_LAUNCH_CHECK(ctx);
   const dim3 g2((unsigned)(kR1 * ngroups)), b2(kRp2Block);
-  if (a.tw == 2) GQ_LAUNCH(ctx, "rp2_probe", k_rp2<2>, g2, b2, rp2_lds(2), stream, a, (int32_t)group);
-  else if (a.tw == 3) GQ_LAUNCH(ctx, "rp2_probe", k_rp2<3>, g2, b2, rp2_lds(3), stream, a, (int32_t)group);
-  else GQ_LAUNCH(ctx, "rp2_probe", k_rp2<4>, g2, b2, rp2_lds(4), stream, a, (int32_t)group);
+  const char* nm2 = a.probe ? "rp2_probe" : "rp2_build";
+  if (a.tw == 2) GQ_LAUNCH(ctx, nm2, k_rp2<2>, g2, b2, rp2_lds(2), stream, a, (int32_t)group);
+  else if (a.tw == 3) GQ_LAUNCH(ctx, nm2, k_rp2<3>, g2, b2, rp2_lds(3), stream, a, (int32_t)group);
+  else GQ_LAUNCH(ctx, nm2, k_rp2<4>, g2, b2, rp2_lds(4), stream, a, (int32_t)group);
   GQ_LAUNCH_CHECK(ctx);
   return GQ_OK;
 }
@@ -1797,7 +1805,9 @@ int rj_build(gq_ctx* ctx, const gq_batch* build, int32_t key_col, const gq_pred*
     return set_error(ctx, GQ_ERR_UNSUPPORTED, "radix join: build staging does not fit");
   a.okey = t->rj_kr;
   a.ocap = build->nrows;
-  return rp_run(ctx, a, t->rj_off, &t->hdr->nrows, stream);
+  a.tw = 2;
+  return rp2_applies(a) ? rp_run2(ctx, a, t->rj_off, &t->hdr->nrows, stream)
+                        : rp_run(ctx, a, t->rj_off, &t->hdr->nrows, stream);
 }
 
 // Staging plan and value words of the probe side; false when it does not fit.
@@ -1896,7 +1906,7 @@ int rj_part_create(gq_ctx* ctx, const gq_batch* in, int32_t probe_key, const gq_
   r.ocap = cap;
   part->toff = part->ws.as<int64_t>(off_toff);
   part->pbits = pbits;
-  const int rc = rp2_applies(r) ? rp_run2(ctx, r, part->toff, stream) : rp_run(ctx, r, part->toff, nullptr, stream);
+  const int rc = rp2_applies(r) ? rp_run2(ctx, r, part->toff, nullptr, stream) : rp_run(ctx, r, part->toff, nullptr, stream);
   if (rc) {
     delete part;
     return rc;
