@@ -551,6 +551,11 @@ def main():
     import torch
     from paper_2606_24647_amd import devgen, gq
     REGIONS_LOG2[0] = args.regions_log2
+    # torch's caching allocator keeps freed blocks per stream (the serving
+    # section's slots hold their heavy queries' workspaces that way); capped at
+    # 90% of the device it gives cached blocks back before taking the memory
+    # the runtime needs for itself (kernels' scratch, queues).
+    torch.cuda.set_per_process_memory_fraction(0.9, 0)
 
     dev = torch.cuda.get_device_properties(0)
     log(f"device: {dev.name} {dev.gcnArchName} CUs={dev.multi_processor_count}")

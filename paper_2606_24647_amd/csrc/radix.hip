@@ -1663,11 +1663,17 @@ int rp_run(gq_ctx* ctx, RpArgs& a, int64_t* offsets, int64_t* total, hipStream_t
 }
 
 
-// Two-level partition of the probe side: tuples without a non-NULL mask, 256
-// to 4096 regions, and LDS room for both kernels (k_rp1 stages its columns for
-// kRp1Sub rows, half the layout built for kRpSub).
+// Two-level partition: tuples without a non-NULL mask, 256 to 4096 regions,
+// first-level slots of at most kRp2MaxSlots bytes (they come on top of the
+// final tuples: above that size, as for a 600M-row input shared by concurrent
+// queries, the single-level path's smaller workspace wins), and LDS room for
+// both kernels (k_rp1 stages its columns for kRp1Sub rows, half the layout
+// built for kRpSub).
+constexpr size_t kRp2MaxSlots = (size_t)4 << 30;
+
 static bool rp2_applies(const RpArgs& a) {
   if (a.need_nn || a.pbits < 8 || a.pbits > 12 || a.tw < 2 || a.tw > 4 || (!a.probe && a.tw != 2)) return false;
+  if ((size_t)(a.n + kRp1Sub) * a.tw * 8 > kRp2MaxSlots) return false;
   const int P = 1 << a.pbits;
   return rp1_lds(P, a.in_bytes / 2, a.tw) + 512 <= kRpMaxLds && rp2_lds(a.tw) + 6144 <= kRpMaxLds;
 }
