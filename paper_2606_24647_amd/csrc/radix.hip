@@ -1665,11 +1665,12 @@ int rp_run(gq_ctx* ctx, RpArgs& a, int64_t* offsets, int64_t* total, hipStream_t
 
 // Two-level partition: tuples without a non-NULL mask, 256 to 4096 regions,
 // first-level slots of at most kRp2MaxSlots bytes (they come on top of the
-// final tuples: above that size, as for a 600M-row input shared by concurrent
-// queries, the single-level path's smaller workspace wins), and LDS room for
+// final tuples: above that size, as for the 600M-row fact and 150M-row
+// dimension sides of concurrent serving queries, each slot's stream caching
+// such workspaces, the single-level path's smaller workspace wins), LDS room for
 // both kernels (k_rp1 stages its columns for kRp1Sub rows, half the layout
 // built for kRpSub).
-constexpr size_t kRp2MaxSlots = (size_t)4 << 30;
+constexpr size_t kRp2MaxSlots = (size_t)2 << 30;
 
 static bool rp2_applies(const RpArgs& a) {
   if (a.need_nn || a.pbits < 8 || a.pbits > 12 || a.tw < 2 || a.tw > 4 || (!a.probe && a.tw != 2)) return false;
