@@ -600,6 +600,15 @@ def main():
         log(f"{name}: {json.dumps(r)[:2000]}")
         return r
 
+    # Serving right after the pipeline: its open-loop runs are the part of the
+    # bench most sensitive to what earlier sections leave behind (allocator
+    # caches, a device that has been under load for minutes).
+    serving = None
+    if not args.no_serving:
+        qps_list = tuple(float(x) for x in args.serving_qps.split(","))
+        serving = section("serving", lambda: run_serving(torch, gq, devgen, nq=args.serving_queries,
+                                                               qps_list=qps_list, slots=args.serving_slots,
+                                                               max_heavy=args.serving_max_heavy))
     operators = None
     if not args.no_operators:
         operators = section("operators", lambda: run_operators(torch, gq, devgen, ctx, c2))
@@ -610,12 +619,6 @@ def main():
     if not args.no_batched:
         batched = section("batched", lambda: run_batched(torch, gq, devgen, ctx, tune=not args.batched_profile,
                                                          plain=not args.batched_profile))
-    serving = None
-    if not args.no_serving:
-        qps_list = tuple(float(x) for x in args.serving_qps.split(","))
-        serving = section("serving", lambda: run_serving(torch, gq, devgen, nq=args.serving_queries,
-                                                               qps_list=qps_list, slots=args.serving_slots,
-                                                               max_heavy=args.serving_max_heavy))
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on a 1/4 sample")
