@@ -1460,31 +1460,33 @@ __global__ __launch_bounds__(kRjBlock) __attribute__((amdgpu_waves_per_eu(4))) v
       if (lane == 0) s_cc[c][wave] = (uint32_t)__popcll(m);
     }
     lds_barrier();
-    if (threadIdx.x == 0) {
-      uint32_t tot = 0;
-      for (int c = 0; c < nchunks; ++c)
-        for (int w = 0; w < NW; ++w) tot += s_cc[c][w];
-      const int64_t base = tot ? (int64_t)atomicAdd((unsigned long long*)a.d_count, (unsigned long long)tot) : 0;
-      if (tot && base + tot > a.out_cap) atomicOr(a.dev_status, GQ_DEV_CAPACITY);
-      s_obase = base;
-      s_tot = tot;
+    // Wave 0 turns the (chunk, wave) counts, in emission order, into their
+    // exclusive prefix (two entries per lane) and reserves the item's output
+    // range.
+    if (wave == 0) {
+      static_assert(kRjChunks * NW <= 2 * kWave, "two (chunk, wave) counts per lane");
+      uint32_t* flat = &s_cc[0][0];
+      const int ne = nchunks * NW, e0 = 2 * lane, e1 = 2 * lane + 1;
+      const uint32_t x0 = e0 < ne ? flat[e0] : 0u, x1 = e1 < ne ? flat[e1] : 0u;
+      uint32_t tot;
+      const uint32_t pre = wave_prefix_small<8>(x0 + x1, &tot);  // x0 + x1 <= 128
+      if (e0 < ne) flat[e0] = pre;
+      if (e1 < ne) flat[e1] = pre + x0;
+      if (lane == 0) {
+        const int64_t base = tot ? (int64_t)atomicAdd((unsigned long long*)a.d_count, (unsigned long long)tot) : 0;
+        if (tot && base + tot > a.out_cap) atomicOr(a.dev_status, GQ_DEV_CAPACITY);
+        s_obase = base;
+        s_tot = tot;
+      }
     }
     lds_barrier();
     const int64_t obase = s_obase, otot = s_tot;
-    int64_t run = 0;
     for (int c = 0; c < nchunks; ++c) {
-      uint32_t wpre = 0, ctot = 0;
-#pragma unroll
-      for (int w = 0; w < NW; ++w) {
-        const uint32_t x = s_cc[c][w];
-        wpre += w < wave ? x : 0;
-        ctot += x;
-      }
       const int i = c * kRjBlock + threadIdx.x;
       const bool occ = (occm >> c) & 1u;
       const uint64_t m = ballot(occ);
       if (occ) {
-        const int64_t rel = run + wpre + rank_in(m);
+        const int64_t rel = (int64_t)s_cc[c][wave] + rank_in(m);
         const int64_t g = obase + rel;
         const uint64_t mult = s_mult[i];
         s_mult[i] = (uint32_t)rel;  // the slot's output row, for the validity bits below
@@ -1518,7 +1520,6 @@ __global__ __launch_bounds__(kRjBlock) __attribute__((amdgpu_waves_per_eu(4))) v
           }
         }
       }
-      run += ctot;
     }
     // 5. Validity bitmaps of the nullable output columns: the item's bits are
     // gathered in LDS, then stored word by word.
