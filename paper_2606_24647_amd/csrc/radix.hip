@@ -1384,14 +1384,12 @@ __global__ __launch_bounds__(kRjBlock) __attribute__((amdgpu_waves_per_eu(4))) v
     uint32_t tnext = 0;
     if (threadIdx.x == 0 && qi < kXcds) tnext = atomicAdd(&a.qticket[(home + qi) % kXcds], 1u);
 
-    // 1. The table is cleared while the item's loads are in flight.
+    // 1. Keys and multiplicities are cleared while the item's loads are in
+    // flight.  A slot's accumulator words are set when its first build key
+    // arrives; the other slots' (and the dump slots') are never read.
     for (int i = threadIdx.x; i < NS; i += kRjBlock) {
       s_keys[i] = kEmpty;
       s_mult[i] = 0;
-    }
-    for (int w = 0; w < a.nacc; ++w) {
-      const uint64_t id = a.ident[w];
-      for (int i = threadIdx.x; i < NS; i += kRjBlock) s_acc[(size_t)i * a.nacc + w] = id;
     }
     lds_barrier();
     // 2. Build keys of sub-region s, counting duplicates.
@@ -1412,7 +1410,8 @@ __global__ __launch_bounds__(kRjBlock) __attribute__((amdgpu_waves_per_eu(4))) v
           atomicOr(a.dev_status, GQ_DEV_TABLE_FULL);
           continue;
         }
-        atomicAdd(&s_mult[slot], 1u);
+        if (atomicAdd(&s_mult[slot], 1u) == 0u)
+          for (int w = 0; w < a.nacc; ++w) s_acc[(size_t)slot * a.nacc + w] = a.ident[w];
       }
     }
     lds_barrier();
@@ -1454,7 +1453,7 @@ __global__ __launch_bounds__(kRjBlock) __attribute__((amdgpu_waves_per_eu(4))) v
     uint32_t occm = 0;
     for (int c = 0; c < nchunks; ++c) {
       const int i = c * kRjBlock + threadIdx.x;
-      const bool occ = i <= L && s_acc[(size_t)i * a.nacc] != 0;
+      const bool occ = i <= L && s_mult[i] != 0u && s_acc[(size_t)i * a.nacc] != 0;
       const uint64_t m = ballot(occ);
       if (occ) occm |= 1u << c;
       if (lane == 0) s_cc[c][wave] = (uint32_t)__popcll(m);
