@@ -702,7 +702,13 @@ __global__ __launch_bounds__(kRp2Block) void k_rp2(const RpArgs a, int32_t group
   const int P = 1 << a.pbits;
   uint64_t* s_tup = reinterpret_cast<uint64_t*>(s_raw);
   uint8_t* s_sid = reinterpret_cast<uint8_t*>(s_tup + (size_t)kRp2Round * tw);
-  const int r1 = (int)(blockIdx.x % kR1);
+  // The kR1 workgroups of a tile group are dispatched together, one XCD
+  // after another; the kR1 / kXcds first-level regions that share an XCD are
+  // adjacent, so the lines their runs share in a slot are read once into that
+  // XCD's L2.
+  static_assert(kR1 % kXcds == 0, "first-level regions spread evenly over the XCDs");
+  const int k = (int)(blockIdx.x % kR1);
+  const int r1 = (k % kXcds) * (kR1 / kXcds) + k / kXcds;
   const int64_t t0 = (int64_t)(blockIdx.x / kR1) * group;
   const int64_t t1 = t0 + group < a.ntiles ? t0 + group : a.ntiles;
   const int64_t subs = a.tile_rows / kRp1Sub;
