@@ -1363,6 +1363,12 @@ __global__ __launch_bounds__(kRjBlock) __attribute__((amdgpu_waves_per_eu(4))) v
   if (threadIdx.x == 0) s_item = cur;
   lds_barrier();
   uint64_t item = s_item;
+  // An empty table for the first item; each later item finds its table
+  // cleared by the threads that emitted the previous one.
+  for (int i = threadIdx.x; i < NS; i += kRjBlock) {
+    s_keys[i] = kEmpty;
+    s_mult[i] = 0;
+  }
   // The loads of an item (its region's offsets, its first build keys and its
   // first probe round) are issued as soon as the item is known: for the first
   // item here, for every later one right after the previous item's probe, so
@@ -1390,13 +1396,9 @@ __global__ __launch_bounds__(kRjBlock) __attribute__((amdgpu_waves_per_eu(4))) v
     uint32_t tnext = 0;
     if (threadIdx.x == 0 && qi < kXcds) tnext = atomicAdd(&a.qticket[(home + qi) % kXcds], 1u);
 
-    // 1. Keys and multiplicities are cleared while the item's loads are in
-    // flight.  A slot's accumulator words are set when its first build key
+    // 1. The table's keys and multiplicities are clear (see the end of the
+    // loop).  A slot's accumulator words are set when its first build key
     // arrives; the other slots' (and the dump slots') are never read.
-    for (int i = threadIdx.x; i < NS; i += kRjBlock) {
-      s_keys[i] = kEmpty;
-      s_mult[i] = 0;
-    }
     lds_barrier();
     // 2. Build keys of sub-region s, counting duplicates.
     for (int64_t base = b0; base < b1; base += (int64_t)kRjBlock * kRjUnroll) {
@@ -1552,8 +1554,19 @@ __global__ __launch_bounds__(kRjBlock) __attribute__((amdgpu_waves_per_eu(4))) v
       lds_barrier();
       rj_store_valid(a.out[oc].valid, s_vw, obase, otot, a.out_cap);
     }
-    // Every thread is done reading this item's table before it is cleared.
-    lds_barrier();
+    // Slots 0..L are read after the probe only by the thread that owns them
+    // (slot c * kRjBlock + thread of every chunk c), which clears them for
+    // the next item once its groups and validity bits are out; the dump
+    // slots' keys and multiplicities are never read.
+    for (int c = 0; c < nchunks; ++c) {
+      const int i = c * kRjBlock + threadIdx.x;
+      if (i <= L) {
+        s_keys[i] = kEmpty;
+        s_mult[i] = 0;
+      }
+    }
+    // (The barrier at the top of the loop orders these clears before the
+    // next item's inserts.)
   }
 }
 
