@@ -276,7 +276,14 @@ typedef struct gq_join_opts {
  * first call that needs its probe index (gq_join_probe, or a pipeline that
  * does not take the radix group-join) builds the index on its own stream and
  * re-records the table's event there, so every later reader, on any stream,
- * is ordered after the index build too. */
+ * is ordered after the index build too.
+ * Keys: 1 to GQ_MAX_KEYS integer columns.  With more than one, their values
+ * are packed into one 64-bit word per row (first column most significant,
+ * each field as wide as its build column's type), which must fit: more than
+ * 64 bits of key types gives GQ_ERR_UNSUPPORTED.  Rows with a NULL in any key
+ * column are not inserted.  Such a table serves gq_join_probe and
+ * gq_join_groupby; gq_pipeline and gq_pipeline_shared group by their one
+ * probe key and take single-key tables only (GQ_ERR_UNSUPPORTED otherwise). */
 int gq_join_build(gq_ctx* ctx, const gq_batch* build, const int32_t* keys, int nkeys,
                   const gq_pred* preds, int npreds, const gq_join_opts* opts,
                   hipStream_t stream, gq_join_table** out);
@@ -285,7 +292,10 @@ int gq_join_build(gq_ctx* ctx, const gq_batch* build, const int32_t* keys, int n
  * emit one (probe row, build row) pair per matching build row.  Pairs are
  * ordered by probe row, then build row, ascending (a canonical order of the
  * SQL result).  `probe_idx`/`build_idx` are device int32[out_cap]; *d_count
- * receives the number of pairs (GQ_DEV_CAPACITY if above out_cap). */
+ * receives the number of pairs (GQ_DEV_CAPACITY if above out_cap).  `nkeys`
+ * must equal the build's (GQ_ERR_INVALID otherwise); the probe's key columns
+ * may be of other integer types, and a row whose value in a key column lies
+ * outside the range of the build column's type, or is NULL, matches nothing. */
 int gq_join_probe(gq_ctx* ctx, const gq_join_table* table, const gq_batch* probe,
                   const int32_t* keys, int nkeys, const gq_pred* preds, int npreds,
                   int32_t* probe_idx, int32_t* build_idx, int64_t out_cap, int64_t* d_count,

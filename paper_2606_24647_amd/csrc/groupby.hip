@@ -1202,6 +1202,8 @@ int gq_pipeline(gq_ctx* ctx, const gq_plan* plan, const gq_batch* in, gq_batch* 
                 hipStream_t stream) {
   if (!ctx) return GQ_ERR_INVALID;
   if (!plan) return set_error(ctx, GQ_ERR_INVALID, "gq_pipeline: NULL plan");
+  if (plan->join && plan->join->nkeys != 1)
+    return set_error(ctx, GQ_ERR_UNSUPPORTED, "gq_pipeline: the join table must have one key column");
   return run_groupby(ctx, in, plan->group_keys, plan->ngroup_keys, plan->preds, plan->npreds, plan->aggs, plan->naggs,
                      &plan->opts, plan->join, plan->probe_key, out, d_groups, stream);
 }
@@ -1233,6 +1235,8 @@ int gq_pipeline_shared(gq_ctx* ctx, const gq_plan* plan, const gq_batch* in, int
     const gq_join_table* t = tables[i];
     if (!t || !d_groups[i]) return set_error(ctx, GQ_ERR_INVALID, "gq_pipeline_shared: NULL table or group count");
     if (t->device != ctx->device) return set_error(ctx, GQ_ERR_INVALID, "gq_pipeline_shared: table on another device");
+    if (t->nkeys != 1)
+      return set_error(ctx, GQ_ERR_UNSUPPORTED, "gq_pipeline_shared: every table must have one key column");
     if (!t->rj_kr || t->rj_pbits != tables[0]->rj_pbits)
       return set_error(ctx, GQ_ERR_UNSUPPORTED,
                        "gq_pipeline_shared: every table must be partitioned with the same region count");

@@ -19,6 +19,8 @@
 // Each thread issues the first probe of all its rows before resolving any of
 // them, so the random reads of a thread overlap; a probe step is one 16-byte
 // load of a (key, meta) pair.
+#include <vector>
+
 #include "agg.h"
 #include "radix.h"
 
@@ -733,6 +735,114 @@ int gather_rows(gq_ctx* ctx, const gq_batch* in, const int32_t* cols, int ncols,
   return GQ_OK;
 }
 
+// Composite join keys.  The key columns of a row are packed into one 64-bit
+// word, first column most significant, each field as wide as the build
+// side's column type (the value's low bits, two's complement), so two rows'
+// words are equal exactly when every key column is.  A row with a NULL key
+// column, or a probe value that does not fit its field (it cannot equal any
+// build value), gets a NULL word and matches nothing.  The tables and kernels
+// of the single-key join then run on that word.
+struct JKeyPack {
+  int32_t nk;
+  int32_t shift[GQ_MAX_KEYS];
+  int32_t bits[GQ_MAX_KEYS];
+  DCol cols[GQ_MAX_KEYS];
+};
+
+constexpr int kJPackBlock = 256;
+
+__global__ __launch_bounds__(kJPackBlock) void k_jpack_keys(const JKeyPack p, int64_t n, int64_t* out,
+                                                           uint32_t* valid) {
+  const int64_t r = (int64_t)blockIdx.x * kJPackBlock + threadIdx.x;
+  bool ok = r < n;
+  uint64_t key = 0;
+  for (int j = 0; j < p.nk && ok; ++j) {
+    const DCol& c = p.cols[j];
+    if (!valid_one(c, r)) {
+      ok = false;
+      break;
+    }
+    const int64_t v = load_one(c, r);
+    const int w = p.bits[j];
+    if (w < 64 && (v < -(1ll << (w - 1)) || v > (1ll << (w - 1)) - 1)) {
+      ok = false;
+      break;
+    }
+    const uint64_t mask = w == 64 ? ~0ull : (1ull << w) - 1;
+    key |= ((uint64_t)v & mask) << p.shift[j];
+  }
+  // Rows r..r+31 of a 32-aligned group give one validity word (every lane
+  // takes part in the ballot).
+  const uint64_t m = ballot(ok);
+  if (r < n) {
+    out[r] = ok ? (int64_t)key : 0;
+    const int lane = (int)(threadIdx.x & (kWave - 1));
+    if ((lane & 31) == 0) valid[r >> 5] = (uint32_t)(m >> lane);
+  }
+}
+
+// Field layout of the key columns `types` (the build side's): widths of the
+// types, first column most significant.  False if they need more than 64 bits.
+bool jkey_layout(const int32_t* types, int nk, JKeyPack& p) {
+  int total = 0;
+  for (int j = 0; j < nk; ++j) total += 8 * type_width(types[j]);
+  if (total > 64) return false;
+  p.nk = nk;
+  int sh = total;
+  for (int j = 0; j < nk; ++j) {
+    p.bits[j] = 8 * type_width(types[j]);
+    sh -= p.bits[j];
+    p.shift[j] = sh;
+  }
+  return true;
+}
+
+// The batch `b` with one more column: the packed key words of its columns
+// keys[0..nk) in the layout of `types`, in workspace memory of `ws`.  `cols`
+// receives the column list of the new batch (ncols + 1 entries).
+int jkey_pack_batch(gq_ctx* ctx, const gq_batch* b, const int32_t* keys, int nk, const int32_t* types, Scratch& ws,
+                    std::vector<gq_column>& cols, gq_batch& packed, hipStream_t stream) {
+  JKeyPack p;
+  std::memset(&p, 0, sizeof(p));
+  if (!jkey_layout(types, nk, p))
+    return set_error(ctx, GQ_ERR_UNSUPPORTED, "join: the key columns need more than 64 bits together");
+  for (int j = 0; j < nk; ++j) {
+    if (keys[j] < 0 || keys[j] >= b->ncols) return set_error(ctx, GQ_ERR_INVALID, "join: key column out of range");
+    p.cols[j] = make_dcol(b->cols[keys[j]]);
+  }
+  const int64_t n = b->nrows;
+  const size_t vbytes = align_up((size_t)((n + 31) / 32) * 4, 256);
+  if (!ws.get(vbytes + align_up((size_t)n * 8, 256)))
+    return set_error(ctx, GQ_ERR_NOMEM, "join: key packing workspace allocation failed");
+  uint32_t* valid = ws.as<uint32_t>(0);
+  int64_t* words = ws.as<int64_t>(vbytes);
+  if (n > 0) {
+    GQ_HIP_CHECK(ctx, hipSetDevice(ctx->device));
+    GQ_LAUNCH(ctx, "jpack_keys", k_jpack_keys, dim3((unsigned)((n + kJPackBlock - 1) / kJPackBlock)),
+              dim3(kJPackBlock), 0, stream, p, n, words, valid);
+    GQ_LAUNCH_CHECK(ctx);
+  }
+  cols.assign(b->cols, b->cols + b->ncols);
+  gq_column c;
+  std::memset(&c, 0, sizeof(c));
+  c.type = GQ_I64;
+  c.length = n;
+  c.offset = 0;
+  c.data = words;
+  c.validity = reinterpret_cast<uint8_t*>(valid);
+  cols.push_back(c);
+  packed = *b;
+  packed.ncols = b->ncols + 1;
+  packed.cols = cols.data();
+  return GQ_OK;
+}
+
+int join_build_one(gq_ctx* ctx, const gq_batch* build, const int32_t* keys, int nkeys, const gq_pred* preds,
+                   int npreds, const gq_join_opts* opts, hipStream_t stream, gq_join_table** out);
+int join_probe_one(gq_ctx* ctx, const gq_join_table* table, const gq_batch* probe, const int32_t* keys, int nkeys,
+                   const gq_pred* preds, int npreds, int32_t* probe_idx, int32_t* build_idx, int64_t out_cap,
+                   int64_t* d_count, hipStream_t stream);
+
 }  // namespace gq
 
 using namespace gq;
@@ -741,6 +851,55 @@ extern "C" {
 
 int gq_join_build(gq_ctx* ctx, const gq_batch* build, const int32_t* keys, int nkeys, const gq_pred* preds,
                   int npreds, const gq_join_opts* opts, hipStream_t stream, gq_join_table** out) {
+  if (!ctx || !out) return GQ_ERR_INVALID;
+  *out = nullptr;
+  if (nkeys <= 1 || !keys) return join_build_one(ctx, build, keys, nkeys, preds, npreds, opts, stream, out);
+  if (nkeys > GQ_MAX_KEYS) return set_error(ctx, GQ_ERR_UNSUPPORTED, "gq_join_build: more than GQ_MAX_KEYS key columns");
+  int rc = check_batch(ctx, build, "gq_join_build input");
+  if (rc) return rc;
+  int32_t types[GQ_MAX_KEYS];
+  for (int j = 0; j < nkeys; ++j) {
+    if (keys[j] < 0 || keys[j] >= build->ncols) return set_error(ctx, GQ_ERR_INVALID, "join: key column out of range");
+    types[j] = build->cols[keys[j]].type;
+  }
+  Scratch ws(ctx, stream);
+  std::vector<gq_column> cols;
+  gq_batch packed;
+  rc = jkey_pack_batch(ctx, build, keys, nkeys, types, ws, cols, packed, stream);
+  if (rc) return rc;
+  const int32_t kp = build->ncols;
+  rc = join_build_one(ctx, &packed, &kp, 1, preds, npreds, opts, stream, out);
+  if (rc) return rc;
+  (*out)->nkeys = nkeys;
+  for (int j = 0; j < nkeys; ++j) (*out)->key_types[j] = types[j];
+  return GQ_OK;
+}
+
+int gq_join_probe(gq_ctx* ctx, const gq_join_table* table, const gq_batch* probe, const int32_t* keys, int nkeys,
+                  const gq_pred* preds, int npreds, int32_t* probe_idx, int32_t* build_idx, int64_t out_cap,
+                  int64_t* d_count, hipStream_t stream) {
+  if (!ctx || !table) return GQ_ERR_INVALID;
+  if (nkeys != table->nkeys || !keys)
+    return set_error(ctx, GQ_ERR_INVALID, "gq_join_probe: the key count differs from the table's");
+  if (nkeys == 1)
+    return join_probe_one(ctx, table, probe, keys, 1, preds, npreds, probe_idx, build_idx, out_cap, d_count, stream);
+  int rc = check_batch(ctx, probe, "gq_join_probe input");
+  if (rc) return rc;
+  Scratch ws(ctx, stream);
+  std::vector<gq_column> cols;
+  gq_batch packed;
+  rc = jkey_pack_batch(ctx, probe, keys, nkeys, table->key_types, ws, cols, packed, stream);
+  if (rc) return rc;
+  const int32_t kp = probe->ncols;
+  return join_probe_one(ctx, table, &packed, &kp, 1, preds, npreds, probe_idx, build_idx, out_cap, d_count, stream);
+}
+
+}  // extern "C"
+
+namespace gq {
+
+int join_build_one(gq_ctx* ctx, const gq_batch* build, const int32_t* keys, int nkeys, const gq_pred* preds,
+                   int npreds, const gq_join_opts* opts, hipStream_t stream, gq_join_table** out) {
   if (!ctx || !out) return GQ_ERR_INVALID;
   *out = nullptr;
   int rc = check_batch(ctx, build, "gq_join_build input");
@@ -823,9 +982,9 @@ int gq_join_build(gq_ctx* ctx, const gq_batch* build, const int32_t* keys, int n
   return GQ_OK;
 }
 
-int gq_join_probe(gq_ctx* ctx, const gq_join_table* table, const gq_batch* probe, const int32_t* keys, int nkeys,
-                  const gq_pred* preds, int npreds, int32_t* probe_idx, int32_t* build_idx, int64_t out_cap,
-                  int64_t* d_count, hipStream_t stream) {
+int join_probe_one(gq_ctx* ctx, const gq_join_table* table, const gq_batch* probe, const int32_t* keys, int nkeys,
+                   const gq_pred* preds, int npreds, int32_t* probe_idx, int32_t* build_idx, int64_t out_cap,
+                   int64_t* d_count, hipStream_t stream) {
   if (!ctx || !table) return GQ_ERR_INVALID;
   int rc = check_batch(ctx, probe, "gq_join_probe input");
   if (rc) return rc;
@@ -876,6 +1035,10 @@ int gq_join_probe(gq_ctx* ctx, const gq_join_table* table, const gq_batch* probe
   }
   return GQ_OK;
 }
+
+}  // namespace gq
+
+extern "C" {
 
 const int64_t* gq_join_table_count_ptr(const gq_join_table* table) {
   return table ? &table->hdr->nrows : nullptr;

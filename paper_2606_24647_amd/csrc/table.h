@@ -240,6 +240,8 @@ struct gq_join_table {
   int32_t acc_slots = 0;
   int64_t build_rows = 0;
   int32_t key_type = GQ_I64;
+  int32_t nkeys = 1;          // key columns; above 1 the table holds their packed word
+  int32_t key_types[GQ_MAX_KEYS] = {GQ_I64, GQ_I64, GQ_I64, GQ_I64};  // the build side's key types
   int32_t device = 0;
   bool acc_dirty = false;     // accumulators used by an earlier group-join
   // Probe index (keys/meta/rows): built by gq_join_build for small build

@@ -212,6 +212,25 @@ def _brute_join(bk, bv, bpass, pk, pv, ppass):
     return out
 
 
+@pytest.mark.parametrize("seed", range(4))
+def test_join_two_keys_brute_force(seed):
+    # Key tuples: a pair matches when both columns are non-NULL and equal.
+    rng = np.random.default_rng(100 + seed)
+    nb, npr = int(rng.integers(1, 200)), int(rng.integers(1, 300))
+    ba, bb = rng.integers(-4, 4, nb), rng.integers(-3, 3, nb).astype(np.int16)
+    pa, pb = rng.integers(-4, 4, npr).astype(np.int32), rng.integers(-3, 3, npr).astype(np.int8)
+    bva, bvb = rng.random(nb) > 0.1, rng.random(nb) > 0.1
+    pva, pvb = rng.random(npr) > 0.1, rng.random(npr) > 0.1
+    build, probe = tbl(a=(ba, bva), b=(bb, bvb)), tbl(a=(pa, pva), b=(pb, pvb))
+    pi, bi = oracle.join(build, [0, 1], [], probe, [0, 1], [])
+    expect = [(i, j) for i in range(npr) for j in range(nb)
+              if pva[i] and pvb[i] and bva[j] and bvb[j] and pa[i] == ba[j] and pb[i] == bb[j]]
+    assert list(zip(pi.tolist(), bi.tolist())) == expect
+    # The key order is the caller's: swapping both sides' key lists changes nothing.
+    pi2, bi2 = oracle.join(build, [1, 0], [], probe, [1, 0], [])
+    assert np.array_equal(pi, pi2) and np.array_equal(bi, bi2)
+
+
 @pytest.mark.parametrize("seed", range(6))
 def test_join_brute_force(seed):
     rng = np.random.default_rng(seed)
