@@ -3,7 +3,9 @@
 The 60M x 15M pipeline and the 60M-row partition are too large for the oracle
 to recompute whole in seconds, so these tests check
   * properties that hold at any size (key uniqueness and range, total counts
-    against a hash-free dense formulation, offsets against the oracle), and
+    against a hash-free dense formulation, offsets against the oracle; for the
+    pipeline, every group's SUM and COUNT against per-key totals of the joined
+    rows), and
   * sampled outputs the oracle computes exactly: the oracle runs on the subset
     of input rows that can contribute to the sampled groups / positions.
 Inputs are generated on the device by the seeded generator (equal to the host
@@ -63,7 +65,16 @@ def test_pipeline_fact60m_dim15m(mods):
     disc = dg.uniform(2, 2, 0, FACT, 0, 10)
     rev = price[ok] * (100 - disc[ok])
     assert int(np.sum(gsum, dtype=np.int64)) == int(np.sum(rev, dtype=np.int64))
-    del price, disc, rev
+    # Complete: every group's SUM and COUNT against per-key totals of the
+    # joined rows.  The float64 per-key sums are exact: each partial sum is an
+    # integer below 2^53 (bounded by the largest revenue times the largest
+    # group).
+    ecnt = np.bincount(fkey[ok], minlength=DIM + 1)
+    assert int(rev.max()) * int(ecnt.max()) < 2**53
+    esum = np.bincount(fkey[ok], weights=rev.astype(np.float64), minlength=DIM + 1)
+    assert np.array_equal(ecnt[gk], gcnt)
+    assert np.array_equal(esum[gk].astype(np.int64), gsum)
+    del price, disc, rev, ecnt, esum
 
     # Sampled groups, exactly, by the oracle on the rows that can reach them.
     rng = np.random.default_rng(0)
