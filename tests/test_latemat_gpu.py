@@ -82,3 +82,15 @@ def test_pair_capacity_overflow_reported(gq, ctx):
     ctx.join_groupby(jt, bd, pd_, [0], [], [3], [("count*",)], pair_capacity=100)
     assert ctx.sync_status() & gq.DEV_CAPACITY
     jt.free()
+
+
+def test_two_key_columns(gq, ctx):
+    # Join on (int32, int16) key tuples with NULLs in either column; group by
+    # a build column and a probe column.
+    rng = np.random.default_rng(11)
+    build = random_table(rng, 4_000, (np.int32, np.int16, np.int8), null_frac=0.05, lo=-20, hi=20)
+    probe = random_table(rng, 30_000, (np.int32, np.int16, np.int32), null_frac=0.05, lo=-20, hi=20)
+    np_ = len(probe.cols)
+    aggs = [("count*",), ("sum", [("col", 2)]), ("max", [("col", np_ + 2)])]
+    check(gq, ctx, build, [0, 1], [], probe, [0, 1], [("range", 2, -15, 15)], [np_ + 2, 2], aggs,
+          pair_capacity=600_000)
